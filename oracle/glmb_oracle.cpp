@@ -1,0 +1,980 @@
+/*
+ * TEST INFRASTRUCTURE -- plain FP64 CPU reference ("oracle") of the multi-detection
+ * GLMB time step of arXiv 2512.06230 (Sec. 3).  Only the test-suite, the smoke entry
+ * point and the CPU-baseline leg of the benchmark may load this library; the product
+ * path (the HIP library) never calls it and shares no code with it.
+ *
+ * Every step is written for clarity, not speed: explicit loops, std::sort, std::map
+ * and a std::priority_queue.  Each function names the passage of the paper it follows.
+ *
+ * Model (paper Sec. 3, with the readings recorded in the design notes):
+ *   - labeled multi-object state, one Gaussian density per (label, association history)
+ *     ("instance"); the GLMB is a weighted list of hypotheses, each a set of instances
+ *     with distinct labels (Sec. 3, labeled RFS and hypotheses (X_k, xi_k));
+ *   - constant-velocity motion, x = [px, py, vx, vy], F = [[I, dt I], [0, I]],
+ *     Q = q [[dt^3/3 I, dt^2/2 I], [dt^2/2 I, dt I]];
+ *   - measurement z = H x + v, H = [I 0], v ~ N(0, sigma^2 I);
+ *   - every existing object yields Poisson(gamma) detections (several detections per
+ *     object, Sec. 3), clutter is Poisson with density kappa; the compatibility matrix
+ *     entry of Eq. 2 is gamma * g_ij * N(z_i; H m_j, S_j) for a track and kappa for
+ *     clutter, where g_ij is the Mahalanobis gate d^2 <= G;
+ *   - a hypothesis' children are all association maps theta: measurements ->
+ *     {clutter} + its tracks; log W(h, theta) = log w_h - gamma |J_h| + sum_i phi_{h,i}(theta_i)
+ *     (parent weight times the likelihood of the associations, Sec. 3 end);
+ *   - the H_max most likely children are retained, then tau pruning (Sec. 3 end).
+ */
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <functional>
+#include <limits>
+#include <map>
+#include <queue>
+#include <string>
+#include <tuple>
+#include <vector>
+
+// Planted mistakes for the pin-sensitivity test (ORACLE_MUTANT=n builds a wrong oracle on
+// purpose; the normal build defines none of them).
+#ifndef ORACLE_MUTANT
+#define ORACLE_MUTANT 0
+#endif
+
+namespace {
+
+const double kNegInf = -std::numeric_limits<double>::infinity();
+const double kLog2Pi = std::log(2.0 * M_PI);
+
+struct Params {
+  double dt, q, sigma, ps, gamma, kappa, gate;
+  double b_rmax, b_rate, b_sigv, b_rumax, b_clusterd;
+  int hmax;
+  double tau;
+};
+
+struct Label {
+  int32_t kb, idx;
+  bool operator<(const Label& o) const { return kb != o.kb ? kb < o.kb : idx < o.idx; }
+  bool operator==(const Label& o) const { return kb == o.kb && idx == o.idx; }
+};
+
+struct Inst {
+  Label lab;
+  double m[4];
+  double P[16];
+  int32_t src;               // index of the instance this one was derived from (input numbering)
+  std::vector<int32_t> S;    // measurement indices assigned at the last update
+};
+
+struct Hyp {
+  double logw;
+  std::vector<int32_t> inst;     // instance indices, sorted by label
+  int32_t parent;                // index of the hypothesis it was derived from (input numbering)
+  std::vector<int32_t> theta;    // after an update: input index of the instance given each measurement, -1 = clutter
+};
+
+struct Birth {
+  Label lab;
+  double m[4];
+  double P[16];
+  double r;
+};
+
+// An option of a (hypothesis, measurement) cell: clutter (track == false) or a track.
+struct OptKey {
+  bool track;
+  Label lab;
+  bool operator<(const OptKey& o) const {
+    if (track != o.track) return !track;
+    if (!track) return false;
+    return lab < o.lab;
+  }
+  bool operator==(const OptKey& o) const { return track == o.track && (!track || lab == o.lab); }
+};
+
+// ---------------------------------------------------------------------------------
+// Exact top-K over implicitly defined children.
+//
+// A parent has a base value and a list of groups; a child picks, independently in
+// every group, either the group's best option (deviation 0) or one of its other
+// options r >= 1 with deviation delta_{g,r} >= 0.  value = base - (sum of picked
+// deviations, added in ascending (delta, group id, option key) order).
+// Children are ordered by value descending, then by the canonical key
+//   (parent rank, number of picks, list of picked item positions ascending),
+// where a parent's items (g, r) are numbered in ascending (delta, group id, option key)
+// order.  This is the plain definition "sort every child, keep the first K"; it is
+// computed with a best-first search (Sec. 3 end: retain the H_max most likely).
+// ---------------------------------------------------------------------------------
+struct GroupSpec {
+  int32_t id;                                    // group id (measurement index or dimension id)
+  std::vector<std::pair<double, OptKey>> devs;   // r = 1..: (delta, option key), ascending
+  std::vector<int32_t> pos;                      // item position of each deviation
+};
+
+struct ParentSpec {
+  double base;
+  std::vector<GroupSpec> groups;                 // only groups with at least one deviation
+};
+
+struct Child {
+  int32_t parent;
+  std::vector<std::pair<int32_t, int32_t>> picks;  // (group index into ParentSpec::groups, r >= 1)
+  double value;
+  std::vector<int32_t> key;                        // sorted item positions
+};
+
+static void number_items(ParentSpec& p) {
+  struct It { double d; int32_t gid; OptKey ok; int32_t g, r; };
+  std::vector<It> items;
+  for (int32_t g = 0; g < (int32_t)p.groups.size(); ++g) {
+    p.groups[g].pos.assign(p.groups[g].devs.size(), -1);
+    for (int32_t r = 0; r < (int32_t)p.groups[g].devs.size(); ++r)
+      items.push_back({p.groups[g].devs[r].first, p.groups[g].id, p.groups[g].devs[r].second, g, r});
+  }
+  std::sort(items.begin(), items.end(), [](const It& a, const It& b) {
+    if (a.d != b.d) return a.d < b.d;
+    if (a.gid != b.gid) return a.gid < b.gid;
+    return a.ok < b.ok;
+  });
+  for (int32_t k = 0; k < (int32_t)items.size(); ++k) p.groups[items[k].g].pos[items[k].r] = k;
+}
+
+static double child_value(const ParentSpec& p, const std::vector<std::pair<int32_t, int32_t>>& picks,
+                          std::vector<int32_t>* key) {
+  std::vector<std::pair<int32_t, double>> chosen;  // (item position, delta)
+  for (auto& pr : picks) {
+    const GroupSpec& g = p.groups[pr.first];
+    chosen.push_back({g.pos[pr.second - 1], g.devs[pr.second - 1].first});
+  }
+  std::sort(chosen.begin(), chosen.end());
+  double v = p.base;
+  for (auto& c : chosen) v -= c.second;
+  if (key) {
+    key->clear();
+    for (auto& c : chosen) key->push_back(c.first);
+  }
+  return v;
+}
+
+static bool child_less(const Child& a, const Child& b) {  // "a ranks before b"
+  if (a.value != b.value) return a.value > b.value;
+  if (a.parent != b.parent) return ORACLE_MUTANT == 7 ? a.parent > b.parent : a.parent < b.parent;
+  if (a.key.size() != b.key.size()) return a.key.size() < b.key.size();
+  return a.key < b.key;
+}
+
+static std::vector<Child> top_k(std::vector<ParentSpec>& ps, int K) {
+  for (auto& p : ps) {
+    // groups in ascending (first deviation, group id) order: the successor rules need it
+    std::sort(p.groups.begin(), p.groups.end(), [](const GroupSpec& a, const GroupSpec& b) {
+      if (a.devs[0].first != b.devs[0].first) return a.devs[0].first < b.devs[0].first;
+      return a.id < b.id;
+    });
+    number_items(p);
+  }
+  struct State {
+    double value;
+    int32_t parent;
+    std::vector<std::pair<int32_t, int32_t>> picks;  // ascending group index
+  };
+  auto cmp = [](const State& a, const State& b) { return a.value < b.value; };
+  std::priority_queue<State, std::vector<State>, decltype(cmp)> heap(cmp);
+  for (int32_t h = 0; h < (int32_t)ps.size(); ++h) heap.push({ps[h].base, h, {}});
+  std::vector<Child> out;
+  if (K <= 0) return out;
+  while (!heap.empty()) {
+    if ((int)out.size() >= K && heap.top().value != out[K - 1].value) break;
+    State s = heap.top();
+    heap.pop();
+    Child c{s.parent, s.picks, 0.0, {}};
+    c.value = child_value(ps[s.parent], s.picks, &c.key);
+    out.push_back(c);
+    // Successors: every multi-choice pick list is reached from exactly one predecessor,
+    // and no successor has a larger value than its predecessor.
+    const ParentSpec& p = ps[s.parent];
+    const int32_t ng = (int32_t)p.groups.size();
+    auto push = [&](std::vector<std::pair<int32_t, int32_t>> picks) {
+      double v = child_value(p, picks, nullptr);
+      heap.push({v, s.parent, std::move(picks)});
+    };
+    if (s.picks.empty()) {
+      if (ng > 0) push({{0, 1}});
+      continue;
+    }
+    const auto last = s.picks.back();
+    // (a) next option of the last picked group
+    if (last.second < (int32_t)p.groups[last.first].devs.size()) {
+      auto pk = s.picks;
+      pk.back().second += 1;
+      push(pk);
+    }
+    if (last.first + 1 < ng) {
+      // (b) additionally pick the first deviation of the next group
+      auto pk = s.picks;
+      pk.push_back({last.first + 1, 1});
+      push(pk);
+      // (c) move a first-deviation pick to the next group
+      if (last.second == 1 && ORACLE_MUTANT != 4) {
+        auto pk2 = s.picks;
+        pk2.back() = {last.first + 1, 1};
+        push(pk2);
+      }
+    }
+  }
+  std::sort(out.begin(), out.end(), child_less);
+  if ((int)out.size() > K) out.resize(K);
+  return out;
+}
+
+// ---------------------------------------------------------------------------------
+// Small dense linear algebra (4x4 row-major)
+// ---------------------------------------------------------------------------------
+static void cv_model(const Params& p, double F[16], double Q[16]) {
+  const double dt = p.dt, q = p.q;
+  std::memset(F, 0, 16 * sizeof(double));
+  std::memset(Q, 0, 16 * sizeof(double));
+  for (int i = 0; i < 4; ++i) F[i * 4 + i] = 1.0;
+  F[0 * 4 + 2] = dt;
+  F[1 * 4 + 3] = dt;
+  const double a = q * dt * dt * dt / 3.0, b = q * dt * dt / (ORACLE_MUTANT == 3 ? 3.0 : 2.0), c = q * dt;
+  for (int ax = 0; ax < 2; ++ax) {
+    Q[ax * 4 + ax] = a;
+    Q[ax * 4 + ax + 2] = b;
+    Q[(ax + 2) * 4 + ax] = b;
+    Q[(ax + 2) * 4 + ax + 2] = c;
+  }
+}
+
+static void kalman_predict(const double F[16], const double Q[16], double m[4], double P[16]) {
+  double m2[4] = {0, 0, 0, 0}, FP[16] = {0}, P2[16] = {0};
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) m2[i] += F[i * 4 + j] * m[j];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
+      for (int k = 0; k < 4; ++k) FP[i * 4 + j] += F[i * 4 + k] * P[k * 4 + j];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      double s = Q[i * 4 + j];
+      for (int k = 0; k < 4; ++k) s += FP[i * 4 + k] * F[j * 4 + k];
+      P2[i * 4 + j] = s;
+    }
+  std::memcpy(m, m2, sizeof(m2));
+  std::memcpy(P, P2, sizeof(P2));
+}
+
+// Update with n >= 1 detections z_1..z_n of the same object: equivalent to one update with
+// their mean and noise R/n (the product of n Gaussians in Hx is Gaussian in the mean).
+static void kalman_update_multi(double sigma, const std::vector<const double*>& zs, double m[4],
+                                double P[16]) {
+  const double n = (double)zs.size();
+  double zb[2] = {0, 0};
+  for (auto z : zs) {
+    zb[0] += z[0];
+    zb[1] += z[1];
+  }
+  zb[0] /= n;
+  zb[1] /= n;
+  const double r = sigma * sigma / n;
+  double S[4] = {P[0] + r, P[1], P[4], P[5] + r};
+  const double det = S[0] * S[3] - S[1] * S[2];
+  const double Si[4] = {S[3] / det, -S[1] / det, -S[2] / det, S[0] / det};
+  double K[8];  // 4x2 = P H^T S^-1
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 2; ++j) K[i * 2 + j] = P[i * 4 + 0] * Si[0 * 2 + j] + P[i * 4 + 1] * Si[1 * 2 + j];
+  const double nu[2] = {zb[0] - m[0], zb[1] - m[1]};
+  for (int i = 0; i < 4; ++i) m[i] += (ORACLE_MUTANT == 2 ? -1.0 : 1.0) * (K[i * 2 + 0] * nu[0] + K[i * 2 + 1] * nu[1]);
+  double P2[16];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      // P - K S K^T
+      double ks = 0.0;
+      for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) ks += K[i * 2 + a] * S[a * 2 + b] * K[j * 2 + b];
+      P2[i * 4 + j] = P[i * 4 + j] - ks;
+    }
+  std::memcpy(P, P2, sizeof(P2));
+}
+
+static double log_add(double a, double b) {
+  if (a == kNegInf) return b;
+  if (b == kNegInf) return a;
+  const double m = std::max(a, b);
+  return m + std::log(std::exp(a - m) + std::exp(b - m));
+}
+
+static double lse(const std::vector<double>& v) {
+  double m = kNegInf;
+  for (double x : v) m = std::max(m, x);
+  if (m == kNegInf) return m;
+  double s = 0.0;
+  for (double x : v) s += std::exp(x - m);
+  return m + std::log(s);
+}
+
+// ---------------------------------------------------------------------------------
+struct Oracle {
+  Params p{};
+  std::vector<Inst> inst;
+  std::vector<Hyp> hyp;
+  std::vector<Birth> births;
+  int last_M = 0;
+  // diagnostics of the last update
+  std::vector<double> d_best;    // per parent: best child log weight minus log Z
+  std::vector<double> d_logpi;   // per parent: log Z_h - log Z
+  std::vector<double> d_ru;      // per measurement: probability of not being clutter
+  double d_retained = 0.0;       // retained posterior mass fraction
+  int64_t d_gated = 0;
+  // association marginals of the last update (over gated (instance, measurement) pairs)
+  std::vector<int32_t> d_pair_u, d_pair_i;
+  std::vector<double> d_pair_phi, d_pair_mass, d_pair_exist;
+  // pairs removed from the option sets by a proposal (instance input index, measurement)
+  std::vector<std::pair<int32_t, int32_t>> skip;
+  double d_lost = 0.0;
+  std::string err;
+
+  void gc() {
+    std::vector<int32_t> remap(inst.size(), -1);
+    std::vector<Inst> keep;
+    for (auto& h : hyp)
+      for (int32_t u : h.inst)
+        if (remap[u] < 0) remap[u] = 0;
+    for (size_t u = 0; u < inst.size(); ++u)
+      if (remap[u] >= 0) {
+        remap[u] = (int32_t)keep.size();
+        keep.push_back(inst[u]);
+      }
+    for (auto& h : hyp)
+      for (auto& u : h.inst) u = remap[u];
+    inst.swap(keep);
+  }
+
+  void sort_by_label(std::vector<int32_t>& v) const {
+    std::sort(v.begin(), v.end(), [&](int32_t a, int32_t b) { return inst[a].lab < inst[b].lab; });
+  }
+
+  // ---- prediction: survival of every track and LMB births (Sec. 3, prediction) -------
+  int predict(int k) {
+    (void)k;
+    double F[16], Q[16];
+    cv_model(p, F, Q);
+    const int32_t n_old = (int32_t)inst.size();
+    for (int32_t u = 0; u < n_old; ++u) {
+      kalman_predict(F, Q, inst[u].m, inst[u].P);
+      inst[u].src = u;
+      inst[u].S.clear();
+    }
+    const int32_t nb = (int32_t)births.size();
+    for (int32_t b = 0; b < nb; ++b) {
+      Inst x;
+      x.lab = births[b].lab;
+      std::memcpy(x.m, births[b].m, sizeof(x.m));
+      std::memcpy(x.P, births[b].P, sizeof(x.P));
+      kalman_predict(F, Q, x.m, x.P);
+      x.src = n_old + b;
+      inst.push_back(x);
+    }
+    // Per dimension (track survives / dies, birth included / excluded): best choice and
+    // the log-probability lost by flipping it.
+    auto dim = [](double pr, double* best, double* delta, bool* best_is_yes) {
+      const double ly = std::log(pr), ln = std::log1p(-pr);
+      *best_is_yes = ly >= ln;
+      *best = std::max(ly, ln);
+      *delta = std::fabs(ly - ln);
+    };
+    double tb, td;
+    bool t_yes;
+    dim(p.ps, &tb, &td, &t_yes);
+    std::vector<double> bb(nb), bd(nb);
+    std::vector<char> b_yes(nb);
+    for (int32_t b = 0; b < nb; ++b) {
+      bool y;
+      dim(births[b].r, &bb[b], &bd[b], &y);
+      b_yes[b] = y;
+    }
+    std::vector<ParentSpec> specs(hyp.size());
+    for (size_t h = 0; h < hyp.size(); ++h) {
+      const int32_t nt = (int32_t)hyp[h].inst.size();
+      specs[h].base = hyp[h].logw + nt * tb;
+      for (int32_t b = 0; b < nb; ++b) specs[h].base += bb[b];
+    }
+    // Lower bound on the K-th best child: K-th largest among the unflipped children and the
+    // one-flip children.  Flips whose one-flip child is below it belong to no retained child.
+    double bound = kNegInf;
+    {
+      std::vector<double> cand;
+      for (size_t h = 0; h < hyp.size(); ++h) {
+        const int32_t nt = (int32_t)hyp[h].inst.size();
+        cand.push_back(specs[h].base);
+        for (int32_t d = 0; d < nt + nb; ++d) {
+          const double delta = d < nt ? td : bd[d - nt];
+          if (std::isfinite(delta)) cand.push_back(specs[h].base - delta);
+        }
+      }
+      if ((int)cand.size() >= p.hmax) {
+        std::nth_element(cand.begin(), cand.begin() + (p.hmax - 1), cand.end(), std::greater<double>());
+        bound = cand[p.hmax - 1];
+      }
+    }
+    for (size_t h = 0; h < hyp.size(); ++h) {
+      ParentSpec& s = specs[h];
+      const int32_t nt = (int32_t)hyp[h].inst.size();
+      for (int32_t d = 0; d < nt + nb; ++d) {
+        const double delta = d < nt ? td : bd[d - nt];
+        if (!std::isfinite(delta)) continue;  // probability 0 or 1: never flipped
+        if (s.base - delta < bound) continue;
+        GroupSpec g;
+        g.id = d;
+        g.devs.push_back({delta, OptKey{false, {0, 0}}});
+        s.groups.push_back(g);
+      }
+    }
+    std::vector<Child> ch = top_k(specs, p.hmax);
+    // children's instance sets; identical sets from different parents are merged
+    struct Merged {
+      std::vector<int32_t> set;
+      double value;
+      const Child* rep;
+    };
+    std::map<std::vector<int32_t>, int32_t> where;
+    std::vector<Merged> merged;
+    for (const Child& c : ch) {
+      const Hyp& ph = hyp[c.parent];
+      const int32_t nt = (int32_t)ph.inst.size();
+      std::vector<char> flip(nt + nb, 0);
+      for (auto& pk : c.picks) flip[specs[c.parent].groups[pk.first].id] = 1;
+      std::vector<int32_t> set;
+      for (int32_t d = 0; d < nt; ++d)
+        if ((bool)t_yes != (bool)flip[d]) set.push_back(ph.inst[d]);
+      for (int32_t b = 0; b < nb; ++b)
+        if ((bool)b_yes[b] != (bool)flip[nt + b]) set.push_back(n_old + b);
+      std::sort(set.begin(), set.end());
+      auto it = where.find(set);
+      if (it == where.end()) {
+        where[set] = (int32_t)merged.size();
+        merged.push_back({set, c.value, &c});
+      } else {
+        Merged& m = merged[it->second];
+        m.value = log_add(m.value, c.value);
+        // representative: the member with the smallest canonical key
+        const Child* r = m.rep;
+        bool smaller = c.parent != r->parent ? c.parent < r->parent
+                       : c.key.size() != r->key.size() ? c.key.size() < r->key.size()
+                                                         : c.key < r->key;
+        if (smaller) m.rep = &c;
+      }
+    }
+    std::sort(merged.begin(), merged.end(), [](const Merged& a, const Merged& b) {
+      if (a.value != b.value) return a.value > b.value;
+      const Child* x = a.rep;
+      const Child* y = b.rep;
+      if (x->parent != y->parent) return x->parent < y->parent;
+      if (x->key.size() != y->key.size()) return x->key.size() < y->key.size();
+      return x->key < y->key;
+    });
+    std::vector<double> vals;
+    for (auto& m : merged) vals.push_back(m.value);
+    const double z = lse(vals);
+    std::vector<Hyp> nh;
+    for (auto& m : merged) {
+      Hyp h;
+      h.logw = m.value - z;
+      h.inst = m.set;
+      sort_by_label(h.inst);
+      h.parent = m.rep->parent;
+      nh.push_back(h);
+    }
+    hyp.swap(nh);
+    births.clear();
+    gc();
+    return 0;
+  }
+
+  // ---- update with the measurement set Z_k (Sec. 3, Eq. 2 and hypothesis weights) ----
+  // Options of cell (h, i): clutter plus every track of h gated with z_i, ordered by
+  // (phi descending, option key ascending).
+  typedef std::vector<std::pair<double, OptKey>> Options;
+
+  int update(int k, const double* z, int M) {
+    last_M = M;
+    const int32_t U = (int32_t)inst.size();
+    const double lgk = std::log(p.kappa);
+    const double lgg = std::log(p.gamma);
+    // Eq. 2 entries for every (instance, measurement) pair that passes the gate,
+    // kept per instance as (measurement, phi, skipped-by-proposal).
+    struct G { int32_t i; double phi; bool skip; };
+    std::vector<std::vector<G>> gated(U);
+    d_gated = 0;
+    for (int32_t u = 0; u < U; ++u) {
+      const double* P = inst[u].P;
+      const double s00 = P[0] + p.sigma * p.sigma, s01 = P[1], s10 = P[4], s11 = P[5] + p.sigma * p.sigma;
+      const double det = s00 * s11 - s01 * s10;
+      for (int i = 0; i < M; ++i) {
+        const double n0 = z[2 * i] - inst[u].m[0], n1 = z[2 * i + 1] - inst[u].m[1];
+        const double d2 = ORACLE_MUTANT == 6 ? (s00 * n0 * n0 - (s01 + s10) * n0 * n1 + s11 * n1 * n1) / det
+                                             : (s11 * n0 * n0 - (s01 + s10) * n0 * n1 + s00 * n1 * n1) / det;
+        if (d2 <= p.gate) {
+          gated[u].push_back({i, lgg - kLog2Pi - (ORACLE_MUTANT == 5 ? 1.0 : 0.5) * std::log(det) - 0.5 * d2, false});
+          ++d_gated;
+        }
+      }
+    }
+    for (auto& sk : skip)
+      if (sk.first >= 0 && sk.first < U)
+        for (auto& g : gated[sk.first])
+          if (g.i == sk.second) g.skip = true;
+    auto opt_less = [](const std::pair<double, OptKey>& a, const std::pair<double, OptKey>& c) {
+      if (a.first != c.first) return a.first > c.first;
+      return a.second < c.second;
+    };
+    // options of every cell of hypothesis h (skipped pairs removed unless `with_skipped`)
+    auto options = [&](int32_t h, std::vector<Options>& o, bool with_skipped) {
+      o.assign(M, Options());
+      for (int i = 0; i < M; ++i) o[i].push_back({lgk, OptKey{false, {0, 0}}});
+      for (int32_t u : hyp[h].inst)
+        for (const G& g : gated[u])
+          if (with_skipped || !g.skip) o[g.i].push_back({g.phi, OptKey{true, inst[u].lab}});
+      for (int i = 0; i < M; ++i) std::sort(o[i].begin(), o[i].end(), opt_less);
+    };
+    const int32_t H = (int32_t)hyp.size();
+    std::vector<double> B(H), logZ(H), logZfull(H);
+    std::vector<double> lse_hi((size_t)H * M);
+    std::vector<double> dev1((size_t)H * M);     // first deviation of each cell (inf if none)
+    std::vector<Options> o;
+    for (int32_t h = 0; h < H; ++h) {
+      const Hyp& hy = hyp[h];
+      const double base = hy.logw - (ORACLE_MUTANT == 1 ? 0.0 : p.gamma) * (double)hy.inst.size();
+      double b = base, lz = base, lzf = base;
+      options(h, o, false);
+      for (int i = 0; i < M; ++i) {
+        std::vector<double> v;
+        for (auto& x : o[i]) v.push_back(x.first);
+        const double l = lse(v);
+        lse_hi[(size_t)h * M + i] = l;
+        b += o[i][0].first;
+        lz += l;
+        dev1[(size_t)h * M + i] = o[i].size() > 1 ? o[i][0].first - o[i][1].first
+                                                  : std::numeric_limits<double>::infinity();
+      }
+      if (!skip.empty()) {
+        options(h, o, true);
+        for (int i = 0; i < M; ++i) {
+          std::vector<double> v;
+          for (auto& x : o[i]) v.push_back(x.first);
+          lzf += lse(v);
+        }
+      } else {
+        lzf = lz;
+      }
+      B[h] = b;
+      logZ[h] = lz;
+      logZfull[h] = lzf;
+    }
+    const double LZ = lse(logZ);
+    // full-posterior quantities (Eq. 1 normaliser over every child of every parent)
+    d_best.assign(H, 0.0);
+    d_logpi.assign(H, 0.0);
+    d_ru.assign(M, 0.0);
+    std::vector<double> pi(H);
+    for (int32_t h = 0; h < H; ++h) {
+      pi[h] = std::exp(logZ[h] - LZ);
+      d_best[h] = B[h] - LZ;
+      d_logpi[h] = logZ[h] - LZ;
+    }
+    for (int i = 0; i < M; ++i) {
+      double pc = 0.0;
+      for (int32_t h = 0; h < H; ++h) pc += pi[h] * std::exp(lgk - lse_hi[(size_t)h * M + i]);
+      d_ru[i] = 1.0 - pc;
+    }
+    {
+      // association marginals per gated pair: m_ui = sum_{h contains u} pi_h q_hi(u)
+      std::vector<double> exist(U, 0.0);
+      std::vector<std::vector<double>> mass(U);
+      for (int32_t u = 0; u < U; ++u) mass[u].assign(gated[u].size(), 0.0);
+      for (int32_t h = 0; h < H; ++h)
+        for (int32_t u : hyp[h].inst) {
+          exist[u] += pi[h];
+          for (size_t g = 0; g < gated[u].size(); ++g) {
+            if (gated[u][g].skip) continue;
+            mass[u][g] += pi[h] * std::exp(gated[u][g].phi - lse_hi[(size_t)h * M + gated[u][g].i]);
+          }
+        }
+      d_pair_u.clear();
+      d_pair_i.clear();
+      d_pair_phi.clear();
+      d_pair_mass.clear();
+      d_pair_exist.clear();
+      for (int32_t u = 0; u < U; ++u)
+        for (size_t g = 0; g < gated[u].size(); ++g) {
+          d_pair_u.push_back(inst[u].src);
+          d_pair_i.push_back(gated[u][g].i);
+          d_pair_phi.push_back(gated[u][g].phi);
+          d_pair_mass.push_back(mass[u][g]);
+          d_pair_exist.push_back(exist[u]);
+        }
+    }
+    {
+      // posterior mass that the proposal's skipped pairs remove, relative to the full update
+      const double LZf = lse(logZfull);
+      double lost = 0.0;
+      for (int32_t h = 0; h < H; ++h) lost += std::exp(logZfull[h] - LZf) * (1.0 - std::exp(logZ[h] - logZfull[h]));
+      d_lost = lost;
+    }
+    // Lower bound on the K-th best child value: the K-th largest among the best children and
+    // the single-deviation children (all of them are children).  A deviation delta with
+    // B_h - delta below it belongs to no retained child, so each parent's deviation list is
+    // cut to the delta-prefix B_h - delta >= bound (item positions are unchanged by the cut).
+    double bound = kNegInf;
+    {
+      std::vector<double> cand;
+      for (int32_t h = 0; h < H; ++h) {
+        cand.push_back(B[h]);
+        for (int i = 0; i < M; ++i)
+          if (std::isfinite(dev1[(size_t)h * M + i])) cand.push_back(B[h] - dev1[(size_t)h * M + i]);
+      }
+      if ((int)cand.size() >= p.hmax) {
+        std::nth_element(cand.begin(), cand.begin() + (p.hmax - 1), cand.end(), std::greater<double>());
+        bound = cand[p.hmax - 1];
+      }
+    }
+    std::vector<ParentSpec> specs(H);
+    for (int32_t h = 0; h < H; ++h) {
+      ParentSpec& s = specs[h];
+      s.base = B[h];
+      bool any = false;
+      for (int i = 0; i < M; ++i)
+        if (B[h] - dev1[(size_t)h * M + i] >= bound) any = true;
+      if (!any) continue;
+      options(h, o, false);
+      for (int i = 0; i < M; ++i) {
+        if (o[i].size() < 2) continue;
+        GroupSpec g;
+        g.id = i;
+        for (size_t r = 1; r < o[i].size(); ++r) {
+          const double d = o[i][0].first - o[i][r].first;
+          if (B[h] - d >= bound) g.devs.push_back({d, o[i][r].second});
+        }
+        if (!g.devs.empty()) s.groups.push_back(g);
+      }
+    }
+    // exact top-H_max children (Sec. 3 end)
+    std::vector<Child> ch = top_k(specs, p.hmax);
+    std::vector<double> vals;
+    for (auto& c : ch) vals.push_back(c.value);
+    double zr = lse(vals);
+    // tau pruning on weights normalised over the retained set; the best child is kept
+    size_t keep = ch.size();
+    if (p.tau > 0.0) {
+      keep = 1;
+      while (keep < ch.size() && std::exp(ch[keep].value - zr) >= p.tau) ++keep;
+    }
+    ch.resize(keep);
+    vals.resize(keep);
+    zr = lse(vals);
+    d_retained = std::exp(zr - LZ);
+    // best option of every cell of every retained parent
+    std::map<int32_t, std::vector<OptKey>> best_of;
+    for (const Child& c : ch) {
+      if (best_of.count(c.parent)) continue;
+      options(c.parent, o, false);
+      std::vector<OptKey> b(M);
+      for (int i = 0; i < M; ++i) b[i] = o[i][0].second;
+      best_of[c.parent] = b;
+    }
+    // materialise: one new instance per distinct (predicted instance, detection set);
+    // its density is the Kalman update with those detections (Sec. 3 end, batched update of
+    // the unique (track, measurement) associations)
+    std::map<std::pair<int32_t, std::vector<int32_t>>, int32_t> made;
+    std::vector<Inst> ninst;
+    std::vector<Hyp> nh;
+    for (const Child& c : ch) {
+      const Hyp& ph = hyp[c.parent];
+      const ParentSpec& s = specs[c.parent];
+      std::vector<OptKey> th = best_of[c.parent];
+      for (auto& pk : c.picks) {
+        const GroupSpec& g = s.groups[pk.first];
+        th[g.id] = g.devs[pk.second - 1].second;
+      }
+      // detection set of every track of the parent (ph.inst is sorted by label)
+      std::vector<std::vector<int32_t>> S(ph.inst.size());
+      Hyp h;
+      h.logw = c.value - zr;
+      h.parent = c.parent;
+      h.theta.assign(M, -1);
+      for (int i = 0; i < M; ++i) {
+        if (!th[i].track) continue;
+        auto it = std::lower_bound(ph.inst.begin(), ph.inst.end(), th[i].lab,
+                                   [&](int32_t u, const Label& l) { return inst[u].lab < l; });
+        const size_t j = (size_t)(it - ph.inst.begin());
+        S[j].push_back(i);
+        h.theta[i] = inst[ph.inst[j]].src;
+      }
+      for (size_t j = 0; j < ph.inst.size(); ++j) {
+        const int32_t u = ph.inst[j];
+        auto key = std::make_pair(u, S[j]);
+        auto it = made.find(key);
+        int32_t id;
+        if (it == made.end()) {
+          Inst x = inst[u];
+          x.S = S[j];
+          if (!S[j].empty()) {
+            std::vector<const double*> zs;
+            for (int32_t i : S[j]) zs.push_back(z + 2 * i);
+            kalman_update_multi(p.sigma, zs, x.m, x.P);
+          }
+          id = (int32_t)ninst.size();
+          made[key] = id;
+          ninst.push_back(x);
+        } else {
+          id = it->second;
+        }
+        h.inst.push_back(id);
+      }
+      nh.push_back(h);
+    }
+    // births for the next scan from measurements that the posterior leaves unexplained
+    make_births(k + 1, z, M);
+    inst.swap(ninst);
+    hyp.swap(nh);
+    for (auto& hh : hyp) sort_by_label(hh.inst);
+    return 0;
+  }
+
+  // Adaptive LMB birth (Sec. 3 prediction names an LMB birth process; its components are
+  // placed at clusters of measurements that the posterior attributes to clutter).
+  void make_births(int kb, const double* z, int M) {
+    births.clear();
+    std::vector<int32_t> seeds;
+    double tot = 0.0;
+    for (int i = 0; i < M; ++i)
+      if (d_ru[i] < p.b_rumax) {
+        seeds.push_back(i);
+        tot += 1.0 - d_ru[i];
+      }
+    std::vector<std::vector<int32_t>> cl;
+    for (int32_t i : seeds) {
+      bool placed = false;
+      for (auto& c : cl) {
+        const double dx = z[2 * i] - z[2 * c[0]], dy = z[2 * i + 1] - z[2 * c[0]];
+        if (std::sqrt(dx * dx + dy * dy) <= p.b_clusterd) {
+          c.push_back(i);
+          placed = true;
+          break;
+        }
+      }
+      if (!placed) cl.push_back({i});
+    }
+    for (size_t c = 0; c < cl.size(); ++c) {
+      Birth b{};
+      b.lab = {kb, (int32_t)c};
+      const double n = (double)cl[c].size();
+      double sx = 0, sy = 0, w = 0;
+      for (int32_t i : cl[c]) {
+        sx += z[2 * i];
+        sy += z[2 * i + 1];
+        w += 1.0 - d_ru[i];
+      }
+      b.m[0] = sx / n;
+      b.m[1] = sy / n;
+      b.m[2] = b.m[3] = 0.0;
+      std::memset(b.P, 0, sizeof(b.P));
+      b.P[0] = b.P[5] = p.sigma * p.sigma / n;
+      b.P[10] = b.P[15] = p.b_sigv * p.b_sigv;
+      b.r = ORACLE_MUTANT == 8 ? p.b_rate * w / tot * 2.0 : std::min(p.b_rmax, p.b_rate * w / tot);
+      births.push_back(b);
+    }
+  }
+
+  // ---- truncation: H_max then tau, each on renormalised weights (Sec. 3 end) ----------
+  int truncate(int hmax, double tau) {
+    if (hmax < 1) return -1;
+    if ((int)hyp.size() > hmax) hyp.resize(hmax);
+    std::vector<double> v;
+    for (auto& h : hyp) v.push_back(h.logw);
+    double z = lse(v);
+    size_t keep = hyp.size();
+    if (tau > 0.0) {
+      keep = 1;
+      while (keep < hyp.size() && std::exp(hyp[keep].logw - z) >= tau) ++keep;
+    }
+    hyp.resize(keep);
+    v.resize(keep);
+    z = lse(v);
+    for (auto& h : hyp) h.logw -= z;
+    gc();
+    return 0;
+  }
+
+  // ---- estimate: MAP cardinality, then the most likely hypothesis of that size --------
+  int estimate(int cap, int32_t* n_out, int32_t* labels, double* means, double* rho, int rho_cap) {
+    size_t nmax = 0;
+    for (auto& h : hyp) nmax = std::max(nmax, h.inst.size());
+    std::vector<double> r(nmax + 1, 0.0);
+    for (auto& h : hyp) r[h.inst.size()] += std::exp(h.logw);
+    size_t best = 0;
+    for (size_t n = 1; n <= nmax; ++n)
+      if (r[n] > r[best]) best = n;
+    if (rho)
+      for (int n = 0; n < rho_cap; ++n) rho[n] = n <= (int)nmax ? r[n] : 0.0;
+    for (auto& h : hyp)
+      if (h.inst.size() == best) {
+        if ((int)best > cap) return -2;
+        *n_out = (int32_t)best;
+        for (size_t j = 0; j < best; ++j) {
+          const Inst& x = inst[h.inst[j]];
+          labels[2 * j] = x.lab.kb;
+          labels[2 * j + 1] = x.lab.idx;
+          for (int d = 0; d < 4; ++d) means[4 * j + d] = x.m[d];
+        }
+        return 0;
+      }
+    *n_out = 0;
+    return 0;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+// params: dt, q, sigma, ps, gamma, kappa, gate, b_rmax, b_rate, b_sigv, b_rumax, b_clusterd, hmax, tau
+void* orc_create(const double* a) {
+  Oracle* o = new Oracle();
+  o->p = Params{a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7], a[8], a[9], a[10], a[11], (int)a[12], a[13]};
+  Hyp h;
+  h.logw = 0.0;
+  h.parent = 0;
+  o->hyp.push_back(h);
+  return o;
+}
+
+void orc_destroy(void* h) { delete static_cast<Oracle*>(h); }
+
+void orc_set_hmax(void* h, int hmax, double tau) {
+  static_cast<Oracle*>(h)->p.hmax = hmax;
+  static_cast<Oracle*>(h)->p.tau = tau;
+}
+
+int orc_import(void* hd, int n_inst, const int32_t* lab, const double* m, const double* P, int n_hyp,
+               const double* logw, const int32_t* off, const int32_t* idx, int n_birth, const int32_t* blab,
+               const double* bm, const double* bP, const double* br) {
+  Oracle* o = static_cast<Oracle*>(hd);
+  o->inst.assign(n_inst, Inst{});
+  for (int u = 0; u < n_inst; ++u) {
+    o->inst[u].lab = {lab[2 * u], lab[2 * u + 1]};
+    std::memcpy(o->inst[u].m, m + 4 * u, 4 * sizeof(double));
+    std::memcpy(o->inst[u].P, P + 16 * u, 16 * sizeof(double));
+    o->inst[u].src = u;
+  }
+  o->hyp.assign(n_hyp, Hyp{});
+  for (int h = 0; h < n_hyp; ++h) {
+    o->hyp[h].logw = logw[h];
+    o->hyp[h].parent = h;
+    for (int j = off[h]; j < off[h + 1]; ++j) o->hyp[h].inst.push_back(idx[j]);
+    o->sort_by_label(o->hyp[h].inst);
+  }
+  o->births.assign(n_birth, Birth{});
+  for (int b = 0; b < n_birth; ++b) {
+    o->births[b].lab = {blab[2 * b], blab[2 * b + 1]};
+    std::memcpy(o->births[b].m, bm + 4 * b, 4 * sizeof(double));
+    std::memcpy(o->births[b].P, bP + 16 * b, 16 * sizeof(double));
+    o->births[b].r = br[b];
+  }
+  return 0;
+}
+
+int orc_predict(void* h, int k) { return static_cast<Oracle*>(h)->predict(k); }
+int orc_update(void* h, int k, const double* z, int M) { return static_cast<Oracle*>(h)->update(k, z, M); }
+int orc_truncate(void* h, int hmax, double tau) { return static_cast<Oracle*>(h)->truncate(hmax, tau); }
+int orc_estimate(void* h, int cap, int32_t* n, int32_t* labels, double* means, double* rho, int rho_cap) {
+  return static_cast<Oracle*>(h)->estimate(cap, n, labels, means, rho, rho_cap);
+}
+
+// sizes: [n_inst, n_hyp, n_birth, n_idx, last_M, n_S_total, n_pairs]
+void orc_sizes(void* hd, int64_t* s) {
+  Oracle* o = static_cast<Oracle*>(hd);
+  int64_t nidx = 0, ns = 0;
+  for (auto& h : o->hyp) nidx += (int64_t)h.inst.size();
+  for (auto& x : o->inst) ns += (int64_t)x.S.size();
+  s[0] = (int64_t)o->inst.size();
+  s[1] = (int64_t)o->hyp.size();
+  s[2] = (int64_t)o->births.size();
+  s[3] = nidx;
+  s[4] = o->last_M;
+  s[5] = ns;
+  s[6] = (int64_t)o->d_pair_u.size();
+}
+
+void orc_export(void* hd, int32_t* lab, double* m, double* P, int32_t* src, int32_t* s_off, int32_t* s_idx,
+                double* logw, int32_t* off, int32_t* idx, int32_t* parent, int32_t* theta, int32_t* blab,
+                double* bm, double* bP, double* br) {
+  Oracle* o = static_cast<Oracle*>(hd);
+  int32_t so = 0;
+  for (size_t u = 0; u < o->inst.size(); ++u) {
+    const Inst& x = o->inst[u];
+    lab[2 * u] = x.lab.kb;
+    lab[2 * u + 1] = x.lab.idx;
+    std::memcpy(m + 4 * u, x.m, 4 * sizeof(double));
+    std::memcpy(P + 16 * u, x.P, 16 * sizeof(double));
+    src[u] = x.src;
+    s_off[u] = so;
+    for (int32_t i : x.S) s_idx[so++] = i;
+  }
+  s_off[o->inst.size()] = so;
+  int32_t j = 0;
+  for (size_t h = 0; h < o->hyp.size(); ++h) {
+    const Hyp& y = o->hyp[h];
+    logw[h] = y.logw;
+    off[h] = j;
+    for (int32_t u : y.inst) idx[j++] = u;
+    parent[h] = y.parent;
+    if (theta)
+      for (int i = 0; i < o->last_M; ++i)
+        theta[(size_t)h * o->last_M + i] = (int)y.theta.size() == o->last_M ? y.theta[i] : -2;
+  }
+  off[o->hyp.size()] = j;
+  for (size_t b = 0; b < o->births.size(); ++b) {
+    const Birth& x = o->births[b];
+    blab[2 * b] = x.lab.kb;
+    blab[2 * b + 1] = x.lab.idx;
+    std::memcpy(bm + 4 * b, x.m, 4 * sizeof(double));
+    std::memcpy(bP + 16 * b, x.P, 16 * sizeof(double));
+    br[b] = x.r;
+  }
+}
+
+// diagnostics of the last update: per parent (best child, log pi), per measurement r_U,
+// scalars [retained mass, gated pair count, lost mass]
+void orc_diag(void* hd, double* best, double* logpi, double* ru, double* scal) {
+  Oracle* o = static_cast<Oracle*>(hd);
+  for (size_t h = 0; h < o->d_best.size(); ++h) {
+    best[h] = o->d_best[h];
+    logpi[h] = o->d_logpi[h];
+  }
+  for (size_t i = 0; i < o->d_ru.size(); ++i) ru[i] = o->d_ru[i];
+  scal[0] = o->d_retained;
+  scal[1] = (double)o->d_gated;
+  scal[2] = o->d_lost;
+}
+
+// association marginals of the last update over gated pairs: instance (input index),
+// measurement, phi, pair mass m_ui = sum_{h contains u} pi_h q_hi(u), existence sum_{h contains u} pi_h
+void orc_pairs(void* hd, int32_t* u, int32_t* i, double* phi, double* mass, double* exist) {
+  Oracle* o = static_cast<Oracle*>(hd);
+  for (size_t k = 0; k < o->d_pair_u.size(); ++k) {
+    u[k] = o->d_pair_u[k];
+    i[k] = o->d_pair_i[k];
+    phi[k] = o->d_pair_phi[k];
+    mass[k] = o->d_pair_mass[k];
+    exist[k] = o->d_pair_exist[k];
+  }
+}
+
+// pairs (instance input index, measurement) that the next update removes from its option sets
+void orc_set_skip(void* hd, int n, const int32_t* u, const int32_t* i) {
+  Oracle* o = static_cast<Oracle*>(hd);
+  o->skip.clear();
+  for (int k = 0; k < n; ++k) o->skip.push_back({u[k], i[k]});
+}
+
+}  // extern "C"

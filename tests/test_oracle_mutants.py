@@ -1,0 +1,45 @@
+"""The oracle's pins are sensitive: every planted mistake (a dropped term, a wrong sign,
+a wrong coefficient, a transposed operand, a missing search rule, a wrong tie-break,
+a missing cap) built into a copy of the oracle on the CPU fails at least one pin."""
+import functools
+import os
+
+import pytest
+
+from oracle import oracle as orc
+from tests import test_oracle_pins as pins
+
+PINS = [
+    lambda: pins.test_predict_moments_match_van_loan(),
+    lambda: pins.test_pair_loglik_matches_scipy_and_gate(),
+    lambda: [pins.test_update_matches_bruteforce(s) for s in range(12)],
+    lambda: [pins.test_predict_matches_bruteforce(s) for s in range(8)],
+    lambda: pins.test_predict_structural_ties_use_canonical_key(),
+    lambda: pins.test_predict_cross_parent_tie_goes_to_lower_rank(),
+    lambda: pins.test_single_object_reduces_to_kalman_filter(),
+    lambda: pins.test_births_from_unexplained_measurements(),
+]
+
+MUTANTS = {
+    1: "miss term -gamma|J| dropped",
+    2: "Kalman correction with the wrong sign",
+    3: "process-noise cross term dt^2/3",
+    4: "best-first successor rule (c) missing",
+    5: "log|S| without the factor 1/2",
+    6: "innovation covariance entries transposed in the gate",
+    7: "tie-break by parent rank reversed",
+    8: "birth existence not capped",
+}
+
+
+@pytest.mark.parametrize("mutant", sorted(MUTANTS))
+def test_planted_mistake_is_caught(mutant, tmp_path, monkeypatch):
+    lib = orc.build(out=os.path.join(str(tmp_path), "liboracle_m%d.so" % mutant), mutant=mutant)
+    monkeypatch.setattr(pins, "Oracle", functools.partial(orc.Oracle, lib=lib))
+    failed = 0
+    for pin in PINS:
+        try:
+            pin()
+        except AssertionError:
+            failed += 1
+    assert failed > 0, "planted mistake %d (%s) passed every pin" % (mutant, MUTANTS[mutant])
