@@ -755,7 +755,7 @@ struct Oracle {
     for (int32_t i : seeds) {
       bool placed = false;
       for (auto& c : cl) {
-        const double dx = z[2 * i] - z[2 * c[0]], dy = z[2 * i + 1] - z[2 * c[0]];
+        const double dx = z[2 * i] - z[2 * c[0]], dy = z[2 * i + 1] - z[2 * c[0] + 1];
         if (std::sqrt(dx * dx + dy * dy) <= p.b_clusterd) {
           c.push_back(i);
           placed = true;

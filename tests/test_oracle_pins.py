@@ -281,6 +281,18 @@ def test_births_from_unexplained_measurements():
     np.testing.assert_allclose(out["birth_m"][1], [50, 40, 0, 0], atol=1e-12)
     np.testing.assert_allclose(out["birth_P"][0].reshape(4, 4), np.diag([0.5, 0.5, 4.0, 4.0]), atol=1e-12)
     np.testing.assert_allclose(out["birth_r"], [min(0.5, 0.5 * 2 / 3), min(0.5, 0.5 * 1 / 3)], atol=1e-12)
+    # clustering uses the Euclidean distance to the first seed of a cluster (both coordinates):
+    # (20, 70) -> (21, 71.5) is 1.8 m away and joins; (24, 52) is 18 m away although its x is
+    # close; (60, 12) starts a cluster, (60.5, 14.5) is 2.55 m from it and joins
+    o = Oracle(p)
+    o.import_state(sc.empty_state())
+    z = np.array([[20.0, 70.0], [21.0, 71.5], [24.0, 52.0], [60.0, 12.0], [60.5, 14.5]], np.float32)
+    o.predict(0)
+    o.update(0, z)
+    out = o.export_state()
+    assert out["birth_lab"].tolist() == [[1, 0], [1, 1], [1, 2]]
+    zz = z.astype(np.float64)
+    np.testing.assert_allclose(out["birth_m"][:, :2], [zz[0:2].mean(0), zz[2], zz[3:5].mean(0)], atol=1e-12)
 
 
 # --------------------------------------------------------------------------- invariants
