@@ -1,0 +1,160 @@
+/*
+ * glmb.h -- C ABI of the MI355X (gfx950) multi-detection GLMB hot path.
+ *
+ * The library implements one time step of the labeled multi-object filter of
+ * arXiv 2512.06230 (Sec. 3): prediction (survival + LMB birth), the update with a
+ * measurement set in which one object may produce several detections (Eq. 2 entries,
+ * factorised hypothesis weights, Kalman update of every (track, detection set)), the
+ * truncation to the H_max best hypotheses with tau pruning, and the state estimate.
+ * All arithmetic runs in hand-written HIP kernels on the stream given at creation.
+ *
+ * Conventions for every entry point:
+ *   - Return value: a glmb_status; nothing crosses the ABI as an exception.
+ *   - Argument errors (GLMB_E_ARG) and capacity errors (GLMB_E_CAPACITY) detected before
+ *     any device work leave the filter state unchanged.  A capacity overflow detected
+ *     during a step (GLMB_E_CAPACITY) and device failures (GLMB_E_DEVICE) leave the
+ *     state undefined: re-import a state before the next step.
+ *   - "device pointer" arguments must point to memory of the context's device and stay
+ *     valid until the context's stream has executed the call; "host pointer" arguments
+ *     are read or written before the call returns.  The caller owns all its buffers.
+ *   - One context per stream; a context must not be used from two threads at once.
+ *   - glmb_last_error() returns a human-readable message for the last failure.
+ */
+#ifndef GLMB_H
+#define GLMB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GLMB_OK = 0,
+  GLMB_E_ARG = -1,       /* invalid argument (null pointer, negative size, NaN, bad label order) */
+  GLMB_E_CAPACITY = -2,  /* a configured capacity would be exceeded                              */
+  GLMB_E_NOMEM = -3,     /* device allocation failed                                             */
+  GLMB_E_DEVICE = -4,    /* a HIP call failed                                                    */
+  GLMB_E_STATE = -5      /* call not valid in the current state (e.g. destroyed context)         */
+} glmb_status;
+
+/* Model and filter parameters (Sec. 3; constant-velocity state [px, py, vx, vy]). */
+typedef struct {
+  float dt;               /* scan interval (s)                                                */
+  float q;                /* white-noise acceleration intensity of the motion model           */
+  float sigma_z;          /* detection noise std (m), R = sigma_z^2 I                         */
+  float p_survive;        /* per-scan survival probability of a track                         */
+  float det_rate;         /* gamma: expected detections per object (Poisson); plays P_D's role */
+  float clutter_density;  /* kappa: clutter intensity per unit area (> 0)                     */
+  float gate_d2;          /* Mahalanobis gate: a pair is compatible iff d^2 <= gate_d2        */
+  float birth_r_max;      /* cap of a birth component's existence probability                 */
+  float birth_rate;       /* expected births per scan, shared over the birth clusters         */
+  float birth_sigma_v;    /* velocity std of a new track (m/s)                                */
+  float birth_ru_max;     /* a detection seeds a birth if P(not clutter) < birth_ru_max       */
+  float birth_cluster_d;  /* seeds within this distance of a cluster's first seed join it     */
+  int32_t h_max;          /* hypotheses kept by predict and by update                         */
+  float tau;              /* weight threshold applied after normalising over the kept set     */
+  int32_t cap_nodes;      /* selection search nodes (0: 1<<22)                                */
+  int32_t cap_labels;     /* distinct labels alive at once (0: 8192)                          */
+} glmb_params;
+
+typedef struct glmb_ctx glmb_ctx;
+
+/* Host-side description of a GLMB (used by import, export and warm start).
+ * Instances: n_inst Gaussian track densities, inst_lab[2*u] = birth scan, inst_lab[2*u+1] =
+ * index within that scan; inst_m[4*u], inst_P[16*u] row-major.  Hypotheses: hyp_logw[h]
+ * (need not be normalised; the order is the rank order), the instances of hypothesis h are
+ * hyp_idx[hyp_off[h] .. hyp_off[h+1]) (distinct labels).  Pending births for the next
+ * predict: birth_lab/m/P as above and existence probability birth_r.  On export the library
+ * also fills inst_src (the input index the instance derives from), inst_nz and
+ * inst_z (number and indices of the detections of the last update, at most 8 per
+ * instance are listed), hyp_parent (input index of the hypothesis it derives from). */
+typedef struct {
+  int32_t n_inst, n_hyp, n_idx, n_birth;
+  int32_t* inst_lab;
+  float* inst_m;
+  float* inst_P;
+  int32_t* inst_src;   /* export only (may be NULL) */
+  int32_t* inst_nz;    /* export only (may be NULL) */
+  int32_t* inst_z;     /* export only, 8 per instance (may be NULL) */
+  float* hyp_logw;
+  int32_t* hyp_off;
+  int32_t* hyp_idx;
+  int32_t* hyp_parent; /* export only (may be NULL) */
+  int32_t* birth_lab;
+  float* birth_m;
+  float* birth_P;
+  float* birth_r;
+} glmb_state_host;
+
+/* Per-step statistics of the last update (filled by glmb_stats, which synchronises). */
+typedef struct {
+  int32_t n_hyp_in, n_hyp_out, n_meas, n_inst_in, n_inst_out, n_labels;
+  int64_t gated_pairs;      /* (instance, measurement) pairs inside the gate              */
+  int64_t option_terms;     /* sum over (hypothesis, measurement) cells of options        */
+  int64_t dense_triples;    /* sum_h |J_h| * M                                           */
+  int32_t search_nodes, search_levels, n_births;
+  double retained_mass;     /* posterior mass of the kept hypotheses                     */
+  double lost_mass;         /* posterior mass removed by the learned proposal (0 if plain) */
+} glmb_step_stats;
+
+/* Library / status utilities */
+const char* glmb_status_string(glmb_status s);
+const char* glmb_last_error(const glmb_ctx* ctx);
+
+/* Create a filter on HIP device `device` using `hip_stream` (a hipStream_t, or NULL for the
+ * null stream) for every launch.  The context holds one hypothesis with no tracks. */
+glmb_status glmb_create(const glmb_params* params, int device, void* hip_stream, glmb_ctx** out);
+glmb_status glmb_destroy(glmb_ctx* ctx);
+
+/* Replace the filter state by a host description (labels of hypotheses must be distinct;
+ * birth labels must sort after every instance label). Synchronises. */
+glmb_status glmb_import_state(glmb_ctx* ctx, const glmb_state_host* s);
+/* Sizes of the current state, for allocating an export: n_inst, n_hyp, n_idx, n_birth. */
+glmb_status glmb_state_sizes(glmb_ctx* ctx, int32_t* n_inst, int32_t* n_hyp, int32_t* n_idx, int32_t* n_birth);
+/* Copy the state to caller-allocated host arrays sized by glmb_state_sizes. Synchronises. */
+glmb_status glmb_export_state(glmb_ctx* ctx, glmb_state_host* s);
+
+/* Prediction to scan k (Sec. 3, prediction): Kalman prediction of every track, the pending
+ * birth components join, and the h_max most likely survive/die x include/exclude children of
+ * every hypothesis are kept; identical track sets are merged. */
+glmb_status glmb_predict(glmb_ctx* ctx, int32_t k);
+
+/* Update with the M detections of scan k (Sec. 3, Eq. 2 to the end of Sec. 3).
+ * z_dev: device pointer, float32 [M][2] (x, y), caller-owned, stream-ordered.
+ * Computes every gated (track, detection) entry of Eq. 2, the factorised weight of every
+ * association map of every hypothesis, keeps the exact h_max best maps (log-weight
+ * descending, canonical key ascending), applies tau, runs the Kalman update of every
+ * distinct (track, detection set), and derives the birth components for scan k+1. */
+glmb_status glmb_update(glmb_ctx* ctx, int32_t k, const float* z_dev, int32_t M);
+
+/* Keep the h_max first hypotheses, renormalise, drop weights below tau (the first is kept),
+ * renormalise again (Sec. 3 end). Idempotent. */
+glmb_status glmb_truncate(glmb_ctx* ctx, int32_t h_max, float tau);
+
+/* State estimate: maximum a posteriori cardinality n, then the most likely hypothesis with
+ * n tracks.  Host buffers: labels_out[2*cap], means_out[4*cap]; *n_out receives n.
+ * Returns GLMB_E_CAPACITY if n > cap. Synchronises. */
+glmb_status glmb_estimate(glmb_ctx* ctx, int32_t cap, int32_t* n_out, int32_t* labels_out, float* means_out);
+
+/* Statistics of the last update. Synchronises. */
+glmb_status glmb_stats(glmb_ctx* ctx, glmb_step_stats* out);
+
+/* Diagnostics of the last update, for parity checks (host buffers, sized by the predicted
+ * hypothesis count H and the detection count M of that update):
+ * best[h] = log weight of hypothesis h's best child minus the log normaliser of every child
+ * of every hypothesis; logpi[h] = log posterior mass of h's children; ru[i] = posterior
+ * probability that detection i is not clutter. Synchronises. */
+glmb_status glmb_update_diag(glmb_ctx* ctx, int32_t H, int32_t M, float* best, float* logpi, float* ru);
+
+/* Association maps of the hypotheses produced by the last update: theta[h*M + i] is the
+ * input index of the predicted instance that detection i is assigned to, -1 for clutter.
+ * Host buffer of n_hyp*M int32. Synchronises. */
+glmb_status glmb_update_theta(glmb_ctx* ctx, int32_t n_hyp, int32_t M, int32_t* theta);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GLMB_H */

@@ -1,0 +1,528 @@
+// C ABI of libglmb: argument checks, state import/export, truncation, estimate and
+// diagnostics.  Every entry point converts internal errors to a glmb_status.
+#include <algorithm>
+#include <climits>
+#include <cstdlib>
+#include <map>
+
+#include "ctx.hpp"
+
+struct glmb_ctx {
+  glmb::Ctx c;
+};
+
+namespace glmb {
+
+// ------------------------------------------------------------------ truncation
+__device__ __forceinline__ float tsum(float v, float* sh) {
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  __syncthreads();
+  if (lane_id() == 0) sh[threadIdx.x / kWave] = v;
+  __syncthreads();
+  float r = 0.0f;
+  for (int j = 0; j < (int)(blockDim.x / kWave); ++j) r += sh[j];
+  return r;
+}
+
+// one block: normalise the first n weights, keep those >= tau (the first always), renormalise
+__global__ __launch_bounds__(1024) void k_truncate(int n, float tau, float* logw, int32_t* nkeep) {
+  __shared__ float red[32];
+  __shared__ int32_t cnt;
+  const float mx = logw[0];
+  float s = 0.0f;
+  for (int h = threadIdx.x; h < n; h += blockDim.x) s += __expf(logw[h] - mx);
+  s = tsum(s, red);
+  const float L = mx + __logf(s);
+  if (threadIdx.x == 0) cnt = 1;
+  __syncthreads();
+  int mine = 0;
+  for (int h = 1 + threadIdx.x; h < n; h += blockDim.x)
+    if (tau <= 0.0f || __expf(logw[h] - L) >= tau) ++mine;
+  if (mine) atomicAdd(&cnt, mine);
+  __syncthreads();
+  const int keep = cnt;
+  float s2 = 0.0f;
+  for (int h = threadIdx.x; h < keep; h += blockDim.x) s2 += __expf(logw[h] - mx);
+  s2 = tsum(s2, red + 16);
+  const float L2 = mx + __logf(s2);
+  __syncthreads();
+  for (int h = threadIdx.x; h < keep; h += blockDim.x) logw[h] -= L2;
+  if (threadIdx.x == 0) *nkeep = keep;
+}
+
+void stage_truncate(Ctx& c, int hmax, float tau) {
+  const int n = std::min(c.nhyp, hmax);
+  int32_t* scal = need<int32_t>(c.scal, 64);
+  GLMB_LAUNCH(k_truncate, 1, 1024, 0, c.s, n, tau, c.logw.as<float>(), scal + 15);
+  int32_t keep = 0;
+  GLMB_HIP(hipMemcpyAsync(&keep, scal + 15, sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
+  GLMB_HIP(hipStreamSynchronize(c.s));
+  c.nhyp = keep;
+}
+
+// ------------------------------------------------------------------ estimate
+__global__ __launch_bounds__(1024) void k_estimate(int H, const float* logw, const int32_t* ntrk, int32_t* out) {
+  __shared__ float red[32];
+  __shared__ int32_t ired[32];
+  // range of track counts
+  int lo = INT_MAX, hi = -1;
+  for (int h = threadIdx.x; h < H; h += blockDim.x) {
+    lo = min(lo, ntrk[h]);
+    hi = max(hi, ntrk[h]);
+  }
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    lo = min(lo, __shfl_xor(lo, d, kWave));
+    hi = max(hi, __shfl_xor(hi, d, kWave));
+  }
+  if (lane_id() == 0) {
+    ired[threadIdx.x / kWave] = lo;
+    ired[16 + threadIdx.x / kWave] = hi;
+  }
+  __syncthreads();
+  lo = INT_MAX;
+  hi = -1;
+  for (int j = 0; j < (int)(blockDim.x / kWave); ++j) {
+    lo = min(lo, ired[j]);
+    hi = max(hi, ired[16 + j]);
+  }
+  __syncthreads();
+  // cardinality distribution, one fixed-order reduction per count; MAP with ties to the smaller
+  float best = -1.0f;
+  int nbest = lo;
+  for (int n = lo; n <= hi; ++n) {
+    float s = 0.0f;
+    for (int h = threadIdx.x; h < H; h += blockDim.x)
+      if (ntrk[h] == n) s += __expf(logw[h]);
+    s = tsum(s, red);
+    if (s > best) {
+      best = s;
+      nbest = n;
+    }
+  }
+  // most likely hypothesis of that size (rows are in rank order)
+  int first = INT_MAX;
+  for (int h = threadIdx.x; h < H; h += blockDim.x)
+    if (ntrk[h] == nbest) {
+      first = h;
+      break;
+    }
+  for (int d = kWave / 2; d > 0; d >>= 1) first = min(first, __shfl_xor(first, d, kWave));
+  __syncthreads();
+  if (lane_id() == 0) ired[threadIdx.x / kWave] = first;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int f = INT_MAX;
+    for (int j = 0; j < (int)(blockDim.x / kWave); ++j) f = min(f, ired[j]);
+    out[0] = nbest;
+    out[1] = f;
+  }
+}
+
+}  // namespace glmb
+
+using glmb::Ctx;
+using glmb::DInst;
+using glmb::DBirth;
+using glmb::Error;
+
+namespace {
+
+glmb_status fail(glmb_ctx* x, glmb_status st, const std::string& msg) {
+  if (x) x->c.err = msg;
+  return st;
+}
+
+template <class F>
+glmb_status guarded(glmb_ctx* x, F&& f) {
+  if (!x) return GLMB_E_ARG;
+  if (!x->c.alive) return fail(x, GLMB_E_STATE, "context is not usable");
+  try {
+    GLMB_HIP(hipSetDevice(x->c.device));
+    f(x->c);
+    return GLMB_OK;
+  } catch (const Error& e) {
+    x->c.err = e.msg;
+    if (e.st == GLMB_E_DEVICE) x->c.alive = false;
+    return e.st;
+  } catch (const std::exception& e) {
+    x->c.err = e.what();
+    return GLMB_E_STATE;
+  }
+}
+
+float log_sum_exp(const std::vector<double>& v) {
+  double m = -INFINITY;
+  for (double x : v) m = std::max(m, x);
+  double s = 0.0;
+  for (double x : v) s += std::exp(x - m);
+  return (float)(m + std::log(s));
+}
+
+void upload_state(Ctx& c, const std::vector<std::pair<int32_t, int32_t>>& labs, const std::vector<DInst>& inst,
+                  const std::vector<int32_t>& rows, const std::vector<float>& logw, const std::vector<int32_t>& ntrk,
+                  const std::vector<DBirth>& births, const std::vector<std::pair<int32_t, int32_t>>& blab) {
+  hipStream_t s = c.s;
+  const int H = (int)logw.size();
+  c.slot_lab = labs;
+  c.nslot = (int)labs.size();
+  c.stride = c.nslot;
+  c.ninst = (int)inst.size();
+  c.nhyp = H;
+  c.nbirth = (int)births.size();
+  c.birth_lab = blab;
+  auto up = [&](glmb::DevBuf& b, const void* src, size_t bytes) {
+    b.reserve(std::max<size_t>(bytes, 64));
+    if (bytes) GLMB_HIP(hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, s));
+  };
+  up(c.inst, inst.data(), inst.size() * sizeof(DInst));
+  up(c.rows, rows.data(), rows.size() * sizeof(int32_t));
+  up(c.logw, logw.data(), logw.size() * sizeof(float));
+  up(c.ntrk, ntrk.data(), ntrk.size() * sizeof(int32_t));
+  up(c.births, births.data(), births.size() * sizeof(DBirth));
+  std::vector<int32_t> par(H);
+  for (int h = 0; h < H; ++h) par[h] = h;
+  up(c.hparent, par.data(), par.size() * sizeof(int32_t));
+  GLMB_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* glmb_status_string(glmb_status s) {
+  switch (s) {
+    case GLMB_OK: return "ok";
+    case GLMB_E_ARG: return "invalid argument";
+    case GLMB_E_CAPACITY: return "capacity exceeded";
+    case GLMB_E_NOMEM: return "device allocation failed";
+    case GLMB_E_DEVICE: return "HIP error";
+    case GLMB_E_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char* glmb_last_error(const glmb_ctx* x) { return x ? x->c.err.c_str() : "null context"; }
+
+glmb_status glmb_create(const glmb_params* p, int device, void* stream, glmb_ctx** out) {
+  if (!p || !out) return GLMB_E_ARG;
+  *out = nullptr;
+  if (!(p->sigma_z > 0) || !(p->clutter_density > 0) || !(p->det_rate > 0) || !(p->gate_d2 > 0) || p->h_max < 1 ||
+      !(p->p_survive >= 0 && p->p_survive <= 1) || !(p->dt > 0) || !(p->q >= 0) || !(p->tau >= 0 && p->tau < 1) ||
+      !(p->birth_r_max >= 0 && p->birth_r_max <= 1) || p->cap_nodes < 0 || p->cap_labels < 0)
+    return GLMB_E_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return GLMB_E_DEVICE;
+  glmb_ctx* x = new glmb_ctx();
+  x->c.p = *p;
+  if (x->c.p.cap_labels == 0) x->c.p.cap_labels = 4096;
+  x->c.device = device;
+  x->c.s = (hipStream_t)stream;
+  const char* tr = std::getenv("GLMB_TRACE");
+  x->c.trace = tr && tr[0] && tr[0] != '0';
+  glmb_status st = guarded(x, [&](Ctx& c) {
+    // one hypothesis without tracks
+    upload_state(c, {}, {}, {}, {0.0f}, {0}, {}, {});
+  });
+  if (st != GLMB_OK) {
+    delete x;
+    return st;
+  }
+  *out = x;
+  return GLMB_OK;
+}
+
+glmb_status glmb_destroy(glmb_ctx* x) {
+  if (!x) return GLMB_E_ARG;
+  (void)hipSetDevice(x->c.device);
+  (void)hipStreamSynchronize(x->c.s);
+  glmb::Ctx& c = x->c;
+  glmb::DevBuf* bufs[] = {&c.inst, &c.inst2, &c.inst_nz, &c.inst_z, &c.logw, &c.ntrk, &c.rows, &c.hparent, &c.logw2,
+                          &c.ntrk2, &c.rows2, &c.births, &c.diag_best, &c.diag_logpi, &c.diag_ru, &c.prev_rows,
+                          &c.prev_src, &c.child_par, &c.dev_off, &c.dev_i, &c.dev_slot, &c.z, &c.cmax, &c.gbits,
+                          &c.phi, &c.lbits, &c.lpre, &c.llen, &c.loff, &c.lmeas, &c.inst_beg, &c.ccnt, &c.coff,
+                          &c.cand, &c.best16, &c.dev1, &c.lserel, &c.bprime, &c.lzprime, &c.vals, &c.cells,
+                          &c.ccount, &c.coff2, &c.it_h, &c.it_delta, &c.it_group, &c.it_opt, &c.it_off, &c.keys,
+                          &c.vals32, &c.scal, &c.sel_logw, &c.hp_map, &c.first, &c.dmask, &c.exc, &c.cmod, &c.recs,
+                          &c.rec_keys, &c.rec_vals, &c.ids, &c.row_mark, &c.ru_part, &c.ru, &c.bt, &c.tmp, &c.tk,
+                          &c.tv, &c.flags, &c.pre, &c.pmult, &c.pvals, &c.sb.nd_parent, &c.sb.nd_item, &c.sb.nd_h,
+                          &c.sb.nd_value, &c.sb.cnt, &c.sb.pre, &c.sb.pre64, &c.sb.flags, &c.sb.map, &c.sb.tmp,
+                          &c.sb.tk, &c.sb.tv, &c.sb.keys, &c.sb.vals, &c.sb.sel_node, &c.sb.sel_val, &c.sb.sel_rank,
+                          &c.sb.scal};
+  for (auto* b : bufs) b->release();
+  delete x;
+  return GLMB_OK;
+}
+
+glmb_status glmb_import_state(glmb_ctx* x, const glmb_state_host* s) {
+  if (!x || !s) return GLMB_E_ARG;
+  if (s->n_inst < 0 || s->n_hyp < 1 || s->n_birth < 0 || (s->n_inst > 0 && (!s->inst_lab || !s->inst_m || !s->inst_P)) ||
+      !s->hyp_logw || !s->hyp_off || (s->n_birth > 0 && (!s->birth_lab || !s->birth_m || !s->birth_P || !s->birth_r)))
+    return fail(x, GLMB_E_ARG, "null pointer or negative count in the state");
+  const int N = s->n_inst, H = s->n_hyp;
+  if (s->hyp_off[0] != 0) return fail(x, GLMB_E_ARG, "hyp_off[0] must be 0");
+  for (int h = 0; h < H; ++h)
+    if (s->hyp_off[h + 1] < s->hyp_off[h]) return fail(x, GLMB_E_ARG, "hyp_off must be non-decreasing");
+  if (s->hyp_off[H] > 0 && !s->hyp_idx) return fail(x, GLMB_E_ARG, "null hyp_idx");
+  // labels -> slots
+  std::map<std::pair<int32_t, int32_t>, int32_t> slot;
+  for (int u = 0; u < N; ++u) slot[{s->inst_lab[2 * u], s->inst_lab[2 * u + 1]}] = 0;
+  std::vector<std::pair<int32_t, int32_t>> labs;
+  for (auto& kv : slot) {
+    kv.second = (int32_t)labs.size();
+    labs.push_back(kv.first);
+  }
+  if ((int)labs.size() > x->c.p.cap_labels || (int)labs.size() > 32766)
+    return fail(x, GLMB_E_CAPACITY, "more labels than cap_labels");
+  std::vector<int32_t> order(N);
+  for (int u = 0; u < N; ++u) order[u] = u;
+  std::vector<int32_t> us(N);
+  for (int u = 0; u < N; ++u) us[u] = slot[{s->inst_lab[2 * u], s->inst_lab[2 * u + 1]}];
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return us[a] < us[b]; });
+  std::vector<int32_t> nid(N);
+  std::vector<DInst> inst(N);
+  for (int k = 0; k < N; ++k) {
+    const int u = order[k];
+    nid[u] = k;
+    DInst d{};
+    for (int j = 0; j < 4; ++j) {
+      d.m[j] = s->inst_m[4 * u + j];
+      if (!std::isfinite(d.m[j])) return fail(x, GLMB_E_ARG, "non-finite instance mean");
+    }
+    const float* P = s->inst_P + 16 * u;
+    const int ij[10][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {1, 1}, {1, 2}, {1, 3}, {2, 2}, {2, 3}, {3, 3}};
+    for (int t = 0; t < 10; ++t) d.P[t] = P[4 * ij[t][0] + ij[t][1]];
+    d.slot = us[u];
+    d.src = u;
+    inst[k] = d;
+  }
+  const int NS = (int)labs.size();
+  std::vector<int32_t> rows((size_t)H * NS, -1);
+  std::vector<int32_t> ntrk(H);
+  std::vector<double> lw(H);
+  for (int h = 0; h < H; ++h) {
+    lw[h] = s->hyp_logw[h];
+    if (!(lw[h] > -INFINITY) || std::isnan(lw[h])) return fail(x, GLMB_E_ARG, "non-finite hypothesis weight");
+    for (int j = s->hyp_off[h]; j < s->hyp_off[h + 1]; ++j) {
+      const int u = s->hyp_idx[j];
+      if (u < 0 || u >= N) return fail(x, GLMB_E_ARG, "instance index out of range");
+      int32_t& r = rows[(size_t)h * NS + us[u]];
+      if (r >= 0) return fail(x, GLMB_E_ARG, "a hypothesis holds a label twice");
+      r = nid[u];
+    }
+    ntrk[h] = s->hyp_off[h + 1] - s->hyp_off[h];
+  }
+  const float L = log_sum_exp(lw);
+  std::vector<float> logw(H);
+  for (int h = 0; h < H; ++h) logw[h] = (float)(lw[h] - L);
+  std::vector<DBirth> births(s->n_birth);
+  std::vector<std::pair<int32_t, int32_t>> blab(s->n_birth);
+  for (int b = 0; b < s->n_birth; ++b) {
+    blab[b] = {s->birth_lab[2 * b], s->birth_lab[2 * b + 1]};
+    if ((NS > 0 && !(labs.back() < blab[b])) || (b > 0 && !(blab[b - 1] < blab[b])))
+      return fail(x, GLMB_E_ARG, "birth labels must sort after all instance labels");
+    const float r = s->birth_r[b];
+    if (!(r >= 0.0f && r <= 1.0f)) return fail(x, GLMB_E_ARG, "birth probability outside [0, 1]");
+    DBirth d{};
+    for (int j = 0; j < 4; ++j) d.m[j] = s->birth_m[4 * b + j];
+    const float* P = s->birth_P + 16 * b;
+    const int ij[10][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {1, 1}, {1, 2}, {1, 3}, {2, 2}, {2, 3}, {3, 3}};
+    for (int t = 0; t < 10; ++t) d.P[t] = P[4 * ij[t][0] + ij[t][1]];
+    d.r = r;
+    births[b] = d;
+  }
+  return guarded(x, [&](Ctx& c) {
+    upload_state(c, labs, inst, rows, logw, ntrk, births, blab);
+    c.last_M = -1;
+  });
+}
+
+glmb_status glmb_state_sizes(glmb_ctx* x, int32_t* n_inst, int32_t* n_hyp, int32_t* n_idx, int32_t* n_birth) {
+  if (!x || !n_inst || !n_hyp || !n_idx || !n_birth) return GLMB_E_ARG;
+  return guarded(x, [&](Ctx& c) {
+    *n_inst = c.ninst;
+    *n_hyp = c.nhyp;
+    *n_birth = c.nbirth;
+    std::vector<int32_t> nt(c.nhyp);
+    if (c.nhyp) GLMB_HIP(hipMemcpyAsync(nt.data(), c.ntrk.p, c.nhyp * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
+    GLMB_HIP(hipStreamSynchronize(c.s));
+    int64_t t = 0;
+    for (int v : nt) t += v;
+    *n_idx = (int32_t)t;
+  });
+}
+
+glmb_status glmb_export_state(glmb_ctx* x, glmb_state_host* o) {
+  if (!x || !o) return GLMB_E_ARG;
+  return guarded(x, [&](Ctx& c) {
+    hipStream_t s = c.s;
+    const int U = c.ninst, H = c.nhyp, NS = c.stride, NB = c.nbirth;
+    std::vector<DInst> inst(U);
+    std::vector<int32_t> rows((size_t)H * NS), par(H), nz(U), zz((size_t)U * 8);
+    std::vector<float> logw(H);
+    std::vector<DBirth> births(NB);
+    if (U) GLMB_HIP(hipMemcpyAsync(inst.data(), c.inst.p, U * sizeof(DInst), hipMemcpyDeviceToHost, s));
+    if (H * NS) GLMB_HIP(hipMemcpyAsync(rows.data(), c.rows.p, rows.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (H) GLMB_HIP(hipMemcpyAsync(logw.data(), c.logw.p, H * sizeof(float), hipMemcpyDeviceToHost, s));
+    if (H) GLMB_HIP(hipMemcpyAsync(par.data(), c.hparent.p, H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (NB) GLMB_HIP(hipMemcpyAsync(births.data(), c.births.p, NB * sizeof(DBirth), hipMemcpyDeviceToHost, s));
+    const bool dets = c.last_M >= 0 && c.inst_nz.bytes >= (size_t)U * sizeof(int32_t) && U > 0;
+    if (dets) {
+      GLMB_HIP(hipMemcpyAsync(nz.data(), c.inst_nz.p, U * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      GLMB_HIP(hipMemcpyAsync(zz.data(), c.inst_z.p, zz.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    }
+    GLMB_HIP(hipStreamSynchronize(s));
+    if (o->n_inst < U || o->n_hyp < H || o->n_birth < NB) throw Error{GLMB_E_CAPACITY, "export arrays too small"};
+    const int ij[10][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {1, 1}, {1, 2}, {1, 3}, {2, 2}, {2, 3}, {3, 3}};
+    for (int u = 0; u < U; ++u) {
+      o->inst_lab[2 * u] = c.slot_lab[inst[u].slot].first;
+      o->inst_lab[2 * u + 1] = c.slot_lab[inst[u].slot].second;
+      for (int j = 0; j < 4; ++j) o->inst_m[4 * u + j] = inst[u].m[j];
+      for (int t = 0; t < 10; ++t) {
+        o->inst_P[16 * u + 4 * ij[t][0] + ij[t][1]] = inst[u].P[t];
+        o->inst_P[16 * u + 4 * ij[t][1] + ij[t][0]] = inst[u].P[t];
+      }
+      if (o->inst_src) o->inst_src[u] = inst[u].src;
+      if (o->inst_nz) o->inst_nz[u] = dets ? nz[u] : 0;
+      if (o->inst_z)
+        for (int j = 0; j < 8; ++j) o->inst_z[8 * u + j] = dets && j < nz[u] ? zz[(size_t)u * 8 + j] : -1;
+    }
+    int j = 0;
+    for (int h = 0; h < H; ++h) {
+      o->hyp_logw[h] = logw[h];
+      o->hyp_off[h] = j;
+      for (int sl = 0; sl < NS; ++sl) {
+        const int u = rows[(size_t)h * NS + sl];
+        if (u >= 0) {
+          if (j >= o->n_idx) throw Error{GLMB_E_CAPACITY, "export index array too small"};
+          o->hyp_idx[j++] = u;
+        }
+      }
+      if (o->hyp_parent) o->hyp_parent[h] = par[h];
+    }
+    o->hyp_off[H] = j;
+    for (int b = 0; b < NB; ++b) {
+      o->birth_lab[2 * b] = c.birth_lab[b].first;
+      o->birth_lab[2 * b + 1] = c.birth_lab[b].second;
+      for (int k = 0; k < 4; ++k) o->birth_m[4 * b + k] = births[b].m[k];
+      for (int t = 0; t < 10; ++t) {
+        o->birth_P[16 * b + 4 * ij[t][0] + ij[t][1]] = births[b].P[t];
+        o->birth_P[16 * b + 4 * ij[t][1] + ij[t][0]] = births[b].P[t];
+      }
+      o->birth_r[b] = births[b].r;
+    }
+    o->n_inst = U;
+    o->n_hyp = H;
+    o->n_idx = j;
+    o->n_birth = NB;
+  });
+}
+
+glmb_status glmb_predict(glmb_ctx* x, int32_t k) {
+  return guarded(x, [&](Ctx& c) {
+    glmb::stage_predict(c, k);
+    c.last_M = -1;
+  });
+}
+
+glmb_status glmb_update(glmb_ctx* x, int32_t k, const float* z, int32_t M) {
+  if (!x) return GLMB_E_ARG;
+  if (M < 0 || (M > 0 && !z)) return fail(x, GLMB_E_ARG, "M < 0 or null detections");
+  if (M > 32768) return fail(x, GLMB_E_CAPACITY, "more than 32768 detections in one scan");
+  return guarded(x, [&](Ctx& c) { glmb::stage_update(c, k, z, M); });
+}
+
+glmb_status glmb_truncate(glmb_ctx* x, int32_t h_max, float tau) {
+  if (!x) return GLMB_E_ARG;
+  if (h_max < 1 || !(tau >= 0.0f && tau < 1.0f)) return fail(x, GLMB_E_ARG, "h_max < 1 or tau outside [0, 1)");
+  return guarded(x, [&](Ctx& c) { glmb::stage_truncate(c, h_max, tau); });
+}
+
+glmb_status glmb_estimate(glmb_ctx* x, int32_t cap, int32_t* n_out, int32_t* labels_out, float* means_out) {
+  if (!x || !n_out || cap < 0 || (cap > 0 && (!labels_out || !means_out))) return GLMB_E_ARG;
+  glmb_status cap_err = GLMB_OK;
+  glmb_status st = guarded(x, [&](Ctx& c) {
+    int32_t* scal = glmb::need<int32_t>(c.scal, 64);
+    GLMB_LAUNCH(glmb::k_estimate, 1, 1024, 0, c.s, c.nhyp, c.logw.as<float>(), c.ntrk.as<int32_t>(), scal + 20);
+    int32_t r[2];
+    GLMB_HIP(hipMemcpyAsync(r, scal + 20, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
+    GLMB_HIP(hipStreamSynchronize(c.s));
+    const int n = r[0], h = r[1];
+    *n_out = n;
+    if (n > cap) {
+      cap_err = GLMB_E_CAPACITY;
+      return;
+    }
+    const int NS = c.stride;
+    std::vector<int32_t> row(NS);
+    if (NS) GLMB_HIP(hipMemcpyAsync(row.data(), c.rows.as<int32_t>() + (size_t)h * NS, NS * sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, c.s));
+    GLMB_HIP(hipStreamSynchronize(c.s));
+    int j = 0;
+    for (int sl = 0; sl < NS; ++sl) {
+      if (row[sl] < 0) continue;
+      DInst d;
+      GLMB_HIP(hipMemcpyAsync(&d, c.inst.as<DInst>() + row[sl], sizeof(DInst), hipMemcpyDeviceToHost, c.s));
+      GLMB_HIP(hipStreamSynchronize(c.s));
+      labels_out[2 * j] = c.slot_lab[sl].first;
+      labels_out[2 * j + 1] = c.slot_lab[sl].second;
+      for (int k = 0; k < 4; ++k) means_out[4 * j + k] = d.m[k];
+      ++j;
+    }
+  });
+  if (st == GLMB_OK && cap_err != GLMB_OK) return fail(x, cap_err, "estimate larger than cap");
+  return st;
+}
+
+glmb_status glmb_stats(glmb_ctx* x, glmb_step_stats* out) {
+  if (!x || !out) return GLMB_E_ARG;
+  return guarded(x, [&](Ctx& c) {
+    GLMB_HIP(hipStreamSynchronize(c.s));
+    *out = c.stats;
+  });
+}
+
+glmb_status glmb_update_diag(glmb_ctx* x, int32_t H, int32_t M, float* best, float* logpi, float* ru) {
+  if (!x || !best || !logpi || (M > 0 && !ru)) return GLMB_E_ARG;
+  return guarded(x, [&](Ctx& c) {
+    if (c.last_M < 0 || H != c.last_H || M != c.last_M) throw Error{GLMB_E_STATE, "no update with these sizes"};
+    GLMB_HIP(hipMemcpyAsync(best, c.diag_best.p, H * sizeof(float), hipMemcpyDeviceToHost, c.s));
+    GLMB_HIP(hipMemcpyAsync(logpi, c.diag_logpi.p, H * sizeof(float), hipMemcpyDeviceToHost, c.s));
+    if (M) GLMB_HIP(hipMemcpyAsync(ru, c.diag_ru.p, M * sizeof(float), hipMemcpyDeviceToHost, c.s));
+    GLMB_HIP(hipStreamSynchronize(c.s));
+  });
+}
+
+glmb_status glmb_update_theta(glmb_ctx* x, int32_t n_hyp, int32_t M, int32_t* theta) {
+  if (!x || (n_hyp * M > 0 && !theta)) return GLMB_E_ARG;
+  return guarded(x, [&](Ctx& c) {
+    if (c.last_M < 0 || M != c.last_M || n_hyp != c.nhyp) throw Error{GLMB_E_STATE, "no update with these sizes"};
+    hipStream_t s = c.s;
+    const int H = c.last_H, SW = c.last_stride, n = c.nhyp;
+    std::vector<int16_t> best((size_t)H * M);
+    std::vector<int32_t> prows((size_t)H * SW), psrc(std::max(1, c.stats.n_inst_in)), par(n), doff(n + 1);
+    if (H * M) GLMB_HIP(hipMemcpyAsync(best.data(), c.best16.p, best.size() * 2, hipMemcpyDeviceToHost, s));
+    if (H * SW) GLMB_HIP(hipMemcpyAsync(prows.data(), c.prev_rows.p, prows.size() * 4, hipMemcpyDeviceToHost, s));
+    if (c.stats.n_inst_in)
+      GLMB_HIP(hipMemcpyAsync(psrc.data(), c.prev_src.p, c.stats.n_inst_in * 4, hipMemcpyDeviceToHost, s));
+    GLMB_HIP(hipMemcpyAsync(par.data(), c.hparent.p, n * 4, hipMemcpyDeviceToHost, s));
+    GLMB_HIP(hipMemcpyAsync(doff.data(), c.dev_off.p, (n + 1) * 4, hipMemcpyDeviceToHost, s));
+    GLMB_HIP(hipStreamSynchronize(s));
+    const int nd = doff[n];
+    std::vector<int32_t> di(nd), dn(nd);
+    if (nd) {
+      GLMB_HIP(hipMemcpyAsync(di.data(), c.dev_i.p, nd * 4, hipMemcpyDeviceToHost, s));
+      GLMB_HIP(hipMemcpyAsync(dn.data(), c.dev_slot.p, nd * 4, hipMemcpyDeviceToHost, s));
+      GLMB_HIP(hipStreamSynchronize(s));
+    }
+    for (int h = 0; h < n; ++h) {
+      const int ph = par[h];
+      std::vector<int32_t> sl(M);
+      for (int i = 0; i < M; ++i) sl[i] = (int)best[(size_t)ph * M + i] - 1;
+      for (int q = doff[h]; q < doff[h + 1]; ++q) sl[di[q]] = dn[q];
+      for (int i = 0; i < M; ++i)
+        theta[(size_t)h * M + i] = sl[i] < 0 ? -1 : psrc[prows[(size_t)ph * SW + sl[i]]];
+    }
+  });
+}
+
+}  // extern "C"

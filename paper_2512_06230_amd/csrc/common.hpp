@@ -1,0 +1,144 @@
+// Internal declarations shared by the HIP translation units of libglmb.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/glmb.h"
+
+namespace glmb {
+
+constexpr int kWave = 64;
+constexpr int kLMax = 128;          // detections gated with one label (mask width)
+constexpr int kMaxOpts = 64;        // options of one (hypothesis, detection) cell
+constexpr int kMaxDepth = 48;       // deviations of one child
+
+struct Error {
+  glmb_status st;
+  std::string msg;
+};
+
+#define GLMB_HIP(call)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw ::glmb::Error{GLMB_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define GLMB_LAUNCH(kernel, grid, block, shmem, stream, ...)                             \
+  do {                                                                                   \
+    if ((grid) > 0) {                                                                    \
+      hipLaunchKernelGGL(kernel, dim3(grid), dim3(block), shmem, stream, __VA_ARGS__);   \
+      GLMB_HIP(hipGetLastError());                                                       \
+    }                                                                                    \
+  } while (0)
+
+inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Growable device buffer (contents are not preserved on growth unless asked).
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void reserve(size_t n, bool keep = false, hipStream_t s = nullptr) {
+    if (n <= bytes) return;
+    size_t nb = bytes ? bytes : 4096;
+    while (nb < n) nb *= 2;
+    void* q = nullptr;
+    if (hipMalloc(&q, nb) != hipSuccess) throw Error{GLMB_E_NOMEM, "hipMalloc of " + std::to_string(nb) + " bytes failed"};
+    if (keep && p && bytes) {
+      GLMB_HIP(hipMemcpyAsync(q, p, bytes, hipMemcpyDeviceToDevice, s));
+      GLMB_HIP(hipStreamSynchronize(s));
+    }
+    if (p) {
+      (void)hipDeviceSynchronize();  // queued work may still use the old allocation
+      (void)hipFree(p);
+    }
+    p = q;
+    bytes = nb;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+template <class T> inline T* need(DevBuf& b, int64_t n) {
+  b.reserve((size_t)std::max<int64_t>(n, 1) * sizeof(T));
+  return b.as<T>();
+}
+
+// ------------------------------------------------------------------ device helpers
+// Order-preserving map of a float to uint32 (ascending floats -> ascending integers).
+__device__ __forceinline__ uint32_t f2o(float f) {
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float o2f(uint32_t o) {
+  uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+  return __uint_as_float(u);
+}
+__host__ __device__ __forceinline__ uint64_t mix64(uint64_t x) {
+  x += 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
+}
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// ------------------------------------------------------------------ primitives (primitives.hip)
+// Exclusive scan of n int32 values (in may equal out); total written to *total (device).
+void scan_excl(const int32_t* in, int32_t* out, int n, int32_t* total, DevBuf& tmp, hipStream_t s);
+void scan_excl64(const int64_t* in, int64_t* out, int n, int64_t* total, DevBuf& tmp, hipStream_t s);
+// Stable LSD radix sort of (key, value) pairs on key bits [bit0, bit1).
+void sort_pairs(uint64_t* keys, uint32_t* vals, int n, int bit0, int bit1, DevBuf& tk, DevBuf& tv,
+                DevBuf& tmp, hipStream_t s);
+// Lower bound t on the K-th largest of n floats with count(v >= t) >= K (a value of the
+// K-th largest's 24-bit orderable bin).  Writes -inf when n < K.  Result in *out (device).
+void kth_bound(const float* v, int n, int K, float* out, DevBuf& tmp, hipStream_t s);
+// Same, for values given as (value, multiplicity) pairs.
+void kth_bound_mult(const float* v, const int32_t* mult, int n, int K, float* out, DevBuf& tmp, hipStream_t s);
+
+// ------------------------------------------------------------------ selection engine (select.hip)
+// Parents with base values; per-parent item lists sorted by (delta, group, option).
+struct SelectIn {
+  int P;                  // number of parents (rank order)
+  const float* base;      // [P]
+  const int32_t* it_off;  // [P+1]
+  const float* it_delta;  // [n_items]
+  const int32_t* it_group;
+  int K;
+  const float* t0;        // device scalar: a lower bound on the K-th best child value
+};
+struct Selected {
+  int n;                  // number of selected children (<= K)
+  // device arrays (owned by the engine's buffers, valid until the next select):
+  int32_t* node;          // [n] node index of each selected child, in rank order
+  float* value;           // [n]
+  int32_t* keyrank;       // [n] position of the child in canonical-key order among the selected
+  // node storage
+  int32_t* nd_parent;     // parent node (-1 for roots)
+  int32_t* nd_item;       // item index (-1 for roots)
+  int32_t* nd_h;          // parent hypothesis
+  float* nd_value;
+  int levels, nodes;
+};
+struct SelectBufs {
+  DevBuf nd_parent, nd_item, nd_h, nd_value, cnt, pre, pre64, flags, map, tmp, tk, tv, keys, vals, sel_node,
+      sel_val, sel_rank, scal;
+};
+glmb_status select_topk(const SelectIn& in, int cap_nodes, SelectBufs& b, Selected& out, hipStream_t s,
+                        std::string& err, bool trace = false);
+
+}  // namespace glmb

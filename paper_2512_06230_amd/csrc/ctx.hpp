@@ -1,0 +1,108 @@
+// Filter context: device-resident GLMB state and per-step work buffers.
+//
+// HBM layout
+//   instances   DInst[ninst] (64 B each: mean, upper-triangular covariance, label slot,
+//               source index), sorted by label slot so that the instances of one label are
+//               contiguous;
+//   hypotheses  logw[nhyp] (normalised), ntrk[nhyp], rows[nhyp][stride] with the instance id
+//               held for every label slot (-1: label absent); rows are in rank order;
+//   labels      host-side table slot -> (birth scan, index), slots in ascending label order;
+//   births      pending LMB birth components for the next prediction.
+#pragma once
+
+#include <utility>
+
+#include "common.hpp"
+
+namespace glmb {
+
+struct DInst {
+  float m[4];
+  float P[10];  // P00 P01 P02 P03 P11 P12 P13 P22 P23 P33
+  int32_t slot;
+  int32_t src;
+};
+static_assert(sizeof(DInst) == 64, "instance record is one 64-byte line");
+
+struct DBirth {
+  float m[4];
+  float P[10];
+  float r;
+  int32_t pad;
+};
+
+struct Ctx {
+  glmb_params p{};
+  int device = 0;
+  hipStream_t s = nullptr;
+  std::string err;
+  bool alive = true;
+  bool trace = false;  // GLMB_TRACE=1: print every host-side stage to stderr (flushed)
+
+  // ---- state (host mirrors of the sizes) ----
+  std::vector<std::pair<int32_t, int32_t>> slot_lab;   // label of each slot (ascending)
+  std::vector<std::pair<int32_t, int32_t>> birth_lab;  // labels of pending births
+  int nslot = 0, ninst = 0, nhyp = 0, nbirth = 0, stride = 0;
+  DevBuf inst, inst2;          // DInst
+  DevBuf inst_nz, inst_z;      // detections of the last update per instance (count, up to 8 indices)
+  DevBuf logw, ntrk, rows, hparent;
+  DevBuf logw2, ntrk2, rows2;  // double buffers
+  DevBuf births;               // DBirth
+
+  // ---- last update (for diagnostics / exports) ----
+  int last_H = 0, last_M = 0, last_stride = 0;
+  DevBuf diag_best, diag_logpi, diag_ru;
+  DevBuf prev_rows, prev_src;  // predicted rows and instance sources of the last update
+  DevBuf child_par, dev_off, dev_i, dev_slot;
+  glmb_step_stats stats{};
+
+  // ---- update work buffers ----
+  DevBuf z, cmax, gbits, phi, lbits, lpre, llen, loff, lmeas, inst_beg, ccnt, coff, cand, best16, dev1, lserel,
+      bprime, lzprime, vals, cells, ccount, coff2, it_h, it_delta, it_group, it_opt, it_off, keys, vals32, scal,
+      sel_logw, hp_map, first, dmask, exc, cmod, recs, rec_keys, rec_vals, ids, row_mark, ru_part, ru, bt,
+      tmp, tk, tv, flags, pre, pmult, pvals;
+  SelectBufs sb;
+};
+
+// opt-in stage trace (host side)
+inline void trace(const Ctx& c, const char* stage, long long a = -1, long long b = -1) {
+  if (!c.trace) return;
+  std::fprintf(stderr, "[glmb] %s %lld %lld\n", stage, a, b);
+  std::fflush(stderr);
+}
+
+// stages
+void stage_predict(Ctx& c, int k);
+void stage_update(Ctx& c, int k, const float* z, int M);
+void stage_truncate(Ctx& c, int hmax, float tau);
+void gc_state(Ctx& c);
+
+// F and Q of the constant-velocity model (host constants passed to kernels)
+struct CV {
+  float dt, a, b, cq;  // Q blocks: a = q dt^3/3, b = q dt^2/2, cq = q dt
+};
+inline CV cv_of(const glmb_params& p) {
+  const double dt = p.dt, q = p.q;
+  return CV{(float)dt, (float)(q * dt * dt * dt / 3.0), (float)(q * dt * dt / 2.0), (float)(q * dt)};
+}
+
+__device__ __forceinline__ void cv_predict(const CV& cv, float* m, float* P) {
+  const float dt = cv.dt;
+  const float m0 = m[0] + dt * m[2], m1 = m[1] + dt * m[3];
+  m[0] = m0;
+  m[1] = m1;
+  const float P00 = P[0], P01 = P[1], P02 = P[2], P03 = P[3], P11 = P[4], P12 = P[5], P13 = P[6], P22 = P[7],
+              P23 = P[8], P33 = P[9];
+  P[0] = P00 + dt * (2.0f * P02) + dt * dt * P22 + cv.a;
+  P[1] = P01 + dt * (P03 + P12) + dt * dt * P23;
+  P[2] = P02 + dt * P22 + cv.b;
+  P[3] = P03 + dt * P23;
+  P[4] = P11 + dt * (2.0f * P13) + dt * dt * P33 + cv.a;
+  P[5] = P12 + dt * P23;
+  P[6] = P13 + dt * P33 + cv.b;
+  P[7] = P22 + cv.cq;
+  P[8] = P23;
+  P[9] = P33 + cv.cq;
+}
+
+}  // namespace glmb

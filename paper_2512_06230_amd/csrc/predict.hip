@@ -1,0 +1,466 @@
+// Prediction (Sec. 3, prediction step): every track is propagated with the constant-velocity
+// Kalman prediction, the pending LMB birth components join as new labels, and of all the
+// survive/die x include/exclude children of every hypothesis the H_max most likely are kept
+// (same exact selection engine as the update: one group per track or birth, its single
+// deviation is |log p - log(1 - p)|).  Children of different parents with the same track set
+// are merged (weights added, representative = smallest canonical key), the result is
+// normalised, and labels and instances no hypothesis uses any more are dropped.
+#include "ctx.hpp"
+
+namespace glmb {
+
+__global__ void k_pfill(int32_t* p, int n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_kpredict(DInst* inst, int U, CV cv) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= U) return;
+  DInst x = inst[u];
+  cv_predict(cv, x.m, x.P);
+  inst[u] = x;
+}
+
+__global__ void k_births_in(const DBirth* b, int NB, int U, int NS, CV cv, DInst* inst) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= NB) return;
+  DInst x;
+  for (int k = 0; k < 4; ++k) x.m[k] = b[j].m[k];
+  for (int k = 0; k < 10; ++k) x.P[k] = b[j].P[k];
+  cv_predict(cv, x.m, x.P);
+  x.slot = NS + j;
+  x.src = U + j;
+  inst[U + j] = x;
+}
+
+// parent values and (value, multiplicity) pairs whose K-th largest bounds the cut
+__global__ void k_pvals(int H, int NB, const float* logw, const int32_t* ntrk, float tb, float dt_, const float* bd,
+                        float* V, float* vals, int32_t* mult) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= H) return;
+  const float v = logw[h] + (float)ntrk[h] * tb;
+  V[h] = v;
+  const size_t o = (size_t)h * (NB + 2);
+  vals[o] = v;
+  mult[o] = 1;
+  vals[o + 1] = v - dt_;
+  mult[o + 1] = isinf(dt_) ? 0 : ntrk[h];
+  for (int b = 0; b < NB; ++b) {
+    vals[o + 2 + b] = v - bd[b];
+    mult[o + 2 + b] = isinf(bd[b]) ? 0 : 1;
+  }
+}
+
+// items of a parent: its tracks (group = slot, delta dt_) and the births (group NS + b)
+__global__ __launch_bounds__(256) void k_pitems(int H, int NS, int NB, int stride, const int32_t* rows,
+                                                const int32_t* ntrk, const float* V, float dt_, const float* bd,
+                                                const float* t0, const int32_t* ioff, int32_t* icount, float* it_d,
+                                                int32_t* it_g, uint64_t* keys, uint32_t* vals) {
+  __shared__ int32_t wsum[4];
+  const int h = blockIdx.x;
+  const float t = *t0, v = V[h];
+  const bool tracks = !isinf(dt_) && v - dt_ >= t;
+  int base = ioff ? ioff[h] : 0;
+  int cnt = 0;
+  if (tracks) {
+    // present slots in slot order: block-wide compaction over the row
+    for (int s0 = 0; s0 < stride; s0 += blockDim.x) {
+      const int sl = s0 + threadIdx.x;
+      const bool pres = sl < stride && rows[(size_t)h * stride + sl] >= 0;
+      const uint64_t bal = __ballot(pres);
+      const int w = threadIdx.x / kWave;
+      if (lane_id() == 0) wsum[w] = __popcll(bal);
+      __syncthreads();
+      int before = 0, all = 0;
+      for (int j = 0; j < (int)(blockDim.x / kWave); ++j) {
+        if (j < w) before += wsum[j];
+        all += wsum[j];
+      }
+      if (pres && ioff) {
+        const int q = base + cnt + before + __popcll(bal & lanemask_lt());
+        it_d[q] = dt_;
+        it_g[q] = sl;
+        keys[q] = ((uint64_t)(uint32_t)h << 32) | f2o(dt_);
+        vals[q] = (uint32_t)q;
+      }
+      cnt += all;
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) {
+    for (int b = 0; b < NB; ++b)
+      if (!isinf(bd[b]) && v - bd[b] >= t) {
+        if (ioff) {
+          const int q = base + cnt;
+          it_d[q] = bd[b];
+          it_g[q] = NS + b;
+          keys[q] = ((uint64_t)(uint32_t)h << 32) | f2o(bd[b]);
+          vals[q] = (uint32_t)q;
+        }
+        ++cnt;
+      }
+    if (!ioff) icount[h] = cnt;
+  }
+}
+
+__global__ void k_pitem_perm(int n, const uint32_t* vals, const float* d0, const int32_t* g0, float* d1, int32_t* g1) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  d1[p] = d0[vals[p]];
+  g1[p] = g0[vals[p]];
+}
+
+__global__ void k_pitem_off(int H, int n, const uint64_t* keys, int32_t* it_off) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h > H) return;
+  int a = 0, b = n;
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    if ((int)(keys[m] >> 32) < h) a = m + 1;
+    else b = m;
+  }
+  it_off[h] = a;
+}
+
+// child rows (width NS + NB), their hash and track count
+__global__ __launch_bounds__(256) void k_prows(int n, int NS, int NB, int stride, int U, int t_yes,
+                                               const int32_t* byes, const int32_t* sel_node, const int32_t* nd_parent,
+                                               const int32_t* nd_item, const int32_t* nd_h, const int32_t* it_g,
+                                               const int32_t* rows, int32_t* out, uint64_t* hash, int32_t* nt,
+                                               int32_t* par) {
+  __shared__ unsigned long long hs;
+  __shared__ int32_t cnt;
+  const int c = blockIdx.x;
+  const int W2 = NS + NB;
+  const int node = sel_node[c];
+  const int h = nd_h[node];
+  if (threadIdx.x == 0) {
+    hs = 0;
+    cnt = 0;
+  }
+  __syncthreads();
+  int32_t* o = out + (size_t)c * W2;
+  for (int s = threadIdx.x; s < W2; s += blockDim.x) {
+    if (s < NS) o[s] = t_yes ? rows[(size_t)h * stride + s] : -1;
+    else o[s] = byes[s - NS] ? U + (s - NS) : -1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int x = node; nd_item[x] >= 0; x = nd_parent[x]) {
+      const int g = it_g[nd_item[x]];
+      if (g < NS) o[g] = t_yes ? -1 : rows[(size_t)h * stride + g];
+      else o[g] = byes[g - NS] ? -1 : U + (g - NS);
+    }
+    par[c] = h;
+  }
+  __syncthreads();
+  unsigned long long hl = 0;
+  int cl = 0;
+  for (int s = threadIdx.x; s < W2; s += blockDim.x)
+    if (o[s] >= 0) {
+      hl += mix64(((uint64_t)(uint32_t)s << 32) | (uint32_t)o[s]);
+      ++cl;
+    }
+  atomicAdd(&hs, hl);
+  atomicAdd(&cnt, cl);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    hash[c] = hs;
+    nt[c] = cnt;
+  }
+}
+
+__global__ void k_hash_keys(int n, const uint64_t* hash, uint64_t* keys, uint32_t* vals) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  keys[c] = hash[c];
+  vals[c] = (uint32_t)c;
+}
+
+__device__ bool rows_equal(const int32_t* a, const int32_t* b, int W2) {
+  for (int s = 0; s < W2; ++s)
+    if (a[s] != b[s]) return false;
+  return true;
+}
+
+// leader of every child: first child of its hash run with an identical row
+__global__ void k_leaders(int n, int W2, const uint64_t* keys, const uint32_t* vals, const int32_t* crow,
+                          int32_t* leader) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  int r0 = p;
+  while (r0 > 0 && keys[r0 - 1] == keys[p]) --r0;
+  const uint32_t me = vals[p];
+  int lead = (int)me;
+  for (int q = r0; q < p; ++q)
+    if (rows_equal(crow + (size_t)vals[q] * W2, crow + (size_t)me * W2, W2)) {
+      lead = (int)vals[q];
+      break;
+    }
+  leader[me] = lead;
+}
+
+// merged value (log-add over the members, in hash-run order) and representative (the member
+// with the smallest canonical key) of each leader; members follow their leader in its hash run
+__global__ void k_merge(int n, const int32_t* leader, const float* val, const int32_t* keyrank, const uint64_t* keys,
+                        const uint32_t* vals, int32_t* is_lead, float* mval, int32_t* mrank, int32_t* mrep) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int c = (int)vals[p];
+  if (leader[c] != c) {
+    is_lead[c] = 0;
+    return;
+  }
+  is_lead[c] = 1;
+  float m = val[c];
+  int r = keyrank[c], rp = c;
+  for (int q = p + 1; q < n && keys[q] == keys[p]; ++q) {
+    const int j = (int)vals[q];
+    if (leader[j] != c) continue;
+    m = fmaxf(m, val[j]);
+    if (keyrank[j] < r) {
+      r = keyrank[j];
+      rp = j;
+    }
+  }
+  float acc = __expf(val[c] - m);
+  for (int q = p + 1; q < n && keys[q] == keys[p]; ++q) {
+    const int j = (int)vals[q];
+    if (leader[j] == c) acc += __expf(val[j] - m);
+  }
+  mval[c] = m + __logf(acc);
+  mrank[c] = r;
+  mrep[c] = rp;
+}
+
+__global__ void k_lead_keys(int n, const int32_t* is_lead, const int32_t* lpre, const float* mval,
+                            const int32_t* mrank, uint64_t* keys, uint32_t* vals) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n || !is_lead[c]) return;
+  const int d = lpre[c];
+  keys[d] = ((uint64_t)(~f2o(mval[c])) << 32) | (uint32_t)mrank[c];
+  vals[d] = (uint32_t)c;
+}
+
+__global__ void k_used(int nh, int W2, const uint32_t* order, const int32_t* crow, int32_t* sused, int32_t* uused) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nh * W2) return;
+  const int h = (int)(t / W2), s = (int)(t % W2);
+  const int u = crow[(size_t)order[h] * W2 + s];
+  if (u >= 0) {
+    sused[s] = 1;
+    uused[u] = 1;
+  }
+}
+
+// one block: normalised log weights of the merged hypotheses in final order
+__device__ __forceinline__ float bsum(float v, float* sh) {
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  __syncthreads();
+  if (lane_id() == 0) sh[threadIdx.x / kWave] = v;
+  __syncthreads();
+  float r = 0.0f;
+  for (int j = 0; j < (int)(blockDim.x / kWave); ++j) r += sh[j];
+  return r;
+}
+__global__ __launch_bounds__(1024) void k_pnorm(int nh, const uint32_t* order, const float* mval, float* logw) {
+  __shared__ float red[16];
+  const float mx = mval[order[0]];
+  float s = 0.0f;
+  for (int h = threadIdx.x; h < nh; h += blockDim.x) s += __expf(mval[order[h]] - mx);
+  s = bsum(s, red);
+  const float L = mx + __logf(s);
+  for (int h = threadIdx.x; h < nh; h += blockDim.x) logw[h] = mval[order[h]] - L;
+}
+
+__global__ void k_final_rows(int nh, int W2, int NS2, const uint32_t* order, const int32_t* crow, const int32_t* spre,
+                             const int32_t* sused, const int32_t* upre, const int32_t* nt_c, const int32_t* par_c,
+                             const int32_t* mrep, int32_t* rows, int32_t* ntrk, int32_t* hpar) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)nh * W2) return;
+  const int h = (int)(t / W2), s = (int)(t % W2);
+  const int c = (int)order[h];
+  if (s == 0) {
+    ntrk[h] = nt_c[c];
+    hpar[h] = par_c[mrep[c]];
+  }
+  if (!sused[s]) return;
+  const int u = crow[(size_t)c * W2 + s];
+  rows[(size_t)h * NS2 + spre[s]] = u >= 0 ? upre[u] : -1;
+}
+
+__global__ void k_compact_inst(int U2, const int32_t* uused, const int32_t* upre, const int32_t* spre, const DInst* in,
+                               DInst* out) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= U2 || !uused[u]) return;
+  DInst x = in[u];
+  x.slot = spre[x.slot];
+  out[upre[u]] = x;
+}
+
+void stage_predict(Ctx& c, int k) {
+  (void)k;
+  hipStream_t s = c.s;
+  const int T = 256;
+  const int H = c.nhyp, U = c.ninst, NS = c.nslot, SW = c.stride, NB = c.nbirth;
+  const glmb_params& p = c.p;
+  // birth labels must sort after every label in use, in index order
+  for (int b = 0; b < NB; ++b) {
+    const auto& L = c.birth_lab[b];
+    if ((NS > 0 && !(c.slot_lab.back() < L)) || (b > 0 && !(c.birth_lab[b - 1] < L)))
+      throw Error{GLMB_E_ARG, "birth labels must sort after all existing labels"};
+  }
+  if (NS + NB > 32766) throw Error{GLMB_E_CAPACITY, "too many labels"};
+  const CV cv = cv_of(p);
+  int32_t* scal = need<int32_t>(c.scal, 64);
+  float* t0 = (float*)(scal + 9);
+  int32_t* tot = scal + 12;
+  trace(c, "predict.begin", H, NB);
+  // ---- Kalman prediction; births become instances U.. and slots NS..
+  c.inst.reserve((size_t)(U + NB + 1) * sizeof(DInst), true, s);
+  GLMB_LAUNCH(k_kpredict, cdiv(U, T), T, 0, s, c.inst.as<DInst>(), U, cv);
+  GLMB_LAUNCH(k_births_in, cdiv(NB, T), T, 0, s, (const DBirth*)c.births.p, NB, U, NS, cv, c.inst.as<DInst>());
+  // ---- dimensions
+  const double ps = p.p_survive;
+  const double ly = std::log(ps), ln = std::log1p(-ps);
+  const int t_yes = ly >= ln ? 1 : 0;
+  const float tb = (float)std::max(ly, ln);
+  const float dt_ = (float)std::fabs(ly - ln);
+  std::vector<DBirth> hb(NB);
+  if (NB) {
+    GLMB_HIP(hipMemcpyAsync(hb.data(), c.births.p, (size_t)NB * sizeof(DBirth), hipMemcpyDeviceToHost, s));
+    GLMB_HIP(hipStreamSynchronize(s));
+  }
+  std::vector<float> bd(NB + 1, 0.0f);
+  std::vector<int32_t> by(NB + 1, 0);
+  for (int b = 0; b < NB; ++b) {
+    const double r = hb[b].r;
+    const double a = std::log(r), q = std::log1p(-r);
+    by[b] = a >= q ? 1 : 0;
+    bd[b] = (float)std::fabs(a - q);
+  }
+  float* dbd = need<float>(c.bt, 2 * (int64_t)NB + 2);
+  int32_t* dby = (int32_t*)(dbd + NB + 1);
+  GLMB_HIP(hipMemcpyAsync(dbd, bd.data(), (NB + 1) * sizeof(float), hipMemcpyHostToDevice, s));
+  GLMB_HIP(hipMemcpyAsync(dby, by.data(), (NB + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  // ---- lower bound of the cut
+  float* V = need<float>(c.bprime, H);
+  float* pv = need<float>(c.pvals, (int64_t)H * (NB + 2));
+  int32_t* pm = need<int32_t>(c.pmult, (int64_t)H * (NB + 2));
+  GLMB_LAUNCH(k_pvals, cdiv(H, T), T, 0, s, H, NB, c.logw.as<float>(), c.ntrk.as<int32_t>(), tb, dt_, dbd, V, pv, pm);
+  kth_bound_mult(pv, pm, H * (NB + 2), p.h_max, t0, c.tmp, s);
+  // ---- items
+  int32_t* icount = need<int32_t>(c.ccount, H + 1);
+  int32_t* ioff = need<int32_t>(c.coff2, H + 1);
+  GLMB_LAUNCH(k_pitems, H, 256, 0, s, H, NS, NB, SW, c.rows.as<int32_t>(), c.ntrk.as<int32_t>(), V, dt_, dbd, t0,
+              (const int32_t*)nullptr, icount, (float*)nullptr, (int32_t*)nullptr, (uint64_t*)nullptr,
+              (uint32_t*)nullptr);
+  scan_excl(icount, ioff, H, ioff + H, c.tmp, s);
+  int32_t nitem = 0;
+  GLMB_HIP(hipMemcpyAsync(&nitem, ioff + H, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipStreamSynchronize(s));
+  float* itd0 = need<float>(c.it_delta, 2 * (int64_t)nitem + 2);
+  int32_t* itg0 = need<int32_t>(c.it_group, 2 * (int64_t)nitem + 2);
+  uint64_t* ik = need<uint64_t>(c.keys, nitem + 1);
+  uint32_t* iv = need<uint32_t>(c.vals32, nitem + 1);
+  GLMB_LAUNCH(k_pitems, H, 256, 0, s, H, NS, NB, SW, c.rows.as<int32_t>(), c.ntrk.as<int32_t>(), V, dt_, dbd, t0,
+              (const int32_t*)ioff, icount, itd0, itg0, ik, iv);
+  int hbits = 0;
+  while ((1 << hbits) < H) ++hbits;
+  sort_pairs(ik, iv, nitem, 0, 32 + ((hbits + 7) / 8) * 8, c.tk, c.tv, c.tmp, s);
+  float* itd = itd0 + nitem + 1;
+  int32_t* itg = itg0 + nitem + 1;
+  GLMB_LAUNCH(k_pitem_perm, cdiv(nitem, T), T, 0, s, nitem, iv, itd0, itg0, itd, itg);
+  int32_t* itoff = need<int32_t>(c.it_off, H + 1);
+  GLMB_LAUNCH(k_pitem_off, cdiv(H + 1, T), T, 0, s, H, nitem, ik, itoff);
+  // ---- exact selection
+  trace(c, "predict.select", nitem);
+  SelectIn si{H, V, itoff, itd, itg, p.h_max, t0};
+  Selected sel{};
+  std::string serr;
+  const int cap_nodes = p.cap_nodes > 0 ? p.cap_nodes : (1 << 22);
+  glmb_status st = select_topk(si, cap_nodes, c.sb, sel, s, serr, c.trace);
+  if (st != GLMB_OK) throw Error{st, serr};
+  const int n = sel.n;
+  if (n < 1) throw Error{GLMB_E_STATE, "prediction kept no hypothesis (non-finite weights?)"};
+  trace(c, "predict.merge", n);
+  const int W2 = NS + NB;
+  // ---- child rows, duplicate merge
+  int32_t* crow = need<int32_t>(c.rows2, (int64_t)n * W2 + 1);
+  uint64_t* hash = need<uint64_t>(c.rec_keys, n + 1);
+  int32_t* ntc = need<int32_t>(c.ntrk2, n + 1);
+  int32_t* parc = need<int32_t>(c.child_par, n + 1);
+  GLMB_LAUNCH(k_prows, n, 256, 0, s, n, NS, NB, SW, U, t_yes, dby, sel.node, sel.nd_parent, sel.nd_item, sel.nd_h, itg,
+              c.rows.as<int32_t>(), crow, hash, ntc, parc);
+  uint64_t* hk = need<uint64_t>(c.keys, n + 1);
+  uint32_t* hv = need<uint32_t>(c.vals32, n + 1);
+  GLMB_LAUNCH(k_hash_keys, cdiv(n, T), T, 0, s, n, hash, hk, hv);
+  sort_pairs(hk, hv, n, 0, 64, c.tk, c.tv, c.tmp, s);
+  int32_t* leader = need<int32_t>(c.first, 4 * (int64_t)n + 4);
+  int32_t* islead = leader + n + 1;
+  int32_t* mrank = islead + n + 1;
+  int32_t* mrep = mrank + n + 1;
+  float* mval = need<float>(c.sel_logw, n + 1);
+  GLMB_LAUNCH(k_leaders, cdiv(n, T), T, 0, s, n, W2, hk, hv, crow, leader);
+  GLMB_LAUNCH(k_merge, cdiv(n, T), T, 0, s, n, leader, sel.value, sel.keyrank, hk, hv, islead, mval, mrank, mrep);
+  int32_t* lpre = need<int32_t>(c.pre, n + 1);
+  scan_excl(islead, lpre, n, tot, c.tmp, s);
+  int32_t nh = 0;
+  GLMB_HIP(hipMemcpyAsync(&nh, tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipStreamSynchronize(s));
+  uint64_t* lk = need<uint64_t>(c.rec_keys, nh + 1);
+  uint32_t* lv = need<uint32_t>(c.rec_vals, nh + 1);
+  GLMB_LAUNCH(k_lead_keys, cdiv(n, T), T, 0, s, n, islead, lpre, mval, mrank, lk, lv);
+  sort_pairs(lk, lv, nh, 0, 64, c.tk, c.tv, c.tmp, s);
+  // ---- normalise, garbage-collect labels and instances, final rows
+  trace(c, "predict.gc", nh);
+  float* nlw = need<float>(c.logw2, nh + 1);
+  GLMB_LAUNCH(k_pnorm, 1, 1024, 0, s, nh, lv, mval, nlw);
+  const int U2 = U + NB;
+  int32_t* sused = need<int32_t>(c.flags, (int64_t)W2 + U2 + 2);
+  int32_t* uused = sused + W2 + 1;
+  GLMB_HIP(hipMemsetAsync(sused, 0, ((size_t)W2 + U2 + 2) * sizeof(int32_t), s));
+  GLMB_LAUNCH(k_used, cdiv((int64_t)nh * W2, T), T, 0, s, nh, W2, lv, crow, sused, uused);
+  int32_t* spre = need<int32_t>(c.lpre, (int64_t)W2 + U2 + 4);
+  int32_t* upre = spre + W2 + 2;
+  scan_excl(sused, spre, W2, spre + W2, c.tmp, s);
+  scan_excl(uused, upre, U2, upre + U2, c.tmp, s);
+  std::vector<int32_t> hsu(W2 + 1);
+  int32_t cnts[2];
+  GLMB_HIP(hipMemcpyAsync(hsu.data(), sused, (size_t)(W2 + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipMemcpyAsync(&cnts[0], spre + W2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipMemcpyAsync(&cnts[1], upre + U2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipStreamSynchronize(s));
+  const int NS2 = cnts[0], Unew = cnts[1];
+  int32_t* frows = need<int32_t>(c.prev_rows, (int64_t)nh * NS2 + 1);
+  int32_t* fnt = need<int32_t>(c.hp_map, nh + 1);
+  int32_t* fpar = need<int32_t>(c.hparent, nh + 1);
+  GLMB_LAUNCH(k_pfill, cdiv((int64_t)nh * NS2, T), T, 0, s, frows, nh * NS2, -1);
+  GLMB_LAUNCH(k_final_rows, cdiv((int64_t)nh * W2, T), T, 0, s, nh, W2, NS2, lv, crow, spre, sused, upre, ntc, parc,
+              mrep, frows, fnt, fpar);
+  DInst* ninst = (DInst*)need<uint8_t>(c.inst2, (int64_t)(Unew + 1) * sizeof(DInst));
+  GLMB_LAUNCH(k_compact_inst, cdiv(U2, T), T, 0, s, U2, uused, upre, spre, c.inst.as<DInst>(), ninst);
+  // rows / counts into the primary buffers
+  int32_t* rows = need<int32_t>(c.rows, (int64_t)nh * NS2 + 1);
+  GLMB_HIP(hipMemcpyAsync(rows, frows, (size_t)nh * NS2 * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  int32_t* nt = need<int32_t>(c.ntrk, nh + 1);
+  GLMB_HIP(hipMemcpyAsync(nt, fnt, (size_t)nh * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  float* lw = need<float>(c.logw, nh + 1);
+  GLMB_HIP(hipMemcpyAsync(lw, nlw, (size_t)nh * sizeof(float), hipMemcpyDeviceToDevice, s));
+  std::swap(c.inst, c.inst2);
+  // host label table
+  std::vector<std::pair<int32_t, int32_t>> lab;
+  for (int sl = 0; sl < W2; ++sl)
+    if (hsu[sl]) lab.push_back(sl < NS ? c.slot_lab[sl] : c.birth_lab[sl - NS]);
+  c.slot_lab.swap(lab);
+  c.nslot = NS2;
+  c.stride = NS2;
+  c.ninst = Unew;
+  c.nhyp = nh;
+  c.nbirth = 0;
+  c.birth_lab.clear();
+  GLMB_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace glmb

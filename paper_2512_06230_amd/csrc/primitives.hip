@@ -1,0 +1,274 @@
+// Device primitives: exclusive scan, stable LSD radix sort of (u64 key, u32 value) pairs,
+// and a two-pass histogram bound on the K-th largest float.
+#include "common.hpp"
+
+namespace glmb {
+
+// ============================================================================ scan
+constexpr int kScanT = 256;
+constexpr int kScanI = 8;
+constexpr int kScanTile = kScanT * kScanI;
+
+template <class I>
+__device__ __forceinline__ I block_excl_scan(I v, I* sh, I* total) {
+  // wave inclusive scan via shuffles, then across the waves of the block
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  I x = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    I y = __shfl_up(x, d, kWave);
+    if (lane >= d) x += y;
+  }
+  if (lane == kWave - 1) sh[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    I run = 0;
+    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) {
+      I t = sh[i];
+      sh[i] = run;
+      run += t;
+    }
+    sh[16] = run;
+  }
+  __syncthreads();
+  I r = x - v + sh[w];
+  *total = sh[16];
+  __syncthreads();
+  return r;
+}
+
+template <class I>
+__global__ __launch_bounds__(kScanT) void k_scan_tiles(const I* in, I* out, int n, I* tile_sums) {
+  __shared__ I sh[32];
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanI;
+  I v[kScanI];
+  I s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanI; ++j) {
+    v[j] = (base + j < n) ? in[base + j] : 0;
+    s += v[j];
+  }
+  I tot;
+  I off = block_excl_scan<I>(s, sh, &tot);
+#pragma unroll
+  for (int j = 0; j < kScanI; ++j) {
+    if (base + j < n) out[base + j] = off;
+    off += v[j];
+  }
+  if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+}
+
+// one block: exclusive scan of the tile sums in chunks with a running carry
+template <class I>
+__global__ __launch_bounds__(kScanT) void k_scan_sums(I* sums, int nt, I* total) {
+  __shared__ I sh[32];
+  I carry = 0;
+  for (int c = 0; c < nt; c += kScanT) {
+    const int i = c + threadIdx.x;
+    I v = i < nt ? sums[i] : 0;
+    I tot;
+    I r = block_excl_scan<I>(v, sh, &tot);
+    if (i < nt) sums[i] = r + carry;
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && total) *total = carry;
+}
+
+template <class I>
+__global__ __launch_bounds__(kScanT) void k_scan_add(I* out, int n, const I* sums) {
+  const int base = blockIdx.x * kScanTile + threadIdx.x * kScanI;
+  const I a = sums[blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < kScanI; ++j)
+    if (base + j < n) out[base + j] += a;
+}
+
+template <class I>
+static void scan_impl(const I* in, I* out, int n, I* total, DevBuf& tmp, hipStream_t s) {
+  const int nt = std::max(1, cdiv(n, kScanTile));
+  I* sums = need<I>(tmp, nt);
+  if (n > 0) GLMB_LAUNCH(k_scan_tiles<I>, nt, kScanT, 0, s, in, out, n, sums);
+  else GLMB_HIP(hipMemsetAsync(sums, 0, sizeof(I), s));
+  GLMB_LAUNCH(k_scan_sums<I>, 1, kScanT, 0, s, sums, nt, total);
+  if (n > 0) GLMB_LAUNCH(k_scan_add<I>, nt, kScanT, 0, s, out, n, sums);
+}
+
+void scan_excl(const int32_t* in, int32_t* out, int n, int32_t* total, DevBuf& tmp, hipStream_t s) {
+  scan_impl<int32_t>(in, out, n, total, tmp, s);
+}
+void scan_excl64(const int64_t* in, int64_t* out, int n, int64_t* total, DevBuf& tmp, hipStream_t s) {
+  scan_impl<int64_t>(in, out, n, total, tmp, s);
+}
+
+// ============================================================================ radix sort
+constexpr int kSortT = 256;
+constexpr int kSortR = 8;                 // rounds per tile
+constexpr int kSortTile = kSortT * kSortR;
+
+__global__ __launch_bounds__(kSortT) void k_sort_hist(const uint64_t* keys, int n, int shift, int nb,
+                                                      int32_t* hist) {
+  __shared__ int32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int base = blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortR; ++r) {
+    const int i = base + r * kSortT + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
+  }
+  __syncthreads();
+  hist[threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kSortT) void k_sort_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
+                                                         uint32_t* vout, int n, int shift, int nb,
+                                                         const int32_t* hist_scan) {
+  __shared__ int32_t base_d[256];
+  __shared__ int32_t running[256];
+  __shared__ int32_t wcnt[kSortT / kWave][256];
+  __shared__ int32_t woff[kSortT / kWave][256];
+  __shared__ int32_t rtot[256];
+  const int t = threadIdx.x, w = t / kWave;
+  base_d[t] = hist_scan[t * nb + blockIdx.x];
+  running[t] = 0;
+  for (int j = 0; j < kSortT / kWave; ++j) wcnt[j][t] = 0;
+  __syncthreads();
+  const int tile = blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortR; ++r) {
+    const int i = tile + r * kSortT + t;
+    const bool valid = i < n;
+    uint64_t k = valid ? kin[i] : 0;
+    uint32_t v = valid ? vin[i] : 0;
+    const int d = (int)((k >> shift) & 255);
+    uint64_t same = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint64_t bal = __ballot((d >> b) & 1);
+      same &= ((d >> b) & 1) ? bal : ~bal;
+    }
+    const int rank = __popcll(same & lanemask_lt());
+    if (valid && rank == 0) wcnt[w][d] = __popcll(same);
+    __syncthreads();
+    {
+      int32_t run = 0;
+      for (int j = 0; j < kSortT / kWave; ++j) {
+        const int32_t c = wcnt[j][t];
+        woff[j][t] = run;
+        run += c;
+      }
+      rtot[t] = run;
+    }
+    __syncthreads();
+    if (valid) {
+      const int pos = base_d[d] + running[d] + woff[w][d] + rank;
+      kout[pos] = k;
+      vout[pos] = v;
+    }
+    __syncthreads();
+    running[t] += rtot[t];
+    for (int j = 0; j < kSortT / kWave; ++j) wcnt[j][t] = 0;
+    __syncthreads();
+  }
+}
+
+void sort_pairs(uint64_t* keys, uint32_t* vals, int n, int bit0, int bit1, DevBuf& tk, DevBuf& tv, DevBuf& tmp,
+                hipStream_t s) {
+  if (n <= 1 || bit1 <= bit0) return;
+  const int nb = cdiv(n, kSortTile);
+  uint64_t* k2 = need<uint64_t>(tk, n);
+  uint32_t* v2 = need<uint32_t>(tv, n);
+  // scan scratch: hist (256*nb) + tile sums
+  tmp.reserve(((size_t)256 * nb + (size_t)cdiv(256 * nb, kScanTile) + 64) * sizeof(int32_t));
+  int32_t* hist = tmp.as<int32_t>();
+  int32_t* sums = hist + (size_t)256 * nb;
+  uint64_t *ka = keys, *kb = k2;
+  uint32_t *va = vals, *vb = v2;
+  int passes = 0;
+  for (int sh = bit0; sh < bit1; sh += 8, ++passes) {
+    GLMB_LAUNCH(k_sort_hist, nb, kSortT, 0, s, ka, n, sh, nb, hist);
+    const int m = 256 * nb;
+    const int nt = cdiv(m, kScanTile);
+    GLMB_LAUNCH(k_scan_tiles<int32_t>, nt, kScanT, 0, s, hist, hist, m, sums);
+    GLMB_LAUNCH(k_scan_sums<int32_t>, 1, kScanT, 0, s, sums, nt, (int32_t*)nullptr);
+    GLMB_LAUNCH(k_scan_add<int32_t>, nt, kScanT, 0, s, hist, m, sums);
+    GLMB_LAUNCH(k_sort_scatter, nb, kSortT, 0, s, ka, va, kb, vb, n, sh, nb, hist);
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  if (passes & 1) {
+    GLMB_HIP(hipMemcpyAsync(keys, ka, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    GLMB_HIP(hipMemcpyAsync(vals, va, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+  }
+}
+
+// ============================================================================ K-th bound
+constexpr int kBins = 4096;
+
+__global__ __launch_bounds__(256) void k_bound_hist(const float* v, const int32_t* mult, int n, int pass,
+                                                    const uint32_t* prefix, int32_t* hist) {
+  __shared__ int32_t h[kBins];
+  for (int j = threadIdx.x; j < kBins; j += blockDim.x) h[j] = 0;
+  __syncthreads();
+  const uint32_t pre = pass ? *prefix : 0u;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint32_t o = f2o(v[i]);
+    const int32_t c = mult ? mult[i] : 1;
+    if (c <= 0) continue;
+    if (pass == 0) atomicAdd(&h[o >> 20], c);
+    else if ((o >> 20) == pre) atomicAdd(&h[(o >> 8) & (kBins - 1)], c);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < kBins; j += blockDim.x)
+    if (h[j]) atomicAdd(&hist[j], h[j]);
+}
+
+// one thread: walk the bins from the top until K values are covered
+__global__ void k_bound_pick(int32_t* hist, int pass, uint32_t* prefix, int32_t* need_k, float* out) {
+  if (threadIdx.x != 0) return;
+  int64_t K = *need_k;
+  int64_t acc = 0;
+  int b = kBins - 1;
+  for (; b >= 0; --b) {
+    if (acc + hist[b] >= K) break;
+    acc += hist[b];
+  }
+  if (b < 0) {
+    *out = -INFINITY;
+    *prefix = 0xffffffffu;  // no second pass restriction matches
+  } else if (pass == 0) {
+    *prefix = (uint32_t)b;
+    *need_k = (int32_t)(K - acc);
+  } else {
+    // lowest value of the bin; the bin of -inf starts below -inf (a NaN pattern)
+    const float e = o2f(((*prefix) << 20) | ((uint32_t)b << 8));
+    *out = e == e ? e : -INFINITY;
+  }
+  for (int j = 0; j < kBins; ++j) hist[j] = 0;
+}
+
+__global__ void k_bound_init(int32_t* hist, int32_t* need_k, int32_t K) {
+  for (int j = threadIdx.x; j < kBins; j += blockDim.x) hist[j] = 0;
+  if (threadIdx.x == 0) *need_k = K;
+}
+
+static void kth_bound_impl(const float* v, const int32_t* mult, int n, int K, float* out, DevBuf& tmp,
+                           hipStream_t s) {
+  tmp.reserve((kBins + 8) * sizeof(int32_t));
+  int32_t* hist = tmp.as<int32_t>();
+  uint32_t* prefix = (uint32_t*)(hist + kBins);
+  int32_t* need_k = hist + kBins + 1;
+  GLMB_LAUNCH(k_bound_init, 1, 256, 0, s, hist, need_k, (int32_t)K);
+  const int grid = std::max(1, std::min(cdiv(n, 256 * 8), 1024));
+  GLMB_LAUNCH(k_bound_hist, grid, 256, 0, s, v, mult, n, 0, prefix, hist);
+  GLMB_LAUNCH(k_bound_pick, 1, 64, 0, s, hist, 0, prefix, need_k, out);
+  GLMB_LAUNCH(k_bound_hist, grid, 256, 0, s, v, mult, n, 1, prefix, hist);
+  GLMB_LAUNCH(k_bound_pick, 1, 64, 0, s, hist, 1, prefix, need_k, out);
+}
+
+void kth_bound(const float* v, int n, int K, float* out, DevBuf& tmp, hipStream_t s) {
+  kth_bound_impl(v, nullptr, n, K, out, tmp, s);
+}
+void kth_bound_mult(const float* v, const int32_t* mult, int n, int K, float* out, DevBuf& tmp, hipStream_t s) {
+  kth_bound_impl(v, mult, n, K, out, tmp, s);
+}
+
+}  // namespace glmb

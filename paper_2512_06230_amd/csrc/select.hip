@@ -1,0 +1,328 @@
+// Exact top-K over implicitly defined children (the "retain the H_max most likely
+// hypotheses" step at the end of Sec. 3, and the same choice in prediction).
+//
+// A parent h has a base value B_h and a list of items (group g, option, delta >= 0)
+// sorted by (delta, group, option).  A child picks at most one item per group; its
+// value is B_h minus the picked deltas subtracted in item order.  Children are
+// ranked by value descending, then by the canonical key (parent rank, number of
+// picks, picked item positions in lexicographic order).
+//
+// GPU method: level-synchronous enumeration.  Level l holds every child with l picks
+// whose value is >= the current threshold t; a node is extended by the items after
+// its last one whose value stays >= t (a binary search on the sorted deltas gives the
+// range, so no candidate below t is ever written).  Since removing a pick never lowers
+// a value, this reaches every child >= t exactly once.  t starts at a lower bound on
+// the K-th best value and is raised to a lower bound on the K-th largest value found so
+// far whenever the node store runs full or a level completes; nodes below the new t are
+// compacted away (their descendants are below it too).  At the end every child >= t is
+// present, and a stable sort by (value desc, key) of those yields the exact top-K: the
+// enumeration order is (level, parent rank, positions), so a stable sort by parent rank
+// gives the canonical key order.
+#include "common.hpp"
+
+namespace glmb {
+
+__global__ void k_root_flags(const float* base, int P, const float* t, int32_t* flags) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h < P) flags[h] = base[h] >= *t ? 1 : 0;
+}
+
+__global__ void k_root_write(const float* base, int P, const float* t, const int32_t* pre, int32_t* nd_parent,
+                             int32_t* nd_item, int32_t* nd_h, float* nd_value) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h < P && base[h] >= *t) {
+    const int n = pre[h];
+    nd_parent[n] = -1;
+    nd_item[n] = -1;
+    nd_h[n] = h;
+    nd_value[n] = base[h];
+  }
+}
+
+// first item index after node n, and the end of the items with value - delta >= t
+__device__ __forceinline__ void ext_range(int n, const int32_t* nd_item, const int32_t* nd_h, const float* nd_value,
+                                          const int32_t* it_off, const float* it_delta, float t, int* lo_out,
+                                          int* hi_out) {
+  const float v = nd_value[n];
+  const int h = nd_h[n];
+  const int lo = nd_item[n] < 0 ? it_off[h] : nd_item[n] + 1;
+  int a = lo, b = it_off[h + 1];
+  if (!(v >= t)) b = lo;
+  // largest prefix of [lo, b) with v - delta >= t (monotone in delta)
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    if (v - it_delta[m] >= t) a = m + 1;
+    else b = m;
+  }
+  *lo_out = lo;
+  *hi_out = a;
+}
+
+__global__ void k_count(int first, int nlev, const int32_t* nd_item, const int32_t* nd_h, const float* nd_value,
+                        const int32_t* it_off, const float* it_delta, const float* t, int64_t* cnt) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nlev) return;
+  int lo, hi;
+  ext_range(first + j, nd_item, nd_h, nd_value, it_off, it_delta, *t, &lo, &hi);
+  cnt[j] = hi - lo;
+}
+
+// largest m with (sum of the first m counts) <= room; out = {m, that sum}
+__global__ void k_cut(const int64_t* pre, const int64_t* cnt, int nlev, int64_t room, int32_t* out) {
+  if (threadIdx.x != 0) return;
+  int a = 0, b = nlev;  // predicate(m): pre[m-1] + cnt[m-1] <= room, monotone
+  while (a < b) {
+    const int m = (a + b + 1) >> 1;
+    if (pre[m - 1] + cnt[m - 1] <= room) a = m;
+    else b = m - 1;
+  }
+  out[0] = a;
+  out[1] = a > 0 ? (int32_t)(pre[a - 1] + cnt[a - 1]) : 0;
+}
+
+__global__ void k_expand(int first, int m, int total, int out_base, const int64_t* pre, int32_t* nd_parent,
+                         int32_t* nd_item, int32_t* nd_h, float* nd_value, const int32_t* it_off,
+                         const float* it_delta, const int32_t* it_group, const float* t) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  int a = 0, b = m - 1;  // last j with pre[j] <= e
+  while (a < b) {
+    const int c = (a + b + 1) >> 1;
+    if (pre[c] <= e) a = c;
+    else b = c - 1;
+  }
+  const int n = first + a;
+  int lo, hi;
+  ext_range(n, nd_item, nd_h, nd_value, it_off, it_delta, *t, &lo, &hi);
+  const int q = lo + (int)(e - pre[a]);
+  float v = nd_value[n] - it_delta[q];
+  const int g = it_group[q];
+  for (int x = n; nd_item[x] >= 0; x = nd_parent[x])
+    if (it_group[nd_item[x]] == g) {
+      // two picks in one group: not a child.  NaN fails every `value >= t` test, so such a
+      // node is never extended nor kept, even while t is still -inf.
+      v = __uint_as_float(0xffc00000u);
+      break;
+    }
+  const int o = out_base + e;
+  nd_parent[o] = n;
+  nd_item[o] = q;
+  nd_h[o] = nd_h[n];
+  nd_value[o] = v;
+}
+
+__global__ void k_keep_flags(const float* nd_value, int n, const float* t, int32_t* flags) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flags[i] = nd_value[i] >= *t ? 1 : 0;
+}
+
+__global__ void k_compact_nodes(int n, const float* t, const int32_t* pre, const int32_t* p0, const int32_t* i0,
+                                const int32_t* h0, const float* v0, int32_t* p1, int32_t* i1, int32_t* h1, float* v1) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !(v0[i] >= *t)) return;
+  const int d = pre[i];
+  p1[d] = p0[i] >= 0 ? pre[p0[i]] : -1;
+  i1[d] = i0[i];
+  h1[d] = h0[i];
+  v1[d] = v0[i];
+}
+
+// remapped positions of the given node indices (index == n maps to the kept total)
+__global__ void k_remap_pos(const int32_t* pre, const int32_t* total, int n, int a, int b, int c, int32_t* out) {
+  if (threadIdx.x != 0) return;
+  const int xs[3] = {a, b, c};
+  for (int j = 0; j < 3; ++j) out[j] = xs[j] >= n ? *total : pre[xs[j]];
+}
+
+__global__ void k_cand_write(int n, const float* t, const int32_t* pre, const float* nd_value, const int32_t* nd_h,
+                             uint64_t* keys, uint32_t* vals) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n || !(nd_value[i] >= *t)) return;
+  const int d = pre[i];
+  keys[d] = (uint64_t)(uint32_t)nd_h[i];
+  vals[d] = (uint32_t)i;
+}
+
+__global__ void k_final_keys(int nc, const uint32_t* byh_vals, const float* nd_value, uint64_t* keys, uint32_t* vals) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nc) return;
+  const uint32_t node = byh_vals[p];
+  keys[p] = ((uint64_t)(~f2o(nd_value[node])) << 32) | (uint32_t)p;  // value desc, key rank asc
+  vals[p] = node;
+}
+
+__global__ void k_take(int n, const uint64_t* keys, const uint32_t* vals, const float* nd_value, int32_t* sel_node,
+                       float* sel_val, int32_t* sel_rank) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  sel_node[j] = (int32_t)vals[j];
+  sel_val[j] = nd_value[vals[j]];
+  sel_rank[j] = (int32_t)(keys[j] & 0xffffffffu);
+}
+
+namespace {
+struct Nodes {
+  int32_t *p, *i, *h;
+  float* v;
+};
+}  // namespace
+
+glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& out, hipStream_t s, std::string& err,
+                        bool trace) {
+  auto tr = [&](const char* what, long long a, long long c) {
+    if (trace) {
+      std::fprintf(stderr, "[glmb] select.%s %lld %lld\n", what, a, c);
+      std::fflush(stderr);
+    }
+  };
+  const int T = 256;
+  // node store: two copies for compaction
+  auto alloc = [&](int which) {
+    Nodes n;
+    const int64_t c2 = 2 * (int64_t)cap;
+    n.p = need<int32_t>(b.nd_parent, c2) + (which ? cap : 0);
+    n.i = need<int32_t>(b.nd_item, c2) + (which ? cap : 0);
+    n.h = need<int32_t>(b.nd_h, c2) + (which ? cap : 0);
+    n.v = need<float>(b.nd_value, c2) + (which ? cap : 0);
+    return n;
+  };
+  if (in.P > cap) {
+    err = "selection: more parents than search nodes";
+    return GLMB_E_CAPACITY;
+  }
+  Nodes A = alloc(0), B = alloc(1);
+  int32_t* scal = need<int32_t>(b.scal, 16);   // [0]=total, [1..2]=cut, [4..6]=remap
+  float* t = (float*)(scal + 8);               // current threshold
+  float* t2 = (float*)(scal + 9);
+  GLMB_HIP(hipMemcpyAsync(t, in.t0, sizeof(float), hipMemcpyDeviceToDevice, s));
+  int32_t hs[8];
+  auto read = [&](int n) {
+    GLMB_HIP(hipMemcpyAsync(hs, scal, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GLMB_HIP(hipStreamSynchronize(s));
+  };
+  // roots
+  {
+    int32_t* fl = need<int32_t>(b.flags, in.P + 1);
+    int32_t* pre = need<int32_t>(b.pre, in.P + 1);
+    GLMB_LAUNCH(k_root_flags, cdiv(in.P, T), T, 0, s, in.base, in.P, t, fl);
+    scan_excl(fl, pre, in.P, scal, b.tmp, s);
+    GLMB_LAUNCH(k_root_write, cdiv(in.P, T), T, 0, s, in.base, in.P, t, pre, A.p, A.i, A.h, A.v);
+    read(1);
+  }
+  int used = hs[0];
+  if (used > cap) {
+    err = "selection: more parents than search nodes";
+    return GLMB_E_CAPACITY;
+  }
+  int level_first = 0, level_end = used, levels = 0;
+
+  // raise t to a bound on the K-th largest node value and drop nodes below it
+  auto raise_and_compact = [&](int* cursor) -> bool {
+    if (used < in.K) return false;
+    kth_bound(A.v, used, in.K, t2, b.tmp, s);
+    // t = max(t, t2)
+    float th[2];
+    GLMB_HIP(hipMemcpyAsync(th, (float*)(scal + 8), 2 * sizeof(float), hipMemcpyDeviceToHost, s));
+    GLMB_HIP(hipStreamSynchronize(s));
+    if (!(th[1] > th[0])) return false;
+    GLMB_HIP(hipMemcpyAsync(t, t2, sizeof(float), hipMemcpyDeviceToDevice, s));
+    int32_t* fl = need<int32_t>(b.flags, used + 1);
+    int32_t* pre = need<int32_t>(b.pre, used + 1);
+    GLMB_LAUNCH(k_keep_flags, cdiv(used, T), T, 0, s, A.v, used, t, fl);
+    scan_excl(fl, pre, used, scal, b.tmp, s);
+    GLMB_LAUNCH(k_compact_nodes, cdiv(used, T), T, 0, s, used, t, pre, A.p, A.i, A.h, A.v, B.p, B.i, B.h, B.v);
+    GLMB_LAUNCH(k_remap_pos, 1, 64, 0, s, pre, scal, used, level_first, *cursor, level_end, scal + 4);
+    GLMB_HIP(hipMemcpyAsync(hs, scal, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GLMB_HIP(hipStreamSynchronize(s));
+    used = hs[0];
+    level_first = hs[4];
+    *cursor = hs[5];
+    level_end = hs[6];
+    std::swap(A, B);
+    return true;
+  };
+
+  while (level_first < level_end) {
+    ++levels;
+    tr("level", levels, level_end - level_first);
+    if (levels > kMaxDepth + 1) {
+      err = "selection: deeper than the supported number of deviations";
+      return GLMB_E_CAPACITY;
+    }
+    int cursor = level_first;
+    while (cursor < level_end) {
+      const int nlev = level_end - cursor;
+      int64_t* cnt = need<int64_t>(b.cnt, nlev + 1);
+      int64_t* pre = need<int64_t>(b.pre64, nlev + 1);
+      int64_t* tot64 = (int64_t*)(scal + 12);
+      GLMB_LAUNCH(k_count, cdiv(nlev, T), T, 0, s, cursor, nlev, A.i, A.h, A.v, in.it_off, in.it_delta, t, cnt);
+      scan_excl64(cnt, pre, nlev, tot64, b.tmp, s);
+      int64_t total = 0;
+      GLMB_HIP(hipMemcpyAsync(&total, tot64, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+      GLMB_HIP(hipStreamSynchronize(s));
+      if (total == 0) break;
+      const int64_t room = (int64_t)cap - used;
+      int m = nlev;
+      int64_t te = total;
+      if (total > room) {
+        GLMB_LAUNCH(k_cut, 1, 64, 0, s, pre, cnt, nlev, room, scal + 1);
+        GLMB_HIP(hipMemcpyAsync(hs, scal, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        GLMB_HIP(hipStreamSynchronize(s));
+        m = hs[1];
+        te = hs[2];
+        if (m == 0 || used > cap / 2) {
+          if (raise_and_compact(&cursor)) continue;
+          if (m == 0) {
+            err = "selection: search node capacity exhausted (tie class at the cut larger than the node store?)";
+            return GLMB_E_CAPACITY;
+          }
+        }
+      }
+      GLMB_LAUNCH(k_expand, cdiv(te, T), T, 0, s, cursor, m, (int)te, used, pre, A.p, A.i, A.h, A.v, in.it_off,
+                  in.it_delta, in.it_group, t);
+      used += (int)te;
+      cursor += m;
+    }
+    const int next_first = level_end, next_end = used;
+    level_first = next_first;
+    level_end = next_end;
+    if (level_first < level_end) {
+      int c = level_first;
+      raise_and_compact(&c);
+    }
+  }
+  tr("final", used, levels);
+  // candidates: every node >= t, in enumeration order
+  int32_t* fl = need<int32_t>(b.flags, used + 1);
+  int32_t* pre = need<int32_t>(b.pre, used + 1);
+  GLMB_LAUNCH(k_keep_flags, cdiv(used, T), T, 0, s, A.v, used, t, fl);
+  scan_excl(fl, pre, used, scal, b.tmp, s);
+  read(1);
+  const int nc = hs[0];
+  uint64_t* keys = need<uint64_t>(b.keys, nc + 1);
+  uint32_t* vals = need<uint32_t>(b.vals, nc + 1);
+  GLMB_LAUNCH(k_cand_write, cdiv(used, T), T, 0, s, used, t, pre, A.v, A.h, keys, vals);
+  int hbits = 0;
+  while ((1 << hbits) < in.P) ++hbits;
+  sort_pairs(keys, vals, nc, 0, ((hbits + 7) / 8) * 8, b.tk, b.tv, b.tmp, s);  // canonical key order
+  GLMB_LAUNCH(k_final_keys, cdiv(nc, T), T, 0, s, nc, vals, A.v, keys, vals);
+  int rbits = 0;
+  while ((1 << rbits) < nc) ++rbits;
+  sort_pairs(keys, vals, nc, 0, 32 + 32, b.tk, b.tv, b.tmp, s);
+  (void)rbits;
+  const int n = std::min(nc, in.K);
+  out.node = need<int32_t>(b.sel_node, n + 1);
+  out.value = need<float>(b.sel_val, n + 1);
+  out.keyrank = need<int32_t>(b.sel_rank, n + 1);
+  GLMB_LAUNCH(k_take, cdiv(n, T), T, 0, s, n, keys, vals, A.v, out.node, out.value, out.keyrank);
+  out.n = n;
+  out.nd_parent = A.p;
+  out.nd_item = A.i;
+  out.nd_h = A.h;
+  out.nd_value = A.v;
+  out.levels = levels;
+  out.nodes = used;
+  return GLMB_OK;
+}
+
+}  // namespace glmb

@@ -1,0 +1,1153 @@
+// The update of Sec. 3 (Eq. 2 through the end of the section) on the GPU.
+//
+//   U1  gate + score  every (track instance, detection) pair: Mahalanobis gate and the
+//       log Eq. 2 entry phi = log gamma + log N(z; H m, S); per-label detection lists.
+//   U2  for every (hypothesis, detection) cell: best option, first deviation and the
+//       log-sum-exp over {clutter} + gated tracks of the hypothesis; per hypothesis the
+//       best-child log weight B_h and the log mass of all its children (factorised).
+//   U3  exact top-H_max children: per-parent deviation item lists under a lower bound
+//       of the cut, then the level-synchronous selection engine; tau pruning.
+//   U4  one new instance per distinct (predicted instance, detection set) with the
+//       multi-detection Kalman update; child hypothesis rows.
+//   births for the next scan from detections the posterior attributes to clutter.
+//
+// Numerics: FP32 throughout.  Per-hypothesis sums are accumulated relative to a
+// per-detection reference c_i = max(log kappa, max phi_ui), so that hypotheses which agree
+// on a detection contribute an exact 0 there (log weights of ~-5000 never appear); the
+// common constant sum_i c_i cancels in every normalised quantity.
+#include "ctx.hpp"
+
+namespace glmb {
+
+enum : uint32_t { ERR_LMAX = 1, ERR_OPTS = 2, ERR_DEPTH = 4, ERR_NAN = 8, ERR_COLL = 16 };
+
+// ------------------------------------------------------------------ U0 / U1
+__global__ void k_z_in(const float* zin, int M, float2* z, uint32_t* errf) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const float x = zin[2 * i], y = zin[2 * i + 1];
+  if (!(x == x) || !(y == y) || isinf(x) || isinf(y)) atomicOr(errf, ERR_NAN);
+  z[i] = make_float2(x, y);
+}
+
+__global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// one wave per (instance, chunk of 64 detections)
+__global__ __launch_bounds__(256) void k_gate(const DInst* inst, int U, const float2* z, int M, int W, float sig2,
+                                              float gate, float lgc, uint32_t* gbits, float* phi, uint32_t* cmax,
+                                              unsigned long long* ngated) {
+  const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  const int nch = (M + kWave - 1) / kWave;
+  const int u = gw / nch, ch = gw % nch;
+  if (u >= U) return;
+  const int lane = lane_id();
+  const int i = ch * kWave + lane;
+  const DInst& x = inst[u];
+  const float s00 = x.P[0] + sig2, s01 = x.P[1], s11 = x.P[4] + sig2;
+  const float det = s00 * s11 - s01 * s01;
+  bool g = false;
+  float f = -INFINITY;
+  if (i < M) {
+    const float2 zi = z[i];
+    const float n0 = zi.x - x.m[0], n1 = zi.y - x.m[1];
+    const float qd = s11 * n0 * n0 - 2.0f * s01 * n0 * n1 + s00 * n1 * n1;
+    const float d2 = qd / det;
+    g = d2 <= gate;
+    if (g) f = lgc - 0.5f * __logf(det) - 0.5f * d2;
+    phi[(size_t)u * M + i] = f;
+    if (g) atomicMax(&cmax[i], f2o(f));
+  }
+  const uint64_t bal = __ballot(g);
+  if (lane == 0) {
+    gbits[(size_t)u * W + 2 * ch] = (uint32_t)bal;
+    if (2 * ch + 1 < W) gbits[(size_t)u * W + 2 * ch + 1] = (uint32_t)(bal >> 32);
+    if (bal) atomicAdd(ngated, (unsigned long long)__popcll(bal));
+  }
+}
+
+// first instance of every slot (instances are sorted by slot; a slot may hold none)
+__global__ void k_inst_beg(const DInst* inst, int U, int nslot, int32_t* beg) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s > nslot) return;
+  int a = 0, b = U;
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    if (inst[m].slot < s) a = m + 1;
+    else b = m;
+  }
+  beg[s] = a;
+}
+
+// per label: union of its instances' gate bits, prefix popcounts, list length
+__global__ __launch_bounds__(256) void k_label_bits(const uint32_t* gbits, const int32_t* beg, int W, uint32_t* lbits,
+                                                    int32_t* lpre, int32_t* llen, uint32_t* errf) {
+  __shared__ int32_t pc[1024];
+  const int s = blockIdx.x;
+  for (int w = threadIdx.x; w < W; w += blockDim.x) {
+    uint32_t acc = 0;
+    for (int u = beg[s]; u < beg[s + 1]; ++u) acc |= gbits[(size_t)u * W + w];
+    lbits[(size_t)s * W + w] = acc;
+    pc[w] = __popc(acc);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int w = 0; w < W; ++w) {
+      lpre[(size_t)s * W + w] = run;
+      run += pc[w];
+    }
+    llen[s] = run;
+    if (run > kLMax) atomicOr(errf, ERR_LMAX);
+  }
+}
+
+__global__ void k_label_list(const uint32_t* lbits, const int32_t* lpre, const int32_t* loff, int nslot, int W,
+                             int32_t* lmeas) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nslot * W) return;
+  const int s = t / W, w = t % W;
+  uint32_t b = lbits[t];
+  int pos = loff[s] + lpre[t];
+  while (b) {
+    const int k = __ffs(b) - 1;
+    lmeas[pos++] = w * 32 + k;
+    b &= b - 1;
+  }
+}
+
+// per detection (one wave each): candidate label slots in ascending order
+__global__ __launch_bounds__(256) void k_cand(const uint32_t* lbits, int nslot, int W, int M, const int32_t* coff,
+                                              int32_t* ccnt, int32_t* cand) {
+  const int i = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  if (i >= M) return;
+  const int lane = lane_id();
+  int run = 0;
+  for (int s0 = 0; s0 < nslot; s0 += kWave) {
+    const int s = s0 + lane;
+    const bool bit = s < nslot && ((lbits[(size_t)s * W + (i >> 5)] >> (i & 31)) & 1u);
+    const uint64_t bal = __ballot(bit);
+    if (coff && bit) cand[coff[i] + run + __popcll(bal & lanemask_lt())] = s;
+    run += __popcll(bal);
+  }
+  if (!coff && lane == 0) ccnt[i] = run;
+}
+
+// ------------------------------------------------------------------ U2
+__device__ __forceinline__ float block_sum_f(float v, float* sh) {
+  // fixed-order tree: wave butterfly, then waves in order
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane_id() == 0) sh[w] = v;
+  __syncthreads();
+  float r = 0.0f;
+  for (int j = 0; j < (int)(blockDim.x / kWave); ++j) r += sh[j];
+  return r;
+}
+__device__ __forceinline__ float block_max_f(float v, float* sh) {
+  for (int d = kWave / 2; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, kWave));
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane_id() == 0) sh[w] = v;
+  __syncthreads();
+  float r = -INFINITY;
+  for (int j = 0; j < (int)(blockDim.x / kWave); ++j) r = fmaxf(r, sh[j]);
+  return r;
+}
+
+// one block per hypothesis; the hypothesis row is staged in LDS
+__global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t* rows, const float* logw,
+                                               const int32_t* ntrk, int nref, float gamma, float lgk,
+                                               const int32_t* coff, const int32_t* cand, const float* phi,
+                                               const uint32_t* cmax, int16_t* best16, float* dev1, float* lserel,
+                                               float* bprime, float* lzprime, unsigned long long* nopts) {
+  extern __shared__ int32_t row[];
+  __shared__ float red[16];
+  const int h = blockIdx.x;
+  for (int s = threadIdx.x; s < stride; s += blockDim.x) row[s] = rows[(size_t)h * stride + s];
+  __syncthreads();
+  float bsum = 0.0f, lsum = 0.0f;
+  unsigned opts = 0;
+  for (int i = threadIdx.x; i < M; i += blockDim.x) {
+    const float c = o2f(cmax[i]);
+    float b1 = lgk, b2 = -INFINITY, mx = lgk, sm = 1.0f;
+    int k1 = -1;
+    const int e1 = coff[i + 1];
+    for (int e = coff[i]; e < e1; ++e) {
+      const int s = cand[e];
+      const int u = row[s];
+      if (u < 0) continue;
+      const float f = phi[(size_t)u * M + i];
+      if (!(f > -INFINITY)) continue;
+      ++opts;
+      if (f > b1) {
+        b2 = b1;
+        b1 = f;
+        k1 = s;
+      } else if (f > b2) {
+        b2 = f;
+      }
+      if (f > mx) {
+        sm = sm * __expf(mx - f) + 1.0f;
+        mx = f;
+      } else {
+        sm += __expf(f - mx);
+      }
+    }
+    const float l = mx + __logf(sm);
+    const size_t cell = (size_t)h * M + i;
+    best16[cell] = (int16_t)(k1 + 1);
+    dev1[cell] = b2 > -INFINITY ? b1 - b2 : INFINITY;
+    lserel[cell] = l - c;
+    bsum += b1 - c;
+    lsum += l - c;
+  }
+  bsum = block_sum_f(bsum, red);
+  lsum = block_sum_f(lsum, red + 8);
+  if (threadIdx.x == 0) {
+    const float base = logw[h] - gamma * (float)(ntrk[h] - nref);
+    bprime[h] = base + bsum;
+    lzprime[h] = base + lsum;
+  }
+  // option count (integer; order irrelevant)
+  for (int d = kWave / 2; d > 0; d >>= 1) opts += __shfl_xor(opts, d, kWave);
+  if (lane_id() == 0 && opts) atomicAdd(nopts, (unsigned long long)opts);
+}
+
+// ------------------------------------------------------------------ U3
+// one block: log of the total mass, per-parent diagnostics
+__global__ __launch_bounds__(1024) void k_norm(int H, const float* bprime, const float* lzprime, float* lz,
+                                               float* diag_best, float* diag_logpi) {
+  __shared__ float red[32];
+  float mx = -INFINITY;
+  for (int h = threadIdx.x; h < H; h += blockDim.x) mx = fmaxf(mx, lzprime[h]);
+  mx = block_max_f(mx, red);
+  float sm = 0.0f;
+  for (int h = threadIdx.x; h < H; h += blockDim.x) sm += __expf(lzprime[h] - mx);
+  sm = block_sum_f(sm, red + 16);
+  const float L = mx + __logf(sm);
+  for (int h = threadIdx.x; h < H; h += blockDim.x) {
+    diag_best[h] = bprime[h] - L;
+    diag_logpi[h] = lzprime[h] - L;
+  }
+  if (threadIdx.x == 0) *lz = L;
+}
+
+__global__ void k_t0_vals(int H, int M, const float* bprime, const float* dev1, float* vals) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)H * (M + 1)) return;
+  const int h = (int)(t / (M + 1)), i = (int)(t % (M + 1));
+  vals[t] = i == M ? bprime[h] : bprime[h] - dev1[(size_t)h * M + i];
+}
+
+__global__ void k_cell_flags(int H, int M, const float* bprime, const float* dev1, const float* t0, int32_t* flags) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (int64_t)H * M) return;
+  flags[c] = bprime[c / M] - dev1[c] >= *t0 ? 1 : 0;
+}
+__global__ void k_cell_write(int64_t n, const int32_t* flags, const int32_t* pre, int32_t* cells) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n && flags[c]) cells[pre[c]] = (int32_t)c;
+}
+
+// options of cell (h, i) ordered by (phi desc, key asc); clutter has key -1
+__device__ int cell_options(int h, int i, int M, int stride, const int32_t* rows, const int32_t* coff,
+                            const int32_t* cand, const float* phi, float lgk, float* f, int* key, uint32_t* errf) {
+  int n = 1;
+  f[0] = lgk;
+  key[0] = -1;
+  for (int e = coff[i]; e < coff[i + 1]; ++e) {
+    const int s = cand[e];
+    const int u = rows[(size_t)h * stride + s];
+    if (u < 0) continue;
+    const float v = phi[(size_t)u * M + i];
+    if (!(v > -INFINITY)) continue;
+    if (n >= kMaxOpts) {
+      atomicOr(errf, ERR_OPTS);
+      break;
+    }
+    // insertion (entries arrive in ascending key, so ties keep the earlier key first)
+    int j = n++;
+    while (j > 0 && f[j - 1] < v) {
+      f[j] = f[j - 1];
+      key[j] = key[j - 1];
+      --j;
+    }
+    f[j] = v;
+    key[j] = s;
+  }
+  return n;
+}
+
+__global__ void k_items(int ncell, const int32_t* cells, int M, int stride, const int32_t* rows, const int32_t* coff,
+                        const int32_t* cand, const float* phi, float lgk, const float* bprime, const float* t0,
+                        const int32_t* ioff, int32_t* icount, float* it_delta, int32_t* it_group, int32_t* it_opt,
+                        uint64_t* keys, uint32_t* vals, uint32_t* errf) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncell) return;
+  const int cell = cells[c];
+  const int h = cell / M, i = cell % M;
+  float f[kMaxOpts];
+  int key[kMaxOpts];
+  const int n = cell_options(h, i, M, stride, rows, coff, cand, phi, lgk, f, key, errf);
+  const float B = bprime[h], t = *t0;
+  int cnt = 0;
+  for (int r = 1; r < n; ++r) {
+    const float d = f[0] - f[r];
+    if (B - d >= t) {
+      if (ioff) {
+        const int q = ioff[c] + cnt;
+        it_delta[q] = d;
+        it_group[q] = i;
+        it_opt[q] = key[r];
+        keys[q] = ((uint64_t)(uint32_t)h << 32) | f2o(d);
+        vals[q] = (uint32_t)q;
+      }
+      ++cnt;
+    }
+  }
+  if (!ioff) icount[c] = cnt;
+}
+
+__global__ void k_item_perm(int n, const uint32_t* vals, const float* d0, const int32_t* g0, const int32_t* o0,
+                            float* d1, int32_t* g1, int32_t* o1) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint32_t q = vals[p];
+  d1[p] = d0[q];
+  g1[p] = g0[q];
+  o1[p] = o0[q];
+}
+
+// it_off[h] = first sorted item with parent >= h
+__global__ void k_item_off(int H, int n, const uint64_t* keys, int32_t* it_off) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h > H) return;
+  int a = 0, b = n;
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    if ((int)(keys[m] >> 32) < h) a = m + 1;
+    else b = m;
+  }
+  it_off[h] = a;
+}
+
+// one block: normalise over the selected children, tau pruning (the first is always kept)
+__global__ __launch_bounds__(1024) void k_prune(int n, const float* v, float tau, const float* lz, float* logw_out,
+                                                int32_t* nkeep, float* retained) {
+  __shared__ float red[32];
+  __shared__ int32_t cnt;
+  float mx = v[0];
+  float sm = 0.0f;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) sm += __expf(v[j] - mx);
+  sm = block_sum_f(sm, red);
+  const float L = mx + __logf(sm);
+  if (threadIdx.x == 0) cnt = 1;
+  __syncthreads();
+  int mine = 0;
+  if (tau > 0.0f) {
+    for (int j = 1 + threadIdx.x; j < n; j += blockDim.x)
+      if (__expf(v[j] - L) >= tau) ++mine;
+  } else {
+    for (int j = 1 + threadIdx.x; j < n; j += blockDim.x) ++mine;
+  }
+  if (mine) atomicAdd(&cnt, mine);
+  __syncthreads();
+  const int keep = cnt;
+  float s2 = 0.0f;
+  for (int j = threadIdx.x; j < keep; j += blockDim.x) s2 += __expf(v[j] - mx);
+  s2 = block_sum_f(s2, red + 16);
+  const float L2 = mx + __logf(s2);
+  for (int j = threadIdx.x; j < keep; j += blockDim.x) logw_out[j] = v[j] - L2;
+  if (threadIdx.x == 0) {
+    *nkeep = keep;
+    *retained = L2 - *lz;  // log of the retained posterior mass
+  }
+}
+
+// ------------------------------------------------------------------ U4 materialise
+__global__ void k_child_depth(int n, const int32_t* sel_node, const int32_t* nd_parent, const int32_t* nd_item,
+                              const int32_t* nd_h, int32_t* depth, int32_t* ch_h, uint32_t* errf) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  int d = 0;
+  int x = sel_node[c];
+  ch_h[c] = nd_h[x];
+  for (; nd_item[x] >= 0; x = nd_parent[x]) ++d;
+  if (d > kMaxDepth) atomicOr(errf, ERR_DEPTH);
+  depth[c] = d;
+}
+
+__global__ void k_child_devs(int n, int M, const int32_t* sel_node, const int32_t* nd_parent, const int32_t* nd_item,
+                             const int32_t* ch_h, const int32_t* doff, const int32_t* it_group, const int32_t* it_opt,
+                             const int16_t* best16, int32_t* dev_i, int32_t* dev_new, int32_t* dev_old) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  int q = doff[c];
+  const int h = ch_h[c];
+  for (int x = sel_node[c]; nd_item[x] >= 0; x = nd_parent[x], ++q) {
+    const int it = nd_item[x];
+    const int i = it_group[it];
+    dev_i[q] = i;
+    dev_new[q] = it_opt[it];
+    dev_old[q] = (int)best16[(size_t)h * M + i] - 1;
+  }
+}
+
+__global__ void k_mark(int n, const int32_t* ch_h, int32_t* mark) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n) mark[ch_h[c]] = 1;
+}
+__global__ void k_plist(int H, const int32_t* mark, const int32_t* pre, int32_t* plist, int32_t* hp_map) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= H) return;
+  hp_map[h] = mark[h] ? pre[h] : -1;
+  if (mark[h]) plist[pre[h]] = h;
+}
+
+__global__ void k_first(int np, const int32_t* plist, int stride, const int32_t* rows, int32_t* first) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)np * stride) return;
+  const int h = plist[t / stride];
+  const int u = rows[(size_t)h * stride + (t % stride)];
+  if (u >= 0) atomicMin(&first[u], h);
+}
+
+__device__ __forceinline__ int lpos(const int32_t* lmeas, int off, int len, int i) {
+  int a = 0, b = len;
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    if (lmeas[off + m] < i) a = m + 1;
+    else b = m;
+  }
+  return a;
+}
+
+// detection-set masks of every slot of hypothesis h under its best association map
+__device__ void build_masks(int h, int M, int nslot, const int16_t* best16, const int32_t* loff, const int32_t* llen,
+                            const int32_t* lmeas, uint32_t* mask) {
+  for (int k = threadIdx.x; k < nslot * 4; k += blockDim.x) mask[k] = 0u;
+  __syncthreads();
+  for (int i = threadIdx.x; i < M; i += blockDim.x) {
+    const int s = (int)best16[(size_t)h * M + i] - 1;
+    if (s < 0) continue;
+    const int j = lpos(lmeas, loff[s], llen[s], i);
+    if (j < llen[s] && j < kLMax) atomicOr(&mask[s * 4 + (j >> 5)], 1u << (j & 31));
+  }
+  __syncthreads();
+}
+
+struct Rec {
+  uint32_t m[4];
+  int32_t u, a, b, pad;  // instance; (parent index, slot) or (child, slot)
+};
+
+__global__ __launch_bounds__(256) void k_default_masks(const int32_t* plist, int M, int nslot, int stride,
+                                                       const int32_t* rows, const int16_t* best16,
+                                                       const int32_t* loff, const int32_t* llen,
+                                                       const int32_t* lmeas, const int32_t* first, uint4* dmask) {
+  extern __shared__ uint32_t mask[];
+  const int h = plist[blockIdx.x];
+  build_masks(h, M, nslot, best16, loff, llen, lmeas, mask);
+  for (int s = threadIdx.x; s < nslot; s += blockDim.x) {
+    const int u = rows[(size_t)h * stride + s];
+    if (u >= 0 && first[u] == h) dmask[u] = make_uint4(mask[4 * s], mask[4 * s + 1], mask[4 * s + 2], mask[4 * s + 3]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_exceptions(const int32_t* plist, int M, int nslot, int stride,
+                                                    const int32_t* rows, const int16_t* best16, const int32_t* loff,
+                                                    const int32_t* llen, const int32_t* lmeas, const uint4* dmask,
+                                                    int32_t* nexc, Rec* exc, int cap) {
+  extern __shared__ uint32_t mask[];
+  const int hp = blockIdx.x;
+  const int h = plist[hp];
+  build_masks(h, M, nslot, best16, loff, llen, lmeas, mask);
+  for (int s = threadIdx.x; s < nslot; s += blockDim.x) {
+    const int u = rows[(size_t)h * stride + s];
+    if (u < 0) continue;
+    const uint4 d = dmask[u];
+    if (d.x != mask[4 * s] || d.y != mask[4 * s + 1] || d.z != mask[4 * s + 2] || d.w != mask[4 * s + 3]) {
+      const int k = atomicAdd(nexc, 1);
+      if (k < cap) {
+        Rec r;
+        for (int j = 0; j < 4; ++j) r.m[j] = mask[4 * s + j];
+        r.u = u;
+        r.a = hp;
+        r.b = s;
+        r.pad = 0;
+        exc[k] = r;
+      }
+    }
+  }
+}
+
+__global__ void k_exc_keys(int n, const Rec* exc, uint64_t* keys, uint32_t* vals) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  keys[k] = ((uint64_t)(uint32_t)exc[k].a << 32) | (uint32_t)exc[k].b;
+  vals[k] = (uint32_t)k;
+}
+__global__ void k_exc_perm(int n, const uint32_t* vals, const Rec* in, Rec* out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = in[vals[k]];
+}
+__global__ void k_exc_off(int np, int n, const Rec* exc, int32_t* eoff) {
+  const int hp = blockIdx.x * blockDim.x + threadIdx.x;
+  if (hp > np) return;
+  int a = 0, b = n;
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    if (exc[m].a < hp) a = m + 1;
+    else b = m;
+  }
+  eoff[hp] = a;
+}
+
+__device__ __forceinline__ int find_exc(const Rec* exc, const int32_t* eoff, int hp, int s) {
+  int a = eoff[hp], b = eoff[hp + 1];
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    if (exc[m].b < s) a = m + 1;
+    else b = m;
+  }
+  return (a < eoff[hp + 1] && exc[a].b == s) ? a : -1;
+}
+
+// per child: detection-set masks of the slots its deviations touch
+__global__ void k_child_mods(int n, const int32_t* ch_h, const int32_t* hp_map, const int32_t* doff,
+                             const int32_t* dev_i, const int32_t* dev_new, const int32_t* dev_old, int stride,
+                             const int32_t* rows, const int32_t* loff, const int32_t* llen, const int32_t* lmeas,
+                             const uint4* dmask, const Rec* exc, const int32_t* eoff, const int32_t* moff,
+                             int32_t* mcount, Rec* mods) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const int h = ch_h[c], hp = hp_map[h];
+  const int d0 = doff[c], d1 = doff[c + 1];
+  int cnt = 0;
+  // affected slots, each handled once (at its first appearance)
+  for (int q = d0; q < d1; ++q) {
+    for (int side = 0; side < 2; ++side) {
+      const int s = side ? dev_new[q] : dev_old[q];
+      if (s < 0) continue;
+      bool seen = side == 1 && dev_old[q] == s;
+      for (int r = d0; r < q && !seen; ++r) seen = dev_old[r] == s || dev_new[r] == s;
+      if (seen) continue;
+      if (moff) {
+        const int u = rows[(size_t)h * stride + s];
+        Rec r;
+        const int e = find_exc(exc, eoff, hp, s);
+        uint4 m0 = e >= 0 ? make_uint4(exc[e].m[0], exc[e].m[1], exc[e].m[2], exc[e].m[3]) : dmask[u];
+        r.m[0] = m0.x;
+        r.m[1] = m0.y;
+        r.m[2] = m0.z;
+        r.m[3] = m0.w;
+        for (int t = d0; t < d1; ++t) {
+          if (dev_old[t] != s && dev_new[t] != s) continue;
+          const int j = lpos(lmeas, loff[s], llen[s], dev_i[t]);
+          if (j >= llen[s] || j >= kLMax) continue;
+          if (dev_old[t] == s) r.m[j >> 5] &= ~(1u << (j & 31));
+          if (dev_new[t] == s) r.m[j >> 5] |= 1u << (j & 31);
+        }
+        r.u = u;
+        r.a = c;
+        r.b = s;
+        r.pad = 0;
+        mods[moff[c] + cnt] = r;
+      }
+      ++cnt;
+    }
+  }
+  if (!moff) mcount[c] = cnt;
+}
+
+__device__ __forceinline__ uint32_t mask_hash(const uint32_t* m) {
+  uint64_t x = ((uint64_t)m[1] << 32) | m[0];
+  uint64_t y = ((uint64_t)m[3] << 32) | m[2];
+  return (uint32_t)(mix64(x ^ mix64(y)) >> 32);
+}
+
+// all (instance, mask) records: defaults (one per referenced instance), exceptions, child masks
+__global__ void k_rec_defaults(int U, const int32_t* first, const uint4* dmask, const int32_t* dpre, Rec* recs) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= U || first[u] == INT32_MAX) return;
+  Rec r;
+  const uint4 d = dmask[u];
+  r.m[0] = d.x;
+  r.m[1] = d.y;
+  r.m[2] = d.z;
+  r.m[3] = d.w;
+  r.u = u;
+  r.a = r.b = r.pad = 0;
+  recs[dpre[u]] = r;
+}
+__global__ void k_rec_copy(int n, const Rec* in, Rec* out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = in[k];
+}
+__global__ void k_rec_keys(int n, const Rec* recs, uint64_t* keys, uint32_t* vals) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  keys[k] = ((uint64_t)(uint32_t)recs[k].u << 32) | mask_hash(recs[k].m);
+  vals[k] = (uint32_t)k;
+}
+__device__ __forceinline__ bool rec_eq(const Rec& a, const Rec& b) {
+  return a.u == b.u && a.m[0] == b.m[0] && a.m[1] == b.m[1] && a.m[2] == b.m[2] && a.m[3] == b.m[3];
+}
+__global__ void k_rec_unique(int n, const uint64_t* keys, const uint32_t* vals, const Rec* recs, int32_t* flag,
+                             uint32_t* errf) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  bool nw = p == 0 || keys[p] != keys[p - 1] || !rec_eq(recs[vals[p]], recs[vals[p - 1]]);
+  if (p > 0 && keys[p] == keys[p - 1] && nw) atomicOr(errf, ERR_COLL);  // hash collision: not exact
+  flag[p] = nw ? 1 : 0;
+}
+__global__ void k_rec_ids(int n, const uint32_t* vals, const int32_t* flag, const int32_t* pre, int32_t* rec_id,
+                          int32_t* rep) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int id = pre[p] + flag[p] - 1;
+  rec_id[vals[p]] = id;
+  if (flag[p]) rep[id] = (int32_t)vals[p];
+}
+
+// Kalman update of every distinct (instance, detection set)
+__global__ void k_kalman(int nnew, const int32_t* rep, const Rec* recs, const DInst* pin, const int32_t* loff,
+                         const int32_t* lmeas, const float2* z, float sig2, DInst* out, int32_t* onz, int32_t* oz) {
+  const int id = blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= nnew) return;
+  const Rec& r = recs[rep[id]];
+  const DInst x = pin[r.u];
+  DInst y = x;
+  int nz = 0;
+  float sx = 0.0f, sy = 0.0f;
+  const int off = loff[x.slot];
+  for (int w = 0; w < 4; ++w) {
+    uint32_t b = r.m[w];
+    while (b) {
+      const int j = w * 32 + __ffs(b) - 1;
+      b &= b - 1;
+      const int i = lmeas[off + j];
+      const float2 zi = z[i];
+      sx += zi.x;
+      sy += zi.y;
+      if (nz < 8) oz[(size_t)id * 8 + nz] = i;
+      ++nz;
+    }
+  }
+  onz[id] = nz;
+  if (nz > 0) {
+    const float inv = 1.0f / (float)nz;
+    const float zb0 = sx * inv, zb1 = sy * inv;
+    const float* P = x.P;
+    const float rr = sig2 * inv;
+    const float s00 = P[0] + rr, s01 = P[1], s11 = P[4] + rr;
+    const float det = s00 * s11 - s01 * s01;
+    const float i00 = s11 / det, i01 = -s01 / det, i11 = s00 / det;
+    // columns of P H^T: a_k = P[k][0], b_k = P[k][1]
+    const float a[4] = {P[0], P[1], P[2], P[3]};
+    const float bq[4] = {P[1], P[4], P[5], P[6]};
+    float K0[4], K1[4];
+    for (int k = 0; k < 4; ++k) {
+      K0[k] = a[k] * i00 + bq[k] * i01;
+      K1[k] = a[k] * i01 + bq[k] * i11;
+    }
+    const float n0 = zb0 - x.m[0], n1 = zb1 - x.m[1];
+    for (int k = 0; k < 4; ++k) y.m[k] = x.m[k] + K0[k] * n0 + K1[k] * n1;
+    // P' = P - [a b] S^-1 [a b]^T
+    int t = 0;
+    for (int r0 = 0; r0 < 4; ++r0)
+      for (int c0 = r0; c0 < 4; ++c0, ++t) y.P[t] = P[t] - (K0[r0] * a[c0] + K1[r0] * bq[c0]);
+  }
+  out[id] = y;
+}
+
+// child rows: parent row with every instance replaced by its updated instance
+__global__ __launch_bounds__(256) void k_child_rows(int n, int stride, const int32_t* ch_h, const int32_t* hp_map,
+                                                    const int32_t* rows, const int32_t* first, const int32_t* did,
+                                                    const Rec* exc, const int32_t* eoff, const int32_t* exc_id,
+                                                    const int32_t* moff, const Rec* mods, const int32_t* mod_id,
+                                                    int32_t* out) {
+  const int c = blockIdx.x;
+  const int h = ch_h[c], hp = hp_map[h];
+  const int m0 = moff[c], m1 = moff[c + 1];
+  for (int s = threadIdx.x; s < stride; s += blockDim.x) {
+    const int u = rows[(size_t)h * stride + s];
+    int id = -1;
+    if (u >= 0) {
+      id = did[u];
+      const int e = find_exc(exc, eoff, hp, s);
+      if (e >= 0) id = exc_id[e];
+      for (int q = m0; q < m1; ++q)
+        if (mods[q].b == s) id = mod_id[q];
+    }
+    out[(size_t)c * stride + s] = id;
+  }
+}
+
+__global__ void k_gather_i32(int n, const int32_t* idx, const int32_t* in, int32_t* out) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) out[k] = in[idx[k]];
+}
+__global__ void k_did(int U, const int32_t* first, const int32_t* dpre, const int32_t* rec_id, int32_t* did) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < U) did[u] = first[u] == INT32_MAX ? -1 : rec_id[dpre[u]];
+}
+__global__ void k_def_flags(int U, const int32_t* first, int32_t* fl) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u < U) fl[u] = first[u] == INT32_MAX ? 0 : 1;
+}
+
+// ------------------------------------------------------------------ births
+__global__ __launch_bounds__(256) void k_ru_part(int H, int M, int hchunk, const float* lzprime, const float* lz,
+                                                 const float* lserel, const uint32_t* cmax, float lgk, float* part) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ch = blockIdx.y;
+  if (i >= M) return;
+  const float c = o2f(cmax[i]);
+  const float L = *lz;
+  float acc = 0.0f;
+  const int h1 = min(H, (ch + 1) * hchunk);
+  for (int h = ch * hchunk; h < h1; ++h) acc += __expf(lzprime[h] - L + lgk - c - lserel[(size_t)h * M + i]);
+  part[(size_t)ch * M + i] = acc;
+}
+__global__ void k_ru_final(int M, int nch, const float* part, float* ru) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  float s = 0.0f;
+  for (int ch = 0; ch < nch; ++ch) s += part[(size_t)ch * M + i];
+  ru[i] = 1.0f - s;
+}
+
+// one wave: greedy clustering of the seeds in detection order (a seed joins the first
+// cluster whose first seed lies within cd), one birth per cluster
+constexpr int kMaxClusters = 4096;
+__global__ __launch_bounds__(64) void k_births(int M, const float2* z, const float* ru, float rumax, float cd,
+                                               float sig2, float sigv2, float rmax, float brate, int32_t* member,
+                                               DBirth* out, int32_t* nb_out, uint32_t* errf) {
+  __shared__ float2 az[kMaxClusters];
+  const int lane = lane_id();
+  int ncl = 0;
+  const float cd2 = cd * cd;
+  for (int i0 = 0; i0 < M; i0 += kWave) {
+    const int ii = i0 + lane;
+    const bool seed = ii < M && ru[ii] < rumax;
+    const uint64_t seeds = __ballot(seed);
+    if (ii < M && !seed) member[ii] = -1;
+    uint64_t b = seeds;
+    while (b) {
+      const int i = i0 + __ffsll((unsigned long long)b) - 1;
+      b &= b - 1;
+      const float2 zi = z[i];
+      int found = -1;
+      for (int c0 = 0; c0 < ncl && found < 0; c0 += kWave) {
+        const int c = c0 + lane;
+        bool hit = false;
+        if (c < ncl) {
+          const float dx = zi.x - az[c].x, dy = zi.y - az[c].y;
+          hit = dx * dx + dy * dy <= cd2;
+        }
+        const uint64_t hb = __ballot(hit);
+        if (hb) found = c0 + __ffsll((unsigned long long)hb) - 1;
+      }
+      if (found < 0) {
+        if (ncl >= kMaxClusters) {
+          if (lane == 0) atomicOr(errf, ERR_LMAX);
+          found = kMaxClusters - 1;
+        } else {
+          if (lane == 0) az[ncl] = zi;
+          found = ncl++;
+        }
+      }
+      if (lane == 0) member[i] = found;
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  // total weight of the seeds (sequential, fixed order)
+  float tot = 0.0f;
+  for (int i = 0; i < M; ++i)
+    if (member[i] >= 0) tot += 1.0f - ru[i];
+  for (int c = lane; c < ncl; c += kWave) {
+    float sx = 0.0f, sy = 0.0f, w = 0.0f;
+    int n = 0;
+    for (int i = 0; i < M; ++i)
+      if (member[i] == c) {
+        sx += z[i].x;
+        sy += z[i].y;
+        w += 1.0f - ru[i];
+        ++n;
+      }
+    DBirth bb;
+    bb.m[0] = sx / (float)n;
+    bb.m[1] = sy / (float)n;
+    bb.m[2] = bb.m[3] = 0.0f;
+    for (int k = 0; k < 10; ++k) bb.P[k] = 0.0f;
+    bb.P[0] = bb.P[4] = sig2 / (float)n;
+    bb.P[7] = bb.P[9] = sigv2;
+    bb.r = fminf(rmax, brate * w / tot);
+    bb.pad = 0;
+    out[c] = bb;
+  }
+  if (lane == 0) *nb_out = ncl;
+}
+
+// ------------------------------------------------------------------ orchestration
+namespace {
+template <class T> T read1(hipStream_t s, const T* p) {
+  T v;
+  GLMB_HIP(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipStreamSynchronize(s));
+  return v;
+}
+void check_err(hipStream_t s, const uint32_t* errf) {
+  const uint32_t e = read1(s, errf);
+  if (e & ERR_NAN) throw Error{GLMB_E_ARG, "detections contain NaN or infinity"};
+  if (e & ERR_LMAX) throw Error{GLMB_E_CAPACITY, "more than 128 detections gated with one label"};
+  if (e & ERR_OPTS) throw Error{GLMB_E_CAPACITY, "more than 64 options in one (hypothesis, detection) cell"};
+  if (e & ERR_DEPTH) throw Error{GLMB_E_CAPACITY, "a kept child deviates in more than 48 detections"};
+  if (e & ERR_COLL) throw Error{GLMB_E_STATE, "detection-set fingerprint collision"};
+}
+}  // namespace
+
+void stage_update(Ctx& c, int k, const float* zin, int M) {
+  (void)k;
+  hipStream_t s = c.s;
+  const int T = 256;
+  const int H = c.nhyp, U = c.ninst, NS = c.nslot, SW = c.stride;
+  const glmb_params& p = c.p;
+  const float sig2 = p.sigma_z * p.sigma_z;
+  const float lgk = logf(p.clutter_density);
+  const float lgc = (float)(std::log((double)p.det_rate) - std::log(2.0 * M_PI));
+  const int W = std::max(1, (M + 31) / 32);
+  // scalars: [0] errf, [1..2] ngated (u64), [3..4] nopts (u64), [8] logZ', [9] t0, [10] nkeep,
+  // [11] retained, [12..] small counters
+  int32_t* scal = need<int32_t>(c.scal, 64);
+  uint32_t* errf = (uint32_t*)scal;
+  unsigned long long* ngated = (unsigned long long*)(scal + 2);
+  unsigned long long* nopts = (unsigned long long*)(scal + 4);
+  float* lz = (float*)(scal + 8);
+  float* t0 = (float*)(scal + 9);
+  int32_t* nkeep = scal + 10;
+  float* retained = (float*)(scal + 11);
+  int32_t* tot = scal + 12;
+  int32_t* nb_out = scal + 13;
+  GLMB_HIP(hipMemsetAsync(scal, 0, 64 * sizeof(int32_t), s));
+
+  c.stats = glmb_step_stats{};
+  c.stats.n_hyp_in = H;
+  c.stats.n_meas = M;
+  c.stats.n_inst_in = U;
+  c.stats.n_labels = NS;
+  int64_t dense = 0;
+
+  // ---- U0: detections
+  trace(c, "update.begin", H, M);
+  float2* z = need<float2>(c.z, M);
+  GLMB_LAUNCH(k_z_in, cdiv(M, T), T, 0, s, zin, M, z, errf);
+
+  // ---- U1: gate and score
+  trace(c, "update.U1");
+  uint32_t* cmax = need<uint32_t>(c.cmax, M);
+  {
+    uint32_t init;
+    float fl = lgk;
+    uint32_t uu;
+    std::memcpy(&uu, &fl, 4);
+    init = (uu & 0x80000000u) ? ~uu : (uu | 0x80000000u);
+    GLMB_LAUNCH(k_fill_u32, cdiv(M, T), T, 0, s, cmax, M, init);
+  }
+  uint32_t* gbits = need<uint32_t>(c.gbits, (int64_t)U * W);
+  float* phi = need<float>(c.phi, (int64_t)U * M);
+  if (U > 0 && M > 0) {
+    const int64_t waves = (int64_t)U * cdiv(M, kWave);
+    GLMB_LAUNCH(k_gate, cdiv(waves * kWave, T), T, 0, s, (const DInst*)c.inst.p, U, z, M, W, sig2, p.gate_d2, lgc,
+                gbits, phi, cmax, ngated);
+  }
+  int32_t* beg = need<int32_t>(c.inst_beg, NS + 1);
+  GLMB_LAUNCH(k_inst_beg, cdiv(NS + 1, T), T, 0, s, (const DInst*)c.inst.p, U, NS, beg);
+  uint32_t* lbits = need<uint32_t>(c.lbits, (int64_t)NS * W);
+  int32_t* lpre = need<int32_t>(c.lpre, (int64_t)NS * W);
+  int32_t* llen = need<int32_t>(c.llen, NS + 1);
+  int32_t* loff = need<int32_t>(c.loff, NS + 1);
+  if (M > 0) GLMB_LAUNCH(k_label_bits, NS, 256, 0, s, gbits, beg, W, lbits, lpre, llen, errf);
+  else GLMB_LAUNCH(k_fill_i32, cdiv(NS + 1, T), T, 0, s, llen, NS + 1, 0);
+  scan_excl(llen, loff, NS, tot, c.tmp, s);
+  const int nl = read1(s, tot);
+  int32_t* lmeas = need<int32_t>(c.lmeas, nl);
+  if (M > 0) GLMB_LAUNCH(k_label_list, cdiv((int64_t)NS * W, T), T, 0, s, lbits, lpre, loff, NS, W, lmeas);
+  int32_t* ccnt = need<int32_t>(c.ccnt, M + 1);
+  int32_t* coff = need<int32_t>(c.coff, M + 1);
+  GLMB_LAUNCH(k_cand, cdiv((int64_t)M * kWave, T), T, 0, s, lbits, NS, W, M, (const int32_t*)nullptr, ccnt,
+              (int32_t*)nullptr);
+  scan_excl(ccnt, coff, M, coff + M, c.tmp, s);
+  const int ncand = M > 0 ? read1(s, coff + M) : 0;
+  int32_t* cand = need<int32_t>(c.cand, ncand);
+  GLMB_LAUNCH(k_cand, cdiv((int64_t)M * kWave, T), T, 0, s, lbits, NS, W, M, (const int32_t*)coff, ccnt, cand);
+  check_err(s, errf);
+
+  // ---- U2: per (hypothesis, detection) normalisers
+  trace(c, "update.U2", ncand, NS);
+  const int64_t HM = (int64_t)H * M;
+  int16_t* best16 = need<int16_t>(c.best16, HM);
+  float* dev1 = need<float>(c.dev1, HM);
+  float* lserel = need<float>(c.lserel, HM);
+  float* bprime = need<float>(c.bprime, H);
+  float* lzprime = need<float>(c.lzprime, H);
+  int32_t nref = 0;
+  GLMB_HIP(hipMemcpyAsync(&nref, c.ntrk.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipStreamSynchronize(s));
+  {
+    std::vector<int32_t> nt(H);
+    GLMB_HIP(hipMemcpyAsync(nt.data(), c.ntrk.p, H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GLMB_HIP(hipStreamSynchronize(s));
+    for (int h = 0; h < H; ++h) dense += (int64_t)nt[h] * M;
+  }
+  GLMB_LAUNCH(k_assoc, H, 256, SW * sizeof(int32_t), s, M, SW, c.rows.as<int32_t>(), c.logw.as<float>(),
+              c.ntrk.as<int32_t>(), nref, p.det_rate, lgk, coff, cand, phi, cmax, best16, dev1, lserel, bprime,
+              lzprime, nopts);
+  float* dbest = need<float>(c.diag_best, H);
+  float* dlogpi = need<float>(c.diag_logpi, H);
+  GLMB_LAUNCH(k_norm, 1, 1024, 0, s, H, bprime, lzprime, lz, dbest, dlogpi);
+
+  // ---- U3: lower bound of the cut, deviation items, exact selection
+  trace(c, "update.U3");
+  const int K = p.h_max;
+  float* vals = need<float>(c.vals, (int64_t)H * (M + 1));
+  GLMB_LAUNCH(k_t0_vals, cdiv((int64_t)H * (M + 1), T), T, 0, s, H, M, bprime, dev1, vals);
+  kth_bound(vals, H * (M + 1), K, t0, c.tmp, s);
+  int32_t* flags = need<int32_t>(c.flags, HM + 1);
+  int32_t* pre = need<int32_t>(c.pre, HM + 1);
+  GLMB_LAUNCH(k_cell_flags, cdiv(HM, T), T, 0, s, H, M, bprime, dev1, t0, flags);
+  scan_excl(flags, pre, (int)HM, tot, c.tmp, s);
+  const int ncell = read1(s, tot);
+  int32_t* cells = need<int32_t>(c.cells, ncell);
+  GLMB_LAUNCH(k_cell_write, cdiv(HM, T), T, 0, s, HM, flags, pre, cells);
+  int32_t* icount = need<int32_t>(c.ccount, ncell + 1);
+  int32_t* ioff = need<int32_t>(c.coff2, ncell + 1);
+  GLMB_LAUNCH(k_items, cdiv(ncell, T), T, 0, s, ncell, cells, M, SW, c.rows.as<int32_t>(), coff, cand, phi, lgk,
+              bprime, t0, (const int32_t*)nullptr, icount, (float*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
+              (uint64_t*)nullptr, (uint32_t*)nullptr, errf);
+  scan_excl(icount, ioff, ncell, ioff + ncell, c.tmp, s);
+  const int nitem = read1(s, ioff + ncell);
+  check_err(s, errf);
+  float* itd0 = need<float>(c.it_delta, 2 * (int64_t)nitem);
+  int32_t* itg0 = need<int32_t>(c.it_group, 2 * (int64_t)nitem);
+  int32_t* ito0 = need<int32_t>(c.it_opt, 2 * (int64_t)nitem);
+  uint64_t* ikeys = need<uint64_t>(c.keys, nitem);
+  uint32_t* ivals = need<uint32_t>(c.vals32, nitem);
+  GLMB_LAUNCH(k_items, cdiv(ncell, T), T, 0, s, ncell, cells, M, SW, c.rows.as<int32_t>(), coff, cand, phi, lgk,
+              bprime, t0, (const int32_t*)ioff, icount, itd0, itg0, ito0, ikeys, ivals, errf);
+  int hbits = 0;
+  while ((1 << hbits) < H) ++hbits;
+  sort_pairs(ikeys, ivals, nitem, 0, 32 + ((hbits + 7) / 8) * 8, c.tk, c.tv, c.tmp, s);
+  float* itd = itd0 + nitem;
+  int32_t* itg = itg0 + nitem;
+  int32_t* ito = ito0 + nitem;
+  GLMB_LAUNCH(k_item_perm, cdiv(nitem, T), T, 0, s, nitem, ivals, itd0, itg0, ito0, itd, itg, ito);
+  int32_t* itoff = need<int32_t>(c.it_off, H + 1);
+  GLMB_LAUNCH(k_item_off, cdiv(H + 1, T), T, 0, s, H, nitem, ikeys, itoff);
+
+  SelectIn si{H, bprime, itoff, itd, itg, K, t0};
+  trace(c, "update.select", ncell, nitem);
+  Selected sel{};
+  std::string serr;
+  const int cap_nodes = p.cap_nodes > 0 ? p.cap_nodes : (1 << 22);
+  glmb_status st = select_topk(si, cap_nodes, c.sb, sel, s, serr, c.trace);
+  if (st != GLMB_OK) throw Error{st, serr};
+  const int nsel = sel.n;
+  if (nsel < 1) throw Error{GLMB_E_STATE, "selection kept no hypothesis (non-finite weights?)"};
+  float* wout = need<float>(c.logw2, nsel);
+  GLMB_LAUNCH(k_prune, 1, 1024, 0, s, nsel, sel.value, p.tau, lz, wout, nkeep, retained);
+  const int nk = read1(s, nkeep);
+
+  // ---- U4: children, distinct (instance, detection set), Kalman, rows
+  trace(c, "update.U4", nsel, nk);
+  int32_t* depth = need<int32_t>(c.ccount, nk + 1);
+  int32_t* chh = need<int32_t>(c.child_par, nk + 1);
+  int32_t* doff = need<int32_t>(c.dev_off, nk + 1);
+  GLMB_LAUNCH(k_child_depth, cdiv(nk, T), T, 0, s, nk, sel.node, sel.nd_parent, sel.nd_item, sel.nd_h, depth, chh,
+              errf);
+  scan_excl(depth, doff, nk, doff + nk, c.tmp, s);
+  const int ndev = read1(s, doff + nk);
+  check_err(s, errf);
+  int32_t* devi = need<int32_t>(c.dev_i, ndev);
+  int32_t* devn = need<int32_t>(c.dev_slot, 2 * (int64_t)ndev);
+  int32_t* devo = devn + ndev;
+  GLMB_LAUNCH(k_child_devs, cdiv(nk, T), T, 0, s, nk, M, sel.node, sel.nd_parent, sel.nd_item, chh, doff, itg, ito,
+              best16, devi, devn, devo);
+  // retained parents
+  int32_t* mark = need<int32_t>(c.row_mark, H + 1);
+  GLMB_LAUNCH(k_fill_i32, cdiv(H + 1, T), T, 0, s, mark, H + 1, 0);
+  GLMB_LAUNCH(k_mark, cdiv(nk, T), T, 0, s, nk, chh, mark);
+  int32_t* ppre = need<int32_t>(c.pre, H + 1);
+  scan_excl(mark, ppre, H, tot, c.tmp, s);
+  const int np = read1(s, tot);
+  int32_t* plist = need<int32_t>(c.cells, np + 1);
+  int32_t* hpm = need<int32_t>(c.hp_map, H + 1);
+  GLMB_LAUNCH(k_plist, cdiv(H, T), T, 0, s, H, mark, ppre, plist, hpm);
+  int32_t* first = need<int32_t>(c.first, 2 * (int64_t)U + 2);  // [first | default ids]
+  GLMB_LAUNCH(k_fill_i32, cdiv(U + 1, T), T, 0, s, first, U + 1, INT32_MAX);
+  GLMB_LAUNCH(k_first, cdiv((int64_t)np * SW, T), T, 0, s, np, plist, SW, c.rows.as<int32_t>(), first);
+  uint4* dmask = need<uint4>(c.dmask, U + 1);
+  const size_t lds = (size_t)NS * 4 * sizeof(uint32_t);
+  GLMB_LAUNCH(k_default_masks, np, 256, lds, s, plist, M, NS, SW, c.rows.as<int32_t>(), best16, loff, llen, lmeas,
+              first, dmask);
+  int ecap = std::max(1024, 4 * nk);
+  Rec* exc = (Rec*)need<uint8_t>(c.exc, 2 * (int64_t)ecap * sizeof(Rec));
+  int32_t* nexc = scal + 14;
+  GLMB_LAUNCH(k_exceptions, np, 256, lds, s, plist, M, NS, SW, c.rows.as<int32_t>(), best16, loff, llen, lmeas,
+              dmask, nexc, exc, ecap);
+  int ne = read1(s, nexc);
+  if (ne > ecap) {  // grow and redo
+    ecap = ne;
+    exc = (Rec*)need<uint8_t>(c.exc, 2 * (int64_t)ecap * sizeof(Rec));
+    GLMB_HIP(hipMemsetAsync(nexc, 0, sizeof(int32_t), s));
+    GLMB_LAUNCH(k_exceptions, np, 256, lds, s, plist, M, NS, SW, c.rows.as<int32_t>(), best16, loff, llen, lmeas,
+                dmask, nexc, exc, ecap);
+    ne = read1(s, nexc);
+  }
+  Rec* excs = exc + ecap;
+  {
+    uint64_t* ek = need<uint64_t>(c.keys, ne + 1);
+    uint32_t* ev = need<uint32_t>(c.vals32, ne + 1);
+    GLMB_LAUNCH(k_exc_keys, cdiv(ne, T), T, 0, s, ne, exc, ek, ev);
+    int pb = 0;
+    while ((1 << pb) < np) ++pb;
+    sort_pairs(ek, ev, ne, 0, 32 + ((pb + 7) / 8) * 8, c.tk, c.tv, c.tmp, s);
+    GLMB_LAUNCH(k_exc_perm, cdiv(ne, T), T, 0, s, ne, ev, exc, excs);
+  }
+  int32_t* eoff = need<int32_t>(c.ids, np + 2);
+  GLMB_LAUNCH(k_exc_off, cdiv(np + 1, T), T, 0, s, np, ne, excs, eoff);
+  // child masks
+  trace(c, "update.masks", np, ne);
+  int32_t* mcount = need<int32_t>(c.ccount, nk + 1);
+  int32_t* moff = need<int32_t>(c.coff2, nk + 1);
+  GLMB_LAUNCH(k_child_mods, cdiv(nk, T), T, 0, s, nk, chh, hpm, doff, devi, devn, devo, SW, c.rows.as<int32_t>(),
+              loff, llen, lmeas, dmask, excs, eoff, (const int32_t*)nullptr, mcount, (Rec*)nullptr);
+  scan_excl(mcount, moff, nk, moff + nk, c.tmp, s);
+  const int nm = read1(s, moff + nk);
+  // records: defaults | exceptions | child masks
+  int32_t* dfl = need<int32_t>(c.flags, U + 1);
+  int32_t* dpre = need<int32_t>(c.pmult, U + 1);
+  GLMB_LAUNCH(k_def_flags, cdiv(U, T), T, 0, s, U, first, dfl);
+  scan_excl(dfl, dpre, U, tot, c.tmp, s);
+  const int nd = read1(s, tot);
+  const int R = nd + ne + nm;
+  Rec* recs = (Rec*)need<uint8_t>(c.recs, (int64_t)(R + 1) * sizeof(Rec));
+  GLMB_LAUNCH(k_rec_defaults, cdiv(U, T), T, 0, s, U, first, dmask, dpre, recs);
+  GLMB_LAUNCH(k_rec_copy, cdiv(ne, T), T, 0, s, ne, excs, recs + nd);
+  GLMB_LAUNCH(k_child_mods, cdiv(nk, T), T, 0, s, nk, chh, hpm, doff, devi, devn, devo, SW, c.rows.as<int32_t>(),
+              loff, llen, lmeas, dmask, excs, eoff, (const int32_t*)moff, mcount, recs + nd + ne);
+  uint64_t* rk = need<uint64_t>(c.rec_keys, R + 1);
+  uint32_t* rv = need<uint32_t>(c.rec_vals, R + 1);
+  GLMB_LAUNCH(k_rec_keys, cdiv(R, T), T, 0, s, R, recs, rk, rv);
+  int ub = 0;
+  while ((1 << ub) < U) ++ub;
+  sort_pairs(rk, rv, R, 0, 32 + ((ub + 7) / 8) * 8, c.tk, c.tv, c.tmp, s);
+  int32_t* rfl = need<int32_t>(c.flags, R + 1);
+  int32_t* rpre = need<int32_t>(c.pre, R + 1);
+  GLMB_LAUNCH(k_rec_unique, cdiv(R, T), T, 0, s, R, rk, rv, recs, rfl, errf);
+  scan_excl(rfl, rpre, R, tot, c.tmp, s);
+  const int nnew = read1(s, tot);
+  check_err(s, errf);
+  int32_t* rec_id = need<int32_t>(c.ids, (int64_t)R + np + 2);
+  int32_t* rep = need<int32_t>(c.bt, nnew + 1);
+  // eoff lives in c.ids too: recompute it after rec_id is placed behind it
+  int32_t* eoff2 = rec_id + R;
+  GLMB_LAUNCH(k_exc_off, cdiv(np + 1, T), T, 0, s, np, ne, excs, eoff2);
+  GLMB_LAUNCH(k_rec_ids, cdiv(R, T), T, 0, s, R, rv, rfl, rpre, rec_id, rep);
+  DInst* ninst = (DInst*)need<uint8_t>(c.inst2, (int64_t)(nnew + 1) * sizeof(DInst));
+  trace(c, "update.kalman", R, nnew);
+  int32_t* onz = need<int32_t>(c.inst_nz, nnew + 1);
+  int32_t* oz = need<int32_t>(c.inst_z, 8 * (int64_t)(nnew + 1));
+  GLMB_LAUNCH(k_kalman, cdiv(nnew, T), T, 0, s, nnew, rep, recs, (const DInst*)c.inst.p, loff, lmeas, z, sig2, ninst,
+              onz, oz);
+  int32_t* did = first + U + 1;
+  GLMB_LAUNCH(k_did, cdiv(U, T), T, 0, s, U, first, dpre, rec_id, did);
+  int32_t* nrows = need<int32_t>(c.rows2, (int64_t)nk * SW);
+  GLMB_LAUNCH(k_child_rows, nk, 256, 0, s, nk, SW, chh, hpm, c.rows.as<int32_t>(), first, did, excs, eoff2,
+              rec_id + nd, moff, recs + nd + ne, rec_id + nd + ne, nrows);
+  int32_t* nntrk = need<int32_t>(c.ntrk2, nk + 1);
+  GLMB_LAUNCH(k_gather_i32, cdiv(nk, T), T, 0, s, nk, chh, c.ntrk.as<int32_t>(), nntrk);
+
+  // ---- births for the next scan
+  trace(c, "update.births");
+  float* ru = need<float>(c.diag_ru, M + 1);
+  if (M > 0) {
+    const int hchunk = 64;
+    const int nch = cdiv(H, hchunk);
+    float* part = need<float>(c.ru_part, (int64_t)nch * M);
+    hipLaunchKernelGGL(k_ru_part, dim3(cdiv(M, T), nch), dim3(T), 0, s, H, M, hchunk, lzprime, lz, lserel, cmax, lgk,
+                       part);
+    GLMB_HIP(hipGetLastError());
+    GLMB_LAUNCH(k_ru_final, cdiv(M, T), T, 0, s, M, nch, part, ru);
+  }
+  int32_t* member = need<int32_t>(c.ru, (int64_t)M + 1);
+  DBirth* nb = (DBirth*)need<uint8_t>(c.births, (int64_t)(M + 1) * sizeof(DBirth));
+  GLMB_LAUNCH(k_births, 1, 64, 0, s, M, z, ru, p.birth_ru_max, p.birth_cluster_d, sig2,
+              p.birth_sigma_v * p.birth_sigma_v, p.birth_r_max, p.birth_rate, member, nb, nb_out, errf);
+
+  // ---- statistics and swap in the new state
+  trace(c, "update.stats");
+  check_err(s, errf);
+  int32_t hs[16];
+  GLMB_HIP(hipMemcpyAsync(hs, scal, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipStreamSynchronize(s));
+  uint64_t ng, no;
+  std::memcpy(&ng, hs + 2, 8);
+  std::memcpy(&no, hs + 4, 8);
+  float ret;
+  std::memcpy(&ret, hs + 11, 4);
+  // keep the predicted rows / instance sources for exports of this update
+  {
+    int32_t* pr = need<int32_t>(c.prev_rows, (int64_t)H * SW);
+    GLMB_HIP(hipMemcpyAsync(pr, c.rows.p, (size_t)H * SW * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    int32_t* ps = need<int32_t>(c.prev_src, U + 1);
+    // source index of every predicted instance
+    std::vector<DInst> hi(U);
+    if (U) {
+      GLMB_HIP(hipMemcpyAsync(hi.data(), c.inst.p, (size_t)U * sizeof(DInst), hipMemcpyDeviceToHost, s));
+      GLMB_HIP(hipStreamSynchronize(s));
+    }
+    std::vector<int32_t> src(U);
+    for (int u = 0; u < U; ++u) src[u] = hi[u].src;
+    if (U) GLMB_HIP(hipMemcpyAsync(ps, src.data(), (size_t)U * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    GLMB_HIP(hipStreamSynchronize(s));
+  }
+  c.last_H = H;
+  c.last_M = M;
+  c.last_stride = SW;
+  std::swap(c.inst, c.inst2);
+  std::swap(c.rows, c.rows2);
+  std::swap(c.ntrk, c.ntrk2);
+  std::swap(c.logw, c.logw2);
+  {
+    int32_t* hp = need<int32_t>(c.hparent, nk + 1);
+    GLMB_HIP(hipMemcpyAsync(hp, chh, (size_t)nk * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  }
+  c.ninst = nnew;
+  c.nhyp = nk;
+  c.nbirth = hs[13];
+  c.birth_lab.clear();
+  for (int b = 0; b < c.nbirth; ++b) c.birth_lab.push_back({k + 1, b});
+  c.stats.n_hyp_out = nk;
+  c.stats.n_inst_out = nnew;
+  c.stats.gated_pairs = (int64_t)ng;
+  c.stats.option_terms = (int64_t)no;
+  c.stats.dense_triples = dense;
+  c.stats.search_nodes = sel.nodes;
+  c.stats.search_levels = sel.levels;
+  c.stats.n_births = c.nbirth;
+  c.stats.retained_mass = std::exp((double)ret);
+  GLMB_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace glmb

@@ -1,0 +1,227 @@
+"""Thin ctypes binding of ``libglmb.so`` (the C ABI declared in ``include/glmb.h``).
+
+Argument marshalling only: every step of the filter runs in the library's HIP kernels.
+PyTorch supplies device memory (the detections) and the stream.  There is no fallback:
+if the library is missing or no GPU is present, construction raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libglmb.so")
+
+GLMB_OK, GLMB_E_ARG, GLMB_E_CAPACITY, GLMB_E_NOMEM, GLMB_E_DEVICE, GLMB_E_STATE = 0, -1, -2, -3, -4, -5
+
+EXPORTS = ["glmb_status_string", "glmb_last_error", "glmb_create", "glmb_destroy", "glmb_import_state",
+           "glmb_state_sizes", "glmb_export_state", "glmb_predict", "glmb_update", "glmb_truncate",
+           "glmb_estimate", "glmb_stats", "glmb_update_diag", "glmb_update_theta"]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("dt", ctypes.c_float), ("q", ctypes.c_float), ("sigma_z", ctypes.c_float),
+                ("p_survive", ctypes.c_float), ("det_rate", ctypes.c_float), ("clutter_density", ctypes.c_float),
+                ("gate_d2", ctypes.c_float), ("birth_r_max", ctypes.c_float), ("birth_rate", ctypes.c_float),
+                ("birth_sigma_v", ctypes.c_float), ("birth_ru_max", ctypes.c_float),
+                ("birth_cluster_d", ctypes.c_float), ("h_max", ctypes.c_int32), ("tau", ctypes.c_float),
+                ("cap_nodes", ctypes.c_int32), ("cap_labels", ctypes.c_int32)]
+
+
+_I = ctypes.POINTER(ctypes.c_int32)
+_F = ctypes.POINTER(ctypes.c_float)
+
+
+class StateHost(ctypes.Structure):
+    _fields_ = [("n_inst", ctypes.c_int32), ("n_hyp", ctypes.c_int32), ("n_idx", ctypes.c_int32),
+                ("n_birth", ctypes.c_int32), ("inst_lab", _I), ("inst_m", _F), ("inst_P", _F), ("inst_src", _I),
+                ("inst_nz", _I), ("inst_z", _I), ("hyp_logw", _F), ("hyp_off", _I), ("hyp_idx", _I),
+                ("hyp_parent", _I), ("birth_lab", _I), ("birth_m", _F), ("birth_P", _F), ("birth_r", _F)]
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("n_hyp_in", ctypes.c_int32), ("n_hyp_out", ctypes.c_int32), ("n_meas", ctypes.c_int32),
+                ("n_inst_in", ctypes.c_int32), ("n_inst_out", ctypes.c_int32), ("n_labels", ctypes.c_int32),
+                ("gated_pairs", ctypes.c_int64), ("option_terms", ctypes.c_int64),
+                ("dense_triples", ctypes.c_int64), ("search_nodes", ctypes.c_int32),
+                ("search_levels", ctypes.c_int32), ("n_births", ctypes.c_int32),
+                ("retained_mass", ctypes.c_double), ("lost_mass", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libglmb.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libglmb.so is not built: run `python paper_2512_06230_amd/build.py`")
+    L = ctypes.CDLL(path)
+    vp = ctypes.c_void_p
+    L.glmb_status_string.restype = ctypes.c_char_p
+    L.glmb_status_string.argtypes = [ctypes.c_int]
+    L.glmb_last_error.restype = ctypes.c_char_p
+    L.glmb_last_error.argtypes = [vp]
+    L.glmb_create.argtypes = [ctypes.POINTER(Params), ctypes.c_int, vp, ctypes.POINTER(vp)]
+    L.glmb_destroy.argtypes = [vp]
+    L.glmb_import_state.argtypes = [vp, ctypes.POINTER(StateHost)]
+    L.glmb_state_sizes.argtypes = [vp, _I, _I, _I, _I]
+    L.glmb_export_state.argtypes = [vp, ctypes.POINTER(StateHost)]
+    L.glmb_predict.argtypes = [vp, ctypes.c_int32]
+    L.glmb_update.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32]
+    L.glmb_truncate.argtypes = [vp, ctypes.c_int32, ctypes.c_float]
+    L.glmb_estimate.argtypes = [vp, ctypes.c_int32, _I, _I, _F]
+    L.glmb_stats.argtypes = [vp, ctypes.POINTER(StepStats)]
+    L.glmb_update_diag.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _F, _F, _F]
+    L.glmb_update_theta.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _I]
+    for name in EXPORTS:
+        getattr(L, name).restype = ctypes.c_int if name not in ("glmb_status_string", "glmb_last_error") \
+            else ctypes.c_char_p
+    _lib = L
+    return L
+
+
+class GlmbError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s (%d): %s" % (msg, status, msg))
+        self.status = status
+
+
+def _params(p: dict) -> Params:
+    return Params(dt=p["dt"], q=p["q"], sigma_z=p["sigma_z"], p_survive=p["p_survive"], det_rate=p["det_rate"],
+                  clutter_density=p["clutter_density"], gate_d2=p["gate_d2"], birth_r_max=p["birth_r_max"],
+                  birth_rate=p["birth_rate"], birth_sigma_v=p["birth_sigma_v"], birth_ru_max=p["birth_ru_max"],
+                  birth_cluster_d=p["birth_cluster_d"], h_max=int(p["h_max"]), tau=float(p["tau"]),
+                  cap_nodes=int(p.get("cap_nodes", 0)), cap_labels=int(p.get("cap_labels", 0)))
+
+
+def _ip(a):
+    return a.ctypes.data_as(_I)
+
+
+def _fp(a):
+    return a.ctypes.data_as(_F)
+
+
+class Tracker:
+    """One filter context on a HIP device, driven on a torch stream."""
+
+    def __init__(self, params: dict, device: int = 0, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the GLMB library runs on the GPU only")
+        self._L = load_library()
+        self.torch = torch
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.params = dict(params)
+        ctx = ctypes.c_void_p()
+        st = self._L.glmb_create(ctypes.byref(_params(params)), device, ctypes.c_void_p(self.stream.cuda_stream),
+                                 ctypes.byref(ctx))
+        if st != GLMB_OK:
+            raise GlmbError(st, "glmb_create: " + self._L.glmb_status_string(st).decode())
+        self._ctx = ctx
+
+    def _check(self, st: int, what: str):
+        if st != GLMB_OK:
+            raise GlmbError(st, "%s: %s" % (what, self._L.glmb_last_error(self._ctx).decode()))
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._L.glmb_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- state
+    def import_state(self, s: dict):
+        lab = np.ascontiguousarray(np.asarray(s["inst_lab"], np.int32).reshape(-1, 2))
+        m = np.ascontiguousarray(np.asarray(s["inst_m"], np.float32).reshape(-1, 4))
+        P = np.ascontiguousarray(np.asarray(s["inst_P"], np.float32).reshape(-1, 16))
+        lw = np.ascontiguousarray(np.asarray(s["hyp_logw"], np.float32))
+        off = np.ascontiguousarray(np.asarray(s["hyp_off"], np.int32))
+        idx = np.ascontiguousarray(np.asarray(s["hyp_idx"], np.int32))
+        blab = np.ascontiguousarray(np.asarray(s["birth_lab"], np.int32).reshape(-1, 2))
+        bm = np.ascontiguousarray(np.asarray(s["birth_m"], np.float32).reshape(-1, 4))
+        bP = np.ascontiguousarray(np.asarray(s["birth_P"], np.float32).reshape(-1, 16))
+        br = np.ascontiguousarray(np.asarray(s["birth_r"], np.float32))
+        h = StateHost(n_inst=lab.shape[0], n_hyp=lw.shape[0], n_idx=idx.shape[0], n_birth=blab.shape[0],
+                      inst_lab=_ip(lab), inst_m=_fp(m), inst_P=_fp(P), hyp_logw=_fp(lw), hyp_off=_ip(off),
+                      hyp_idx=_ip(idx), birth_lab=_ip(blab), birth_m=_fp(bm), birth_P=_fp(bP), birth_r=_fp(br))
+        self._check(self._L.glmb_import_state(self._ctx, ctypes.byref(h)), "glmb_import_state")
+
+    def sizes(self):
+        a = [ctypes.c_int32() for _ in range(4)]
+        self._check(self._L.glmb_state_sizes(self._ctx, *[ctypes.byref(x) for x in a]), "glmb_state_sizes")
+        return dict(n_inst=a[0].value, n_hyp=a[1].value, n_idx=a[2].value, n_birth=a[3].value)
+
+    def export_state(self) -> dict:
+        z = self.sizes()
+        ni, nh, nx, nb = z["n_inst"], z["n_hyp"], z["n_idx"], z["n_birth"]
+        out = dict(inst_lab=np.zeros((ni, 2), np.int32), inst_m=np.zeros((ni, 4), np.float32),
+                   inst_P=np.zeros((ni, 16), np.float32), inst_src=np.zeros(ni, np.int32),
+                   inst_nz=np.zeros(ni, np.int32), inst_z=np.zeros((ni, 8), np.int32),
+                   hyp_logw=np.zeros(nh, np.float32), hyp_off=np.zeros(nh + 1, np.int32),
+                   hyp_idx=np.zeros(max(nx, 1), np.int32), hyp_parent=np.zeros(nh, np.int32),
+                   birth_lab=np.zeros((nb, 2), np.int32), birth_m=np.zeros((nb, 4), np.float32),
+                   birth_P=np.zeros((nb, 16), np.float32), birth_r=np.zeros(nb, np.float32))
+        h = StateHost(n_inst=ni, n_hyp=nh, n_idx=max(nx, 1), n_birth=nb, inst_lab=_ip(out["inst_lab"]),
+                      inst_m=_fp(out["inst_m"]), inst_P=_fp(out["inst_P"]), inst_src=_ip(out["inst_src"]),
+                      inst_nz=_ip(out["inst_nz"]), inst_z=_ip(out["inst_z"]), hyp_logw=_fp(out["hyp_logw"]),
+                      hyp_off=_ip(out["hyp_off"]), hyp_idx=_ip(out["hyp_idx"]), hyp_parent=_ip(out["hyp_parent"]),
+                      birth_lab=_ip(out["birth_lab"]), birth_m=_fp(out["birth_m"]), birth_P=_fp(out["birth_P"]),
+                      birth_r=_fp(out["birth_r"]))
+        self._check(self._L.glmb_export_state(self._ctx, ctypes.byref(h)), "glmb_export_state")
+        out["hyp_idx"] = out["hyp_idx"][:nx]
+        return out
+
+    # ---- the time step
+    def predict(self, k: int):
+        self._check(self._L.glmb_predict(self._ctx, int(k)), "glmb_predict")
+
+    def update(self, k: int, z):
+        """z: torch CUDA float32 tensor [M, 2] (contiguous) or a numpy array (copied to the device)."""
+        t = self.torch
+        if not isinstance(z, t.Tensor):
+            z = t.as_tensor(np.ascontiguousarray(np.asarray(z, np.float32).reshape(-1, 2)), device="cuda")
+        if not (z.is_cuda and z.dtype == t.float32 and z.is_contiguous() and z.dim() == 2 and z.shape[1] == 2):
+            raise ValueError("detections must be a contiguous CUDA float32 tensor of shape [M, 2]")
+        self._z_keep = z
+        self._check(self._L.glmb_update(self._ctx, int(k), ctypes.c_void_p(z.data_ptr()), int(z.shape[0])),
+                    "glmb_update")
+
+    def truncate(self, h_max: int, tau: float):
+        self._check(self._L.glmb_truncate(self._ctx, int(h_max), float(tau)), "glmb_truncate")
+
+    def estimate(self, cap: int = 65536):
+        n = ctypes.c_int32()
+        labs = np.zeros((cap, 2), np.int32)
+        means = np.zeros((cap, 4), np.float32)
+        self._check(self._L.glmb_estimate(self._ctx, int(cap), ctypes.byref(n), _ip(labs), _fp(means)),
+                    "glmb_estimate")
+        return labs[:n.value].copy(), means[:n.value].copy()
+
+    def stats(self) -> dict:
+        s = StepStats()
+        self._check(self._L.glmb_stats(self._ctx, ctypes.byref(s)), "glmb_stats")
+        return {f: getattr(s, f) for f, _ in StepStats._fields_}
+
+    def diag(self, H: int, M: int) -> dict:
+        best, logpi = np.zeros(H, np.float32), np.zeros(H, np.float32)
+        ru = np.zeros(max(M, 1), np.float32)
+        self._check(self._L.glmb_update_diag(self._ctx, int(H), int(M), _fp(best), _fp(logpi), _fp(ru)),
+                    "glmb_update_diag")
+        return dict(best=best, logpi=logpi, ru=ru[:M])
+
+    def theta(self, n_hyp: int, M: int) -> np.ndarray:
+        th = np.zeros((n_hyp, max(M, 1)), np.int32)
+        self._check(self._L.glmb_update_theta(self._ctx, int(n_hyp), int(M), _ip(th)), "glmb_update_theta")
+        return th[:, :M]
