@@ -1,0 +1,147 @@
+"""Benchmark of the multi-detection GLMB time step on one MI355X.
+
+A step is one pass of the whole hot path over one scan of synthetic detections:
+glmb_predict -> glmb_update -> glmb_truncate -> glmb_estimate, on the N=500-object,
+H_max=1e4 workload (100x100 m, clutter 100 per scan, warm start).  All scans are
+uploaded to HBM before the timed region.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GLMB updates/s and hyp·track·meas evals/s, N=500 H_max=1e4; learned vs plain"
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
+FP32_VECTOR_TFLOPS = 157.3  # MI355X FP32 vector (packed)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n-obj", type=int, default=500)
+    ap.add_argument("--h-max", type=int, default=10000)
+    ap.add_argument("--clutter", type=float, default=None)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the multi-detection GLMB path runs on a single device "
+              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2512_06230_amd import scenarios as sc
+    from paper_2512_06230_amd.glmb import Tracker
+
+    clutter = 0.2 * args.n_obj if args.clutter is None else args.clutter
+    spec = sc.spec_for("c3:%d" % args.n_obj, clutter_mean=clutter, seed=args.seed)
+    n_scans = args.warmup + args.steps
+    scene = sc.make_scene(spec, n_steps=n_scans)
+    params = sc.filter_params(spec, args.h_max, 0.0)
+    dev = torch.device("cuda:0")
+    # every scan resident in HBM before timing
+    zs = [torch.as_tensor(z, device=dev) for z in scene.meas]
+    torch.cuda.synchronize()
+
+    trk = Tracker(params)
+    trk.import_state(sc.warm_start_state(scene))
+
+    def step(k):
+        trk.predict(k)
+        trk.update(k, zs[k])
+        trk.truncate(args.h_max, 0.0)
+        return trk.estimate()
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for k in range(args.warmup, n_scans):
+        labs, _ = step(k)
+        stats.append(trk.stats())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = 1e3 * elapsed / args.steps
+    dense = sum(s["dense_triples"] for s in stats)
+    gated = sum(s["option_terms"] for s in stats)
+    stage = np.mean(np.array([s["stage_ms"] for s in stats]), axis=0)
+
+    # roofline of the dominant kernel: the per-(hypothesis, detection) association kernel.
+    # Algorithmic HBM bytes per launch: the hypothesis rows read (H x stride x 4 B) plus the three
+    # per-cell outputs written (best option 2 B, first deviation 4 B, relative log-sum-exp 4 B).
+    H = np.mean([s["n_hyp_in"] for s in stats])
+    M = np.mean([s["n_meas"] for s in stats])
+    L = np.mean([s["n_labels"] for s in stats])
+    bytes_assoc = H * L * 4.0 + H * M * 10.0
+    t_assoc = float(stage[1]) * 1e-3
+    achieved = bytes_assoc / t_assoc / 1e9 if t_assoc > 0 else 0.0
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "assoc_traffic_n500_h1e4.json")
+    if os.path.exists(tf):
+        try:
+            traffic = json.load(open(tf)).get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    out = {
+        "metric": METRIC,
+        "value": args.steps / elapsed,
+        "unit": "GLMB updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "N=%d objects, H_max=%d, clutter %.0f/scan, 100x100 m, warm start, plain update"
+                               % (args.n_obj, args.h_max, clutter),
+                   "n_obj": args.n_obj, "h_max": args.h_max, "clutter_mean": clutter,
+                   "mean_detections": float(M), "mean_hypotheses_in": float(H), "parallelism": "single GPU"},
+        "evals_per_s": dense / elapsed,
+        "gated_evals_per_s": gated / elapsed,
+        "stage_ms": {"gate": float(stage[0]), "assoc": float(stage[1]), "select": float(stage[2]),
+                     "materialise": float(stage[3]), "births": float(stage[4]), "update": float(stage[5])},
+        "roofline": {"kernel": "k_assoc", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes": bytes_assoc},
+    }
+
+    if not args.no_cpu_baseline:
+        from oracle.oracle import Oracle
+        st = trk.export_state()
+        o = Oracle(params)
+        o.import_state({k: (np.asarray(v, np.float64) if np.asarray(v).dtype == np.float32 else v)
+                        for k, v in st.items()})
+        k0 = n_scans - 1
+        tc = time.perf_counter()
+        for j in range(args.cpu_sample_steps):
+            kk = min(k0 + j, n_scans - 1)
+            o.predict(kk)
+            o.update(kk, scene.meas[kk])
+            o.truncate(args.h_max, 0.0)
+            o.estimate()
+        tcpu = time.perf_counter() - tc
+        out["cpu_baseline"] = {"value": args.cpu_sample_steps / tcpu, "unit": "GLMB updates/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "%d full step(s) (predict+update+truncate+estimate) of the same workload "
+                                         "from the GPU's state after the timed steps, FP64, single thread"
+                                         % args.cpu_sample_steps}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

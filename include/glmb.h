@@ -97,6 +97,11 @@ typedef struct {
   int32_t search_nodes, search_levels, n_births;
   double retained_mass;     /* posterior mass of the kept hypotheses                     */
   double lost_mass;         /* posterior mass removed by the learned proposal (0 if plain) */
+  /* stage durations of the last update from HIP events on the context's stream (ms):
+   * [0] gate + score, [1] association normalisers (the per-(hypothesis, detection) kernel
+   * alone), [2] cut bound + deviation items + selection, [3] materialise + Kalman,
+   * [4] births, [5] whole update */
+  float stage_ms[6];
 } glmb_step_stats;
 
 /* Library / status utilities */

@@ -220,6 +220,8 @@ glmb_status glmb_create(const glmb_params* p, int device, void* stream, glmb_ctx
   const char* tr = std::getenv("GLMB_TRACE");
   x->c.trace = tr && tr[0] && tr[0] != '0';
   glmb_status st = guarded(x, [&](Ctx& c) {
+    c.ev_ok = true;
+    for (auto& e : c.ev) GLMB_HIP(hipEventCreate(&e));
     // one hypothesis without tracks
     upload_state(c, {}, {}, {}, {0.0f}, {0}, {}, {});
   });
@@ -249,6 +251,8 @@ glmb_status glmb_destroy(glmb_ctx* x) {
                           &c.sb.tk, &c.sb.tv, &c.sb.keys, &c.sb.vals, &c.sb.sel_node, &c.sb.sel_val, &c.sb.sel_rank,
                           &c.sb.scal};
   for (auto* b : bufs) b->release();
+  if (c.ev_ok)
+    for (auto& e : c.ev) (void)hipEventDestroy(e);
   delete x;
   return GLMB_OK;
 }

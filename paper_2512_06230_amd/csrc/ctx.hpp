@@ -38,6 +38,11 @@ struct Ctx {
   std::string err;
   bool alive = true;
   bool trace = false;  // GLMB_TRACE=1: print every host-side stage to stderr (flushed)
+  hipEvent_t ev[8] = {};  // stage timing events on the context's stream
+  bool ev_ok = false;
+  void mark(int i) {
+    if (ev_ok) (void)hipEventRecord(ev[i], s);
+  }
 
   // ---- state (host mirrors of the sizes) ----
   std::vector<std::pair<int32_t, int32_t>> slot_lab;   // label of each slot (ascending)

@@ -274,17 +274,22 @@ __global__ __launch_bounds__(1024) void k_pnorm(int nh, const uint32_t* order, c
   for (int h = threadIdx.x; h < nh; h += blockDim.x) logw[h] = mval[order[h]] - L;
 }
 
+// track count and parent of every final hypothesis (also when rows have no slots)
+__global__ void k_final_meta(int nh, const uint32_t* order, const int32_t* nt_c, const int32_t* par_c,
+                             const int32_t* mrep, int32_t* ntrk, int32_t* hpar) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h >= nh) return;
+  const int c = (int)order[h];
+  ntrk[h] = nt_c[c];
+  hpar[h] = par_c[mrep[c]];
+}
+
 __global__ void k_final_rows(int nh, int W2, int NS2, const uint32_t* order, const int32_t* crow, const int32_t* spre,
-                             const int32_t* sused, const int32_t* upre, const int32_t* nt_c, const int32_t* par_c,
-                             const int32_t* mrep, int32_t* rows, int32_t* ntrk, int32_t* hpar) {
+                             const int32_t* sused, const int32_t* upre, int32_t* rows) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= (int64_t)nh * W2) return;
   const int h = (int)(t / W2), s = (int)(t % W2);
   const int c = (int)order[h];
-  if (s == 0) {
-    ntrk[h] = nt_c[c];
-    hpar[h] = par_c[mrep[c]];
-  }
   if (!sused[s]) return;
   const int u = crow[(size_t)c * W2 + s];
   rows[(size_t)h * NS2 + spre[s]] = u >= 0 ? upre[u] : -1;
@@ -437,8 +442,8 @@ void stage_predict(Ctx& c, int k) {
   int32_t* fnt = need<int32_t>(c.hp_map, nh + 1);
   int32_t* fpar = need<int32_t>(c.hparent, nh + 1);
   GLMB_LAUNCH(k_pfill, cdiv((int64_t)nh * NS2, T), T, 0, s, frows, nh * NS2, -1);
-  GLMB_LAUNCH(k_final_rows, cdiv((int64_t)nh * W2, T), T, 0, s, nh, W2, NS2, lv, crow, spre, sused, upre, ntc, parc,
-              mrep, frows, fnt, fpar);
+  GLMB_LAUNCH(k_final_rows, cdiv((int64_t)nh * W2, T), T, 0, s, nh, W2, NS2, lv, crow, spre, sused, upre, frows);
+  GLMB_LAUNCH(k_final_meta, cdiv(nh, T), T, 0, s, nh, lv, ntc, parc, mrep, fnt, fpar);
   DInst* ninst = (DInst*)need<uint8_t>(c.inst2, (int64_t)(Unew + 1) * sizeof(DInst));
   GLMB_LAUNCH(k_compact_inst, cdiv(U2, T), T, 0, s, U2, uused, upre, spre, c.inst.as<DInst>(), ninst);
   // rows / counts into the primary buffers

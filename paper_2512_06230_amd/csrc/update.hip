@@ -855,6 +855,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
 
   // ---- U1: gate and score
   trace(c, "update.U1");
+  c.mark(0);
   uint32_t* cmax = need<uint32_t>(c.cmax, M);
   {
     uint32_t init;
@@ -910,9 +911,11 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     GLMB_HIP(hipStreamSynchronize(s));
     for (int h = 0; h < H; ++h) dense += (int64_t)nt[h] * M;
   }
+  c.mark(1);
   GLMB_LAUNCH(k_assoc, H, 256, SW * sizeof(int32_t), s, M, SW, c.rows.as<int32_t>(), c.logw.as<float>(),
               c.ntrk.as<int32_t>(), nref, p.det_rate, lgk, coff, cand, phi, cmax, best16, dev1, lserel, bprime,
               lzprime, nopts);
+  c.mark(2);
   float* dbest = need<float>(c.diag_best, H);
   float* dlogpi = need<float>(c.diag_logpi, H);
   GLMB_LAUNCH(k_norm, 1, 1024, 0, s, H, bprime, lzprime, lz, dbest, dlogpi);
@@ -970,6 +973,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
 
   // ---- U4: children, distinct (instance, detection set), Kalman, rows
   trace(c, "update.U4", nsel, nk);
+  c.mark(3);
   int32_t* depth = need<int32_t>(c.ccount, nk + 1);
   int32_t* chh = need<int32_t>(c.child_par, nk + 1);
   int32_t* doff = need<int32_t>(c.dev_off, nk + 1);
@@ -1080,6 +1084,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
 
   // ---- births for the next scan
   trace(c, "update.births");
+  c.mark(4);
   float* ru = need<float>(c.diag_ru, M + 1);
   if (M > 0) {
     const int hchunk = 64;
@@ -1097,6 +1102,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
 
   // ---- statistics and swap in the new state
   trace(c, "update.stats");
+  c.mark(5);
   check_err(s, errf);
   int32_t hs[16];
   GLMB_HIP(hipMemcpyAsync(hs, scal, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1148,6 +1154,14 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   c.stats.n_births = c.nbirth;
   c.stats.retained_mass = std::exp((double)ret);
   GLMB_HIP(hipStreamSynchronize(s));
+  if (c.ev_ok) {
+    const int a[6] = {0, 1, 2, 3, 4, 0}, b[6] = {1, 2, 3, 4, 5, 5};
+    for (int j = 0; j < 6; ++j) {
+      float ms = 0.0f;
+      GLMB_HIP(hipEventElapsedTime(&ms, c.ev[a[j]], c.ev[b[j]]));
+      c.stats.stage_ms[j] = ms;
+    }
+  }
 }
 
 }  // namespace glmb

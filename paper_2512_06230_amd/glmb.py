@@ -47,7 +47,8 @@ class StepStats(ctypes.Structure):
                 ("gated_pairs", ctypes.c_int64), ("option_terms", ctypes.c_int64),
                 ("dense_triples", ctypes.c_int64), ("search_nodes", ctypes.c_int32),
                 ("search_levels", ctypes.c_int32), ("n_births", ctypes.c_int32),
-                ("retained_mass", ctypes.c_double), ("lost_mass", ctypes.c_double)]
+                ("retained_mass", ctypes.c_double), ("lost_mass", ctypes.c_double),
+                ("stage_ms", ctypes.c_float * 6)]
 
 
 _lib = None
@@ -212,7 +213,9 @@ class Tracker:
     def stats(self) -> dict:
         s = StepStats()
         self._check(self._L.glmb_stats(self._ctx, ctypes.byref(s)), "glmb_stats")
-        return {f: getattr(s, f) for f, _ in StepStats._fields_}
+        out = {f: getattr(s, f) for f, _ in StepStats._fields_}
+        out["stage_ms"] = list(s.stage_ms)
+        return out
 
     def diag(self, H: int, M: int) -> dict:
         best, logpi = np.zeros(H, np.float32), np.zeros(H, np.float32)
