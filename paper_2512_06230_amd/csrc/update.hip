@@ -19,7 +19,7 @@
 
 namespace glmb {
 
-enum : uint32_t { ERR_LMAX = 1, ERR_OPTS = 2, ERR_DEPTH = 4, ERR_NAN = 8, ERR_COLL = 16 };
+enum : uint32_t { ERR_BIRTH = 1, ERR_OPTS = 2, ERR_DEPTH = 4, ERR_NAN = 8, ERR_COLL = 16 };
 
 // ------------------------------------------------------------------ U0 / U1
 __global__ void k_z_in(const float* zin, int M, float2* z, uint32_t* errf) {
@@ -104,7 +104,6 @@ __global__ __launch_bounds__(256) void k_label_bits(const uint32_t* gbits, const
       run += pc[w];
     }
     llen[s] = run;
-    if (run > kLMax) atomicOr(errf, ERR_LMAX);
   }
 }
 
@@ -430,109 +429,112 @@ __device__ __forceinline__ int lpos(const int32_t* lmeas, int off, int len, int 
   return a;
 }
 
-// detection-set masks of every slot of hypothesis h under its best association map
-__device__ void build_masks(int h, int M, int nslot, const int16_t* best16, const int32_t* loff, const int32_t* llen,
-                            const int32_t* lmeas, uint32_t* mask) {
-  for (int k = threadIdx.x; k < nslot * 4; k += blockDim.x) mask[k] = 0u;
+// Detection-set masks of every slot of hypothesis h under its best association map.  A mask
+// has LW 32-bit words; bit j stands for the j-th detection gated with the slot's label.
+__device__ void build_masks(int h, int M, int nslot, int LW, const int16_t* best16, const int32_t* loff,
+                            const int32_t* llen, const int32_t* lmeas, uint32_t* mask) {
+  for (int k = threadIdx.x; k < nslot * LW; k += blockDim.x) mask[k] = 0u;
   __syncthreads();
   for (int i = threadIdx.x; i < M; i += blockDim.x) {
     const int s = (int)best16[(size_t)h * M + i] - 1;
     if (s < 0) continue;
     const int j = lpos(lmeas, loff[s], llen[s], i);
-    if (j < llen[s] && j < kLMax) atomicOr(&mask[s * 4 + (j >> 5)], 1u << (j & 31));
+    if (j < llen[s]) atomicOr(&mask[s * LW + (j >> 5)], 1u << (j & 31));
   }
   __syncthreads();
 }
 
-struct Rec {
-  uint32_t m[4];
-  int32_t u, a, b, pad;  // instance; (parent index, slot) or (child, slot)
-};
-
-__global__ __launch_bounds__(256) void k_default_masks(const int32_t* plist, int M, int nslot, int stride,
+__global__ __launch_bounds__(256) void k_default_masks(const int32_t* plist, int M, int nslot, int LW, int stride,
                                                        const int32_t* rows, const int16_t* best16,
                                                        const int32_t* loff, const int32_t* llen,
-                                                       const int32_t* lmeas, const int32_t* first, uint4* dmask) {
+                                                       const int32_t* lmeas, const int32_t* first, uint32_t* dmask) {
   extern __shared__ uint32_t mask[];
   const int h = plist[blockIdx.x];
-  build_masks(h, M, nslot, best16, loff, llen, lmeas, mask);
+  build_masks(h, M, nslot, LW, best16, loff, llen, lmeas, mask);
   for (int s = threadIdx.x; s < nslot; s += blockDim.x) {
     const int u = rows[(size_t)h * stride + s];
-    if (u >= 0 && first[u] == h) dmask[u] = make_uint4(mask[4 * s], mask[4 * s + 1], mask[4 * s + 2], mask[4 * s + 3]);
+    if (u >= 0 && first[u] == h)
+      for (int w = 0; w < LW; ++w) dmask[(size_t)u * LW + w] = mask[s * LW + w];
   }
 }
 
-__global__ __launch_bounds__(256) void k_exceptions(const int32_t* plist, int M, int nslot, int stride,
+// (instance, slot) pairs of retained parents whose detection set differs from the default
+__global__ __launch_bounds__(256) void k_exceptions(const int32_t* plist, int M, int nslot, int LW, int stride,
                                                     const int32_t* rows, const int16_t* best16, const int32_t* loff,
-                                                    const int32_t* llen, const int32_t* lmeas, const uint4* dmask,
-                                                    int32_t* nexc, Rec* exc, int cap) {
+                                                    const int32_t* llen, const int32_t* lmeas, const uint32_t* dmask,
+                                                    int32_t* nexc, int32_t* eu, int32_t* ea, int32_t* eb,
+                                                    uint32_t* em, int cap) {
   extern __shared__ uint32_t mask[];
   const int hp = blockIdx.x;
   const int h = plist[hp];
-  build_masks(h, M, nslot, best16, loff, llen, lmeas, mask);
+  build_masks(h, M, nslot, LW, best16, loff, llen, lmeas, mask);
   for (int s = threadIdx.x; s < nslot; s += blockDim.x) {
     const int u = rows[(size_t)h * stride + s];
     if (u < 0) continue;
-    const uint4 d = dmask[u];
-    if (d.x != mask[4 * s] || d.y != mask[4 * s + 1] || d.z != mask[4 * s + 2] || d.w != mask[4 * s + 3]) {
-      const int k = atomicAdd(nexc, 1);
-      if (k < cap) {
-        Rec r;
-        for (int j = 0; j < 4; ++j) r.m[j] = mask[4 * s + j];
-        r.u = u;
-        r.a = hp;
-        r.b = s;
-        r.pad = 0;
-        exc[k] = r;
-      }
-    }
+    bool diff = false;
+    for (int w = 0; w < LW && !diff; ++w) diff = dmask[(size_t)u * LW + w] != mask[s * LW + w];
+    if (!diff) continue;
+    const int k = atomicAdd(nexc, 1);
+    if (k >= cap) continue;
+    eu[k] = u;
+    ea[k] = hp;
+    eb[k] = s;
+    for (int w = 0; w < LW; ++w) em[(size_t)k * LW + w] = mask[s * LW + w];
   }
 }
 
-__global__ void k_exc_keys(int n, const Rec* exc, uint64_t* keys, uint32_t* vals) {
+__global__ void k_exc_keys(int n, const int32_t* ea, const int32_t* eb, uint64_t* keys, uint32_t* vals) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  keys[k] = ((uint64_t)(uint32_t)exc[k].a << 32) | (uint32_t)exc[k].b;
+  keys[k] = ((uint64_t)(uint32_t)ea[k] << 32) | (uint32_t)eb[k];
   vals[k] = (uint32_t)k;
 }
-__global__ void k_exc_perm(int n, const uint32_t* vals, const Rec* in, Rec* out) {
+__global__ void k_exc_perm(int n, int LW, const uint32_t* vals, const int32_t* u0, const int32_t* a0,
+                           const int32_t* b0, const uint32_t* m0, int32_t* u1, int32_t* a1, int32_t* b1,
+                           uint32_t* m1) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) out[k] = in[vals[k]];
+  if (k >= n) return;
+  const uint32_t q = vals[k];
+  u1[k] = u0[q];
+  a1[k] = a0[q];
+  b1[k] = b0[q];
+  for (int w = 0; w < LW; ++w) m1[(size_t)k * LW + w] = m0[(size_t)q * LW + w];
 }
-__global__ void k_exc_off(int np, int n, const Rec* exc, int32_t* eoff) {
+__global__ void k_exc_off(int np, int n, const int32_t* ea, int32_t* eoff) {
   const int hp = blockIdx.x * blockDim.x + threadIdx.x;
   if (hp > np) return;
   int a = 0, b = n;
   while (a < b) {
     const int m = (a + b) >> 1;
-    if (exc[m].a < hp) a = m + 1;
+    if (ea[m] < hp) a = m + 1;
     else b = m;
   }
   eoff[hp] = a;
 }
 
-__device__ __forceinline__ int find_exc(const Rec* exc, const int32_t* eoff, int hp, int s) {
+__device__ __forceinline__ int find_exc(const int32_t* eb, const int32_t* eoff, int hp, int s) {
   int a = eoff[hp], b = eoff[hp + 1];
+  const int e1 = b;
   while (a < b) {
     const int m = (a + b) >> 1;
-    if (exc[m].b < s) a = m + 1;
+    if (eb[m] < s) a = m + 1;
     else b = m;
   }
-  return (a < eoff[hp + 1] && exc[a].b == s) ? a : -1;
+  return (a < e1 && eb[a] == s) ? a : -1;
 }
 
-// per child: detection-set masks of the slots its deviations touch
-__global__ void k_child_mods(int n, const int32_t* ch_h, const int32_t* hp_map, const int32_t* doff,
+// per child: detection-set masks of the slots its deviations touch (count pass: mu == null)
+__global__ void k_child_mods(int n, int LW, const int32_t* ch_h, const int32_t* hp_map, const int32_t* doff,
                              const int32_t* dev_i, const int32_t* dev_new, const int32_t* dev_old, int stride,
                              const int32_t* rows, const int32_t* loff, const int32_t* llen, const int32_t* lmeas,
-                             const uint4* dmask, const Rec* exc, const int32_t* eoff, const int32_t* moff,
-                             int32_t* mcount, Rec* mods) {
+                             const uint32_t* dmask, const int32_t* eb, const uint32_t* em, const int32_t* eoff,
+                             const int32_t* moff, int32_t* mcount, int32_t* mu, int32_t* ma, int32_t* mb,
+                             uint32_t* mm) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   const int h = ch_h[c], hp = hp_map[h];
   const int d0 = doff[c], d1 = doff[c + 1];
   int cnt = 0;
-  // affected slots, each handled once (at its first appearance)
   for (int q = d0; q < d1; ++q) {
     for (int side = 0; side < 2; ++side) {
       const int s = side ? dev_new[q] : dev_old[q];
@@ -540,73 +542,71 @@ __global__ void k_child_mods(int n, const int32_t* ch_h, const int32_t* hp_map, 
       bool seen = side == 1 && dev_old[q] == s;
       for (int r = d0; r < q && !seen; ++r) seen = dev_old[r] == s || dev_new[r] == s;
       if (seen) continue;
-      if (moff) {
+      if (mu) {
+        const int o = moff[c] + cnt;
         const int u = rows[(size_t)h * stride + s];
-        Rec r;
-        const int e = find_exc(exc, eoff, hp, s);
-        uint4 m0 = e >= 0 ? make_uint4(exc[e].m[0], exc[e].m[1], exc[e].m[2], exc[e].m[3]) : dmask[u];
-        r.m[0] = m0.x;
-        r.m[1] = m0.y;
-        r.m[2] = m0.z;
-        r.m[3] = m0.w;
+        const int e = find_exc(eb, eoff, hp, s);
+        const uint32_t* base = e >= 0 ? em + (size_t)e * LW : dmask + (size_t)u * LW;
+        uint32_t* out = mm + (size_t)o * LW;
+        for (int w = 0; w < LW; ++w) out[w] = base[w];
         for (int t = d0; t < d1; ++t) {
           if (dev_old[t] != s && dev_new[t] != s) continue;
           const int j = lpos(lmeas, loff[s], llen[s], dev_i[t]);
-          if (j >= llen[s] || j >= kLMax) continue;
-          if (dev_old[t] == s) r.m[j >> 5] &= ~(1u << (j & 31));
-          if (dev_new[t] == s) r.m[j >> 5] |= 1u << (j & 31);
+          if (j >= llen[s]) continue;
+          if (dev_old[t] == s) out[j >> 5] &= ~(1u << (j & 31));
+          if (dev_new[t] == s) out[j >> 5] |= 1u << (j & 31);
         }
-        r.u = u;
-        r.a = c;
-        r.b = s;
-        r.pad = 0;
-        mods[moff[c] + cnt] = r;
+        mu[o] = u;
+        ma[o] = c;
+        mb[o] = s;
       }
       ++cnt;
     }
   }
-  if (!moff) mcount[c] = cnt;
+  if (!mu) mcount[c] = cnt;
 }
 
-__device__ __forceinline__ uint32_t mask_hash(const uint32_t* m) {
-  uint64_t x = ((uint64_t)m[1] << 32) | m[0];
-  uint64_t y = ((uint64_t)m[3] << 32) | m[2];
-  return (uint32_t)(mix64(x ^ mix64(y)) >> 32);
+__device__ __forceinline__ uint32_t mask_hash(const uint32_t* m, int LW) {
+  uint64_t x = 0x51ed270b27ull;
+  for (int w = 0; w < LW; ++w) x = mix64(x ^ ((uint64_t)m[w] << 17) ^ (uint64_t)w);
+  return (uint32_t)(x >> 32);
 }
 
-// all (instance, mask) records: defaults (one per referenced instance), exceptions, child masks
-__global__ void k_rec_defaults(int U, const int32_t* first, const uint4* dmask, const int32_t* dpre, Rec* recs) {
+// records (instance, mask): defaults (one per referenced instance), exceptions, child masks
+__global__ void k_rec_defaults(int U, int LW, const int32_t* first, const uint32_t* dmask, const int32_t* dpre,
+                               int32_t* ru, uint32_t* rm) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= U || first[u] == INT32_MAX) return;
-  Rec r;
-  const uint4 d = dmask[u];
-  r.m[0] = d.x;
-  r.m[1] = d.y;
-  r.m[2] = d.z;
-  r.m[3] = d.w;
-  r.u = u;
-  r.a = r.b = r.pad = 0;
-  recs[dpre[u]] = r;
+  const int o = dpre[u];
+  ru[o] = u;
+  for (int w = 0; w < LW; ++w) rm[(size_t)o * LW + w] = dmask[(size_t)u * LW + w];
 }
-__global__ void k_rec_copy(int n, const Rec* in, Rec* out) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < n) out[k] = in[k];
-}
-__global__ void k_rec_keys(int n, const Rec* recs, uint64_t* keys, uint32_t* vals) {
+__global__ void k_rec_copy(int n, int LW, const int32_t* u0, const uint32_t* m0, int32_t* u1, uint32_t* m1) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  keys[k] = ((uint64_t)(uint32_t)recs[k].u << 32) | mask_hash(recs[k].m);
+  u1[k] = u0[k];
+  for (int w = 0; w < LW; ++w) m1[(size_t)k * LW + w] = m0[(size_t)k * LW + w];
+}
+__global__ void k_rec_keys(int n, int LW, const int32_t* ru, const uint32_t* rm, uint64_t* keys, uint32_t* vals) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  keys[k] = ((uint64_t)(uint32_t)ru[k] << 32) | mask_hash(rm + (size_t)k * LW, LW);
   vals[k] = (uint32_t)k;
 }
-__device__ __forceinline__ bool rec_eq(const Rec& a, const Rec& b) {
-  return a.u == b.u && a.m[0] == b.m[0] && a.m[1] == b.m[1] && a.m[2] == b.m[2] && a.m[3] == b.m[3];
-}
-__global__ void k_rec_unique(int n, const uint64_t* keys, const uint32_t* vals, const Rec* recs, int32_t* flag,
-                             uint32_t* errf) {
+__global__ void k_rec_unique(int n, int LW, const uint64_t* keys, const uint32_t* vals, const int32_t* ru,
+                             const uint32_t* rm, int32_t* flag, uint32_t* errf) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  bool nw = p == 0 || keys[p] != keys[p - 1] || !rec_eq(recs[vals[p]], recs[vals[p - 1]]);
-  if (p > 0 && keys[p] == keys[p - 1] && nw) atomicOr(errf, ERR_COLL);  // hash collision: not exact
+  bool nw = p == 0 || keys[p] != keys[p - 1];
+  if (!nw) {
+    const uint32_t a = vals[p], b = vals[p - 1];
+    bool eq = ru[a] == ru[b];
+    for (int w = 0; w < LW && eq; ++w) eq = rm[(size_t)a * LW + w] == rm[(size_t)b * LW + w];
+    if (!eq) {
+      nw = true;
+      atomicOr(errf, ERR_COLL);  // equal fingerprints, different sets: refuse rather than guess
+    }
+  }
   flag[p] = nw ? 1 : 0;
 }
 __global__ void k_rec_ids(int n, const uint32_t* vals, const int32_t* flag, const int32_t* pre, int32_t* rec_id,
@@ -618,19 +618,22 @@ __global__ void k_rec_ids(int n, const uint32_t* vals, const int32_t* flag, cons
   if (flag[p]) rep[id] = (int32_t)vals[p];
 }
 
-// Kalman update of every distinct (instance, detection set)
-__global__ void k_kalman(int nnew, const int32_t* rep, const Rec* recs, const DInst* pin, const int32_t* loff,
-                         const int32_t* lmeas, const float2* z, float sig2, DInst* out, int32_t* onz, int32_t* oz) {
+// Kalman update of every distinct (instance, detection set): the detections of one object are
+// equivalent to their mean observed with noise R / n
+__global__ void k_kalman(int nnew, int LW, const int32_t* rep, const int32_t* ru, const uint32_t* rm,
+                         const DInst* pin, const int32_t* loff, const int32_t* lmeas, const float2* z, float sig2,
+                         DInst* out, int32_t* onz, int32_t* oz) {
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= nnew) return;
-  const Rec& r = recs[rep[id]];
-  const DInst x = pin[r.u];
+  const int r = rep[id];
+  const DInst x = pin[ru[r]];
   DInst y = x;
   int nz = 0;
   float sx = 0.0f, sy = 0.0f;
   const int off = loff[x.slot];
-  for (int w = 0; w < 4; ++w) {
-    uint32_t b = r.m[w];
+  const uint32_t* m = rm + (size_t)r * LW;
+  for (int w = 0; w < LW; ++w) {
+    uint32_t b = m[w];
     while (b) {
       const int j = w * 32 + __ffs(b) - 1;
       b &= b - 1;
@@ -671,10 +674,9 @@ __global__ void k_kalman(int nnew, const int32_t* rep, const Rec* recs, const DI
 
 // child rows: parent row with every instance replaced by its updated instance
 __global__ __launch_bounds__(256) void k_child_rows(int n, int stride, const int32_t* ch_h, const int32_t* hp_map,
-                                                    const int32_t* rows, const int32_t* first, const int32_t* did,
-                                                    const Rec* exc, const int32_t* eoff, const int32_t* exc_id,
-                                                    const int32_t* moff, const Rec* mods, const int32_t* mod_id,
-                                                    int32_t* out) {
+                                                    const int32_t* rows, const int32_t* did, const int32_t* eb,
+                                                    const int32_t* eoff, const int32_t* exc_id, const int32_t* moff,
+                                                    const int32_t* mod_b, const int32_t* mod_id, int32_t* out) {
   const int c = blockIdx.x;
   const int h = ch_h[c], hp = hp_map[h];
   const int m0 = moff[c], m1 = moff[c + 1];
@@ -683,10 +685,10 @@ __global__ __launch_bounds__(256) void k_child_rows(int n, int stride, const int
     int id = -1;
     if (u >= 0) {
       id = did[u];
-      const int e = find_exc(exc, eoff, hp, s);
+      const int e = find_exc(eb, eoff, hp, s);
       if (e >= 0) id = exc_id[e];
       for (int q = m0; q < m1; ++q)
-        if (mods[q].b == s) id = mod_id[q];
+        if (mod_b[q] == s) id = mod_id[q];
     }
     out[(size_t)c * stride + s] = id;
   }
@@ -759,7 +761,7 @@ __global__ __launch_bounds__(64) void k_births(int M, const float2* z, const flo
       }
       if (found < 0) {
         if (ncl >= kMaxClusters) {
-          if (lane == 0) atomicOr(errf, ERR_LMAX);
+          if (lane == 0) atomicOr(errf, ERR_BIRTH);
           found = kMaxClusters - 1;
         } else {
           if (lane == 0) az[ncl] = zi;
@@ -810,7 +812,7 @@ template <class T> T read1(hipStream_t s, const T* p) {
 void check_err(hipStream_t s, const uint32_t* errf) {
   const uint32_t e = read1(s, errf);
   if (e & ERR_NAN) throw Error{GLMB_E_ARG, "detections contain NaN or infinity"};
-  if (e & ERR_LMAX) throw Error{GLMB_E_CAPACITY, "more than 128 detections gated with one label"};
+  if (e & ERR_BIRTH) throw Error{GLMB_E_CAPACITY, "more than 4096 birth clusters in one scan"};
   if (e & ERR_OPTS) throw Error{GLMB_E_CAPACITY, "more than 64 options in one (hypothesis, detection) cell"};
   if (e & ERR_DEPTH) throw Error{GLMB_E_CAPACITY, "a kept child deviates in more than 48 detections"};
   if (e & ERR_COLL) throw Error{GLMB_E_STATE, "detection-set fingerprint collision"};
@@ -882,6 +884,24 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   else GLMB_LAUNCH(k_fill_i32, cdiv(NS + 1, T), T, 0, s, llen, NS + 1, 0);
   scan_excl(llen, loff, NS, tot, c.tmp, s);
   const int nl = read1(s, tot);
+  int LW = 1;
+  {
+    std::vector<int32_t> hl(NS + 1);
+    if (NS) GLMB_HIP(hipMemcpyAsync(hl.data(), llen, NS * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GLMB_HIP(hipStreamSynchronize(s));
+    int mx = 0;
+    for (int j = 0; j < NS; ++j) mx = std::max(mx, hl[j]);
+    LW = std::max(1, (mx + 31) / 32);
+    const size_t lds_need = (size_t)NS * LW * sizeof(uint32_t);
+    if (lds_need > 160 * 1024)
+      throw Error{GLMB_E_CAPACITY, "labels x detection-set mask width exceed the 160 KB LDS of a workgroup"};
+    if (lds_need > 64 * 1024) {
+      GLMB_HIP(hipFuncSetAttribute((const void*)k_default_masks, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds_need));
+      GLMB_HIP(hipFuncSetAttribute((const void*)k_exceptions, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)lds_need));
+    }
+  }
   int32_t* lmeas = need<int32_t>(c.lmeas, nl);
   if (M > 0) GLMB_LAUNCH(k_label_list, cdiv((int64_t)NS * W, T), T, 0, s, lbits, lpre, loff, NS, W, lmeas);
   int32_t* ccnt = need<int32_t>(c.ccnt, M + 1);
@@ -1000,44 +1020,52 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   int32_t* first = need<int32_t>(c.first, 2 * (int64_t)U + 2);  // [first | default ids]
   GLMB_LAUNCH(k_fill_i32, cdiv(U + 1, T), T, 0, s, first, U + 1, INT32_MAX);
   GLMB_LAUNCH(k_first, cdiv((int64_t)np * SW, T), T, 0, s, np, plist, SW, c.rows.as<int32_t>(), first);
-  uint4* dmask = need<uint4>(c.dmask, U + 1);
-  const size_t lds = (size_t)NS * 4 * sizeof(uint32_t);
-  GLMB_LAUNCH(k_default_masks, np, 256, lds, s, plist, M, NS, SW, c.rows.as<int32_t>(), best16, loff, llen, lmeas,
+  uint32_t* dmask = need<uint32_t>(c.dmask, (int64_t)(U + 1) * LW);
+  const size_t lds = (size_t)NS * LW * sizeof(uint32_t);
+  GLMB_LAUNCH(k_default_masks, np, 256, lds, s, plist, M, NS, LW, SW, c.rows.as<int32_t>(), best16, loff, llen, lmeas,
               first, dmask);
   int ecap = std::max(1024, 4 * nk);
-  Rec* exc = (Rec*)need<uint8_t>(c.exc, 2 * (int64_t)ecap * sizeof(Rec));
   int32_t* nexc = scal + 14;
-  GLMB_LAUNCH(k_exceptions, np, 256, lds, s, plist, M, NS, SW, c.rows.as<int32_t>(), best16, loff, llen, lmeas,
-              dmask, nexc, exc, ecap);
+  auto exc_bufs = [&](int cap_) {
+    int32_t* b = need<int32_t>(c.exc, 6 * (int64_t)cap_ + 6);
+    uint32_t* m = need<uint32_t>(c.cmod, 2 * (int64_t)cap_ * LW + 2);
+    return std::make_pair(b, m);
+  };
+  auto eb_ = exc_bufs(ecap);
+  GLMB_LAUNCH(k_exceptions, np, 256, lds, s, plist, M, NS, LW, SW, c.rows.as<int32_t>(), best16, loff, llen, lmeas,
+              dmask, nexc, eb_.first, eb_.first + ecap, eb_.first + 2 * ecap, eb_.second, ecap);
   int ne = read1(s, nexc);
   if (ne > ecap) {  // grow and redo
     ecap = ne;
-    exc = (Rec*)need<uint8_t>(c.exc, 2 * (int64_t)ecap * sizeof(Rec));
-    GLMB_HIP(hipMemsetAsync(nexc, 0, sizeof(int32_t), s));
-    GLMB_LAUNCH(k_exceptions, np, 256, lds, s, plist, M, NS, SW, c.rows.as<int32_t>(), best16, loff, llen, lmeas,
-                dmask, nexc, exc, ecap);
+    eb_ = exc_bufs(ecap);
+    GLMB_LAUNCH(k_fill_i32, 1, T, 0, s, nexc, 1, 0);
+    GLMB_LAUNCH(k_exceptions, np, 256, lds, s, plist, M, NS, LW, SW, c.rows.as<int32_t>(), best16, loff, llen,
+                lmeas, dmask, nexc, eb_.first, eb_.first + ecap, eb_.first + 2 * ecap, eb_.second, ecap);
     ne = read1(s, nexc);
   }
-  Rec* excs = exc + ecap;
+  // exceptions sorted by (retained parent, slot)
+  int32_t *eu0 = eb_.first, *ea0 = eu0 + ecap, *eb0 = ea0 + ecap, *eu = eb0 + ecap, *ea = eu + ecap, *eb = ea + ecap;
+  uint32_t *em0 = eb_.second, *em = em0 + (size_t)ecap * LW;
   {
     uint64_t* ek = need<uint64_t>(c.keys, ne + 1);
     uint32_t* ev = need<uint32_t>(c.vals32, ne + 1);
-    GLMB_LAUNCH(k_exc_keys, cdiv(ne, T), T, 0, s, ne, exc, ek, ev);
+    GLMB_LAUNCH(k_exc_keys, cdiv(ne, T), T, 0, s, ne, ea0, eb0, ek, ev);
     int pb = 0;
     while ((1 << pb) < np) ++pb;
     sort_pairs(ek, ev, ne, 0, 32 + ((pb + 7) / 8) * 8, c.tk, c.tv, c.tmp, s);
-    GLMB_LAUNCH(k_exc_perm, cdiv(ne, T), T, 0, s, ne, ev, exc, excs);
+    GLMB_LAUNCH(k_exc_perm, cdiv(ne, T), T, 0, s, ne, LW, ev, eu0, ea0, eb0, em0, eu, ea, eb, em);
   }
   int32_t* eoff = need<int32_t>(c.ids, np + 2);
-  GLMB_LAUNCH(k_exc_off, cdiv(np + 1, T), T, 0, s, np, ne, excs, eoff);
-  // child masks
-  trace(c, "update.masks", np, ne);
+  GLMB_LAUNCH(k_exc_off, cdiv(np + 1, T), T, 0, s, np, ne, ea, eoff);
+  // child masks: count
   int32_t* mcount = need<int32_t>(c.ccount, nk + 1);
   int32_t* moff = need<int32_t>(c.coff2, nk + 1);
-  GLMB_LAUNCH(k_child_mods, cdiv(nk, T), T, 0, s, nk, chh, hpm, doff, devi, devn, devo, SW, c.rows.as<int32_t>(),
-              loff, llen, lmeas, dmask, excs, eoff, (const int32_t*)nullptr, mcount, (Rec*)nullptr);
+  GLMB_LAUNCH(k_child_mods, cdiv(nk, T), T, 0, s, nk, LW, chh, hpm, doff, devi, devn, devo, SW, c.rows.as<int32_t>(),
+              loff, llen, lmeas, dmask, eb, em, eoff, (const int32_t*)nullptr, mcount, (int32_t*)nullptr,
+              (int32_t*)nullptr, (int32_t*)nullptr, (uint32_t*)nullptr);
   scan_excl(mcount, moff, nk, moff + nk, c.tmp, s);
   const int nm = read1(s, moff + nk);
+  trace(c, "update.masks", np, ne);
   // records: defaults | exceptions | child masks
   int32_t* dfl = need<int32_t>(c.flags, U + 1);
   int32_t* dpre = need<int32_t>(c.pmult, U + 1);
@@ -1045,40 +1073,44 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   scan_excl(dfl, dpre, U, tot, c.tmp, s);
   const int nd = read1(s, tot);
   const int R = nd + ne + nm;
-  Rec* recs = (Rec*)need<uint8_t>(c.recs, (int64_t)(R + 1) * sizeof(Rec));
-  GLMB_LAUNCH(k_rec_defaults, cdiv(U, T), T, 0, s, U, first, dmask, dpre, recs);
-  GLMB_LAUNCH(k_rec_copy, cdiv(ne, T), T, 0, s, ne, excs, recs + nd);
-  GLMB_LAUNCH(k_child_mods, cdiv(nk, T), T, 0, s, nk, chh, hpm, doff, devi, devn, devo, SW, c.rows.as<int32_t>(),
-              loff, llen, lmeas, dmask, excs, eoff, (const int32_t*)moff, mcount, recs + nd + ne);
+  int32_t* rec_u = need<int32_t>(c.recs, 3 * (int64_t)R + 3);
+  int32_t* rec_a = rec_u + R + 1;
+  int32_t* rec_b = rec_a + R + 1;
+  uint32_t* rec_m = need<uint32_t>(c.rec_m, (int64_t)(R + 1) * LW);
+  GLMB_LAUNCH(k_rec_defaults, cdiv(U, T), T, 0, s, U, LW, first, dmask, dpre, rec_u, rec_m);
+  GLMB_LAUNCH(k_rec_copy, cdiv(ne, T), T, 0, s, ne, LW, eu, em, rec_u + nd, rec_m + (size_t)nd * LW);
+  GLMB_LAUNCH(k_child_mods, cdiv(nk, T), T, 0, s, nk, LW, chh, hpm, doff, devi, devn, devo, SW, c.rows.as<int32_t>(),
+              loff, llen, lmeas, dmask, eb, em, eoff, (const int32_t*)moff, mcount, rec_u + nd + ne,
+              rec_a + nd + ne, rec_b + nd + ne, rec_m + (size_t)(nd + ne) * LW);
   uint64_t* rk = need<uint64_t>(c.rec_keys, R + 1);
   uint32_t* rv = need<uint32_t>(c.rec_vals, R + 1);
-  GLMB_LAUNCH(k_rec_keys, cdiv(R, T), T, 0, s, R, recs, rk, rv);
+  GLMB_LAUNCH(k_rec_keys, cdiv(R, T), T, 0, s, R, LW, rec_u, rec_m, rk, rv);
   int ub = 0;
   while ((1 << ub) < U) ++ub;
   sort_pairs(rk, rv, R, 0, 32 + ((ub + 7) / 8) * 8, c.tk, c.tv, c.tmp, s);
   int32_t* rfl = need<int32_t>(c.flags, R + 1);
   int32_t* rpre = need<int32_t>(c.pre, R + 1);
-  GLMB_LAUNCH(k_rec_unique, cdiv(R, T), T, 0, s, R, rk, rv, recs, rfl, errf);
+  GLMB_LAUNCH(k_rec_unique, cdiv(R, T), T, 0, s, R, LW, rk, rv, rec_u, rec_m, rfl, errf);
   scan_excl(rfl, rpre, R, tot, c.tmp, s);
   const int nnew = read1(s, tot);
   check_err(s, errf);
   int32_t* rec_id = need<int32_t>(c.ids, (int64_t)R + np + 2);
   int32_t* rep = need<int32_t>(c.bt, nnew + 1);
-  // eoff lives in c.ids too: recompute it after rec_id is placed behind it
+  // eoff shares c.ids with rec_id: place it behind the record ids again
   int32_t* eoff2 = rec_id + R;
-  GLMB_LAUNCH(k_exc_off, cdiv(np + 1, T), T, 0, s, np, ne, excs, eoff2);
+  GLMB_LAUNCH(k_exc_off, cdiv(np + 1, T), T, 0, s, np, ne, ea, eoff2);
   GLMB_LAUNCH(k_rec_ids, cdiv(R, T), T, 0, s, R, rv, rfl, rpre, rec_id, rep);
-  DInst* ninst = (DInst*)need<uint8_t>(c.inst2, (int64_t)(nnew + 1) * sizeof(DInst));
   trace(c, "update.kalman", R, nnew);
+  DInst* ninst = (DInst*)need<uint8_t>(c.inst2, (int64_t)(nnew + 1) * sizeof(DInst));
   int32_t* onz = need<int32_t>(c.inst_nz, nnew + 1);
   int32_t* oz = need<int32_t>(c.inst_z, 8 * (int64_t)(nnew + 1));
-  GLMB_LAUNCH(k_kalman, cdiv(nnew, T), T, 0, s, nnew, rep, recs, (const DInst*)c.inst.p, loff, lmeas, z, sig2, ninst,
-              onz, oz);
+  GLMB_LAUNCH(k_kalman, cdiv(nnew, T), T, 0, s, nnew, LW, rep, rec_u, rec_m, (const DInst*)c.inst.p, loff, lmeas, z,
+              sig2, ninst, onz, oz);
   int32_t* did = first + U + 1;
   GLMB_LAUNCH(k_did, cdiv(U, T), T, 0, s, U, first, dpre, rec_id, did);
   int32_t* nrows = need<int32_t>(c.rows2, (int64_t)nk * SW);
-  GLMB_LAUNCH(k_child_rows, nk, 256, 0, s, nk, SW, chh, hpm, c.rows.as<int32_t>(), first, did, excs, eoff2,
-              rec_id + nd, moff, recs + nd + ne, rec_id + nd + ne, nrows);
+  GLMB_LAUNCH(k_child_rows, nk, 256, 0, s, nk, SW, chh, hpm, c.rows.as<int32_t>(), did, eb, eoff2, rec_id + nd, moff,
+              rec_b + nd + ne, rec_id + nd + ne, nrows);
   int32_t* nntrk = need<int32_t>(c.ntrk2, nk + 1);
   GLMB_LAUNCH(k_gather_i32, cdiv(nk, T), T, 0, s, nk, chh, c.ntrk.as<int32_t>(), nntrk);
 

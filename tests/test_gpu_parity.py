@@ -156,6 +156,26 @@ def test_scene_c2(torch_cuda):
     assert _scene_parity("c2", 8, 1024, 1e-5, warm=True) > 0
 
 
+def test_full_size_step(torch_cuda):
+    """The benchmarked workload (N=500 objects, H_max=1e4, clutter 100): one prediction and one
+    update from a state the oracle produced, compared hypothesis by hypothesis (densities of
+    the first 200 matched hypotheses)."""
+    spec = sc.spec_for("c5")
+    scene = sc.make_scene(spec, n_steps=2)
+    p = sc.filter_params(spec, 10000, 0.0)
+    o = Oracle(p)
+    o.import_state(sc.warm_start_state(scene))
+    o.predict(0)
+    o.update(0, scene.meas[0])
+    post = to_f32_state(o.export_state())
+    check_predict(post, p, 1)
+    o.import_state(post)
+    o.predict(1)
+    pred = to_f32_state(o.export_state())
+    matched, stats, out_o, out_g = check_update(pred, scene.meas[1], p, 1, full_density=False)
+    assert len(out_g["hyp_logw"]) == 10000 and matched > 9000, matched
+
+
 @pytest.mark.slow
 def test_scene_c3_n100(torch_cuda):
     assert _scene_parity("c3:100", 3, 1000, 0.0, warm=True) > 0
@@ -172,6 +192,16 @@ def test_empty_state(torch_cuda):
     z = np.array([[1.0, 2.0], [1.5, 2.2], [40.0, 40.0]], np.float32)
     check_update(sc.empty_state(), z, dict(BASE, h_max=10))
     check_predict(sc.empty_state(), dict(BASE, h_max=10))
+
+
+def test_wide_gate(torch_cuda):
+    """A lost track with a very wide gate: more than 128 detections are compatible with its label."""
+    rng = np.random.default_rng(12)
+    st = sc.random_state(rng, n_lab=6, n_hyp=5, side=60.0, versions=2)
+    st["inst_P"][0] = np.diag([300.0, 300.0, 20.0, 20.0]).reshape(16)
+    z = sc.measurements_near(rng, st, 260, 60.0, 1.0)
+    for K in (16, 300):
+        check_update(st, z, dict(BASE, h_max=K, clutter_density=0.05))
 
 
 def test_hmax_one(torch_cuda):
