@@ -239,7 +239,7 @@ glmb_status glmb_destroy(glmb_ctx* x) {
   (void)hipStreamSynchronize(x->c.s);
   glmb::Ctx& c = x->c;
   glmb::DevBuf* bufs[] = {&c.inst, &c.inst2, &c.inst_nz, &c.inst_z, &c.logw, &c.ntrk, &c.rows, &c.hparent, &c.logw2,
-                          &c.ntrk2, &c.rows2, &c.births, &c.diag_best, &c.diag_logpi, &c.diag_ru, &c.prev_rows,
+                          &c.ntrk2, &c.rows2, &c.births, &c.births2, &c.diag_best, &c.diag_logpi, &c.diag_ru, &c.prev_rows,
                           &c.prev_src, &c.child_par, &c.dev_off, &c.dev_i, &c.dev_slot, &c.z, &c.cmax, &c.gbits,
                           &c.phi, &c.lbits, &c.lpre, &c.llen, &c.loff, &c.lmeas, &c.inst_beg, &c.ccnt, &c.coff,
                           &c.cand, &c.best16, &c.dev1, &c.lserel, &c.bprime, &c.lzprime, &c.vals, &c.cells,

@@ -52,7 +52,7 @@ struct Ctx {
   DevBuf inst_nz, inst_z;      // detections of the last update per instance (count, up to 8 indices)
   DevBuf logw, ntrk, rows, hparent;
   DevBuf logw2, ntrk2, rows2;  // double buffers
-  DevBuf births;               // DBirth
+  DevBuf births, births2;      // DBirth (the update writes the next scan's into births2)
 
   // ---- last update (for diagnostics / exports) ----
   int last_H = 0, last_M = 0, last_stride = 0;

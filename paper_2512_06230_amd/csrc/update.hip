@@ -163,10 +163,11 @@ __device__ __forceinline__ float block_max_f(float v, float* sh) {
 
 // one block per hypothesis; the hypothesis row is staged in LDS
 __global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t* rows, const float* logw,
-                                               const int32_t* ntrk, int nref, float gamma, float lgk,
+                                               const int32_t* ntrk, float gamma, float lgk,
                                                const int32_t* coff, const int32_t* cand, const float* phi,
                                                const uint32_t* cmax, int16_t* best16, float* dev1, float* lserel,
-                                               float* bprime, float* lzprime, unsigned long long* nopts) {
+                                               float* bprime, float* lzprime, unsigned long long* nopts,
+                                               unsigned long long* ndense) {
   extern __shared__ int32_t row[];
   __shared__ float red[16];
   const int h = blockIdx.x;
@@ -211,9 +212,11 @@ __global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t*
   bsum = block_sum_f(bsum, red);
   lsum = block_sum_f(lsum, red + 8);
   if (threadIdx.x == 0) {
-    const float base = logw[h] - gamma * (float)(ntrk[h] - nref);
+    // the miss terms relative to hypothesis 0's track count keep the values small
+    const float base = logw[h] - gamma * (float)(ntrk[h] - ntrk[0]);
     bprime[h] = base + bsum;
     lzprime[h] = base + lsum;
+    atomicAdd(ndense, (unsigned long long)ntrk[h] * (unsigned long long)M);
   }
   // option count (integer; order irrelevant)
   for (int d = kWave / 2; d > 0; d >>= 1) opts += __shfl_xor(opts, d, kWave);
@@ -841,6 +844,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   float* retained = (float*)(scal + 11);
   int32_t* tot = scal + 12;
   int32_t* nb_out = scal + 13;
+  unsigned long long* ndense = (unsigned long long*)(scal + 16);
   GLMB_HIP(hipMemsetAsync(scal, 0, 64 * sizeof(int32_t), s));
 
   c.stats = glmb_step_stats{};
@@ -848,7 +852,6 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   c.stats.n_meas = M;
   c.stats.n_inst_in = U;
   c.stats.n_labels = NS;
-  int64_t dense = 0;
 
   // ---- U0: detections
   trace(c, "update.begin", H, M);
@@ -883,12 +886,11 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   if (M > 0) GLMB_LAUNCH(k_label_bits, NS, 256, 0, s, gbits, beg, W, lbits, lpre, llen, errf);
   else GLMB_LAUNCH(k_fill_i32, cdiv(NS + 1, T), T, 0, s, llen, NS + 1, 0);
   scan_excl(llen, loff, NS, tot, c.tmp, s);
-  const int nl = read1(s, tot);
-  int LW = 1;
+  int LW = 1, nl = 0;
   {
     std::vector<int32_t> hl(NS + 1);
     if (NS) GLMB_HIP(hipMemcpyAsync(hl.data(), llen, NS * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(hipStreamSynchronize(s));
+    nl = read1(s, tot);
     int mx = 0;
     for (int j = 0; j < NS; ++j) mx = std::max(mx, hl[j]);
     LW = std::max(1, (mx + 31) / 32);
@@ -922,19 +924,10 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   float* lserel = need<float>(c.lserel, HM);
   float* bprime = need<float>(c.bprime, H);
   float* lzprime = need<float>(c.lzprime, H);
-  int32_t nref = 0;
-  GLMB_HIP(hipMemcpyAsync(&nref, c.ntrk.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipStreamSynchronize(s));
-  {
-    std::vector<int32_t> nt(H);
-    GLMB_HIP(hipMemcpyAsync(nt.data(), c.ntrk.p, H * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(hipStreamSynchronize(s));
-    for (int h = 0; h < H; ++h) dense += (int64_t)nt[h] * M;
-  }
   c.mark(1);
   GLMB_LAUNCH(k_assoc, H, 256, SW * sizeof(int32_t), s, M, SW, c.rows.as<int32_t>(), c.logw.as<float>(),
-              c.ntrk.as<int32_t>(), nref, p.det_rate, lgk, coff, cand, phi, cmax, best16, dev1, lserel, bprime,
-              lzprime, nopts);
+              c.ntrk.as<int32_t>(), p.det_rate, lgk, coff, cand, phi, cmax, best16, dev1, lserel, bprime, lzprime,
+              nopts, ndense);
   c.mark(2);
   float* dbest = need<float>(c.diag_best, H);
   float* dlogpi = need<float>(c.diag_logpi, H);
@@ -960,7 +953,6 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
               (uint64_t*)nullptr, (uint32_t*)nullptr, errf);
   scan_excl(icount, ioff, ncell, ioff + ncell, c.tmp, s);
   const int nitem = read1(s, ioff + ncell);
-  check_err(s, errf);
   float* itd0 = need<float>(c.it_delta, 2 * (int64_t)nitem);
   int32_t* itg0 = need<int32_t>(c.it_group, 2 * (int64_t)nitem);
   int32_t* ito0 = need<int32_t>(c.it_opt, 2 * (int64_t)nitem);
@@ -1001,7 +993,6 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
               errf);
   scan_excl(depth, doff, nk, doff + nk, c.tmp, s);
   const int ndev = read1(s, doff + nk);
-  check_err(s, errf);
   int32_t* devi = need<int32_t>(c.dev_i, ndev);
   int32_t* devn = need<int32_t>(c.dev_slot, 2 * (int64_t)ndev);
   int32_t* devo = devn + ndev;
@@ -1093,7 +1084,6 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   GLMB_LAUNCH(k_rec_unique, cdiv(R, T), T, 0, s, R, LW, rk, rv, rec_u, rec_m, rfl, errf);
   scan_excl(rfl, rpre, R, tot, c.tmp, s);
   const int nnew = read1(s, tot);
-  check_err(s, errf);
   int32_t* rec_id = need<int32_t>(c.ids, (int64_t)R + np + 2);
   int32_t* rep = need<int32_t>(c.bt, nnew + 1);
   // eoff shares c.ids with rec_id: place it behind the record ids again
@@ -1128,7 +1118,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     GLMB_LAUNCH(k_ru_final, cdiv(M, T), T, 0, s, M, nch, part, ru);
   }
   int32_t* member = need<int32_t>(c.ru, (int64_t)M + 1);
-  DBirth* nb = (DBirth*)need<uint8_t>(c.births, (int64_t)(M + 1) * sizeof(DBirth));
+  DBirth* nb = (DBirth*)need<uint8_t>(c.births2, (int64_t)(M + 1) * sizeof(DBirth));
   GLMB_LAUNCH(k_births, 1, 64, 0, s, M, z, ru, p.birth_ru_max, p.birth_cluster_d, sig2,
               p.birth_sigma_v * p.birth_sigma_v, p.birth_r_max, p.birth_rate, member, nb, nb_out, errf);
 
@@ -1136,12 +1126,14 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   trace(c, "update.stats");
   c.mark(5);
   check_err(s, errf);
-  int32_t hs[16];
-  GLMB_HIP(hipMemcpyAsync(hs, scal, 16 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  int32_t hs[18];
+  GLMB_HIP(hipMemcpyAsync(hs, scal, 18 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   GLMB_HIP(hipStreamSynchronize(s));
   uint64_t ng, no;
   std::memcpy(&ng, hs + 2, 8);
   std::memcpy(&no, hs + 4, 8);
+  uint64_t dense;
+  std::memcpy(&dense, hs + 16, 8);
   float ret;
   std::memcpy(&ret, hs + 11, 4);
   // keep the predicted rows / instance sources for exports of this update
@@ -1167,6 +1159,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   std::swap(c.rows, c.rows2);
   std::swap(c.ntrk, c.ntrk2);
   std::swap(c.logw, c.logw2);
+  std::swap(c.births, c.births2);
   {
     int32_t* hp = need<int32_t>(c.hparent, nk + 1);
     GLMB_HIP(hipMemcpyAsync(hp, chh, (size_t)nk * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
@@ -1180,7 +1173,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   c.stats.n_inst_out = nnew;
   c.stats.gated_pairs = (int64_t)ng;
   c.stats.option_terms = (int64_t)no;
-  c.stats.dense_triples = dense;
+  c.stats.dense_triples = (int64_t)dense;
   c.stats.search_nodes = sel.nodes;
   c.stats.search_levels = sel.levels;
   c.stats.n_births = c.nbirth;
