@@ -160,6 +160,195 @@ __global__ void k_take(int n, const uint64_t* keys, const uint32_t* vals, const 
   sel_rank[j] = (int32_t)(keys[j] & 0xffffffffu);
 }
 
+// ---------------------------------------------------------------- single-workgroup search
+// The same level-synchronous search in one 1024-thread workgroup: no host round trip per
+// level.  Used first; if the node store would overflow it reports it and the multi-kernel
+// search below (with compaction) takes over.
+constexpr int kSB = 1024;
+
+__device__ __forceinline__ int64_t sb_excl_scan(int64_t v, int64_t* sh, int64_t* total) {
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  int64_t x = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int64_t y = __shfl_up(x, d, kWave);
+    if (lane >= d) x += y;
+  }
+  __syncthreads();  // sh may still be read from the previous call
+  if (lane == kWave - 1) sh[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int i = 0; i < kSB / kWave; ++i) {
+      const int64_t t = sh[i];
+      sh[i] = run;
+      run += t;
+    }
+    sh[32] = run;
+  }
+  __syncthreads();
+  *total = sh[32];
+  return x - v + sh[w];
+}
+
+// lower edge of the 24-bit orderable bin holding the K-th largest of v[0..n) (-inf if n < K)
+__device__ float sb_bound(const float* v, int n, int K, int32_t* hist, int64_t* sh, int64_t* sel) {
+  if (n < K) return -INFINITY;
+  uint32_t prefix = 0, bin2 = 0;
+  int64_t need_k = K;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int j = threadIdx.x; j < 4096; j += kSB) hist[j] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += kSB) {
+      const uint32_t o = f2o(v[i]);
+      if (pass == 0) atomicAdd(&hist[o >> 20], 1);
+      else if ((o >> 20) == prefix) atomicAdd(&hist[(o >> 8) & 4095], 1);
+    }
+    __syncthreads();
+    const int t = threadIdx.x;  // owns bins 4t .. 4t+3
+    const int64_t mine = (int64_t)hist[4 * t] + hist[4 * t + 1] + hist[4 * t + 2] + hist[4 * t + 3];
+    int64_t tot;
+    const int64_t excl = sb_excl_scan(mine, sh, &tot);
+    const int64_t above = tot - excl - mine;  // count in bins above this thread's
+    if (above < need_k && above + mine >= need_k) {
+      int64_t acc = above;
+      int b = 4 * t + 3;
+      for (; b > 4 * t; --b) {
+        if (acc + hist[b] >= need_k) break;
+        acc += hist[b];
+      }
+      sel[0] = b;
+      sel[1] = need_k - acc;
+    }
+    __syncthreads();
+    if (pass == 0) {
+      prefix = (uint32_t)sel[0];
+      need_k = sel[1];
+    } else {
+      bin2 = (uint32_t)sel[0];
+    }
+    __syncthreads();
+  }
+  const float e = o2f((prefix << 20) | (bin2 << 8));
+  return e == e ? e : -INFINITY;
+}
+
+__global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, const int32_t* it_off,
+                                                      const float* it_delta, const int32_t* it_group, int K,
+                                                      const float* t0, int cap, int32_t* nd_p, int32_t* nd_i,
+                                                      int32_t* nd_h, float* nd_v, float* t_out, int32_t* out) {
+  __shared__ int64_t sh[40];
+  __shared__ int32_t hist[4096];
+  __shared__ int64_t sel[4];
+  __shared__ int64_t cpre[kSB];
+  __shared__ int64_t ccnt[kSB];
+  __shared__ int32_t clo[kSB];
+  const float nan = __uint_as_float(0xffc00000u);
+  float t = *t0;
+  int status = 0;  // 0 done, 1 node store full, 2 too deep
+  int used = 0;
+  // roots, in parent rank order
+  for (int c0 = 0; c0 < P; c0 += kSB) {
+    const int h = c0 + threadIdx.x;
+    const int f = (h < P && base[h] >= t) ? 1 : 0;
+    int64_t tot;
+    const int64_t off = sb_excl_scan(f, sh, &tot);
+    if (used + tot > cap) {
+      status = 1;
+      break;
+    }
+    if (f) {
+      const int n = used + (int)off;
+      nd_p[n] = -1;
+      nd_i[n] = -1;
+      nd_h[n] = h;
+      nd_v[n] = base[h];
+    }
+    used += (int)tot;
+  }
+  __syncthreads();
+  int first = 0, end = used, levels = 0;
+  while (status == 0 && first < end) {
+    if (++levels > kMaxDepth + 1) {
+      status = 2;
+      break;
+    }
+    int c0 = first;
+    while (c0 < end) {
+      const int nchunk = min(kSB, end - c0);
+      const int n = c0 + (int)threadIdx.x;
+      int lo = 0, hi = 0;
+      if ((int)threadIdx.x < nchunk) ext_range(n, nd_i, nd_h, nd_v, it_off, it_delta, t, &lo, &hi);
+      const int64_t cnt = hi - lo;
+      int64_t tot;
+      const int64_t excl = sb_excl_scan(cnt, sh, &tot);
+      cpre[threadIdx.x] = excl;
+      ccnt[threadIdx.x] = cnt;
+      clo[threadIdx.x] = lo;
+      if (threadIdx.x == 0) sel[2] = 0;
+      __syncthreads();
+      const int64_t room = (int64_t)cap - used;
+      int take = nchunk;
+      int64_t te = tot;
+      if (tot > room) {
+        // nodes of the chunk (a prefix) whose extensions still fit
+        if ((int)threadIdx.x < nchunk && excl + cnt <= room) atomicMax((unsigned long long*)&sel[2],
+                                                                       (unsigned long long)(threadIdx.x + 1));
+        __syncthreads();
+        take = (int)sel[2];
+        if (take == 0) {
+          const float b = sb_bound(nd_v, used, K, hist, sh, sel);
+          if (b > t) {
+            t = b;  // recount this chunk under the raised threshold
+            continue;
+          }
+          status = 1;
+          break;
+        }
+        te = cpre[take - 1] + ccnt[take - 1];
+      }
+      for (int64_t e = threadIdx.x; e < te; e += kSB) {
+        int a = 0, b = take - 1;  // last node with cpre <= e
+        while (a < b) {
+          const int m = (a + b + 1) >> 1;
+          if (cpre[m] <= e) a = m;
+          else b = m - 1;
+        }
+        const int nn = c0 + a;
+        const int q = clo[a] + (int)(e - cpre[a]);
+        float v = nd_v[nn] - it_delta[q];
+        const int g = it_group[q];
+        for (int x = nn; nd_i[x] >= 0; x = nd_p[x])
+          if (it_group[nd_i[x]] == g) {
+            v = nan;  // two picks in one group: not a child
+            break;
+          }
+        const int o = used + (int)e;
+        nd_p[o] = nn;
+        nd_i[o] = q;
+        nd_h[o] = nd_h[nn];
+        nd_v[o] = v;
+      }
+      __syncthreads();
+      used += (int)te;
+      c0 += take;
+    }
+    if (status != 0) break;
+    first = end;
+    end = used;
+    if (first < end && used >= K) {
+      const float b = sb_bound(nd_v, used, K, hist, sh, sel);
+      if (b > t) t = b;
+    }
+  }
+  if (threadIdx.x == 0) {
+    out[0] = used;
+    out[1] = levels;
+    out[2] = status;
+    *t_out = t;
+  }
+}
+
 namespace {
 struct Nodes {
   int32_t *p, *i, *h;
@@ -200,21 +389,27 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
     GLMB_HIP(hipMemcpyAsync(hs, scal, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     GLMB_HIP(hipStreamSynchronize(s));
   };
-  // roots
-  {
+  // first attempt: the whole search in one workgroup
+  GLMB_LAUNCH(k_select_block, 1, kSB, 0, s, in.P, in.base, in.it_off, in.it_delta, in.it_group, in.K, in.t0, cap,
+              A.p, A.i, A.h, A.v, t, scal + 4);
+  GLMB_HIP(hipMemcpyAsync(hs, scal + 4, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipStreamSynchronize(s));
+  int used = hs[0], levels = hs[1];
+  const bool fast = hs[2] == 0;
+  tr("block", used, hs[2]);
+  if (!fast) {
+    // roots
+    GLMB_HIP(hipMemcpyAsync(t, in.t0, sizeof(float), hipMemcpyDeviceToDevice, s));
     int32_t* fl = need<int32_t>(b.flags, in.P + 1);
     int32_t* pre = need<int32_t>(b.pre, in.P + 1);
     GLMB_LAUNCH(k_root_flags, cdiv(in.P, T), T, 0, s, in.base, in.P, t, fl);
     scan_excl(fl, pre, in.P, scal, b.tmp, s);
     GLMB_LAUNCH(k_root_write, cdiv(in.P, T), T, 0, s, in.base, in.P, t, pre, A.p, A.i, A.h, A.v);
     read(1);
+    used = hs[0];
+    levels = 0;
   }
-  int used = hs[0];
-  if (used > cap) {
-    err = "selection: more parents than search nodes";
-    return GLMB_E_CAPACITY;
-  }
-  int level_first = 0, level_end = used, levels = 0;
+  int level_first = 0, level_end = fast ? 0 : used;
 
   // raise t to a bound on the K-th largest node value and drop nodes below it
   auto raise_and_compact = [&](int* cursor) -> bool {

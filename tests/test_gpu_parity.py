@@ -204,6 +204,16 @@ def test_wide_gate(torch_cuda):
         check_update(st, z, dict(BASE, h_max=K, clutter_density=0.05))
 
 
+def test_small_node_store(torch_cuda):
+    """A node store too small for the one-workgroup search: the multi-kernel search with
+    threshold raising and compaction must reach the same hypotheses."""
+    rng = np.random.default_rng(21)
+    st = sc.random_state(rng, n_lab=6, n_hyp=10, side=20.0, versions=2)
+    z = sc.measurements_near(rng, st, 4, 20.0, 1.0)
+    for cap in (90, 110, 0):  # 90 and 110 overflow the one-workgroup search; 0 = default store
+        check_update(st, z, dict(BASE, h_max=64, cap_nodes=cap))
+
+
 def test_hmax_one(torch_cuda):
     rng = np.random.default_rng(4)
     st = sc.random_state(rng, n_lab=5, n_hyp=6, side=20.0)
