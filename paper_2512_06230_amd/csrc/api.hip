@@ -503,14 +503,17 @@ glmb_status glmb_update_theta(glmb_ctx* x, int32_t n_hyp, int32_t M, int32_t* th
     hipStream_t s = c.s;
     const int H = c.last_H, SW = c.last_stride, n = c.nhyp;
     std::vector<int16_t> best((size_t)H * M);
-    std::vector<int32_t> prows((size_t)H * SW), psrc(std::max(1, c.stats.n_inst_in)), par(n), doff(n + 1);
+    // the predicted rows and instances of the last update are kept in rows2 / inst2
+    const int UP = c.stats.n_inst_in;
+    std::vector<int32_t> prows((size_t)H * SW), psrc(std::max(1, UP)), par(n), doff(n + 1);
+    std::vector<DInst> pinst(std::max(1, UP));
     if (H * M) GLMB_HIP(hipMemcpyAsync(best.data(), c.best16.p, best.size() * 2, hipMemcpyDeviceToHost, s));
-    if (H * SW) GLMB_HIP(hipMemcpyAsync(prows.data(), c.prev_rows.p, prows.size() * 4, hipMemcpyDeviceToHost, s));
-    if (c.stats.n_inst_in)
-      GLMB_HIP(hipMemcpyAsync(psrc.data(), c.prev_src.p, c.stats.n_inst_in * 4, hipMemcpyDeviceToHost, s));
+    if (H * SW) GLMB_HIP(hipMemcpyAsync(prows.data(), c.rows2.p, prows.size() * 4, hipMemcpyDeviceToHost, s));
+    if (UP) GLMB_HIP(hipMemcpyAsync(pinst.data(), c.inst2.p, (size_t)UP * sizeof(DInst), hipMemcpyDeviceToHost, s));
     GLMB_HIP(hipMemcpyAsync(par.data(), c.hparent.p, n * 4, hipMemcpyDeviceToHost, s));
     GLMB_HIP(hipMemcpyAsync(doff.data(), c.dev_off.p, (n + 1) * 4, hipMemcpyDeviceToHost, s));
     GLMB_HIP(hipStreamSynchronize(s));
+    for (int u = 0; u < UP; ++u) psrc[u] = pinst[u].src;
     const int nd = doff[n];
     std::vector<int32_t> di(nd), dn(nd);
     if (nd) {

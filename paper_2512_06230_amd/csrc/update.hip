@@ -1136,22 +1136,8 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   std::memcpy(&dense, hs + 16, 8);
   float ret;
   std::memcpy(&ret, hs + 11, 4);
-  // keep the predicted rows / instance sources for exports of this update
-  {
-    int32_t* pr = need<int32_t>(c.prev_rows, (int64_t)H * SW);
-    GLMB_HIP(hipMemcpyAsync(pr, c.rows.p, (size_t)H * SW * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    int32_t* ps = need<int32_t>(c.prev_src, U + 1);
-    // source index of every predicted instance
-    std::vector<DInst> hi(U);
-    if (U) {
-      GLMB_HIP(hipMemcpyAsync(hi.data(), c.inst.p, (size_t)U * sizeof(DInst), hipMemcpyDeviceToHost, s));
-      GLMB_HIP(hipStreamSynchronize(s));
-    }
-    std::vector<int32_t> src(U);
-    for (int u = 0; u < U; ++u) src[u] = hi[u].src;
-    if (U) GLMB_HIP(hipMemcpyAsync(ps, src.data(), (size_t)U * sizeof(int32_t), hipMemcpyHostToDevice, s));
-    GLMB_HIP(hipStreamSynchronize(s));
-  }
+  // the predicted rows and instances stay in rows2 / inst2 after the swap below, until the
+  // next prediction: the association-map export of this update reads them there
   c.last_H = H;
   c.last_M = M;
   c.last_stride = SW;
