@@ -134,8 +134,12 @@ def predict(state: dict, p: dict, K: int):
     return [dict(logw=v - z, src=mem, parent=k[0]) for v, k, mem in items], moments
 
 
-def update(state: dict, z: np.ndarray, p: dict, K: int, tau: float = 0.0):
-    """Enumerate every association map of every hypothesis of a *predicted* state."""
+def update(state: dict, z: np.ndarray, p: dict, K: int, tau: float = 0.0, skip=()):
+    """Enumerate every association map of every hypothesis of a *predicted* state.
+
+    ``skip``: (instance, measurement) pairs a proposal removes.  Maps that use one of them
+    are left out of the ranking and the marginals; ``lost`` is their share of the mass of
+    all maps."""
     z = np.asarray(z, dtype=np.float64).reshape(-1, 2)
     M = z.shape[0]
     labs = np.asarray(state["inst_lab"]).reshape(-1, 2)
@@ -157,14 +161,17 @@ def update(state: dict, z: np.ndarray, p: dict, K: int, tau: float = 0.0):
             dens[u, i] = stats.multivariate_normal(mean=m[u][:2], cov=S[u]).pdf(z[i])
     children = []
     Zh = []
+    total_all = 0.0
+    pair_mass, exist_mass = {}, {}
+    skip = set((int(a), int(b)) for a, b in skip)
     for h in range(len(state["hyp_logw"])):
         tracks = list(state["hyp_idx"][state["hyp_off"][h]:state["hyp_off"][h + 1]])
         tracks.sort(key=lambda u: lab[u])
         w_h = math.exp(state["hyp_logw"][h])
-        opts = []
+        opts, opts_all = [], []
         for i in range(M):
-            o = [-1] + [u for u in tracks if gated[u, i]]
-            opts.append(o)
+            opts_all.append([-1] + [u for u in tracks if gated[u, i]])
+            opts.append([-1] + [u for u in tracks if gated[u, i] and (u, i) not in skip])
         # best option per measurement and the deviation items for the canonical key
         def lphi(u, i):
             return math.log(kappa) if u < 0 else math.log(gamma * dens[u, i])
@@ -179,7 +186,7 @@ def update(state: dict, z: np.ndarray, p: dict, K: int, tau: float = 0.0):
                 devs.append((lphi(o[0], i) - lphi(u, i), i, okey(u)))
         pos = _items_positions(devs)
         total = 0.0
-        for theta in itertools.product(*opts):
+        for theta in itertools.product(*opts_all):
             prob = w_h
             for u in tracks:
                 Su = [i for i in range(M) if theta[i] == u]
@@ -189,7 +196,15 @@ def update(state: dict, z: np.ndarray, p: dict, K: int, tau: float = 0.0):
             for i in range(M):
                 if theta[i] < 0:
                     prob *= kappa
+            total_all += prob
+            if any((theta[i], i) in skip for i in range(M)):
+                continue
             total += prob
+            for i in range(M):
+                if theta[i] >= 0:
+                    pair_mass[(theta[i], i)] = pair_mass.get((theta[i], i), 0.0) + prob
+            for u in tracks:
+                exist_mass[u] = exist_mass.get(u, 0.0) + prob
             dv = [i for i in range(M) if theta[i] != best[i]]
             key = (h, len(dv), tuple(sorted(pos[(i, okey(theta[i]))] for i in dv)))
             children.append((math.log(prob) if prob > 0 else -np.inf, key, (h, tuple(theta))))
@@ -227,4 +242,7 @@ def update(state: dict, z: np.ndarray, p: dict, K: int, tau: float = 0.0):
             dens_out[lab[u]] = (mm, PP)
         out.append(dict(logw=v - lz, parent=h, theta=tuple(theta), dens=dens_out))
     return dict(children=out, logpi=np.log(Zh / Ztot), ru=1.0 - pc,
-                retained=math.exp(lz) / Ztot, Zh=Zh, gated=gated, dens=dens)
+                retained=math.exp(lz) / Ztot, Zh=Zh, gated=gated, dens=dens,
+                lost=1.0 - Ztot / total_all,
+                pair_mass={k: v / Ztot for k, v in pair_mass.items()},
+                exist={k: v / Ztot for k, v in exist_mass.items()})

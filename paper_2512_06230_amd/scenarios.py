@@ -281,3 +281,17 @@ def measurements_near(rng: np.random.Generator, state: dict, n_clutter: int, sid
     z = np.concatenate(zs, axis=0) if zs else np.zeros((0, 2))
     z = z[rng.permutation(z.shape[0])]
     return np.ascontiguousarray(z, dtype=np.float32)
+
+
+def mlp_init(seed: int, n_in: int = 6, n_hid: int = 64) -> np.ndarray:
+    """Seeded initial parameters of the pair-scoring network, in the flat layout
+    W1[n_hid][n_in] | b1 | W2[n_hid][n_hid] | b2 | w3[n_hid] | b3 (float32 values).
+
+    Weights are uniform in +-sqrt(6 / fan_in) (He initialisation for ReLU layers; the
+    output layer uses +-sqrt(1 / fan_in)); biases start at zero."""
+    rng = np.random.default_rng(seed)
+    a1, a2, a3 = math.sqrt(6.0 / n_in), math.sqrt(6.0 / n_hid), math.sqrt(1.0 / n_hid)
+    parts = [rng.uniform(-a1, a1, n_hid * n_in), np.zeros(n_hid),
+             rng.uniform(-a2, a2, n_hid * n_hid), np.zeros(n_hid),
+             rng.uniform(-a3, a3, n_hid), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
