@@ -96,7 +96,9 @@ typedef struct {
   int64_t dense_triples;    /* sum_h |J_h| * M                                           */
   int32_t search_nodes, search_levels, n_births;
   double retained_mass;     /* posterior mass of the kept hypotheses                     */
-  double lost_mass;         /* posterior mass removed by the learned proposal (0 if plain) */
+  double lost_mass;         /* posterior mass removed by the learned proposal (measured only
+                               when enabled by glmb_set_proposal; 0 otherwise)           */
+  int32_t pairs_removed;    /* gated pairs the learned proposal removed                   */
   /* stage durations of the last update from HIP events on the context's stream (ms):
    * [0] gate + score, [1] association normalisers (the per-(hypothesis, detection) kernel
    * alone), [2] cut bound + deviation items + selection, [3] materialise + Kalman,
@@ -157,6 +159,72 @@ glmb_status glmb_update_diag(glmb_ctx* ctx, int32_t H, int32_t M, float* best, f
  * input index of the predicted instance that detection i is assigned to, -1 for clutter.
  * Host buffer of n_hyp*M int32. Synchronises. */
 glmb_status glmb_update_theta(glmb_ctx* ctx, int32_t n_hyp, int32_t M, int32_t* theta);
+
+/* ---- Learned pair proposal ------------------------------------------------------------
+ * An addition to the update of Sec. 3: a small network scores every gated (track instance,
+ * detection) pair of the predicted GLMB from six features, and pairs scoring below a
+ * threshold are removed from the option sets of the update (Eq. 2 entries to which the
+ * posterior gives negligible mass).  Without parameters the update is the plain method.
+ *
+ * Network: features -> standardise -> 64 ReLU -> 64 ReLU -> logit.  Parameters: float32
+ * vector of GLMB_MLP_NPARAM values W1[64][6] | b1[64] | W2[64][64] | b2[64] | w3[64] | b3,
+ * W[j][k] the weight from input k to output j.  Arithmetic: weights, standardised inputs
+ * and both hidden activations are rounded to bfloat16 (nearest, ties to even); every sum is
+ * accumulated in float32.
+ * Features of pair (u, i), from predicted instance u (mean m, covariance P) and detection
+ * z_i, in this order: d2 = nu^T (H P H^T + sigma_z^2 I)^-1 nu with nu = z_i - H m; nu_x;
+ * nu_y; r_label = existence probability of u's label (total weight of the hypotheses that
+ * hold it); age = k - birth scan of the label; n_gate = detections gated with u.
+ * norm: host float[12], per-feature mean[6] then standard deviation[6]. */
+#define GLMB_MLP_NPARAM 4673
+#define GLMB_MLP_NFEAT 6
+
+/* Enable the proposal for the following updates (params_dev: device float32 parameters,
+ * copied before the call returns; NULL disables it).  A pair is removed when
+ * sigmoid(logit) < threshold, 0 < threshold < 1.  measure != 0: each update first measures,
+ * on the full association space, the posterior mass the removal loses (stats.lost_mass;
+ * costs one extra pass over the hypotheses). Synchronises. */
+glmb_status glmb_set_proposal(glmb_ctx* ctx, const float* params_dev, const float* norm, float threshold,
+                              int32_t measure);
+
+/* Training data from the current (predicted) state and the M detections of scan k
+ * (z_dev as in glmb_update); the state is unchanged.  For every gated pair:
+ * feat_dev[cap][6] the features above, pair_dev[cap][2] (input index of the instance as
+ * exported, detection index), target_dev[cap] = m_ui / e_u and weight_dev[cap] = e_u, where
+ * over the full posterior of the plain update m_ui = sum of pi_h q_hi(u) over the
+ * hypotheses h holding u (pi_h: posterior mass of h's children; q_hi(u): probability that
+ * detection i belongs to u given h) and e_u = sum of those pi_h.  Pairs are listed by
+ * instance (state order), then detection.  *n_pairs (host) receives the pair count;
+ * GLMB_E_CAPACITY when it exceeds cap (nothing written). Synchronises. */
+glmb_status glmb_pair_features(glmb_ctx* ctx, int32_t k, const float* z_dev, int32_t M, int32_t cap,
+                               float* feat_dev, int32_t* pair_dev, float* target_dev, float* weight_dev,
+                               int32_t* n_pairs);
+
+/* Posterior mass the proposal with the parameters of glmb_set_proposal would remove, for
+ * each of T thresholds (host thresholds[T], 1 <= T <= 16, each in (0, 1); host lost[T]),
+ * on the current predicted state and the detections of scan k; the state is unchanged.
+ * lost = 1 - Z_kept / Z_full with Z the total weight of every association map of every
+ * hypothesis (with the kept options only, resp. with all). Synchronises. */
+glmb_status glmb_proposal_lost(glmb_ctx* ctx, int32_t k, const float* z_dev, int32_t M, int32_t T,
+                               const float* thresholds, double* lost);
+
+/* Network kernels on the context's stream (device arrays; n >= 0 samples; feat_dev[n][6]
+ * raw features; norm host float[12]).
+ * glmb_mlp_forward: logit_dev[n].
+ * glmb_mlp_grad: weighted binary cross-entropy L = sum_p w_p (softplus(s_p) - y_p s_p) /
+ *   sum_p w_p (s: logit, y: target in [0, 1], w >= 0 with a positive sum) into loss_dev[1],
+ *   its gradient into grad_dev[GLMB_MLP_NPARAM]; the bfloat16 roundings pass the gradient
+ *   unchanged.  Deterministic: fixed reduction order.
+ * glmb_mlp_adam: one Adam step (Kingma & Ba, 2015, with bias correction) at step number
+ *   t >= 1: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ *   params -= lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps); m_dev, v_dev start at zero. */
+glmb_status glmb_mlp_forward(glmb_ctx* ctx, const float* params_dev, const float* norm, const float* feat_dev,
+                             int32_t n, float* logit_dev);
+glmb_status glmb_mlp_grad(glmb_ctx* ctx, const float* params_dev, const float* norm, const float* feat_dev,
+                          const float* target_dev, const float* weight_dev, int32_t n, float* grad_dev,
+                          float* loss_dev);
+glmb_status glmb_mlp_adam(glmb_ctx* ctx, float* params_dev, float* m_dev, float* v_dev, const float* grad_dev,
+                          int32_t t, float lr, float beta1, float beta2, float eps);
 
 #ifdef __cplusplus
 }

@@ -249,7 +249,8 @@ glmb_status glmb_destroy(glmb_ctx* x) {
                           &c.tv, &c.flags, &c.pre, &c.pmult, &c.pvals, &c.rec_m, &c.sb.nd_parent, &c.sb.nd_item, &c.sb.nd_h,
                           &c.sb.nd_value, &c.sb.cnt, &c.sb.pre, &c.sb.pre64, &c.sb.flags, &c.sb.map, &c.sb.tmp,
                           &c.sb.tk, &c.sb.tv, &c.sb.keys, &c.sb.vals, &c.sb.sel_node, &c.sb.sel_val, &c.sb.sel_rank,
-                          &c.sb.scal};
+                          &c.sb.scal, &c.prop_w, &c.pcnt, &c.poff, &c.ppre, &c.pu, &c.pi, &c.plogit, &c.slot_r,
+                          &c.slot_part, &c.slot_age, &c.pm_part, &c.pe_part, &c.lz_t, &c.mlp_part};
   for (auto* b : bufs) b->release();
   if (c.ev_ok)
     for (auto& e : c.ev) (void)hipEventDestroy(e);
@@ -530,6 +531,75 @@ glmb_status glmb_update_theta(glmb_ctx* x, int32_t n_hyp, int32_t M, int32_t* th
         theta[(size_t)h * M + i] = sl[i] < 0 ? -1 : psrc[prows[(size_t)ph * SW + sl[i]]];
     }
   });
+}
+
+glmb_status glmb_set_proposal(glmb_ctx* x, const float* params, const float* norm, float threshold, int32_t measure) {
+  if (!x) return GLMB_E_ARG;
+  if (!params) {
+    x->c.prop_on = false;
+    return GLMB_OK;
+  }
+  if (!norm || !(threshold > 0.0f && threshold < 1.0f))
+    return fail(x, GLMB_E_ARG, "null norm or threshold outside (0, 1)");
+  for (int k = 0; k < 12; ++k)
+    if (!std::isfinite(norm[k]) || (k >= 6 && !(norm[k] > 0.0f)))
+      return fail(x, GLMB_E_ARG, "feature norm must be finite with positive standard deviations");
+  return guarded(x, [&](Ctx& c) {
+    float* w = glmb::need<float>(c.prop_w, glmb::kNParam);
+    GLMB_HIP(hipMemcpyAsync(w, params, glmb::kNParam * sizeof(float), hipMemcpyDeviceToDevice, c.s));
+    GLMB_HIP(hipStreamSynchronize(c.s));
+    std::memcpy(c.prop_norm, norm, sizeof(c.prop_norm));
+    c.prop_thr = (float)std::log((double)threshold / (1.0 - (double)threshold));
+    c.prop_t = threshold;
+    c.prop_measure = measure != 0;
+    c.prop_on = true;
+  });
+}
+
+glmb_status glmb_pair_features(glmb_ctx* x, int32_t k, const float* z, int32_t M, int32_t cap, float* feat,
+                               int32_t* pair, float* target, float* weight, int32_t* n_pairs) {
+  if (!x || !n_pairs || cap < 0 || M < 0 || (M > 0 && !z) || (cap > 0 && (!feat || !pair || !target || !weight)))
+    return GLMB_E_ARG;
+  if (M > 32768) return fail(x, GLMB_E_CAPACITY, "more than 32768 detections in one scan");
+  int n = 0;
+  glmb_status st = guarded(x, [&](Ctx& c) { n = glmb::proposal_features(c, k, z, M, cap, feat, pair, target, weight); });
+  if (st != GLMB_OK) return st;
+  *n_pairs = n;
+  if (n > cap) return fail(x, GLMB_E_CAPACITY, "more gated pairs than cap");
+  return GLMB_OK;
+}
+
+glmb_status glmb_proposal_lost(glmb_ctx* x, int32_t k, const float* z, int32_t M, int32_t T, const float* thr,
+                               double* lost) {
+  if (!x || !thr || !lost || M < 0 || (M > 0 && !z)) return GLMB_E_ARG;
+  if (T < 1 || T > glmb::kMaxThr) return fail(x, GLMB_E_ARG, "1 <= T <= 16 thresholds");
+  for (int j = 0; j < T; ++j)
+    if (!(thr[j] > 0.0f && thr[j] < 1.0f)) return fail(x, GLMB_E_ARG, "thresholds must lie in (0, 1)");
+  if (M > 32768) return fail(x, GLMB_E_CAPACITY, "more than 32768 detections in one scan");
+  return guarded(x, [&](Ctx& c) {
+    if (c.prop_w.bytes < glmb::kNParam * sizeof(float)) throw Error{GLMB_E_STATE, "no proposal parameters set"};
+    glmb::proposal_lost(c, k, z, M, thr, T, lost);
+  });
+}
+
+glmb_status glmb_mlp_forward(glmb_ctx* x, const float* params, const float* norm, const float* feat, int32_t n,
+                             float* logit) {
+  if (!x || !params || !norm || n < 0 || (n > 0 && (!feat || !logit))) return GLMB_E_ARG;
+  return guarded(x, [&](Ctx& c) { glmb::mlp_forward(c, params, norm, feat, n, logit); });
+}
+
+glmb_status glmb_mlp_grad(glmb_ctx* x, const float* params, const float* norm, const float* feat, const float* y,
+                          const float* w, int32_t n, float* grad, float* loss) {
+  if (!x || !params || !norm || !grad || !loss || n < 1 || !feat || !y || !w) return GLMB_E_ARG;
+  return guarded(x, [&](Ctx& c) { glmb::mlp_grad(c, params, norm, feat, y, w, n, grad, loss); });
+}
+
+glmb_status glmb_mlp_adam(glmb_ctx* x, float* params, float* m, float* v, const float* g, int32_t t, float lr,
+                          float beta1, float beta2, float eps) {
+  if (!x || !params || !m || !v || !g || t < 1 || !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) ||
+      !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return GLMB_E_ARG;
+  return guarded(x, [&](Ctx& c) { glmb::mlp_adam(c, params, m, v, g, t, lr, beta1, beta2, eps); });
 }
 
 }  // extern "C"

@@ -67,6 +67,16 @@ struct Ctx {
       sel_logw, hp_map, first, dmask, exc, cmod, recs, rec_keys, rec_vals, ids, row_mark, ru_part, ru, bt,
       tmp, tk, tv, flags, pre, pmult, pvals, rec_m;
   SelectBufs sb;
+  int LW = 1;  // detection-set mask width (32-bit words) of the last gate
+
+  // ---- learned pair proposal
+  bool prop_on = false, prop_measure = false;
+  float prop_thr = 0.0f;  // logit threshold: pairs with a lower logit are removed
+  float prop_t = 0.5f;    // the same threshold as a probability
+  float prop_norm[12] = {};
+  DevBuf prop_w;          // float32 parameters
+  DevBuf pcnt, poff, ppre, pu, pi, plogit, slot_r, slot_part, slot_age, pm_part, pe_part, lz_t, mlp_part;
+  std::vector<int32_t> h_age;
 };
 
 // opt-in stage trace (host side)
@@ -80,6 +90,21 @@ inline void trace(const Ctx& c, const char* stage, long long a = -1, long long b
 void stage_predict(Ctx& c, int k);
 void stage_update(Ctx& c, int k, const float* z, int M);
 void stage_truncate(Ctx& c, int hmax, float tau);
+// pieces of the update shared with the proposal
+void gate_scores(Ctx& c, const float* z, int M);
+void gate_lists(Ctx& c, int M);
+void assoc_norm(Ctx& c, int M);
+// proposal (proposal.hip)
+constexpr int kNFeat = 6, kNHid = 64, kNParam = 4673, kMaxThr = 16;
+void proposal_apply(Ctx& c, int k, int M);
+void proposal_lost(Ctx& c, int k, const float* z, int M, const float* thr_prob, int T, double* lost);
+int proposal_features(Ctx& c, int k, const float* z, int M, int cap, float* feat, int32_t* pair, float* target,
+                      float* weight);
+void mlp_forward(Ctx& c, const float* params, const float* norm, const float* feat, int n, float* logit);
+void mlp_grad(Ctx& c, const float* params, const float* norm, const float* feat, const float* y, const float* w,
+              int n, float* grad, float* loss);
+void mlp_adam(Ctx& c, float* params, float* m, float* v, const float* g, int t, float lr, float b1, float b2,
+              float eps);
 void gc_state(Ctx& c);
 
 // F and Q of the constant-velocity model (host constants passed to kernels)

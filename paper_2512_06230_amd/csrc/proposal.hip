@@ -1,0 +1,603 @@
+// Learned pair proposal, an addition to the update of Sec. 3, on the GPU:
+//
+//   pairs      compaction of the gated (instance, detection) pairs from the gate bits;
+//   features   [d2, nu_x, nu_y, r_label, age, n_gate] of every pair;
+//   network    6 -> 64 -> 64 -> 1 with ReLU: bfloat16 weights, standardised inputs and
+//              hidden activations, float32 sums; one thread per pair, weights in LDS;
+//   removal    pairs whose logit is below the threshold leave the gate (gate bit cleared,
+//              Eq. 2 entry set to -inf) before the per-label lists are built, so every later
+//              stage of the update sees fewer options;
+//   lost mass  1 - Z_kept / Z_full for up to 16 thresholds in one pass over the hypotheses;
+//   training   targets from the full posterior of the plain update; forward + backward over
+//              64 samples per workgroup with per-sample vectors in LDS and a fixed-order
+//              gradient reduction; Adam.
+#include "ctx.hpp"
+
+namespace glmb {
+
+namespace {
+
+// offsets in the parameter vector W1[64][6] | b1[64] | W2[64][64] | b2[64] | w3[64] | b3
+constexpr int oW1 = 0, oB1 = oW1 + kNHid * kNFeat, oW2 = oB1 + kNHid, oB2 = oW2 + kNHid * kNHid, oW3 = oB2 + kNHid,
+              oB3 = oW3 + kNHid;
+static_assert(oB3 + 1 == kNParam, "parameter layout");
+constexpr int kPartW = kNParam + 2;  // partial gradients + [sum of weights, sum of weighted losses]
+constexpr int kLS = 65;              // LDS row stride of per-sample vectors (odd: no bank conflicts)
+
+struct Norm {
+  float mu[kNFeat], sd[kNFeat];
+};
+struct Thr {
+  float t[kMaxThr];
+};
+
+// round to the nearest bfloat16 value, ties to even
+__device__ __forceinline__ float bf16r(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xFFFF0000u);
+}
+
+__device__ __forceinline__ void load_params(const float* __restrict__ w, float* sw) {
+  for (int q = threadIdx.x; q < kNParam; q += blockDim.x) sw[q] = bf16r(w[q]);
+  __syncthreads();
+}
+
+__device__ __forceinline__ void standardise(const float* x, const Norm& nm, float* xs) {
+#pragma unroll
+  for (int k = 0; k < kNFeat; ++k) xs[k] = bf16r((x[k] - nm.mu[k]) / nm.sd[k]);
+}
+
+__device__ __forceinline__ void layer1(const float* sw, const float* xs, float* h1) {
+#pragma unroll
+  for (int j = 0; j < kNHid; ++j) {
+    float a = sw[oB1 + j];
+#pragma unroll
+    for (int k = 0; k < kNFeat; ++k) a = fmaf(sw[oW1 + j * kNFeat + k], xs[k], a);
+    h1[j] = bf16r(fmaxf(a, 0.0f));
+  }
+}
+
+// pre-activation of unit j of the second hidden layer
+__device__ __forceinline__ float layer2_unit(const float* sw, const float* h1, int j) {
+  float a = sw[oB2 + j];
+  const float* wr = sw + oW2 + j * kNHid;
+#pragma unroll
+  for (int k = 0; k < kNHid; ++k) a = fmaf(wr[k], h1[k], a);
+  return a;
+}
+
+__device__ __forceinline__ float mlp_logit(const float* sw, const float* x, const Norm& nm) {
+  float xs[kNFeat], h1[kNHid];
+  standardise(x, nm, xs);
+  layer1(sw, xs, h1);
+  float s = sw[oB3];
+  for (int j = 0; j < kNHid; ++j) s = fmaf(sw[oW3 + j], bf16r(fmaxf(layer2_unit(sw, h1, j), 0.0f)), s);
+  return s;
+}
+
+// features of pair (instance x, detection zi); d2 uses the gate's expression
+__device__ __forceinline__ void pair_feature(const DInst& x, float2 zi, float sig2, float r, float age, float ng,
+                                             float* f) {
+  const float s00 = x.P[0] + sig2, s01 = x.P[1], s11 = x.P[4] + sig2;
+  const float det = s00 * s11 - s01 * s01;
+  const float n0 = zi.x - x.m[0], n1 = zi.y - x.m[1];
+  const float qd = s11 * n0 * n0 - 2.0f * s01 * n0 * n1 + s00 * n1 * n1;
+  f[0] = qd / det;
+  f[1] = n0;
+  f[2] = n1;
+  f[3] = r;
+  f[4] = age;
+  f[5] = ng;
+}
+
+__device__ __forceinline__ float wsum(float v, float* sh) {
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  __syncthreads();
+  if (lane_id() == 0) sh[threadIdx.x / kWave] = v;
+  __syncthreads();
+  float r = 0.0f;
+  for (int j = 0; j < (int)(blockDim.x / kWave); ++j) r += sh[j];
+  return r;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ pairs and features
+// per instance: gated detection count and per-word prefix counts of its gate bits
+__global__ void k_pair_count(int U, int W, const uint32_t* gbits, int32_t* cnt, int32_t* ppre) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= U) return;
+  int run = 0;
+  for (int w = 0; w < W; ++w) {
+    ppre[(size_t)u * W + w] = run;
+    run += __popc(gbits[(size_t)u * W + w]);
+  }
+  cnt[u] = run;
+}
+
+__global__ void k_pair_list(int U, int W, const uint32_t* gbits, const int32_t* poff, int32_t* pu, int32_t* pi) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= U) return;
+  int pos = poff[u];
+  for (int w = 0; w < W; ++w) {
+    uint32_t b = gbits[(size_t)u * W + w];
+    while (b) {
+      pu[pos] = u;
+      pi[pos] = w * 32 + __ffs(b) - 1;
+      ++pos;
+      b &= b - 1;
+    }
+  }
+}
+
+// existence probability of every label slot: partial sums over chunks of 256 hypotheses
+__global__ void k_slot_part(int H, int NS, int SW, const int32_t* rows, const float* logw, float* part) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ch = blockIdx.y;
+  if (s >= NS) return;
+  float acc = 0.0f;
+  const int h1 = min(H, (ch + 1) * 256);
+  for (int h = ch * 256; h < h1; ++h)
+    if (rows[(size_t)h * SW + s] >= 0) acc += __expf(logw[h]);
+  part[(size_t)ch * NS + s] = acc;
+}
+__global__ void k_slot_final(int NS, int nch, const float* part, float* r) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= NS) return;
+  float acc = 0.0f;
+  for (int ch = 0; ch < nch; ++ch) acc += part[(size_t)ch * NS + s];
+  r[s] = acc;
+}
+
+__global__ void k_pair_feat(int n, const int32_t* pu, const int32_t* pi, const DInst* inst, const float2* z,
+                            float sig2, const float* slot_r, const int32_t* slot_age, const int32_t* pcnt, float* feat,
+                            int32_t* pair) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int u = pu[p], i = pi[p];
+  const DInst x = inst[u];
+  float f[kNFeat];
+  pair_feature(x, z[i], sig2, slot_r[x.slot], (float)slot_age[x.slot], (float)pcnt[u], f);
+#pragma unroll
+  for (int k = 0; k < kNFeat; ++k) feat[(size_t)p * kNFeat + k] = f[k];
+  pair[2 * (size_t)p] = x.src;
+  pair[2 * (size_t)p + 1] = i;
+}
+
+// network score of every pair; with `remove`, pairs scoring below thr leave the gate
+__global__ __launch_bounds__(256) void k_prop_apply(int n, const int32_t* pu, const int32_t* pi, const DInst* inst,
+                                                    const float2* z, float sig2, const float* slot_r,
+                                                    const int32_t* slot_age, const int32_t* pcnt,
+                                                    const float* params, Norm nm, float thr, int remove, int M,
+                                                    int W, float* phi, uint32_t* gbits, float* logit_out,
+                                                    int32_t* nremoved) {
+  __shared__ float sw[kNParam];
+  load_params(params, sw);
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  bool rm = false;
+  if (p < n) {
+    const int u = pu[p], i = pi[p];
+    const DInst x = inst[u];
+    float f[kNFeat];
+    pair_feature(x, z[i], sig2, slot_r[x.slot], (float)slot_age[x.slot], (float)pcnt[u], f);
+    const float s = mlp_logit(sw, f, nm);
+    if (logit_out) logit_out[p] = s;
+    if (remove && s < thr) {
+      rm = true;
+      phi[(size_t)u * M + i] = -INFINITY;
+      atomicAnd(&gbits[(size_t)u * W + (i >> 5)], ~(1u << (i & 31)));
+    }
+  }
+  const uint64_t b = __ballot(rm);
+  if (lane_id() == 0 && b) atomicAdd(nremoved, (int32_t)__popcll(b));
+}
+
+// ------------------------------------------------------------------ lost mass
+// One block per hypothesis (as the association kernel).  Per cell: the log-sum-exp over all
+// options and, for each threshold j, over the options kept at j (clutter is always kept);
+// per hypothesis: lz_full = log w - gamma (n - n_0) + sum_i (l_i - c_i) and
+// dlt[j] = sum_i (l_ij - l_i), the log of the kept share of the hypothesis' children.
+__global__ __launch_bounds__(256) void k_assoc_lost(int M, int stride, const int32_t* rows, const float* logw,
+                                                    const int32_t* ntrk, float gamma, float lgk, const int32_t* coff,
+                                                    const int32_t* cand, const float* phi, const uint32_t* cmax,
+                                                    int W, const uint32_t* gbits, const int32_t* ppre,
+                                                    const int32_t* poff, const float* plogit, int T, Thr thr, int H,
+                                                    float* lz_full, float* dlt) {
+  extern __shared__ int32_t row[];
+  __shared__ float red[(kMaxThr + 1) * 4];
+  const int h = blockIdx.x;
+  for (int s = threadIdx.x; s < stride; s += blockDim.x) row[s] = rows[(size_t)h * stride + s];
+  __syncthreads();
+  float lsum = 0.0f;
+  float dsum[kMaxThr];
+#pragma unroll
+  for (int j = 0; j < kMaxThr; ++j) dsum[j] = 0.0f;
+  for (int i = threadIdx.x; i < M; i += blockDim.x) {
+    const float c = o2f(cmax[i]);
+    float mx = lgk, mj[kMaxThr];
+#pragma unroll
+    for (int j = 0; j < kMaxThr; ++j) mj[j] = lgk;
+    const int e1 = coff[i + 1];
+    const int w = i >> 5;
+    const uint32_t below = (1u << (i & 31)) - 1u;
+    for (int e = coff[i]; e < e1; ++e) {
+      const int u = row[cand[e]];
+      if (u < 0) continue;
+      const float f = phi[(size_t)u * M + i];
+      if (!(f > -INFINITY)) continue;
+      const float s = plogit[poff[u] + ppre[(size_t)u * W + w] + __popc(gbits[(size_t)u * W + w] & below)];
+      mx = fmaxf(mx, f);
+#pragma unroll
+      for (int j = 0; j < kMaxThr; ++j)
+        if (j < T && s >= thr.t[j]) mj[j] = fmaxf(mj[j], f);
+    }
+    float sm = __expf(lgk - mx), sj[kMaxThr];
+#pragma unroll
+    for (int j = 0; j < kMaxThr; ++j) sj[j] = __expf(lgk - mj[j]);
+    for (int e = coff[i]; e < e1; ++e) {
+      const int u = row[cand[e]];
+      if (u < 0) continue;
+      const float f = phi[(size_t)u * M + i];
+      if (!(f > -INFINITY)) continue;
+      const float s = plogit[poff[u] + ppre[(size_t)u * W + w] + __popc(gbits[(size_t)u * W + w] & below)];
+      sm += __expf(f - mx);
+#pragma unroll
+      for (int j = 0; j < kMaxThr; ++j)
+        if (j < T && s >= thr.t[j]) sj[j] += __expf(f - mj[j]);
+    }
+    const float l = mx + __logf(sm);
+    lsum += l - c;
+#pragma unroll
+    for (int j = 0; j < kMaxThr; ++j)
+      if (j < T) dsum[j] += (mj[j] + __logf(sj[j])) - l;
+  }
+  lsum = wsum(lsum, red);
+#pragma unroll
+  for (int j = 0; j < kMaxThr; ++j)
+    if (j < T) dsum[j] = wsum(dsum[j], red + 4 * (j + 1));
+  if (threadIdx.x == 0) {
+    lz_full[h] = logw[h] - gamma * (float)(ntrk[h] - ntrk[0]) + lsum;
+    for (int j = 0; j < T; ++j) dlt[(size_t)j * H + h] = fminf(dsum[j], 0.0f);
+  }
+}
+
+// one block: lost[j] = sum_h pi_h (1 - exp(dlt[j][h])), pi_h = exp(lz_full[h] - LSE lz_full)
+__global__ __launch_bounds__(1024) void k_lost_final(int H, int T, const float* lz_full, const float* dlt,
+                                                     float* lost) {
+  __shared__ float red[32];
+  float mx = -INFINITY;
+  for (int h = threadIdx.x; h < H; h += blockDim.x) mx = fmaxf(mx, lz_full[h]);
+  for (int d = kWave / 2; d > 0; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d, kWave));
+  if (lane_id() == 0) red[threadIdx.x / kWave] = mx;
+  __syncthreads();
+  mx = -INFINITY;
+  for (int j = 0; j < (int)(blockDim.x / kWave); ++j) mx = fmaxf(mx, red[j]);
+  __syncthreads();
+  float sm = 0.0f;
+  for (int h = threadIdx.x; h < H; h += blockDim.x) sm += __expf(lz_full[h] - mx);
+  sm = wsum(sm, red + 16);
+  const float L = mx + __logf(sm);
+  for (int j = 0; j < T; ++j) {
+    float a = 0.0f;
+    for (int h = threadIdx.x; h < H; h += blockDim.x)
+      a += __expf(lz_full[h] - L) * -expm1f(dlt[(size_t)j * H + h]);
+    a = wsum(a, red + 16);
+    if (threadIdx.x == 0) lost[j] = a;
+  }
+}
+
+// ------------------------------------------------------------------ training targets
+// partial association masses over chunks of 256 hypotheses, one thread per (instance, chunk):
+// pm[ch][p] = sum over h in the chunk holding u of pi_h exp(phi_ui - LSE_hi), pe[ch][u] = sum of pi_h
+__global__ void k_pair_mass(int U, int H, int M, int SW, const DInst* inst, const int32_t* rows, const float* logpi,
+                            const float* lserel, const uint32_t* cmax, const float* phi, const int32_t* poff,
+                            const int32_t* pi, int npairs, float* pm, float* pe) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  const int ch = blockIdx.y;
+  if (u >= U) return;
+  const int slot = inst[u].slot;
+  const int p0 = poff[u], p1 = poff[u + 1];
+  float* out = pm + (size_t)ch * npairs;
+  for (int p = p0; p < p1; ++p) out[p] = 0.0f;
+  float e = 0.0f;
+  const int h1 = min(H, (ch + 1) * 256);
+  for (int h = ch * 256; h < h1; ++h) {
+    if (rows[(size_t)h * SW + slot] != u) continue;
+    const float w = __expf(logpi[h]);
+    e += w;
+    for (int p = p0; p < p1; ++p) {
+      const int i = pi[p];
+      out[p] += w * __expf(phi[(size_t)u * M + i] - (lserel[(size_t)h * M + i] + o2f(cmax[i])));
+    }
+  }
+  pe[(size_t)ch * U + u] = e;
+}
+
+__global__ void k_pair_target(int n, int U, int nch, const int32_t* pu, const float* pm, const float* pe, float* y,
+                              float* w) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int u = pu[p];
+  float m = 0.0f, e = 0.0f;
+  for (int ch = 0; ch < nch; ++ch) {
+    m += pm[(size_t)ch * n + p];
+    e += pe[(size_t)ch * U + u];
+  }
+  w[p] = e;
+  y[p] = e > 0.0f ? fminf(fmaxf(m / e, 0.0f), 1.0f) : 0.0f;
+}
+
+// ------------------------------------------------------------------ network kernels
+__global__ __launch_bounds__(256) void k_mlp_fwd(int n, const float* feat, const float* params, Norm nm,
+                                                 float* logit) {
+  __shared__ float sw[kNParam];
+  load_params(params, sw);
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  float f[kNFeat];
+#pragma unroll
+  for (int k = 0; k < kNFeat; ++k) f[k] = feat[(size_t)p * kNFeat + k];
+  logit[p] = mlp_logit(sw, f, nm);
+}
+
+// One wave per 64 samples: forward, loss, backward to per-sample vectors in LDS, then the
+// wave's partial sums of every gradient entry in sample order.  LDS: parameters | xs[6][65] |
+// h1[64][65] | h2[64][65] | da1[64][65] | da2[64][65] | ds[64] | w l[64] | w[64].
+__global__ __launch_bounds__(64) void k_mlp_fb(int n, const float* feat, const float* y, const float* wt,
+                                               const float* params, Norm nm, float* part) {
+  extern __shared__ float lds[];
+  float* sw = lds;
+  float* Lxs = sw + kNParam + 3;
+  float* Lh1 = Lxs + kNFeat * kLS;
+  float* Lh2 = Lh1 + kNHid * kLS;
+  float* Lda1 = Lh2 + kNHid * kLS;
+  float* Lda2 = Lda1 + kNHid * kLS;
+  float* Lds = Lda2 + kNHid * kLS;
+  float* Lwl = Lds + 64;
+  float* Lw = Lwl + 64;
+  load_params(params, sw);
+  const int s = threadIdx.x;
+  const int q = blockIdx.x * 64 + s;
+  const bool valid = q < n;
+  float x[kNFeat], xs[kNFeat], h1[kNHid], dh1[kNHid];
+#pragma unroll
+  for (int k = 0; k < kNFeat; ++k) x[k] = valid ? feat[(size_t)q * kNFeat + k] : nm.mu[k];
+  const float w = valid ? wt[q] : 0.0f;
+  const float yy = valid ? y[q] : 0.0f;
+  standardise(x, nm, xs);
+#pragma unroll
+  for (int k = 0; k < kNFeat; ++k) Lxs[k * kLS + s] = xs[k];
+  layer1(sw, xs, h1);
+#pragma unroll
+  for (int k = 0; k < kNHid; ++k) Lh1[k * kLS + s] = h1[k];
+  float sc = sw[oB3];
+  for (int j = 0; j < kNHid; ++j) {
+    const float h2 = bf16r(fmaxf(layer2_unit(sw, h1, j), 0.0f));
+    Lh2[j * kLS + s] = h2;
+    sc = fmaf(sw[oW3 + j], h2, sc);
+  }
+  const float sig = 1.0f / (1.0f + expf(-sc));
+  const float ds = w * (sig - yy);
+  const float loss = w * (fmaxf(sc, 0.0f) + log1pf(expf(-fabsf(sc))) - yy * sc);
+#pragma unroll
+  for (int k = 0; k < kNHid; ++k) dh1[k] = 0.0f;
+  for (int j = 0; j < kNHid; ++j) {
+    const float da2 = Lh2[j * kLS + s] > 0.0f ? ds * sw[oW3 + j] : 0.0f;
+    Lda2[j * kLS + s] = da2;
+    const float* wr = sw + oW2 + j * kNHid;
+#pragma unroll
+    for (int k = 0; k < kNHid; ++k) dh1[k] = fmaf(da2, wr[k], dh1[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < kNHid; ++k) Lda1[k * kLS + s] = h1[k] > 0.0f ? dh1[k] : 0.0f;
+  Lds[s] = ds;
+  Lwl[s] = loss;
+  Lw[s] = w;
+  __syncthreads();
+  float* out = part + (size_t)blockIdx.x * kPartW;
+  for (int t = s; t < kPartW; t += 64) {
+    float acc = 0.0f;
+    if (t < oB1) {
+      const float* a = Lda1 + (t / kNFeat) * kLS;
+      const float* b = Lxs + (t % kNFeat) * kLS;
+      for (int r = 0; r < 64; ++r) acc = fmaf(a[r], b[r], acc);
+    } else if (t < oW2) {
+      const float* a = Lda1 + (t - oB1) * kLS;
+      for (int r = 0; r < 64; ++r) acc += a[r];
+    } else if (t < oB2) {
+      const int j = (t - oW2) / kNHid, k = (t - oW2) % kNHid;
+      const float* a = Lda2 + j * kLS;
+      const float* b = Lh1 + k * kLS;
+      for (int r = 0; r < 64; ++r) acc = fmaf(a[r], b[r], acc);
+    } else if (t < oW3) {
+      const float* a = Lda2 + (t - oB2) * kLS;
+      for (int r = 0; r < 64; ++r) acc += a[r];
+    } else if (t < oB3) {
+      const float* b = Lh2 + (t - oW3) * kLS;
+      for (int r = 0; r < 64; ++r) acc = fmaf(Lds[r], b[r], acc);
+    } else if (t == oB3) {
+      for (int r = 0; r < 64; ++r) acc += Lds[r];
+    } else if (t == kNParam) {
+      for (int r = 0; r < 64; ++r) acc += Lw[r];
+    } else {
+      for (int r = 0; r < 64; ++r) acc += Lwl[r];
+    }
+    out[t] = acc;
+  }
+}
+
+// gradient and loss: sums of the partials in block order, divided by the sum of the weights
+__global__ void k_mlp_reduce(int nblk, const float* part, float* grad, float* loss) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t > kNParam) return;
+  float W = 0.0f, a = 0.0f;
+  const int col = t < kNParam ? t : kNParam + 1;
+  for (int b = 0; b < nblk; ++b) {
+    W += part[(size_t)b * kPartW + kNParam];
+    a += part[(size_t)b * kPartW + col];
+  }
+  if (t < kNParam) grad[t] = a / W;
+  else *loss = a / W;
+}
+
+__global__ void k_adam(int n, float* th, float* m, float* v, const float* g, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const float gg = g[q];
+  const float mm = b1 * m[q] + (1.0f - b1) * gg;
+  const float vv = b2 * v[q] + (1.0f - b2) * gg * gg;
+  m[q] = mm;
+  v[q] = vv;
+  th[q] -= lr * (mm * c1) / (sqrtf(vv * c2) + eps);
+}
+
+// ------------------------------------------------------------------ host side
+namespace {
+template <class T> T read_one(hipStream_t s, const T* p) {
+  T v;
+  GLMB_HIP(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipStreamSynchronize(s));
+  return v;
+}
+
+Norm norm_of(const float* nm) {
+  Norm n;
+  for (int k = 0; k < kNFeat; ++k) {
+    n.mu[k] = nm[k];
+    n.sd[k] = nm[kNFeat + k];
+  }
+  return n;
+}
+
+// label existence, label ages, and the compacted pair list of the current gate; returns the
+// pair count
+int prepare_pairs(Ctx& c, int k, int M) {
+  hipStream_t s = c.s;
+  const int T = 256;
+  const int H = c.nhyp, U = c.ninst, NS = c.nslot, SW = c.stride;
+  const int W = std::max(1, (M + 31) / 32);
+  const int nch = cdiv(H, 256);
+  float* part = need<float>(c.slot_part, (int64_t)nch * std::max(NS, 1));
+  float* r = need<float>(c.slot_r, NS + 1);
+  if (NS > 0) {
+    hipLaunchKernelGGL(k_slot_part, dim3(cdiv(NS, T), nch), dim3(T), 0, s, H, NS, SW, c.rows.as<int32_t>(),
+                       c.logw.as<float>(), part);
+    GLMB_HIP(hipGetLastError());
+    GLMB_LAUNCH(k_slot_final, cdiv(NS, T), T, 0, s, NS, nch, part, r);
+  }
+  c.h_age.resize(NS + 1);
+  for (int j = 0; j < NS; ++j) c.h_age[j] = k - c.slot_lab[j].first;
+  int32_t* age = need<int32_t>(c.slot_age, NS + 1);
+  if (NS) GLMB_HIP(hipMemcpyAsync(age, c.h_age.data(), NS * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  int32_t* cnt = need<int32_t>(c.pcnt, U + 1);
+  int32_t* off = need<int32_t>(c.poff, U + 1);
+  int32_t* ppre = need<int32_t>(c.ppre, (int64_t)U * W);
+  GLMB_LAUNCH(k_pair_count, cdiv(U, T), T, 0, s, U, W, c.gbits.as<uint32_t>(), cnt, ppre);
+  scan_excl(cnt, off, U, off + U, c.tmp, s);
+  const int n = U > 0 ? read_one(s, off + U) : 0;
+  int32_t* pu = need<int32_t>(c.pu, n);
+  int32_t* pi = need<int32_t>(c.pi, n);
+  GLMB_LAUNCH(k_pair_list, cdiv(U, T), T, 0, s, U, W, c.gbits.as<uint32_t>(), off, pu, pi);
+  return n;
+}
+
+// network scores of the listed pairs (into c.plogit), optionally removing the low ones
+void score_pairs(Ctx& c, int n, int M, bool remove) {
+  const int W = std::max(1, (M + 31) / 32);
+  float* logit = need<float>(c.plogit, n);
+  int32_t* nremoved = c.scal.as<int32_t>() + 18;
+  GLMB_LAUNCH(k_prop_apply, cdiv(n, 256), 256, 0, c.s, n, c.pu.as<int32_t>(), c.pi.as<int32_t>(),
+              (const DInst*)c.inst.p, c.z.as<float2>(), c.p.sigma_z * c.p.sigma_z, c.slot_r.as<float>(),
+              c.slot_age.as<int32_t>(), c.pcnt.as<int32_t>(), c.prop_w.as<float>(), norm_of(c.prop_norm),
+              c.prop_thr, remove ? 1 : 0, M, W, c.phi.as<float>(), c.gbits.as<uint32_t>(), logit, nremoved);
+}
+}  // namespace
+
+void proposal_apply(Ctx& c, int k, int M) {
+  trace(c, "update.proposal");
+  const int n = prepare_pairs(c, k, M);
+  score_pairs(c, n, M, true);
+}
+
+void proposal_lost(Ctx& c, int k, const float* zin, int M, const float* thr_prob, int T, double* lost) {
+  if (T < 1 || T > kMaxThr) throw Error{GLMB_E_ARG, "1 <= T <= 16 thresholds"};
+  Thr thr{};
+  for (int j = 0; j < T; ++j) {
+    const double t = thr_prob[j];
+    if (!(t > 0.0 && t < 1.0)) throw Error{GLMB_E_ARG, "thresholds must lie in (0, 1)"};
+    thr.t[j] = (float)std::log(t / (1.0 - t));
+  }
+  hipStream_t s = c.s;
+  const int H = c.nhyp, SW = c.stride;
+  gate_scores(c, zin, M);
+  gate_lists(c, M);
+  const int n = prepare_pairs(c, k, M);
+  score_pairs(c, n, M, false);
+  float* lzf = need<float>(c.lz_t, (int64_t)(T + 1) * H + 32);
+  float* dlt = lzf + H;
+  float* out = dlt + (size_t)T * H;
+  const int W = std::max(1, (M + 31) / 32);
+  GLMB_LAUNCH(k_assoc_lost, H, 256, SW * sizeof(int32_t), s, M, SW, c.rows.as<int32_t>(), c.logw.as<float>(),
+              c.ntrk.as<int32_t>(), c.p.det_rate, logf(c.p.clutter_density), c.coff.as<int32_t>(),
+              c.cand.as<int32_t>(), c.phi.as<float>(), c.cmax.as<uint32_t>(), W, c.gbits.as<uint32_t>(),
+              c.ppre.as<int32_t>(), c.poff.as<int32_t>(), c.plogit.as<float>(), T, thr, H, lzf, dlt);
+  GLMB_LAUNCH(k_lost_final, 1, 1024, 0, s, H, T, lzf, dlt, out);
+  float h[kMaxThr];
+  GLMB_HIP(hipMemcpyAsync(h, out, T * sizeof(float), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipStreamSynchronize(s));
+  for (int j = 0; j < T; ++j) lost[j] = h[j];
+  c.last_M = -1;  // the update diagnostics buffers no longer describe an update
+}
+
+int proposal_features(Ctx& c, int k, const float* zin, int M, int cap, float* feat, int32_t* pair, float* target,
+                      float* weight) {
+  hipStream_t s = c.s;
+  const int T = 256;
+  const int H = c.nhyp, U = c.ninst, SW = c.stride;
+  gate_scores(c, zin, M);
+  gate_lists(c, M);
+  assoc_norm(c, M);
+  c.last_M = -1;
+  const int n = prepare_pairs(c, k, M);
+  if (n > cap) return n;
+  if (n == 0) return 0;
+  GLMB_LAUNCH(k_pair_feat, cdiv(n, T), T, 0, s, n, c.pu.as<int32_t>(), c.pi.as<int32_t>(), (const DInst*)c.inst.p,
+              c.z.as<float2>(), c.p.sigma_z * c.p.sigma_z, c.slot_r.as<float>(), c.slot_age.as<int32_t>(),
+              c.pcnt.as<int32_t>(), feat, pair);
+  const int nch = cdiv(H, 256);
+  float* pm = need<float>(c.pm_part, (int64_t)nch * n);
+  float* pe = need<float>(c.pe_part, (int64_t)nch * std::max(U, 1));
+  hipLaunchKernelGGL(k_pair_mass, dim3(cdiv(U, T), nch), dim3(T), 0, s, U, H, M, SW, (const DInst*)c.inst.p,
+                     c.rows.as<int32_t>(), c.diag_logpi.as<float>(), c.lserel.as<float>(), c.cmax.as<uint32_t>(),
+                     c.phi.as<float>(), c.poff.as<int32_t>(), c.pi.as<int32_t>(), n, pm, pe);
+  GLMB_HIP(hipGetLastError());
+  GLMB_LAUNCH(k_pair_target, cdiv(n, T), T, 0, s, n, U, nch, c.pu.as<int32_t>(), pm, pe, target, weight);
+  GLMB_HIP(hipStreamSynchronize(s));
+  return n;
+}
+
+void mlp_forward(Ctx& c, const float* params, const float* norm, const float* feat, int n, float* logit) {
+  GLMB_LAUNCH(k_mlp_fwd, cdiv(n, 256), 256, 0, c.s, n, feat, params, norm_of(norm), logit);
+}
+
+void mlp_grad(Ctx& c, const float* params, const float* norm, const float* feat, const float* y, const float* w,
+              int n, float* grad, float* loss) {
+  const int nblk = std::max(1, cdiv(n, 64));
+  float* part = need<float>(c.mlp_part, (int64_t)nblk * kPartW);
+  const size_t lds = (size_t)(kNParam + 3 + kNFeat * kLS + 4 * kNHid * kLS + 3 * 64) * sizeof(float);
+  static_assert((kNParam + 3 + kNFeat * kLS + 4 * kNHid * kLS + 3 * 64) * 4 <= 160 * 1024, "LDS of k_mlp_fb");
+  GLMB_HIP(hipFuncSetAttribute((const void*)k_mlp_fb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  GLMB_LAUNCH(k_mlp_fb, nblk, 64, lds, c.s, n, feat, y, w, params, norm_of(norm), part);
+  GLMB_LAUNCH(k_mlp_reduce, cdiv(kNParam + 1, 256), 256, 0, c.s, nblk, part, grad, loss);
+}
+
+void mlp_adam(Ctx& c, float* params, float* m, float* v, const float* g, int t, float lr, float b1, float b2,
+              float eps) {
+  const float c1 = (float)(1.0 / (1.0 - std::pow((double)b1, (double)t)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow((double)b2, (double)t)));
+  GLMB_LAUNCH(k_adam, cdiv(kNParam, 256), 256, 0, c.s, kNParam, params, m, v, g, lr, b1, b2, eps, c1, c2);
+}
+
+}  // namespace glmb

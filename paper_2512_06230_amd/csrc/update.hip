@@ -822,52 +822,29 @@ void check_err(hipStream_t s, const uint32_t* errf) {
 }
 }  // namespace
 
-void stage_update(Ctx& c, int k, const float* zin, int M) {
-  (void)k;
+// U0 + U1 scores: detections, gate bits and Eq. 2 entries of every (instance, detection) pair.
+// Scalars: see stage_update.
+void gate_scores(Ctx& c, const float* zin, int M) {
   hipStream_t s = c.s;
   const int T = 256;
-  const int H = c.nhyp, U = c.ninst, NS = c.nslot, SW = c.stride;
+  const int U = c.ninst;
   const glmb_params& p = c.p;
   const float sig2 = p.sigma_z * p.sigma_z;
   const float lgk = logf(p.clutter_density);
   const float lgc = (float)(std::log((double)p.det_rate) - std::log(2.0 * M_PI));
   const int W = std::max(1, (M + 31) / 32);
-  // scalars: [0] errf, [1..2] ngated (u64), [3..4] nopts (u64), [8] logZ', [9] t0, [10] nkeep,
-  // [11] retained, [12..] small counters
   int32_t* scal = need<int32_t>(c.scal, 64);
   uint32_t* errf = (uint32_t*)scal;
   unsigned long long* ngated = (unsigned long long*)(scal + 2);
-  unsigned long long* nopts = (unsigned long long*)(scal + 4);
-  float* lz = (float*)(scal + 8);
-  float* t0 = (float*)(scal + 9);
-  int32_t* nkeep = scal + 10;
-  float* retained = (float*)(scal + 11);
-  int32_t* tot = scal + 12;
-  int32_t* nb_out = scal + 13;
-  unsigned long long* ndense = (unsigned long long*)(scal + 16);
   GLMB_HIP(hipMemsetAsync(scal, 0, 64 * sizeof(int32_t), s));
-
-  c.stats = glmb_step_stats{};
-  c.stats.n_hyp_in = H;
-  c.stats.n_meas = M;
-  c.stats.n_inst_in = U;
-  c.stats.n_labels = NS;
-
-  // ---- U0: detections
-  trace(c, "update.begin", H, M);
   float2* z = need<float2>(c.z, M);
   GLMB_LAUNCH(k_z_in, cdiv(M, T), T, 0, s, zin, M, z, errf);
-
-  // ---- U1: gate and score
-  trace(c, "update.U1");
-  c.mark(0);
   uint32_t* cmax = need<uint32_t>(c.cmax, M);
   {
-    uint32_t init;
     float fl = lgk;
     uint32_t uu;
     std::memcpy(&uu, &fl, 4);
-    init = (uu & 0x80000000u) ? ~uu : (uu | 0x80000000u);
+    const uint32_t init = (uu & 0x80000000u) ? ~uu : (uu | 0x80000000u);
     GLMB_LAUNCH(k_fill_u32, cdiv(M, T), T, 0, s, cmax, M, init);
   }
   uint32_t* gbits = need<uint32_t>(c.gbits, (int64_t)U * W);
@@ -876,7 +853,22 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     const int64_t waves = (int64_t)U * cdiv(M, kWave);
     GLMB_LAUNCH(k_gate, cdiv(waves * kWave, T), T, 0, s, (const DInst*)c.inst.p, U, z, M, W, sig2, p.gate_d2, lgc,
                 gbits, phi, cmax, ngated);
+  } else if (U > 0) {
+    GLMB_LAUNCH(k_fill_u32, cdiv((int64_t)U * W, T), T, 0, s, gbits, U * W, 0u);  // no detections: nothing gated
   }
+}
+
+// U1 lists from the gate bits: per-label gated detection lists and per-detection candidate
+// label slots.  Sets c.LW (detection-set mask width in words).
+void gate_lists(Ctx& c, int M) {
+  hipStream_t s = c.s;
+  const int T = 256;
+  const int U = c.ninst, NS = c.nslot;
+  const int W = std::max(1, (M + 31) / 32);
+  int32_t* scal = c.scal.as<int32_t>();
+  uint32_t* errf = (uint32_t*)scal;
+  int32_t* tot = scal + 12;
+  const uint32_t* gbits = c.gbits.as<uint32_t>();
   int32_t* beg = need<int32_t>(c.inst_beg, NS + 1);
   GLMB_LAUNCH(k_inst_beg, cdiv(NS + 1, T), T, 0, s, (const DInst*)c.inst.p, U, NS, beg);
   uint32_t* lbits = need<uint32_t>(c.lbits, (int64_t)NS * W);
@@ -904,6 +896,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
                                    (int)lds_need));
     }
   }
+  c.LW = LW;
   int32_t* lmeas = need<int32_t>(c.lmeas, nl);
   if (M > 0) GLMB_LAUNCH(k_label_list, cdiv((int64_t)NS * W, T), T, 0, s, lbits, lpre, loff, NS, W, lmeas);
   int32_t* ccnt = need<int32_t>(c.ccnt, M + 1);
@@ -915,9 +908,19 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   int32_t* cand = need<int32_t>(c.cand, ncand);
   GLMB_LAUNCH(k_cand, cdiv((int64_t)M * kWave, T), T, 0, s, lbits, NS, W, M, (const int32_t*)coff, ccnt, cand);
   check_err(s, errf);
+  trace(c, "update.lists", ncand, NS);
+}
 
-  // ---- U2: per (hypothesis, detection) normalisers
-  trace(c, "update.U2", ncand, NS);
+// U2 on the current lists: per-cell normalisers, per-hypothesis B'_h and log Z'_h, log Z'.
+void assoc_norm(Ctx& c, int M) {
+  hipStream_t s = c.s;
+  const int H = c.nhyp, SW = c.stride;
+  const glmb_params& p = c.p;
+  const float lgk = logf(p.clutter_density);
+  int32_t* scal = c.scal.as<int32_t>();
+  unsigned long long* nopts = (unsigned long long*)(scal + 4);
+  float* lz = (float*)(scal + 8);
+  unsigned long long* ndense = (unsigned long long*)(scal + 16);
   const int64_t HM = (int64_t)H * M;
   int16_t* best16 = need<int16_t>(c.best16, HM);
   float* dev1 = need<float>(c.dev1, HM);
@@ -926,12 +929,74 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   float* lzprime = need<float>(c.lzprime, H);
   c.mark(1);
   GLMB_LAUNCH(k_assoc, H, 256, SW * sizeof(int32_t), s, M, SW, c.rows.as<int32_t>(), c.logw.as<float>(),
-              c.ntrk.as<int32_t>(), p.det_rate, lgk, coff, cand, phi, cmax, best16, dev1, lserel, bprime, lzprime,
-              nopts, ndense);
+              c.ntrk.as<int32_t>(), p.det_rate, lgk, c.coff.as<int32_t>(), c.cand.as<int32_t>(), c.phi.as<float>(),
+              c.cmax.as<uint32_t>(), best16, dev1, lserel, bprime, lzprime, nopts, ndense);
   c.mark(2);
   float* dbest = need<float>(c.diag_best, H);
   float* dlogpi = need<float>(c.diag_logpi, H);
   GLMB_LAUNCH(k_norm, 1, 1024, 0, s, H, bprime, lzprime, lz, dbest, dlogpi);
+}
+
+void stage_update(Ctx& c, int k, const float* zin, int M) {
+  hipStream_t s = c.s;
+  const int T = 256;
+  const int H = c.nhyp, U = c.ninst, NS = c.nslot, SW = c.stride;
+  const glmb_params& p = c.p;
+  const float sig2 = p.sigma_z * p.sigma_z;
+  const float lgk = logf(p.clutter_density);
+  // scalars: [0] errf, [2..3] ngated (u64), [4..5] nopts (u64), [8] logZ', [9] t0, [10] nkeep,
+  // [11] retained, [12] scratch total, [13] births, [14] exceptions, [16..17] dense triples (u64),
+  // [18] pairs removed by the proposal
+  c.stats = glmb_step_stats{};
+  c.stats.n_hyp_in = H;
+  c.stats.n_meas = M;
+  c.stats.n_inst_in = U;
+  c.stats.n_labels = NS;
+  double lost = 0.0;
+  if (c.prop_on && c.prop_measure) {
+    // posterior mass the proposal removes, measured on the full association space first
+    proposal_lost(c, k, zin, M, &c.prop_t, 1, &lost);
+  }
+
+  // ---- U0 + U1: detections, gate, scores
+  trace(c, "update.begin", H, M);
+  c.mark(0);
+  gate_scores(c, zin, M);
+  int32_t* scal = c.scal.as<int32_t>();
+  uint32_t* errf = (uint32_t*)scal;
+  unsigned long long* ngated = (unsigned long long*)(scal + 2);
+  unsigned long long* nopts = (unsigned long long*)(scal + 4);
+  float* lz = (float*)(scal + 8);
+  float* t0 = (float*)(scal + 9);
+  int32_t* nkeep = scal + 10;
+  float* retained = (float*)(scal + 11);
+  int32_t* tot = scal + 12;
+  int32_t* nb_out = scal + 13;
+  unsigned long long* ndense = (unsigned long long*)(scal + 16);
+  (void)ngated;
+  (void)nopts;
+  (void)ndense;
+  float2* z = c.z.as<float2>();
+  uint32_t* cmax = c.cmax.as<uint32_t>();
+  float* phi = c.phi.as<float>();
+  if (c.prop_on && M > 0) proposal_apply(c, k, M);
+  gate_lists(c, M);
+  const int LW = c.LW;
+  int32_t* loff = c.loff.as<int32_t>();
+  int32_t* llen = c.llen.as<int32_t>();
+  int32_t* lmeas = c.lmeas.as<int32_t>();
+  int32_t* coff = c.coff.as<int32_t>();
+  int32_t* cand = c.cand.as<int32_t>();
+
+  // ---- U2: per (hypothesis, detection) normalisers
+  trace(c, "update.U2");
+  assoc_norm(c, M);
+  const int64_t HM = (int64_t)H * M;
+  int16_t* best16 = c.best16.as<int16_t>();
+  float* dev1 = c.dev1.as<float>();
+  float* lserel = c.lserel.as<float>();
+  float* bprime = c.bprime.as<float>();
+  float* lzprime = c.lzprime.as<float>();
 
   // ---- U3: lower bound of the cut, deviation items, exact selection
   trace(c, "update.U3");
@@ -1126,8 +1191,8 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   trace(c, "update.stats");
   c.mark(5);
   check_err(s, errf);
-  int32_t hs[18];
-  GLMB_HIP(hipMemcpyAsync(hs, scal, 18 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  int32_t hs[19];
+  GLMB_HIP(hipMemcpyAsync(hs, scal, 19 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   GLMB_HIP(hipStreamSynchronize(s));
   uint64_t ng, no;
   std::memcpy(&ng, hs + 2, 8);
@@ -1164,6 +1229,8 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   c.stats.search_levels = sel.levels;
   c.stats.n_births = c.nbirth;
   c.stats.retained_mass = std::exp((double)ret);
+  c.stats.lost_mass = lost;
+  c.stats.pairs_removed = hs[18];
   GLMB_HIP(hipStreamSynchronize(s));
   if (c.ev_ok) {
     const int a[6] = {0, 1, 2, 3, 4, 0}, b[6] = {1, 2, 3, 4, 5, 5};

@@ -18,7 +18,10 @@ GLMB_OK, GLMB_E_ARG, GLMB_E_CAPACITY, GLMB_E_NOMEM, GLMB_E_DEVICE, GLMB_E_STATE 
 
 EXPORTS = ["glmb_status_string", "glmb_last_error", "glmb_create", "glmb_destroy", "glmb_import_state",
            "glmb_state_sizes", "glmb_export_state", "glmb_predict", "glmb_update", "glmb_truncate",
-           "glmb_estimate", "glmb_stats", "glmb_update_diag", "glmb_update_theta"]
+           "glmb_estimate", "glmb_stats", "glmb_update_diag", "glmb_update_theta", "glmb_set_proposal",
+           "glmb_pair_features", "glmb_proposal_lost", "glmb_mlp_forward", "glmb_mlp_grad", "glmb_mlp_adam"]
+
+MLP_NPARAM, MLP_NFEAT = 4673, 6
 
 
 class Params(ctypes.Structure):
@@ -48,7 +51,7 @@ class StepStats(ctypes.Structure):
                 ("dense_triples", ctypes.c_int64), ("search_nodes", ctypes.c_int32),
                 ("search_levels", ctypes.c_int32), ("n_births", ctypes.c_int32),
                 ("retained_mass", ctypes.c_double), ("lost_mass", ctypes.c_double),
-                ("stage_ms", ctypes.c_float * 6)]
+                ("pairs_removed", ctypes.c_int32), ("stage_ms", ctypes.c_float * 6)]
 
 
 _lib = None
@@ -79,6 +82,14 @@ def load_library(path: str = LIB_PATH):
     L.glmb_stats.argtypes = [vp, ctypes.POINTER(StepStats)]
     L.glmb_update_diag.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _F, _F, _F]
     L.glmb_update_theta.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, _I]
+    L.glmb_set_proposal.argtypes = [vp, vp, _F, ctypes.c_float, ctypes.c_int32]
+    L.glmb_pair_features.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_int32, vp, vp, vp, vp, _I]
+    L.glmb_proposal_lost.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_int32, ctypes.c_int32, _F,
+                                     ctypes.POINTER(ctypes.c_double)]
+    L.glmb_mlp_forward.argtypes = [vp, vp, _F, vp, ctypes.c_int32, vp]
+    L.glmb_mlp_grad.argtypes = [vp, vp, _F, vp, vp, vp, ctypes.c_int32, vp, vp]
+    L.glmb_mlp_adam.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                ctypes.c_float]
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_int if name not in ("glmb_status_string", "glmb_last_error") \
             else ctypes.c_char_p
@@ -228,3 +239,110 @@ class Tracker:
         th = np.zeros((n_hyp, max(M, 1)), np.int32)
         self._check(self._L.glmb_update_theta(self._ctx, int(n_hyp), int(M), _ip(th)), "glmb_update_theta")
         return th[:, :M]
+
+    # ---- learned pair proposal
+    def to_device(self, a, dtype=np.float32):
+        """A CUDA tensor copy of a host array."""
+        return self.torch.as_tensor(np.ascontiguousarray(np.asarray(a, dtype)), device="cuda")
+
+    @staticmethod
+    def to_host(t) -> np.ndarray:
+        return t.detach().cpu().numpy()
+
+    def _dev(self, a, shape, dtype=None):
+        t = self.torch
+        dtype = dtype or t.float32
+        if not isinstance(a, t.Tensor):
+            a = t.as_tensor(np.ascontiguousarray(a), device="cuda")
+        if not (a.is_cuda and a.dtype == dtype and a.is_contiguous() and tuple(a.shape) == tuple(shape)):
+            raise ValueError("expected a contiguous CUDA %s tensor of shape %s" % (dtype, tuple(shape)))
+        return a
+
+    def _z(self, z):
+        t = self.torch
+        if not isinstance(z, t.Tensor):
+            z = t.as_tensor(np.ascontiguousarray(np.asarray(z, np.float32).reshape(-1, 2)), device="cuda")
+        return self._dev(z, (z.shape[0], 2))
+
+    @staticmethod
+    def _norm(norm):
+        n = np.ascontiguousarray(np.asarray(norm, np.float32).reshape(12))
+        return n
+
+    def set_proposal(self, params, norm, threshold: float, measure: bool = False):
+        """params: CUDA float32 [4673] (None disables the proposal); norm: 12 floats."""
+        if params is None:
+            self._check(self._L.glmb_set_proposal(self._ctx, None, None, 0.5, 0), "glmb_set_proposal")
+            return
+        params = self._dev(params, (MLP_NPARAM,))
+        n = self._norm(norm)
+        self._check(self._L.glmb_set_proposal(self._ctx, ctypes.c_void_p(params.data_ptr()), _fp(n),
+                                              float(threshold), int(bool(measure))), "glmb_set_proposal")
+
+    def pair_features(self, k: int, z, cap: int = 0):
+        """Training data of the current predicted state: (feat [n,6], pair [n,2], target [n],
+        weight [n]) as CUDA tensors."""
+        t = self.torch
+        z = self._z(z)
+        cap = max(int(cap), getattr(self, "_pair_cap", 4096))
+        for _ in range(2):
+            feat = t.empty((cap, MLP_NFEAT), dtype=t.float32, device="cuda")
+            pair = t.empty((cap, 2), dtype=t.int32, device="cuda")
+            y = t.empty(cap, dtype=t.float32, device="cuda")
+            w = t.empty(cap, dtype=t.float32, device="cuda")
+            n = ctypes.c_int32()
+            st = self._L.glmb_pair_features(self._ctx, int(k), ctypes.c_void_p(z.data_ptr()), int(z.shape[0]), cap,
+                                            ctypes.c_void_p(feat.data_ptr()), ctypes.c_void_p(pair.data_ptr()),
+                                            ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(w.data_ptr()),
+                                            ctypes.byref(n))
+            if st == GLMB_E_CAPACITY and n.value > cap:
+                cap = self._pair_cap = n.value
+                continue
+            self._check(st, "glmb_pair_features")
+            m = n.value
+            return feat[:m], pair[:m], y[:m], w[:m]
+        raise GlmbError(GLMB_E_CAPACITY, "glmb_pair_features: pair count changed between calls")
+
+    def proposal_lost(self, k: int, z, thresholds) -> np.ndarray:
+        z = self._z(z)
+        thr = np.ascontiguousarray(np.asarray(thresholds, np.float32).reshape(-1))
+        out = np.zeros(len(thr), np.float64)
+        self._check(self._L.glmb_proposal_lost(self._ctx, int(k), ctypes.c_void_p(z.data_ptr()), int(z.shape[0]),
+                                               len(thr), _fp(thr), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                    "glmb_proposal_lost")
+        return out
+
+    def mlp_forward(self, params, norm, feat):
+        t = self.torch
+        params = self._dev(params, (MLP_NPARAM,))
+        feat = self._dev(feat, (feat.shape[0], MLP_NFEAT))
+        n = self._norm(norm)
+        out = t.empty(feat.shape[0], dtype=t.float32, device="cuda")
+        self._check(self._L.glmb_mlp_forward(self._ctx, ctypes.c_void_p(params.data_ptr()), _fp(n),
+                                             ctypes.c_void_p(feat.data_ptr()), int(feat.shape[0]),
+                                             ctypes.c_void_p(out.data_ptr())), "glmb_mlp_forward")
+        return out
+
+    def mlp_grad(self, params, norm, feat, y, w):
+        """(grad [4673], loss [1]) CUDA tensors of the weighted cross-entropy."""
+        t = self.torch
+        params = self._dev(params, (MLP_NPARAM,))
+        feat = self._dev(feat, (feat.shape[0], MLP_NFEAT))
+        y = self._dev(y, (feat.shape[0],))
+        w = self._dev(w, (feat.shape[0],))
+        n = self._norm(norm)
+        g = t.empty(MLP_NPARAM, dtype=t.float32, device="cuda")
+        loss = t.empty(1, dtype=t.float32, device="cuda")
+        self._check(self._L.glmb_mlp_grad(self._ctx, ctypes.c_void_p(params.data_ptr()), _fp(n),
+                                          ctypes.c_void_p(feat.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                          ctypes.c_void_p(w.data_ptr()), int(feat.shape[0]),
+                                          ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(loss.data_ptr())),
+                    "glmb_mlp_grad")
+        return g, loss
+
+    def mlp_adam(self, params, m, v, g, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8):
+        """One Adam step, in place on params, m and v (CUDA float32 [4673] each)."""
+        ps = [self._dev(a, (MLP_NPARAM,)) for a in (params, m, v, g)]
+        self._check(self._L.glmb_mlp_adam(self._ctx, *[ctypes.c_void_p(a.data_ptr()) for a in ps], int(step),
+                                          float(lr), float(beta1), float(beta2), float(eps)), "glmb_mlp_adam")

@@ -44,3 +44,36 @@ def test_status_strings_without_gpu():
     assert L.glmb_create(None, 0, None, None) == glmb.GLMB_E_ARG
     assert L.glmb_destroy(None) == glmb.GLMB_E_ARG
     assert L.glmb_update(None, 0, None, 0) == glmb.GLMB_E_ARG
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """sizeof and field offsets of the ABI structs, from a C program built against the header."""
+    import subprocess
+    from paper_2512_06230_amd import glmb
+    src = tmp_path / "sz.c"
+    fields = {"glmb_params": glmb.Params, "glmb_state_host": glmb.StateHost, "glmb_step_stats": glmb.StepStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "glmb.h"', "int main(void) {"]
+    for cname, py in fields.items():
+        lines.append('printf("%s %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('printf("%s.%s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("return 0; }")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = dict(l.split() for l in subprocess.check_output([str(exe)]).decode().splitlines())
+    for cname, py in fields.items():
+        assert int(out[cname]) == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert int(out["%s.%s" % (cname, f)]) == getattr(py, f).offset, (cname, f)
+
+
+def test_new_entry_points_reject_null_context():
+    from paper_2512_06230_amd import glmb
+    L = glmb.load_library()
+    assert L.glmb_set_proposal(None, None, None, 0.5, 0) == glmb.GLMB_E_ARG
+    assert L.glmb_pair_features(None, 0, None, 0, 0, None, None, None, None, None) == glmb.GLMB_E_ARG
+    assert L.glmb_proposal_lost(None, 0, None, 0, 1, None, None) == glmb.GLMB_E_ARG
+    assert L.glmb_mlp_forward(None, None, None, None, 0, None) == glmb.GLMB_E_ARG
+    assert L.glmb_mlp_grad(None, None, None, None, None, None, 1, None, None) == glmb.GLMB_E_ARG
+    assert L.glmb_mlp_adam(None, None, None, None, None, 1, 1e-3, 0.9, 0.999, 1e-8) == glmb.GLMB_E_ARG

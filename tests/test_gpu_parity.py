@@ -37,20 +37,29 @@ def _update_both(state, z, p, k=0):
     d_o = o.diag(len(st["hyp_logw"]))
     g = _tracker(p)
     g.import_state(st)
+    near = pt.near_gate_instances(st, z, p["sigma_z"], p["gate_d2"])
+    if near:
+        # keep only the instances whose gate decisions really differ between FP32 and FP64
+        pr = o.pairs()
+        ref = set(zip(pr["u"].tolist(), pr["i"].tolist()))
+        _, pair, _, _ = g.pair_features(k, z)
+        got = set(map(tuple, g.to_host(pair).tolist()))
+        near = {u for u, _ in ref ^ got}
+    g.near = near
     g.update(k, z)
     out_g = g.export_state()
     M = np.asarray(z).reshape(-1, 2).shape[0]
     th_g = g.theta(len(out_g["hyp_logw"]), M)
     d_g = g.diag(len(st["hyp_logw"]), M)
     stats = g.stats()
+    stats["near"] = g.near
     g.close()
     return st, out_o, d_o, out_g, th_g, d_g, stats
 
 
 def check_update(state, z, p, k=0, full_density=True):
     st, out_o, d_o, out_g, th_g, d_g, stats = _update_both(state, z, p, k)
-    near = pt.near_gate_instances(st, z, p["sigma_z"], p["gate_d2"])
-    skip = pt.parents_with(st, near)
+    skip = pt.parents_with(st, stats["near"])
     keep = np.array([h not in skip for h in range(len(st["hyp_logw"]))])
     if keep.any():
         assert np.all(np.abs(d_g["best"][keep] - d_o["best"][keep]) <= pt.tol(d_o["best"][keep])), "best child"
