@@ -15,8 +15,6 @@
 namespace glmb {
 
 constexpr int kWave = 64;
-constexpr int kLMax = 128;          // detections gated with one label (mask width)
-constexpr int kMaxOpts = 64;        // options of one (hypothesis, detection) cell
 constexpr int kMaxDepth = 48;       // deviations of one child
 
 struct Error {

@@ -19,7 +19,7 @@
 
 namespace glmb {
 
-enum : uint32_t { ERR_BIRTH = 1, ERR_OPTS = 2, ERR_DEPTH = 4, ERR_NAN = 8, ERR_COLL = 16 };
+enum : uint32_t { ERR_BIRTH = 1, ERR_DEPTH = 4, ERR_NAN = 8, ERR_COLL = 16 };
 
 // ------------------------------------------------------------------ U0 / U1
 __global__ void k_z_in(const float* zin, int M, float2* z, uint32_t* errf) {
@@ -259,61 +259,57 @@ __global__ void k_cell_write(int64_t n, const int32_t* flags, const int32_t* pre
   if (c < n && flags[c]) cells[pre[c]] = (int32_t)c;
 }
 
-// options of cell (h, i) ordered by (phi desc, key asc); clutter has key -1
-__device__ int cell_options(int h, int i, int M, int stride, const int32_t* rows, const int32_t* coff,
-                            const int32_t* cand, const float* phi, float lgk, float* f, int* key, uint32_t* errf) {
-  int n = 1;
-  f[0] = lgk;
-  key[0] = -1;
-  for (int e = coff[i]; e < coff[i + 1]; ++e) {
-    const int s = cand[e];
-    const int u = rows[(size_t)h * stride + s];
-    if (u < 0) continue;
-    const float v = phi[(size_t)u * M + i];
-    if (!(v > -INFINITY)) continue;
-    if (n >= kMaxOpts) {
-      atomicOr(errf, ERR_OPTS);
-      break;
-    }
-    // insertion (entries arrive in ascending key, so ties keep the earlier key first)
-    int j = n++;
-    while (j > 0 && f[j - 1] < v) {
-      f[j] = f[j - 1];
-      key[j] = key[j - 1];
-      --j;
-    }
-    f[j] = v;
-    key[j] = s;
-  }
-  return n;
-}
-
+// Deviation items of cell (h, i): every option other than the cell's best (largest phi,
+// ties to the smaller key; clutter has key -1 and comes first) whose deviation
+// d = phi_best - phi keeps B'_h - d above the cut bound.  Candidates arrive in ascending key,
+// so items are emitted in ascending option key; the stable sort by (h, d) that follows puts
+// equal deviations in key order.  Two passes over the options, no per-cell storage.
 __global__ void k_items(int ncell, const int32_t* cells, int M, int stride, const int32_t* rows, const int32_t* coff,
                         const int32_t* cand, const float* phi, float lgk, const float* bprime, const float* t0,
                         const int32_t* ioff, int32_t* icount, float* it_delta, int32_t* it_group, int32_t* it_opt,
                         uint64_t* keys, uint32_t* vals, uint32_t* errf) {
+  (void)errf;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncell) return;
   const int cell = cells[c];
   const int h = cell / M, i = cell % M;
-  float f[kMaxOpts];
-  int key[kMaxOpts];
-  const int n = cell_options(h, i, M, stride, rows, coff, cand, phi, lgk, f, key, errf);
+  const int32_t* row = rows + (size_t)h * stride;
+  const int e0 = coff[i], e1 = coff[i + 1];
+  float best = lgk;
+  int bkey = -1;
+  for (int e = e0; e < e1; ++e) {
+    const int s = cand[e];
+    const int u = row[s];
+    if (u < 0) continue;
+    const float v = phi[(size_t)u * M + i];
+    if (v > best) {
+      best = v;
+      bkey = s;
+    }
+  }
   const float B = bprime[h], t = *t0;
   int cnt = 0;
-  for (int r = 1; r < n; ++r) {
-    const float d = f[0] - f[r];
-    if (B - d >= t) {
-      if (ioff) {
-        const int q = ioff[c] + cnt;
-        it_delta[q] = d;
-        it_group[q] = i;
-        it_opt[q] = key[r];
-        keys[q] = ((uint64_t)(uint32_t)h << 32) | f2o(d);
-        vals[q] = (uint32_t)q;
-      }
-      ++cnt;
+  auto emit = [&](float d, int key) {
+    if (!(B - d >= t)) return;
+    if (ioff) {
+      const int q = ioff[c] + cnt;
+      it_delta[q] = d;
+      it_group[q] = i;
+      it_opt[q] = key;
+      keys[q] = ((uint64_t)(uint32_t)h << 32) | f2o(d);
+      vals[q] = (uint32_t)q;
     }
+    ++cnt;
+  };
+  if (bkey >= 0) emit(best - lgk, -1);
+  for (int e = e0; e < e1; ++e) {
+    const int s = cand[e];
+    if (s == bkey) continue;
+    const int u = row[s];
+    if (u < 0) continue;
+    const float v = phi[(size_t)u * M + i];
+    if (!(v > -INFINITY)) continue;
+    emit(best - v, s);
   }
   if (!ioff) icount[c] = cnt;
 }
@@ -816,7 +812,6 @@ void check_err(hipStream_t s, const uint32_t* errf) {
   const uint32_t e = read1(s, errf);
   if (e & ERR_NAN) throw Error{GLMB_E_ARG, "detections contain NaN or infinity"};
   if (e & ERR_BIRTH) throw Error{GLMB_E_CAPACITY, "more than 4096 birth clusters in one scan"};
-  if (e & ERR_OPTS) throw Error{GLMB_E_CAPACITY, "more than 64 options in one (hypothesis, detection) cell"};
   if (e & ERR_DEPTH) throw Error{GLMB_E_CAPACITY, "a kept child deviates in more than 48 detections"};
   if (e & ERR_COLL) throw Error{GLMB_E_STATE, "detection-set fingerprint collision"};
 }

@@ -213,6 +213,15 @@ def test_wide_gate(torch_cuda):
         check_update(st, z, dict(BASE, h_max=K, clutter_density=0.05))
 
 
+def test_crowded_cell(torch_cuda):
+    """Ninety tracks of one hypothesis compete for every detection (cells with 91 options)."""
+    rng = np.random.default_rng(31)
+    st = sc.random_state(rng, n_lab=90, n_hyp=3, side=4.0, versions=1, p_present=1.0)
+    z = sc.measurements_near(rng, st, 0, 4.0, 1.0)[:6]
+    for K in (8, 200):
+        check_update(st, z, dict(BASE, h_max=K))
+
+
 def test_small_node_store(torch_cuda):
     """A node store too small for the one-workgroup search: the multi-kernel search with
     threshold raising and compaction must reach the same hypotheses."""
