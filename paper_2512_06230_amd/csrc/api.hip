@@ -118,6 +118,18 @@ __global__ __launch_bounds__(1024) void k_estimate(int H, const float* logw, con
   }
 }
 
+// mean of every slot's instance in estimated hypothesis res[1] (present[s] = 0 if absent)
+__global__ void k_est_gather(int NS, int stride, const int32_t* rows, const DInst* inst, const int32_t* res,
+                             int32_t* present, float4* means) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= NS) return;
+  const int h = res[1];
+  const int u = h >= 0 && h != INT_MAX ? rows[(size_t)h * stride + s] : -1;
+  present[s] = u >= 0 ? 1 : 0;
+  means[s] = u >= 0 ? make_float4(inst[u].m[0], inst[u].m[1], inst[u].m[2], inst[u].m[3])
+                    : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
 }  // namespace glmb
 
 using glmb::Ctx;
@@ -250,7 +262,7 @@ glmb_status glmb_destroy(glmb_ctx* x) {
                           &c.sb.nd_value, &c.sb.cnt, &c.sb.pre, &c.sb.pre64, &c.sb.flags, &c.sb.map, &c.sb.tmp,
                           &c.sb.tk, &c.sb.tv, &c.sb.keys, &c.sb.vals, &c.sb.sel_node, &c.sb.sel_val, &c.sb.sel_rank,
                           &c.sb.scal, &c.prop_w, &c.pcnt, &c.poff, &c.ppre, &c.pu, &c.pi, &c.plogit, &c.slot_r,
-                          &c.slot_part, &c.slot_age, &c.pm_part, &c.pe_part, &c.lz_t, &c.mlp_part};
+                          &c.slot_part, &c.slot_age, &c.pm_part, &c.pe_part, &c.lz_t, &c.mlp_part, &c.est_buf};
   for (auto* b : bufs) b->release();
   if (c.ev_ok)
     for (auto& e : c.ev) (void)hipEventDestroy(e);
@@ -448,29 +460,33 @@ glmb_status glmb_estimate(glmb_ctx* x, int32_t cap, int32_t* n_out, int32_t* lab
   glmb_status st = guarded(x, [&](Ctx& c) {
     int32_t* scal = glmb::need<int32_t>(c.scal, 64);
     GLMB_LAUNCH(glmb::k_estimate, 1, 1024, 0, c.s, c.nhyp, c.logw.as<float>(), c.ntrk.as<int32_t>(), scal + 20);
+    // one gather and one round trip: the estimated hypothesis' row and its instance means
+    const int NS = c.stride;
+    int32_t* present = glmb::need<int32_t>(c.est_buf, 5 * (int64_t)NS + 4);
+    float4* means = (float4*)(present + ((NS + 3) & ~3));
+    GLMB_LAUNCH(glmb::k_est_gather, glmb::cdiv(NS, 256), 256, 0, c.s, NS, NS, c.rows.as<int32_t>(),
+                c.inst.as<DInst>(), scal + 20, present, means);
     int32_t r[2];
+    std::vector<int32_t> hp(NS);
+    std::vector<float> hm(4 * (size_t)NS);
     GLMB_HIP(hipMemcpyAsync(r, scal + 20, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
+    if (NS) {
+      GLMB_HIP(hipMemcpyAsync(hp.data(), present, NS * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
+      GLMB_HIP(hipMemcpyAsync(hm.data(), means, NS * sizeof(float4), hipMemcpyDeviceToHost, c.s));
+    }
     GLMB_HIP(hipStreamSynchronize(c.s));
-    const int n = r[0], h = r[1];
+    const int n = r[0];
     *n_out = n;
     if (n > cap) {
       cap_err = GLMB_E_CAPACITY;
       return;
     }
-    const int NS = c.stride;
-    std::vector<int32_t> row(NS);
-    if (NS) GLMB_HIP(hipMemcpyAsync(row.data(), c.rows.as<int32_t>() + (size_t)h * NS, NS * sizeof(int32_t),
-                                    hipMemcpyDeviceToHost, c.s));
-    GLMB_HIP(hipStreamSynchronize(c.s));
     int j = 0;
-    for (int sl = 0; sl < NS; ++sl) {
-      if (row[sl] < 0) continue;
-      DInst d;
-      GLMB_HIP(hipMemcpyAsync(&d, c.inst.as<DInst>() + row[sl], sizeof(DInst), hipMemcpyDeviceToHost, c.s));
-      GLMB_HIP(hipStreamSynchronize(c.s));
+    for (int sl = 0; sl < NS && j < n; ++sl) {
+      if (!hp[sl]) continue;
       labels_out[2 * j] = c.slot_lab[sl].first;
       labels_out[2 * j + 1] = c.slot_lab[sl].second;
-      for (int k = 0; k < 4; ++k) means_out[4 * j + k] = d.m[k];
+      for (int k = 0; k < 4; ++k) means_out[4 * j + k] = hm[4 * (size_t)sl + k];
       ++j;
     }
   });

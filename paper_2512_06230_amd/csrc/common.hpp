@@ -118,6 +118,7 @@ struct SelectIn {
   const int32_t* it_group;
   int K;
   const float* t0;        // device scalar: a lower bound on the K-th best child value
+  bool* prefer_multi;     // per call site: the previous search outgrew one workgroup (may be null)
 };
 struct Selected {
   int n;                  // number of selected children (<= K)

@@ -67,6 +67,7 @@ struct Ctx {
       sel_logw, hp_map, first, dmask, exc, cmod, recs, rec_keys, rec_vals, ids, row_mark, ru_part, ru, bt,
       tmp, tk, tv, flags, pre, pmult, pvals, rec_m;
   SelectBufs sb;
+  bool sel_multi[2] = {false, false};  // per search site (prediction, update): start on the whole GPU
   int LW = 1;  // detection-set mask width (32-bit words) of the last gate
 
   // ---- learned pair proposal
@@ -77,6 +78,7 @@ struct Ctx {
   DevBuf prop_w;          // float32 parameters
   DevBuf pcnt, poff, ppre, pu, pi, plogit, slot_r, slot_part, slot_age, pm_part, pe_part, lz_t, mlp_part;
   std::vector<int32_t> h_age;
+  DevBuf est_buf;  // estimate: presence flags and means of the estimated hypothesis' tracks
 };
 
 // opt-in stage trace (host side)

@@ -165,6 +165,7 @@ __global__ void k_take(int n, const uint64_t* keys, const uint32_t* vals, const 
 // level.  Used first; if the node store would overflow it reports it and the multi-kernel
 // search below (with compaction) takes over.
 constexpr int kSB = 1024;
+constexpr int kBlockNodes = 1 << 16;  // node budget of the one-workgroup search
 
 __device__ __forceinline__ int64_t sb_excl_scan(int64_t v, int64_t* sh, int64_t* total) {
   const int lane = lane_id(), w = threadIdx.x / kWave;
@@ -389,14 +390,22 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
     GLMB_HIP(hipMemcpyAsync(hs, scal, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     GLMB_HIP(hipStreamSynchronize(s));
   };
-  // first attempt: the whole search in one workgroup
-  GLMB_LAUNCH(k_select_block, 1, kSB, 0, s, in.P, in.base, in.it_off, in.it_delta, in.it_group, in.K, in.t0, cap,
-              A.p, A.i, A.h, A.v, t, scal + 4);
-  GLMB_HIP(hipMemcpyAsync(hs, scal + 4, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipStreamSynchronize(s));
-  int used = hs[0], levels = hs[1];
-  const bool fast = hs[2] == 0;
-  tr("block", used, hs[2]);
+  // Small searches run in one workgroup (no host round trip per level).  A search that
+  // outgrows kBlockNodes continues on the whole GPU (multi-kernel levels below); the call
+  // site remembers that and starts there next time, until a search is small again.
+  int used = 0, levels = 0;
+  bool fast = false;
+  if (!(in.prefer_multi && *in.prefer_multi)) {
+    GLMB_LAUNCH(k_select_block, 1, kSB, 0, s, in.P, in.base, in.it_off, in.it_delta, in.it_group, in.K, in.t0,
+                std::min(cap, kBlockNodes), A.p, A.i, A.h, A.v, t, scal + 4);
+    GLMB_HIP(hipMemcpyAsync(hs, scal + 4, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GLMB_HIP(hipStreamSynchronize(s));
+    used = hs[0];
+    levels = hs[1];
+    fast = hs[2] == 0;
+    tr("block", used, hs[2]);
+    if (in.prefer_multi) *in.prefer_multi = !fast;
+  }
   if (!fast) {
     // roots
     GLMB_HIP(hipMemcpyAsync(t, in.t0, sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -437,6 +446,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
     return true;
   };
 
+  int last_raise = used;  // node count after the last threshold raise
   while (level_first < level_end) {
     ++levels;
     tr("level", levels, level_end - level_first);
@@ -456,17 +466,31 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
       GLMB_HIP(hipMemcpyAsync(&total, tot64, sizeof(int64_t), hipMemcpyDeviceToHost, s));
       GLMB_HIP(hipStreamSynchronize(s));
       if (total == 0) break;
-      const int64_t room = (int64_t)cap - used;
+      // Expand at most about as many nodes as the store holds (at least 2K) before the
+      // threshold is raised again: a raised threshold prunes the rest of the level.
+      const int64_t hard_room = (int64_t)cap - used;
+      const int64_t room = std::min(hard_room, std::max<int64_t>(2 * (int64_t)in.K, used));
       int m = nlev;
       int64_t te = total;
-      if (total > room) {
-        GLMB_LAUNCH(k_cut, 1, 64, 0, s, pre, cnt, nlev, room, scal + 1);
+      auto cut = [&](int64_t r) {
+        GLMB_LAUNCH(k_cut, 1, 64, 0, s, pre, cnt, nlev, r, scal + 1);
         GLMB_HIP(hipMemcpyAsync(hs, scal, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         GLMB_HIP(hipStreamSynchronize(s));
         m = hs[1];
         te = hs[2];
+      };
+      if (total > room) {
+        if (used >= 2 * last_raise && raise_and_compact(&cursor)) {
+          last_raise = used;
+          continue;
+        }
+        cut(room);
+        if (m == 0 && room < hard_room) cut(hard_room);
         if (m == 0 || used > cap / 2) {
-          if (raise_and_compact(&cursor)) continue;
+          if (raise_and_compact(&cursor)) {
+            last_raise = used;
+            continue;
+          }
           if (m == 0) {
             err = "selection: search node capacity exhausted (tie class at the cut larger than the node store?)";
             return GLMB_E_CAPACITY;
@@ -483,9 +507,10 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
     level_end = next_end;
     if (level_first < level_end) {
       int c = level_first;
-      raise_and_compact(&c);
+      if (raise_and_compact(&c)) last_raise = used;
     }
   }
+  if (!fast && in.prefer_multi && used < kBlockNodes / 4) *in.prefer_multi = false;
   tr("final", used, levels);
   // candidates: every node >= t, in enumeration order
   int32_t* fl = need<int32_t>(b.flags, used + 1);
