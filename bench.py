@@ -33,10 +33,12 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--proposal", default=None, help="trained proposal (.npz); default: the packaged one")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the multi-detection GLMB path runs on a single device "
-              "(see DESIGN.md for how it would shard); run with --gpus 1", file=sys.stderr)
+              "(a scene would shard by ranges of prior-hypothesis rank); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -54,29 +56,65 @@ def main():
     zs = [torch.as_tensor(z, device=dev) for z in scene.meas]
     torch.cuda.synchronize()
 
-    trk = Tracker(params)
-    trk.import_state(sc.warm_start_state(scene))
+    def run(proposal=None, measure=False):
+        """Warm-up scans, then the timed scans; returns (seconds, per-scan stats)."""
+        trk = Tracker(params)
+        trk.import_state(sc.warm_start_state(scene))
+        if proposal is not None:
+            trk.set_proposal(torch.as_tensor(proposal.params, device=dev), proposal.norm, proposal.threshold,
+                             apply=True, measure=measure)
 
-    def step(k):
-        trk.predict(k)
-        trk.update(k, zs[k])
-        trk.truncate(args.h_max, 0.0)
-        return trk.estimate()
+        def step(k):
+            trk.predict(k)
+            trk.update(k, zs[k])
+            trk.truncate(args.h_max, 0.0)
+            return trk.estimate()
 
-    for k in range(args.warmup):
-        step(k)
-    torch.cuda.synchronize()
-    stats = []
-    t0 = time.perf_counter()
-    for k in range(args.warmup, n_scans):
-        labs, _ = step(k)
-        stats.append(trk.stats())
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+        for k in range(args.warmup):
+            step(k)
+        torch.cuda.synchronize()
+        st = []
+        t0 = time.perf_counter()
+        for k in range(args.warmup, n_scans):
+            step(k)
+            st.append(trk.stats())
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        return el, st, trk
+
+    elapsed, stats, trk = run()
     ms_step = 1e3 * elapsed / args.steps
     dense = sum(s["dense_triples"] for s in stats)
     gated = sum(s["option_terms"] for s in stats)
     stage = np.mean(np.array([s["stage_ms"] for s in stats]), axis=0)
+
+    learned = None
+    prop_path = args.proposal or os.path.join(ROOT, "paper_2512_06230_amd", "proposal_n500.npz")
+    if not args.no_learned and os.path.exists(prop_path):
+        from paper_2512_06230_amd.proposal import Proposal
+        prop = Proposal.load(prop_path)
+        el_l, st_l, trk_l = run(prop)
+        trk_l.close()
+        # the same scans again, untimed, with the lost posterior mass measured at every update
+        _, st_m, trk_m = run(prop, measure=True)
+        trk_m.close()
+        lost = np.array([s["lost_mass"] for s in st_m])
+        stage_l = np.mean(np.array([s["stage_ms"] for s in st_l]), axis=0)
+        learned = {
+            "value": args.steps / el_l, "unit": "GLMB updates/s", "ms_per_step": 1e3 * el_l / args.steps,
+            "speedup_vs_plain": elapsed / el_l,
+            "update_ms": float(stage_l[5]), "plain_update_ms": float(stage[5]),
+            "threshold": prop.threshold,
+            "lost_mass_mean": float(lost.mean()), "lost_mass_max": float(lost.max()),
+            "pairs_removed_frac": float(sum(s["pairs_removed"] for s in st_l) /
+                                        max(1, sum(s["gated_pairs"] for s in st_l))),
+            "option_terms_frac": float(sum(s["option_terms"] for s in st_l) / max(1, gated)),
+            "evals_per_s": sum(s["dense_triples"] for s in st_l) / el_l,
+            "stage_ms": {"gate": float(stage_l[0]), "assoc": float(stage_l[1]), "select": float(stage_l[2]),
+                         "materialise": float(stage_l[3]), "births": float(stage_l[4]),
+                         "update": float(stage_l[5])},
+            "proposal_file": os.path.relpath(prop_path, ROOT),
+        }
 
     # roofline of the dominant kernel: the per-(hypothesis, detection) association kernel.
     # Algorithmic HBM bytes per launch: the hypothesis rows read (H x stride x 4 B) plus the three
@@ -112,6 +150,7 @@ def main():
                    "n_obj": args.n_obj, "h_max": args.h_max, "clutter_mean": clutter,
                    "mean_detections": float(M), "mean_hypotheses_in": float(H), "parallelism": "single GPU"},
         "evals_per_s": dense / elapsed,
+        "update_per_s": 1e3 / float(stage[5]) if stage[5] > 0 else None,
         "gated_evals_per_s": gated / elapsed,
         "stage_ms": {"gate": float(stage[0]), "assoc": float(stage[1]), "select": float(stage[2]),
                      "materialise": float(stage[3]), "births": float(stage[4]), "update": float(stage[5])},
@@ -119,6 +158,8 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "algorithmic_bytes": bytes_assoc},
     }
+    if learned is not None:
+        out["learned"] = learned
 
     if not args.no_cpu_baseline:
         from oracle.oracle import Oracle

@@ -262,7 +262,7 @@ glmb_status glmb_destroy(glmb_ctx* x) {
                           &c.sb.nd_value, &c.sb.cnt, &c.sb.pre, &c.sb.pre64, &c.sb.flags, &c.sb.map, &c.sb.tmp,
                           &c.sb.tk, &c.sb.tv, &c.sb.keys, &c.sb.vals, &c.sb.sel_node, &c.sb.sel_val, &c.sb.sel_rank,
                           &c.sb.scal, &c.prop_w, &c.pcnt, &c.poff, &c.ppre, &c.pu, &c.pi, &c.plogit, &c.slot_r,
-                          &c.slot_part, &c.slot_age, &c.pm_part, &c.pe_part, &c.lz_t, &c.mlp_part, &c.est_buf};
+                          &c.slot_part, &c.slot_age, &c.pm_part, &c.pe_part, &c.lz_t, &c.mlp_part, &c.est_buf, &c.ref_b1, &c.ref_opts};
   for (auto* b : bufs) b->release();
   if (c.ev_ok)
     for (auto& e : c.ev) (void)hipEventDestroy(e);
@@ -549,14 +549,15 @@ glmb_status glmb_update_theta(glmb_ctx* x, int32_t n_hyp, int32_t M, int32_t* th
   });
 }
 
-glmb_status glmb_set_proposal(glmb_ctx* x, const float* params, const float* norm, float threshold, int32_t measure) {
+glmb_status glmb_set_proposal(glmb_ctx* x, const float* params, const float* norm, float threshold, int32_t flags) {
   if (!x) return GLMB_E_ARG;
   if (!params) {
     x->c.prop_on = false;
+    x->c.prop_loaded = false;
     return GLMB_OK;
   }
-  if (!norm || !(threshold > 0.0f && threshold < 1.0f))
-    return fail(x, GLMB_E_ARG, "null norm or threshold outside (0, 1)");
+  if (!norm || !(threshold > 0.0f && threshold < 1.0f) || (flags & ~3))
+    return fail(x, GLMB_E_ARG, "null norm, threshold outside (0, 1) or unknown flags");
   for (int k = 0; k < 12; ++k)
     if (!std::isfinite(norm[k]) || (k >= 6 && !(norm[k] > 0.0f)))
       return fail(x, GLMB_E_ARG, "feature norm must be finite with positive standard deviations");
@@ -567,8 +568,9 @@ glmb_status glmb_set_proposal(glmb_ctx* x, const float* params, const float* nor
     std::memcpy(c.prop_norm, norm, sizeof(c.prop_norm));
     c.prop_thr = (float)std::log((double)threshold / (1.0 - (double)threshold));
     c.prop_t = threshold;
-    c.prop_measure = measure != 0;
-    c.prop_on = true;
+    c.prop_loaded = true;
+    c.prop_on = (flags & GLMB_PROPOSAL_APPLY) != 0;
+    c.prop_measure = (flags & GLMB_PROPOSAL_MEASURE) != 0;
   });
 }
 
@@ -593,7 +595,7 @@ glmb_status glmb_proposal_lost(glmb_ctx* x, int32_t k, const float* z, int32_t M
     if (!(thr[j] > 0.0f && thr[j] < 1.0f)) return fail(x, GLMB_E_ARG, "thresholds must lie in (0, 1)");
   if (M > 32768) return fail(x, GLMB_E_CAPACITY, "more than 32768 detections in one scan");
   return guarded(x, [&](Ctx& c) {
-    if (c.prop_w.bytes < glmb::kNParam * sizeof(float)) throw Error{GLMB_E_STATE, "no proposal parameters set"};
+    if (!c.prop_loaded) throw Error{GLMB_E_STATE, "no proposal parameters loaded"};
     glmb::proposal_lost(c, k, z, M, thr, T, lost);
   });
 }

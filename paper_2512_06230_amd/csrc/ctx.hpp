@@ -65,13 +65,13 @@ struct Ctx {
   DevBuf z, cmax, gbits, phi, lbits, lpre, llen, loff, lmeas, inst_beg, ccnt, coff, cand, best16, dev1, lserel,
       bprime, lzprime, vals, cells, ccount, coff2, it_h, it_delta, it_group, it_opt, it_off, keys, vals32, scal,
       sel_logw, hp_map, first, dmask, exc, cmod, recs, rec_keys, rec_vals, ids, row_mark, ru_part, ru, bt,
-      tmp, tk, tv, flags, pre, pmult, pvals, rec_m;
+      tmp, tk, tv, flags, pre, pmult, pvals, rec_m, ref_b1, ref_opts;
   SelectBufs sb;
   bool sel_multi[2] = {false, false};  // per search site (prediction, update): start on the whole GPU
   int LW = 1;  // detection-set mask width (32-bit words) of the last gate
 
   // ---- learned pair proposal
-  bool prop_on = false, prop_measure = false;
+  bool prop_loaded = false, prop_on = false, prop_measure = false;
   float prop_thr = 0.0f;  // logit threshold: pairs with a lower logit are removed
   float prop_t = 0.5f;    // the same threshold as a probability
   float prop_norm[12] = {};

@@ -221,28 +221,55 @@ __global__ __launch_bounds__(256) void k_bound_hist(const float* v, const int32_
     if (h[j]) atomicAdd(&hist[j], h[j]);
 }
 
-// one thread: walk the bins from the top until K values are covered
-__global__ void k_bound_pick(int32_t* hist, int pass, uint32_t* prefix, int32_t* need_k, float* out) {
-  if (threadIdx.x != 0) return;
-  int64_t K = *need_k;
-  int64_t acc = 0;
-  int b = kBins - 1;
-  for (; b >= 0; --b) {
-    if (acc + hist[b] >= K) break;
-    acc += hist[b];
+// one workgroup of 1024 threads, four bins each: find the bin holding the K-th largest value
+// (counting from the top), then clear the histogram for the next use
+__global__ __launch_bounds__(1024) void k_bound_pick(int32_t* hist, int pass, uint32_t* prefix, int32_t* need_k,
+                                                     float* out) {
+  static_assert(kBins == 4 * 1024, "four bins per thread");
+  __shared__ int64_t wsum[16];
+  __shared__ int found;
+  const int t = threadIdx.x, lane = lane_id(), w = t / kWave;
+  const int64_t K = *need_k;
+  int32_t c[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) c[j] = hist[4 * t + j];
+  const int64_t mine = (int64_t)c[0] + c[1] + c[2] + c[3];
+  // inclusive scan of `mine` over threads in descending bin order (thread 1023 first)
+  int64_t x = mine;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int64_t y = __shfl_down(x, d, kWave);
+    if (lane + d < kWave) x += y;
   }
-  if (b < 0) {
+  if (lane == 0) wsum[w] = x;  // total of this wave
+  if (t == 0) found = 0;
+  __syncthreads();
+  int64_t above = x - mine;  // bins of higher threads within the wave
+  for (int j = w + 1; j < 16; ++j) above += wsum[j];
+  if (above < K && above + mine >= K) {
+    int64_t acc = above;
+    int b = 4 * t + 3;
+    for (; b > 4 * t; --b) {
+      if (acc + c[b - 4 * t] >= K) break;
+      acc += c[b - 4 * t];
+    }
+    found = 1;
+    if (pass == 0) {
+      *prefix = (uint32_t)b;
+      *need_k = (int32_t)(K - acc);
+    } else {
+      // lowest value of the bin; the bin of -inf starts below -inf (a NaN pattern)
+      const float e = o2f(((*prefix) << 20) | ((uint32_t)b << 8));
+      *out = e == e ? e : -INFINITY;
+    }
+  }
+  __syncthreads();
+  if (t == 0 && !found) {
     *out = -INFINITY;
     *prefix = 0xffffffffu;  // no second pass restriction matches
-  } else if (pass == 0) {
-    *prefix = (uint32_t)b;
-    *need_k = (int32_t)(K - acc);
-  } else {
-    // lowest value of the bin; the bin of -inf starts below -inf (a NaN pattern)
-    const float e = o2f(((*prefix) << 20) | ((uint32_t)b << 8));
-    *out = e == e ? e : -INFINITY;
   }
-  for (int j = 0; j < kBins; ++j) hist[j] = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) hist[4 * t + j] = 0;
 }
 
 __global__ void k_bound_init(int32_t* hist, int32_t* need_k, int32_t K) {
@@ -259,9 +286,9 @@ static void kth_bound_impl(const float* v, const int32_t* mult, int n, int K, fl
   GLMB_LAUNCH(k_bound_init, 1, 256, 0, s, hist, need_k, (int32_t)K);
   const int grid = std::max(1, std::min(cdiv(n, 256 * 8), 1024));
   GLMB_LAUNCH(k_bound_hist, grid, 256, 0, s, v, mult, n, 0, prefix, hist);
-  GLMB_LAUNCH(k_bound_pick, 1, 64, 0, s, hist, 0, prefix, need_k, out);
+  GLMB_LAUNCH(k_bound_pick, 1, 1024, 0, s, hist, 0, prefix, need_k, out);
   GLMB_LAUNCH(k_bound_hist, grid, 256, 0, s, v, mult, n, 1, prefix, hist);
-  GLMB_LAUNCH(k_bound_pick, 1, 64, 0, s, hist, 1, prefix, need_k, out);
+  GLMB_LAUNCH(k_bound_pick, 1, 1024, 0, s, hist, 1, prefix, need_k, out);
 }
 
 void kth_bound(const float* v, int n, int K, float* out, DevBuf& tmp, hipStream_t s) {

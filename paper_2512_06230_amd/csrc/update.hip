@@ -161,54 +161,50 @@ __device__ __forceinline__ float block_max_f(float v, float* sh) {
   return r;
 }
 
-// one block per hypothesis; the hypothesis row is staged in LDS
-__global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t* rows, const float* logw,
-                                               const int32_t* ntrk, float gamma, float lgk,
-                                               const int32_t* coff, const int32_t* cand, const float* phi,
-                                               const uint32_t* cmax, int16_t* best16, float* dev1, float* lserel,
-                                               float* bprime, float* lzprime, unsigned long long* nopts,
-                                               unsigned long long* ndense) {
-  extern __shared__ int32_t row[];
-  __shared__ float red[16];
-  const int h = blockIdx.x;
-  for (int s = threadIdx.x; s < stride; s += blockDim.x) row[s] = rows[(size_t)h * stride + s];
-  __syncthreads();
-  float bsum = 0.0f, lsum = 0.0f;
+// Cell (h, i) from the hypothesis row in LDS: best option (slot + 1, 0 = clutter), first
+// deviation, log-sum-exp over clutter and the gated tracks; returns the best value b1.
+struct CellOut {
+  float b1, l;
+  unsigned opts;
+};
+__device__ __forceinline__ CellOut assoc_cell(int i, int M, const int32_t* row, float lgk, const int32_t* coff,
+                                              const int32_t* cand, const float* phi, int16_t* best16, float* dev1,
+                                              size_t cell, float c) {
+  float b1 = lgk, b2 = -INFINITY, mx = lgk, sm = 1.0f;
+  int k1 = -1;
   unsigned opts = 0;
-  for (int i = threadIdx.x; i < M; i += blockDim.x) {
-    const float c = o2f(cmax[i]);
-    float b1 = lgk, b2 = -INFINITY, mx = lgk, sm = 1.0f;
-    int k1 = -1;
-    const int e1 = coff[i + 1];
-    for (int e = coff[i]; e < e1; ++e) {
-      const int s = cand[e];
-      const int u = row[s];
-      if (u < 0) continue;
-      const float f = phi[(size_t)u * M + i];
-      if (!(f > -INFINITY)) continue;
-      ++opts;
-      if (f > b1) {
-        b2 = b1;
-        b1 = f;
-        k1 = s;
-      } else if (f > b2) {
-        b2 = f;
-      }
-      if (f > mx) {
-        sm = sm * __expf(mx - f) + 1.0f;
-        mx = f;
-      } else {
-        sm += __expf(f - mx);
-      }
+  const int e1 = coff[i + 1];
+  for (int e = coff[i]; e < e1; ++e) {
+    const int s = cand[e];
+    const int u = row[s];
+    if (u < 0) continue;
+    const float f = phi[(size_t)u * M + i];
+    if (!(f > -INFINITY)) continue;
+    ++opts;
+    if (f > b1) {
+      b2 = b1;
+      b1 = f;
+      k1 = s;
+    } else if (f > b2) {
+      b2 = f;
     }
-    const float l = mx + __logf(sm);
-    const size_t cell = (size_t)h * M + i;
-    best16[cell] = (int16_t)(k1 + 1);
-    dev1[cell] = b2 > -INFINITY ? b1 - b2 : INFINITY;
-    lserel[cell] = l - c;
-    bsum += b1 - c;
-    lsum += l - c;
+    if (f > mx) {
+      sm = sm * __expf(mx - f) + 1.0f;
+      mx = f;
+    } else {
+      sm += __expf(f - mx);
+    }
   }
+  const float l = mx + __logf(sm);
+  best16[cell] = (int16_t)(k1 + 1);
+  dev1[cell] = b2 > -INFINITY ? b1 - b2 : INFINITY;
+  (void)c;
+  return CellOut{b1, l, opts};
+}
+
+__device__ __forceinline__ void assoc_finish(int h, float bsum, float lsum, unsigned opts, const float* logw,
+                                             const int32_t* ntrk, float gamma, int M, float* bprime, float* lzprime,
+                                             unsigned long long* nopts, unsigned long long* ndense, float* red) {
   bsum = block_sum_f(bsum, red);
   lsum = block_sum_f(lsum, red + 8);
   if (threadIdx.x == 0) {
@@ -221,6 +217,87 @@ __global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t*
   // option count (integer; order irrelevant)
   for (int d = kWave / 2; d > 0; d >>= 1) opts += __shfl_xor(opts, d, kWave);
   if (lane_id() == 0 && opts) atomicAdd(nopts, (unsigned long long)opts);
+}
+
+// Hypothesis 0 (one workgroup, row in LDS): every cell, plus the reference values the other
+// hypotheses copy where their options are the same (b1 - c_i and the option count).
+__global__ __launch_bounds__(256) void k_assoc_ref(int M, int stride, const int32_t* rows, const float* logw,
+                                                   const int32_t* ntrk, float gamma, float lgk, const int32_t* coff,
+                                                   const int32_t* cand, const float* phi, const uint32_t* cmax,
+                                                   int16_t* best16, float* dev1, float* lserel, float* bprime,
+                                                   float* lzprime, float* ref_b1, int32_t* ref_opts,
+                                                   unsigned long long* nopts, unsigned long long* ndense) {
+  extern __shared__ int32_t row[];
+  __shared__ float red[16];
+  for (int s = threadIdx.x; s < stride; s += blockDim.x) row[s] = rows[s];
+  __syncthreads();
+  float bsum = 0.0f, lsum = 0.0f;
+  unsigned opts = 0;
+  for (int i = threadIdx.x; i < M; i += blockDim.x) {
+    const float c = o2f(cmax[i]);
+    const CellOut o = assoc_cell(i, M, row, lgk, coff, cand, phi, best16, dev1, (size_t)i, c);
+    lserel[i] = o.l - c;
+    ref_b1[i] = o.b1 - c;
+    ref_opts[i] = (int32_t)o.opts;
+    bsum += o.b1 - c;
+    lsum += o.l - c;
+    opts += o.opts;
+  }
+  assoc_finish(0, bsum, lsum, opts, logw, ntrk, gamma, M, bprime, lzprime, nopts, ndense, red);
+}
+
+// Hypotheses 1..H-1, one workgroup each (row in LDS).  A cell's options depend only on the
+// instances of the labels gated with its detection, so only the detections gated with a
+// label whose instance differs from hypothesis 0's (including presence) are recomputed;
+// every other cell is a copy of hypothesis 0's.  The sums run over the cells in the same
+// order with the same per-cell values, so the results equal a full recomputation bit for bit.
+__global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t* rows, const float* logw,
+                                               const int32_t* ntrk, float gamma, float lgk,
+                                               const int32_t* coff, const int32_t* cand, const float* phi,
+                                               const uint32_t* cmax, const int32_t* loff, const int32_t* llen,
+                                               const int32_t* lmeas, const float* ref_b1, const int32_t* ref_opts,
+                                               int16_t* best16, float* dev1, float* lserel, float* bprime,
+                                               float* lzprime, unsigned long long* nopts,
+                                               unsigned long long* ndense) {
+  extern __shared__ int32_t row[];  // row[stride] | touched-detection bits[(M + 31) / 32]
+  __shared__ float red[16];
+  const int h = blockIdx.x + 1;
+  const int W = (M + 31) / 32;
+  uint32_t* touched = (uint32_t*)(row + stride);
+  for (int s = threadIdx.x; s < stride; s += blockDim.x) row[s] = rows[(size_t)h * stride + s];
+  for (int w = threadIdx.x; w < W; w += blockDim.x) touched[w] = 0u;
+  __syncthreads();
+  for (int s = threadIdx.x; s < stride; s += blockDim.x) {
+    if (row[s] == rows[s]) continue;
+    const int b = loff[s], e = b + llen[s];
+    for (int q = b; q < e; ++q) {
+      const int i = lmeas[q];
+      atomicOr(&touched[i >> 5], 1u << (i & 31));
+    }
+  }
+  __syncthreads();
+  float bsum = 0.0f, lsum = 0.0f;
+  unsigned opts = 0;
+  for (int i = threadIdx.x; i < M; i += blockDim.x) {
+    const size_t cell = (size_t)h * M + i;
+    if ((touched[i >> 5] >> (i & 31)) & 1u) {
+      const float c = o2f(cmax[i]);
+      const CellOut o = assoc_cell(i, M, row, lgk, coff, cand, phi, best16, dev1, cell, c);
+      lserel[cell] = o.l - c;
+      bsum += o.b1 - c;
+      lsum += o.l - c;
+      opts += o.opts;
+    } else {
+      best16[cell] = best16[i];
+      dev1[cell] = dev1[i];
+      const float ls = lserel[i];
+      lserel[cell] = ls;
+      bsum += ref_b1[i];
+      lsum += ls;
+      opts += (unsigned)ref_opts[i];
+    }
+  }
+  assoc_finish(h, bsum, lsum, opts, logw, ntrk, gamma, M, bprime, lzprime, nopts, ndense, red);
 }
 
 // ------------------------------------------------------------------ U3
@@ -922,10 +999,19 @@ void assoc_norm(Ctx& c, int M) {
   float* lserel = need<float>(c.lserel, HM);
   float* bprime = need<float>(c.bprime, H);
   float* lzprime = need<float>(c.lzprime, H);
+  float* ref_b1 = need<float>(c.ref_b1, M + 1);
+  int32_t* ref_opts = need<int32_t>(c.ref_opts, M + 1);
   c.mark(1);
-  GLMB_LAUNCH(k_assoc, H, 256, SW * sizeof(int32_t), s, M, SW, c.rows.as<int32_t>(), c.logw.as<float>(),
+  GLMB_LAUNCH(k_assoc_ref, 1, 256, SW * sizeof(int32_t), s, M, SW, c.rows.as<int32_t>(), c.logw.as<float>(),
               c.ntrk.as<int32_t>(), p.det_rate, lgk, c.coff.as<int32_t>(), c.cand.as<int32_t>(), c.phi.as<float>(),
-              c.cmax.as<uint32_t>(), best16, dev1, lserel, bprime, lzprime, nopts, ndense);
+              c.cmax.as<uint32_t>(), best16, dev1, lserel, bprime, lzprime, ref_b1, ref_opts, nopts, ndense);
+  const size_t lds = (size_t)(SW + (M + 31) / 32) * sizeof(int32_t);
+  if (lds > 64 * 1024)
+    GLMB_HIP(hipFuncSetAttribute((const void*)k_assoc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  GLMB_LAUNCH(k_assoc, H - 1, 256, lds, s, M, SW, c.rows.as<int32_t>(), c.logw.as<float>(), c.ntrk.as<int32_t>(),
+              p.det_rate, lgk, c.coff.as<int32_t>(), c.cand.as<int32_t>(), c.phi.as<float>(), c.cmax.as<uint32_t>(),
+              c.loff.as<int32_t>(), c.llen.as<int32_t>(), c.lmeas.as<int32_t>(), ref_b1, ref_opts, best16, dev1,
+              lserel, bprime, lzprime, nopts, ndense);
   c.mark(2);
   float* dbest = need<float>(c.diag_best, H);
   float* dlogpi = need<float>(c.diag_logpi, H);

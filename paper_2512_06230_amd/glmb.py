@@ -22,6 +22,7 @@ EXPORTS = ["glmb_status_string", "glmb_last_error", "glmb_create", "glmb_destroy
            "glmb_pair_features", "glmb_proposal_lost", "glmb_mlp_forward", "glmb_mlp_grad", "glmb_mlp_adam"]
 
 MLP_NPARAM, MLP_NFEAT = 4673, 6
+PROPOSAL_APPLY, PROPOSAL_MEASURE = 1, 2
 
 
 class Params(ctypes.Structure):
@@ -269,15 +270,18 @@ class Tracker:
         n = np.ascontiguousarray(np.asarray(norm, np.float32).reshape(12))
         return n
 
-    def set_proposal(self, params, norm, threshold: float, measure: bool = False):
-        """params: CUDA float32 [4673] (None disables the proposal); norm: 12 floats."""
+    def set_proposal(self, params, norm, threshold: float = 0.5, apply: bool = True, measure: bool = False):
+        """params: CUDA float32 [4673] (None unloads the proposal); norm: 12 floats.
+        apply: the following updates remove low-scoring pairs; measure: they also report the
+        lost posterior mass.  With apply=False the parameters serve proposal_lost only."""
         if params is None:
             self._check(self._L.glmb_set_proposal(self._ctx, None, None, 0.5, 0), "glmb_set_proposal")
             return
         params = self._dev(params, (MLP_NPARAM,))
         n = self._norm(norm)
+        flags = (PROPOSAL_APPLY if apply else 0) | (PROPOSAL_MEASURE if measure else 0)
         self._check(self._L.glmb_set_proposal(self._ctx, ctypes.c_void_p(params.data_ptr()), _fp(n),
-                                              float(threshold), int(bool(measure))), "glmb_set_proposal")
+                                              float(threshold), flags), "glmb_set_proposal")
 
     def pair_features(self, k: int, z, cap: int = 0):
         """Training data of the current predicted state: (feat [n,6], pair [n,2], target [n],

@@ -165,7 +165,9 @@ def make_scene(spec: SceneSpec, n_steps: Optional[int] = None) -> Scene:
 
 
 def filter_params(spec: SceneSpec, h_max: int, tau: float) -> dict:
-    """Tracker parameters matched to a simulated scene (input recipe)."""
+    """Tracker parameters matched to a simulated scene: gamma = the simulator's mean
+    detections per object, kappa = clutter mean / region area, chi-square(2) gate at 0.9999,
+    adaptive births seeded from detections with P(not clutter) < 0.5."""
     area = spec.side * spec.side
     return dict(
         dt=spec.dt, q=spec.q, sigma_z=spec.sigma, p_survive=0.99,
