@@ -165,7 +165,7 @@ __global__ void k_take(int n, const uint64_t* keys, const uint32_t* vals, const 
 // level.  Used first; if the node store would overflow it reports it and the multi-kernel
 // search below (with compaction) takes over.
 constexpr int kSB = 1024;
-constexpr int kBlockNodes = 1 << 16;  // node budget of the one-workgroup search
+constexpr int kBlockNodes = 1 << 18;  // node budget of the one-workgroup search
 
 __device__ __forceinline__ int64_t sb_excl_scan(int64_t v, int64_t* sh, int64_t* total) {
   const int lane = lane_id(), w = threadIdx.x / kWave;
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
     used += (int)tot;
   }
   __syncthreads();
-  int first = 0, end = used, levels = 0;
+  int first = 0, end = used, levels = 0, last_raise = used;
   while (status == 0 && first < end) {
     if (++levels > kMaxDepth + 1) {
       status = 2;
@@ -333,13 +333,21 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
       __syncthreads();
       used += (int)te;
       c0 += take;
+      // raise the threshold whenever the store has doubled since the last raise: the rest of
+      // the level is then expanded under the higher threshold
+      if (used >= K && used >= 2 * last_raise) {
+        const float b = sb_bound(nd_v, used, K, hist, sh, sel);
+        if (b > t) t = b;
+        last_raise = used;
+      }
     }
     if (status != 0) break;
     first = end;
     end = used;
-    if (first < end && used >= K) {
+    if (first < end && used >= K && used > last_raise) {
       const float b = sb_bound(nd_v, used, K, hist, sh, sel);
       if (b > t) t = b;
+      last_raise = used;
     }
   }
   if (threadIdx.x == 0) {
@@ -510,7 +518,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
       if (raise_and_compact(&c)) last_raise = used;
     }
   }
-  if (!fast && in.prefer_multi && used < kBlockNodes / 4) *in.prefer_multi = false;
+  if (!fast && in.prefer_multi && used < kBlockNodes / 64) *in.prefer_multi = false;
   tr("final", used, levels);
   // candidates: every node >= t, in enumeration order
   int32_t* fl = need<int32_t>(b.flags, used + 1);
