@@ -258,7 +258,7 @@ glmb_status glmb_destroy(glmb_ctx* x) {
                           &c.ccount, &c.coff2, &c.it_h, &c.it_delta, &c.it_group, &c.it_opt, &c.it_off, &c.keys,
                           &c.vals32, &c.scal, &c.sel_logw, &c.hp_map, &c.first, &c.dmask, &c.exc, &c.cmod, &c.recs,
                           &c.rec_keys, &c.rec_vals, &c.ids, &c.row_mark, &c.ru_part, &c.ru, &c.bt, &c.tmp, &c.tk,
-                          &c.tv, &c.flags, &c.pre, &c.pmult, &c.pvals, &c.rec_m, &c.sb.nd_parent, &c.sb.nd_item, &c.sb.nd_h,
+                          &c.tv, &c.flags, &c.pre, &c.pmult, &c.pvals, &c.rec_m, &c.sb.nd_parent, &c.sb.nd_item, &c.sb.nd_h, &c.sb.nd_bloom,
                           &c.sb.nd_value, &c.sb.cnt, &c.sb.pre, &c.sb.pre64, &c.sb.flags, &c.sb.map, &c.sb.tmp,
                           &c.sb.tk, &c.sb.tv, &c.sb.keys, &c.sb.vals, &c.sb.sel_node, &c.sb.sel_val, &c.sb.sel_rank,
                           &c.sb.scal, &c.prop_w, &c.pcnt, &c.poff, &c.ppre, &c.pu, &c.pi, &c.plogit, &c.slot_r,

@@ -134,7 +134,7 @@ struct Selected {
   int levels, nodes;
 };
 struct SelectBufs {
-  DevBuf nd_parent, nd_item, nd_h, nd_value, cnt, pre, pre64, flags, map, tmp, tk, tv, keys, vals, sel_node,
+  DevBuf nd_parent, nd_item, nd_h, nd_value, nd_bloom, cnt, pre, pre64, flags, map, tmp, tk, tv, keys, vals, sel_node,
       sel_val, sel_rank, scal;
 };
 glmb_status select_topk(const SelectIn& in, int cap_nodes, SelectBufs& b, Selected& out, hipStream_t s,

@@ -22,16 +22,21 @@
 
 namespace glmb {
 
+// one bit per group out of 64 (a one-hash Bloom filter of the groups a node has picked): a
+// clear bit proves the group is not picked yet, so the walk up the node's picks is skipped
+__device__ __forceinline__ uint64_t group_bit(int g) { return 1ull << (((uint32_t)g * 0x9E3779B1u) >> 26); }
+
 __global__ void k_root_flags(const float* base, int P, const float* t, int32_t* flags) {
   const int h = blockIdx.x * blockDim.x + threadIdx.x;
   if (h < P) flags[h] = base[h] >= *t ? 1 : 0;
 }
 
 __global__ void k_root_write(const float* base, int P, const float* t, const int32_t* pre, int32_t* nd_parent,
-                             int32_t* nd_item, int32_t* nd_h, float* nd_value) {
+                             int32_t* nd_item, int32_t* nd_h, float* nd_value, uint64_t* nd_b) {
   const int h = blockIdx.x * blockDim.x + threadIdx.x;
   if (h < P && base[h] >= *t) {
     const int n = pre[h];
+    nd_b[n] = 0ull;
     nd_parent[n] = -1;
     nd_item[n] = -1;
     nd_h[n] = h;
@@ -81,7 +86,7 @@ __global__ void k_cut(const int64_t* pre, const int64_t* cnt, int nlev, int64_t 
 }
 
 __global__ void k_expand(int first, int m, int total, int out_base, const int64_t* pre, int32_t* nd_parent,
-                         int32_t* nd_item, int32_t* nd_h, float* nd_value, const int32_t* it_off,
+                         int32_t* nd_item, int32_t* nd_h, float* nd_value, uint64_t* nd_b, const int32_t* it_off,
                          const float* it_delta, const int32_t* it_group, const float* t) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
@@ -97,14 +102,17 @@ __global__ void k_expand(int first, int m, int total, int out_base, const int64_
   const int q = lo + (int)(e - pre[a]);
   float v = nd_value[n] - it_delta[q];
   const int g = it_group[q];
-  for (int x = n; nd_item[x] >= 0; x = nd_parent[x])
-    if (it_group[nd_item[x]] == g) {
-      // two picks in one group: not a child.  NaN fails every `value >= t` test, so such a
-      // node is never extended nor kept, even while t is still -inf.
-      v = __uint_as_float(0xffc00000u);
-      break;
-    }
+  const uint64_t pb = nd_b[n], gb = group_bit(g);
+  if (pb & gb)
+    for (int x = n; nd_item[x] >= 0; x = nd_parent[x])
+      if (it_group[nd_item[x]] == g) {
+        // two picks in one group: not a child.  NaN fails every `value >= t` test, so such a
+        // node is never extended nor kept, even while t is still -inf.
+        v = __uint_as_float(0xffc00000u);
+        break;
+      }
   const int o = out_base + e;
+  nd_b[o] = pb | gb;
   nd_parent[o] = n;
   nd_item[o] = q;
   nd_h[o] = nd_h[n];
@@ -117,10 +125,12 @@ __global__ void k_keep_flags(const float* nd_value, int n, const float* t, int32
 }
 
 __global__ void k_compact_nodes(int n, const float* t, const int32_t* pre, const int32_t* p0, const int32_t* i0,
-                                const int32_t* h0, const float* v0, int32_t* p1, int32_t* i1, int32_t* h1, float* v1) {
+                                const int32_t* h0, const float* v0, const uint64_t* b0, int32_t* p1, int32_t* i1,
+                                int32_t* h1, float* v1, uint64_t* b1) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || !(v0[i] >= *t)) return;
   const int d = pre[i];
+  b1[d] = b0[i];
   p1[d] = p0[i] >= 0 ? pre[p0[i]] : -1;
   i1[d] = i0[i];
   h1[d] = h0[i];
@@ -237,7 +247,8 @@ __device__ float sb_bound(const float* v, int n, int K, int32_t* hist, int64_t* 
 __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, const int32_t* it_off,
                                                       const float* it_delta, const int32_t* it_group, int K,
                                                       const float* t0, int cap, int32_t* nd_p, int32_t* nd_i,
-                                                      int32_t* nd_h, float* nd_v, float* t_out, int32_t* out) {
+                                                      int32_t* nd_h, float* nd_v, uint64_t* nd_b, float* t_out,
+                                                      int32_t* out) {
   __shared__ int64_t sh[40];
   __shared__ int32_t hist[4096];
   __shared__ int64_t sel[4];
@@ -264,6 +275,7 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
       nd_i[n] = -1;
       nd_h[n] = h;
       nd_v[n] = base[h];
+      nd_b[n] = 0ull;
     }
     used += (int)tot;
   }
@@ -319,12 +331,15 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
         const int q = clo[a] + (int)(e - cpre[a]);
         float v = nd_v[nn] - it_delta[q];
         const int g = it_group[q];
-        for (int x = nn; nd_i[x] >= 0; x = nd_p[x])
-          if (it_group[nd_i[x]] == g) {
-            v = nan;  // two picks in one group: not a child
-            break;
-          }
+        const uint64_t pb = nd_b[nn], gb = group_bit(g);
+        if (pb & gb)
+          for (int x = nn; nd_i[x] >= 0; x = nd_p[x])
+            if (it_group[nd_i[x]] == g) {
+              v = nan;  // two picks in one group: not a child
+              break;
+            }
         const int o = used + (int)e;
+        nd_b[o] = pb | gb;
         nd_p[o] = nn;
         nd_i[o] = q;
         nd_h[o] = nd_h[nn];
@@ -362,6 +377,7 @@ namespace {
 struct Nodes {
   int32_t *p, *i, *h;
   float* v;
+  uint64_t* b;
 };
 }  // namespace
 
@@ -382,6 +398,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
     n.i = need<int32_t>(b.nd_item, c2) + (which ? cap : 0);
     n.h = need<int32_t>(b.nd_h, c2) + (which ? cap : 0);
     n.v = need<float>(b.nd_value, c2) + (which ? cap : 0);
+    n.b = need<uint64_t>(b.nd_bloom, c2) + (which ? cap : 0);
     return n;
   };
   if (in.P > cap) {
@@ -405,7 +422,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
   bool fast = false;
   if (!(in.prefer_multi && *in.prefer_multi)) {
     GLMB_LAUNCH(k_select_block, 1, kSB, 0, s, in.P, in.base, in.it_off, in.it_delta, in.it_group, in.K, in.t0,
-                std::min(cap, kBlockNodes), A.p, A.i, A.h, A.v, t, scal + 4);
+                std::min(cap, kBlockNodes), A.p, A.i, A.h, A.v, A.b, t, scal + 4);
     GLMB_HIP(hipMemcpyAsync(hs, scal + 4, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     GLMB_HIP(hipStreamSynchronize(s));
     used = hs[0];
@@ -421,7 +438,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
     int32_t* pre = need<int32_t>(b.pre, in.P + 1);
     GLMB_LAUNCH(k_root_flags, cdiv(in.P, T), T, 0, s, in.base, in.P, t, fl);
     scan_excl(fl, pre, in.P, scal, b.tmp, s);
-    GLMB_LAUNCH(k_root_write, cdiv(in.P, T), T, 0, s, in.base, in.P, t, pre, A.p, A.i, A.h, A.v);
+    GLMB_LAUNCH(k_root_write, cdiv(in.P, T), T, 0, s, in.base, in.P, t, pre, A.p, A.i, A.h, A.v, A.b);
     read(1);
     used = hs[0];
     levels = 0;
@@ -442,7 +459,8 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
     int32_t* pre = need<int32_t>(b.pre, used + 1);
     GLMB_LAUNCH(k_keep_flags, cdiv(used, T), T, 0, s, A.v, used, t, fl);
     scan_excl(fl, pre, used, scal, b.tmp, s);
-    GLMB_LAUNCH(k_compact_nodes, cdiv(used, T), T, 0, s, used, t, pre, A.p, A.i, A.h, A.v, B.p, B.i, B.h, B.v);
+    GLMB_LAUNCH(k_compact_nodes, cdiv(used, T), T, 0, s, used, t, pre, A.p, A.i, A.h, A.v, A.b, B.p, B.i, B.h, B.v,
+                B.b);
     GLMB_LAUNCH(k_remap_pos, 1, 64, 0, s, pre, scal, used, level_first, *cursor, level_end, scal + 4);
     GLMB_HIP(hipMemcpyAsync(hs, scal, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     GLMB_HIP(hipStreamSynchronize(s));
@@ -505,7 +523,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
           }
         }
       }
-      GLMB_LAUNCH(k_expand, cdiv(te, T), T, 0, s, cursor, m, (int)te, used, pre, A.p, A.i, A.h, A.v, in.it_off,
+      GLMB_LAUNCH(k_expand, cdiv(te, T), T, 0, s, cursor, m, (int)te, used, pre, A.p, A.i, A.h, A.v, A.b, in.it_off,
                   in.it_delta, in.it_group, t);
       used += (int)te;
       cursor += m;
@@ -518,7 +536,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
       if (raise_and_compact(&c)) last_raise = used;
     }
   }
-  if (!fast && in.prefer_multi && used < kBlockNodes / 64) *in.prefer_multi = false;
+  if (!fast && in.prefer_multi && used < kBlockNodes / 4) *in.prefer_multi = false;
   tr("final", used, levels);
   // candidates: every node >= t, in enumeration order
   int32_t* fl = need<int32_t>(b.flags, used + 1);
