@@ -300,21 +300,36 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
       clo[threadIdx.x] = lo;
       if (threadIdx.x == 0) sel[2] = 0;
       __syncthreads();
-      const int64_t room = (int64_t)cap - used;
+      // Expand a prefix of the chunk whose extensions fit a soft room of about the store's
+      // current size (at least 2K), so that the threshold is raised (below) before the store
+      // grows much further; the hard room is what the store can still hold.
+      const int64_t hard = (int64_t)cap - used;
+      const int64_t soft = min(hard, max(2 * (int64_t)K, (int64_t)used));
       int take = nchunk;
       int64_t te = tot;
-      if (tot > room) {
-        // nodes of the chunk (a prefix) whose extensions still fit
-        if ((int)threadIdx.x < nchunk && excl + cnt <= room) atomicMax((unsigned long long*)&sel[2],
-                                                                       (unsigned long long)(threadIdx.x + 1));
+      if (tot > soft) {
+        if ((int)threadIdx.x < nchunk && excl + cnt <= soft)
+          atomicMax((unsigned long long*)&sel[2], (unsigned long long)(threadIdx.x + 1));
         __syncthreads();
         take = (int)sel[2];
-        if (take == 0) {
+        if (take == 0 && used >= K && used > last_raise) {
           const float b = sb_bound(nd_v, used, K, hist, sh, sel);
+          last_raise = used;
           if (b > t) {
             t = b;  // recount this chunk under the raised threshold
             continue;
           }
+        }
+        if (take == 0 && soft < hard) {
+          __syncthreads();
+          if (threadIdx.x == 0) sel[2] = 0;
+          __syncthreads();
+          if ((int)threadIdx.x < nchunk && excl + cnt <= hard)
+            atomicMax((unsigned long long*)&sel[2], (unsigned long long)(threadIdx.x + 1));
+          __syncthreads();
+          take = (int)sel[2];
+        }
+        if (take == 0) {
           status = 1;
           break;
         }
