@@ -488,6 +488,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
   };
 
   int last_raise = used;  // node count after the last threshold raise
+  int64_t created = used;  // nodes written by this search (compacted ones included)
   while (level_first < level_end) {
     ++levels;
     tr("level", levels, level_end - level_first);
@@ -541,6 +542,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
       GLMB_LAUNCH(k_expand, cdiv(te, T), T, 0, s, cursor, m, (int)te, used, pre, A.p, A.i, A.h, A.v, A.b, in.it_off,
                   in.it_delta, in.it_group, t);
       used += (int)te;
+      created += te;
       cursor += m;
     }
     const int next_first = level_end, next_end = used;
@@ -551,8 +553,9 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
       if (raise_and_compact(&c)) last_raise = used;
     }
   }
-  if (!fast && in.prefer_multi && used < kBlockNodes / 4) *in.prefer_multi = false;
+  if (!fast && in.prefer_multi && created < kBlockNodes / 4) *in.prefer_multi = false;
   tr("final", used, levels);
+  tr("created", created, fast ? 1 : 0);
   // candidates: every node >= t, in enumeration order
   int32_t* fl = need<int32_t>(b.flags, used + 1);
   int32_t* pre = need<int32_t>(b.pre, used + 1);
