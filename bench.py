@@ -34,6 +34,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=1)
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--batch-scenes", type=int, default=256, help="scenes of the batched leg (0: skip it)")
+    ap.add_argument("--no-autotune-cache", action="store_true")
     ap.add_argument("--proposal", default=None, help="trained proposal (.npz); default: the packaged one")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -136,6 +138,44 @@ def main():
             "proposal_file": os.path.relpath(prop_path, ROOT),
         }
 
+    batched = None
+    if args.batch_scenes > 0:
+        from paper_2512_06230_amd.autotune import BatchTuner, workload_key
+        from paper_2512_06230_amd.glmb import Batch
+        nb_warm, nb_steps = 6, 5
+        specs = sc.batch_specs(args.batch_scenes, seed=args.seed, n_steps=nb_warm + nb_steps)
+        bscenes = [sc.make_scene(sp, n_steps=nb_warm + nb_steps) for sp, _ in specs]
+        bparams = [sc.filter_params(sp, h, 1e-5) for sp, h in specs]
+        bz, boff = [], []
+        for k in range(nb_warm + nb_steps):  # every scan of every scene resident in HBM
+            zk = [bs.meas[k] for bs in bscenes]
+            boff.append(np.concatenate([[0], np.cumsum([z.shape[0] for z in zk])]).astype(np.int32))
+            bz.append(torch.as_tensor(np.concatenate(zk, axis=0).reshape(-1, 2), device=dev).contiguous())
+        batch = Batch(bparams, workers=4)
+        for i, bs in enumerate(bscenes):
+            batch.scene(i).import_state(sc.warm_start_state(bs))
+        cost = sum(h * float(bz[0].shape[0]) / len(bscenes) for _, h in specs)
+        tuner = BatchTuner(batch, workload_key(torch.cuda.get_device_name(0), len(bscenes), cost),
+                           cache_path=None if args.no_autotune_cache else os.path.join(
+                               ROOT, "paper_2512_06230_amd", "autotune_cache.json"))
+        for k in range(nb_warm):
+            tuner.step(k, bz[k], boff[k])
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for k in range(nb_warm, nb_warm + nb_steps):
+            tuner.step(k, bz[k], boff[k])
+        torch.cuda.synchronize()
+        el_b = time.perf_counter() - tb
+        bst = batch.stats()
+        batched = {"value": len(bscenes) * nb_steps / el_b, "unit": "scene-updates/s",
+                   "ms_per_step": 1e3 * el_b / nb_steps, "scenes": len(bscenes), "steps": nb_steps,
+                   "warmup": nb_warm, "workers": bst["workers"], "longest_first": bool(bst["longest_first"]),
+                   "workload": "%d scenes: N ~ U{5..200} objects, H_max ~ logU[256, 8192], clutter 2/scan, "
+                               "100x100 m, warm start" % len(bscenes),
+                   "mean_h_max": float(np.mean([h for _, h in specs])),
+                   "mean_objects": float(np.mean([sp.n_obj for sp, _ in specs]))}
+        batch.close()
+
     # roofline of the dominant kernel: the per-(hypothesis, detection) association kernel.
     # Algorithmic HBM bytes per launch: the hypothesis rows read (H x stride x 4 B) plus the three
     # per-cell outputs written (best option 2 B, first deviation 4 B, relative log-sum-exp 4 B).
@@ -180,6 +220,8 @@ def main():
     }
     if learned is not None:
         out["learned"] = learned
+    if batched is not None:
+        out["batched"] = batched
 
     if not args.no_cpu_baseline:
         from oracle.oracle import Oracle

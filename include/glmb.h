@@ -179,13 +179,18 @@ glmb_status glmb_update_theta(glmb_ctx* ctx, int32_t n_hyp, int32_t M, int32_t* 
 #define GLMB_MLP_NPARAM 4673
 #define GLMB_MLP_NFEAT 6
 
-/* Enable the proposal for the following updates (params_dev: device float32 parameters,
- * copied before the call returns; NULL disables it).  A pair is removed when
- * sigmoid(logit) < threshold, 0 < threshold < 1.  measure != 0: each update first measures,
- * on the full association space, the posterior mass the removal loses (stats.lost_mass;
- * costs one extra pass over the hypotheses). Synchronises. */
+/* Load the proposal's parameters (params_dev: device float32 [GLMB_MLP_NPARAM], copied
+ * before the call returns; NULL unloads them and makes every update plain).  flags:
+ * GLMB_PROPOSAL_APPLY: the following updates remove every pair with
+ *   sigmoid(logit) < threshold (0 < threshold < 1);
+ * GLMB_PROPOSAL_MEASURE: each such update first measures, on the full association space,
+ *   the posterior mass the removal loses (stats.lost_mass; one extra pass over the
+ *   hypotheses).
+ * With flags = 0 the parameters serve glmb_proposal_lost only. Synchronises. */
+#define GLMB_PROPOSAL_APPLY 1
+#define GLMB_PROPOSAL_MEASURE 2
 glmb_status glmb_set_proposal(glmb_ctx* ctx, const float* params_dev, const float* norm, float threshold,
-                              int32_t measure);
+                              int32_t flags);
 
 /* Training data from the current (predicted) state and the M detections of scan k
  * (z_dev as in glmb_update); the state is unchanged.  For every gated pair:
@@ -200,7 +205,7 @@ glmb_status glmb_pair_features(glmb_ctx* ctx, int32_t k, const float* z_dev, int
                                float* feat_dev, int32_t* pair_dev, float* target_dev, float* weight_dev,
                                int32_t* n_pairs);
 
-/* Posterior mass the proposal with the parameters of glmb_set_proposal would remove, for
+/* Posterior mass the proposal with the loaded parameters (glmb_set_proposal) would remove, for
  * each of T thresholds (host thresholds[T], 1 <= T <= 16, each in (0, 1); host lost[T]),
  * on the current predicted state and the detections of scan k; the state is unchanged.
  * lost = 1 - Z_kept / Z_full with Z the total weight of every association map of every
@@ -225,6 +230,42 @@ glmb_status glmb_mlp_grad(glmb_ctx* ctx, const float* params_dev, const float* n
                           float* loss_dev);
 glmb_status glmb_mlp_adam(glmb_ctx* ctx, float* params_dev, float* m_dev, float* v_dev, const float* grad_dev,
                           int32_t t, float lr, float beta1, float beta2, float eps);
+
+/* ---- Batched scenes -------------------------------------------------------------------
+ * An addition to the method (the paper filters one scene): many independent scenes of uneven
+ * size advance one time step in one call.  Each scene is a context of its own (its state,
+ * parameters and statistics); host worker threads, each driving its own HIP stream, pull the
+ * scenes in longest-job-first order of the cost estimate H * M * (1 + gated tracks per
+ * detection) of the previous step (H * M on the first) and run glmb_predict, glmb_update and
+ * glmb_truncate(h_max, tau) on them.  A scene's result equals that of its own single-scene
+ * calls bit for bit, whatever the number of workers or the order. */
+#define GLMB_BATCH_MAX_WORKERS 16
+typedef struct glmb_batch glmb_batch;
+
+typedef struct {
+  int32_t n_scenes, workers, longest_first;
+  float step_ms;               /* wall time of the last glmb_batch_step (host clock)          */
+  double scene_updates_per_s;  /* n_scenes / step time                                        */
+  int32_t first_error_scene;   /* -1 if every scene succeeded                                  */
+} glmb_batch_stats;
+
+/* n scenes with parameters params[n] on HIP device `device`; 1 <= workers <= 16 worker
+ * streams (created by the batch, default priority).  Every scene starts as glmb_create's. */
+glmb_status glmb_batch_create(int32_t n, const glmb_params* params, int device, int32_t workers,
+                              glmb_batch** out);
+glmb_status glmb_batch_destroy(glmb_batch* b);
+/* Schedule of the following steps: number of workers, longest-job-first (1) or index order (0). */
+glmb_status glmb_batch_set_schedule(glmb_batch* b, int32_t workers, int32_t longest_first);
+/* The context of scene `scene` (owned by the batch: valid until glmb_batch_destroy, not to be
+ * destroyed by the caller) for import, export, estimate and statistics. */
+glmb_status glmb_batch_scene(glmb_batch* b, int32_t scene, glmb_ctx** out);
+/* One time step k of every scene.  z_dev: device float32 [z_off[n]][2], the detections of
+ * scene s are rows z_off[s] .. z_off[s+1]); z_off: host int32 [n+1], z_off[0] = 0,
+ * non-decreasing.  Synchronises.  On failure the status of the first failing scene is returned
+ * (glmb_batch_last_error names it) and the other scenes have still been stepped. */
+glmb_status glmb_batch_step(glmb_batch* b, int32_t k, const float* z_dev, const int32_t* z_off);
+glmb_status glmb_batch_stats_get(glmb_batch* b, glmb_batch_stats* out);
+const char* glmb_batch_last_error(const glmb_batch* b);
 
 #ifdef __cplusplus
 }

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libglmb.so")
-SOURCES = ["primitives.hip", "select.hip", "predict.hip", "update.hip", "proposal.hip", "api.hip"]
+SOURCES = ["primitives.hip", "select.hip", "predict.hip", "update.hip", "proposal.hip", "api.hip", "batch.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of every kernel
@@ -33,7 +33,7 @@ def build(verbose: bool = False) -> str:
         if verbose and text.strip():
             print(text)
     tmp = LIB + ".tmp"
-    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs)
     os.replace(tmp, LIB)
     return LIB
 

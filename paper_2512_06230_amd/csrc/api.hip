@@ -7,10 +7,6 @@
 
 #include "ctx.hpp"
 
-struct glmb_ctx {
-  glmb::Ctx c;
-};
-
 namespace glmb {
 
 // ------------------------------------------------------------------ truncation

@@ -138,3 +138,8 @@ __device__ __forceinline__ void cv_predict(const CV& cv, float* m, float* P) {
 }
 
 }  // namespace glmb
+
+// the opaque context of the C ABI
+struct glmb_ctx {
+  glmb::Ctx c;
+};

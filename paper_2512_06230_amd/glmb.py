@@ -19,7 +19,9 @@ GLMB_OK, GLMB_E_ARG, GLMB_E_CAPACITY, GLMB_E_NOMEM, GLMB_E_DEVICE, GLMB_E_STATE 
 EXPORTS = ["glmb_status_string", "glmb_last_error", "glmb_create", "glmb_destroy", "glmb_import_state",
            "glmb_state_sizes", "glmb_export_state", "glmb_predict", "glmb_update", "glmb_truncate",
            "glmb_estimate", "glmb_stats", "glmb_update_diag", "glmb_update_theta", "glmb_set_proposal",
-           "glmb_pair_features", "glmb_proposal_lost", "glmb_mlp_forward", "glmb_mlp_grad", "glmb_mlp_adam"]
+           "glmb_pair_features", "glmb_proposal_lost", "glmb_mlp_forward", "glmb_mlp_grad", "glmb_mlp_adam",
+           "glmb_batch_create", "glmb_batch_destroy", "glmb_batch_set_schedule", "glmb_batch_scene",
+           "glmb_batch_step", "glmb_batch_stats_get", "glmb_batch_last_error"]
 
 MLP_NPARAM, MLP_NFEAT = 4673, 6
 PROPOSAL_APPLY, PROPOSAL_MEASURE = 1, 2
@@ -53,6 +55,12 @@ class StepStats(ctypes.Structure):
                 ("search_levels", ctypes.c_int32), ("n_births", ctypes.c_int32),
                 ("retained_mass", ctypes.c_double), ("lost_mass", ctypes.c_double),
                 ("pairs_removed", ctypes.c_int32), ("stage_ms", ctypes.c_float * 6)]
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("n_scenes", ctypes.c_int32), ("workers", ctypes.c_int32), ("longest_first", ctypes.c_int32),
+                ("step_ms", ctypes.c_float), ("scene_updates_per_s", ctypes.c_double),
+                ("first_error_scene", ctypes.c_int32)]
 
 
 _lib = None
@@ -91,9 +99,17 @@ def load_library(path: str = LIB_PATH):
     L.glmb_mlp_grad.argtypes = [vp, vp, _F, vp, vp, vp, ctypes.c_int32, vp, vp]
     L.glmb_mlp_adam.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float]
+    L.glmb_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_int, ctypes.c_int32,
+                                    ctypes.POINTER(vp)]
+    L.glmb_batch_destroy.argtypes = [vp]
+    L.glmb_batch_set_schedule.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
+    L.glmb_batch_scene.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(vp)]
+    L.glmb_batch_step.argtypes = [vp, ctypes.c_int32, vp, _I]
+    L.glmb_batch_stats_get.argtypes = [vp, ctypes.POINTER(BatchStats)]
+    L.glmb_batch_last_error.argtypes = [vp]
     for name in EXPORTS:
-        getattr(L, name).restype = ctypes.c_int if name not in ("glmb_status_string", "glmb_last_error") \
-            else ctypes.c_char_p
+        getattr(L, name).restype = ctypes.c_int if name not in ("glmb_status_string", "glmb_last_error",
+                                                                "glmb_batch_last_error") else ctypes.c_char_p
     _lib = L
     return L
 
@@ -123,15 +139,19 @@ def _fp(a):
 class Tracker:
     """One filter context on a HIP device, driven on a torch stream."""
 
-    def __init__(self, params: dict, device: int = 0, stream=None):
+    def __init__(self, params: dict, device: int = 0, stream=None, _ctx=None, _owner=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU: the GLMB library runs on the GPU only")
         self._L = load_library()
         self.torch = torch
         self.device = device
-        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         self.params = dict(params)
+        if _ctx is not None:  # a context owned by a Batch
+            self._ctx = _ctx
+            self._owner = _owner
+            return
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         ctx = ctypes.c_void_p()
         st = self._L.glmb_create(ctypes.byref(_params(params)), device, ctypes.c_void_p(self.stream.cuda_stream),
                                  ctypes.byref(ctx))
@@ -145,7 +165,8 @@ class Tracker:
 
     def close(self):
         if getattr(self, "_ctx", None):
-            self._L.glmb_destroy(self._ctx)
+            if getattr(self, "_owner", None) is None:
+                self._L.glmb_destroy(self._ctx)
             self._ctx = None
 
     def __del__(self):
@@ -350,3 +371,65 @@ class Tracker:
         ps = [self._dev(a, (MLP_NPARAM,)) for a in (params, m, v, g)]
         self._check(self._L.glmb_mlp_adam(self._ctx, *[ctypes.c_void_p(a.data_ptr()) for a in ps], int(step),
                                           float(lr), float(beta1), float(beta2), float(eps)), "glmb_mlp_adam")
+
+
+class Batch:
+    """Many independent scenes advanced one time step per call (glmb_batch_*)."""
+
+    def __init__(self, params_list, device: int = 0, workers: int = 4):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the GLMB library runs on the GPU only")
+        self._L = load_library()
+        self.torch = torch
+        self.params = [dict(p) for p in params_list]
+        arr = (Params * len(self.params))(*[_params(p) for p in self.params])
+        b = ctypes.c_void_p()
+        st = self._L.glmb_batch_create(len(self.params), arr, device, int(workers), ctypes.byref(b))
+        if st != GLMB_OK:
+            raise GlmbError(st, "glmb_batch_create: " + self._L.glmb_status_string(st).decode())
+        self._b = b
+        self.n = len(self.params)
+
+    def _check(self, st: int, what: str):
+        if st != GLMB_OK:
+            raise GlmbError(st, "%s: %s" % (what, self._L.glmb_batch_last_error(self._b).decode()))
+
+    def scene(self, i: int) -> Tracker:
+        """The scene's context as a Tracker (owned by the batch)."""
+        ctx = ctypes.c_void_p()
+        self._check(self._L.glmb_batch_scene(self._b, int(i), ctypes.byref(ctx)), "glmb_batch_scene")
+        return Tracker(self.params[i], _ctx=ctx, _owner=self)
+
+    def set_schedule(self, workers: int, longest_first: bool = True):
+        self._check(self._L.glmb_batch_set_schedule(self._b, int(workers), int(bool(longest_first))),
+                    "glmb_batch_set_schedule")
+
+    def step(self, k: int, z, z_off):
+        """z: CUDA float32 [total, 2] (all scenes' detections, concatenated); z_off: host int [n+1]."""
+        t = self.torch
+        if not (isinstance(z, t.Tensor) and z.is_cuda and z.dtype == t.float32 and z.is_contiguous()
+                and z.dim() == 2 and z.shape[1] == 2):
+            raise ValueError("detections must be a contiguous CUDA float32 tensor of shape [total, 2]")
+        off = np.ascontiguousarray(np.asarray(z_off, np.int32).reshape(-1))
+        if off.shape[0] != self.n + 1:
+            raise ValueError("z_off must hold n + 1 offsets")
+        self._z_keep = z
+        self._check(self._L.glmb_batch_step(self._b, int(k), ctypes.c_void_p(z.data_ptr()), _ip(off)),
+                    "glmb_batch_step")
+
+    def stats(self) -> dict:
+        s = BatchStats()
+        self._check(self._L.glmb_batch_stats_get(self._b, ctypes.byref(s)), "glmb_batch_stats_get")
+        return {f: getattr(s, f) for f, _ in BatchStats._fields_}
+
+    def close(self):
+        if getattr(self, "_b", None):
+            self._L.glmb_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -297,3 +297,17 @@ def mlp_init(seed: int, n_in: int = 6, n_hid: int = 64) -> np.ndarray:
              rng.uniform(-a2, a2, n_hid * n_hid), np.zeros(n_hid),
              rng.uniform(-a3, a3, n_hid), np.zeros(1)]
     return np.concatenate(parts).astype(np.float32)
+
+
+def batch_specs(n_scenes: int = 256, seed: int = 0, n_min: int = 5, n_max: int = 200,
+                h_lo: int = 256, h_hi: int = 8192, n_steps: int = 50):
+    """Many independent scenes of uneven size: scene s has seed `seed + s`, N ~ U{n_min..n_max}
+    objects of the c1 model (100x100 m, clutter Poisson(2)) and H_max = round(exp(U[ln h_lo,
+    ln h_hi])).  Returns a list of (SceneSpec, H_max)."""
+    rng = np.random.default_rng(10_000 + seed)
+    out = []
+    for s in range(n_scenes):
+        n = int(rng.integers(n_min, n_max + 1))
+        h = int(round(math.exp(rng.uniform(math.log(h_lo), math.log(h_hi)))))
+        out.append((spec_for("c1", n_obj=n, seed=seed + s, n_steps=n_steps), h))
+    return out

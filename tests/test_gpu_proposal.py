@@ -223,7 +223,7 @@ def test_learned_update_matches_oracle_with_removed_pairs(torch_cuda, seed):
         d_o = o.diag(len(st["hyp_logw"]))
         g = _tracker(p)
         g.import_state(st)
-        g.set_proposal(g.to_device(params), norm, t, measure=True)
+        g.set_proposal(g.to_device(params), norm, t, apply=True, measure=True)
         lost_g = g.proposal_lost(K_SCAN, z, [t])[0]
         g.update(K_SCAN, z)
         stats = g.stats()
@@ -260,7 +260,7 @@ def test_lost_mass_at_several_thresholds(torch_cuda, seed):
     ts = sorted(set(ts))
     g = _tracker(BASE)
     g.import_state(st)
-    g.set_proposal(g.to_device(params), norm, 0.5)
+    g.set_proposal(g.to_device(params), norm, apply=False)
     lost = g.proposal_lost(K_SCAN, z, ts)
     g.close()
     prev = -1.0
