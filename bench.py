@@ -36,6 +36,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batch-scenes", type=int, default=256, help="scenes of the batched leg (0: skip it)")
     ap.add_argument("--no-autotune-cache", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a known-size kernel that scales "
+                         "hardware byte counters)")
     ap.add_argument("--proposal", default=None, help="trained proposal (.npz); default: the packaged one")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -48,6 +51,14 @@ def main():
     from paper_2512_06230_amd import scenarios as sc
     from paper_2512_06230_amd.glmb import Tracker
 
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     clutter = 0.2 * args.n_obj if args.clutter is None else args.clutter
     spec = sc.spec_for("c3:%d" % args.n_obj, clutter_mean=clutter, seed=args.seed)
     n_scans = args.warmup + args.steps
@@ -142,7 +153,7 @@ def main():
     if args.batch_scenes > 0:
         from paper_2512_06230_amd.autotune import BatchTuner, workload_key
         from paper_2512_06230_amd.glmb import Batch
-        nb_warm, nb_steps = 6, 5
+        nb_warm, nb_steps = 12, 5  # warm-up steps also serve the schedule tuner when its cache misses
         specs = sc.batch_specs(args.batch_scenes, seed=args.seed, n_steps=nb_warm + nb_steps)
         bscenes = [sc.make_scene(sp, n_steps=nb_warm + nb_steps) for sp, _ in specs]
         bparams = [sc.filter_params(sp, h, 1e-5) for sp, h in specs]

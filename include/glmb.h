@@ -100,8 +100,8 @@ typedef struct {
                                when enabled by glmb_set_proposal; 0 otherwise)           */
   int32_t pairs_removed;    /* gated pairs the learned proposal removed                   */
   /* stage durations of the last update from HIP events on the context's stream (ms):
-   * [0] gate + score, [1] association normalisers (the per-(hypothesis, detection) kernel
-   * alone), [2] cut bound + deviation items + selection, [3] materialise + Kalman,
+   * [0] gate + score (through the per-label lists and hypothesis 0's cells), [1] the
+   * per-(hypothesis, detection) association kernel of hypotheses 1..H-1 alone, [2] cut bound + deviation items + selection, [3] materialise + Kalman,
    * [4] births, [5] whole update */
   float stage_ms[6];
 } glmb_step_stats;

@@ -12,11 +12,9 @@ import json
 import math
 import os
 
-import numpy as np
-
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "autotune_cache.json")
-CANDIDATES = [(1, True), (2, True), (4, True), (8, True), (16, True), (8, False)]
+CANDIDATES = [(1, True), (2, True), (4, True), (8, True), (16, True), (16, False)]
 
 
 def workload_key(device_name: str, n_scenes: int, cost: float) -> str:
@@ -47,24 +45,24 @@ class BatchTuner:
         return self.choice is not None
 
     def step(self, k: int, z, z_off):
-        """One batched step; while untuned, the step measures the next candidate schedule."""
+        """One batched step; while untuned, the step measures the next candidate schedule.
+
+        The candidates are measured in a palindromic order (c1 .. cn cn .. c1): the first
+        steps of a run grow heavier as the state fills up to H_max, and summing each
+        candidate's two times cancels a trend that is linear in the step number."""
         if self.tuned:
             self.batch.step(k, z, z_off)
             return
-        cand = self.candidates[len(self.trials)]
+        seq = self.candidates + self.candidates[::-1]
+        cand = seq[len(self.trials)]
         self.batch.set_schedule(*cand)
         self.batch.step(k, z, z_off)
         self.trials.append((cand, float(self.batch.stats()["step_ms"])))
-        if len(self.trials) == len(self.candidates):
-            # the first steps of a run can be heavier than later ones (the state grows toward
-            # H_max), so each candidate's time is compared with its neighbours' through a fit
-            # of the per-step trend: the residual decides
-            t = np.array([ms for _, ms in self.trials])
-            x = np.arange(len(t), dtype=np.float64)
-            slope, icpt = np.polyfit(x, t, 1) if len(t) > 2 else (0.0, 0.0)
-            resid = t - (slope * x + icpt) if len(t) > 2 else t
-            best = int(np.argmin(resid))
-            self.choice = self.trials[best][0]
+        if len(self.trials) == len(seq):
+            total = {}
+            for c, ms in self.trials:
+                total[c] = total.get(c, 0.0) + ms
+            self.choice = min(self.candidates, key=lambda c: total[c])
             self.batch.set_schedule(*self.choice)
             self.cache[self.key] = {"workers": self.choice[0], "longest_first": self.choice[1],
                                     "trials": [{"workers": c[0], "longest_first": c[1], "step_ms": ms}
@@ -74,3 +72,8 @@ class BatchTuner:
                 with open(tmp, "w") as f:
                     json.dump(self.cache, f, indent=1, sort_keys=True)
                 os.replace(tmp, self.cache_path)
+
+    @property
+    def warmup_steps(self) -> int:
+        """Steps the tuner still needs before its choice is made (0 when cached)."""
+        return 0 if self.tuned else 2 * len(self.candidates) - len(self.trials)

@@ -1001,13 +1001,13 @@ void assoc_norm(Ctx& c, int M) {
   float* lzprime = need<float>(c.lzprime, H);
   float* ref_b1 = need<float>(c.ref_b1, M + 1);
   int32_t* ref_opts = need<int32_t>(c.ref_opts, M + 1);
-  c.mark(1);
   GLMB_LAUNCH(k_assoc_ref, 1, 256, SW * sizeof(int32_t), s, M, SW, c.rows.as<int32_t>(), c.logw.as<float>(),
               c.ntrk.as<int32_t>(), p.det_rate, lgk, c.coff.as<int32_t>(), c.cand.as<int32_t>(), c.phi.as<float>(),
               c.cmax.as<uint32_t>(), best16, dev1, lserel, bprime, lzprime, ref_b1, ref_opts, nopts, ndense);
   const size_t lds = (size_t)(SW + (M + 31) / 32) * sizeof(int32_t);
   if (lds > 64 * 1024)
     GLMB_HIP(hipFuncSetAttribute((const void*)k_assoc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  c.mark(1);  // the events bracket k_assoc alone
   GLMB_LAUNCH(k_assoc, H - 1, 256, lds, s, M, SW, c.rows.as<int32_t>(), c.logw.as<float>(), c.ntrk.as<int32_t>(),
               p.det_rate, lgk, c.coff.as<int32_t>(), c.cand.as<int32_t>(), c.phi.as<float>(), c.cmax.as<uint32_t>(),
               c.loff.as<int32_t>(), c.llen.as<int32_t>(), c.lmeas.as<int32_t>(), ref_b1, ref_opts, best16, dev1,
