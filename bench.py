@@ -187,22 +187,27 @@ def main():
                    "mean_objects": float(np.mean([sp.n_obj for sp, _ in specs]))}
         batch.close()
 
-    # roofline of the dominant kernel: the per-(hypothesis, detection) association kernel.
-    # Algorithmic HBM bytes per launch: the hypothesis rows read (H x stride x 4 B) plus the three
+    # roofline of the dominant kernel: the per-(hypothesis, detection) association kernel, which
+    # covers hypotheses 1..H-1 (hypothesis 0's cells come from a one-workgroup kernel before it).
+    # Algorithmic HBM bytes per launch: each hypothesis row read once (L x 4 B) plus the three
     # per-cell outputs written (best option 2 B, first deviation 4 B, relative log-sum-exp 4 B).
     H = np.mean([s["n_hyp_in"] for s in stats])
     M = np.mean([s["n_meas"] for s in stats])
     L = np.mean([s["n_labels"] for s in stats])
-    bytes_assoc = H * L * 4.0 + H * M * 10.0
+    bytes_assoc = (H - 1.0) * (L * 4.0 + M * 10.0)
     t_assoc = float(stage[1]) * 1e-3
     achieved = bytes_assoc / t_assoc / 1e9 if t_assoc > 0 else 0.0
+    # measured HBM bytes per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a copy kernel);
+    # null once the kernel's source differs from the one the counters were taken with
     traffic = None
-    tf = os.path.join(ROOT, "profiles", "assoc_traffic_n500_h1e4.json")
+    tf = os.path.join(ROOT, "profiles", "k_assoc_n500_h1e4_traffic.json")
     if os.path.exists(tf):
-        try:
-            traffic = json.load(open(tf)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+        import hashlib
+        rec = json.load(open(tf))
+        src = os.path.join(ROOT, rec["source"])
+        if os.path.exists(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == rec["source_sha256"] \
+                and args.n_obj == 500 and args.h_max == 10000:
+            traffic = rec["bytes_per_launch"]
     out = {
         "metric": METRIC,
         "value": args.steps / elapsed,
