@@ -135,7 +135,8 @@ struct Selected {
 };
 struct SelectBufs {
   DevBuf nd_parent, nd_item, nd_h, nd_value, nd_bloom, cnt, pre, pre64, flags, map, tmp, tk, tv, keys, vals, sel_node,
-      sel_val, sel_rank, scal;
+      sel_val, sel_rank, scal, hist;
+  bool hist_ready = false;  // hist holds zeros (the cooperative search leaves it so)
 };
 glmb_status select_topk(const SelectIn& in, int cap_nodes, SelectBufs& b, Selected& out, hipStream_t s,
                         std::string& err, bool trace = false);

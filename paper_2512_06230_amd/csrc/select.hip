@@ -18,6 +18,10 @@
 // present, and a stable sort by (value desc, key) of those yields the exact top-K: the
 // enumeration order is (level, parent rank, positions), so a stable sort by parent rank
 // gives the canonical key order.
+#include <hip/hip_cooperative_groups.h>
+
+#include <atomic>
+
 #include "common.hpp"
 
 namespace glmb {
@@ -388,6 +392,331 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
   }
 }
 
+// ---------------------------------------------------------------- cooperative search
+// The same level-synchronous search as one cooperative launch on the whole GPU: every
+// workgroup runs the same loop, the phases (count, scan, expand, threshold raise, compaction)
+// are separated by grid-wide barriers, and every control decision is computed identically by
+// all workgroups from values in global memory written before the last barrier, so the
+// barriers are always reached by every workgroup the same number of times.
+constexpr int kCB = 256;          // threads per workgroup
+constexpr int kChunk = 1 << 16;   // nodes of a level expanded per iteration at most
+
+struct CoopArgs {
+  int P;
+  const float* base;
+  const int32_t* it_off;
+  const float* it_delta;
+  const int32_t* it_group;
+  int K;
+  const float* t0;
+  int cap;
+  int32_t* np[2];
+  int32_t* ni[2];
+  int32_t* nh[2];
+  float* nv[2];
+  uint64_t* nb[2];
+  int32_t* cnt;     // [kChunk] extension counts of the chunk's nodes
+  int64_t* pre;     // [kChunk] their exclusive prefix
+  int32_t* map;     // [cap] compaction: kept nodes before each node
+  int64_t* part;    // [gridDim.x] per-workgroup partial sums
+  int32_t* hist;    // [2][4096] K-th value histograms (zero on entry, zero on exit)
+  int32_t* out;     // used, levels, status, which
+  float* t_out;
+};
+
+namespace {
+namespace cg = cooperative_groups;
+
+__device__ __forceinline__ void grid_barrier() {
+  __threadfence();
+  cg::this_grid().sync();
+}
+
+// exclusive scan of one value per thread of the workgroup (kCB threads); total in *tot
+__device__ __forceinline__ int64_t cb_excl_scan(int64_t v, int64_t* lds, int64_t* tot) {
+  const int lane = lane_id(), w = threadIdx.x / kWave;
+  int64_t x = v;
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const int64_t y = __shfl_up(x, d, kWave);
+    if (lane >= d) x += y;
+  }
+  __syncthreads();
+  if (lane == kWave - 1) lds[w] = x;
+  __syncthreads();
+  int64_t before = 0, all = 0;
+  for (int j = 0; j < kCB / kWave; ++j) {
+    const int64_t y = lds[j];
+    if (j < w) before += y;
+    all += y;
+  }
+  *tot = all;
+  return x - v + before;
+}
+
+__device__ __forceinline__ int64_t cb_sum(int64_t v, int64_t* lds) {
+  int64_t tot;
+  (void)cb_excl_scan(v, lds, &tot);
+  return tot;
+}
+
+// exclusive scan over the grid of f(0..n-1): out(i, prefix) for every i; returns the total
+// (in every thread).  Each workgroup scans one contiguous range.  The caller places a grid
+// barrier before the outputs are read.
+template <class F, class O>
+__device__ int64_t grid_scan(int n, F f, O out, int64_t* part, int64_t* lds) {
+  const int G = gridDim.x, b = blockIdx.x;
+  const int per = (n + G - 1) / G;
+  const int lo = min(n, b * per), hi = min(n, lo + per);
+  int64_t s = 0;
+  for (int i = lo + (int)threadIdx.x; i < hi; i += kCB) s += f(i);
+  s = cb_sum(s, lds);
+  if (threadIdx.x == 0) part[b] = s;
+  grid_barrier();
+  int64_t off = 0, tot = 0;
+  for (int j = threadIdx.x; j < G; j += kCB) {
+    const int64_t v = part[j];
+    tot += v;
+    if (j < b) off += v;
+  }
+  off = cb_sum(off, lds);
+  tot = cb_sum(tot, lds);
+  int64_t carry = off;
+  for (int base = lo; base < hi; base += kCB) {
+    const int i = base + (int)threadIdx.x;
+    const int64_t v = i < hi ? f(i) : 0;
+    int64_t t;
+    const int64_t ex = cb_excl_scan(v, lds, &t);
+    if (i < hi) out(i, carry + ex);
+    carry += t;
+  }
+  return tot;
+}
+
+// bin (from the top) holding the K-th largest count of a 4096-bin histogram in global memory;
+// every workgroup computes the same result.  *need_k: in the rank, out the rank in the bin.
+__device__ int pick_bin(const int32_t* hist, int64_t* need_k, int64_t* lds, int32_t* sel) {
+  constexpr int per = 4096 / kCB;
+  const int t = threadIdx.x;
+  int64_t mine = 0;
+  for (int j = 0; j < per; ++j) mine += hist[per * t + j];
+  int64_t tot;
+  const int64_t excl = cb_excl_scan(mine, lds, &tot);
+  const int64_t above = tot - excl - mine;
+  if (t == 0) sel[0] = -1;
+  __syncthreads();
+  const int64_t K = *need_k;
+  if (above < K && above + mine >= K) {
+    int64_t acc = above;
+    int bb = per * t + per - 1;
+    for (; bb > per * t; --bb) {
+      if (acc + hist[bb] >= K) break;
+      acc += hist[bb];
+    }
+    sel[0] = bb;
+    sel[1] = (int32_t)(K - acc);
+  }
+  __syncthreads();
+  const int r = sel[0];
+  if (r >= 0) *need_k = sel[1];
+  __syncthreads();
+  return r;
+}
+
+// lower edge of the 24-bit orderable bin holding the K-th largest of v[0..n) (-inf if n < K)
+__device__ float grid_kth(const float* v, int n, int K, int32_t* hist, int32_t* lhist, int64_t* lds, int32_t* sel) {
+  if (n < K) return -INFINITY;
+  int64_t need = K;
+  uint32_t prefix = 0;
+  int bin2 = 0;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int j = threadIdx.x; j < 4096; j += kCB) lhist[j] = 0;
+    __syncthreads();
+    for (int i = blockIdx.x * kCB + threadIdx.x; i < n; i += gridDim.x * kCB) {
+      const uint32_t o = f2o(v[i]);
+      if (pass == 0) atomicAdd(&lhist[o >> 20], 1);
+      else if ((o >> 20) == prefix) atomicAdd(&lhist[(o >> 8) & 4095], 1);
+    }
+    __syncthreads();
+    int32_t* gh = hist + 4096 * pass;
+    for (int j = threadIdx.x; j < 4096; j += kCB)
+      if (lhist[j]) atomicAdd(&gh[j], lhist[j]);
+    grid_barrier();
+    const int b = pick_bin(gh, &need, lds, sel);
+    if (b < 0) {
+      bin2 = -1;
+      break;
+    }
+    if (pass == 0) prefix = (uint32_t)b;
+    else bin2 = b;
+  }
+  grid_barrier();  // every workgroup has read both histograms
+  if (blockIdx.x == 0)
+    for (int j = threadIdx.x; j < 2 * 4096; j += kCB) hist[j] = 0;
+  if (bin2 < 0) return -INFINITY;
+  const float e = o2f((prefix << 20) | ((uint32_t)bin2 << 8));
+  return e == e ? e : -INFINITY;
+}
+}  // namespace
+
+__global__ __launch_bounds__(kCB) void k_select_coop(CoopArgs a) {
+  extern __shared__ int32_t smem[];
+  int32_t* lhist = smem;                              // 4096
+  int64_t* lds = (int64_t*)(smem + 4096);             // 8
+  int32_t* sel = smem + 4096 + 16;                    // 2
+  const float nan = __uint_as_float(0xffc00000u);
+  float t = *a.t0;
+  int which = 0, status = 0;
+  // roots, in parent rank order
+  int used;
+  {
+    int32_t *P0 = a.np[0], *I0 = a.ni[0], *H0 = a.nh[0];
+    float* V0 = a.nv[0];
+    uint64_t* B0 = a.nb[0];
+    const float* base = a.base;
+    used = (int)grid_scan(a.P, [&](int h) -> int64_t { return base[h] >= t ? 1 : 0; },
+                          [&](int h, int64_t pos) {
+                            if (base[h] >= t) {
+                              P0[pos] = -1;
+                              I0[pos] = -1;
+                              H0[pos] = h;
+                              V0[pos] = base[h];
+                              B0[pos] = 0ull;
+                            }
+                          },
+                          a.part, lds);
+    grid_barrier();
+  }
+  int lfirst = 0, lend = used, cursor = 0, levels = 1, last_raise = used;
+
+  // raise the threshold to the bin of the K-th largest node value; compact if it rose
+  auto raise = [&]() {
+    const float t2 = grid_kth(a.nv[which], used, a.K, a.hist, lhist, lds, sel);
+    last_raise = used;
+    if (!(t2 > t)) return;
+    t = t2;
+    const float* V = a.nv[which];
+    int32_t* map = a.map;
+    const int kept = (int)grid_scan(used, [&](int i) -> int64_t { return V[i] >= t ? 1 : 0; },
+                                    [&](int i, int64_t pos) { map[i] = (int32_t)pos; }, a.part, lds);
+    grid_barrier();
+    const int o = which ^ 1;
+    for (int i = blockIdx.x * kCB + threadIdx.x; i < used; i += gridDim.x * kCB) {
+      if (!(V[i] >= t)) continue;
+      const int d = map[i];
+      const int p = a.np[which][i];
+      a.np[o][d] = p >= 0 ? map[p] : -1;
+      a.ni[o][d] = a.ni[which][i];
+      a.nh[o][d] = a.nh[which][i];
+      a.nv[o][d] = V[i];
+      a.nb[o][d] = a.nb[which][i];
+    }
+    auto remap = [&](int x) { return x < used ? map[x] : kept; };
+    lfirst = remap(lfirst);
+    lend = remap(lend);
+    cursor = remap(cursor);
+    grid_barrier();
+    which = o;
+    used = kept;
+    last_raise = kept;
+  };
+
+  for (;;) {
+    if (cursor >= lend) {  // the level is complete
+      lfirst = lend;
+      lend = used;
+      cursor = lfirst;
+      if (lfirst >= lend) break;
+      if (++levels > kMaxDepth + 1) {
+        status = 2;
+        break;
+      }
+      if (used >= a.K && used > last_raise) raise();
+      continue;
+    }
+    const int nchunk = min(lend - cursor, kChunk);
+    const int32_t* NI = a.ni[which];
+    const int32_t* NH = a.nh[which];
+    const float* NV = a.nv[which];
+    for (int j = blockIdx.x * kCB + threadIdx.x; j < nchunk; j += gridDim.x * kCB) {
+      int lo, hi;
+      ext_range(cursor + j, NI, NH, NV, a.it_off, a.it_delta, t, &lo, &hi);
+      a.cnt[j] = hi - lo;
+    }
+    grid_barrier();
+    const int32_t* cnt = a.cnt;
+    int64_t* pre = a.pre;
+    (void)grid_scan(nchunk, [&](int j) -> int64_t { return cnt[j]; }, [&](int j, int64_t x) { pre[j] = x; },
+                    a.part, lds);
+    grid_barrier();
+    // largest prefix of the chunk whose extensions fit the room (monotone)
+    auto fit = [&](int64_t room) {
+      int lo2 = 0, hi2 = nchunk;
+      while (lo2 < hi2) {
+        const int m = (lo2 + hi2 + 1) >> 1;
+        if (pre[m - 1] + cnt[m - 1] <= room) lo2 = m;
+        else hi2 = m - 1;
+      }
+      return lo2;
+    };
+    const int64_t hard = (int64_t)a.cap - used;
+    const int64_t soft = min(hard, max(2 * (int64_t)a.K, (int64_t)used));
+    int m = fit(soft);
+    if (m == 0 && soft < hard) m = fit(hard);
+    if (m == 0) {
+      if (used >= a.K && used > last_raise) {
+        raise();  // a higher threshold shrinks the counts
+        continue;
+      }
+      status = 1;
+      break;
+    }
+    const int64_t te = pre[m - 1] + cnt[m - 1];
+    {
+      int32_t *NP = a.np[which], *NIw = a.ni[which], *NHw = a.nh[which];
+      float* NVw = a.nv[which];
+      uint64_t* NB = a.nb[which];
+      for (int64_t e = blockIdx.x * kCB + threadIdx.x; e < te; e += (int64_t)gridDim.x * kCB) {
+        int x0 = 0, x1 = m - 1;  // last node with pre <= e
+        while (x0 < x1) {
+          const int c = (x0 + x1 + 1) >> 1;
+          if (pre[c] <= e) x0 = c;
+          else x1 = c - 1;
+        }
+        const int nn = cursor + x0;
+        const int lo = NIw[nn] < 0 ? a.it_off[NHw[nn]] : NIw[nn] + 1;
+        const int q = lo + (int)(e - pre[x0]);
+        float v = NVw[nn] - a.it_delta[q];
+        const int g = a.it_group[q];
+        const uint64_t pb = NB[nn], gb = group_bit(g);
+        if (pb & gb)
+          for (int x = nn; NIw[x] >= 0; x = NP[x])
+            if (a.it_group[NIw[x]] == g) {
+              v = nan;  // two picks in one group: not a child
+              break;
+            }
+        const int o = used + (int)e;
+        NB[o] = pb | gb;
+        NP[o] = nn;
+        NIw[o] = q;
+        NHw[o] = NHw[nn];
+        NVw[o] = v;
+      }
+    }
+    grid_barrier();
+    used += (int)te;
+    cursor += m;
+    if (used >= a.K && used >= 2 * last_raise) raise();
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.out[0] = used;
+    a.out[1] = levels;
+    a.out[2] = status;
+    a.out[3] = which;
+    *a.t_out = t;
+  }
+}
+
 namespace {
 struct Nodes {
   int32_t *p, *i, *h;
@@ -395,6 +724,28 @@ struct Nodes {
   uint64_t* b;
 };
 }  // namespace
+
+// Workgroups of the cooperative search: one per compute unit when the device supports
+// cooperative launches and that many fit at once (0: use the multi-kernel levels).
+constexpr size_t kCoopLds = (4096 + 16 + 4) * sizeof(int32_t);
+namespace {
+std::atomic<int> g_coop_grid{-1};  // per process (one device type)
+}
+static int coop_grid(size_t lds) {
+  const int known = g_coop_grid.load();
+  if (known >= 0) return known;
+  int dev = 0, ncu = 0, coop = 0, per = 0;
+  g_coop_grid = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_select_coop, kCB, lds) != hipSuccess ||
+      per < 1)
+    return 0;
+  g_coop_grid = ncu;
+  return ncu;
+}
+static void coop_disable() { g_coop_grid = 0; }
 
 glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& out, hipStream_t s, std::string& err,
                         bool trace) {
@@ -446,7 +797,67 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
     tr("block", used, hs[2]);
     if (in.prefer_multi) *in.prefer_multi = !fast;
   }
+  // On the whole GPU: one cooperative launch when the device supports it, else the
+  // host-driven multi-kernel levels below.
+  bool coop = false;
   if (!fast) {
+    int G = coop_grid(kCoopLds);
+    if (G > 0) {
+      CoopArgs ca{};
+      ca.P = in.P;
+      ca.base = in.base;
+      ca.it_off = in.it_off;
+      ca.it_delta = in.it_delta;
+      ca.it_group = in.it_group;
+      ca.K = in.K;
+      ca.t0 = in.t0;
+      ca.cap = cap;
+      const Nodes* nb2[2] = {&A, &B};
+      for (int j = 0; j < 2; ++j) {
+        ca.np[j] = nb2[j]->p;
+        ca.ni[j] = nb2[j]->i;
+        ca.nh[j] = nb2[j]->h;
+        ca.nv[j] = nb2[j]->v;
+        ca.nb[j] = nb2[j]->b;
+      }
+      ca.cnt = need<int32_t>(b.flags, std::max(kChunk, in.P) + 1);
+      ca.pre = need<int64_t>(b.pre64, kChunk + 1);
+      ca.map = need<int32_t>(b.map, (int64_t)cap + 1);
+      ca.part = need<int64_t>(b.cnt, G + 1);
+      if (!b.hist_ready) {
+        int32_t* hz = need<int32_t>(b.hist, 2 * 4096);
+        GLMB_HIP(hipMemsetAsync(hz, 0, 2 * 4096 * sizeof(int32_t), s));  // the kernel leaves it zeroed
+        b.hist_ready = true;
+      }
+      ca.hist = b.hist.as<int32_t>();
+      ca.out = scal + 4;
+      ca.t_out = t;
+      void* args[] = {&ca};
+      const hipError_t e = hipLaunchCooperativeKernel((const void*)k_select_coop, dim3(G), dim3(kCB), args,
+                                                      kCoopLds, s);
+      if (e == hipSuccess) {
+        GLMB_HIP(hipMemcpyAsync(hs, scal + 4, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        GLMB_HIP(hipStreamSynchronize(s));
+        used = hs[0];
+        levels = hs[1];
+        tr("coop", used, hs[2]);
+        if (hs[2] == 1) {
+          err = "selection: search node capacity exhausted (tie class at the cut larger than the node store?)";
+          return GLMB_E_CAPACITY;
+        }
+        if (hs[2] == 2) {
+          err = "selection: deeper than the supported number of deviations";
+          return GLMB_E_CAPACITY;
+        }
+        if (hs[3]) std::swap(A, B);
+        coop = true;
+      } else {
+        (void)hipGetLastError();  // not launchable here: the multi-kernel levels take over
+        coop_disable();
+      }
+    }
+  }
+  if (!fast && !coop) {
     // roots
     GLMB_HIP(hipMemcpyAsync(t, in.t0, sizeof(float), hipMemcpyDeviceToDevice, s));
     int32_t* fl = need<int32_t>(b.flags, in.P + 1);
@@ -458,7 +869,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
     used = hs[0];
     levels = 0;
   }
-  int level_first = 0, level_end = fast ? 0 : used;
+  int level_first = 0, level_end = (fast || coop) ? 0 : used;
 
   // raise t to a bound on the K-th largest node value and drop nodes below it
   auto raise_and_compact = [&](int* cursor) -> bool {
@@ -553,7 +964,8 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
       if (raise_and_compact(&c)) last_raise = used;
     }
   }
-  if (!fast && in.prefer_multi && created < kBlockNodes / 4) *in.prefer_multi = false;
+  if (!fast && !coop && in.prefer_multi && created < kBlockNodes / 4) *in.prefer_multi = false;
+  if (coop && in.prefer_multi && used < kBlockNodes / 16) *in.prefer_multi = false;
   tr("final", used, levels);
   tr("created", created, fast ? 1 : 0);
   // candidates: every node >= t, in enumeration order
