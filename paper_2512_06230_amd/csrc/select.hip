@@ -399,7 +399,8 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
 // all workgroups from values in global memory written before the last barrier, so the
 // barriers are always reached by every workgroup the same number of times.
 constexpr int kCB = 256;          // threads per workgroup
-constexpr int kChunk = 1 << 16;   // nodes of a level expanded per iteration at most
+constexpr int kChunk = 1 << 16;   // nodes of a level counted at once at most
+constexpr int kCoopGrid = 16;     // workgroups: the phases are short, so grid barriers dominate
 
 struct CoopArgs {
   int P;
@@ -621,11 +622,15 @@ __global__ __launch_bounds__(kCB) void k_select_coop(CoopArgs a) {
     last_raise = kept;
   };
 
+  // extension counts of the nodes [cbase, cend) under the current threshold, with their
+  // exclusive prefix; valid until the threshold changes, so a level is counted once per raise
+  int cbase = 0, cend = 0;
   for (;;) {
     if (cursor >= lend) {  // the level is complete
       lfirst = lend;
       lend = used;
       cursor = lfirst;
+      cbase = cend = 0;
       if (lfirst >= lend) break;
       if (++levels > kMaxDepth + 1) {
         status = 2;
@@ -634,27 +639,35 @@ __global__ __launch_bounds__(kCB) void k_select_coop(CoopArgs a) {
       if (used >= a.K && used > last_raise) raise();
       continue;
     }
-    const int nchunk = min(lend - cursor, kChunk);
     const int32_t* NI = a.ni[which];
     const int32_t* NH = a.nh[which];
     const float* NV = a.nv[which];
-    for (int j = blockIdx.x * kCB + threadIdx.x; j < nchunk; j += gridDim.x * kCB) {
-      int lo, hi;
-      ext_range(cursor + j, NI, NH, NV, a.it_off, a.it_delta, t, &lo, &hi);
-      a.cnt[j] = hi - lo;
+    if (cursor < cbase || cursor >= cend) {
+      const int nchunk = min(lend - cursor, kChunk);
+      for (int j = blockIdx.x * kCB + threadIdx.x; j < nchunk; j += gridDim.x * kCB) {
+        int lo, hi;
+        ext_range(cursor + j, NI, NH, NV, a.it_off, a.it_delta, t, &lo, &hi);
+        a.cnt[j] = hi - lo;
+      }
+      grid_barrier();
+      const int32_t* cnt0 = a.cnt;
+      int64_t* pre0 = a.pre;
+      (void)grid_scan(nchunk, [&](int j) -> int64_t { return cnt0[j]; }, [&](int j, int64_t x) { pre0[j] = x; },
+                      a.part, lds);
+      grid_barrier();
+      cbase = cursor;
+      cend = cursor + nchunk;
     }
-    grid_barrier();
-    const int32_t* cnt = a.cnt;
-    int64_t* pre = a.pre;
-    (void)grid_scan(nchunk, [&](int j) -> int64_t { return cnt[j]; }, [&](int j, int64_t x) { pre[j] = x; },
-                    a.part, lds);
-    grid_barrier();
-    // largest prefix of the chunk whose extensions fit the room (monotone)
+    const int off = cursor - cbase, avail = cend - cursor;
+    const int32_t* cnt = a.cnt + off;
+    const int64_t* pre = a.pre + off;
+    const int64_t p0 = pre[0];
+    // largest prefix of the counted nodes whose extensions fit the room (monotone)
     auto fit = [&](int64_t room) {
-      int lo2 = 0, hi2 = nchunk;
+      int lo2 = 0, hi2 = avail;
       while (lo2 < hi2) {
         const int m = (lo2 + hi2 + 1) >> 1;
-        if (pre[m - 1] + cnt[m - 1] <= room) lo2 = m;
+        if (pre[m - 1] + cnt[m - 1] - p0 <= room) lo2 = m;
         else hi2 = m - 1;
       }
       return lo2;
@@ -666,26 +679,28 @@ __global__ __launch_bounds__(kCB) void k_select_coop(CoopArgs a) {
     if (m == 0) {
       if (used >= a.K && used > last_raise) {
         raise();  // a higher threshold shrinks the counts
+        cbase = cend = 0;
         continue;
       }
       status = 1;
       break;
     }
-    const int64_t te = pre[m - 1] + cnt[m - 1];
+    const int64_t te = pre[m - 1] + cnt[m - 1] - p0;
     {
       int32_t *NP = a.np[which], *NIw = a.ni[which], *NHw = a.nh[which];
       float* NVw = a.nv[which];
       uint64_t* NB = a.nb[which];
       for (int64_t e = blockIdx.x * kCB + threadIdx.x; e < te; e += (int64_t)gridDim.x * kCB) {
-        int x0 = 0, x1 = m - 1;  // last node with pre <= e
+        const int64_t ee = e + p0;
+        int x0 = 0, x1 = m - 1;  // last node with pre <= ee
         while (x0 < x1) {
           const int c = (x0 + x1 + 1) >> 1;
-          if (pre[c] <= e) x0 = c;
+          if (pre[c] <= ee) x0 = c;
           else x1 = c - 1;
         }
         const int nn = cursor + x0;
         const int lo = NIw[nn] < 0 ? a.it_off[NHw[nn]] : NIw[nn] + 1;
-        const int q = lo + (int)(e - pre[x0]);
+        const int q = lo + (int)(ee - pre[x0]);
         float v = NVw[nn] - a.it_delta[q];
         const int g = a.it_group[q];
         const uint64_t pb = NB[nn], gb = group_bit(g);
@@ -706,7 +721,11 @@ __global__ __launch_bounds__(kCB) void k_select_coop(CoopArgs a) {
     grid_barrier();
     used += (int)te;
     cursor += m;
-    if (used >= a.K && used >= 2 * last_raise) raise();
+    if (used >= a.K && used >= 2 * last_raise) {
+      const float before = t;
+      raise();
+      if (t != before) cbase = cend = 0;
+    }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.out[0] = used;
@@ -742,8 +761,9 @@ static int coop_grid(size_t lds) {
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_select_coop, kCB, lds) != hipSuccess ||
       per < 1)
     return 0;
-  g_coop_grid = ncu;
-  return ncu;
+  const int G = std::min(ncu, kCoopGrid);
+  g_coop_grid = G;
+  return G;
 }
 static void coop_disable() { g_coop_grid = 0; }
 
@@ -965,7 +985,6 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
     }
   }
   if (!fast && !coop && in.prefer_multi && created < kBlockNodes / 4) *in.prefer_multi = false;
-  if (coop && in.prefer_multi && used < kBlockNodes / 16) *in.prefer_multi = false;
   tr("final", used, levels);
   tr("created", created, fast ? 1 : 0);
   // candidates: every node >= t, in enumeration order
@@ -982,10 +1001,8 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
   while ((1 << hbits) < in.P) ++hbits;
   sort_pairs(keys, vals, nc, 0, ((hbits + 7) / 8) * 8, b.tk, b.tv, b.tmp, s);  // canonical key order
   GLMB_LAUNCH(k_final_keys, cdiv(nc, T), T, 0, s, nc, vals, A.v, keys, vals);
-  int rbits = 0;
-  while ((1 << rbits) < nc) ++rbits;
-  sort_pairs(keys, vals, nc, 0, 32 + 32, b.tk, b.tv, b.tmp, s);
-  (void)rbits;
+  // stable sort on the value bits only: the input is in canonical key order already
+  sort_pairs(keys, vals, nc, 32, 64, b.tk, b.tv, b.tmp, s);
   const int n = std::min(nc, in.K);
   out.node = need<int32_t>(b.sel_node, n + 1);
   out.value = need<float>(b.sel_val, n + 1);
