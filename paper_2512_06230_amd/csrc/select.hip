@@ -421,7 +421,7 @@ struct CoopArgs {
   int32_t* map;     // [cap] compaction: kept nodes before each node
   int64_t* part;    // [gridDim.x] per-workgroup partial sums
   int32_t* hist;    // [2][4096] K-th value histograms (zero on entry, zero on exit)
-  int32_t* out;     // used, levels, status, which
+  int32_t* out;     // used, levels, status, which, nodes created
   float* t_out;
 };
 
@@ -625,6 +625,7 @@ __global__ __launch_bounds__(kCB) void k_select_coop(CoopArgs a) {
   // extension counts of the nodes [cbase, cend) under the current threshold, with their
   // exclusive prefix; valid until the threshold changes, so a level is counted once per raise
   int cbase = 0, cend = 0;
+  int64_t created = used;
   for (;;) {
     if (cursor >= lend) {  // the level is complete
       lfirst = lend;
@@ -720,6 +721,7 @@ __global__ __launch_bounds__(kCB) void k_select_coop(CoopArgs a) {
     }
     grid_barrier();
     used += (int)te;
+    created += te;
     cursor += m;
     if (used >= a.K && used >= 2 * last_raise) {
       const float before = t;
@@ -732,6 +734,7 @@ __global__ __launch_bounds__(kCB) void k_select_coop(CoopArgs a) {
     a.out[1] = levels;
     a.out[2] = status;
     a.out[3] = which;
+    a.out[4] = (int32_t)min(created, (int64_t)INT32_MAX);
     *a.t_out = t;
   }
 }
@@ -792,7 +795,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
     return GLMB_E_CAPACITY;
   }
   Nodes A = alloc(0), B = alloc(1);
-  int32_t* scal = need<int32_t>(b.scal, 16);   // [0]=total, [1..2]=cut, [4..6]=remap
+  int32_t* scal = need<int32_t>(b.scal, 32);   // [0]=total, [1..2]=cut, [4..6]=remap, [8..9] t, [16..20] coop
   float* t = (float*)(scal + 8);               // current threshold
   float* t2 = (float*)(scal + 9);
   GLMB_HIP(hipMemcpyAsync(t, in.t0, sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -850,17 +853,19 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
         b.hist_ready = true;
       }
       ca.hist = b.hist.as<int32_t>();
-      ca.out = scal + 4;
+      ca.out = scal + 16;
       ca.t_out = t;
       void* args[] = {&ca};
       const hipError_t e = hipLaunchCooperativeKernel((const void*)k_select_coop, dim3(G), dim3(kCB), args,
                                                       kCoopLds, s);
       if (e == hipSuccess) {
-        GLMB_HIP(hipMemcpyAsync(hs, scal + 4, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        GLMB_HIP(hipMemcpyAsync(hs, scal + 16, 5 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         GLMB_HIP(hipStreamSynchronize(s));
         used = hs[0];
         levels = hs[1];
-        tr("coop", used, hs[2]);
+        tr("coop", used, hs[4]);
+        // a search that created few nodes fits one workgroup: try that first next time
+        if (in.prefer_multi && hs[2] == 0 && hs[4] < kBlockNodes / 4) *in.prefer_multi = false;
         if (hs[2] == 1) {
           err = "selection: search node capacity exhausted (tie class at the cut larger than the node store?)";
           return GLMB_E_CAPACITY;
