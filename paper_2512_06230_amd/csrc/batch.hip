@@ -57,6 +57,9 @@ glmb_status glmb_batch_create(int32_t n, const glmb_params* params, int device, 
       glmb_batch_destroy(b);
       return st;
     }
+    // cooperative launches run one at a time on a device: concurrent scenes use the
+    // multi-kernel form of the whole-GPU search, which overlaps across streams
+    b->ctx[i]->c.coop_ok = false;
   }
   *out = b;
   return GLMB_OK;

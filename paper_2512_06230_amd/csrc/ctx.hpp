@@ -68,6 +68,7 @@ struct Ctx {
       tmp, tk, tv, flags, pre, pmult, pvals, rec_m, ref_b1, ref_opts;
   SelectBufs sb;
   bool sel_multi[2] = {false, false};  // per search site (prediction, update): start on the whole GPU
+  bool coop_ok = true;  // cooperative launches allowed (they run one at a time on a device)
   int LW = 1;  // detection-set mask width (32-bit words) of the last gate
 
   // ---- learned pair proposal

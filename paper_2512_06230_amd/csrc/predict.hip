@@ -381,7 +381,7 @@ void stage_predict(Ctx& c, int k) {
   GLMB_LAUNCH(k_pitem_off, cdiv(H + 1, T), T, 0, s, H, nitem, ik, itoff);
   // ---- exact selection
   trace(c, "predict.select", nitem);
-  SelectIn si{H, V, itoff, itd, itg, p.h_max, t0, &c.sel_multi[0]};
+  SelectIn si{H, V, itoff, itd, itg, p.h_max, t0, &c.sel_multi[0], c.coop_ok};
   Selected sel{};
   std::string serr;
   const int cap_nodes = p.cap_nodes > 0 ? p.cap_nodes : (1 << 22);

@@ -823,7 +823,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
   // On the whole GPU: one cooperative launch when the device supports it, else the
   // host-driven multi-kernel levels below.
   bool coop = false;
-  if (!fast) {
+  if (!fast && in.allow_coop) {
     int G = coop_grid(kCoopLds);
     if (G > 0) {
       CoopArgs ca{};

@@ -1116,7 +1116,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   int32_t* itoff = need<int32_t>(c.it_off, H + 1);
   GLMB_LAUNCH(k_item_off, cdiv(H + 1, T), T, 0, s, H, nitem, ikeys, itoff);
 
-  SelectIn si{H, bprime, itoff, itd, itg, K, t0, &c.sel_multi[1]};
+  SelectIn si{H, bprime, itoff, itd, itg, K, t0, &c.sel_multi[1], c.coop_ok};
   trace(c, "update.select", ncell, nitem);
   Selected sel{};
   std::string serr;
