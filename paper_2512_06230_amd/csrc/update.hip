@@ -46,15 +46,15 @@ __global__ __launch_bounds__(256) void k_gate(const DInst* inst, int U, const fl
   const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   const int nch = (M + kWave - 1) / kWave;
   const int u = gw / nch, ch = gw % nch;
-  if (u >= U) return;
   const int lane = lane_id();
   const int i = ch * kWave + lane;
-  const DInst& x = inst[u];
-  const float s00 = x.P[0] + sig2, s01 = x.P[1], s11 = x.P[4] + sig2;
-  const float det = s00 * s11 - s01 * s01;
+  const bool live = u < U;  // waves past the last instance only join the workgroup barrier
   bool g = false;
   float f = -INFINITY;
-  if (i < M) {
+  if (live && i < M) {
+    const DInst& x = inst[u];
+    const float s00 = x.P[0] + sig2, s01 = x.P[1], s11 = x.P[4] + sig2;
+    const float det = s00 * s11 - s01 * s01;
     const float2 zi = z[i];
     const float n0 = zi.x - x.m[0], n1 = zi.y - x.m[1];
     const float qd = s11 * n0 * n0 - 2.0f * s01 * n0 * n1 + s00 * n1 * n1;
@@ -65,10 +65,17 @@ __global__ __launch_bounds__(256) void k_gate(const DInst* inst, int U, const fl
     if (g) atomicMax(&cmax[i], f2o(f));
   }
   const uint64_t bal = __ballot(g);
-  if (lane == 0) {
+  if (live && lane == 0) {
     gbits[(size_t)u * W + 2 * ch] = (uint32_t)bal;
     if (2 * ch + 1 < W) gbits[(size_t)u * W + 2 * ch + 1] = (uint32_t)(bal >> 32);
-    if (bal) atomicAdd(ngated, (unsigned long long)__popcll(bal));
+  }
+  // one counter update per workgroup
+  __shared__ int32_t wg[4];
+  if (lane == 0) wg[threadIdx.x / kWave] = __popcll(bal);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int n = wg[0] + wg[1] + wg[2] + wg[3];
+    if (n) atomicAdd(ngated, (unsigned long long)n);
   }
 }
 
@@ -173,13 +180,8 @@ __device__ __forceinline__ CellOut assoc_cell(int i, int M, const int32_t* row, 
   float b1 = lgk, b2 = -INFINITY, mx = lgk, sm = 1.0f;
   int k1 = -1;
   unsigned opts = 0;
-  const int e1 = coff[i + 1];
-  for (int e = coff[i]; e < e1; ++e) {
-    const int s = cand[e];
-    const int u = row[s];
-    if (u < 0) continue;
-    const float f = phi[(size_t)u * M + i];
-    if (!(f > -INFINITY)) continue;
+  auto take = [&](int s, float f) {
+    if (!(f > -INFINITY)) return;  // label absent from the hypothesis, or not gated
     ++opts;
     if (f > b1) {
       b2 = b1;
@@ -194,6 +196,24 @@ __device__ __forceinline__ CellOut assoc_cell(int i, int M, const int32_t* row, 
     } else {
       sm += __expf(f - mx);
     }
+  };
+  auto gather = [&](int u) { return u >= 0 ? phi[(size_t)u * M + i] : -INFINITY; };
+  const int e1 = coff[i + 1];
+  int e = coff[i];
+  // eight independent gathers in flight, then the options in candidate order
+  for (; e + 8 <= e1; e += 8) {
+    int sv[8];
+    float fv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) sv[j] = cand[e + j];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) fv[j] = gather(row[sv[j]]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) take(sv[j], fv[j]);
+  }
+  for (; e < e1; ++e) {
+    const int s = cand[e];
+    take(s, gather(row[s]));
   }
   const float l = mx + __logf(sm);
   best16[cell] = (int16_t)(k1 + 1);
@@ -202,21 +222,21 @@ __device__ __forceinline__ CellOut assoc_cell(int i, int M, const int32_t* row, 
   return CellOut{b1, l, opts};
 }
 
+// per-hypothesis results; the option count goes to hopts[h] (summed later in a fixed order:
+// one global counter updated by every workgroup would serialise ten thousand atomics)
 __device__ __forceinline__ void assoc_finish(int h, float bsum, float lsum, unsigned opts, const float* logw,
-                                             const int32_t* ntrk, float gamma, int M, float* bprime, float* lzprime,
-                                             unsigned long long* nopts, unsigned long long* ndense, float* red) {
+                                             const int32_t* ntrk, float gamma, float* bprime, float* lzprime,
+                                             int32_t* hopts, float* red) {
   bsum = block_sum_f(bsum, red);
   lsum = block_sum_f(lsum, red + 8);
+  const float o = block_sum_f((float)opts, red);  // exact: counts stay far below 2^24
   if (threadIdx.x == 0) {
     // the miss terms relative to hypothesis 0's track count keep the values small
     const float base = logw[h] - gamma * (float)(ntrk[h] - ntrk[0]);
     bprime[h] = base + bsum;
     lzprime[h] = base + lsum;
-    atomicAdd(ndense, (unsigned long long)ntrk[h] * (unsigned long long)M);
+    hopts[h] = (int32_t)o;
   }
-  // option count (integer; order irrelevant)
-  for (int d = kWave / 2; d > 0; d >>= 1) opts += __shfl_xor(opts, d, kWave);
-  if (lane_id() == 0 && opts) atomicAdd(nopts, (unsigned long long)opts);
 }
 
 // Hypothesis 0 (one workgroup, row in LDS): every cell, plus the reference values the other
@@ -226,7 +246,7 @@ __global__ __launch_bounds__(256) void k_assoc_ref(int M, int stride, const int3
                                                    const int32_t* cand, const float* phi, const uint32_t* cmax,
                                                    int16_t* best16, float* dev1, float* lserel, float* bprime,
                                                    float* lzprime, float* ref_b1, int32_t* ref_opts,
-                                                   unsigned long long* nopts, unsigned long long* ndense) {
+                                                   int32_t* hopts) {
   extern __shared__ int32_t row[];
   __shared__ float red[16];
   for (int s = threadIdx.x; s < stride; s += blockDim.x) row[s] = rows[s];
@@ -243,35 +263,60 @@ __global__ __launch_bounds__(256) void k_assoc_ref(int M, int stride, const int3
     lsum += o.l - c;
     opts += o.opts;
   }
-  assoc_finish(0, bsum, lsum, opts, logw, ntrk, gamma, M, bprime, lzprime, nopts, ndense, red);
+  assoc_finish(0, bsum, lsum, opts, logw, ntrk, gamma, bprime, lzprime, hopts, red);
 }
 
 // Hypotheses 1..H-1, one workgroup each (row in LDS).  A cell's options depend only on the
-// instances of the labels gated with its detection, so only the detections gated with a
-// label whose instance differs from hypothesis 0's (including presence) are recomputed;
-// every other cell is a copy of hypothesis 0's.  The sums run over the cells in the same
-// order with the same per-cell values, so the results equal a full recomputation bit for bit.
+// instances of the labels gated with its detection, so a cell whose labels hold the same
+// instances as in hypothesis 0 is a copy of hypothesis 0's cell.  A cell that differs is
+// derived from hypothesis 0's: its options lose the changed labels' old instances and gain
+// their new ones, so with S = sum over options of exp(phi - c_i) (= exp(lserel)),
+//   S_h = S_0 - sum(removed) + sum(added),
+// and the best option and first deviation follow from hypothesis 0's best and second best
+// and the added options.  The cell is recomputed from all its options instead when a removed
+// option is hypothesis 0's best or could be its second best, or when the removed options
+// carry more than half of S_0 (the difference would lose precision).
 __global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t* rows, const float* logw,
                                                const int32_t* ntrk, float gamma, float lgk,
                                                const int32_t* coff, const int32_t* cand, const float* phi,
                                                const uint32_t* cmax, const int32_t* loff, const int32_t* llen,
-                                               const int32_t* lmeas, const float* ref_b1, const int32_t* ref_opts,
-                                               int16_t* best16, float* dev1, float* lserel, float* bprime,
-                                               float* lzprime, unsigned long long* nopts,
-                                               unsigned long long* ndense) {
-  extern __shared__ int32_t row[];  // row[stride] | touched-detection bits[(M + 31) / 32]
+                                               const int32_t* lmeas, const uint32_t* lbits, const float* ref_b1,
+                                               const int32_t* ref_opts, int16_t* best16, float* dev1, float* lserel,
+                                               float* bprime, float* lzprime, int32_t* hopts) {
+  // LDS: row[stride] | changed slots, ascending[stride] | touched-detection bits[(M + 31) / 32]
+  extern __shared__ int32_t row[];
   __shared__ float red[16];
+  __shared__ int32_t wcnt[8];
   const int h = blockIdx.x + 1;
   const int W = (M + 31) / 32;
-  uint32_t* touched = (uint32_t*)(row + stride);
+  int32_t* dl = row + stride;
+  uint32_t* touched = (uint32_t*)(dl + stride);
   for (int s = threadIdx.x; s < stride; s += blockDim.x) row[s] = rows[(size_t)h * stride + s];
   for (int w = threadIdx.x; w < W; w += blockDim.x) touched[w] = 0u;
   __syncthreads();
-  for (int s = threadIdx.x; s < stride; s += blockDim.x) {
-    if (row[s] == rows[s]) continue;
+  // changed slots in ascending order (ballot prefix per wave, waves in order)
+  int nd = 0;
+  const int lane = lane_id(), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  for (int s0 = 0; s0 < stride; s0 += blockDim.x) {
+    const int s = s0 + (int)threadIdx.x;
+    const bool f = s < stride && row[s] != rows[s];
+    const uint64_t bal = __ballot(f);
+    if (lane == 0) wcnt[wv] = __popcll(bal);
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int j = 0; j < nw; ++j) {
+      before += j < wv ? wcnt[j] : 0;
+      all += wcnt[j];
+    }
+    if (f) dl[nd + before + __popcll(bal & lanemask_lt())] = s;
+    nd += all;
+    __syncthreads();
+  }
+  for (int q = threadIdx.x; q < nd; q += blockDim.x) {
+    const int s = dl[q];
     const int b = loff[s], e = b + llen[s];
-    for (int q = b; q < e; ++q) {
-      const int i = lmeas[q];
+    for (int r = b; r < e; ++r) {
+      const int i = lmeas[r];
       atomicOr(&touched[i >> 5], 1u << (i & 31));
     }
   }
@@ -280,14 +325,7 @@ __global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t*
   unsigned opts = 0;
   for (int i = threadIdx.x; i < M; i += blockDim.x) {
     const size_t cell = (size_t)h * M + i;
-    if ((touched[i >> 5] >> (i & 31)) & 1u) {
-      const float c = o2f(cmax[i]);
-      const CellOut o = assoc_cell(i, M, row, lgk, coff, cand, phi, best16, dev1, cell, c);
-      lserel[cell] = o.l - c;
-      bsum += o.b1 - c;
-      lsum += o.l - c;
-      opts += o.opts;
-    } else {
+    if (!((touched[i >> 5] >> (i & 31)) & 1u)) {
       best16[cell] = best16[i];
       dev1[cell] = dev1[i];
       const float ls = lserel[i];
@@ -295,16 +333,98 @@ __global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t*
       bsum += ref_b1[i];
       lsum += ls;
       opts += (unsigned)ref_opts[i];
+      continue;
+    }
+    const float c = o2f(cmax[i]);
+    const float s_ref = __expf(lserel[i]);
+    const int k1r = (int)best16[i] - 1;
+    const float b1r = ref_b1[i] + c;
+    const float d1r = dev1[i];
+    const float b2r = d1r < INFINITY ? b1r - d1r : -INFINITY;
+    float rem = 0.0f, add = 0.0f, nb1 = b1r, nb2 = b2r;
+    int nk1 = k1r, dopt = 0;
+    bool full = false;
+    const uint32_t bit = 1u << (i & 31);
+    for (int q = 0; q < nd && !full; ++q) {
+      const int s = dl[q];
+      if (!(lbits[(size_t)s * W + (i >> 5)] & bit)) continue;
+      const int u0 = rows[s], uh = row[s];
+      if (u0 >= 0) {
+        const float f0 = phi[(size_t)u0 * M + i];
+        if (f0 > -INFINITY) {
+          if (s == k1r || f0 >= b2r) full = true;
+          rem += __expf(f0 - c);
+          --dopt;
+        }
+      }
+      if (uh >= 0) {
+        const float fh = phi[(size_t)uh * M + i];
+        if (fh > -INFINITY) {
+          add += __expf(fh - c);
+          ++dopt;
+          if (fh > nb1 || (fh == nb1 && s < nk1)) {
+            nb2 = nb1;
+            nb1 = fh;
+            nk1 = s;
+          } else if (fh > nb2) {
+            nb2 = fh;
+          }
+        }
+      }
+    }
+    if (full || rem > 0.5f * s_ref) {
+      const CellOut o = assoc_cell(i, M, row, lgk, coff, cand, phi, best16, dev1, cell, c);
+      lserel[cell] = o.l - c;
+      bsum += o.b1 - c;
+      lsum += o.l - c;
+      opts += o.opts;
+    } else {
+      const float lc = __logf(s_ref - rem + add);
+      best16[cell] = (int16_t)(nk1 + 1);
+      dev1[cell] = nb2 > -INFINITY ? nb1 - nb2 : INFINITY;
+      lserel[cell] = lc;
+      bsum += nb1 - c;
+      lsum += lc;
+      opts += (unsigned)(ref_opts[i] + dopt);
     }
   }
-  assoc_finish(h, bsum, lsum, opts, logw, ntrk, gamma, M, bprime, lzprime, nopts, ndense, red);
+  assoc_finish(h, bsum, lsum, opts, logw, ntrk, gamma, bprime, lzprime, hopts, red);
 }
 
 // ------------------------------------------------------------------ U3
 // one block: log of the total mass, per-parent diagnostics
-__global__ __launch_bounds__(1024) void k_norm(int H, const float* bprime, const float* lzprime, float* lz,
-                                               float* diag_best, float* diag_logpi) {
+__global__ __launch_bounds__(1024) void k_norm(int H, int M, const float* bprime, const float* lzprime,
+                                               const int32_t* hopts, const int32_t* ntrk, float* lz,
+                                               float* diag_best, float* diag_logpi, unsigned long long* nopts,
+                                               unsigned long long* ndense) {
   __shared__ float red[32];
+  __shared__ unsigned long long ired[32];
+  {
+    // statistics: options of every cell, and sum_h |J_h| * M
+    unsigned long long o = 0, d = 0;
+    for (int h = threadIdx.x; h < H; h += blockDim.x) {
+      o += (unsigned long long)hopts[h];
+      d += (unsigned long long)ntrk[h] * (unsigned long long)M;
+    }
+    for (int k = kWave / 2; k > 0; k >>= 1) {
+      o += __shfl_xor(o, k, kWave);
+      d += __shfl_xor(d, k, kWave);
+    }
+    if (lane_id() == 0) {
+      ired[threadIdx.x / kWave] = o;
+      ired[16 + threadIdx.x / kWave] = d;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long so = 0, sd = 0;
+      for (int j = 0; j < (int)(blockDim.x / kWave); ++j) {
+        so += ired[j];
+        sd += ired[16 + j];
+      }
+      *nopts = so;
+      *ndense = sd;
+    }
+  }
   float mx = -INFINITY;
   for (int h = threadIdx.x; h < H; h += blockDim.x) mx = fmaxf(mx, lzprime[h]);
   mx = block_max_f(mx, red);
@@ -1001,21 +1121,23 @@ void assoc_norm(Ctx& c, int M) {
   float* lzprime = need<float>(c.lzprime, H);
   float* ref_b1 = need<float>(c.ref_b1, M + 1);
   int32_t* ref_opts = need<int32_t>(c.ref_opts, M + 1);
+  int32_t* hopts = need<int32_t>(c.hopts, H + 1);
   GLMB_LAUNCH(k_assoc_ref, 1, 256, SW * sizeof(int32_t), s, M, SW, c.rows.as<int32_t>(), c.logw.as<float>(),
               c.ntrk.as<int32_t>(), p.det_rate, lgk, c.coff.as<int32_t>(), c.cand.as<int32_t>(), c.phi.as<float>(),
-              c.cmax.as<uint32_t>(), best16, dev1, lserel, bprime, lzprime, ref_b1, ref_opts, nopts, ndense);
-  const size_t lds = (size_t)(SW + (M + 31) / 32) * sizeof(int32_t);
+              c.cmax.as<uint32_t>(), best16, dev1, lserel, bprime, lzprime, ref_b1, ref_opts, hopts);
+  const size_t lds = (size_t)(2 * SW + (M + 31) / 32) * sizeof(int32_t);
   if (lds > 64 * 1024)
     GLMB_HIP(hipFuncSetAttribute((const void*)k_assoc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   c.mark(1);  // the events bracket k_assoc alone
   GLMB_LAUNCH(k_assoc, H - 1, 256, lds, s, M, SW, c.rows.as<int32_t>(), c.logw.as<float>(), c.ntrk.as<int32_t>(),
               p.det_rate, lgk, c.coff.as<int32_t>(), c.cand.as<int32_t>(), c.phi.as<float>(), c.cmax.as<uint32_t>(),
-              c.loff.as<int32_t>(), c.llen.as<int32_t>(), c.lmeas.as<int32_t>(), ref_b1, ref_opts, best16, dev1,
-              lserel, bprime, lzprime, nopts, ndense);
+              c.loff.as<int32_t>(), c.llen.as<int32_t>(), c.lmeas.as<int32_t>(), c.lbits.as<uint32_t>(), ref_b1,
+              ref_opts, best16, dev1, lserel, bprime, lzprime, hopts);
   c.mark(2);
   float* dbest = need<float>(c.diag_best, H);
   float* dlogpi = need<float>(c.diag_logpi, H);
-  GLMB_LAUNCH(k_norm, 1, 1024, 0, s, H, bprime, lzprime, lz, dbest, dlogpi);
+  GLMB_LAUNCH(k_norm, 1, 1024, 0, s, H, M, bprime, lzprime, hopts, c.ntrk.as<int32_t>(), lz, dbest, dlogpi, nopts,
+              ndense);
 }
 
 void stage_update(Ctx& c, int k, const float* zin, int M) {
