@@ -183,6 +183,7 @@ def main():
                    "warmup": nb_warm, "workers": bst["workers"], "longest_first": bool(bst["longest_first"]),
                    "workload": "%d scenes: N ~ U{5..200} objects, H_max ~ logU[256, 8192], clutter 2/scan, "
                                "100x100 m, warm start" % len(bscenes),
+                   "tuner_trials": [{"workers": c[0], "longest_first": c[1], "step_ms": ms} for c, ms in tuner.trials],
                    "mean_h_max": float(np.mean([h for _, h in specs])),
                    "mean_objects": float(np.mean([sp.n_obj for sp, _ in specs]))}
         batch.close()

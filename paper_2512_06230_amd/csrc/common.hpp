@@ -120,6 +120,7 @@ struct SelectIn {
   const float* t0;        // device scalar: a lower bound on the K-th best child value
   bool* prefer_multi;     // per call site: the previous search outgrew one workgroup (may be null)
   bool allow_coop = true; // the whole-GPU search may be one cooperative launch
+  bool refine = false;    // tighten t0 with the counting bound before searching
 };
 struct Selected {
   int n;                  // number of selected children (<= K)
@@ -136,8 +137,9 @@ struct Selected {
 };
 struct SelectBufs {
   DevBuf nd_parent, nd_item, nd_h, nd_value, nd_bloom, cnt, pre, pre64, flags, map, tmp, tk, tv, keys, vals, sel_node,
-      sel_val, sel_rank, scal, hist;
+      sel_val, sel_rank, scal, hist, dp, dpc, dpa;
   bool hist_ready = false;  // hist holds zeros (the cooperative search leaves it so)
+  bool dpc_ready = false;   // dpc holds zeros (the counting bound leaves it so)
 };
 glmb_status select_topk(const SelectIn& in, int cap_nodes, SelectBufs& b, Selected& out, hipStream_t s,
                         std::string& err, bool trace = false);

@@ -83,8 +83,37 @@ __global__ __launch_bounds__(kScanT) void k_scan_add(I* out, int n, const I* sum
     if (base + j < n) out[base + j] += a;
 }
 
+// one workgroup of 1024 threads, each scanning a contiguous run of at most 16 elements:
+// one launch for the small scans (radix-sort histograms, per-hypothesis counts)
+constexpr int kScanSmallT = 1024, kScanSmallI = 16;
+template <class I>
+__global__ __launch_bounds__(kScanSmallT) void k_scan_small(const I* in, I* out, int n, I* total) {
+  __shared__ I sh[32];
+  const int per = (n + kScanSmallT - 1) / kScanSmallT;
+  const int b = min(n, (int)threadIdx.x * per), e = min(n, b + per);
+  I v[kScanSmallI];
+  I sum = 0;
+#pragma unroll
+  for (int j = 0; j < kScanSmallI; ++j) {
+    v[j] = b + j < e ? in[b + j] : (I)0;
+    sum += v[j];
+  }
+  I tot;
+  I off = block_excl_scan<I>(sum, sh, &tot);
+#pragma unroll
+  for (int j = 0; j < kScanSmallI; ++j) {
+    if (b + j < e) out[b + j] = off;
+    off += v[j];
+  }
+  if (threadIdx.x == 0 && total) *total = tot;
+}
+
 template <class I>
 static void scan_impl(const I* in, I* out, int n, I* total, DevBuf& tmp, hipStream_t s) {
+  if (n <= kScanSmallT * kScanSmallI) {
+    GLMB_LAUNCH(k_scan_small<I>, 1, kScanSmallT, 0, s, in, out, n, total);
+    return;
+  }
   const int nt = std::max(1, cdiv(n, kScanTile));
   I* sums = need<I>(tmp, nt);
   if (n > 0) GLMB_LAUNCH(k_scan_tiles<I>, nt, kScanT, 0, s, in, out, n, sums);
@@ -186,10 +215,14 @@ void sort_pairs(uint64_t* keys, uint32_t* vals, int n, int bit0, int bit1, DevBu
   for (int sh = bit0; sh < bit1; sh += 8, ++passes) {
     GLMB_LAUNCH(k_sort_hist, nb, kSortT, 0, s, ka, n, sh, nb, hist);
     const int m = 256 * nb;
-    const int nt = cdiv(m, kScanTile);
-    GLMB_LAUNCH(k_scan_tiles<int32_t>, nt, kScanT, 0, s, hist, hist, m, sums);
-    GLMB_LAUNCH(k_scan_sums<int32_t>, 1, kScanT, 0, s, sums, nt, (int32_t*)nullptr);
-    GLMB_LAUNCH(k_scan_add<int32_t>, nt, kScanT, 0, s, hist, m, sums);
+    if (m <= kScanSmallT * kScanSmallI) {
+      GLMB_LAUNCH(k_scan_small<int32_t>, 1, kScanSmallT, 0, s, hist, hist, m, (int32_t*)nullptr);
+    } else {
+      const int nt = cdiv(m, kScanTile);
+      GLMB_LAUNCH(k_scan_tiles<int32_t>, nt, kScanT, 0, s, hist, hist, m, sums);
+      GLMB_LAUNCH(k_scan_sums<int32_t>, 1, kScanT, 0, s, sums, nt, (int32_t*)nullptr);
+      GLMB_LAUNCH(k_scan_add<int32_t>, nt, kScanT, 0, s, hist, m, sums);
+    }
     GLMB_LAUNCH(k_sort_scatter, nb, kSortT, 0, s, ka, va, kb, vb, n, sh, nb, hist);
     std::swap(ka, kb);
     std::swap(va, vb);

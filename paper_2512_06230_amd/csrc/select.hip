@@ -563,8 +563,8 @@ __device__ float grid_kth(const float* v, int n, int K, int32_t* hist, int32_t* 
 __global__ __launch_bounds__(kCB) void k_select_coop(CoopArgs a) {
   extern __shared__ int32_t smem[];
   int32_t* lhist = smem;                              // 4096
-  int64_t* lds = (int64_t*)(smem + 4096);             // 8
-  int32_t* sel = smem + 4096 + 16;                    // 2
+  int64_t* lds = (int64_t*)(smem + 4096);             // kCB / 64 partial sums
+  int32_t* sel = smem + 4096 + 2 * (kCB / kWave);     // 2
   const float nan = __uint_as_float(0xffc00000u);
   float t = *a.t0;
   int which = 0, status = 0;
@@ -739,6 +739,210 @@ __global__ __launch_bounds__(kCB) void k_select_coop(CoopArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- starting threshold
+// The search writes every child above its running threshold, so its cost is set by how tight
+// the starting bound is.  When the K best children are combinations of many near-zero
+// deviations of a few parents, the K-th best root or single deviation (the caller's bound)
+// lies far below the K-th best child, and the search would write many times K children on
+// its way up.  A counting bound closes the gap without enumerating: with a bin width w, every
+// delta is rounded up to a multiple of w, and each parent's valid pick sets (at most one item
+// per group) are counted by total rounded cost with the multiple-choice knapsack recursion over
+// its groups, counts saturating at K.  Rounding up only lowers a child's value and saturation
+// or leaving items out only lowers a count, so if at least K counted children of all parents
+// have rounded value >= v_max - j*w (v_max: the best parent), the K-th best child is at least
+// v_max - j*w, less a margin for the float rounding of the sequential subtractions.  A first
+// pass with coarse bins over the whole range [t0, v_max] and each parent's first items finds a
+// range E; a second with fine bins over [v_max - E, v_max] sharpens the bound.
+constexpr int kDpBins1 = 1024, kDpItems1 = 256;   // first pass
+constexpr int kDpBins2 = 4096, kDpItems2 = 2048;  // second pass
+constexpr int kDpThreads = 1024;
+
+constexpr int kDpGrid = 512;  // workgroups of a counting pass (each takes parents in turn)
+
+struct DpState {
+  float vmax, t0, tref;
+  int32_t ok;       // the current pass runs (a previous one found its count)
+  double E;         // range of the current pass below vmax
+  int32_t refined;  // tref > t0
+  int32_t nact;     // parents with base >= t0, listed in act (any order)
+};
+
+__global__ __launch_bounds__(kDpThreads) void k_dp_init(int P, const float* base, const float* t0, DpState* st,
+                                                        int32_t* act) {
+  __shared__ float red[kDpThreads / kWave];
+  __shared__ int32_t nact;
+  const float t = *t0;
+  if (threadIdx.x == 0) nact = 0;
+  __syncthreads();
+  float m = -INFINITY;
+  for (int h = threadIdx.x; h < P; h += kDpThreads) {
+    const float b = base[h];
+    if (b >= t) {
+      act[atomicAdd(&nact, 1)] = h;
+      if (b > m) m = b;
+    }
+  }
+  for (int d = kWave / 2; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, kWave));
+  if (lane_id() == 0) red[threadIdx.x / kWave] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kDpThreads / kWave; ++w) m = fmaxf(m, red[w]);
+    const double E = (double)m - (double)t;
+    st->vmax = m;
+    st->t0 = t;
+    st->tref = t;
+    st->E = E;
+    st->ok = (m >= t && E < INFINITY) ? 1 : 0;
+    st->refined = 0;
+    st->nact = nact;
+  }
+}
+
+// Every workgroup takes listed parents in turn: the counts of the parent's valid pick sets by
+// rounded cost, added into C at the parent's offset (its own rounded distance below vmax).
+__global__ __launch_bounds__(kDpThreads) void k_dp_count(int pass, const float* base, const int32_t* it_off,
+                                                         const float* it_delta, const int32_t* it_group, int K,
+                                                         const DpState* st, const int32_t* act,
+                                                         unsigned long long* C) {
+  __shared__ uint64_t key[kDpItems2];
+  __shared__ int32_t fa[kDpBins2], fb[kDpBins2];
+  __shared__ int32_t ne_s;
+  if (!st->ok) return;
+  const int NB = pass == 1 ? kDpBins1 : kDpBins2, ncap = pass == 1 ? kDpItems1 : kDpItems2;
+  const double E = st->E, w = E / NB;
+  const int nact = st->nact;
+  for (int k = blockIdx.x; k < nact; k += gridDim.x) {
+    const int h = act[k];
+    const double gap = (double)st->vmax - (double)base[h];
+    const double dd = ceil(gap / w);
+    if (!(dd < NB)) continue;
+    const int dh = (int)dd;
+    const int a = it_off[h], n = it_off[h + 1] - a;
+    __syncthreads();  // ne_s, key and fa of the previous parent are no longer read
+    if (threadIdx.x == 0) {
+      // items with delta <= E - gap can be picked within the range (the list is sorted by delta)
+      const double Eh = E - gap;
+      int lo = 0, hi = n;
+      while (lo < hi) {
+        const int m = (lo + hi) >> 1;
+        if ((double)it_delta[a + m] <= Eh) lo = m + 1;
+        else hi = m;
+      }
+      ne_s = min(lo, ncap);
+    }
+    __syncthreads();
+    const int ne = ne_s;
+    if (ne == 0) {
+      if (threadIdx.x == 0) atomicAdd(&C[dh], 1ull);
+      continue;
+    }
+    // (group, rounded cost) of the items, sorted by group so that each group is one run
+    int P2 = 1;
+    while (P2 < ne) P2 <<= 1;
+    for (int q = threadIdx.x; q < P2; q += kDpThreads) {
+      if (q < ne) {
+        const double c = ceil((double)it_delta[a + q] / w);
+        const uint32_t cost = c < NB ? (uint32_t)c : (uint32_t)NB;
+        key[q] = ((uint64_t)(uint32_t)it_group[a + q] << 32) | cost;
+      } else {
+        key[q] = ~0ull;
+      }
+    }
+    for (int b = threadIdx.x; b < NB; b += kDpThreads) fa[b] = b == 0 ? 1 : 0;
+    __syncthreads();
+    for (int kk = 2; kk <= P2; kk <<= 1)
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        for (int q = threadIdx.x; q < P2; q += kDpThreads) {
+          const int r = q ^ j;
+          if (r > q) {
+            const uint64_t x = key[q], y = key[r];
+            if ((x > y) == ((q & kk) == 0)) {
+              key[q] = y;
+              key[r] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    int32_t* f = fa;
+    int32_t* g = fb;
+    for (int q = 0; q < ne;) {
+      const uint32_t grp = (uint32_t)(key[q] >> 32);
+      int e = q + 1;
+      while (e < ne && (uint32_t)(key[e] >> 32) == grp) ++e;
+      for (int b = threadIdx.x; b < NB; b += kDpThreads) {
+        int v = f[b];
+        for (int i = q; i < e; ++i) {
+          const int c = (int)(uint32_t)key[i];
+          if (c <= b) v = min(K, v + f[b - c]);
+        }
+        g[b] = v;
+      }
+      __syncthreads();
+      int32_t* x = f;
+      f = g;
+      g = x;
+      q = e;
+    }
+    for (int b = threadIdx.x; b < NB - dh; b += kDpThreads)
+      if (f[b]) atomicAdd(&C[b + dh], (unsigned long long)f[b]);
+  }
+}
+
+// first bin whose cumulative count reaches K; the bound it gives, and the next pass's range.
+// Leaves C zeroed.
+__global__ __launch_bounds__(kDpThreads) void k_dp_pick(int pass, int K, DpState* st, unsigned long long* C) {
+  __shared__ unsigned long long part[kDpThreads];
+  __shared__ int32_t first;
+  const int NB = pass == 1 ? kDpBins1 : kDpBins2, per = NB / kDpThreads;
+  if (!st->ok) return;
+  const int t = threadIdx.x;
+  unsigned long long mine = 0;
+  for (int j = 0; j < per; ++j) mine += C[per * t + j];
+  part[t] = mine;
+  if (t == 0) first = NB;
+  __syncthreads();
+  // inclusive scan of the per-thread sums (Hillis-Steele in LDS)
+  for (int d = 1; d < kDpThreads; d <<= 1) {
+    const unsigned long long y = t >= d ? part[t - d] : 0ull;
+    __syncthreads();
+    part[t] += y;
+    __syncthreads();
+  }
+  const unsigned long long before = part[t] - mine;
+  if (before < (unsigned long long)K && part[t] >= (unsigned long long)K) {
+    unsigned long long acc = before;
+    int j = per * t;
+    for (; j < per * t + per - 1; ++j) {
+      acc += C[j];
+      if (acc >= (unsigned long long)K) break;
+    }
+    first = j;
+  }
+  __syncthreads();
+  for (int j = 0; j < per; ++j) C[per * t + j] = 0ull;
+  if (t != 0) return;
+  const int j = first;
+  if (j >= NB) {  // not enough counted children in range: keep the bound found so far
+    st->ok = 0;
+    return;
+  }
+  const double w = st->E / NB;
+  const double vmax = st->vmax;
+  // rounding of up to kMaxDepth sequential float subtractions, and one bin
+  const double tau = vmax - j * w - w - 1e-5 * fmax(1.0, fabs(vmax));
+  float f = (float)tau;
+  if ((double)f > tau) f = nextafterf(f, -INFINITY);
+  if (f > st->tref) {
+    st->tref = f;
+    st->refined = 1;
+  }
+  if (pass == 1) {
+    st->E = (j + 2) * w;  // the fine pass covers the coarse bin found and the next
+    st->ok = j > 0 ? 1 : 0;
+  }
+}
+
 namespace {
 struct Nodes {
   int32_t *p, *i, *h;
@@ -749,7 +953,7 @@ struct Nodes {
 
 // Workgroups of the cooperative search: one per compute unit when the device supports
 // cooperative launches and that many fit at once (0: use the multi-kernel levels).
-constexpr size_t kCoopLds = (4096 + 16 + 4) * sizeof(int32_t);
+constexpr size_t kCoopLds = (4096 + 2 * (kCB / kWave) + 4) * sizeof(int32_t);
 namespace {
 std::atomic<int> g_coop_grid{-1};  // per process (one device type)
 }
@@ -778,6 +982,43 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
       std::fflush(stderr);
     }
   };
+  if (in.refine && in.K > 0 && in.P > 0) {
+    // counting bound (two passes, no host round trip), then the search from it
+    DpState* st = need<DpState>(b.dp, 1);
+    int32_t* act = need<int32_t>(b.dpa, in.P);
+    unsigned long long* C = need<unsigned long long>(b.dpc, kDpBins2);
+    if (!b.dpc_ready) {
+      GLMB_HIP(hipMemsetAsync(C, 0, kDpBins2 * sizeof(unsigned long long), s));  // k_dp_pick leaves it zeroed
+      b.dpc_ready = true;
+    }
+    GLMB_LAUNCH(k_dp_init, 1, kDpThreads, 0, s, in.P, in.base, in.t0, st, act);
+    for (int pass = 1; pass <= 2; ++pass) {
+      GLMB_LAUNCH(k_dp_count, std::min(in.P, kDpGrid), kDpThreads, 0, s, pass, in.base, in.it_off, in.it_delta,
+                  in.it_group, in.K, st, (const int32_t*)act, C);
+      GLMB_LAUNCH(k_dp_pick, 1, kDpThreads, 0, s, pass, in.K, st, C);
+    }
+    if (trace) {
+      DpState h{};
+      GLMB_HIP(hipMemcpyAsync(&h, st, sizeof(DpState), hipMemcpyDeviceToHost, s));
+      GLMB_HIP(hipStreamSynchronize(s));
+      std::fprintf(stderr, "[glmb] select.refine t0 %.7g tref %.7g vmax %.7g refined %d\n", h.t0, h.tref, h.vmax,
+                   h.refined);
+    }
+    SelectIn r = in;
+    r.refine = false;
+    r.t0 = &st->tref;
+    const glmb_status e = select_topk(r, cap, b, out, s, err, trace);
+    if (e != GLMB_OK || out.n >= in.K) return e;
+    // Fewer than K children above the refined bound would contradict its count: search again
+    // from the caller's bound.
+    int32_t refined = 0;
+    GLMB_HIP(hipMemcpyAsync(&refined, &st->refined, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GLMB_HIP(hipStreamSynchronize(s));
+    if (!refined) return e;
+    tr("refine_retry", out.n, in.K);
+    r.t0 = in.t0;
+    return select_topk(r, cap, b, out, s, err, trace);
+  }
   const int T = 256;
   // node store: two copies for compaction
   auto alloc = [&](int which) {

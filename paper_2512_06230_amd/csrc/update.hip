@@ -15,6 +15,8 @@
 // per-detection reference c_i = max(log kappa, max phi_ui), so that hypotheses which agree
 // on a detection contribute an exact 0 there (log weights of ~-5000 never appear); the
 // common constant sum_i c_i cancels in every normalised quantity.
+#include <climits>
+
 #include "ctx.hpp"
 
 namespace glmb {
@@ -461,54 +463,154 @@ __global__ void k_cell_write(int64_t n, const int32_t* flags, const int32_t* pre
 // d = phi_best - phi keeps B'_h - d above the cut bound.  Candidates arrive in ascending key,
 // so items are emitted in ascending option key; the stable sort by (h, d) that follows puts
 // equal deviations in key order.  Two passes over the options, no per-cell storage.
-__global__ void k_items(int ncell, const int32_t* cells, int M, int stride, const int32_t* rows, const int32_t* coff,
-                        const int32_t* cand, const float* phi, float lgk, const float* bprime, const float* t0,
-                        const int32_t* ioff, int32_t* icount, float* it_delta, int32_t* it_group, int32_t* it_opt,
-                        uint64_t* keys, uint32_t* vals, uint32_t* errf) {
-  (void)errf;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+// One wave per cell (h, i): the lanes take detection i's gated candidates 64 at a time.  The
+// best option of the cell is the first candidate (in list order) of the largest score if that
+// beats the clutter score, else clutter; every other option within the cut is an item with
+// delta = best - score, in the order clutter first, then the candidates in list order.
+// Counting pass (ioff null): icount[c] = number of items; writing pass: items at ioff[c].
+__global__ __launch_bounds__(256) void k_items(int ncell, const int32_t* cells, int M, int stride,
+                                               const int32_t* rows, const int32_t* coff, const int32_t* cand,
+                                               const float* phi, float lgk, const float* bprime, const float* t0,
+                                               const int32_t* ioff, int32_t* icount, float* it_delta,
+                                               int32_t* it_group, int32_t* it_opt, uint64_t* keys, uint32_t* vals) {
+  const int c = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kWave);
   if (c >= ncell) return;
+  const int lane = lane_id();
   const int cell = cells[c];
   const int h = cell / M, i = cell % M;
   const int32_t* row = rows + (size_t)h * stride;
   const int e0 = coff[i], e1 = coff[i + 1];
-  float best = lgk;
-  int bkey = -1;
-  for (int e = e0; e < e1; ++e) {
-    const int s = cand[e];
-    const int u = row[s];
+  float lv = -INFINITY;
+  int le = INT_MAX;
+  for (int e = e0 + lane; e < e1; e += kWave) {
+    const int u = row[cand[e]];
     if (u < 0) continue;
     const float v = phi[(size_t)u * M + i];
-    if (v > best) {
-      best = v;
-      bkey = s;
+    if (v > lv) {
+      lv = v;
+      le = e;
     }
   }
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    const float ov = __shfl_xor(lv, d, kWave);
+    const int oe = __shfl_xor(le, d, kWave);
+    if (ov > lv || (ov == lv && oe < le)) {
+      lv = ov;
+      le = oe;
+    }
+  }
+  const bool cand_best = lv > lgk;
+  const float best = cand_best ? lv : lgk;
+  const int bkey = cand_best ? cand[le] : -1;
   const float B = bprime[h], t = *t0;
   int cnt = 0;
-  auto emit = [&](float d, int key) {
-    if (!(B - d >= t)) return;
-    if (ioff) {
-      const int q = ioff[c] + cnt;
-      it_delta[q] = d;
-      it_group[q] = i;
-      it_opt[q] = key;
+  const int q0 = ioff ? ioff[c] : 0;
+  auto put = [&](int q, float d, int key) {
+    it_delta[q] = d;
+    it_group[q] = i;
+    it_opt[q] = key;
+    if (keys) {
       keys[q] = ((uint64_t)(uint32_t)h << 32) | f2o(d);
       vals[q] = (uint32_t)q;
     }
-    ++cnt;
   };
-  if (bkey >= 0) emit(best - lgk, -1);
-  for (int e = e0; e < e1; ++e) {
-    const int s = cand[e];
-    if (s == bkey) continue;
-    const int u = row[s];
-    if (u < 0) continue;
-    const float v = phi[(size_t)u * M + i];
-    if (!(v > -INFINITY)) continue;
-    emit(best - v, s);
+  if (bkey >= 0) {
+    const float d = best - lgk;
+    if (B - d >= t) {
+      if (ioff && lane == 0) put(q0, d, -1);
+      cnt = 1;
+    }
   }
-  if (!ioff) icount[c] = cnt;
+  for (int eb = e0; eb < e1; eb += kWave) {
+    const int e = eb + lane;
+    bool emit = false;
+    float d = 0.f;
+    int sk = -1;
+    if (e < e1) {
+      sk = cand[e];
+      const int u = row[sk];
+      if (sk != bkey && u >= 0) {
+        const float v = phi[(size_t)u * M + i];
+        d = best - v;
+        emit = v > -INFINITY && B - d >= t;
+      }
+    }
+    const uint64_t bal = __ballot(emit);
+    if (ioff && emit) put(q0 + cnt + __popcll(bal & lanemask_lt()), d, sk);
+    cnt += __popcll(bal);
+  }
+  if (!ioff && lane == 0) icount[c] = cnt;
+}
+
+// first item of every parent (items are generated in cell order, so each parent's items are
+// contiguous), the largest per-parent count, and the list of parents with items (any order)
+__global__ void k_item_ranges(int H, int ncell, int M, const int32_t* cells, const int32_t* ioff, int32_t* itoff,
+                              int32_t* maxlen, int32_t* nlist, int32_t* list) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h > H) return;
+  auto first_cell = [&](int64_t key) {
+    int a = 0, b = ncell;
+    while (a < b) {
+      const int m = (a + b) >> 1;
+      if ((int64_t)cells[m] < key) a = m + 1;
+      else b = m;
+    }
+    return a;
+  };
+  const int c0 = first_cell((int64_t)h * M);
+  itoff[h] = ioff[c0];
+  if (h < H) {
+    const int len = ioff[first_cell((int64_t)(h + 1) * M)] - ioff[c0];
+    if (len > 0) list[atomicAdd(nlist, 1)] = h;
+    if (len > 1) atomicMax(maxlen, len);
+  }
+}
+
+// Every workgroup takes listed parents in turn and sorts the parent's items by delta in LDS
+// (at most kSegSort items).  Ties keep the generation order (detection, then option), as the
+// stable radix sort of the general path does, through the item's position in the low bits of
+// the key.
+constexpr int kSegSort = 4096;
+#ifndef GLMB_SEGSORT_MAX
+#define GLMB_SEGSORT_MAX kSegSort  // largest per-parent item count sorted in LDS (a build may lower it)
+#endif
+static_assert(GLMB_SEGSORT_MAX <= kSegSort, "per-parent LDS sort holds at most kSegSort items");
+template <int NT>
+__global__ __launch_bounds__(NT) void k_item_segsort(const int32_t* nlist, const int32_t* list, const int32_t* itoff,
+                                                     const float* d0, const int32_t* g0, const int32_t* o0,
+                                                     float* d1, int32_t* g1, int32_t* o1) {
+  __shared__ uint64_t key[kSegSort];
+  const int nl = *nlist;
+  for (int k = blockIdx.x; k < nl; k += gridDim.x) {
+    const int h = list[k];
+    const int b = itoff[h], n = itoff[h + 1] - b;
+    int P = 1;
+    while (P < n) P <<= 1;
+    __syncthreads();  // the previous parent's keys are read
+    for (int q = threadIdx.x; q < P; q += NT)
+      key[q] = q < n ? ((uint64_t)f2o(d0[b + q]) << 32) | (uint32_t)q : ~0ull;
+    __syncthreads();
+    for (int kk = 2; kk <= P; kk <<= 1)
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        for (int q = threadIdx.x; q < P; q += NT) {
+          const int r = q ^ j;
+          if (r > q) {
+            const uint64_t x = key[q], y = key[r];
+            if ((x > y) == ((q & kk) == 0)) {
+              key[q] = y;
+              key[r] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    for (int q = threadIdx.x; q < n; q += NT) {
+      const int src = b + (int)(uint32_t)key[q];
+      d1[b + q] = d0[src];
+      g1[b + q] = g0[src];
+      o1[b + q] = o0[src];
+    }
+  }
 }
 
 __global__ void k_item_perm(int n, const uint32_t* vals, const float* d0, const int32_t* g0, const int32_t* o0,
@@ -519,19 +621,6 @@ __global__ void k_item_perm(int n, const uint32_t* vals, const float* d0, const 
   d1[p] = d0[q];
   g1[p] = g0[q];
   o1[p] = o0[q];
-}
-
-// it_off[h] = first sorted item with parent >= h
-__global__ void k_item_off(int H, int n, const uint64_t* keys, int32_t* it_off) {
-  const int h = blockIdx.x * blockDim.x + threadIdx.x;
-  if (h > H) return;
-  int a = 0, b = n;
-  while (a < b) {
-    const int m = (a + b) >> 1;
-    if ((int)(keys[m] >> 32) < h) a = m + 1;
-    else b = m;
-  }
-  it_off[h] = a;
 }
 
 // one block: normalise over the selected children, tau pruning (the first is always kept)
@@ -1216,29 +1305,51 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   GLMB_LAUNCH(k_cell_write, cdiv(HM, T), T, 0, s, HM, flags, pre, cells);
   int32_t* icount = need<int32_t>(c.ccount, ncell + 1);
   int32_t* ioff = need<int32_t>(c.coff2, ncell + 1);
-  GLMB_LAUNCH(k_items, cdiv(ncell, T), T, 0, s, ncell, cells, M, SW, c.rows.as<int32_t>(), coff, cand, phi, lgk,
+  const int item_blocks = cdiv((int64_t)ncell * kWave, 256);
+  GLMB_LAUNCH(k_items, item_blocks, 256, 0, s, ncell, cells, M, SW, c.rows.as<int32_t>(), coff, cand, phi, lgk,
               bprime, t0, (const int32_t*)nullptr, icount, (float*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
-              (uint64_t*)nullptr, (uint32_t*)nullptr, errf);
+              (uint64_t*)nullptr, (uint32_t*)nullptr);
   scan_excl(icount, ioff, ncell, ioff + ncell, c.tmp, s);
-  const int nitem = read1(s, ioff + ncell);
+  int32_t* itoff = need<int32_t>(c.it_off, H + 1);
+  int32_t* maxlen = scal + 22;
+  int32_t* nlist = scal + 23;
+  int32_t* ilist = need<int32_t>(c.it_h, H);
+  GLMB_LAUNCH(k_item_ranges, cdiv(H + 1, T), T, 0, s, H, ncell, M, cells, ioff, itoff, maxlen, nlist, ilist);
+  int32_t hv[2];
+  GLMB_HIP(hipMemcpyAsync(hv, ioff + ncell, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipMemcpyAsync(hv + 1, maxlen, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipStreamSynchronize(s));
+  const int nitem = hv[0];
   float* itd0 = need<float>(c.it_delta, 2 * (int64_t)nitem);
   int32_t* itg0 = need<int32_t>(c.it_group, 2 * (int64_t)nitem);
   int32_t* ito0 = need<int32_t>(c.it_opt, 2 * (int64_t)nitem);
   uint64_t* ikeys = need<uint64_t>(c.keys, nitem);
   uint32_t* ivals = need<uint32_t>(c.vals32, nitem);
-  GLMB_LAUNCH(k_items, cdiv(ncell, T), T, 0, s, ncell, cells, M, SW, c.rows.as<int32_t>(), coff, cand, phi, lgk,
-              bprime, t0, (const int32_t*)ioff, icount, itd0, itg0, ito0, ikeys, ivals, errf);
-  int hbits = 0;
-  while ((1 << hbits) < H) ++hbits;
-  sort_pairs(ikeys, ivals, nitem, 0, 32 + ((hbits + 7) / 8) * 8, c.tk, c.tv, c.tmp, s);
+  const bool segsort = hv[1] <= GLMB_SEGSORT_MAX;
+  GLMB_LAUNCH(k_items, item_blocks, 256, 0, s, ncell, cells, M, SW, c.rows.as<int32_t>(), coff, cand, phi, lgk,
+              bprime, t0, (const int32_t*)ioff, icount, itd0, itg0, ito0, segsort ? nullptr : ikeys,
+              segsort ? nullptr : ivals);
   float* itd = itd0 + nitem;
   int32_t* itg = itg0 + nitem;
   int32_t* ito = ito0 + nitem;
-  GLMB_LAUNCH(k_item_perm, cdiv(nitem, T), T, 0, s, nitem, ivals, itd0, itg0, ito0, itd, itg, ito);
-  int32_t* itoff = need<int32_t>(c.it_off, H + 1);
-  GLMB_LAUNCH(k_item_off, cdiv(H + 1, T), T, 0, s, H, nitem, ikeys, itoff);
+  if (segsort) {
+    // per-parent lists sorted in LDS, one workgroup per parent
+    if (hv[1] > 1024)
+      GLMB_LAUNCH(k_item_segsort<1024>, std::min(H, 512), 1024, 0, s, nlist, ilist, itoff, itd0, itg0, ito0, itd,
+                  itg, ito);
+    else
+      GLMB_LAUNCH(k_item_segsort<256>, std::min(H, 1024), 256, 0, s, nlist, ilist, itoff, itd0, itg0, ito0, itd,
+                  itg, ito);
+  } else {
+    // a parent with more items than one workgroup sorts: stable radix sort by (parent, delta)
+    // of the items in generation order (detection, then option key)
+    int hbits = 0;
+    while ((1 << hbits) < H) ++hbits;
+    sort_pairs(ikeys, ivals, nitem, 0, 32 + ((hbits + 7) / 8) * 8, c.tk, c.tv, c.tmp, s);
+    GLMB_LAUNCH(k_item_perm, cdiv(nitem, T), T, 0, s, nitem, ivals, itd0, itg0, ito0, itd, itg, ito);
+  }
 
-  SelectIn si{H, bprime, itoff, itd, itg, K, t0, &c.sel_multi[1], c.coop_ok};
+  SelectIn si{H, bprime, itoff, itd, itg, K, t0, &c.sel_multi[1], c.coop_ok, true};
   trace(c, "update.select", ncell, nitem);
   Selected sel{};
   std::string serr;
