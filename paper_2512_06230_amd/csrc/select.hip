@@ -57,7 +57,17 @@ __device__ __forceinline__ void ext_range(int n, const int32_t* nd_item, const i
   const int lo = nd_item[n] < 0 ? it_off[h] : nd_item[n] + 1;
   int a = lo, b = it_off[h + 1];
   if (!(v >= t)) b = lo;
-  // largest prefix of [lo, b) with v - delta >= t (monotone in delta)
+  // largest prefix of [lo, b) with v - delta >= t (monotone in delta): probes at lo + 2^k - 1
+  // first, since near the threshold the prefix is short, then bisection of the last gap
+  for (int step = 1; a < b; step <<= 1) {
+    const int m = min(a + step - 1, b - 1);
+    if (v - it_delta[m] >= t) {
+      a = m + 1;
+    } else {
+      b = m;
+      break;
+    }
+  }
   while (a < b) {
     const int m = (a + b) >> 1;
     if (v - it_delta[m] >= t) a = m + 1;
@@ -259,6 +269,9 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
   __shared__ int64_t cpre[kSB];
   __shared__ int64_t ccnt[kSB];
   __shared__ int32_t clo[kSB];
+  __shared__ float cv[kSB];       // value, parent and group bits of the chunk's nodes
+  __shared__ int32_t chh[kSB];
+  __shared__ uint64_t cbb[kSB];
   const float nan = __uint_as_float(0xffc00000u);
   float t = *t0;
   int status = 0;  // 0 done, 1 node store full, 2 too deep
@@ -295,7 +308,12 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
       const int nchunk = min(kSB, end - c0);
       const int n = c0 + (int)threadIdx.x;
       int lo = 0, hi = 0;
-      if ((int)threadIdx.x < nchunk) ext_range(n, nd_i, nd_h, nd_v, it_off, it_delta, t, &lo, &hi);
+      if ((int)threadIdx.x < nchunk) {
+        ext_range(n, nd_i, nd_h, nd_v, it_off, it_delta, t, &lo, &hi);
+        cv[threadIdx.x] = nd_v[n];
+        chh[threadIdx.x] = nd_h[n];
+        cbb[threadIdx.x] = nd_b[n];
+      }
       const int64_t cnt = hi - lo;
       int64_t tot;
       const int64_t excl = sb_excl_scan(cnt, sh, &tot);
@@ -348,9 +366,9 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
         }
         const int nn = c0 + a;
         const int q = clo[a] + (int)(e - cpre[a]);
-        float v = nd_v[nn] - it_delta[q];
+        float v = cv[a] - it_delta[q];
         const int g = it_group[q];
-        const uint64_t pb = nd_b[nn], gb = group_bit(g);
+        const uint64_t pb = cbb[a], gb = group_bit(g);
         if (pb & gb)
           for (int x = nn; nd_i[x] >= 0; x = nd_p[x])
             if (it_group[nd_i[x]] == g) {
@@ -361,7 +379,7 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
         nd_b[o] = pb | gb;
         nd_p[o] = nn;
         nd_i[o] = q;
-        nd_h[o] = nd_h[nn];
+        nd_h[o] = chh[a];
         nd_v[o] = v;
       }
       __syncthreads();
@@ -753,9 +771,10 @@ __global__ __launch_bounds__(kCB) void k_select_coop(CoopArgs a) {
 // v_max - j*w, less a margin for the float rounding of the sequential subtractions.  A first
 // pass with coarse bins over the whole range [t0, v_max] and each parent's first items finds a
 // range E; a second with fine bins over [v_max - E, v_max] sharpens the bound.
-constexpr int kDpBins1 = 1024, kDpItems1 = 256;   // first pass
+constexpr int kDpBins1 = 1024, kDpItems1 = 64;    // first pass
 constexpr int kDpBins2 = 4096, kDpItems2 = 2048;  // second pass
-constexpr int kDpThreads = 1024;
+constexpr int kDpThreads = 1024;      // init and pick
+constexpr int kDpCountThreads = 1024;  // counting: one or a few bins per thread and step
 
 constexpr int kDpGrid = 512;  // workgroups of a counting pass (each takes parents in turn)
 
@@ -800,13 +819,15 @@ __global__ __launch_bounds__(kDpThreads) void k_dp_init(int P, const float* base
 
 // Every workgroup takes listed parents in turn: the counts of the parent's valid pick sets by
 // rounded cost, added into C at the parent's offset (its own rounded distance below vmax).
-__global__ __launch_bounds__(kDpThreads) void k_dp_count(int pass, const float* base, const int32_t* it_off,
+__global__ __launch_bounds__(kDpCountThreads) void k_dp_count(int pass, const float* base, const int32_t* it_off,
                                                          const float* it_delta, const int32_t* it_group, int K,
                                                          const DpState* st, const int32_t* act,
                                                          unsigned long long* C) {
   __shared__ uint64_t key[kDpItems2];
+  __shared__ int32_t gs[kDpItems2 + 1];    // starts of the group runs
   __shared__ int32_t fa[kDpBins2], fb[kDpBins2];
-  __shared__ int32_t ne_s;
+  __shared__ int32_t wcnt[kDpCountThreads / kWave];
+  __shared__ int32_t ne_s, ngs;
   if (!st->ok) return;
   const int NB = pass == 1 ? kDpBins1 : kDpBins2, ncap = pass == 1 ? kDpItems1 : kDpItems2;
   const double E = st->E, w = E / NB;
@@ -829,6 +850,7 @@ __global__ __launch_bounds__(kDpThreads) void k_dp_count(int pass, const float* 
         else hi = m;
       }
       ne_s = min(lo, ncap);
+      ngs = 0;
     }
     __syncthreads();
     const int ne = ne_s;
@@ -839,7 +861,7 @@ __global__ __launch_bounds__(kDpThreads) void k_dp_count(int pass, const float* 
     // (group, rounded cost) of the items, sorted by group so that each group is one run
     int P2 = 1;
     while (P2 < ne) P2 <<= 1;
-    for (int q = threadIdx.x; q < P2; q += kDpThreads) {
+    for (int q = threadIdx.x; q < P2; q += kDpCountThreads) {
       if (q < ne) {
         const double c = ceil((double)it_delta[a + q] / w);
         const uint32_t cost = c < NB ? (uint32_t)c : (uint32_t)NB;
@@ -848,11 +870,11 @@ __global__ __launch_bounds__(kDpThreads) void k_dp_count(int pass, const float* 
         key[q] = ~0ull;
       }
     }
-    for (int b = threadIdx.x; b < NB; b += kDpThreads) fa[b] = b == 0 ? 1 : 0;
+    for (int b = threadIdx.x; b < NB; b += kDpCountThreads) fa[b] = b == 0 ? 1 : 0;
     __syncthreads();
     for (int kk = 2; kk <= P2; kk <<= 1)
       for (int j = kk >> 1; j > 0; j >>= 1) {
-        for (int q = threadIdx.x; q < P2; q += kDpThreads) {
+        for (int q = threadIdx.x; q < P2; q += kDpCountThreads) {
           const int r = q ^ j;
           if (r > q) {
             const uint64_t x = key[q], y = key[r];
@@ -864,17 +886,46 @@ __global__ __launch_bounds__(kDpThreads) void k_dp_count(int pass, const float* 
         }
         __syncthreads();
       }
+    // starts of the group runs, in order (wave ballots, then the waves' counts)
+    for (int c0 = 0; c0 < ne; c0 += kDpCountThreads) {
+      const int q = c0 + (int)threadIdx.x;
+      const bool st0 = q < ne && (q == 0 || (key[q] >> 32) != (key[q - 1] >> 32));
+      const uint64_t bal = __ballot(st0);
+      if (lane_id() == 0) wcnt[threadIdx.x / kWave] = __popcll(bal);
+      __syncthreads();
+      int before = ngs;
+      for (int w2 = 0; w2 < (int)threadIdx.x / kWave; ++w2) before += wcnt[w2];
+      if (st0) gs[before + __popcll(bal & lanemask_lt())] = q;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w2 = 0; w2 < kDpCountThreads / kWave; ++w2) tot += wcnt[w2];
+        ngs += tot;
+      }
+      __syncthreads();
+    }
+    const int ng = ngs;
+    if (threadIdx.x == 0) gs[ng] = ne;
+    __syncthreads();
+    // two groups per step: f'' = f * (1 + sum_i x^c_i) * (1 + sum_j x^c_j), counts saturating at K
     int32_t* f = fa;
     int32_t* g = fb;
-    for (int q = 0; q < ne;) {
-      const uint32_t grp = (uint32_t)(key[q] >> 32);
-      int e = q + 1;
-      while (e < ne && (uint32_t)(key[e] >> 32) == grp) ++e;
-      for (int b = threadIdx.x; b < NB; b += kDpThreads) {
+    for (int k2 = 0; k2 < ng; k2 += 2) {
+      const int a0 = gs[k2], a1 = gs[k2 + 1], a2 = k2 + 1 < ng ? gs[k2 + 2] : a1;
+      for (int b = threadIdx.x; b < NB; b += kDpCountThreads) {
         int v = f[b];
-        for (int i = q; i < e; ++i) {
-          const int c = (int)(uint32_t)key[i];
-          if (c <= b) v = min(K, v + f[b - c]);
+        for (int i = a0; i < a1; ++i) {
+          const int ci = (int)(uint32_t)key[i];
+          if (ci > b) continue;
+          v = min(K, v + f[b - ci]);
+          for (int j = a1; j < a2; ++j) {
+            const int cj = (int)(uint32_t)key[j];
+            if (ci + cj <= b) v = min(K, v + f[b - ci - cj]);
+          }
+        }
+        for (int j = a1; j < a2; ++j) {
+          const int cj = (int)(uint32_t)key[j];
+          if (cj <= b) v = min(K, v + f[b - cj]);
         }
         g[b] = v;
       }
@@ -882,9 +933,8 @@ __global__ __launch_bounds__(kDpThreads) void k_dp_count(int pass, const float* 
       int32_t* x = f;
       f = g;
       g = x;
-      q = e;
     }
-    for (int b = threadIdx.x; b < NB - dh; b += kDpThreads)
+    for (int b = threadIdx.x; b < NB - dh; b += kDpCountThreads)
       if (f[b]) atomicAdd(&C[b + dh], (unsigned long long)f[b]);
   }
 }
@@ -993,7 +1043,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
     }
     GLMB_LAUNCH(k_dp_init, 1, kDpThreads, 0, s, in.P, in.base, in.t0, st, act);
     for (int pass = 1; pass <= 2; ++pass) {
-      GLMB_LAUNCH(k_dp_count, std::min(in.P, kDpGrid), kDpThreads, 0, s, pass, in.base, in.it_off, in.it_delta,
+      GLMB_LAUNCH(k_dp_count, std::min(in.P, kDpGrid), kDpCountThreads, 0, s, pass, in.base, in.it_off, in.it_delta,
                   in.it_group, in.K, st, (const int32_t*)act, C);
       GLMB_LAUNCH(k_dp_pick, 1, kDpThreads, 0, s, pass, in.K, st, C);
     }

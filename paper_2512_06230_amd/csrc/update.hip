@@ -808,16 +808,12 @@ __device__ __forceinline__ int find_exc(const int32_t* eb, const int32_t* eoff, 
   return (a < e1 && eb[a] == s) ? a : -1;
 }
 
-// per child: detection-set masks of the slots its deviations touch (count pass: mu == null)
-__global__ void k_child_mods(int n, int LW, const int32_t* ch_h, const int32_t* hp_map, const int32_t* doff,
-                             const int32_t* dev_i, const int32_t* dev_new, const int32_t* dev_old, int stride,
-                             const int32_t* rows, const int32_t* loff, const int32_t* llen, const int32_t* lmeas,
-                             const uint32_t* dmask, const int32_t* eb, const uint32_t* em, const int32_t* eoff,
-                             const int32_t* moff, int32_t* mcount, int32_t* mu, int32_t* ma, int32_t* mb,
-                             uint32_t* mm) {
+// per child: the slots its deviations touch, each once (count pass: ma == null; writing pass:
+// child and slot of every touched slot at moff[c])
+__global__ void k_child_mods(int n, const int32_t* doff, const int32_t* dev_new, const int32_t* dev_old,
+                             const int32_t* moff, int32_t* mcount, int32_t* ma, int32_t* mb) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
-  const int h = ch_h[c], hp = hp_map[h];
   const int d0 = doff[c], d1 = doff[c + 1];
   int cnt = 0;
   for (int q = d0; q < d1; ++q) {
@@ -827,28 +823,43 @@ __global__ void k_child_mods(int n, int LW, const int32_t* ch_h, const int32_t* 
       bool seen = side == 1 && dev_old[q] == s;
       for (int r = d0; r < q && !seen; ++r) seen = dev_old[r] == s || dev_new[r] == s;
       if (seen) continue;
-      if (mu) {
+      if (ma) {
         const int o = moff[c] + cnt;
-        const int u = rows[(size_t)h * stride + s];
-        const int e = find_exc(eb, eoff, hp, s);
-        const uint32_t* base = e >= 0 ? em + (size_t)e * LW : dmask + (size_t)u * LW;
-        uint32_t* out = mm + (size_t)o * LW;
-        for (int w = 0; w < LW; ++w) out[w] = base[w];
-        for (int t = d0; t < d1; ++t) {
-          if (dev_old[t] != s && dev_new[t] != s) continue;
-          const int j = lpos(lmeas, loff[s], llen[s], dev_i[t]);
-          if (j >= llen[s]) continue;
-          if (dev_old[t] == s) out[j >> 5] &= ~(1u << (j & 31));
-          if (dev_new[t] == s) out[j >> 5] |= 1u << (j & 31);
-        }
-        mu[o] = u;
         ma[o] = c;
         mb[o] = s;
       }
       ++cnt;
     }
   }
-  if (!mu) mcount[c] = cnt;
+  if (!ma) mcount[c] = cnt;
+}
+
+// one thread per touched (child, slot): the slot's detection-set mask in the child, i.e. the
+// parent's mask (its exception, else the instance's default) with the child's deviations on
+// that slot applied
+__global__ void k_mod_masks(int nm, int LW, const int32_t* ch_h, const int32_t* hp_map, const int32_t* doff,
+                            const int32_t* dev_i, const int32_t* dev_new, const int32_t* dev_old, int stride,
+                            const int32_t* rows, const int32_t* loff, const int32_t* llen, const int32_t* lmeas,
+                            const uint32_t* dmask, const int32_t* eb, const uint32_t* em, const int32_t* eoff,
+                            const int32_t* ma, const int32_t* mb, int32_t* mu, uint32_t* mm) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= nm) return;
+  const int c = ma[o], s = mb[o];
+  const int h = ch_h[c], hp = hp_map[h];
+  const int d0 = doff[c], d1 = doff[c + 1];
+  const int u = rows[(size_t)h * stride + s];
+  const int e = find_exc(eb, eoff, hp, s);
+  const uint32_t* base = e >= 0 ? em + (size_t)e * LW : dmask + (size_t)u * LW;
+  uint32_t* out = mm + (size_t)o * LW;
+  for (int w = 0; w < LW; ++w) out[w] = base[w];
+  for (int t = d0; t < d1; ++t) {
+    if (dev_old[t] != s && dev_new[t] != s) continue;
+    const int j = lpos(lmeas, loff[s], llen[s], dev_i[t]);
+    if (j >= llen[s]) continue;
+    if (dev_old[t] == s) out[j >> 5] &= ~(1u << (j & 31));
+    if (dev_new[t] == s) out[j >> 5] |= 1u << (j & 31);
+  }
+  mu[o] = u;
 }
 
 __device__ __forceinline__ uint32_t mask_hash(const uint32_t* m, int LW) {
@@ -1014,25 +1025,36 @@ __global__ void k_ru_final(int M, int nch, const float* part, float* ru) {
 }
 
 // one wave: greedy clustering of the seeds in detection order (a seed joins the first
-// cluster whose first seed lies within cd), one birth per cluster
+// cluster whose first seed lies within cd), one birth per cluster.  Lane 0 keeps every
+// cluster's sums while it assigns the seeds in detection order, so each sum adds its terms in
+// detection order; the lanes fetch the detections of a chunk of 64 at once.
 constexpr int kMaxClusters = 4096;
 __global__ __launch_bounds__(64) void k_births(int M, const float2* z, const float* ru, float rumax, float cd,
                                                float sig2, float sigv2, float rmax, float brate, int32_t* member,
                                                DBirth* out, int32_t* nb_out, uint32_t* errf) {
-  __shared__ float2 az[kMaxClusters];
+  __shared__ float2 az[kMaxClusters];   // first seed of each cluster
+  __shared__ float4 acc[kMaxClusters];  // sum x, sum y, sum (1 - r_U), count
   const int lane = lane_id();
   int ncl = 0;
+  float tot = 0.0f;  // lane 0: total weight of the seeds, in detection order
   const float cd2 = cd * cd;
   for (int i0 = 0; i0 < M; i0 += kWave) {
     const int ii = i0 + lane;
-    const bool seed = ii < M && ru[ii] < rumax;
+    float2 zl = make_float2(0.f, 0.f);
+    float rl = 1.0f;
+    if (ii < M) {
+      zl = z[ii];
+      rl = ru[ii];
+    }
+    const bool seed = ii < M && rl < rumax;
     const uint64_t seeds = __ballot(seed);
     if (ii < M && !seed) member[ii] = -1;
     uint64_t b = seeds;
     while (b) {
-      const int i = i0 + __ffsll((unsigned long long)b) - 1;
+      const int k = __ffsll((unsigned long long)b) - 1;
       b &= b - 1;
-      const float2 zi = z[i];
+      const float2 zi = make_float2(__shfl(zl.x, k, kWave), __shfl(zl.y, k, kWave));
+      const float ri = __shfl(rl, k, kWave);
       int found = -1;
       for (int c0 = 0; c0 < ncl && found < 0; c0 += kWave) {
         const int c = c0 + lane;
@@ -1049,37 +1071,39 @@ __global__ __launch_bounds__(64) void k_births(int M, const float2* z, const flo
           if (lane == 0) atomicOr(errf, ERR_BIRTH);
           found = kMaxClusters - 1;
         } else {
-          if (lane == 0) az[ncl] = zi;
+          if (lane == 0) {
+            az[ncl] = zi;
+            acc[ncl] = make_float4(0.f, 0.f, 0.f, 0.f);
+          }
           found = ncl++;
         }
       }
-      if (lane == 0) member[i] = found;
+      if (lane == 0) {
+        member[i0 + k] = found;
+        float4 a4 = acc[found];
+        a4.x += zi.x;
+        a4.y += zi.y;
+        a4.z += 1.0f - ri;
+        a4.w += 1.0f;
+        acc[found] = a4;
+        tot += 1.0f - ri;
+      }
       __syncthreads();
     }
   }
+  tot = __shfl(tot, 0, kWave);
   __syncthreads();
-  // total weight of the seeds (sequential, fixed order)
-  float tot = 0.0f;
-  for (int i = 0; i < M; ++i)
-    if (member[i] >= 0) tot += 1.0f - ru[i];
   for (int c = lane; c < ncl; c += kWave) {
-    float sx = 0.0f, sy = 0.0f, w = 0.0f;
-    int n = 0;
-    for (int i = 0; i < M; ++i)
-      if (member[i] == c) {
-        sx += z[i].x;
-        sy += z[i].y;
-        w += 1.0f - ru[i];
-        ++n;
-      }
+    const float4 a4 = acc[c];
+    const float n = a4.w;
     DBirth bb;
-    bb.m[0] = sx / (float)n;
-    bb.m[1] = sy / (float)n;
+    bb.m[0] = a4.x / n;
+    bb.m[1] = a4.y / n;
     bb.m[2] = bb.m[3] = 0.0f;
     for (int k = 0; k < 10; ++k) bb.P[k] = 0.0f;
-    bb.P[0] = bb.P[4] = sig2 / (float)n;
+    bb.P[0] = bb.P[4] = sig2 / n;
     bb.P[7] = bb.P[9] = sigv2;
-    bb.r = fminf(rmax, brate * w / tot);
+    bb.r = fminf(rmax, brate * a4.z / tot);
     bb.pad = 0;
     out[c] = bb;
   }
@@ -1430,9 +1454,8 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   // child masks: count
   int32_t* mcount = need<int32_t>(c.ccount, nk + 1);
   int32_t* moff = need<int32_t>(c.coff2, nk + 1);
-  GLMB_LAUNCH(k_child_mods, cdiv(nk, T), T, 0, s, nk, LW, chh, hpm, doff, devi, devn, devo, SW, c.rows.as<int32_t>(),
-              loff, llen, lmeas, dmask, eb, em, eoff, (const int32_t*)nullptr, mcount, (int32_t*)nullptr,
-              (int32_t*)nullptr, (int32_t*)nullptr, (uint32_t*)nullptr);
+  GLMB_LAUNCH(k_child_mods, cdiv(nk, T), T, 0, s, nk, doff, devn, devo, (const int32_t*)nullptr, mcount,
+              (int32_t*)nullptr, (int32_t*)nullptr);
   scan_excl(mcount, moff, nk, moff + nk, c.tmp, s);
   const int nm = read1(s, moff + nk);
   trace(c, "update.masks", np, ne);
@@ -1449,9 +1472,11 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   uint32_t* rec_m = need<uint32_t>(c.rec_m, (int64_t)(R + 1) * LW);
   GLMB_LAUNCH(k_rec_defaults, cdiv(U, T), T, 0, s, U, LW, first, dmask, dpre, rec_u, rec_m);
   GLMB_LAUNCH(k_rec_copy, cdiv(ne, T), T, 0, s, ne, LW, eu, em, rec_u + nd, rec_m + (size_t)nd * LW);
-  GLMB_LAUNCH(k_child_mods, cdiv(nk, T), T, 0, s, nk, LW, chh, hpm, doff, devi, devn, devo, SW, c.rows.as<int32_t>(),
-              loff, llen, lmeas, dmask, eb, em, eoff, (const int32_t*)moff, mcount, rec_u + nd + ne,
-              rec_a + nd + ne, rec_b + nd + ne, rec_m + (size_t)(nd + ne) * LW);
+  GLMB_LAUNCH(k_child_mods, cdiv(nk, T), T, 0, s, nk, doff, devn, devo, (const int32_t*)moff, mcount,
+              rec_a + nd + ne, rec_b + nd + ne);
+  GLMB_LAUNCH(k_mod_masks, cdiv(nm, T), T, 0, s, nm, LW, chh, hpm, doff, devi, devn, devo, SW, c.rows.as<int32_t>(),
+              loff, llen, lmeas, dmask, eb, em, eoff, (const int32_t*)(rec_a + nd + ne),
+              (const int32_t*)(rec_b + nd + ne), rec_u + nd + ne, rec_m + (size_t)(nd + ne) * LW);
   uint64_t* rk = need<uint64_t>(c.rec_keys, R + 1);
   uint32_t* rv = need<uint32_t>(c.rec_vals, R + 1);
   GLMB_LAUNCH(k_rec_keys, cdiv(R, T), T, 0, s, R, LW, rec_u, rec_m, rk, rv);
