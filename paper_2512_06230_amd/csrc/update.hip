@@ -176,6 +176,12 @@ struct CellOut {
   float b1, l;
   unsigned opts;
 };
+// The four first options of a cell in (value descending, candidate position) order, clutter
+// (slot -1) first among equals; unused entries hold -inf and slot -2.
+struct Top4 {
+  float v[4];
+  int32_t s[4];
+};
 __device__ __forceinline__ CellOut assoc_cell(int i, int M, const int32_t* row, float lgk, const int32_t* coff,
                                               const int32_t* cand, const float* phi, int16_t* best16, float* dev1,
                                               size_t cell, float c) {
@@ -241,29 +247,111 @@ __device__ __forceinline__ void assoc_finish(int h, float bsum, float lsum, unsi
   }
 }
 
-// Hypothesis 0 (one workgroup, row in LDS): every cell, plus the reference values the other
-// hypotheses copy where their options are the same (b1 - c_i and the option count).
-__global__ __launch_bounds__(256) void k_assoc_ref(int M, int stride, const int32_t* rows, const float* logw,
-                                                   const int32_t* ntrk, float gamma, float lgk, const int32_t* coff,
+// Hypothesis 0, one wave per cell: the lanes take the detection's candidates 64 at a time,
+// each keeping its first four options, log-sum-exp and option count, merged across the wave
+// in a fixed butterfly.  Besides the cell's own results it stores the reference values the
+// other hypotheses start from (b1 - c_i, the option count, the first four options).
+__device__ __forceinline__ bool top_before(float va, int sa, float vb, int sb) {
+  return va > vb || (va == vb && sa < sb);
+}
+__global__ __launch_bounds__(256) void k_assoc_ref(int M, const int32_t* rows, float lgk, const int32_t* coff,
                                                    const int32_t* cand, const float* phi, const uint32_t* cmax,
-                                                   int16_t* best16, float* dev1, float* lserel, float* bprime,
-                                                   float* lzprime, float* ref_b1, int32_t* ref_opts,
-                                                   int32_t* hopts) {
-  extern __shared__ int32_t row[];
+                                                   int16_t* best16, float* dev1, float* lserel, float* ref_b1,
+                                                   int32_t* ref_opts, Top4* ref_top) {
+  const int i = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kWave);
+  if (i >= M) return;
+  const int lane = lane_id();
+  Top4 t;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    t.v[j] = -INFINITY;
+    t.s[j] = -2;
+  }
+  float mx = -INFINITY, sm = 0.0f;
+  unsigned opts = 0;
+  if (lane == 0) {  // clutter, ahead of every candidate
+    t.v[0] = lgk;
+    t.s[0] = -1;
+    mx = lgk;
+    sm = 1.0f;
+  }
+  for (int e = coff[i] + lane; e < coff[i + 1]; e += kWave) {
+    const int sl = cand[e];
+    const int u = rows[sl];
+    if (u < 0) continue;
+    const float f = phi[(size_t)u * M + i];
+    if (!(f > -INFINITY)) continue;
+    ++opts;
+    if (f > t.v[3]) {
+      int j = 3;
+      while (j > 0 && f > t.v[j - 1]) {
+        t.v[j] = t.v[j - 1];
+        t.s[j] = t.s[j - 1];
+        --j;
+      }
+      t.v[j] = f;
+      t.s[j] = sl;
+    }
+    if (f > mx) {
+      sm = sm * __expf(mx - f) + 1.0f;
+      mx = f;
+    } else {
+      sm += __expf(f - mx);
+    }
+  }
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    Top4 o;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      o.v[j] = __shfl_xor(t.v[j], d, kWave);
+      o.s[j] = __shfl_xor(t.s[j], d, kWave);
+    }
+    const float omx = __shfl_xor(mx, d, kWave), osm = __shfl_xor(sm, d, kWave);
+    opts += __shfl_xor(opts, d, kWave);
+    // merge of two ordered lists (the same result on both partners)
+    Top4 r;
+    int a = 0, b = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if (top_before(t.v[a], t.s[a], o.v[b], o.s[b])) {
+        r.v[j] = t.v[a];
+        r.s[j] = t.s[a];
+        ++a;
+      } else {
+        r.v[j] = o.v[b];
+        r.s[j] = o.s[b];
+        ++b;
+      }
+    }
+    t = r;
+    const float m = fmaxf(mx, omx);
+    sm = m > -INFINITY ? sm * __expf(mx - m) + osm * __expf(omx - m) : 0.0f;
+    mx = m;
+  }
+  if (lane == 0) {
+    const float c = o2f(cmax[i]);
+    const float l = mx + __logf(sm);
+    best16[i] = (int16_t)(t.s[0] + 1);
+    dev1[i] = t.v[1] > -INFINITY ? t.v[0] - t.v[1] : INFINITY;
+    lserel[i] = l - c;
+    ref_b1[i] = t.v[0] - c;
+    ref_opts[i] = (int32_t)opts;
+    ref_top[i] = t;
+  }
+}
+
+// hypothesis 0's sums over its cells, in a fixed order
+__global__ __launch_bounds__(256) void k_assoc_ref_sum(int M, const float* ref_b1, const float* lserel,
+                                                       const int32_t* ref_opts, const float* logw,
+                                                       const int32_t* ntrk, float gamma, float* bprime,
+                                                       float* lzprime, int32_t* hopts) {
   __shared__ float red[16];
-  for (int s = threadIdx.x; s < stride; s += blockDim.x) row[s] = rows[s];
-  __syncthreads();
   float bsum = 0.0f, lsum = 0.0f;
   unsigned opts = 0;
   for (int i = threadIdx.x; i < M; i += blockDim.x) {
-    const float c = o2f(cmax[i]);
-    const CellOut o = assoc_cell(i, M, row, lgk, coff, cand, phi, best16, dev1, (size_t)i, c);
-    lserel[i] = o.l - c;
-    ref_b1[i] = o.b1 - c;
-    ref_opts[i] = (int32_t)o.opts;
-    bsum += o.b1 - c;
-    lsum += o.l - c;
-    opts += o.opts;
+    bsum += ref_b1[i];
+    lsum += lserel[i];
+    opts += (unsigned)ref_opts[i];
   }
   assoc_finish(0, bsum, lsum, opts, logw, ntrk, gamma, bprime, lzprime, hopts, red);
 }
@@ -283,7 +371,8 @@ __global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t*
                                                const int32_t* coff, const int32_t* cand, const float* phi,
                                                const uint32_t* cmax, const int32_t* loff, const int32_t* llen,
                                                const int32_t* lmeas, const uint32_t* lbits, const float* ref_b1,
-                                               const int32_t* ref_opts, int16_t* best16, float* dev1, float* lserel,
+                                               const int32_t* ref_opts, const Top4* ref_top, int16_t* best16,
+                                               float* dev1, float* lserel,
                                                float* bprime, float* lzprime, int32_t* hopts) {
   // LDS: row[stride] | changed slots, ascending[stride] | touched-detection bits[(M + 31) / 32]
   extern __shared__ int32_t row[];
@@ -339,24 +428,24 @@ __global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t*
     }
     const float c = o2f(cmax[i]);
     const float s_ref = __expf(lserel[i]);
-    const int k1r = (int)best16[i] - 1;
-    const float b1r = ref_b1[i] + c;
-    const float d1r = dev1[i];
-    const float b2r = d1r < INFINITY ? b1r - d1r : -INFINITY;
-    float rem = 0.0f, add = 0.0f, nb1 = b1r, nb2 = b2r;
-    int nk1 = k1r, dopt = 0;
-    bool full = false;
+    const Top4 T = ref_top[i];
+    float rem = 0.0f, add = 0.0f;
+    float a1 = -INFINITY, a2 = -INFINITY;  // best two added options (best: smallest slot among equals)
+    int a1s = INT_MAX, dopt = 0;
+    unsigned gone = 0;  // entries of T whose option is removed
     const uint32_t bit = 1u << (i & 31);
-    for (int q = 0; q < nd && !full; ++q) {
+    for (int q = 0; q < nd; ++q) {
       const int s = dl[q];
       if (!(lbits[(size_t)s * W + (i >> 5)] & bit)) continue;
       const int u0 = rows[s], uh = row[s];
       if (u0 >= 0) {
         const float f0 = phi[(size_t)u0 * M + i];
         if (f0 > -INFINITY) {
-          if (s == k1r || f0 >= b2r) full = true;
           rem += __expf(f0 - c);
           --dopt;
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (T.s[j] == s) gone |= 1u << j;
         }
       }
       if (uh >= 0) {
@@ -364,23 +453,52 @@ __global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t*
         if (fh > -INFINITY) {
           add += __expf(fh - c);
           ++dopt;
-          if (fh > nb1 || (fh == nb1 && s < nk1)) {
-            nb2 = nb1;
-            nb1 = fh;
-            nk1 = s;
-          } else if (fh > nb2) {
-            nb2 = fh;
+          if (fh > a1 || (fh == a1 && s < a1s)) {
+            a2 = a1;
+            a1 = fh;
+            a1s = s;
+          } else if (fh > a2) {
+            a2 = fh;
           }
         }
       }
     }
-    if (full || rem > 0.5f * s_ref) {
+    // hypothesis 0's first options that remain, in order
+    float r1 = -INFINITY, r2 = -INFINITY;
+    int r1s = -2, nrem = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (T.s[j] != -2 && !((gone >> j) & 1u)) {
+        if (nrem == 0) {
+          r1 = T.v[j];
+          r1s = T.s[j];
+        } else if (nrem == 1) {
+          r2 = T.v[j];
+        }
+        ++nrem;
+      }
+    // Options of hypothesis 0 beyond its first four are worth at most T.v[3] and come after
+    // the first four's equals in candidate order, so the first remaining one is best among
+    // them and, with two remaining, the second value is known too.
+    const bool known = ref_opts[i] + 1 <= 4 || nrem >= 2;
+    if (!known || rem > 0.5f * s_ref) {
       const CellOut o = assoc_cell(i, M, row, lgk, coff, cand, phi, best16, dev1, cell, c);
       lserel[cell] = o.l - c;
       bsum += o.b1 - c;
       lsum += o.l - c;
       opts += o.opts;
     } else {
+      float nb1, nb2;
+      int nk1;
+      if (a1 > r1 || (a1 == r1 && a1s < r1s)) {
+        nb1 = a1;
+        nk1 = a1s;
+        nb2 = fmaxf(r1, a2);
+      } else {
+        nb1 = r1;
+        nk1 = r1s;
+        nb2 = fmaxf(r2, a1);
+      }
       const float lc = __logf(s_ref - rem + add);
       best16[cell] = (int16_t)(nk1 + 1);
       dev1[cell] = nb2 > -INFINITY ? nb1 - nb2 : INFINITY;
@@ -1234,10 +1352,14 @@ void assoc_norm(Ctx& c, int M) {
   float* lzprime = need<float>(c.lzprime, H);
   float* ref_b1 = need<float>(c.ref_b1, M + 1);
   int32_t* ref_opts = need<int32_t>(c.ref_opts, M + 1);
+  Top4* ref_top = need<Top4>(c.ref_top, M + 1);
   int32_t* hopts = need<int32_t>(c.hopts, H + 1);
-  GLMB_LAUNCH(k_assoc_ref, 1, 256, SW * sizeof(int32_t), s, M, SW, c.rows.as<int32_t>(), c.logw.as<float>(),
-              c.ntrk.as<int32_t>(), p.det_rate, lgk, c.coff.as<int32_t>(), c.cand.as<int32_t>(), c.phi.as<float>(),
-              c.cmax.as<uint32_t>(), best16, dev1, lserel, bprime, lzprime, ref_b1, ref_opts, hopts);
+  GLMB_LAUNCH(k_assoc_ref, cdiv((int64_t)M * kWave, 256), 256, 0, s, M, c.rows.as<int32_t>(), lgk,
+              c.coff.as<int32_t>(), c.cand.as<int32_t>(), c.phi.as<float>(), c.cmax.as<uint32_t>(), best16, dev1,
+              lserel, ref_b1, ref_opts, ref_top);
+  GLMB_LAUNCH(k_assoc_ref_sum, 1, 256, 0, s, M, (const float*)ref_b1, (const float*)lserel,
+              (const int32_t*)ref_opts, c.logw.as<float>(), c.ntrk.as<int32_t>(), p.det_rate, bprime, lzprime,
+              hopts);
   const size_t lds = (size_t)(2 * SW + (M + 31) / 32) * sizeof(int32_t);
   if (lds > 64 * 1024)
     GLMB_HIP(hipFuncSetAttribute((const void*)k_assoc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
@@ -1245,7 +1367,7 @@ void assoc_norm(Ctx& c, int M) {
   GLMB_LAUNCH(k_assoc, H - 1, 256, lds, s, M, SW, c.rows.as<int32_t>(), c.logw.as<float>(), c.ntrk.as<int32_t>(),
               p.det_rate, lgk, c.coff.as<int32_t>(), c.cand.as<int32_t>(), c.phi.as<float>(), c.cmax.as<uint32_t>(),
               c.loff.as<int32_t>(), c.llen.as<int32_t>(), c.lmeas.as<int32_t>(), c.lbits.as<uint32_t>(), ref_b1,
-              ref_opts, best16, dev1, lserel, bprime, lzprime, hopts);
+              ref_opts, (const Top4*)ref_top, best16, dev1, lserel, bprime, lzprime, hopts);
   c.mark(2);
   float* dbest = need<float>(c.diag_best, H);
   float* dlogpi = need<float>(c.diag_logpi, H);
