@@ -65,7 +65,7 @@ struct Ctx {
   DevBuf z, cmax, gbits, phi, lbits, lpre, llen, loff, lmeas, inst_beg, ccnt, coff, cand, best16, dev1, lserel,
       bprime, lzprime, vals, cells, ccount, coff2, it_h, it_delta, it_group, it_opt, it_off, keys, vals32, scal,
       sel_logw, hp_map, first, dmask, exc, cmod, recs, rec_keys, rec_vals, ids, row_mark, ru_part, ru, bt,
-      tmp, tk, tv, flags, pre, pmult, pvals, rec_m, ref_b1, ref_opts, ref_top, hopts;
+      tmp, tk, tv, flags, pre, pmult, pvals, rec_m, ref_b1, ref_opts, ref_top, ref_rest, hopts;
   SelectBufs sb;
   bool sel_multi[2] = {false, false};  // per search site (prediction, update): start on the whole GPU
   bool coop_ok = true;  // cooperative launches allowed (they run one at a time on a device)

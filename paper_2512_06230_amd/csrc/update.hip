@@ -257,7 +257,7 @@ __device__ __forceinline__ bool top_before(float va, int sa, float vb, int sb) {
 __global__ __launch_bounds__(256) void k_assoc_ref(int M, const int32_t* rows, float lgk, const int32_t* coff,
                                                    const int32_t* cand, const float* phi, const uint32_t* cmax,
                                                    int16_t* best16, float* dev1, float* lserel, float* ref_b1,
-                                                   int32_t* ref_opts, Top4* ref_top) {
+                                                   int32_t* ref_opts, Top4* ref_top, float* ref_rest) {
   const int i = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kWave);
   if (i >= M) return;
   const int lane = lane_id();
@@ -328,15 +328,42 @@ __global__ __launch_bounds__(256) void k_assoc_ref(int M, const int32_t* rows, f
     sm = m > -INFINITY ? sm * __expf(mx - m) + osm * __expf(omx - m) : 0.0f;
     mx = m;
   }
+  // the same log-sum-exp without the best option, for hypotheses that lose it
+  const int k1 = t.s[0];
+  float rx = -INFINITY, rs = 0.0f;
+  if (lane == 0 && k1 != -1) {
+    rx = lgk;
+    rs = 1.0f;
+  }
+  for (int e = coff[i] + lane; e < coff[i + 1]; e += kWave) {
+    const int sl = cand[e];
+    const int u = rows[sl];
+    if (u < 0 || sl == k1) continue;
+    const float f = phi[(size_t)u * M + i];
+    if (!(f > -INFINITY)) continue;
+    if (f > rx) {
+      rs = rs * __expf(rx - f) + 1.0f;
+      rx = f;
+    } else {
+      rs += __expf(f - rx);
+    }
+  }
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    const float ox = __shfl_xor(rx, d, kWave), os = __shfl_xor(rs, d, kWave);
+    const float m = fmaxf(rx, ox);
+    rs = m > -INFINITY ? rs * __expf(rx - m) + os * __expf(ox - m) : 0.0f;
+    rx = m;
+  }
   if (lane == 0) {
     const float c = o2f(cmax[i]);
     const float l = mx + __logf(sm);
-    best16[i] = (int16_t)(t.s[0] + 1);
+    best16[i] = (int16_t)(k1 + 1);
     dev1[i] = t.v[1] > -INFINITY ? t.v[0] - t.v[1] : INFINITY;
     lserel[i] = l - c;
     ref_b1[i] = t.v[0] - c;
     ref_opts[i] = (int32_t)opts;
     ref_top[i] = t;
+    ref_rest[i] = rx > -INFINITY ? rs * __expf(rx - c) : 0.0f;
   }
 }
 
@@ -362,17 +389,18 @@ __global__ __launch_bounds__(256) void k_assoc_ref_sum(int M, const float* ref_b
 // derived from hypothesis 0's: its options lose the changed labels' old instances and gain
 // their new ones, so with S = sum over options of exp(phi - c_i) (= exp(lserel)),
 //   S_h = S_0 - sum(removed) + sum(added),
-// and the best option and first deviation follow from hypothesis 0's best and second best
-// and the added options.  The cell is recomputed from all its options instead when a removed
-// option is hypothesis 0's best or could be its second best, or when the removed options
-// carry more than half of S_0 (the difference would lose precision).
+// taken from hypothesis 0's sum without its best option when that one is removed; the best
+// option and the second value follow from hypothesis 0's first four options that remain and
+// the added options.  The cell is recomputed from all its options instead when fewer than two
+// of the four remain (and hypothesis 0 had more), or when the removed options carry more than
+// half of the sum they are taken from (the difference would lose precision).
 __global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t* rows, const float* logw,
                                                const int32_t* ntrk, float gamma, float lgk,
                                                const int32_t* coff, const int32_t* cand, const float* phi,
                                                const uint32_t* cmax, const int32_t* loff, const int32_t* llen,
                                                const int32_t* lmeas, const uint32_t* lbits, const float* ref_b1,
-                                               const int32_t* ref_opts, const Top4* ref_top, int16_t* best16,
-                                               float* dev1, float* lserel,
+                                               const int32_t* ref_opts, const Top4* ref_top,
+                                               const float* ref_rest, int16_t* best16, float* dev1, float* lserel,
                                                float* bprime, float* lzprime, int32_t* hopts) {
   // LDS: row[stride] | changed slots, ascending[stride] | touched-detection bits[(M + 31) / 32]
   extern __shared__ int32_t row[];
@@ -429,7 +457,8 @@ __global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t*
     const float c = o2f(cmax[i]);
     const float s_ref = __expf(lserel[i]);
     const Top4 T = ref_top[i];
-    float rem = 0.0f, add = 0.0f;
+    float rem = 0.0f, add = 0.0f;  // removed mass (hypothesis 0's best apart) and added mass
+    bool rbest = false;            // hypothesis 0's best option is removed
     float a1 = -INFINITY, a2 = -INFINITY;  // best two added options (best: smallest slot among equals)
     int a1s = INT_MAX, dopt = 0;
     unsigned gone = 0;  // entries of T whose option is removed
@@ -441,7 +470,8 @@ __global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t*
       if (u0 >= 0) {
         const float f0 = phi[(size_t)u0 * M + i];
         if (f0 > -INFINITY) {
-          rem += __expf(f0 - c);
+          if (s == T.s[0]) rbest = true;
+          else rem += __expf(f0 - c);
           --dopt;
 #pragma unroll
           for (int j = 0; j < 4; ++j)
@@ -481,7 +511,10 @@ __global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t*
     // the first four's equals in candidate order, so the first remaining one is best among
     // them and, with two remaining, the second value is known too.
     const bool known = ref_opts[i] + 1 <= 4 || nrem >= 2;
-    if (!known || rem > 0.5f * s_ref) {
+    // the remaining mass from a sum that excludes hypothesis 0's best when that is removed; a
+    // difference that would cancel most of it is recomputed instead
+    const float base = rbest ? ref_rest[i] : s_ref;
+    if (!known || rem > 0.5f * base) {
       const CellOut o = assoc_cell(i, M, row, lgk, coff, cand, phi, best16, dev1, cell, c);
       lserel[cell] = o.l - c;
       bsum += o.b1 - c;
@@ -499,7 +532,7 @@ __global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t*
         nk1 = r1s;
         nb2 = fmaxf(r2, a1);
       }
-      const float lc = __logf(s_ref - rem + add);
+      const float lc = __logf(base - rem + add);
       best16[cell] = (int16_t)(nk1 + 1);
       dev1[cell] = nb2 > -INFINITY ? nb1 - nb2 : INFINITY;
       lserel[cell] = lc;
@@ -1353,10 +1386,11 @@ void assoc_norm(Ctx& c, int M) {
   float* ref_b1 = need<float>(c.ref_b1, M + 1);
   int32_t* ref_opts = need<int32_t>(c.ref_opts, M + 1);
   Top4* ref_top = need<Top4>(c.ref_top, M + 1);
+  float* ref_rest = need<float>(c.ref_rest, M + 1);
   int32_t* hopts = need<int32_t>(c.hopts, H + 1);
   GLMB_LAUNCH(k_assoc_ref, cdiv((int64_t)M * kWave, 256), 256, 0, s, M, c.rows.as<int32_t>(), lgk,
               c.coff.as<int32_t>(), c.cand.as<int32_t>(), c.phi.as<float>(), c.cmax.as<uint32_t>(), best16, dev1,
-              lserel, ref_b1, ref_opts, ref_top);
+              lserel, ref_b1, ref_opts, ref_top, ref_rest);
   GLMB_LAUNCH(k_assoc_ref_sum, 1, 256, 0, s, M, (const float*)ref_b1, (const float*)lserel,
               (const int32_t*)ref_opts, c.logw.as<float>(), c.ntrk.as<int32_t>(), p.det_rate, bprime, lzprime,
               hopts);
@@ -1367,7 +1401,7 @@ void assoc_norm(Ctx& c, int M) {
   GLMB_LAUNCH(k_assoc, H - 1, 256, lds, s, M, SW, c.rows.as<int32_t>(), c.logw.as<float>(), c.ntrk.as<int32_t>(),
               p.det_rate, lgk, c.coff.as<int32_t>(), c.cand.as<int32_t>(), c.phi.as<float>(), c.cmax.as<uint32_t>(),
               c.loff.as<int32_t>(), c.llen.as<int32_t>(), c.lmeas.as<int32_t>(), c.lbits.as<uint32_t>(), ref_b1,
-              ref_opts, (const Top4*)ref_top, best16, dev1, lserel, bprime, lzprime, hopts);
+              ref_opts, (const Top4*)ref_top, (const float*)ref_rest, best16, dev1, lserel, bprime, lzprime, hopts);
   c.mark(2);
   float* dbest = need<float>(c.diag_best, H);
   float* dlogpi = need<float>(c.diag_logpi, H);
