@@ -257,7 +257,7 @@ glmb_status glmb_destroy(glmb_ctx* x) {
                           &c.tv, &c.flags, &c.pre, &c.pmult, &c.pvals, &c.rec_m, &c.sb.nd_parent, &c.sb.nd_item, &c.sb.nd_h, &c.sb.nd_bloom,
                           &c.sb.nd_value, &c.sb.cnt, &c.sb.pre, &c.sb.pre64, &c.sb.flags, &c.sb.map, &c.sb.tmp,
                           &c.sb.tk, &c.sb.tv, &c.sb.keys, &c.sb.vals, &c.sb.sel_node, &c.sb.sel_val, &c.sb.sel_rank, &c.sb.hist,
-                          &c.sb.scal, &c.sb.dp, &c.sb.dpc, &c.sb.dpa, &c.prop_w, &c.pcnt, &c.poff, &c.ppre, &c.pu, &c.pi, &c.plogit, &c.slot_r,
+                          &c.sb.scal, &c.sb.dp, &c.sb.dpc, &c.sb.dpa, &c.sb.cand, &c.prop_w, &c.pcnt, &c.poff, &c.ppre, &c.pu, &c.pi, &c.plogit, &c.slot_r,
                           &c.slot_part, &c.slot_age, &c.pm_part, &c.pe_part, &c.lz_t, &c.mlp_part, &c.est_buf, &c.ref_b1, &c.ref_opts, &c.ref_top, &c.ref_rest, &c.hopts};
   for (auto* b : bufs) b->release();
   if (c.ev_ok)

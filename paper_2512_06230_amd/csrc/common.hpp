@@ -45,8 +45,10 @@ struct DevBuf {
   size_t bytes = 0;
   void reserve(size_t n, bool keep = false, hipStream_t s = nullptr) {
     if (n <= bytes) return;
+    // at least twice the request: sizes creep up over the first scans of a scene, and every
+    // growth costs an allocation and a device-wide synchronisation
     size_t nb = bytes ? bytes : 4096;
-    while (nb < n) nb *= 2;
+    while (nb < 2 * n) nb *= 2;
     void* q = nullptr;
     if (hipMalloc(&q, nb) != hipSuccess) throw Error{GLMB_E_NOMEM, "hipMalloc of " + std::to_string(nb) + " bytes failed"};
     if (keep && p && bytes) {
@@ -107,6 +109,9 @@ void sort_pairs(uint64_t* keys, uint32_t* vals, int n, int bit0, int bit1, DevBu
 void kth_bound(const float* v, int n, int K, float* out, DevBuf& tmp, hipStream_t s);
 // Same, for values given as (value, multiplicity) pairs.
 void kth_bound_mult(const float* v, const int32_t* mult, int n, int K, float* out, DevBuf& tmp, hipStream_t s);
+// Same, over the H * (M + 1) values B[h] - dev1[h * M + i] (i < M) and B[h].
+void kth_bound_cells(const float* B, const float* dev1, int H, int M, int K, float* out, DevBuf& tmp,
+                     hipStream_t s);
 
 // ------------------------------------------------------------------ selection engine (select.hip)
 // Parents with base values; per-parent item lists sorted by (delta, group, option).
@@ -137,7 +142,7 @@ struct Selected {
 };
 struct SelectBufs {
   DevBuf nd_parent, nd_item, nd_h, nd_value, nd_bloom, cnt, pre, pre64, flags, map, tmp, tk, tv, keys, vals, sel_node,
-      sel_val, sel_rank, scal, hist, dp, dpc, dpa;
+      sel_val, sel_rank, scal, hist, dp, dpc, dpa, cand;
   bool hist_ready = false;  // hist holds zeros (the cooperative search leaves it so)
   bool dpc_ready = false;   // dpc holds zeros (the counting bound leaves it so)
 };

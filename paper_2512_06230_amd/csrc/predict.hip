@@ -5,6 +5,9 @@
 // deviation is |log p - log(1 - p)|).  Children of different parents with the same track set
 // are merged (weights added, representative = smallest canonical key), the result is
 // normalised, and labels and instances no hypothesis uses any more are dropped.
+#include <algorithm>
+#include <cmath>
+
 #include "ctx.hpp"
 
 namespace glmb {
@@ -52,17 +55,35 @@ __global__ void k_pvals(int H, int NB, const float* logw, const int32_t* ntrk, f
   }
 }
 
-// items of a parent: its tracks (group = slot, delta dt_) and the births (group NS + b)
-__global__ __launch_bounds__(256) void k_pitems(int H, int NS, int NB, int stride, const int32_t* rows,
-                                                const int32_t* ntrk, const float* V, float dt_, const float* bd,
+// Items of a parent, already in (delta, generation) order: its tracks (group = slot, delta
+// dt_, in slot order) and the births (group NS + b, delta bd[b]) whose value stays above the
+// cut bound.  The births come sorted by (bd, b) (bs, bg); the nlt of them with bd < dt_ go
+// before the tracks, the others after (tracks are generated first, so they lead among equal
+// deltas).  V - bd is non-increasing along the sorted births, so the kept ones are a prefix.
+// Counting pass (ioff null): icount[h]; writing pass: items at ioff[h].
+__global__ __launch_bounds__(256) void k_pitems(int H, int nbs, int nlt, int stride, const int32_t* rows,
+                                                const float* V, float dt_, const float* bs, const int32_t* bg,
                                                 const float* t0, const int32_t* ioff, int32_t* icount, float* it_d,
-                                                int32_t* it_g, uint64_t* keys, uint32_t* vals) {
+                                                int32_t* it_g) {
   __shared__ int32_t wsum[4];
+  __shared__ int32_t nkb_s;
   const int h = blockIdx.x;
   const float t = *t0, v = V[h];
   const bool tracks = !isinf(dt_) && v - dt_ >= t;
-  int base = ioff ? ioff[h] : 0;
-  int cnt = 0;
+  if (threadIdx.x == 0) {
+    int lo = 0, hi = nbs;  // kept births: the prefix with v - bs >= t
+    while (lo < hi) {
+      const int m = (lo + hi) >> 1;
+      if (v - bs[m] >= t) lo = m + 1;
+      else hi = m;
+    }
+    nkb_s = lo;
+  }
+  __syncthreads();
+  const int nkb = nkb_s;
+  const int nbefore = min(nlt, nkb);
+  const int q0 = ioff ? ioff[h] : 0;
+  int ntr = 0;
   if (tracks) {
     // present slots in slot order: block-wide compaction over the row
     for (int s0 = 0; s0 < stride; s0 += blockDim.x) {
@@ -78,49 +99,21 @@ __global__ __launch_bounds__(256) void k_pitems(int H, int NS, int NB, int strid
         all += wsum[j];
       }
       if (pres && ioff) {
-        const int q = base + cnt + before + __popcll(bal & lanemask_lt());
+        const int q = q0 + nbefore + ntr + before + __popcll(bal & lanemask_lt());
         it_d[q] = dt_;
         it_g[q] = sl;
-        keys[q] = ((uint64_t)(uint32_t)h << 32) | f2o(dt_);
-        vals[q] = (uint32_t)q;
       }
-      cnt += all;
+      ntr += all;
       __syncthreads();
     }
   }
-  if (threadIdx.x == 0) {
-    for (int b = 0; b < NB; ++b)
-      if (!isinf(bd[b]) && v - bd[b] >= t) {
-        if (ioff) {
-          const int q = base + cnt;
-          it_d[q] = bd[b];
-          it_g[q] = NS + b;
-          keys[q] = ((uint64_t)(uint32_t)h << 32) | f2o(bd[b]);
-          vals[q] = (uint32_t)q;
-        }
-        ++cnt;
-      }
-    if (!ioff) icount[h] = cnt;
-  }
-}
-
-__global__ void k_pitem_perm(int n, const uint32_t* vals, const float* d0, const int32_t* g0, float* d1, int32_t* g1) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  d1[p] = d0[vals[p]];
-  g1[p] = g0[vals[p]];
-}
-
-__global__ void k_pitem_off(int H, int n, const uint64_t* keys, int32_t* it_off) {
-  const int h = blockIdx.x * blockDim.x + threadIdx.x;
-  if (h > H) return;
-  int a = 0, b = n;
-  while (a < b) {
-    const int m = (a + b) >> 1;
-    if ((int)(keys[m] >> 32) < h) a = m + 1;
-    else b = m;
-  }
-  it_off[h] = a;
+  if (ioff)
+    for (int j = threadIdx.x; j < nkb; j += blockDim.x) {
+      const int q = j < nlt ? q0 + j : q0 + ntr + j;
+      it_d[q] = bs[j];
+      it_g[q] = bg[j];
+    }
+  if (!ioff && threadIdx.x == 0) icount[h] = ntr + nkb;
 }
 
 // child rows (width NS + NB), their hash and track count
@@ -171,10 +164,12 @@ __global__ __launch_bounds__(256) void k_prows(int n, int NS, int NB, int stride
   }
 }
 
+// 32 bits of the row hash: children with equal rows share them, and rows of one run are
+// compared in full, so a shorter key only lengthens a few runs
 __global__ void k_hash_keys(int n, const uint64_t* hash, uint64_t* keys, uint32_t* vals) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
-  keys[c] = hash[c];
+  keys[c] = hash[c] >> 32;
   vals[c] = (uint32_t)c;
 }
 
@@ -234,12 +229,13 @@ __global__ void k_merge(int n, const int32_t* leader, const float* val, const in
   mrep[c] = rp;
 }
 
-__global__ void k_lead_keys(int n, const int32_t* is_lead, const int32_t* lpre, const float* mval,
+// sort keys of the merged hypotheses: value descending, then rank (below 2^rb)
+__global__ void k_lead_keys(int n, int rb, const int32_t* is_lead, const int32_t* lpre, const float* mval,
                             const int32_t* mrank, uint64_t* keys, uint32_t* vals) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n || !is_lead[c]) return;
   const int d = lpre[c];
-  keys[d] = ((uint64_t)(~f2o(mval[c])) << 32) | (uint32_t)mrank[c];
+  keys[d] = ((uint64_t)(~f2o(mval[c])) << rb) | (uint32_t)mrank[c];
   vals[d] = (uint32_t)c;
 }
 
@@ -345,10 +341,28 @@ void stage_predict(Ctx& c, int k) {
     by[b] = a >= q ? 1 : 0;
     bd[b] = (float)std::fabs(a - q);
   }
-  float* dbd = need<float>(c.bt, 2 * (int64_t)NB + 2);
+  // births with a finite deviation sorted by (bd, b), and how many lie below the tracks' dt_
+  std::vector<int32_t> bord;
+  for (int b = 0; b < NB; ++b)
+    if (!std::isinf(bd[b])) bord.push_back(b);
+  std::stable_sort(bord.begin(), bord.end(), [&](int32_t x, int32_t y) { return bd[x] < bd[y]; });
+  const int nbs = (int)bord.size();
+  int nlt = 0;
+  while (nlt < nbs && bd[bord[nlt]] < dt_) ++nlt;
+  std::vector<float> bsv(nbs + 1, 0.0f);
+  std::vector<int32_t> bgv(nbs + 1, 0);
+  for (int j = 0; j < nbs; ++j) {
+    bsv[j] = bd[bord[j]];
+    bgv[j] = NS + bord[j];
+  }
+  float* dbd = need<float>(c.bt, 4 * (int64_t)NB + 4);
   int32_t* dby = (int32_t*)(dbd + NB + 1);
+  float* dbs = (float*)(dby + NB + 1);
+  int32_t* dbg = (int32_t*)(dbs + NB + 1);
   GLMB_HIP(hipMemcpyAsync(dbd, bd.data(), (NB + 1) * sizeof(float), hipMemcpyHostToDevice, s));
   GLMB_HIP(hipMemcpyAsync(dby, by.data(), (NB + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  GLMB_HIP(hipMemcpyAsync(dbs, bsv.data(), (nbs + 1) * sizeof(float), hipMemcpyHostToDevice, s));
+  GLMB_HIP(hipMemcpyAsync(dbg, bgv.data(), (nbs + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
   // ---- lower bound of the cut
   float* V = need<float>(c.bprime, H);
   float* pv = need<float>(c.pvals, (int64_t)H * (NB + 2));
@@ -357,28 +371,17 @@ void stage_predict(Ctx& c, int k) {
   kth_bound_mult(pv, pm, H * (NB + 2), p.h_max, t0, c.tmp, s);
   // ---- items
   int32_t* icount = need<int32_t>(c.ccount, H + 1);
-  int32_t* ioff = need<int32_t>(c.coff2, H + 1);
-  GLMB_LAUNCH(k_pitems, H, 256, 0, s, H, NS, NB, SW, c.rows.as<int32_t>(), c.ntrk.as<int32_t>(), V, dt_, dbd, t0,
-              (const int32_t*)nullptr, icount, (float*)nullptr, (int32_t*)nullptr, (uint64_t*)nullptr,
-              (uint32_t*)nullptr);
-  scan_excl(icount, ioff, H, ioff + H, c.tmp, s);
-  int32_t nitem = 0;
-  GLMB_HIP(hipMemcpyAsync(&nitem, ioff + H, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipStreamSynchronize(s));
-  float* itd0 = need<float>(c.it_delta, 2 * (int64_t)nitem + 2);
-  int32_t* itg0 = need<int32_t>(c.it_group, 2 * (int64_t)nitem + 2);
-  uint64_t* ik = need<uint64_t>(c.keys, nitem + 1);
-  uint32_t* iv = need<uint32_t>(c.vals32, nitem + 1);
-  GLMB_LAUNCH(k_pitems, H, 256, 0, s, H, NS, NB, SW, c.rows.as<int32_t>(), c.ntrk.as<int32_t>(), V, dt_, dbd, t0,
-              (const int32_t*)ioff, icount, itd0, itg0, ik, iv);
-  int hbits = 0;
-  while ((1 << hbits) < H) ++hbits;
-  sort_pairs(ik, iv, nitem, 0, 32 + ((hbits + 7) / 8) * 8, c.tk, c.tv, c.tmp, s);
-  float* itd = itd0 + nitem + 1;
-  int32_t* itg = itg0 + nitem + 1;
-  GLMB_LAUNCH(k_pitem_perm, cdiv(nitem, T), T, 0, s, nitem, iv, itd0, itg0, itd, itg);
+  GLMB_LAUNCH(k_pitems, H, 256, 0, s, H, nbs, nlt, SW, c.rows.as<int32_t>(), V, dt_, dbs, dbg, t0,
+              (const int32_t*)nullptr, icount, (float*)nullptr, (int32_t*)nullptr);
   int32_t* itoff = need<int32_t>(c.it_off, H + 1);
-  GLMB_LAUNCH(k_pitem_off, cdiv(H + 1, T), T, 0, s, H, nitem, ik, itoff);
+  scan_excl(icount, itoff, H, itoff + H, c.tmp, s);
+  int32_t nitem = 0;
+  GLMB_HIP(hipMemcpyAsync(&nitem, itoff + H, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipStreamSynchronize(s));
+  float* itd = need<float>(c.it_delta, (int64_t)nitem + 1);
+  int32_t* itg = need<int32_t>(c.it_group, (int64_t)nitem + 1);
+  GLMB_LAUNCH(k_pitems, H, 256, 0, s, H, nbs, nlt, SW, c.rows.as<int32_t>(), V, dt_, dbs, dbg, t0,
+              (const int32_t*)itoff, icount, itd, itg);
   // ---- exact selection
   trace(c, "predict.select", nitem);
   SelectIn si{H, V, itoff, itd, itg, p.h_max, t0, &c.sel_multi[0], c.coop_ok};
@@ -401,7 +404,7 @@ void stage_predict(Ctx& c, int k) {
   uint64_t* hk = need<uint64_t>(c.keys, n + 1);
   uint32_t* hv = need<uint32_t>(c.vals32, n + 1);
   GLMB_LAUNCH(k_hash_keys, cdiv(n, T), T, 0, s, n, hash, hk, hv);
-  sort_pairs(hk, hv, n, 0, 64, c.tk, c.tv, c.tmp, s);
+  sort_pairs(hk, hv, n, 0, 32, c.tk, c.tv, c.tmp, s);
   int32_t* leader = need<int32_t>(c.first, 4 * (int64_t)n + 4);
   int32_t* islead = leader + n + 1;
   int32_t* mrank = islead + n + 1;
@@ -416,8 +419,11 @@ void stage_predict(Ctx& c, int k) {
   GLMB_HIP(hipStreamSynchronize(s));
   uint64_t* lk = need<uint64_t>(c.rec_keys, nh + 1);
   uint32_t* lv = need<uint32_t>(c.rec_vals, nh + 1);
-  GLMB_LAUNCH(k_lead_keys, cdiv(n, T), T, 0, s, n, islead, lpre, mval, mrank, lk, lv);
-  sort_pairs(lk, lv, nh, 0, 64, c.tk, c.tv, c.tmp, s);
+  int rb = 0;  // ranks are positions among the search's candidates, below its node count
+  while (((int64_t)1 << rb) < (int64_t)sel.nodes + 1) ++rb;
+  rb = std::min(32, (rb + 7) / 8 * 8);
+  GLMB_LAUNCH(k_lead_keys, cdiv(n, T), T, 0, s, n, rb, islead, lpre, mval, mrank, lk, lv);
+  sort_pairs(lk, lv, nh, 0, 32 + rb, c.tk, c.tv, c.tmp, s);
   // ---- normalise, garbage-collect labels and instances, final rows
   trace(c, "predict.gc", nh);
   float* nlw = need<float>(c.logw2, nh + 1);

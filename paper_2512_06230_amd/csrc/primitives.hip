@@ -324,6 +324,40 @@ static void kth_bound_impl(const float* v, const int32_t* mult, int n, int K, fl
   GLMB_LAUNCH(k_bound_pick, 1, 1024, 0, s, hist, 1, prefix, need_k, out);
 }
 
+// the same bound over the values B[h] - dev1[h * M + i] of every cell and B[h] of every row
+__global__ __launch_bounds__(256) void k_bound_hist_cells(int H, int M, const float* B, const float* dev1, int pass,
+                                                          const uint32_t* prefix, int32_t* hist) {
+  __shared__ int32_t h[kBins];
+  for (int j = threadIdx.x; j < kBins; j += blockDim.x) h[j] = 0;
+  __syncthreads();
+  const uint32_t pre = pass ? *prefix : 0u;
+  const int64_t HM = (int64_t)H * M, n = HM + H;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
+    const float v = x < HM ? B[x / M] - dev1[x] : B[x - HM];
+    const uint32_t o = f2o(v);
+    if (pass == 0) atomicAdd(&h[o >> 20], 1);
+    else if ((o >> 20) == pre) atomicAdd(&h[(o >> 8) & (kBins - 1)], 1);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < kBins; j += blockDim.x)
+    if (h[j]) atomicAdd(&hist[j], h[j]);
+}
+
+void kth_bound_cells(const float* B, const float* dev1, int H, int M, int K, float* out, DevBuf& tmp,
+                     hipStream_t s) {
+  tmp.reserve((kBins + 8) * sizeof(int32_t));
+  int32_t* hist = tmp.as<int32_t>();
+  uint32_t* prefix = (uint32_t*)(hist + kBins);
+  int32_t* need_k = hist + kBins + 1;
+  const int64_t n = (int64_t)H * (M + 1);
+  GLMB_LAUNCH(k_bound_init, 1, 256, 0, s, hist, need_k, (int32_t)K);
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 256 * 8 - 1) / (256 * 8), 1024));
+  GLMB_LAUNCH(k_bound_hist_cells, grid, 256, 0, s, H, M, B, dev1, 0, prefix, hist);
+  GLMB_LAUNCH(k_bound_pick, 1, 1024, 0, s, hist, 0, prefix, need_k, out);
+  GLMB_LAUNCH(k_bound_hist_cells, grid, 256, 0, s, H, M, B, dev1, 1, prefix, hist);
+  GLMB_LAUNCH(k_bound_pick, 1, 1024, 0, s, hist, 1, prefix, need_k, out);
+}
+
 void kth_bound(const float* v, int n, int K, float* out, DevBuf& tmp, hipStream_t s) {
   kth_bound_impl(v, nullptr, n, K, out, tmp, s);
 }

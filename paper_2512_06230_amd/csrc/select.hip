@@ -158,15 +158,6 @@ __global__ void k_remap_pos(const int32_t* pre, const int32_t* total, int n, int
   for (int j = 0; j < 3; ++j) out[j] = xs[j] >= n ? *total : pre[xs[j]];
 }
 
-__global__ void k_cand_write(int n, const float* t, const int32_t* pre, const float* nd_value, const int32_t* nd_h,
-                             uint64_t* keys, uint32_t* vals) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || !(nd_value[i] >= *t)) return;
-  const int d = pre[i];
-  keys[d] = (uint64_t)(uint32_t)nd_h[i];
-  vals[d] = (uint32_t)i;
-}
-
 __global__ void k_final_keys(int nc, const uint32_t* byh_vals, const float* nd_value, uint64_t* keys, uint32_t* vals) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nc) return;
@@ -262,7 +253,7 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
                                                       const float* it_delta, const int32_t* it_group, int K,
                                                       const float* t0, int cap, int32_t* nd_p, int32_t* nd_i,
                                                       int32_t* nd_h, float* nd_v, uint64_t* nd_b, float* t_out,
-                                                      int32_t* out) {
+                                                      int32_t* out, int32_t* cand) {
   __shared__ int64_t sh[40];
   __shared__ int32_t hist[4096];
   __shared__ int64_t sel[4];
@@ -402,12 +393,36 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
       last_raise = used;
     }
   }
+  // candidates: every node >= t, in enumeration order
+  int nc = 0;
+  if (status == 0)
+    for (int c0 = 0; c0 < used; c0 += kSB) {
+      const int n = c0 + (int)threadIdx.x;
+      const int f = n < used && nd_v[n] >= t ? 1 : 0;
+      int64_t tot;
+      const int64_t off = sb_excl_scan(f, sh, &tot);
+      if (f) cand[nc + off] = n;
+      nc += (int)tot;
+    }
   if (threadIdx.x == 0) {
     out[0] = used;
     out[1] = levels;
     out[2] = status;
+    out[3] = nc;
     *t_out = t;
   }
+}
+
+// candidate list of the whole-GPU searches: nodes >= t in enumeration order
+__global__ void k_cand_list(int n, const float* t, const int32_t* pre, const float* nd_value, int32_t* cand) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && nd_value[i] >= *t) cand[pre[i]] = i;
+}
+__global__ void k_cand_keys(int nc, const int32_t* cand, const int32_t* nd_h, uint64_t* keys, uint32_t* vals) {
+  const int d = blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= nc) return;
+  keys[d] = (uint64_t)(uint32_t)nd_h[cand[d]];
+  vals[d] = (uint32_t)cand[d];
 }
 
 // ---------------------------------------------------------------- cooperative search
@@ -1098,16 +1113,18 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
   // Small searches run in one workgroup (no host round trip per level).  A search that
   // outgrows kBlockNodes continues on the whole GPU (multi-kernel levels below); the call
   // site remembers that and starts there next time, until a search is small again.
-  int used = 0, levels = 0;
+  int used = 0, levels = 0, nc_fast = 0;
   bool fast = false;
   if (!(in.prefer_multi && *in.prefer_multi)) {
     GLMB_LAUNCH(k_select_block, 1, kSB, 0, s, in.P, in.base, in.it_off, in.it_delta, in.it_group, in.K, in.t0,
-                std::min(cap, kBlockNodes), A.p, A.i, A.h, A.v, A.b, t, scal + 4);
-    GLMB_HIP(hipMemcpyAsync(hs, scal + 4, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+                std::min(cap, kBlockNodes), A.p, A.i, A.h, A.v, A.b, t, scal + 4,
+                need<int32_t>(b.cand, std::min(cap, kBlockNodes) + 1));
+    GLMB_HIP(hipMemcpyAsync(hs, scal + 4, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     GLMB_HIP(hipStreamSynchronize(s));
     used = hs[0];
     levels = hs[1];
     fast = hs[2] == 0;
+    nc_fast = hs[3];
     tr("block", used, hs[2]);
     if (in.prefer_multi) *in.prefer_multi = !fast;
   }
@@ -1284,25 +1301,30 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
   tr("final", used, levels);
   tr("created", created, fast ? 1 : 0);
   // candidates: every node >= t, in enumeration order
-  int32_t* fl = need<int32_t>(b.flags, used + 1);
-  int32_t* pre = need<int32_t>(b.pre, used + 1);
-  GLMB_LAUNCH(k_keep_flags, cdiv(used, T), T, 0, s, A.v, used, t, fl);
-  scan_excl(fl, pre, used, scal, b.tmp, s);
-  read(1);
-  const int nc = hs[0];
-  uint64_t* keys = need<uint64_t>(b.keys, nc + 1);
-  uint32_t* vals = need<uint32_t>(b.vals, nc + 1);
-  GLMB_LAUNCH(k_cand_write, cdiv(used, T), T, 0, s, used, t, pre, A.v, A.h, keys, vals);
+  int nc = nc_fast;
+  if (!fast) {
+    int32_t* fl = need<int32_t>(b.flags, used + 1);
+    int32_t* pre = need<int32_t>(b.pre, used + 1);
+    GLMB_LAUNCH(k_keep_flags, cdiv(used, T), T, 0, s, A.v, used, t, fl);
+    scan_excl(fl, pre, used, scal, b.tmp, s);
+    read(1);
+    nc = hs[0];
+    GLMB_LAUNCH(k_cand_list, cdiv(used, T), T, 0, s, used, t, pre, A.v, need<int32_t>(b.cand, nc + 1));
+  }
+  const int32_t* cand = b.cand.as<int32_t>();
   int hbits = 0;
   while ((1 << hbits) < in.P) ++hbits;
-  sort_pairs(keys, vals, nc, 0, ((hbits + 7) / 8) * 8, b.tk, b.tv, b.tmp, s);  // canonical key order
-  GLMB_LAUNCH(k_final_keys, cdiv(nc, T), T, 0, s, nc, vals, A.v, keys, vals);
-  // stable sort on the value bits only: the input is in canonical key order already
-  sort_pairs(keys, vals, nc, 32, 64, b.tk, b.tv, b.tmp, s);
   const int n = std::min(nc, in.K);
   out.node = need<int32_t>(b.sel_node, n + 1);
   out.value = need<float>(b.sel_val, n + 1);
   out.keyrank = need<int32_t>(b.sel_rank, n + 1);
+  uint64_t* keys = need<uint64_t>(b.keys, nc + 1);
+  uint32_t* vals = need<uint32_t>(b.vals, nc + 1);
+  GLMB_LAUNCH(k_cand_keys, cdiv(nc, T), T, 0, s, nc, cand, A.h, keys, vals);
+  sort_pairs(keys, vals, nc, 0, ((hbits + 7) / 8) * 8, b.tk, b.tv, b.tmp, s);  // canonical key order
+  GLMB_LAUNCH(k_final_keys, cdiv(nc, T), T, 0, s, nc, vals, A.v, keys, vals);
+  // stable sort on the value bits only: the input is in canonical key order already
+  sort_pairs(keys, vals, nc, 32, 64, b.tk, b.tv, b.tmp, s);
   GLMB_LAUNCH(k_take, cdiv(n, T), T, 0, s, n, keys, vals, A.v, out.node, out.value, out.keyrank);
   out.n = n;
   out.nd_parent = A.p;

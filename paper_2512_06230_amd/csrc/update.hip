@@ -592,32 +592,36 @@ __global__ __launch_bounds__(1024) void k_norm(int H, int M, const float* bprime
   if (threadIdx.x == 0) *lz = L;
 }
 
-__global__ void k_t0_vals(int H, int M, const float* bprime, const float* dev1, float* vals) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)H * (M + 1)) return;
-  const int h = (int)(t / (M + 1)), i = (int)(t % (M + 1));
-  vals[t] = i == M ? bprime[h] : bprime[h] - dev1[(size_t)h * M + i];
+// One wave per parent: its cells (h, i) with B'_h - dev1 >= t0, in ascending i.  dev1 >= 0, so
+// a parent below the bound has none and its row is not read.  Counting pass (roff null):
+// rcount[h]; writing pass: cell indices h * M + i at roff[h].
+__global__ __launch_bounds__(256) void k_row_cells(int H, int M, const float* bprime, const float* dev1,
+                                                   const float* t0, const int32_t* roff, int32_t* rcount,
+                                                   int32_t* cells) {
+  const int h = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kWave);
+  if (h >= H) return;
+  const int lane = lane_id();
+  const float B = bprime[h], t = *t0;
+  int cnt = 0;
+  if (B >= t) {
+    const int q0 = roff ? roff[h] : 0;
+    for (int i0 = 0; i0 < M; i0 += kWave) {
+      const int i = i0 + lane;
+      const bool f = i < M && B - dev1[(size_t)h * M + i] >= t;
+      const uint64_t bal = __ballot(f);
+      if (roff && f) cells[q0 + cnt + __popcll(bal & lanemask_lt())] = h * M + i;
+      cnt += __popcll(bal);
+    }
+  }
+  if (!roff && lane == 0) rcount[h] = cnt;
 }
 
-__global__ void k_cell_flags(int H, int M, const float* bprime, const float* dev1, const float* t0, int32_t* flags) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= (int64_t)H * M) return;
-  flags[c] = bprime[c / M] - dev1[c] >= *t0 ? 1 : 0;
-}
-__global__ void k_cell_write(int64_t n, const int32_t* flags, const int32_t* pre, int32_t* cells) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c < n && flags[c]) cells[pre[c]] = (int32_t)c;
-}
-
-// Deviation items of cell (h, i): every option other than the cell's best (largest phi,
-// ties to the smaller key; clutter has key -1 and comes first) whose deviation
-// d = phi_best - phi keeps B'_h - d above the cut bound.  Candidates arrive in ascending key,
-// so items are emitted in ascending option key; the stable sort by (h, d) that follows puts
-// equal deviations in key order.  Two passes over the options, no per-cell storage.
-// One wave per cell (h, i): the lanes take detection i's gated candidates 64 at a time.  The
-// best option of the cell is the first candidate (in list order) of the largest score if that
-// beats the clutter score, else clutter; every other option within the cut is an item with
-// delta = best - score, in the order clutter first, then the candidates in list order.
+// Deviation items of cell (h, i): every option other than the cell's best whose deviation
+// d = phi_best - phi keeps B'_h - d above the cut bound.  One wave per cell: the lanes take
+// detection i's gated candidates 64 at a time.  The best option is the first candidate (in
+// list order, i.e. ascending key) of the largest score if that beats the clutter score, else
+// clutter (key -1); the items come in the order clutter first, then the candidates in list
+// order, and the sort by (h, d) that follows keeps that order among equal deviations.
 // Counting pass (ioff null): icount[c] = number of items; writing pass: items at ioff[c].
 __global__ __launch_bounds__(256) void k_items(int ncell, const int32_t* cells, int M, int stride,
                                                const int32_t* rows, const int32_t* coff, const int32_t* cand,
@@ -1463,7 +1467,6 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   // ---- U2: per (hypothesis, detection) normalisers
   trace(c, "update.U2");
   assoc_norm(c, M);
-  const int64_t HM = (int64_t)H * M;
   int16_t* best16 = c.best16.as<int16_t>();
   float* dev1 = c.dev1.as<float>();
   float* lserel = c.lserel.as<float>();
@@ -1473,16 +1476,16 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   // ---- U3: lower bound of the cut, deviation items, exact selection
   trace(c, "update.U3");
   const int K = p.h_max;
-  float* vals = need<float>(c.vals, (int64_t)H * (M + 1));
-  GLMB_LAUNCH(k_t0_vals, cdiv((int64_t)H * (M + 1), T), T, 0, s, H, M, bprime, dev1, vals);
-  kth_bound(vals, H * (M + 1), K, t0, c.tmp, s);
-  int32_t* flags = need<int32_t>(c.flags, HM + 1);
-  int32_t* pre = need<int32_t>(c.pre, HM + 1);
-  GLMB_LAUNCH(k_cell_flags, cdiv(HM, T), T, 0, s, H, M, bprime, dev1, t0, flags);
-  scan_excl(flags, pre, (int)HM, tot, c.tmp, s);
+  kth_bound_cells(bprime, dev1, H, M, K, t0, c.tmp, s);
+  int32_t* rcount = need<int32_t>(c.flags, H + 1);
+  int32_t* roff = need<int32_t>(c.pre, H + 1);
+  const int row_blocks = cdiv((int64_t)H * kWave, 256);
+  GLMB_LAUNCH(k_row_cells, row_blocks, 256, 0, s, H, M, bprime, dev1, t0, (const int32_t*)nullptr, rcount,
+              (int32_t*)nullptr);
+  scan_excl(rcount, roff, H, tot, c.tmp, s);
   const int ncell = read1(s, tot);
   int32_t* cells = need<int32_t>(c.cells, ncell);
-  GLMB_LAUNCH(k_cell_write, cdiv(HM, T), T, 0, s, HM, flags, pre, cells);
+  GLMB_LAUNCH(k_row_cells, row_blocks, 256, 0, s, H, M, bprime, dev1, t0, (const int32_t*)roff, rcount, cells);
   int32_t* icount = need<int32_t>(c.ccount, ncell + 1);
   int32_t* ioff = need<int32_t>(c.coff2, ncell + 1);
   const int item_blocks = cdiv((int64_t)ncell * kWave, 256);
