@@ -125,7 +125,6 @@ struct SelectIn {
   const float* t0;        // device scalar: a lower bound on the K-th best child value
   bool* prefer_multi;     // per call site: the previous search outgrew one workgroup (may be null)
   bool allow_coop = true; // the whole-GPU search may be one cooperative launch
-  bool refine = false;    // tighten t0 with the counting bound before searching
 };
 struct Selected {
   int n;                  // number of selected children (<= K)
@@ -148,5 +147,14 @@ struct SelectBufs {
 };
 glmb_status select_topk(const SelectIn& in, int cap_nodes, SelectBufs& b, Selected& out, hipStream_t s,
                         std::string& err, bool trace = false);
+// Counting lower bound on the K-th best child (select.hip): the first pass counts each parent's
+// first deviations dev1[h * M + i] and returns a device scalar holding the bound (t0 when no
+// count reaches K); dp_bound_items raises it with the items of the children above it;
+// dp_bound_refined reads whether it rose above t0 (synchronises).
+const float* dp_bound_rows(const float* base, int P, const float* dev1, int M, int K, const float* t0,
+                           SelectBufs& b, hipStream_t s);
+void dp_bound_items(const SelectIn& in, SelectBufs& b, hipStream_t s);
+bool dp_bound_refined(SelectBufs& b, hipStream_t s);
+void dp_bound_trace(SelectBufs& b, hipStream_t s);
 
 }  // namespace glmb

@@ -331,12 +331,30 @@ __global__ __launch_bounds__(256) void k_bound_hist_cells(int H, int M, const fl
   for (int j = threadIdx.x; j < kBins; j += blockDim.x) h[j] = 0;
   __syncthreads();
   const uint32_t pre = pass ? *prefix : 0u;
-  const int64_t HM = (int64_t)H * M, n = HM + H;
-  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x) {
-    const float v = x < HM ? B[x / M] - dev1[x] : B[x - HM];
+  auto bin_of = [&](float v) -> int {
     const uint32_t o = f2o(v);
-    if (pass == 0) atomicAdd(&h[o >> 20], 1);
-    else if ((o >> 20) == pre) atomicAdd(&h[(o >> 8) & (kBins - 1)], 1);
+    if (pass == 0) return (int)(o >> 20);
+    return (o >> 20) == pre ? (int)((o >> 8) & (kBins - 1)) : -1;
+  };
+  // rows in turn, the threads along a row (no division per element); the values crowd into
+  // few bins, so a wave whose lanes all share one bin adds 64 with one atomic
+  for (int r = blockIdx.x; r < H; r += gridDim.x) {
+    const float b = B[r];
+    const float* d = dev1 + (size_t)r * M;
+    for (int i0 = 0; i0 < M; i0 += blockDim.x) {
+      const int i = i0 + threadIdx.x;
+      const int bin = i < M ? bin_of(b - d[i]) : -1;
+      const int b0 = __shfl(bin, 0, kWave);
+      if (b0 >= 0 && __ballot(bin == b0) == ~0ull) {
+        if (lane_id() == 0) atomicAdd(&h[b0], kWave);
+      } else if (bin >= 0) {
+        atomicAdd(&h[bin], 1);
+      }
+    }
+    if (threadIdx.x == 0) {
+      const int br = bin_of(b);
+      if (br >= 0) atomicAdd(&h[br], 1);
+    }
   }
   __syncthreads();
   for (int j = threadIdx.x; j < kBins; j += blockDim.x)
@@ -351,7 +369,7 @@ void kth_bound_cells(const float* B, const float* dev1, int H, int M, int K, flo
   int32_t* need_k = hist + kBins + 1;
   const int64_t n = (int64_t)H * (M + 1);
   GLMB_LAUNCH(k_bound_init, 1, 256, 0, s, hist, need_k, (int32_t)K);
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 256 * 8 - 1) / (256 * 8), 1024));
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 256 * 8 - 1) / (256 * 8), std::min(H, 1024)));
   GLMB_LAUNCH(k_bound_hist_cells, grid, 256, 0, s, H, M, B, dev1, 0, prefix, hist);
   GLMB_LAUNCH(k_bound_pick, 1, 1024, 0, s, hist, 0, prefix, need_k, out);
   GLMB_LAUNCH(k_bound_hist_cells, grid, 256, 0, s, H, M, B, dev1, 1, prefix, hist);

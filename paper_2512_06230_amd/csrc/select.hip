@@ -181,6 +181,7 @@ __global__ void k_take(int n, const uint64_t* keys, const uint32_t* vals, const 
 // search below (with compaction) takes over.
 constexpr int kSB = 1024;
 constexpr int kBlockNodes = 1 << 18;  // node budget of the one-workgroup search
+constexpr int kSearchLdsItems = 24576;  // item deltas kept in LDS (the 160 KB of a CDNA4 workgroup)
 
 __device__ __forceinline__ int64_t sb_excl_scan(int64_t v, int64_t* sh, int64_t* total) {
   const int lane = lane_id(), w = threadIdx.x / kWave;
@@ -263,6 +264,14 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
   __shared__ float cv[kSB];       // value, parent and group bits of the chunk's nodes
   __shared__ int32_t chh[kSB];
   __shared__ uint64_t cbb[kSB];
+  __shared__ float ldel[kSearchLdsItems];  // the item deltas, when they fit
+  const int nitem = it_off[P];
+  const float* idel = it_delta;
+  if (nitem <= kSearchLdsItems) {
+    for (int q = threadIdx.x; q < nitem; q += kSB) ldel[q] = it_delta[q];
+    __syncthreads();
+    idel = ldel;
+  }
   const float nan = __uint_as_float(0xffc00000u);
   float t = *t0;
   int status = 0;  // 0 done, 1 node store full, 2 too deep
@@ -300,7 +309,7 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
       const int n = c0 + (int)threadIdx.x;
       int lo = 0, hi = 0;
       if ((int)threadIdx.x < nchunk) {
-        ext_range(n, nd_i, nd_h, nd_v, it_off, it_delta, t, &lo, &hi);
+        ext_range(n, nd_i, nd_h, nd_v, it_off, idel, t, &lo, &hi);
         cv[threadIdx.x] = nd_v[n];
         chh[threadIdx.x] = nd_h[n];
         cbb[threadIdx.x] = nd_b[n];
@@ -357,7 +366,7 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
         }
         const int nn = c0 + a;
         const int q = clo[a] + (int)(e - cpre[a]);
-        float v = cv[a] - it_delta[q];
+        float v = cv[a] - idel[q];
         const int g = it_group[q];
         const uint64_t pb = cbb[a], gb = group_bit(g);
         if (pb & gb)
@@ -387,7 +396,9 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
     if (status != 0) break;
     first = end;
     end = used;
-    if (first < end && used >= K && used > last_raise) {
+    // at a level's end once the store has grown by a quarter since the last raise (each raise
+    // reads every node twice)
+    if (first < end && used >= K && used >= last_raise + last_raise / 4) {
       const float b = sb_bound(nd_v, used, K, hist, sh, sel);
       if (b > t) t = b;
       last_raise = used;
@@ -784,10 +795,12 @@ __global__ __launch_bounds__(kCB) void k_select_coop(CoopArgs a) {
 // or leaving items out only lowers a count, so if at least K counted children of all parents
 // have rounded value >= v_max - j*w (v_max: the best parent), the K-th best child is at least
 // v_max - j*w, less a margin for the float rounding of the sequential subtractions.  A first
-// pass with coarse bins over the whole range [t0, v_max] and each parent's first items finds a
-// range E; a second with fine bins over [v_max - E, v_max] sharpens the bound.
+// pass with coarse bins over the whole range [t0, v_max] counts each parent's smallest first
+// deviations (one item per detection, read from the dense rows of the association step) and
+// finds a range E, so that the items can be generated for that range only; a second pass
+// with fine bins over [v_max - E, v_max] counts the items and sharpens the bound.
 constexpr int kDpBins1 = 1024, kDpItems1 = 64;    // first pass
-constexpr int kDpBins2 = 4096, kDpItems2 = 2048;  // second pass
+constexpr int kDpBins2 = 2048, kDpItems2 = 2048;  // second pass
 constexpr int kDpThreads = 1024;      // init and pick
 constexpr int kDpCountThreads = 1024;  // counting: one or a few bins per thread and step
 
@@ -832,9 +845,87 @@ __global__ __launch_bounds__(kDpThreads) void k_dp_init(int P, const float* base
   }
 }
 
-// Every workgroup takes listed parents in turn: the counts of the parent's valid pick sets by
-// rounded cost, added into C at the parent's offset (its own rounded distance below vmax).
-__global__ __launch_bounds__(kDpCountThreads) void k_dp_count(int pass, const float* base, const int32_t* it_off,
+// First pass.  Every workgroup takes listed parents in turn: the parent's smallest first
+// deviations (dev1 of its detections, one item per detection) sorted in LDS, counted by
+// rounded cost with the 0/1 knapsack recursion (two items per step), added into C at the
+// parent's offset (its own rounded distance below vmax).
+constexpr int kDpRowMax = 4096;  // detections of a row looked at (a subset only loosens the bound)
+__global__ __launch_bounds__(kDpThreads) void k_dp_rows(const float* base, const float* dev1, int M, int K,
+                                                        const DpState* st, const int32_t* act,
+                                                        unsigned long long* C) {
+  __shared__ float sv[kDpRowMax];
+  __shared__ int32_t fa[kDpBins1], fb[kDpBins1];
+  __shared__ int32_t cst[kDpItems1];
+  __shared__ int32_t ne_s;
+  if (!st->ok) return;
+  const int NB = kDpBins1;
+  const double E = st->E, w = E / NB;
+  const int nact = st->nact, Mr = min(M, kDpRowMax);
+  int P2 = 1;
+  while (P2 < Mr) P2 <<= 1;
+  for (int k = blockIdx.x; k < nact; k += gridDim.x) {
+    const int h = act[k];
+    const double gap = (double)st->vmax - (double)base[h];
+    const double dd = ceil(gap / w);
+    if (!(dd < NB)) continue;
+    const int dh = (int)dd;
+    __syncthreads();  // the previous parent's arrays are no longer read
+    for (int q = threadIdx.x; q < P2; q += kDpThreads) sv[q] = q < Mr ? dev1[(size_t)h * M + q] : INFINITY;
+    for (int b = threadIdx.x; b < NB; b += kDpThreads) fa[b] = b == 0 ? 1 : 0;
+    __syncthreads();
+    for (int kk = 2; kk <= P2; kk <<= 1)
+      for (int j = kk >> 1; j > 0; j >>= 1) {
+        for (int q = threadIdx.x; q < P2; q += kDpThreads) {
+          const int r = q ^ j;
+          if (r > q) {
+            const float x = sv[q], y = sv[r];
+            if ((x > y) == ((q & kk) == 0)) {
+              sv[q] = y;
+              sv[r] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    // the first deviations within the range (a prefix of the sorted ones), at most kDpItems1
+    if (threadIdx.x < kWave) {
+      const int q = threadIdx.x;
+      const bool in = q < min(Mr, kDpItems1) && (double)sv[q] <= E - gap;
+      const uint64_t bal = __ballot(in);
+      if (in) {
+        const double c = ceil((double)sv[q] / w);
+        cst[q] = c < NB ? (int)c : NB;
+      }
+      if (q == 0) ne_s = __popcll(bal);
+    }
+    __syncthreads();
+    const int ne = ne_s;
+    int32_t* f = fa;
+    int32_t* g = fb;
+    for (int q = 0; q < ne; q += 2) {
+      const int c1 = cst[q], c2 = q + 1 < ne ? cst[q + 1] : NB;
+      for (int b = threadIdx.x; b < NB; b += kDpThreads) {
+        int v = f[b];
+        if (c1 <= b) v = min(K, v + f[b - c1]);
+        if (c2 <= b) {
+          v = min(K, v + f[b - c2]);
+          if (c1 + c2 <= b) v = min(K, v + f[b - c1 - c2]);
+        }
+        g[b] = v;
+      }
+      __syncthreads();
+      int32_t* x = f;
+      f = g;
+      g = x;
+    }
+    for (int b = threadIdx.x; b < NB - dh; b += kDpThreads)
+      if (f[b]) atomicAdd(&C[b + dh], (unsigned long long)f[b]);
+  }
+}
+
+// Second pass.  Every workgroup takes listed parents in turn: the counts of the parent's valid
+// pick sets of items by rounded cost, added into C at the parent's offset.
+__global__ __launch_bounds__(kDpCountThreads) void k_dp_count(const float* base, const int32_t* it_off,
                                                          const float* it_delta, const int32_t* it_group, int K,
                                                          const DpState* st, const int32_t* act,
                                                          unsigned long long* C) {
@@ -844,7 +935,7 @@ __global__ __launch_bounds__(kDpCountThreads) void k_dp_count(int pass, const fl
   __shared__ int32_t wcnt[kDpCountThreads / kWave];
   __shared__ int32_t ne_s, ngs;
   if (!st->ok) return;
-  const int NB = pass == 1 ? kDpBins1 : kDpBins2, ncap = pass == 1 ? kDpItems1 : kDpItems2;
+  const int NB = kDpBins2, ncap = kDpItems2;
   const double E = st->E, w = E / NB;
   const int nact = st->nact;
   for (int k = blockIdx.x; k < nact; k += gridDim.x) {
@@ -1039,6 +1130,49 @@ static int coop_grid(size_t lds) {
 }
 static void coop_disable() { g_coop_grid = 0; }
 
+const float* dp_bound_rows(const float* base, int P, const float* dev1, int M, int K, const float* t0,
+                           SelectBufs& b, hipStream_t s) {
+  DpState* st = need<DpState>(b.dp, 1);
+  int32_t* act = need<int32_t>(b.dpa, std::max(P, 1));
+  unsigned long long* C = need<unsigned long long>(b.dpc, kDpBins2);
+  if (!b.dpc_ready) {
+    GLMB_HIP(hipMemsetAsync(C, 0, kDpBins2 * sizeof(unsigned long long), s));  // k_dp_pick leaves it zeroed
+    b.dpc_ready = true;
+  }
+  GLMB_LAUNCH(k_dp_init, 1, kDpThreads, 0, s, P, base, t0, st, act);
+  if (K > 0 && P > 0 && M > 0) {
+    GLMB_LAUNCH(k_dp_rows, std::min(P, kDpGrid), kDpThreads, 0, s, base, dev1, M, K, (const DpState*)st,
+                (const int32_t*)act, C);
+    GLMB_LAUNCH(k_dp_pick, 1, kDpThreads, 0, s, 1, K, st, C);
+  }
+  return &st->tref;
+}
+
+void dp_bound_items(const SelectIn& in, SelectBufs& b, hipStream_t s) {
+  if (in.K <= 0 || in.P <= 0) return;
+  DpState* st = b.dp.as<DpState>();
+  unsigned long long* C = b.dpc.as<unsigned long long>();
+  GLMB_LAUNCH(k_dp_count, std::min(in.P, kDpGrid), kDpCountThreads, 0, s, in.base, in.it_off, in.it_delta,
+              in.it_group, in.K, (const DpState*)st, (const int32_t*)b.dpa.as<int32_t>(), C);
+  GLMB_LAUNCH(k_dp_pick, 1, kDpThreads, 0, s, 2, in.K, st, C);
+}
+
+bool dp_bound_refined(SelectBufs& b, hipStream_t s) {
+  int32_t refined = 0;
+  GLMB_HIP(hipMemcpyAsync(&refined, &b.dp.as<DpState>()->refined, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipStreamSynchronize(s));
+  return refined != 0;
+}
+
+void dp_bound_trace(SelectBufs& b, hipStream_t s) {
+  DpState h{};
+  GLMB_HIP(hipMemcpyAsync(&h, b.dp.p, sizeof(DpState), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipStreamSynchronize(s));
+  std::fprintf(stderr, "[glmb] select.refine t0 %.7g tref %.7g vmax %.7g refined %d\n", h.t0, h.tref, h.vmax,
+               h.refined);
+  std::fflush(stderr);
+}
+
 glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& out, hipStream_t s, std::string& err,
                         bool trace) {
   auto tr = [&](const char* what, long long a, long long c) {
@@ -1047,43 +1181,6 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
       std::fflush(stderr);
     }
   };
-  if (in.refine && in.K > 0 && in.P > 0) {
-    // counting bound (two passes, no host round trip), then the search from it
-    DpState* st = need<DpState>(b.dp, 1);
-    int32_t* act = need<int32_t>(b.dpa, in.P);
-    unsigned long long* C = need<unsigned long long>(b.dpc, kDpBins2);
-    if (!b.dpc_ready) {
-      GLMB_HIP(hipMemsetAsync(C, 0, kDpBins2 * sizeof(unsigned long long), s));  // k_dp_pick leaves it zeroed
-      b.dpc_ready = true;
-    }
-    GLMB_LAUNCH(k_dp_init, 1, kDpThreads, 0, s, in.P, in.base, in.t0, st, act);
-    for (int pass = 1; pass <= 2; ++pass) {
-      GLMB_LAUNCH(k_dp_count, std::min(in.P, kDpGrid), kDpCountThreads, 0, s, pass, in.base, in.it_off, in.it_delta,
-                  in.it_group, in.K, st, (const int32_t*)act, C);
-      GLMB_LAUNCH(k_dp_pick, 1, kDpThreads, 0, s, pass, in.K, st, C);
-    }
-    if (trace) {
-      DpState h{};
-      GLMB_HIP(hipMemcpyAsync(&h, st, sizeof(DpState), hipMemcpyDeviceToHost, s));
-      GLMB_HIP(hipStreamSynchronize(s));
-      std::fprintf(stderr, "[glmb] select.refine t0 %.7g tref %.7g vmax %.7g refined %d\n", h.t0, h.tref, h.vmax,
-                   h.refined);
-    }
-    SelectIn r = in;
-    r.refine = false;
-    r.t0 = &st->tref;
-    const glmb_status e = select_topk(r, cap, b, out, s, err, trace);
-    if (e != GLMB_OK || out.n >= in.K) return e;
-    // Fewer than K children above the refined bound would contradict its count: search again
-    // from the caller's bound.
-    int32_t refined = 0;
-    GLMB_HIP(hipMemcpyAsync(&refined, &st->refined, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(hipStreamSynchronize(s));
-    if (!refined) return e;
-    tr("refine_retry", out.n, in.K);
-    r.t0 = in.t0;
-    return select_topk(r, cap, b, out, s, err, trace);
-  }
   const int T = 256;
   // node store: two copies for compaction
   auto alloc = [&](int which) {

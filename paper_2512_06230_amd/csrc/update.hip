@@ -1477,68 +1477,97 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   trace(c, "update.U3");
   const int K = p.h_max;
   kth_bound_cells(bprime, dev1, H, M, K, t0, c.tmp, s);
-  int32_t* rcount = need<int32_t>(c.flags, H + 1);
-  int32_t* roff = need<int32_t>(c.pre, H + 1);
-  const int row_blocks = cdiv((int64_t)H * kWave, 256);
-  GLMB_LAUNCH(k_row_cells, row_blocks, 256, 0, s, H, M, bprime, dev1, t0, (const int32_t*)nullptr, rcount,
-              (int32_t*)nullptr);
-  scan_excl(rcount, roff, H, tot, c.tmp, s);
-  const int ncell = read1(s, tot);
-  int32_t* cells = need<int32_t>(c.cells, ncell);
-  GLMB_LAUNCH(k_row_cells, row_blocks, 256, 0, s, H, M, bprime, dev1, t0, (const int32_t*)roff, rcount, cells);
-  int32_t* icount = need<int32_t>(c.ccount, ncell + 1);
-  int32_t* ioff = need<int32_t>(c.coff2, ncell + 1);
-  const int item_blocks = cdiv((int64_t)ncell * kWave, 256);
-  GLMB_LAUNCH(k_items, item_blocks, 256, 0, s, ncell, cells, M, SW, c.rows.as<int32_t>(), coff, cand, phi, lgk,
-              bprime, t0, (const int32_t*)nullptr, icount, (float*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
-              (uint64_t*)nullptr, (uint32_t*)nullptr);
-  scan_excl(icount, ioff, ncell, ioff + ncell, c.tmp, s);
-  int32_t* itoff = need<int32_t>(c.it_off, H + 1);
-  int32_t* maxlen = scal + 22;
-  int32_t* nlist = scal + 23;
-  int32_t* ilist = need<int32_t>(c.it_h, H);
-  GLMB_LAUNCH(k_item_ranges, cdiv(H + 1, T), T, 0, s, H, ncell, M, cells, ioff, itoff, maxlen, nlist, ilist);
-  int32_t hv[2];
-  GLMB_HIP(hipMemcpyAsync(hv, ioff + ncell, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipMemcpyAsync(hv + 1, maxlen, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipStreamSynchronize(s));
-  const int nitem = hv[0];
-  float* itd0 = need<float>(c.it_delta, 2 * (int64_t)nitem);
-  int32_t* itg0 = need<int32_t>(c.it_group, 2 * (int64_t)nitem);
-  int32_t* ito0 = need<int32_t>(c.it_opt, 2 * (int64_t)nitem);
-  uint64_t* ikeys = need<uint64_t>(c.keys, nitem);
-  uint32_t* ivals = need<uint32_t>(c.vals32, nitem);
-  const bool segsort = hv[1] <= GLMB_SEGSORT_MAX;
-  GLMB_LAUNCH(k_items, item_blocks, 256, 0, s, ncell, cells, M, SW, c.rows.as<int32_t>(), coff, cand, phi, lgk,
-              bprime, t0, (const int32_t*)ioff, icount, itd0, itg0, ito0, segsort ? nullptr : ikeys,
-              segsort ? nullptr : ivals);
-  float* itd = itd0 + nitem;
-  int32_t* itg = itg0 + nitem;
-  int32_t* ito = ito0 + nitem;
-  if (segsort) {
-    // per-parent lists sorted in LDS, one workgroup per parent
-    if (hv[1] > 1024)
-      GLMB_LAUNCH(k_item_segsort<1024>, std::min(H, 512), 1024, 0, s, nlist, ilist, itoff, itd0, itg0, ito0, itd,
-                  itg, ito);
-    else
-      GLMB_LAUNCH(k_item_segsort<256>, std::min(H, 1024), 256, 0, s, nlist, ilist, itoff, itd0, itg0, ito0, itd,
-                  itg, ito);
-  } else {
-    // a parent with more items than one workgroup sorts: stable radix sort by (parent, delta)
-    // of the items in generation order (detection, then option key)
-    int hbits = 0;
-    while ((1 << hbits) < H) ++hbits;
-    sort_pairs(ikeys, ivals, nitem, 0, 32 + ((hbits + 7) / 8) * 8, c.tk, c.tv, c.tmp, s);
-    GLMB_LAUNCH(k_item_perm, cdiv(nitem, T), T, 0, s, nitem, ivals, itd0, itg0, ito0, itd, itg, ito);
-  }
-
-  SelectIn si{H, bprime, itoff, itd, itg, K, t0, &c.sel_multi[1], c.coop_ok, true};
-  trace(c, "update.select", ncell, nitem);
+  // counting bound, first pass (from the cells' first deviations): the items are generated
+  // for the children above it only
+  const float* tcut = dp_bound_rows(bprime, H, dev1, M, K, t0, c.sb, s);
+  struct Items {
+    int ncell, nitem;
+    int32_t *itoff, *itg, *ito;
+    float* itd;
+  };
+  // cells (h, i) and their deviation items above the bound *tb, sorted per parent by delta
+  auto make_items = [&](const float* tb) {
+    Items r{};
+    int32_t* rcount = need<int32_t>(c.flags, H + 1);
+    int32_t* roff = need<int32_t>(c.pre, H + 1);
+    const int row_blocks = cdiv((int64_t)H * kWave, 256);
+    GLMB_LAUNCH(k_row_cells, row_blocks, 256, 0, s, H, M, bprime, dev1, tb, (const int32_t*)nullptr, rcount,
+                (int32_t*)nullptr);
+    scan_excl(rcount, roff, H, tot, c.tmp, s);
+    const int ncell = read1(s, tot);
+    int32_t* cells = need<int32_t>(c.cells, ncell);
+    GLMB_LAUNCH(k_row_cells, row_blocks, 256, 0, s, H, M, bprime, dev1, tb, (const int32_t*)roff, rcount, cells);
+    int32_t* icount = need<int32_t>(c.ccount, ncell + 1);
+    int32_t* ioff = need<int32_t>(c.coff2, ncell + 1);
+    const int item_blocks = cdiv((int64_t)ncell * kWave, 256);
+    GLMB_LAUNCH(k_items, item_blocks, 256, 0, s, ncell, cells, M, SW, c.rows.as<int32_t>(), coff, cand, phi, lgk,
+                bprime, tb, (const int32_t*)nullptr, icount, (float*)nullptr, (int32_t*)nullptr, (int32_t*)nullptr,
+                (uint64_t*)nullptr, (uint32_t*)nullptr);
+    scan_excl(icount, ioff, ncell, ioff + ncell, c.tmp, s);
+    int32_t* itoff = need<int32_t>(c.it_off, H + 1);
+    int32_t* maxlen = scal + 22;
+    int32_t* nlist = scal + 23;
+    int32_t* ilist = need<int32_t>(c.it_h, H);
+    GLMB_LAUNCH(k_fill_i32, 1, T, 0, s, maxlen, 2, 0);
+    GLMB_LAUNCH(k_item_ranges, cdiv(H + 1, T), T, 0, s, H, ncell, M, cells, ioff, itoff, maxlen, nlist, ilist);
+    int32_t hv[2];
+    GLMB_HIP(hipMemcpyAsync(hv, ioff + ncell, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GLMB_HIP(hipMemcpyAsync(hv + 1, maxlen, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GLMB_HIP(hipStreamSynchronize(s));
+    const int nitem = hv[0];
+    float* itd0 = need<float>(c.it_delta, 2 * (int64_t)nitem);
+    int32_t* itg0 = need<int32_t>(c.it_group, 2 * (int64_t)nitem);
+    int32_t* ito0 = need<int32_t>(c.it_opt, 2 * (int64_t)nitem);
+    uint64_t* ikeys = need<uint64_t>(c.keys, nitem);
+    uint32_t* ivals = need<uint32_t>(c.vals32, nitem);
+    const bool segsort = hv[1] <= GLMB_SEGSORT_MAX;
+    GLMB_LAUNCH(k_items, item_blocks, 256, 0, s, ncell, cells, M, SW, c.rows.as<int32_t>(), coff, cand, phi, lgk,
+                bprime, tb, (const int32_t*)ioff, icount, itd0, itg0, ito0, segsort ? nullptr : ikeys,
+                segsort ? nullptr : ivals);
+    r.ncell = ncell;
+    r.nitem = nitem;
+    r.itoff = itoff;
+    r.itd = itd0 + nitem;
+    r.itg = itg0 + nitem;
+    r.ito = ito0 + nitem;
+    if (segsort) {
+      // per-parent lists sorted in LDS, one workgroup per parent
+      if (hv[1] > 1024)
+        GLMB_LAUNCH(k_item_segsort<1024>, std::min(H, 512), 1024, 0, s, nlist, ilist, itoff, itd0, itg0, ito0, r.itd,
+                    r.itg, r.ito);
+      else
+        GLMB_LAUNCH(k_item_segsort<256>, std::min(H, 1024), 256, 0, s, nlist, ilist, itoff, itd0, itg0, ito0, r.itd,
+                    r.itg, r.ito);
+    } else {
+      // a parent with more items than one workgroup sorts: stable radix sort by (parent, delta)
+      // of the items in generation order (detection, then option key)
+      int hbits = 0;
+      while ((1 << hbits) < H) ++hbits;
+      sort_pairs(ikeys, ivals, nitem, 0, 32 + ((hbits + 7) / 8) * 8, c.tk, c.tv, c.tmp, s);
+      GLMB_LAUNCH(k_item_perm, cdiv(nitem, T), T, 0, s, nitem, ivals, itd0, itg0, ito0, r.itd, r.itg, r.ito);
+    }
+    return r;
+  };
+  Items it = make_items(tcut);
+  SelectIn si{H, bprime, it.itoff, it.itd, it.itg, K, tcut, &c.sel_multi[1], c.coop_ok};
+  dp_bound_items(si, c.sb, s);  // second pass: raises *tcut
+  if (c.trace) dp_bound_trace(c.sb, s);
+  trace(c, "update.select", it.ncell, it.nitem);
   Selected sel{};
   std::string serr;
   const int cap_nodes = p.cap_nodes > 0 ? p.cap_nodes : (1 << 22);
   glmb_status st = select_topk(si, cap_nodes, c.sb, sel, s, serr, c.trace);
+  if (st == GLMB_OK && sel.n < K && dp_bound_refined(c.sb, s)) {
+    // fewer than K children above a bound whose count promised K: search again from the
+    // caller's bound, with the items above it
+    trace(c, "update.refine_retry", sel.n, K);
+    it = make_items(t0);
+    si = SelectIn{H, bprime, it.itoff, it.itd, it.itg, K, t0, &c.sel_multi[1], c.coop_ok};
+    st = select_topk(si, cap_nodes, c.sb, sel, s, serr, c.trace);
+  }
   if (st != GLMB_OK) throw Error{st, serr};
+  const int32_t* ito = it.ito;
+  const int32_t* itg = it.itg;
   const int nsel = sel.n;
   if (nsel < 1) throw Error{GLMB_E_STATE, "selection kept no hypothesis (non-finite weights?)"};
   float* wout = need<float>(c.logw2, nsel);
