@@ -260,6 +260,7 @@ glmb_status glmb_destroy(glmb_ctx* x) {
                           &c.sb.scal, &c.sb.dp, &c.sb.dpc, &c.sb.dpa, &c.sb.cand, &c.prop_w, &c.pcnt, &c.poff, &c.ppre, &c.pu, &c.pi, &c.plogit, &c.slot_r,
                           &c.slot_part, &c.slot_age, &c.pm_part, &c.pe_part, &c.lz_t, &c.mlp_part, &c.est_buf, &c.ref_b1, &c.ref_opts, &c.ref_top, &c.ref_rest, &c.hopts};
   for (auto* b : bufs) b->release();
+  if (c.age_pin) (void)hipHostFree(c.age_pin);
   if (c.ev_ok)
     for (auto& e : c.ev) (void)hipEventDestroy(e);
   delete x;

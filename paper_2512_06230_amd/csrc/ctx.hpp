@@ -78,7 +78,8 @@ struct Ctx {
   float prop_norm[12] = {};
   DevBuf prop_w;          // float32 parameters
   DevBuf pcnt, poff, ppre, pu, pi, plogit, slot_r, slot_part, slot_age, pm_part, pe_part, lz_t, mlp_part;
-  std::vector<int32_t> h_age;
+  int32_t* age_pin = nullptr;  // pinned host buffer of the label ages uploaded per update
+  int age_cap = 0;
   DevBuf est_buf;  // estimate: presence flags and means of the estimated hypothesis' tracks
 };
 

@@ -105,49 +105,63 @@ __device__ __forceinline__ float wsum(float v, float* sh) {
 
 // ------------------------------------------------------------------ pairs and features
 // per instance: gated detection count and per-word prefix counts of its gate bits
-__global__ void k_pair_count(int U, int W, const uint32_t* gbits, int32_t* cnt, int32_t* ppre) {
-  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+// one wave per instance: gated detections per word of its gate bits, their prefix and total
+__global__ __launch_bounds__(256) void k_pair_count(int U, int W, const uint32_t* gbits, int32_t* cnt,
+                                                    int32_t* ppre) {
+  const int u = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kWave);
   if (u >= U) return;
+  const int lane = lane_id();
   int run = 0;
-  for (int w = 0; w < W; ++w) {
-    ppre[(size_t)u * W + w] = run;
-    run += __popc(gbits[(size_t)u * W + w]);
-  }
-  cnt[u] = run;
-}
-
-__global__ void k_pair_list(int U, int W, const uint32_t* gbits, const int32_t* poff, int32_t* pu, int32_t* pi) {
-  const int u = blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= U) return;
-  int pos = poff[u];
-  for (int w = 0; w < W; ++w) {
-    uint32_t b = gbits[(size_t)u * W + w];
-    while (b) {
-      pu[pos] = u;
-      pi[pos] = w * 32 + __ffs(b) - 1;
-      ++pos;
-      b &= b - 1;
+  for (int w0 = 0; w0 < W; w0 += kWave) {
+    const int w = w0 + lane;
+    const int c = w < W ? __popc(gbits[(size_t)u * W + w]) : 0;
+    int x = c;  // inclusive scan over the lanes
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int y = __shfl_up(x, d, kWave);
+      if (lane >= d) x += y;
     }
+    if (w < W) ppre[(size_t)u * W + w] = run + x - c;
+    run += __shfl(x, kWave - 1, kWave);
+  }
+  if (lane == 0) cnt[u] = run;
+}
+
+// one thread per (instance, word): the pairs of the word's gate bits, in detection order
+__global__ void k_pair_list(int U, int W, const uint32_t* gbits, const int32_t* poff, const int32_t* ppre,
+                            int32_t* pu, int32_t* pi) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)U * W) return;
+  const int u = (int)(t / W), w = (int)(t % W);
+  uint32_t b = gbits[t];
+  int pos = poff[u] + ppre[t];
+  while (b) {
+    pu[pos] = u;
+    pi[pos] = w * 32 + __ffs(b) - 1;
+    ++pos;
+    b &= b - 1;
   }
 }
 
-// existence probability of every label slot: partial sums over chunks of 256 hypotheses
+// existence probability of every label slot: partial sums over chunks of kSlotChunk hypotheses
+constexpr int kSlotChunk = 32;
 __global__ void k_slot_part(int H, int NS, int SW, const int32_t* rows, const float* logw, float* part) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   const int ch = blockIdx.y;
   if (s >= NS) return;
   float acc = 0.0f;
-  const int h1 = min(H, (ch + 1) * 256);
-  for (int h = ch * 256; h < h1; ++h)
+  const int h1 = min(H, (ch + 1) * kSlotChunk);
+  for (int h = ch * kSlotChunk; h < h1; ++h)
     if (rows[(size_t)h * SW + s] >= 0) acc += __expf(logw[h]);
   part[(size_t)ch * NS + s] = acc;
 }
-__global__ void k_slot_final(int NS, int nch, const float* part, float* r) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+// one wave per slot: the partial sums, lanes over the chunks, then a fixed butterfly
+__global__ __launch_bounds__(256) void k_slot_final(int NS, int nch, const float* part, float* r) {
+  const int s = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kWave);
   if (s >= NS) return;
   float acc = 0.0f;
-  for (int ch = 0; ch < nch; ++ch) acc += part[(size_t)ch * NS + s];
-  r[s] = acc;
+  for (int ch = lane_id(); ch < nch; ch += kWave) acc += part[(size_t)ch * NS + s];
+  for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_xor(acc, d, kWave);
+  if (lane_id() == 0) r[s] = acc;
 }
 
 __global__ void k_pair_feat(int n, const int32_t* pu, const int32_t* pi, const DInst* inst, const float2* z,
@@ -166,13 +180,16 @@ __global__ void k_pair_feat(int n, const int32_t* pu, const int32_t* pi, const D
 }
 
 // network score of every pair; with `remove`, pairs scoring below thr leave the gate
-__global__ __launch_bounds__(256) void k_prop_apply(int n, const int32_t* pu, const int32_t* pi, const DInst* inst,
+__global__ __launch_bounds__(256) void k_prop_apply(const int32_t* np, const int32_t* pu, const int32_t* pi,
+                                                    const DInst* inst,
                                                     const float2* z, float sig2, const float* slot_r,
                                                     const int32_t* slot_age, const int32_t* pcnt,
                                                     const float* params, Norm nm, float thr, int remove, int M,
                                                     int W, float* phi, uint32_t* gbits, float* logit_out,
                                                     int32_t* nremoved) {
   __shared__ float sw[kNParam];
+  const int n = *np;
+  if ((int)(blockIdx.x * blockDim.x) >= n) return;  // the grid covers an upper bound
   load_params(params, sw);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   bool rm = false;
@@ -472,43 +489,56 @@ Norm norm_of(const float* nm) {
 }
 
 // label existence, label ages, and the compacted pair list of the current gate; returns the
-// pair count
-int prepare_pairs(Ctx& c, int k, int M) {
+// pair count when host_count, else -1 (the count stays on the device at c.poff[U], the lists
+// are sized for every instance x detection pair)
+int prepare_pairs(Ctx& c, int k, int M, bool host_count = true) {
   hipStream_t s = c.s;
   const int T = 256;
   const int H = c.nhyp, U = c.ninst, NS = c.nslot, SW = c.stride;
   const int W = std::max(1, (M + 31) / 32);
-  const int nch = cdiv(H, 256);
+  const int nch = cdiv(H, kSlotChunk);
   float* part = need<float>(c.slot_part, (int64_t)nch * std::max(NS, 1));
   float* r = need<float>(c.slot_r, NS + 1);
   if (NS > 0) {
     hipLaunchKernelGGL(k_slot_part, dim3(cdiv(NS, T), nch), dim3(T), 0, s, H, NS, SW, c.rows.as<int32_t>(),
                        c.logw.as<float>(), part);
     GLMB_HIP(hipGetLastError());
-    GLMB_LAUNCH(k_slot_final, cdiv(NS, T), T, 0, s, NS, nch, part, r);
+    GLMB_LAUNCH(k_slot_final, cdiv((int64_t)NS * kWave, T), T, 0, s, NS, nch, part, r);
   }
-  c.h_age.resize(NS + 1);
-  for (int j = 0; j < NS; ++j) c.h_age[j] = k - c.slot_lab[j].first;
+  if (c.age_cap < NS + 1) {  // pinned, so that the upload below does not wait for the stream
+    if (c.age_pin) GLMB_HIP(hipHostFree(c.age_pin));
+    c.age_pin = nullptr;
+    c.age_cap = 0;
+    GLMB_HIP(hipHostMalloc((void**)&c.age_pin, (size_t)2 * (NS + 1) * sizeof(int32_t), hipHostMallocDefault));
+    c.age_cap = 2 * (NS + 1);
+  }
+  // every caller synchronises the stream before it can get here again (the update reads its
+  // counts back, the lost-mass and feature calls their results), so no upload still reads it
+  for (int j = 0; j < NS; ++j) c.age_pin[j] = k - c.slot_lab[j].first;
   int32_t* age = need<int32_t>(c.slot_age, NS + 1);
-  if (NS) GLMB_HIP(hipMemcpyAsync(age, c.h_age.data(), NS * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  if (NS) GLMB_HIP(hipMemcpyAsync(age, c.age_pin, NS * sizeof(int32_t), hipMemcpyHostToDevice, s));
   int32_t* cnt = need<int32_t>(c.pcnt, U + 1);
   int32_t* off = need<int32_t>(c.poff, U + 1);
   int32_t* ppre = need<int32_t>(c.ppre, (int64_t)U * W);
-  GLMB_LAUNCH(k_pair_count, cdiv(U, T), T, 0, s, U, W, c.gbits.as<uint32_t>(), cnt, ppre);
+  GLMB_LAUNCH(k_pair_count, cdiv((int64_t)U * kWave, T), T, 0, s, U, W, c.gbits.as<uint32_t>(), cnt, ppre);
   scan_excl(cnt, off, U, off + U, c.tmp, s);
-  const int n = U > 0 ? read_one(s, off + U) : 0;
-  int32_t* pu = need<int32_t>(c.pu, n);
-  int32_t* pi = need<int32_t>(c.pi, n);
-  GLMB_LAUNCH(k_pair_list, cdiv(U, T), T, 0, s, U, W, c.gbits.as<uint32_t>(), off, pu, pi);
+  const int n = !host_count ? -1 : U > 0 ? read_one(s, off + U) : 0;
+  const int64_t cap = host_count ? n : (int64_t)U * M;
+  int32_t* pu = need<int32_t>(c.pu, cap);
+  int32_t* pi = need<int32_t>(c.pi, cap);
+  GLMB_LAUNCH(k_pair_list, cdiv((int64_t)U * W, T), T, 0, s, U, W, c.gbits.as<uint32_t>(), off, ppre, pu, pi);
   return n;
 }
 
-// network scores of the listed pairs (into c.plogit), optionally removing the low ones
+// network scores of the listed pairs (into c.plogit unless removing), optionally removing the
+// low ones; n < 0: the count is on the device (c.poff[U]) and the grid covers at most cap pairs
 void score_pairs(Ctx& c, int n, int M, bool remove) {
   const int W = std::max(1, (M + 31) / 32);
-  float* logit = need<float>(c.plogit, n);
+  const int64_t cap = n >= 0 ? n : (int64_t)c.ninst * M;
+  float* logit = remove ? nullptr : need<float>(c.plogit, cap);
   int32_t* nremoved = c.scal.as<int32_t>() + 18;
-  GLMB_LAUNCH(k_prop_apply, cdiv(n, 256), 256, 0, c.s, n, c.pu.as<int32_t>(), c.pi.as<int32_t>(),
+  const int grid = cdiv(cap, 256);
+  GLMB_LAUNCH(k_prop_apply, grid, 256, 0, c.s, c.poff.as<int32_t>() + c.ninst, c.pu.as<int32_t>(), c.pi.as<int32_t>(),
               (const DInst*)c.inst.p, c.z.as<float2>(), c.p.sigma_z * c.p.sigma_z, c.slot_r.as<float>(),
               c.slot_age.as<int32_t>(), c.pcnt.as<int32_t>(), c.prop_w.as<float>(), norm_of(c.prop_norm),
               c.prop_thr, remove ? 1 : 0, M, W, c.phi.as<float>(), c.gbits.as<uint32_t>(), logit, nremoved);
@@ -517,7 +547,7 @@ void score_pairs(Ctx& c, int n, int M, bool remove) {
 
 void proposal_apply(Ctx& c, int k, int M) {
   trace(c, "update.proposal");
-  const int n = prepare_pairs(c, k, M);
+  const int n = prepare_pairs(c, k, M, false);
   score_pairs(c, n, M, true);
 }
 
