@@ -22,6 +22,22 @@ HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
 FP32_VECTOR_TFLOPS = 157.3  # MI355X FP32 vector (packed)
 
 
+
+def assoc_source_sha(rec):
+    """sha256 of the source region holding the association kernels (the text between the
+    two marker lines named in the traffic record), or None when the file or a marker is gone."""
+    import hashlib
+    src = os.path.join(ROOT, rec["source"])
+    if not os.path.exists(src):
+        return None
+    text = open(src).read()
+    a, b = rec.get("region") or (None, None)
+    if not a or not b or a not in text or b not in text:
+        return None
+    i = text.index(a)
+    j = text.index(b, i)
+    return hashlib.sha256(text[i:j].encode()).hexdigest()
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,11 +219,8 @@ def main():
     traffic = None
     tf = os.path.join(ROOT, "profiles", "k_assoc_n500_h1e4_traffic.json")
     if os.path.exists(tf):
-        import hashlib
         rec = json.load(open(tf))
-        src = os.path.join(ROOT, rec["source"])
-        if os.path.exists(src) and hashlib.sha256(open(src, "rb").read()).hexdigest() == rec["source_sha256"] \
-                and args.n_obj == 500 and args.h_max == 10000:
+        if assoc_source_sha(rec) == rec["source_sha256"] and args.n_obj == 500 and args.h_max == 10000:
             traffic = rec["bytes_per_launch"]
     out = {
         "metric": METRIC,
