@@ -1583,19 +1583,22 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   GLMB_LAUNCH(k_child_depth, cdiv(nk, T), T, 0, s, nk, sel.node, sel.nd_parent, sel.nd_item, sel.nd_h, depth, chh,
               errf);
   scan_excl(depth, doff, nk, doff + nk, c.tmp, s);
-  const int ndev = read1(s, doff + nk);
-  int32_t* devi = need<int32_t>(c.dev_i, ndev);
-  int32_t* devn = need<int32_t>(c.dev_slot, 2 * (int64_t)ndev);
-  int32_t* devo = devn + ndev;
-  GLMB_LAUNCH(k_child_devs, cdiv(nk, T), T, 0, s, nk, M, sel.node, sel.nd_parent, sel.nd_item, chh, doff, itg, ito,
-              best16, devi, devn, devo);
   // retained parents
   int32_t* mark = need<int32_t>(c.row_mark, H + 1);
   GLMB_LAUNCH(k_fill_i32, cdiv(H + 1, T), T, 0, s, mark, H + 1, 0);
   GLMB_LAUNCH(k_mark, cdiv(nk, T), T, 0, s, nk, chh, mark);
   int32_t* ppre = need<int32_t>(c.pre, H + 1);
   scan_excl(mark, ppre, H, tot, c.tmp, s);
-  const int np = read1(s, tot);
+  int32_t cnt2[2];  // deviations of the kept children, retained parents: one round trip
+  GLMB_HIP(hipMemcpyAsync(&cnt2[0], doff + nk, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipMemcpyAsync(&cnt2[1], tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipStreamSynchronize(s));
+  const int ndev = cnt2[0], np = cnt2[1];
+  int32_t* devi = need<int32_t>(c.dev_i, ndev);
+  int32_t* devn = need<int32_t>(c.dev_slot, 2 * (int64_t)ndev);
+  int32_t* devo = devn + ndev;
+  GLMB_LAUNCH(k_child_devs, cdiv(nk, T), T, 0, s, nk, M, sel.node, sel.nd_parent, sel.nd_item, chh, doff, itg, ito,
+              best16, devi, devn, devo);
   int32_t* plist = need<int32_t>(c.cells, np + 1);
   int32_t* hpm = need<int32_t>(c.hp_map, H + 1);
   GLMB_LAUNCH(k_plist, cdiv(H, T), T, 0, s, H, mark, ppre, plist, hpm);
@@ -1616,7 +1619,24 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   auto eb_ = exc_bufs(ecap);
   GLMB_LAUNCH(k_exceptions, np, 256, lds, s, plist, M, NS, LW, SW, c.rows.as<int32_t>(), best16, loff, llen, lmeas,
               dmask, nexc, eb_.first, eb_.first + ecap, eb_.first + 2 * ecap, eb_.second, ecap);
-  int ne = read1(s, nexc);
+  // child masks (count) and default records (flags) before the one round trip that reads the
+  // exception, child-mask and default counts
+  int32_t* mcount = need<int32_t>(c.ccount, nk + 1);
+  int32_t* moff = need<int32_t>(c.coff2, nk + 1);
+  GLMB_LAUNCH(k_child_mods, cdiv(nk, T), T, 0, s, nk, doff, devn, devo, (const int32_t*)nullptr, mcount,
+              (int32_t*)nullptr, (int32_t*)nullptr);
+  scan_excl(mcount, moff, nk, moff + nk, c.tmp, s);
+  int32_t* dfl = need<int32_t>(c.flags, U + 1);
+  int32_t* dpre = need<int32_t>(c.pmult, U + 1);
+  GLMB_LAUNCH(k_def_flags, cdiv(U, T), T, 0, s, U, first, dfl);
+  scan_excl(dfl, dpre, U, tot, c.tmp, s);
+  int32_t cnt3[3];
+  GLMB_HIP(hipMemcpyAsync(&cnt3[0], nexc, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipMemcpyAsync(&cnt3[1], moff + nk, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipMemcpyAsync(&cnt3[2], tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(hipStreamSynchronize(s));
+  int ne = cnt3[0];
+  const int nm = cnt3[1], nd = cnt3[2];
   if (ne > ecap) {  // grow and redo
     ecap = ne;
     eb_ = exc_bufs(ecap);
@@ -1639,20 +1659,8 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   }
   int32_t* eoff = need<int32_t>(c.ids, np + 2);
   GLMB_LAUNCH(k_exc_off, cdiv(np + 1, T), T, 0, s, np, ne, ea, eoff);
-  // child masks: count
-  int32_t* mcount = need<int32_t>(c.ccount, nk + 1);
-  int32_t* moff = need<int32_t>(c.coff2, nk + 1);
-  GLMB_LAUNCH(k_child_mods, cdiv(nk, T), T, 0, s, nk, doff, devn, devo, (const int32_t*)nullptr, mcount,
-              (int32_t*)nullptr, (int32_t*)nullptr);
-  scan_excl(mcount, moff, nk, moff + nk, c.tmp, s);
-  const int nm = read1(s, moff + nk);
   trace(c, "update.masks", np, ne);
   // records: defaults | exceptions | child masks
-  int32_t* dfl = need<int32_t>(c.flags, U + 1);
-  int32_t* dpre = need<int32_t>(c.pmult, U + 1);
-  GLMB_LAUNCH(k_def_flags, cdiv(U, T), T, 0, s, U, first, dfl);
-  scan_excl(dfl, dpre, U, tot, c.tmp, s);
-  const int nd = read1(s, tot);
   const int R = nd + ne + nm;
   int32_t* rec_u = need<int32_t>(c.recs, 3 * (int64_t)R + 3);
   int32_t* rec_a = rec_u + R + 1;
