@@ -404,22 +404,44 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
       last_raise = used;
     }
   }
-  // candidates: every node >= t, in enumeration order
+  // candidates: every node >= t, in enumeration order, and the range of their value keys
+  __shared__ uint32_t vlo, vhi;
+  if (threadIdx.x == 0) {
+    vlo = 0xffffffffu;
+    vhi = 0u;
+  }
   int nc = 0;
+  uint32_t mlo = 0xffffffffu, mhi = 0u;
   if (status == 0)
     for (int c0 = 0; c0 < used; c0 += kSB) {
       const int n = c0 + (int)threadIdx.x;
       const int f = n < used && nd_v[n] >= t ? 1 : 0;
       int64_t tot;
       const int64_t off = sb_excl_scan(f, sh, &tot);
-      if (f) cand[nc + off] = n;
+      if (f) {
+        cand[nc + off] = n;
+        const uint32_t o = f2o(nd_v[n]);
+        mlo = min(mlo, o);
+        mhi = max(mhi, o);
+      }
       nc += (int)tot;
     }
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    mlo = min(mlo, (uint32_t)__shfl_xor((int)mlo, d, kWave));
+    mhi = max(mhi, (uint32_t)__shfl_xor((int)mhi, d, kWave));
+  }
+  __syncthreads();
+  if (lane_id() == 0) {
+    atomicMin(&vlo, mlo);
+    atomicMax(&vhi, mhi);
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     out[0] = used;
     out[1] = levels;
     out[2] = status;
     out[3] = nc;
+    out[4] = (int32_t)(vlo ^ vhi);  // the value-key bits that vary among the candidates
     *t_out = t;
   }
 }
@@ -1198,7 +1220,8 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
     return GLMB_E_CAPACITY;
   }
   Nodes A = alloc(0), B = alloc(1);
-  int32_t* scal = need<int32_t>(b.scal, 32);   // [0]=total, [1..2]=cut, [4..6]=remap, [8..9] t, [16..20] coop
+  int32_t* scal = need<int32_t>(b.scal, 32);   // [0]=total, [1..2]=cut, [4..6]=remap, [8..9] t, [16..20] coop,
+                                               // [24..28] one-workgroup search
   float* t = (float*)(scal + 8);               // current threshold
   float* t2 = (float*)(scal + 9);
   GLMB_HIP(hipMemcpyAsync(t, in.t0, sizeof(float), hipMemcpyDeviceToDevice, s));
@@ -1211,17 +1234,19 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
   // outgrows kBlockNodes continues on the whole GPU (multi-kernel levels below); the call
   // site remembers that and starts there next time, until a search is small again.
   int used = 0, levels = 0, nc_fast = 0;
+  uint32_t vary = 0xffffffffu;  // value-key bits that differ among the candidates
   bool fast = false;
   if (!(in.prefer_multi && *in.prefer_multi)) {
     GLMB_LAUNCH(k_select_block, 1, kSB, 0, s, in.P, in.base, in.it_off, in.it_delta, in.it_group, in.K, in.t0,
-                std::min(cap, kBlockNodes), A.p, A.i, A.h, A.v, A.b, t, scal + 4,
+                std::min(cap, kBlockNodes), A.p, A.i, A.h, A.v, A.b, t, scal + 24,
                 need<int32_t>(b.cand, std::min(cap, kBlockNodes) + 1));
-    GLMB_HIP(hipMemcpyAsync(hs, scal + 4, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GLMB_HIP(hipMemcpyAsync(hs, scal + 24, 5 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     GLMB_HIP(hipStreamSynchronize(s));
     used = hs[0];
     levels = hs[1];
     fast = hs[2] == 0;
     nc_fast = hs[3];
+    vary = (uint32_t)hs[4];
     tr("block", used, hs[2]);
     if (in.prefer_multi) *in.prefer_multi = !fast;
   }
@@ -1418,10 +1443,15 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
   uint64_t* keys = need<uint64_t>(b.keys, nc + 1);
   uint32_t* vals = need<uint32_t>(b.vals, nc + 1);
   GLMB_LAUNCH(k_cand_keys, cdiv(nc, T), T, 0, s, nc, cand, A.h, keys, vals);
-  sort_pairs(keys, vals, nc, 0, ((hbits + 7) / 8) * 8, b.tk, b.tv, b.tmp, s);  // canonical key order
+  // canonical key order: a stable sort by parent rank of the enumeration order, unless every
+  // candidate is a root (one level), whose enumeration order is the parent order
+  if (!(fast && levels <= 1)) sort_pairs(keys, vals, nc, 0, ((hbits + 7) / 8) * 8, b.tk, b.tv, b.tmp, s);
   GLMB_LAUNCH(k_final_keys, cdiv(nc, T), T, 0, s, nc, vals, A.v, keys, vals);
-  // stable sort on the value bits only: the input is in canonical key order already
-  sort_pairs(keys, vals, nc, 32, 64, b.tk, b.tv, b.tmp, s);
+  // stable sort on the value bits only (the input is in canonical key order already), and only
+  // on the bytes below the highest one in which the candidates' values differ
+  int vb = 32;
+  while (vb > 0 && !((vary >> (vb - 1)) & 1u)) --vb;
+  sort_pairs(keys, vals, nc, 32, 32 + ((vb + 7) / 8) * 8, b.tk, b.tv, b.tmp, s);
   GLMB_LAUNCH(k_take, cdiv(n, T), T, 0, s, n, keys, vals, A.v, out.node, out.value, out.keyrank);
   out.n = n;
   out.nd_parent = A.p;
