@@ -250,7 +250,7 @@ glmb_status glmb_destroy(glmb_ctx* x) {
                           &c.ntrk2, &c.rows2, &c.births, &c.births2, &c.diag_best, &c.diag_logpi, &c.diag_ru, &c.prev_rows,
                           &c.prev_src, &c.child_par, &c.dev_off, &c.dev_i, &c.dev_slot, &c.z, &c.cmax, &c.gbits,
                           &c.phi, &c.lbits, &c.lpre, &c.llen, &c.loff, &c.lmeas, &c.inst_beg, &c.ccnt, &c.coff,
-                          &c.cand, &c.best16, &c.dev1, &c.lserel, &c.bprime, &c.lzprime, &c.vals, &c.cells,
+                          &c.cand, &c.best16, &c.dev1, &c.lserel, &c.bprime, &c.lzprime, &c.cells,
                           &c.ccount, &c.coff2, &c.it_h, &c.it_delta, &c.it_group, &c.it_opt, &c.it_off, &c.keys,
                           &c.vals32, &c.scal, &c.sel_logw, &c.hp_map, &c.first, &c.dmask, &c.exc, &c.cmod, &c.recs,
                           &c.rec_keys, &c.rec_vals, &c.ids, &c.row_mark, &c.ru_part, &c.ru, &c.bt, &c.tmp, &c.tk,

@@ -63,7 +63,7 @@ struct Ctx {
 
   // ---- update work buffers ----
   DevBuf z, cmax, gbits, phi, lbits, lpre, llen, loff, lmeas, inst_beg, ccnt, coff, cand, best16, dev1, lserel,
-      bprime, lzprime, vals, cells, ccount, coff2, it_h, it_delta, it_group, it_opt, it_off, keys, vals32, scal,
+      bprime, lzprime, cells, ccount, coff2, it_h, it_delta, it_group, it_opt, it_off, keys, vals32, scal,
       sel_logw, hp_map, first, dmask, exc, cmod, recs, rec_keys, rec_vals, ids, row_mark, ru_part, ru, bt,
       tmp, tk, tv, flags, pre, pmult, pvals, rec_m, ref_b1, ref_opts, ref_top, ref_rest, hopts;
   SelectBufs sb;

@@ -116,23 +116,16 @@ __global__ __launch_bounds__(256) void k_pitems(int H, int nbs, int nlt, int str
   if (!ioff && threadIdx.x == 0) icount[h] = ntr + nkb;
 }
 
-// child rows (width NS + NB), their hash and track count
-__global__ __launch_bounds__(256) void k_prows(int n, int NS, int NB, int stride, int U, int t_yes,
-                                               const int32_t* byes, const int32_t* sel_node, const int32_t* nd_parent,
-                                               const int32_t* nd_item, const int32_t* nd_h, const int32_t* it_g,
-                                               const int32_t* rows, int32_t* out, uint64_t* hash, int32_t* nt,
-                                               int32_t* par) {
-  __shared__ unsigned long long hs;
-  __shared__ int32_t cnt;
+// child rows (width NS + NB), their hash and track count; one wave per child
+__global__ __launch_bounds__(64) void k_prows(int n, int NS, int NB, int stride, int U, int t_yes,
+                                              const int32_t* byes, const int32_t* sel_node, const int32_t* nd_parent,
+                                              const int32_t* nd_item, const int32_t* nd_h, const int32_t* it_g,
+                                              const int32_t* rows, int32_t* out, uint64_t* hash, int32_t* nt,
+                                              int32_t* par) {
   const int c = blockIdx.x;
   const int W2 = NS + NB;
   const int node = sel_node[c];
   const int h = nd_h[node];
-  if (threadIdx.x == 0) {
-    hs = 0;
-    cnt = 0;
-  }
-  __syncthreads();
   int32_t* o = out + (size_t)c * W2;
   for (int s = threadIdx.x; s < W2; s += blockDim.x) {
     if (s < NS) o[s] = t_yes ? rows[(size_t)h * stride + s] : -1;
@@ -155,12 +148,13 @@ __global__ __launch_bounds__(256) void k_prows(int n, int NS, int NB, int stride
       hl += mix64(((uint64_t)(uint32_t)s << 32) | (uint32_t)o[s]);
       ++cl;
     }
-  atomicAdd(&hs, hl);
-  atomicAdd(&cnt, cl);
-  __syncthreads();
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    hl += __shfl_xor(hl, d, kWave);
+    cl += __shfl_xor(cl, d, kWave);
+  }
   if (threadIdx.x == 0) {
-    hash[c] = hs;
-    nt[c] = cnt;
+    hash[c] = hl;
+    nt[c] = cl;
   }
 }
 
@@ -399,7 +393,7 @@ void stage_predict(Ctx& c, int k) {
   uint64_t* hash = need<uint64_t>(c.rec_keys, n + 1);
   int32_t* ntc = need<int32_t>(c.ntrk2, n + 1);
   int32_t* parc = need<int32_t>(c.child_par, n + 1);
-  GLMB_LAUNCH(k_prows, n, 256, 0, s, n, NS, NB, SW, U, t_yes, dby, sel.node, sel.nd_parent, sel.nd_item, sel.nd_h, itg,
+  GLMB_LAUNCH(k_prows, n, kWave, 0, s, n, NS, NB, SW, U, t_yes, dby, sel.node, sel.nd_parent, sel.nd_item, sel.nd_h, itg,
               c.rows.as<int32_t>(), crow, hash, ntc, parc);
   uint64_t* hk = need<uint64_t>(c.keys, n + 1);
   uint32_t* hv = need<uint32_t>(c.vals32, n + 1);
