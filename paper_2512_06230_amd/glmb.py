@@ -237,8 +237,8 @@ class Tracker:
 
     def estimate(self, cap: int = 65536):
         n = ctypes.c_int32()
-        labs = np.zeros((cap, 2), np.int32)
-        means = np.zeros((cap, 4), np.float32)
+        labs = np.empty((cap, 2), np.int32)  # the library fills the first n rows
+        means = np.empty((cap, 4), np.float32)
         self._check(self._L.glmb_estimate(self._ctx, int(cap), ctypes.byref(n), _ip(labs), _fp(means)),
                     "glmb_estimate")
         return labs[:n.value].copy(), means[:n.value].copy()
