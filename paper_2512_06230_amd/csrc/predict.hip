@@ -158,12 +158,12 @@ __global__ __launch_bounds__(64) void k_prows(int n, int NS, int NB, int stride,
   }
 }
 
-// 32 bits of the row hash: children with equal rows share them, and rows of one run are
-// compared in full, so a shorter key only lengthens a few runs
+// 24 bits of the row hash: children with equal rows share them, and rows of one run are
+// compared in full, so a shorter key only lengthens a few runs (about n^2 / 2^25 collisions)
 __global__ void k_hash_keys(int n, const uint64_t* hash, uint64_t* keys, uint32_t* vals) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
-  keys[c] = hash[c] >> 32;
+  keys[c] = hash[c] >> 40;
   vals[c] = (uint32_t)c;
 }
 
@@ -398,7 +398,7 @@ void stage_predict(Ctx& c, int k) {
   uint64_t* hk = need<uint64_t>(c.keys, n + 1);
   uint32_t* hv = need<uint32_t>(c.vals32, n + 1);
   GLMB_LAUNCH(k_hash_keys, cdiv(n, T), T, 0, s, n, hash, hk, hv);
-  sort_pairs(hk, hv, n, 0, 32, c.tk, c.tv, c.tmp, s);
+  sort_pairs(hk, hv, n, 0, 24, c.tk, c.tv, c.tmp, s);
   int32_t* leader = need<int32_t>(c.first, 4 * (int64_t)n + 4);
   int32_t* islead = leader + n + 1;
   int32_t* mrank = islead + n + 1;
