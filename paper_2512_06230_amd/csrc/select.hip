@@ -276,7 +276,8 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
   float t = *t0;
   int status = 0;  // 0 done, 1 node store full, 2 too deep
   int used = 0;
-  // roots, in parent rank order
+  // roots, in parent rank order, with the number of their extensions above t
+  int64_t rext = 0;
   for (int c0 = 0; c0 < P; c0 += kSB) {
     const int h = c0 + threadIdx.x;
     const int f = (h < P && base[h] >= t) ? 1 : 0;
@@ -288,16 +289,24 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
     }
     if (f) {
       const int n = used + (int)off;
+      const float v = base[h];
       nd_p[n] = -1;
       nd_i[n] = -1;
       nd_h[n] = h;
-      nd_v[n] = base[h];
+      nd_v[n] = v;
       nd_b[n] = 0ull;
+      // extensions of the root: the items with v - delta >= t, a prefix of the parent's list
+      const int b0 = it_off[h], b1 = it_off[h + 1];
+      if (b0 < b1 && v - idel[b0] >= t) rext += 1;
     }
     used += (int)tot;
   }
   __syncthreads();
-  int first = 0, end = used, levels = 0, last_raise = used;
+  int64_t rext_all;
+  (void)sb_excl_scan(rext, sh, &rext_all);
+  // no root has a child above t: the candidates are the roots, in order
+  const bool roots_only = status == 0 && rext_all == 0;
+  int first = 0, end = roots_only ? 0 : used, levels = roots_only ? 1 : 0, last_raise = used;
   while (status == 0 && first < end) {
     if (++levels > kMaxDepth + 1) {
       status = 2;
@@ -412,7 +421,15 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
   }
   int nc = 0;
   uint32_t mlo = 0xffffffffu, mhi = 0u;
-  if (status == 0)
+  if (roots_only) {
+    for (int n = threadIdx.x; n < used; n += kSB) {
+      cand[n] = n;
+      const uint32_t o = f2o(nd_v[n]);
+      mlo = min(mlo, o);
+      mhi = max(mhi, o);
+    }
+    nc = used;
+  } else if (status == 0)
     for (int c0 = 0; c0 < used; c0 += kSB) {
       const int n = c0 + (int)threadIdx.x;
       const int f = n < used && nd_v[n] >= t ? 1 : 0;
