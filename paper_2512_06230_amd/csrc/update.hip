@@ -1172,12 +1172,14 @@ __global__ __launch_bounds__(256) void k_ru_part(int H, int M, int hchunk, const
   for (int h = ch * hchunk; h < h1; ++h) acc += __expf(lzprime[h] - L + lgk - c - lserel[(size_t)h * M + i]);
   part[(size_t)ch * M + i] = acc;
 }
-__global__ void k_ru_final(int M, int nch, const float* part, float* ru) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+// one wave per detection: the chunks' partial sums, lanes over the chunks, fixed butterfly
+__global__ __launch_bounds__(256) void k_ru_final(int M, int nch, const float* part, float* ru) {
+  const int i = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kWave);
   if (i >= M) return;
   float s = 0.0f;
-  for (int ch = 0; ch < nch; ++ch) s += part[(size_t)ch * M + i];
-  ru[i] = 1.0f - s;
+  for (int ch = lane_id(); ch < nch; ch += kWave) s += part[(size_t)ch * M + i];
+  for (int d = kWave / 2; d > 0; d >>= 1) s += __shfl_xor(s, d, kWave);
+  if (lane_id() == 0) ru[i] = 1.0f - s;
 }
 
 // one wave: greedy clustering of the seeds in detection order (a seed joins the first
@@ -1716,7 +1718,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     hipLaunchKernelGGL(k_ru_part, dim3(cdiv(M, T), nch), dim3(T), 0, s, H, M, hchunk, lzprime, lz, lserel, cmax, lgk,
                        part);
     GLMB_HIP(hipGetLastError());
-    GLMB_LAUNCH(k_ru_final, cdiv(M, T), T, 0, s, M, nch, part, ru);
+    GLMB_LAUNCH(k_ru_final, cdiv((int64_t)M * kWave, T), T, 0, s, M, nch, part, ru);
   }
   int32_t* member = need<int32_t>(c.ru, (int64_t)M + 1);
   DBirth* nb = (DBirth*)need<uint8_t>(c.births2, (int64_t)(M + 1) * sizeof(DBirth));
