@@ -1712,7 +1712,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   c.mark(4);
   float* ru = need<float>(c.diag_ru, M + 1);
   if (M > 0) {
-    const int hchunk = 64;
+    const int hchunk = 16;
     const int nch = cdiv(H, hchunk);
     float* part = need<float>(c.ru_part, (int64_t)nch * M);
     hipLaunchKernelGGL(k_ru_part, dim3(cdiv(M, T), nch), dim3(T), 0, s, H, M, hchunk, lzprime, lz, lserel, cmax, lgk,
