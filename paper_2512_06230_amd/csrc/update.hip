@@ -1123,8 +1123,7 @@ __global__ void k_kalman(int nnew, int LW, const int32_t* rep, const int32_t* ru
   out[id] = y;
 }
 
-// child rows: parent row with every instance replaced by its updated instance (one wave per
-// child)
+// child rows: parent row with every instance replaced by its updated instance
 __global__ __launch_bounds__(256) void k_child_rows(int n, int stride, const int32_t* ch_h, const int32_t* hp_map,
                                                     const int32_t* rows, const int32_t* did, const int32_t* eb,
                                                     const int32_t* eoff, const int32_t* exc_id, const int32_t* moff,
@@ -1702,7 +1701,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   int32_t* did = first + U + 1;
   GLMB_LAUNCH(k_did, cdiv(U, T), T, 0, s, U, first, dpre, rec_id, did);
   int32_t* nrows = need<int32_t>(c.rows2, (int64_t)nk * SW);
-  GLMB_LAUNCH(k_child_rows, nk, kWave, 0, s, nk, SW, chh, hpm, c.rows.as<int32_t>(), did, eb, eoff2, rec_id + nd, moff,
+  GLMB_LAUNCH(k_child_rows, nk, 256, 0, s, nk, SW, chh, hpm, c.rows.as<int32_t>(), did, eb, eoff2, rec_id + nd, moff,
               rec_b + nd + ne, rec_id + nd + ne, nrows);
   int32_t* nntrk = need<int32_t>(c.ntrk2, nk + 1);
   GLMB_LAUNCH(k_gather_i32, cdiv(nk, T), T, 0, s, nk, chh, c.ntrk.as<int32_t>(), nntrk);
