@@ -64,7 +64,9 @@ typedef struct glmb_ctx glmb_ctx;
 /* Host-side description of a GLMB (used by import, export and warm start).
  * Instances: n_inst Gaussian track densities, inst_lab[2*u] = birth scan, inst_lab[2*u+1] =
  * index within that scan; inst_m[4*u], inst_P[16*u] row-major.  Hypotheses: hyp_logw[h]
- * (need not be normalised; the order is the rank order), the instances of hypothesis h are
+ * (need not be normalised; the state keeps its hypotheses in rank order, weight descending,
+ * so import ranks them by weight, stably: equal weights keep the input order; export lists
+ * them in that order and hyp_parent names the input position), the instances of hypothesis h are
  * hyp_idx[hyp_off[h] .. hyp_off[h+1]) (distinct labels).  Pending births for the next
  * predict: birth_lab/m/P as above and existence probability birth_r.  On export the library
  * also fills inst_src (the input index the instance derives from), inst_nz and
@@ -104,6 +106,14 @@ typedef struct {
    * per-(hypothesis, detection) association kernel of hypotheses 1..H-1 alone, [2] cut bound + deviation items + selection, [3] materialise + Kalman,
    * [4] births, [5] whole update */
   float stage_ms[6];
+  /* (instance, detection set) records whose 32-bit fingerprint equalled that of a different
+   * set of the same instance; such runs are resolved by full comparison (results unchanged).
+   * The environment variable GLMB_REC_HASH_BITS (1..32, read by glmb_create) narrows the
+   * fingerprint so that this path can be exercised. */
+  int32_t rec_collisions;
+  int32_t host_syncs;       /* host-device synchronisations made by the update            */
+  int32_t search_form;      /* selection search of the update: 0 one workgroup, 1 one cooperative
+                               whole-GPU launch, 2 host-driven levels of whole-GPU kernels  */
 } glmb_step_stats;
 
 /* Library / status utilities */
@@ -136,8 +146,9 @@ glmb_status glmb_predict(glmb_ctx* ctx, int32_t k);
  * distinct (track, detection set), and derives the birth components for scan k+1. */
 glmb_status glmb_update(glmb_ctx* ctx, int32_t k, const float* z_dev, int32_t M);
 
-/* Keep the h_max first hypotheses, renormalise, drop weights below tau (the first is kept),
- * renormalise again (Sec. 3 end). Idempotent. */
+/* Keep the h_max first hypotheses in rank order, renormalise over them, drop the hypotheses
+ * from the first weight below tau on (the first is always kept), renormalise again (Sec. 3
+ * end). Idempotent. */
 glmb_status glmb_truncate(glmb_ctx* ctx, int32_t h_max, float tau);
 
 /* State estimate: maximum a posteriori cardinality n, then the most likely hypothesis with
@@ -261,9 +272,12 @@ glmb_status glmb_batch_set_schedule(glmb_batch* b, int32_t workers, int32_t long
 glmb_status glmb_batch_scene(glmb_batch* b, int32_t scene, glmb_ctx** out);
 /* One time step k of every scene.  z_dev: device float32 [z_off[n]][2], the detections of
  * scene s are rows z_off[s] .. z_off[s+1]); z_off: host int32 [n+1], z_off[0] = 0,
- * non-decreasing.  Synchronises.  On failure the status of the first failing scene is returned
+ * non-decreasing.  caller_stream: the hipStream_t on which z_dev was written (NULL: the null
+ * stream); the worker streams wait for the work queued there before reading it.
+ * Synchronises.  On failure the status of the first failing scene is returned
  * (glmb_batch_last_error names it) and the other scenes have still been stepped. */
-glmb_status glmb_batch_step(glmb_batch* b, int32_t k, const float* z_dev, const int32_t* z_off);
+glmb_status glmb_batch_step(glmb_batch* b, int32_t k, const float* z_dev, const int32_t* z_off,
+                            void* caller_stream);
 glmb_status glmb_batch_stats_get(glmb_batch* b, glmb_batch_stats* out);
 const char* glmb_batch_last_error(const glmb_batch* b);
 

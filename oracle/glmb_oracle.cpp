@@ -788,10 +788,14 @@ struct Oracle {
   // ---- truncation: H_max then tau, each on renormalised weights (Sec. 3 end) ----------
   int truncate(int hmax, double tau) {
     if (hmax < 1) return -1;
-    if ((int)hyp.size() > hmax) hyp.resize(hmax);
     std::vector<double> v;
-    for (auto& h : hyp) v.push_back(h.logw);
+    if (ORACLE_MUTANT == 12)
+      for (auto& h : hyp) v.push_back(h.logw);  // planted: tau against the normaliser before the H_max cut
+    if ((int)hyp.size() > hmax) hyp.resize(hmax);
+    if (ORACLE_MUTANT != 12)
+      for (auto& h : hyp) v.push_back(h.logw);
     double z = lse(v);
+    // the hypotheses are in rank order (weight descending): tau keeps a prefix
     size_t keep = hyp.size();
     if (tau > 0.0) {
       keep = 1;
@@ -799,7 +803,7 @@ struct Oracle {
     }
     hyp.resize(keep);
     v.resize(keep);
-    z = lse(v);
+    if (ORACLE_MUTANT != 11) z = lse(v);  // planted 11: no renormalisation after tau
     for (auto& h : hyp) h.logw -= z;
     gc();
     return 0;
@@ -811,9 +815,11 @@ struct Oracle {
     for (auto& h : hyp) nmax = std::max(nmax, h.inst.size());
     std::vector<double> r(nmax + 1, 0.0);
     for (auto& h : hyp) r[h.inst.size()] += std::exp(h.logw);
+    // MAP cardinality; a tie goes to the smaller count
     size_t best = 0;
     for (size_t n = 1; n <= nmax; ++n)
-      if (r[n] > r[best]) best = n;
+      if (ORACLE_MUTANT == 10 ? r[n] >= r[best] : r[n] > r[best]) best = n;
+    if (ORACLE_MUTANT == 9 && !hyp.empty()) best = hyp[0].inst.size();  // planted: the globally best hypothesis
     if (rho)
       for (int n = 0; n < rho_cap; ++n) rho[n] = n <= (int)nmax ? r[n] : 0.0;
     for (auto& h : hyp)
@@ -873,6 +879,9 @@ int orc_import(void* hd, int n_inst, const int32_t* lab, const double* m, const 
     for (int j = off[h]; j < off[h + 1]; ++j) o->hyp[h].inst.push_back(idx[j]);
     o->sort_by_label(o->hyp[h].inst);
   }
+  // the hypothesis list is kept in rank order, i.e. by weight descending; an input in another
+  // order is ranked here (stable: equal weights keep the input order)
+  std::stable_sort(o->hyp.begin(), o->hyp.end(), [](const Hyp& a, const Hyp& b) { return a.logw > b.logw; });
   o->births.assign(n_birth, Birth{});
   for (int b = 0; b < n_birth; ++b) {
     o->births[b].lab = {blab[2 * b], blab[2 * b + 1]};

@@ -171,3 +171,71 @@ def adam_step(params, m, v, g, t: int, lr: float, beta1: float = 0.9, beta2: flo
 def logit_threshold(t: float) -> float:
     """sigma(s) < t  <=>  s < log(t / (1 - t)) for 0 < t < 1."""
     return math.log(t / (1.0 - t))
+
+
+# --------------------------------------------------------------------------- comparison aids
+def _near_bf16_midpoint(v, err):
+    """True where a value computed with absolute error up to ``err`` may round to a different
+    bfloat16 value than the exact one: within ``err`` of a rounding midpoint, or of zero."""
+    v = np.asarray(v, np.float64)
+    m, e = np.frexp(np.abs(v))
+    ulp = np.ldexp(1.0, e - 8)  # spacing of bfloat16 values around |v|
+    t = np.abs(v) / ulp
+    mid = (np.floor(t) + 0.5) * ulp
+    return (np.abs(np.abs(v) - mid) <= err) | (np.abs(v) <= err)
+
+
+def _f32_sequential(A, B, bias):
+    """float32 sums over k of A[p, k] * B[j, k] + bias[j] taken in index order (the products of
+    two bfloat16 values are exact in float32); used only to tell exact sums from rounded ones."""
+    A32, B32 = A.astype(np.float32), B.astype(np.float32)
+    acc = np.broadcast_to(bias.astype(np.float32), (A.shape[0], B.shape[0])).copy()
+    for k in range(A.shape[1]):
+        acc = (acc + np.outer(A32[:, k], B32[:, k]).astype(np.float32)).astype(np.float32)
+    return acc.astype(np.float64)
+
+
+def rounding_sensitive(params, norm, X, rel: float = 2e-7) -> np.ndarray:
+    """Samples for which a float32 evaluation of the network may take a different bfloat16
+    rounding (or ReLU) decision than the exact one: some standardised input or hidden
+    pre-activation lies within ``rel`` times the sum of the magnitudes of its terms of a
+    rounding midpoint (or of zero, for the ReLU).  A pre-activation that a float32 sum reaches
+    exactly (products of bfloat16 values are exact in float32) is not sensitive.  These are the
+    samples whose float32 and float64 logits may legitimately differ by one bfloat16 unit of an
+    activation."""
+    p = {k: bf16(v) for k, v in unpack(params).items()}
+    norm = np.asarray(norm, np.float64)
+    X = np.asarray(X, np.float64)
+    u = (X - norm[:N_IN]) / norm[N_IN:]
+    flag = np.any(_near_bf16_midpoint(u, rel * np.abs(u) + 1e-30), axis=1)
+    xs = bf16(u)
+    a1 = xs @ p["W1"].T + p["b1"]
+    s1 = np.abs(xs) @ np.abs(p["W1"]).T + np.abs(p["b1"])
+    inexact1 = _f32_sequential(xs, p["W1"], p["b1"]) != a1
+    flag |= np.any(_near_bf16_midpoint(a1, rel * s1) & inexact1, axis=1)
+    h1 = bf16(np.maximum(a1, 0.0))
+    a2 = h1 @ p["W2"].T + p["b2"]
+    s2 = np.abs(h1) @ np.abs(p["W2"]).T + np.abs(p["b2"])
+    inexact2 = _f32_sequential(h1, p["W2"], p["b2"]) != a2
+    flag |= np.any(_near_bf16_midpoint(a2, rel * s2) & inexact2, axis=1)
+    return flag
+
+
+def grad_abs_terms(params, norm, X, y, w) -> np.ndarray:
+    """For every parameter, the sum over samples of the magnitudes of the terms whose sum is
+    its gradient (the scale of the rounding error of a float32 accumulation)."""
+    y = np.asarray(y, np.float64)
+    w = np.asarray(w, np.float64)
+    s, c = forward(params, norm, X, True)
+    ds = np.abs(w * (1.0 / (1.0 + np.exp(-s)) - y) / w.sum())
+    p = c["p"]
+    g = {}
+    g["w3"] = np.abs(c["h2"]).T @ ds
+    g["b3"] = np.array([ds.sum()])
+    da2 = np.outer(ds, np.abs(p["w3"])) * (c["a2"] > 0)
+    g["W2"] = da2.T @ np.abs(c["h1"])
+    g["b2"] = da2.sum(axis=0)
+    da1 = (da2 @ np.abs(p["W2"])) * (c["a1"] > 0)
+    g["W1"] = da1.T @ np.abs(c["xs"])
+    g["b1"] = da1.sum(axis=0)
+    return pack(g)

@@ -20,23 +20,37 @@ __device__ __forceinline__ float tsum(float v, float* sh) {
   return r;
 }
 
-// one block: normalise the first n weights, keep those >= tau (the first always), renormalise
+// one block: normalise the first n weights, keep the prefix before the first weight below tau
+// (the first is always kept), renormalise.  The rows are in rank order (weight descending),
+// so the prefix is the set of weights >= tau; the maximum is reduced rather than assumed.
 __global__ __launch_bounds__(1024) void k_truncate(int n, float tau, float* logw, int32_t* nkeep) {
   __shared__ float red[32];
-  __shared__ int32_t cnt;
-  const float mx = logw[0];
+  __shared__ int32_t ired[16];
+  float mx = -INFINITY;
+  for (int h = threadIdx.x; h < n; h += blockDim.x) mx = fmaxf(mx, logw[h]);
+  for (int d = kWave / 2; d > 0; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d, kWave));
+  if (lane_id() == 0) red[threadIdx.x / kWave] = mx;
+  __syncthreads();
+  mx = red[0];
+  for (int j = 1; j < (int)(blockDim.x / kWave); ++j) mx = fmaxf(mx, red[j]);
+  __syncthreads();
   float s = 0.0f;
   for (int h = threadIdx.x; h < n; h += blockDim.x) s += __expf(logw[h] - mx);
   s = tsum(s, red);
   const float L = mx + __logf(s);
-  if (threadIdx.x == 0) cnt = 1;
+  // first index h >= 1 whose normalised weight is below tau
+  int first = n;
+  if (tau > 0.0f)
+    for (int h = 1 + threadIdx.x; h < n; h += blockDim.x)
+      if (__expf(logw[h] - L) < tau) {
+        first = h;
+        break;
+      }
+  for (int d = kWave / 2; d > 0; d >>= 1) first = min(first, __shfl_xor(first, d, kWave));
+  if (lane_id() == 0) ired[threadIdx.x / kWave] = first;
   __syncthreads();
-  int mine = 0;
-  for (int h = 1 + threadIdx.x; h < n; h += blockDim.x)
-    if (tau <= 0.0f || __expf(logw[h] - L) >= tau) ++mine;
-  if (mine) atomicAdd(&cnt, mine);
-  __syncthreads();
-  const int keep = cnt;
+  int keep = ired[0];
+  for (int j = 1; j < (int)(blockDim.x / kWave); ++j) keep = min(keep, ired[j]);
   float s2 = 0.0f;
   for (int h = threadIdx.x; h < keep; h += blockDim.x) s2 += __expf(logw[h] - mx);
   s2 = tsum(s2, red + 16);
@@ -52,7 +66,7 @@ void stage_truncate(Ctx& c, int hmax, float tau) {
   GLMB_LAUNCH(k_truncate, 1, 1024, 0, c.s, n, tau, c.logw.as<float>(), scal + 15);
   int32_t keep = 0;
   GLMB_HIP(hipMemcpyAsync(&keep, scal + 15, sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
-  GLMB_HIP(hipStreamSynchronize(c.s));
+  GLMB_HIP(stream_sync(c.s));
   c.nhyp = keep;
 }
 
@@ -132,6 +146,7 @@ using glmb::Ctx;
 using glmb::DInst;
 using glmb::DBirth;
 using glmb::Error;
+using glmb::stream_sync;
 
 namespace {
 
@@ -168,7 +183,8 @@ float log_sum_exp(const std::vector<double>& v) {
 
 void upload_state(Ctx& c, const std::vector<std::pair<int32_t, int32_t>>& labs, const std::vector<DInst>& inst,
                   const std::vector<int32_t>& rows, const std::vector<float>& logw, const std::vector<int32_t>& ntrk,
-                  const std::vector<DBirth>& births, const std::vector<std::pair<int32_t, int32_t>>& blab) {
+                  const std::vector<DBirth>& births, const std::vector<std::pair<int32_t, int32_t>>& blab,
+                  const std::vector<int32_t>* parent = nullptr) {
   hipStream_t s = c.s;
   const int H = (int)logw.size();
   c.slot_lab = labs;
@@ -188,9 +204,9 @@ void upload_state(Ctx& c, const std::vector<std::pair<int32_t, int32_t>>& labs, 
   up(c.ntrk, ntrk.data(), ntrk.size() * sizeof(int32_t));
   up(c.births, births.data(), births.size() * sizeof(DBirth));
   std::vector<int32_t> par(H);
-  for (int h = 0; h < H; ++h) par[h] = h;
+  for (int h = 0; h < H; ++h) par[h] = parent ? (*parent)[h] : h;
   up(c.hparent, par.data(), par.size() * sizeof(int32_t));
-  GLMB_HIP(hipStreamSynchronize(s));
+  GLMB_HIP(stream_sync(s));
 }
 
 }  // namespace
@@ -227,6 +243,10 @@ glmb_status glmb_create(const glmb_params* p, int device, void* stream, glmb_ctx
   x->c.s = (hipStream_t)stream;
   const char* tr = std::getenv("GLMB_TRACE");
   x->c.trace = tr && tr[0] && tr[0] != '0';
+  if (const char* hb = std::getenv("GLMB_REC_HASH_BITS")) {
+    const int bits = std::atoi(hb);
+    if (bits >= 1 && bits < 32) x->c.rec_hash_mask = (1u << bits) - 1u;
+  }
   glmb_status st = guarded(x, [&](Ctx& c) {
     c.ev_ok = true;
     for (auto& e : c.ev) GLMB_HIP(hipEventCreate(&e));
@@ -258,7 +278,7 @@ glmb_status glmb_destroy(glmb_ctx* x) {
                           &c.sb.nd_value, &c.sb.cnt, &c.sb.pre, &c.sb.pre64, &c.sb.flags, &c.sb.map, &c.sb.tmp,
                           &c.sb.tk, &c.sb.tv, &c.sb.keys, &c.sb.vals, &c.sb.sel_node, &c.sb.sel_val, &c.sb.sel_rank, &c.sb.hist,
                           &c.sb.scal, &c.sb.dp, &c.sb.dpc, &c.sb.dpa, &c.sb.cand, &c.prop_w, &c.pcnt, &c.poff, &c.ppre, &c.pu, &c.pi, &c.plogit, &c.slot_r,
-                          &c.slot_part, &c.slot_age, &c.pm_part, &c.pe_part, &c.lz_t, &c.mlp_part, &c.est_buf, &c.ref_b1, &c.ref_opts, &c.ref_top, &c.ref_rest, &c.hopts};
+                          &c.slot_part, &c.slot_age, &c.pm_part, &c.pe_part, &c.lz_t, &c.mlp_part, &c.est_buf, &c.ref_b1, &c.ref_opts, &c.ref_top, &c.ref_rest, &c.hopts, &c.rec_lead};
   for (auto* b : bufs) b->release();
   if (c.age_pin) (void)hipHostFree(c.age_pin);
   if (c.ev_ok)
@@ -310,20 +330,29 @@ glmb_status glmb_import_state(glmb_ctx* x, const glmb_state_host* s) {
     inst[k] = d;
   }
   const int NS = (int)labs.size();
+  // the rows are kept in rank order (weight descending): an input in another order is ranked
+  // here, stably (equal weights keep the input order); hparent names the input position
+  std::vector<int32_t> hord(H);
+  for (int h = 0; h < H; ++h) {
+    const float w = s->hyp_logw[h];
+    if (!(w > -INFINITY) || std::isnan(w) || std::isinf(w)) return fail(x, GLMB_E_ARG, "non-finite hypothesis weight");
+    hord[h] = h;
+  }
+  std::stable_sort(hord.begin(), hord.end(), [&](int32_t a, int32_t b) { return s->hyp_logw[a] > s->hyp_logw[b]; });
   std::vector<int32_t> rows((size_t)H * NS, -1);
   std::vector<int32_t> ntrk(H);
   std::vector<double> lw(H);
-  for (int h = 0; h < H; ++h) {
-    lw[h] = s->hyp_logw[h];
-    if (!(lw[h] > -INFINITY) || std::isnan(lw[h])) return fail(x, GLMB_E_ARG, "non-finite hypothesis weight");
+  for (int r0 = 0; r0 < H; ++r0) {
+    const int h = hord[r0];
+    lw[r0] = s->hyp_logw[h];
     for (int j = s->hyp_off[h]; j < s->hyp_off[h + 1]; ++j) {
       const int u = s->hyp_idx[j];
       if (u < 0 || u >= N) return fail(x, GLMB_E_ARG, "instance index out of range");
-      int32_t& r = rows[(size_t)h * NS + us[u]];
+      int32_t& r = rows[(size_t)r0 * NS + us[u]];
       if (r >= 0) return fail(x, GLMB_E_ARG, "a hypothesis holds a label twice");
       r = nid[u];
     }
-    ntrk[h] = s->hyp_off[h + 1] - s->hyp_off[h];
+    ntrk[r0] = s->hyp_off[h + 1] - s->hyp_off[h];
   }
   const float L = log_sum_exp(lw);
   std::vector<float> logw(H);
@@ -345,7 +374,7 @@ glmb_status glmb_import_state(glmb_ctx* x, const glmb_state_host* s) {
     births[b] = d;
   }
   return guarded(x, [&](Ctx& c) {
-    upload_state(c, labs, inst, rows, logw, ntrk, births, blab);
+    upload_state(c, labs, inst, rows, logw, ntrk, births, blab, &hord);
     c.last_M = -1;
   });
 }
@@ -358,7 +387,7 @@ glmb_status glmb_state_sizes(glmb_ctx* x, int32_t* n_inst, int32_t* n_hyp, int32
     *n_birth = c.nbirth;
     std::vector<int32_t> nt(c.nhyp);
     if (c.nhyp) GLMB_HIP(hipMemcpyAsync(nt.data(), c.ntrk.p, c.nhyp * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
-    GLMB_HIP(hipStreamSynchronize(c.s));
+    GLMB_HIP(stream_sync(c.s));
     int64_t t = 0;
     for (int v : nt) t += v;
     *n_idx = (int32_t)t;
@@ -384,7 +413,7 @@ glmb_status glmb_export_state(glmb_ctx* x, glmb_state_host* o) {
       GLMB_HIP(hipMemcpyAsync(nz.data(), c.inst_nz.p, U * sizeof(int32_t), hipMemcpyDeviceToHost, s));
       GLMB_HIP(hipMemcpyAsync(zz.data(), c.inst_z.p, zz.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     }
-    GLMB_HIP(hipStreamSynchronize(s));
+    GLMB_HIP(stream_sync(s));
     if (o->n_inst < U || o->n_hyp < H || o->n_birth < NB) throw Error{GLMB_E_CAPACITY, "export arrays too small"};
     const int ij[10][2] = {{0, 0}, {0, 1}, {0, 2}, {0, 3}, {1, 1}, {1, 2}, {1, 3}, {2, 2}, {2, 3}, {3, 3}};
     for (int u = 0; u < U; ++u) {
@@ -471,7 +500,7 @@ glmb_status glmb_estimate(glmb_ctx* x, int32_t cap, int32_t* n_out, int32_t* lab
       GLMB_HIP(hipMemcpyAsync(hp.data(), present, NS * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
       GLMB_HIP(hipMemcpyAsync(hm.data(), means, NS * sizeof(float4), hipMemcpyDeviceToHost, c.s));
     }
-    GLMB_HIP(hipStreamSynchronize(c.s));
+    GLMB_HIP(stream_sync(c.s));
     const int n = r[0];
     *n_out = n;
     if (n > cap) {
@@ -494,7 +523,7 @@ glmb_status glmb_estimate(glmb_ctx* x, int32_t cap, int32_t* n_out, int32_t* lab
 glmb_status glmb_stats(glmb_ctx* x, glmb_step_stats* out) {
   if (!x || !out) return GLMB_E_ARG;
   return guarded(x, [&](Ctx& c) {
-    GLMB_HIP(hipStreamSynchronize(c.s));
+    GLMB_HIP(stream_sync(c.s));
     *out = c.stats;
   });
 }
@@ -506,7 +535,7 @@ glmb_status glmb_update_diag(glmb_ctx* x, int32_t H, int32_t M, float* best, flo
     GLMB_HIP(hipMemcpyAsync(best, c.diag_best.p, H * sizeof(float), hipMemcpyDeviceToHost, c.s));
     GLMB_HIP(hipMemcpyAsync(logpi, c.diag_logpi.p, H * sizeof(float), hipMemcpyDeviceToHost, c.s));
     if (M) GLMB_HIP(hipMemcpyAsync(ru, c.diag_ru.p, M * sizeof(float), hipMemcpyDeviceToHost, c.s));
-    GLMB_HIP(hipStreamSynchronize(c.s));
+    GLMB_HIP(stream_sync(c.s));
   });
 }
 
@@ -526,14 +555,14 @@ glmb_status glmb_update_theta(glmb_ctx* x, int32_t n_hyp, int32_t M, int32_t* th
     if (UP) GLMB_HIP(hipMemcpyAsync(pinst.data(), c.inst2.p, (size_t)UP * sizeof(DInst), hipMemcpyDeviceToHost, s));
     GLMB_HIP(hipMemcpyAsync(par.data(), c.hparent.p, n * 4, hipMemcpyDeviceToHost, s));
     GLMB_HIP(hipMemcpyAsync(doff.data(), c.dev_off.p, (n + 1) * 4, hipMemcpyDeviceToHost, s));
-    GLMB_HIP(hipStreamSynchronize(s));
+    GLMB_HIP(stream_sync(s));
     for (int u = 0; u < UP; ++u) psrc[u] = pinst[u].src;
     const int nd = doff[n];
     std::vector<int32_t> di(nd), dn(nd);
     if (nd) {
       GLMB_HIP(hipMemcpyAsync(di.data(), c.dev_i.p, nd * 4, hipMemcpyDeviceToHost, s));
       GLMB_HIP(hipMemcpyAsync(dn.data(), c.dev_slot.p, nd * 4, hipMemcpyDeviceToHost, s));
-      GLMB_HIP(hipStreamSynchronize(s));
+      GLMB_HIP(stream_sync(s));
     }
     for (int h = 0; h < n; ++h) {
       const int ph = par[h];
@@ -561,7 +590,7 @@ glmb_status glmb_set_proposal(glmb_ctx* x, const float* params, const float* nor
   return guarded(x, [&](Ctx& c) {
     float* w = glmb::need<float>(c.prop_w, glmb::kNParam);
     GLMB_HIP(hipMemcpyAsync(w, params, glmb::kNParam * sizeof(float), hipMemcpyDeviceToDevice, c.s));
-    GLMB_HIP(hipStreamSynchronize(c.s));
+    GLMB_HIP(stream_sync(c.s));
     std::memcpy(c.prop_norm, norm, sizeof(c.prop_norm));
     c.prop_thr = (float)std::log((double)threshold / (1.0 - (double)threshold));
     c.prop_t = threshold;

@@ -15,6 +15,7 @@ struct glmb_batch {
   int device = 0;
   std::vector<glmb_ctx*> ctx;
   std::vector<hipStream_t> streams;
+  hipEvent_t ready = nullptr;  // recorded on the caller's stream at every step
   int workers = 1;
   bool ljf = true;
   std::vector<double> cost;  // cost estimate of every scene for the next step
@@ -49,6 +50,10 @@ glmb_status glmb_batch_create(int32_t n, const glmb_params* params, int device, 
       glmb_batch_destroy(b);
       return GLMB_E_DEVICE;
     }
+  if (hipEventCreateWithFlags(&b->ready, hipEventDisableTiming) != hipSuccess) {
+    glmb_batch_destroy(b);
+    return GLMB_E_DEVICE;
+  }
   b->ctx.resize(n, nullptr);
   b->cost.assign(n, 0.0);
   for (int i = 0; i < n; ++i) {
@@ -71,6 +76,7 @@ glmb_status glmb_batch_destroy(glmb_batch* b) {
     if (x) glmb_destroy(x);
   for (auto s : b->streams)
     if (s) (void)hipStreamDestroy(s);
+  if (b->ready) (void)hipEventDestroy(b->ready);
   delete b;
   return GLMB_OK;
 }
@@ -88,7 +94,7 @@ glmb_status glmb_batch_scene(glmb_batch* b, int32_t scene, glmb_ctx** out) {
   return GLMB_OK;
 }
 
-glmb_status glmb_batch_step(glmb_batch* b, int32_t k, const float* z, const int32_t* z_off) {
+glmb_status glmb_batch_step(glmb_batch* b, int32_t k, const float* z, const int32_t* z_off, void* caller_stream) {
   if (!b || !z_off) return GLMB_E_ARG;
   const int n = (int)b->ctx.size();
   if (z_off[0] != 0) return bfail(b, GLMB_E_ARG, "z_off[0] must be 0");
@@ -104,6 +110,14 @@ glmb_status glmb_batch_step(glmb_batch* b, int32_t k, const float* z, const int3
   }
   if (b->ljf)
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) { return b->cost[x] > b->cost[y]; });
+  // the detections may still be in flight on the caller's stream: every worker stream waits
+  // for the work queued there before its first launch
+  if (hipSetDevice(b->device) != hipSuccess) return bfail(b, GLMB_E_DEVICE, "hipSetDevice failed");
+  if (hipEventRecord(b->ready, (hipStream_t)caller_stream) != hipSuccess)
+    return bfail(b, GLMB_E_DEVICE, "hipEventRecord on the caller's stream failed");
+  for (int w = 0; w < std::min(b->workers, n); ++w)
+    if (hipStreamWaitEvent(b->streams[w], b->ready, 0) != hipSuccess)
+      return bfail(b, GLMB_E_DEVICE, "hipStreamWaitEvent failed");
   std::atomic<int> next{0};
   std::atomic<int> first_bad{-1};
   std::vector<glmb_status> st(n, GLMB_OK);

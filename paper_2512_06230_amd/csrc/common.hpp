@@ -39,6 +39,13 @@ struct Error {
 
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// Host waits on a stream, counted per host thread (the update reports how many it made).
+inline thread_local int64_t g_stream_syncs = 0;
+inline hipError_t stream_sync(hipStream_t s) {
+  ++g_stream_syncs;
+  return hipStreamSynchronize(s);
+}
+
 // Growable device buffer (contents are not preserved on growth unless asked).
 struct DevBuf {
   void* p = nullptr;
@@ -53,7 +60,7 @@ struct DevBuf {
     if (hipMalloc(&q, nb) != hipSuccess) throw Error{GLMB_E_NOMEM, "hipMalloc of " + std::to_string(nb) + " bytes failed"};
     if (keep && p && bytes) {
       GLMB_HIP(hipMemcpyAsync(q, p, bytes, hipMemcpyDeviceToDevice, s));
-      GLMB_HIP(hipStreamSynchronize(s));
+      GLMB_HIP(stream_sync(s));
     }
     if (p) {
       (void)hipDeviceSynchronize();  // queued work may still use the old allocation
@@ -138,6 +145,7 @@ struct Selected {
   int32_t* nd_h;          // parent hypothesis
   float* nd_value;
   int levels, nodes;
+  int form;               // 0: one workgroup, 1: cooperative whole-GPU launch, 2: multi-kernel levels
 };
 struct SelectBufs {
   DevBuf nd_parent, nd_item, nd_h, nd_value, nd_bloom, cnt, pre, pre64, flags, map, tmp, tk, tv, keys, vals, sel_node,

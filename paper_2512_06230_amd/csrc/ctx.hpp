@@ -70,6 +70,8 @@ struct Ctx {
   bool sel_multi[2] = {false, false};  // per search site (prediction, update): start on the whole GPU
   bool coop_ok = true;  // cooperative launches allowed (they run one at a time on a device)
   int LW = 1;  // detection-set mask width (32-bit words) of the last gate
+  uint32_t rec_hash_mask = 0xffffffffu;  // fingerprint bits of the (instance, detection set) records
+  DevBuf rec_lead;                       // collision path: leader position of every record
 
   // ---- learned pair proposal
   bool prop_loaded = false, prop_on = false, prop_measure = false;

@@ -325,7 +325,7 @@ void stage_predict(Ctx& c, int k) {
   std::vector<DBirth> hb(NB);
   if (NB) {
     GLMB_HIP(hipMemcpyAsync(hb.data(), c.births.p, (size_t)NB * sizeof(DBirth), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(hipStreamSynchronize(s));
+    GLMB_HIP(stream_sync(s));
   }
   std::vector<float> bd(NB + 1, 0.0f);
   std::vector<int32_t> by(NB + 1, 0);
@@ -371,7 +371,7 @@ void stage_predict(Ctx& c, int k) {
   scan_excl(icount, itoff, H, itoff + H, c.tmp, s);
   int32_t nitem = 0;
   GLMB_HIP(hipMemcpyAsync(&nitem, itoff + H, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipStreamSynchronize(s));
+  GLMB_HIP(stream_sync(s));
   float* itd = need<float>(c.it_delta, (int64_t)nitem + 1);
   int32_t* itg = need<int32_t>(c.it_group, (int64_t)nitem + 1);
   GLMB_LAUNCH(k_pitems, H, 256, 0, s, H, nbs, nlt, SW, c.rows.as<int32_t>(), V, dt_, dbs, dbg, t0,
@@ -410,7 +410,7 @@ void stage_predict(Ctx& c, int k) {
   scan_excl(islead, lpre, n, tot, c.tmp, s);
   int32_t nh = 0;
   GLMB_HIP(hipMemcpyAsync(&nh, tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipStreamSynchronize(s));
+  GLMB_HIP(stream_sync(s));
   uint64_t* lk = need<uint64_t>(c.rec_keys, nh + 1);
   uint32_t* lv = need<uint32_t>(c.rec_vals, nh + 1);
   int rb = 0;  // ranks are positions among the search's candidates, below its node count
@@ -436,7 +436,7 @@ void stage_predict(Ctx& c, int k) {
   GLMB_HIP(hipMemcpyAsync(hsu.data(), sused, (size_t)(W2 + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   GLMB_HIP(hipMemcpyAsync(&cnts[0], spre + W2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   GLMB_HIP(hipMemcpyAsync(&cnts[1], upre + U2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipStreamSynchronize(s));
+  GLMB_HIP(stream_sync(s));
   const int NS2 = cnts[0], Unew = cnts[1];
   int32_t* frows = need<int32_t>(c.prev_rows, (int64_t)nh * NS2 + 1);
   int32_t* fnt = need<int32_t>(c.hp_map, nh + 1);
@@ -465,7 +465,7 @@ void stage_predict(Ctx& c, int k) {
   c.nhyp = nh;
   c.nbirth = 0;
   c.birth_lab.clear();
-  GLMB_HIP(hipStreamSynchronize(s));
+  GLMB_HIP(stream_sync(s));
 }
 
 }  // namespace glmb

@@ -475,7 +475,7 @@ namespace {
 template <class T> T read_one(hipStream_t s, const T* p) {
   T v;
   GLMB_HIP(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipStreamSynchronize(s));
+  GLMB_HIP(stream_sync(s));
   return v;
 }
 
@@ -576,7 +576,7 @@ void proposal_lost(Ctx& c, int k, const float* zin, int M, const float* thr_prob
   GLMB_LAUNCH(k_lost_final, 1, 1024, 0, s, H, T, lzf, dlt, out);
   float h[kMaxThr];
   GLMB_HIP(hipMemcpyAsync(h, out, T * sizeof(float), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipStreamSynchronize(s));
+  GLMB_HIP(stream_sync(s));
   for (int j = 0; j < T; ++j) lost[j] = h[j];
   c.last_M = -1;  // the update diagnostics buffers no longer describe an update
 }
@@ -604,7 +604,7 @@ int proposal_features(Ctx& c, int k, const float* zin, int M, int cap, float* fe
                      c.phi.as<float>(), c.poff.as<int32_t>(), c.pi.as<int32_t>(), n, pm, pe);
   GLMB_HIP(hipGetLastError());
   GLMB_LAUNCH(k_pair_target, cdiv(n, T), T, 0, s, n, U, nch, c.pu.as<int32_t>(), pm, pe, target, weight);
-  GLMB_HIP(hipStreamSynchronize(s));
+  GLMB_HIP(stream_sync(s));
   return n;
 }
 

@@ -1199,14 +1199,14 @@ void dp_bound_items(const SelectIn& in, SelectBufs& b, hipStream_t s) {
 bool dp_bound_refined(SelectBufs& b, hipStream_t s) {
   int32_t refined = 0;
   GLMB_HIP(hipMemcpyAsync(&refined, &b.dp.as<DpState>()->refined, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipStreamSynchronize(s));
+  GLMB_HIP(stream_sync(s));
   return refined != 0;
 }
 
 void dp_bound_trace(SelectBufs& b, hipStream_t s) {
   DpState h{};
   GLMB_HIP(hipMemcpyAsync(&h, b.dp.p, sizeof(DpState), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipStreamSynchronize(s));
+  GLMB_HIP(stream_sync(s));
   std::fprintf(stderr, "[glmb] select.refine t0 %.7g tref %.7g vmax %.7g refined %d\n", h.t0, h.tref, h.vmax,
                h.refined);
   std::fflush(stderr);
@@ -1245,7 +1245,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
   int32_t hs[8];
   auto read = [&](int n) {
     GLMB_HIP(hipMemcpyAsync(hs, scal, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(hipStreamSynchronize(s));
+    GLMB_HIP(stream_sync(s));
   };
   // Small searches run in one workgroup (no host round trip per level).  A search that
   // outgrows kBlockNodes continues on the whole GPU (multi-kernel levels below); the call
@@ -1258,7 +1258,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
                 std::min(cap, kBlockNodes), A.p, A.i, A.h, A.v, A.b, t, scal + 24,
                 need<int32_t>(b.cand, std::min(cap, kBlockNodes) + 1));
     GLMB_HIP(hipMemcpyAsync(hs, scal + 24, 5 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(hipStreamSynchronize(s));
+    GLMB_HIP(stream_sync(s));
     used = hs[0];
     levels = hs[1];
     fast = hs[2] == 0;
@@ -1307,7 +1307,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
                                                       kCoopLds, s);
       if (e == hipSuccess) {
         GLMB_HIP(hipMemcpyAsync(hs, scal + 16, 5 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        GLMB_HIP(hipStreamSynchronize(s));
+        GLMB_HIP(stream_sync(s));
         used = hs[0];
         levels = hs[1];
         tr("coop", used, hs[4]);
@@ -1350,7 +1350,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
     // t = max(t, t2)
     float th[2];
     GLMB_HIP(hipMemcpyAsync(th, (float*)(scal + 8), 2 * sizeof(float), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(hipStreamSynchronize(s));
+    GLMB_HIP(stream_sync(s));
     if (!(th[1] > th[0])) return false;
     GLMB_HIP(hipMemcpyAsync(t, t2, sizeof(float), hipMemcpyDeviceToDevice, s));
     int32_t* fl = need<int32_t>(b.flags, used + 1);
@@ -1361,7 +1361,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
                 B.b);
     GLMB_LAUNCH(k_remap_pos, 1, 64, 0, s, pre, scal, used, level_first, *cursor, level_end, scal + 4);
     GLMB_HIP(hipMemcpyAsync(hs, scal, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(hipStreamSynchronize(s));
+    GLMB_HIP(stream_sync(s));
     used = hs[0];
     level_first = hs[4];
     *cursor = hs[5];
@@ -1389,7 +1389,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
       scan_excl64(cnt, pre, nlev, tot64, b.tmp, s);
       int64_t total = 0;
       GLMB_HIP(hipMemcpyAsync(&total, tot64, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-      GLMB_HIP(hipStreamSynchronize(s));
+      GLMB_HIP(stream_sync(s));
       if (total == 0) break;
       // Expand at most about as many nodes as the store holds (at least 2K) before the
       // threshold is raised again: a raised threshold prunes the rest of the level.
@@ -1400,7 +1400,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
       auto cut = [&](int64_t r) {
         GLMB_LAUNCH(k_cut, 1, 64, 0, s, pre, cnt, nlev, r, scal + 1);
         GLMB_HIP(hipMemcpyAsync(hs, scal, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        GLMB_HIP(hipStreamSynchronize(s));
+        GLMB_HIP(stream_sync(s));
         m = hs[1];
         te = hs[2];
       };
@@ -1477,6 +1477,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
   out.nd_value = A.v;
   out.levels = levels;
   out.nodes = used;
+  out.form = fast ? 0 : (coop ? 1 : 2);
   return GLMB_OK;
 }
 

@@ -21,7 +21,7 @@
 
 namespace glmb {
 
-enum : uint32_t { ERR_BIRTH = 1, ERR_DEPTH = 4, ERR_NAN = 8, ERR_COLL = 16 };
+enum : uint32_t { ERR_BIRTH = 1, ERR_DEPTH = 4, ERR_NAN = 8 };
 
 // ------------------------------------------------------------------ U0 / U1
 __global__ void k_z_in(const float* zin, int M, float2* z, uint32_t* errf) {
@@ -1038,33 +1038,53 @@ __global__ void k_rec_copy(int n, int LW, const int32_t* u0, const uint32_t* m0,
   u1[k] = u0[k];
   for (int w = 0; w < LW; ++w) m1[(size_t)k * LW + w] = m0[(size_t)k * LW + w];
 }
-__global__ void k_rec_keys(int n, int LW, const int32_t* ru, const uint32_t* rm, uint64_t* keys, uint32_t* vals) {
+__global__ void k_rec_keys(int n, int LW, uint32_t hmask, const int32_t* ru, const uint32_t* rm, uint64_t* keys,
+                           uint32_t* vals) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  keys[k] = ((uint64_t)(uint32_t)ru[k] << 32) | mask_hash(rm + (size_t)k * LW, LW);
+  keys[k] = ((uint64_t)(uint32_t)ru[k] << 32) | (mask_hash(rm + (size_t)k * LW, LW) & hmask);
   vals[k] = (uint32_t)k;
 }
+__device__ __forceinline__ bool rec_equal(int LW, const int32_t* ru, const uint32_t* rm, uint32_t a, uint32_t b) {
+  bool eq = ru[a] == ru[b];
+  for (int w = 0; w < LW && eq; ++w) eq = rm[(size_t)a * LW + w] == rm[(size_t)b * LW + w];
+  return eq;
+}
+// distinct records in (instance, fingerprint) order: a record starts a new id unless it equals
+// its predecessor.  Two different detection sets of one instance with equal fingerprints make
+// a run in which equal records need not be adjacent; such a run is flagged (*ncoll) and
+// k_rec_resolve then assigns the ids by full comparison.
 __global__ void k_rec_unique(int n, int LW, const uint64_t* keys, const uint32_t* vals, const int32_t* ru,
-                             const uint32_t* rm, int32_t* flag, uint32_t* errf) {
+                             const uint32_t* rm, int32_t* flag, int32_t* ncoll) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   bool nw = p == 0 || keys[p] != keys[p - 1];
-  if (!nw) {
-    const uint32_t a = vals[p], b = vals[p - 1];
-    bool eq = ru[a] == ru[b];
-    for (int w = 0; w < LW && eq; ++w) eq = rm[(size_t)a * LW + w] == rm[(size_t)b * LW + w];
-    if (!eq) {
-      nw = true;
-      atomicOr(errf, ERR_COLL);  // equal fingerprints, different sets: refuse rather than guess
-    }
+  if (!nw && !rec_equal(LW, ru, rm, vals[p], vals[p - 1])) {
+    nw = true;
+    atomicAdd(ncoll, 1);
   }
   flag[p] = nw ? 1 : 0;
 }
-__global__ void k_rec_ids(int n, const uint32_t* vals, const int32_t* flag, const int32_t* pre, int32_t* rec_id,
-                          int32_t* rep) {
+// collision path: the leader of a record is the first record of its fingerprint run that
+// equals it (full comparison); only leaders start an id
+__global__ void k_rec_resolve(int n, int LW, const uint64_t* keys, const uint32_t* vals, const int32_t* ru,
+                              const uint32_t* rm, int32_t* flag, int32_t* lead) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
-  const int id = pre[p] + flag[p] - 1;
+  int r0 = p;
+  while (r0 > 0 && keys[r0 - 1] == keys[p]) --r0;
+  int q = r0;
+  while (q < p && !rec_equal(LW, ru, rm, vals[q], vals[p])) ++q;
+  lead[p] = q;
+  flag[p] = q == p ? 1 : 0;
+}
+// id of every record (pre: exclusive scan of the leader flags); lead == null: equal records
+// are adjacent, so a record's leader is the last flagged one at or before it
+__global__ void k_rec_ids(int n, const uint32_t* vals, const int32_t* flag, const int32_t* pre, const int32_t* lead,
+                          int32_t* rec_id, int32_t* rep) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const int id = lead ? pre[lead[p]] : pre[p] + flag[p] - 1;
   rec_id[vals[p]] = id;
   if (flag[p]) rep[id] = (int32_t)vals[p];
 }
@@ -1272,7 +1292,7 @@ namespace {
 template <class T> T read1(hipStream_t s, const T* p) {
   T v;
   GLMB_HIP(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipStreamSynchronize(s));
+  GLMB_HIP(stream_sync(s));
   return v;
 }
 void check_err(hipStream_t s, const uint32_t* errf) {
@@ -1280,7 +1300,6 @@ void check_err(hipStream_t s, const uint32_t* errf) {
   if (e & ERR_NAN) throw Error{GLMB_E_ARG, "detections contain NaN or infinity"};
   if (e & ERR_BIRTH) throw Error{GLMB_E_CAPACITY, "more than 4096 birth clusters in one scan"};
   if (e & ERR_DEPTH) throw Error{GLMB_E_CAPACITY, "a kept child deviates in more than 48 detections"};
-  if (e & ERR_COLL) throw Error{GLMB_E_STATE, "detection-set fingerprint collision"};
 }
 }  // namespace
 
@@ -1426,6 +1445,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   // [11] retained, [12] scratch total, [13] births, [14] exceptions, [16..17] dense triples (u64),
   // [18] pairs removed by the proposal
   c.stats = glmb_step_stats{};
+  const int64_t syncs0 = g_stream_syncs;
   c.stats.n_hyp_in = H;
   c.stats.n_meas = M;
   c.stats.n_inst_in = U;
@@ -1515,7 +1535,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     int32_t hv[2];
     GLMB_HIP(hipMemcpyAsync(hv, ioff + ncell, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     GLMB_HIP(hipMemcpyAsync(hv + 1, maxlen, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(hipStreamSynchronize(s));
+    GLMB_HIP(stream_sync(s));
     const int nitem = hv[0];
     float* itd0 = need<float>(c.it_delta, 2 * (int64_t)nitem);
     int32_t* itg0 = need<int32_t>(c.it_group, 2 * (int64_t)nitem);
@@ -1594,7 +1614,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   int32_t cnt2[2];  // deviations of the kept children, retained parents: one round trip
   GLMB_HIP(hipMemcpyAsync(&cnt2[0], doff + nk, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   GLMB_HIP(hipMemcpyAsync(&cnt2[1], tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipStreamSynchronize(s));
+  GLMB_HIP(stream_sync(s));
   const int ndev = cnt2[0], np = cnt2[1];
   int32_t* devi = need<int32_t>(c.dev_i, ndev);
   int32_t* devn = need<int32_t>(c.dev_slot, 2 * (int64_t)ndev);
@@ -1636,7 +1656,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   GLMB_HIP(hipMemcpyAsync(&cnt3[0], nexc, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   GLMB_HIP(hipMemcpyAsync(&cnt3[1], moff + nk, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   GLMB_HIP(hipMemcpyAsync(&cnt3[2], tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipStreamSynchronize(s));
+  GLMB_HIP(stream_sync(s));
   int ne = cnt3[0];
   const int nm = cnt3[1], nd = cnt3[2];
   if (ne > ecap) {  // grow and redo
@@ -1677,21 +1697,38 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
               (const int32_t*)(rec_b + nd + ne), rec_u + nd + ne, rec_m + (size_t)(nd + ne) * LW);
   uint64_t* rk = need<uint64_t>(c.rec_keys, R + 1);
   uint32_t* rv = need<uint32_t>(c.rec_vals, R + 1);
-  GLMB_LAUNCH(k_rec_keys, cdiv(R, T), T, 0, s, R, LW, rec_u, rec_m, rk, rv);
+  GLMB_LAUNCH(k_rec_keys, cdiv(R, T), T, 0, s, R, LW, c.rec_hash_mask, rec_u, rec_m, rk, rv);
   int ub = 0;
   while ((1 << ub) < U) ++ub;
   sort_pairs(rk, rv, R, 0, 32 + ((ub + 7) / 8) * 8, c.tk, c.tv, c.tmp, s);
   int32_t* rfl = need<int32_t>(c.flags, R + 1);
   int32_t* rpre = need<int32_t>(c.pre, R + 1);
-  GLMB_LAUNCH(k_rec_unique, cdiv(R, T), T, 0, s, R, LW, rk, rv, rec_u, rec_m, rfl, errf);
+  int32_t* ncoll = scal + 24;  // tot (scal + 12) and this count come back in one round trip
+  GLMB_LAUNCH(k_fill_i32, 1, T, 0, s, ncoll, 1, 0);
+  GLMB_LAUNCH(k_rec_unique, cdiv(R, T), T, 0, s, R, LW, rk, rv, rec_u, rec_m, rfl, ncoll);
   scan_excl(rfl, rpre, R, tot, c.tmp, s);
-  const int nnew = read1(s, tot);
+  int32_t* rlead = nullptr;
+  int nnew = 0;
+  {
+    int32_t hv2[13];
+    GLMB_HIP(hipMemcpyAsync(hv2, tot, 13 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GLMB_HIP(stream_sync(s));
+    nnew = hv2[0];
+    if (hv2[12] > 0) {  // fingerprint collisions: ids by full comparison within each run
+      trace(c, "update.fingerprint_collisions", hv2[12]);
+      rlead = need<int32_t>(c.rec_lead, R + 1);
+      GLMB_LAUNCH(k_rec_resolve, cdiv(R, T), T, 0, s, R, LW, rk, rv, rec_u, rec_m, rfl, rlead);
+      scan_excl(rfl, rpre, R, tot, c.tmp, s);
+      nnew = read1(s, tot);
+    }
+    c.stats.rec_collisions = hv2[12];
+  }
   int32_t* rec_id = need<int32_t>(c.ids, (int64_t)R + np + 2);
   int32_t* rep = need<int32_t>(c.bt, nnew + 1);
   // eoff shares c.ids with rec_id: place it behind the record ids again
   int32_t* eoff2 = rec_id + R;
   GLMB_LAUNCH(k_exc_off, cdiv(np + 1, T), T, 0, s, np, ne, ea, eoff2);
-  GLMB_LAUNCH(k_rec_ids, cdiv(R, T), T, 0, s, R, rv, rfl, rpre, rec_id, rep);
+  GLMB_LAUNCH(k_rec_ids, cdiv(R, T), T, 0, s, R, rv, rfl, rpre, (const int32_t*)rlead, rec_id, rep);
   trace(c, "update.kalman", R, nnew);
   DInst* ninst = (DInst*)need<uint8_t>(c.inst2, (int64_t)(nnew + 1) * sizeof(DInst));
   int32_t* onz = need<int32_t>(c.inst_nz, nnew + 1);
@@ -1730,7 +1767,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   check_err(s, errf);
   int32_t hs[19];
   GLMB_HIP(hipMemcpyAsync(hs, scal, 19 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipStreamSynchronize(s));
+  GLMB_HIP(stream_sync(s));
   uint64_t ng, no;
   std::memcpy(&ng, hs + 2, 8);
   std::memcpy(&no, hs + 4, 8);
@@ -1764,11 +1801,13 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   c.stats.dense_triples = (int64_t)dense;
   c.stats.search_nodes = sel.nodes;
   c.stats.search_levels = sel.levels;
+  c.stats.search_form = sel.form;
   c.stats.n_births = c.nbirth;
   c.stats.retained_mass = std::exp((double)ret);
   c.stats.lost_mass = lost;
   c.stats.pairs_removed = hs[18];
-  GLMB_HIP(hipStreamSynchronize(s));
+  GLMB_HIP(stream_sync(s));
+  c.stats.host_syncs = (int32_t)(g_stream_syncs - syncs0);
   if (c.ev_ok) {
     const int a[6] = {0, 1, 2, 3, 4, 0}, b[6] = {1, 2, 3, 4, 5, 5};
     for (int j = 0; j < 6; ++j) {

@@ -54,7 +54,9 @@ class StepStats(ctypes.Structure):
                 ("dense_triples", ctypes.c_int64), ("search_nodes", ctypes.c_int32),
                 ("search_levels", ctypes.c_int32), ("n_births", ctypes.c_int32),
                 ("retained_mass", ctypes.c_double), ("lost_mass", ctypes.c_double),
-                ("pairs_removed", ctypes.c_int32), ("stage_ms", ctypes.c_float * 6)]
+                ("pairs_removed", ctypes.c_int32), ("stage_ms", ctypes.c_float * 6),
+                ("rec_collisions", ctypes.c_int32), ("host_syncs", ctypes.c_int32),
+                ("search_form", ctypes.c_int32)]
 
 
 class BatchStats(ctypes.Structure):
@@ -104,7 +106,7 @@ def load_library(path: str = LIB_PATH):
     L.glmb_batch_destroy.argtypes = [vp]
     L.glmb_batch_set_schedule.argtypes = [vp, ctypes.c_int32, ctypes.c_int32]
     L.glmb_batch_scene.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(vp)]
-    L.glmb_batch_step.argtypes = [vp, ctypes.c_int32, vp, _I]
+    L.glmb_batch_step.argtypes = [vp, ctypes.c_int32, vp, _I, vp]
     L.glmb_batch_stats_get.argtypes = [vp, ctypes.POINTER(BatchStats)]
     L.glmb_batch_last_error.argtypes = [vp]
     for name in EXPORTS:
@@ -415,8 +417,9 @@ class Batch:
         if off.shape[0] != self.n + 1:
             raise ValueError("z_off must hold n + 1 offsets")
         self._z_keep = z
-        self._check(self._L.glmb_batch_step(self._b, int(k), ctypes.c_void_p(z.data_ptr()), _ip(off)),
-                    "glmb_batch_step")
+        stream = t.cuda.current_stream(z.device).cuda_stream  # where z was written
+        self._check(self._L.glmb_batch_step(self._b, int(k), ctypes.c_void_p(z.data_ptr()), _ip(off),
+                                            ctypes.c_void_p(stream)), "glmb_batch_step")
 
     def stats(self) -> dict:
         s = BatchStats()

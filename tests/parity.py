@@ -88,21 +88,46 @@ def track_densities(out: dict, h: int) -> dict:
     return res
 
 
+def _rows_by_label(out: dict, hs):
+    """Instances of hypotheses ``hs`` in label order: (row ids, labels [n,2], instances [n])."""
+    off = np.asarray(out["hyp_off"])
+    lab = np.asarray(out["inst_lab"]).reshape(-1, 2)
+    rid, ins = [], []
+    for r, h in enumerate(hs):
+        u = np.asarray(out["hyp_idx"][off[h]:off[h + 1]])
+        key = lab[u, 0].astype(np.int64) * (1 << 32) + lab[u, 1].astype(np.int64)
+        u = u[np.argsort(key, kind="stable")]
+        rid.append(np.full(len(u), r))
+        ins.append(u)
+    rid = np.concatenate(rid) if rid else np.zeros(0, np.int64)
+    ins = np.concatenate(ins).astype(np.int64) if ins else np.zeros(0, np.int64)
+    return rid, lab[ins] if len(ins) else np.zeros((0, 2), np.int32), ins
+
+
 def compare_densities(out_o, ids_o, out_g, ids_g, skip_parents=frozenset(), limit=None):
+    """Track densities of every hypothesis present on both sides (or the first ``limit``):
+    same labels, and means and covariances of each (oracle instance, GPU instance) pair met
+    within the tolerance.  Returns the number of hypotheses compared."""
     pos_g = {k: h for h, k in enumerate(ids_g)}
-    n = 0
-    for ho, k in enumerate(ids_o):
-        if k not in pos_g or k[0] in skip_parents:
-            continue
-        do = track_densities(out_o, ho)
-        dg = track_densities(out_g, pos_g[k])
-        assert do.keys() == dg.keys(), ("track labels differ", k)
-        for lab in do:
-            mo, Po = do[lab]
-            mg, Pg = dg[lab]
-            assert np.all(np.abs(mg - mo) <= tol(mo)), ("mean", k, lab, mg, mo)
-            assert np.all(np.abs(Pg - Po) <= tol(Po)), ("covariance", k, lab, Pg, Po)
-        n += 1
-        if limit and n >= limit:
-            break
-    return n
+    ho, hg = [], []
+    for h, k in enumerate(ids_o):
+        if k in pos_g and k[0] not in skip_parents:
+            ho.append(h)
+            hg.append(pos_g[k])
+            if limit and len(ho) >= limit:
+                break
+    if not ho:
+        return 0
+    ro, lo, uo = _rows_by_label(out_o, ho)
+    rg, lg, ug = _rows_by_label(out_g, hg)
+    assert ro.shape == rg.shape and np.array_equal(ro, rg) and np.array_equal(lo, lg), "track labels differ"
+    pairs = np.unique(np.stack([uo, ug], axis=1), axis=0)
+    mo = np.asarray(out_o["inst_m"], np.float64)[pairs[:, 0]]
+    mg = np.asarray(out_g["inst_m"], np.float64)[pairs[:, 1]]
+    Po = np.asarray(out_o["inst_P"], np.float64)[pairs[:, 0]]
+    Pg = np.asarray(out_g["inst_P"], np.float64)[pairs[:, 1]]
+    bm = np.abs(mg - mo) > tol(mo)
+    assert not bm.any(), ("mean", pairs[np.nonzero(bm.any(1))[0][:3]], mg[bm][:4], mo[bm][:4])
+    bP = np.abs(Pg - Po) > tol(Po)
+    assert not bP.any(), ("covariance", pairs[np.nonzero(bP.any(1))[0][:3]], Pg[bP][:4], Po[bP][:4])
+    return len(ho)

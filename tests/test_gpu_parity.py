@@ -69,7 +69,9 @@ def check_update(state, z, p, k=0, full_density=True):
     ids_o = pt.update_ids(out_o, out_o["theta"])
     ids_g = pt.update_ids(out_g, th_g)
     matched = pt.compare_sets(ids_o, out_o["hyp_logw"], ids_g, out_g["hyp_logw"], skip)
-    pt.compare_densities(out_o, ids_o, out_g, ids_g, skip, limit=None if full_density else 200)
+    nd = pt.compare_densities(out_o, ids_o, out_g, ids_g, skip, limit=None if full_density else 200)
+    stats["densities_compared"] = nd
+    stats["unmatched"] = len(ids_o) - matched
     # births for the next scan (skip when a clutter probability sits at the seed threshold)
     if not skip and np.all(np.abs(d_o["ru"] - p["birth_ru_max"]) > 1e-3):
         assert out_g["birth_lab"].tolist() == out_o["birth_lab"].tolist()
@@ -167,8 +169,8 @@ def test_scene_c2(torch_cuda):
 
 def test_full_size_step(torch_cuda):
     """The benchmarked workload (N=500 objects, H_max=1e4, clutter 100): one prediction and one
-    update from a state the oracle produced, compared hypothesis by hypothesis (densities of
-    the first 200 matched hypotheses)."""
+    update from a state the oracle produced, compared hypothesis by hypothesis (the track
+    densities of every hypothesis found on both sides)."""
     spec = sc.spec_for("c5")
     scene = sc.make_scene(spec, n_steps=2)
     p = sc.filter_params(spec, 10000, 0.0)
@@ -181,13 +183,40 @@ def test_full_size_step(torch_cuda):
     o.import_state(post)
     o.predict(1)
     pred = to_f32_state(o.export_state())
-    matched, stats, out_o, out_g = check_update(pred, scene.meas[1], p, 1, full_density=False)
+    matched, stats, out_o, out_g = check_update(pred, scene.meas[1], p, 1)
+    print("full size: %d of %d hypotheses matched (%d only near the cut), densities of %d compared"
+          % (matched, len(out_o["hyp_logw"]), stats["unmatched"], stats["densities_compared"]), flush=True)
     assert len(out_g["hyp_logw"]) == 10000 and matched > 9000, matched
+    assert stats["densities_compared"] == matched
 
 
 @pytest.mark.slow
 def test_scene_c3_n100(torch_cuda):
     assert _scene_parity("c3:100", 3, 1000, 0.0, warm=True) > 0
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("n_obj,h_max", [(250, 10000), (100, 100000)])
+def test_sweep_points_one_step(torch_cuda, n_obj, h_max):
+    """Points of the scaling sweep (N objects, clutter 0.2 N, 100x100 m): one prediction and one
+    update from a state the oracle produced, compared hypothesis by hypothesis."""
+    spec = sc.spec_for("c3:%d" % n_obj)
+    scene = sc.make_scene(spec, n_steps=2)
+    p = sc.filter_params(spec, h_max, 0.0)
+    o = Oracle(p)
+    o.import_state(sc.warm_start_state(scene))
+    o.predict(0)
+    o.update(0, scene.meas[0])
+    post = to_f32_state(o.export_state())
+    check_predict(post, p, 1)
+    o.import_state(post)
+    o.predict(1)
+    pred = to_f32_state(o.export_state())
+    matched, stats, out_o, out_g = check_update(pred, scene.meas[1], p, 1)
+    print("N=%d H_max=%d: %d of %d matched, densities of %d compared, search form %d"
+          % (n_obj, h_max, matched, len(out_o["hyp_logw"]), stats["densities_compared"], stats["search_form"]),
+          flush=True)
+    assert len(out_g["hyp_logw"]) == h_max and matched > 0.9 * h_max
 
 
 # --------------------------------------------------------------------------- edge cases
@@ -290,3 +319,65 @@ def test_truncate_and_estimate(torch_cuda):
         assert la.tolist() == lb.tolist()
         np.testing.assert_allclose(mb, ma, rtol=1e-4, atol=1e-4)
         g.close()
+
+
+def test_unsorted_import_truncate_and_estimate(torch_cuda):
+    """A state imported out of rank order is ranked by weight on both sides (stable), so the
+    H_max cut and the tau prefix keep the same hypotheses as the oracle."""
+    spec = sc.spec_for("c1")
+    scene = sc.make_scene(spec, n_steps=6)
+    p = sc.filter_params(spec, 64, 0.0)
+    o = Oracle(p)
+    o.import_state(sc.empty_state())
+    for k in range(6):
+        o.predict(k)
+        o.update(k, scene.meas[k])
+    st = to_f32_state(o.export_state())
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(len(st["hyp_logw"]))
+    shuffled = dict(st)
+    offs, idx = [0], []
+    for h in perm:
+        idx.extend(st["hyp_idx"][st["hyp_off"][h]:st["hyp_off"][h + 1]].tolist())
+        offs.append(len(idx))
+    shuffled["hyp_logw"] = st["hyp_logw"][perm]
+    shuffled["hyp_off"] = np.array(offs, np.int32)
+    shuffled["hyp_idx"] = np.array(idx, np.int32)
+    for hmax, tau in ((64, 0.0), (7, 0.0), (40, 2e-3), (64, 0.05)):
+        oo = Oracle(p)
+        oo.import_state(shuffled)
+        oo.truncate(hmax, tau)
+        g = _tracker(p)
+        g.import_state(shuffled)
+        g.truncate(hmax, tau)
+        a, b = oo.export_state(), g.export_state()
+        assert len(a["hyp_logw"]) == len(b["hyp_logw"]), (hmax, tau)
+        # ties in weight keep the input order on both sides: parents match one to one
+        assert a["hyp_parent"].tolist() == b["hyp_parent"].tolist()
+        assert np.all(np.abs(b["hyp_logw"] - a["hyp_logw"]) <= pt.tol(a["hyp_logw"]))
+        la, ma, _ = oo.estimate()
+        lb, mb = g.estimate()
+        assert la.tolist() == lb.tolist()
+        np.testing.assert_allclose(mb, ma, rtol=1e-4, atol=1e-4)
+        g.close()
+
+
+def test_fingerprint_collisions_resolved(torch_cuda, monkeypatch):
+    """(instance, detection set) records are deduplicated on a fingerprint; with the fingerprint
+    narrowed to one bit, different sets of one instance collide in almost every update and must
+    still become distinct instances (compared with the oracle, densities included)."""
+    monkeypatch.setenv("GLMB_REC_HASH_BITS", "1")
+    spec = sc.spec_for("c1")
+    scene = sc.make_scene(spec, n_steps=8)
+    p = sc.filter_params(spec, 64, 1e-5)
+    o = Oracle(p)
+    o.import_state(sc.empty_state())
+    collisions = 0
+    for k in range(8):
+        o.predict(k)
+        pred = to_f32_state(o.export_state())
+        _, stats, _, _ = check_update(pred, scene.meas[k], p, k)
+        collisions += stats["rec_collisions"]
+        o.import_state(pred)
+        o.update(k, scene.meas[k])
+    assert collisions > 0

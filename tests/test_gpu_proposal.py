@@ -166,7 +166,6 @@ def test_network_forward_and_gradient(torch_cuda, n):
     s = g.to_host(g.mlp_forward(P, norm, g.to_device(X)))
     grad, loss = g.mlp_grad(P, norm, g.to_device(X), g.to_device(y), g.to_device(w))
     grad, loss = g.to_host(grad), float(g.to_host(loss)[0])
-    g.close()
     s_ref = _ref_logits(params, norm, X)
     err = np.abs(s - s_ref) / np.maximum(1.0, np.abs(s_ref))
     assert np.mean(err <= 1e-4) >= 0.99 and err.max() <= 5e-2, (np.sort(err)[-5:])
@@ -174,6 +173,23 @@ def test_network_forward_and_gradient(torch_cuda, n):
                                     y.astype(np.float64), w.astype(np.float64))
     assert abs(loss - l_ref) <= 1e-4 * abs(l_ref)
     assert np.linalg.norm(grad - g_ref) <= 2e-3 * np.linalg.norm(g_ref)
+    # element by element, on the samples whose float32 evaluation takes the same bfloat16
+    # rounding and ReLU decisions as the exact one
+    keep = ~pp.rounding_sensitive(params, norm, X)
+    assert keep.mean() >= 0.9, keep.mean()
+    Xk, yk, wk = X[keep], y[keep], w[keep]
+    sk = g.to_host(g.mlp_forward(P, norm, g.to_device(Xk)))
+    assert np.all(np.abs(sk - s_ref[keep]) <= 1e-4 * np.maximum(1.0, np.abs(s_ref[keep])))
+    grad_k, loss_k = g.mlp_grad(P, norm, g.to_device(Xk), g.to_device(yk), g.to_device(wk))
+    grad_k, loss_k = g.to_host(grad_k), float(g.to_host(loss_k)[0])
+    g.close()
+    args = (params.astype(np.float64), norm.astype(np.float64), Xk.astype(np.float64), yk.astype(np.float64),
+            wk.astype(np.float64))
+    l_k, g_k = pp.loss_and_grad(*args)
+    scale = pp.grad_abs_terms(*args)
+    assert abs(loss_k - l_k) <= 1e-5 * abs(l_k) + 1e-7
+    bad = np.abs(grad_k - g_k) > 3e-5 * scale + 1e-9
+    assert not bad.any(), (np.nonzero(bad)[0][:10], grad_k[bad][:5], g_k[bad][:5], scale[bad][:5])
 
 
 def test_adam_steps(torch_cuda):

@@ -18,6 +18,10 @@ PINS = [
     lambda: pins.test_predict_cross_parent_tie_goes_to_lower_rank(),
     lambda: pins.test_single_object_reduces_to_kalman_filter(),
     lambda: pins.test_births_from_unexplained_measurements(),
+    lambda: pins.test_truncate_hmax_then_tau_prefix_renormalised(),
+    lambda: pins.test_truncate_tau_is_relative_to_the_kept_set(),
+    lambda: pins.test_estimate_map_cardinality_not_global_best(),
+    lambda: pins.test_estimate_cardinality_tie_goes_to_the_smaller_count(),
 ]
 
 MUTANTS = {
@@ -29,6 +33,10 @@ MUTANTS = {
     6: "innovation covariance entries transposed in the gate",
     7: "tie-break by parent rank reversed",
     8: "birth existence not capped",
+    9: "estimate returns the globally best hypothesis",
+    10: "cardinality tie goes to the larger count",
+    11: "no renormalisation after tau",
+    12: "tau against the normaliser before the H_max cut",
 }
 
 

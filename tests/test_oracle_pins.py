@@ -407,3 +407,101 @@ def test_scene_tracking_accuracy_c1():
     # foresee; a track can be lost for a few scans there, hence the median
     assert np.mean(card[5:]) < 0.05
     assert np.median(err) < 1.5
+
+
+# --------------------------------------------------------------------------- truncate / estimate
+def _hand_state(weights, members, labels=None):
+    """A state given by hand: hypothesis h holds the instances ``members[h]`` and has the
+    (unnormalised) weight ``weights[h]``; instance u has label (0, u) and mean (u, 10u, 0, 0)."""
+    n_inst = 1 + max([u for m in members for u in m] + [-1])
+    off = np.concatenate([[0], np.cumsum([len(m) for m in members])]).astype(np.int32)
+    idx = np.array([u for m in members for u in m] or [0], np.int32)[: off[-1]]
+    return dict(
+        inst_lab=np.array([[0, u] for u in range(n_inst)], np.int32).reshape(-1, 2),
+        inst_m=np.array([[u, 10.0 * u, 0.0, 0.0] for u in range(n_inst)]).reshape(-1, 4),
+        inst_P=np.tile(np.eye(4).reshape(1, 16), (n_inst, 1)),
+        hyp_logw=np.log(np.asarray(weights, np.float64)), hyp_off=off, hyp_idx=idx,
+        birth_lab=np.zeros((0, 2), np.int32), birth_m=np.zeros((0, 4)), birth_P=np.zeros((0, 16)),
+        birth_r=np.zeros(0))
+
+
+def test_truncate_hmax_then_tau_prefix_renormalised():
+    """Sec. 3 end: the H_max best are kept, weights are renormalised over them, those below tau
+    are dropped (the best always stays) and the rest renormalised.  Hand-computed: weights
+    0.4, 0.3, 0.2, 0.06, 0.04 cut to 4 give 0.4/0.96 = 0.41667, 0.3125, 0.20833, 0.0625;
+    tau = 0.1 keeps the first three; renormalised: 4/9, 3/9, 2/9."""
+    st = _hand_state([0.4, 0.3, 0.2, 0.06, 0.04], [[0], [1], [2], [3], [4]])
+    o = Oracle(BASE)
+    o.import_state(st)
+    o.truncate(4, 0.1)
+    out = o.export_state()
+    np.testing.assert_allclose(np.exp(out["hyp_logw"]), [4 / 9, 3 / 9, 2 / 9], rtol=1e-12)
+    assert out["hyp_parent"].tolist() == [0, 1, 2]
+
+
+def test_truncate_tau_is_relative_to_the_kept_set():
+    """Reading of tau: relative to the weights normalised over the H_max kept set.  The fourth
+    hypothesis weighs 0.0625 over the four kept and 0.06 over all five; tau = 0.061 keeps it
+    under this reading and would drop it under the other."""
+    st = _hand_state([0.4, 0.3, 0.2, 0.06, 0.04], [[0], [1], [2], [3], [4]])
+    o = Oracle(BASE)
+    o.import_state(st)
+    o.truncate(4, 0.061)
+    out = o.export_state()
+    np.testing.assert_allclose(np.exp(out["hyp_logw"]), [0.4 / 0.96, 0.3 / 0.96, 0.2 / 0.96, 0.06 / 0.96],
+                               rtol=1e-12)
+
+
+def test_truncate_keeps_the_best_and_is_idempotent():
+    st = _hand_state([0.3, 0.25, 0.25, 0.2], [[0], [1], [2], [3]])
+    o = Oracle(BASE)
+    o.import_state(st)
+    o.truncate(10, 0.9)  # every weight is below tau: the best alone stays, with weight 1
+    out = o.export_state()
+    assert len(out["hyp_logw"]) == 1 and out["hyp_logw"][0] == 0.0 and out["hyp_parent"][0] == 0
+    o2 = Oracle(BASE)
+    o2.import_state(st)
+    o2.truncate(3, 0.2)
+    a = o2.export_state()
+    o2.truncate(3, 0.2)
+    b = o2.export_state()
+    np.testing.assert_array_equal(a["hyp_logw"], b["hyp_logw"])
+    np.testing.assert_allclose(np.exp(a["hyp_logw"]), [0.375, 0.3125, 0.3125], rtol=1e-12)
+
+
+def test_import_ranks_hypotheses_by_weight():
+    """The hypothesis list is the rank order: an input listed in another order is ranked by
+    weight (ties keep the input order); the parent index names the input position."""
+    st = _hand_state([0.1, 0.5, 0.2, 0.2], [[0], [1], [2], [3]])
+    o = Oracle(BASE)
+    o.import_state(st)
+    o.truncate(3, 0.0)
+    out = o.export_state()
+    assert out["hyp_parent"].tolist() == [1, 2, 3]
+    np.testing.assert_allclose(np.exp(out["hyp_logw"]), [5 / 9, 2 / 9, 2 / 9], rtol=1e-12)
+
+
+def test_estimate_map_cardinality_not_global_best():
+    """Estimator reading: the MAP cardinality first, then the best hypothesis of that size.
+    Hand-computed: {a, b} 0.4, {a} 0.35, {b} 0.25 give rho(2) = 0.4 < rho(1) = 0.6, so the
+    estimate is {a}, although {a, b} is the most likely hypothesis."""
+    st = _hand_state([0.4, 0.35, 0.25], [[0, 1], [0], [1]])
+    o = Oracle(BASE)
+    o.import_state(st)
+    labs, means, rho = o.estimate()
+    assert [tuple(x) for x in labs] == [(0, 0)]
+    np.testing.assert_allclose(means, [[0.0, 0.0, 0.0, 0.0]])
+    np.testing.assert_allclose(rho[:3], [0.0, 0.6, 0.4], rtol=1e-12)
+
+
+def test_estimate_cardinality_tie_goes_to_the_smaller_count():
+    """rho(1) = 0.25 + 0.25 = rho(2) = 0.5 exactly (powers of two survive log and exp):
+    the smaller count wins, and of the two size-1 hypotheses the first in rank order."""
+    assert 2 * np.exp(np.log(0.25)) == np.exp(np.log(0.5))
+    st = _hand_state([0.5, 0.25, 0.25], [[0, 1], [2], [1]])
+    o = Oracle(BASE)
+    o.import_state(st)
+    labs, means, rho = o.estimate()
+    assert rho[1] == rho[2] == 0.5
+    assert [tuple(x) for x in labs] == [(0, 2)]
+    np.testing.assert_allclose(means, [[2.0, 20.0, 0.0, 0.0]])
