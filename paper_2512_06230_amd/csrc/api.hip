@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdlib>
+#include <cstring>
 #include <map>
 
 #include "ctx.hpp"
@@ -243,6 +244,9 @@ glmb_status glmb_create(const glmb_params* p, int device, void* stream, glmb_ctx
   x->c.s = (hipStream_t)stream;
   const char* tr = std::getenv("GLMB_TRACE");
   x->c.trace = tr && tr[0] && tr[0] != '0';
+  // diagnostic: GLMB_SEARCH_FORM=multi runs every selection on the host-driven multi-kernel
+  // levels (the form a batched scene falls back to when its search outgrows one workgroup)
+  if (const char* sf = std::getenv("GLMB_SEARCH_FORM")) x->c.force_multi = std::strcmp(sf, "multi") == 0;
   if (const char* hb = std::getenv("GLMB_REC_HASH_BITS")) {
     const int bits = std::atoi(hb);
     if (bits >= 1 && bits < 32) x->c.rec_hash_mask = (1u << bits) - 1u;

@@ -132,6 +132,7 @@ struct SelectIn {
   const float* t0;        // device scalar: a lower bound on the K-th best child value
   bool* prefer_multi;     // per call site: the previous search outgrew one workgroup (may be null)
   bool allow_coop = true; // the whole-GPU search may be one cooperative launch
+  bool force_multi = false;  // always the host-driven multi-kernel levels (diagnostic setting)
 };
 struct Selected {
   int n;                  // number of selected children (<= K)

@@ -69,6 +69,7 @@ struct Ctx {
   SelectBufs sb;
   bool sel_multi[2] = {false, false};  // per search site (prediction, update): start on the whole GPU
   bool coop_ok = true;  // cooperative launches allowed (they run one at a time on a device)
+  bool force_multi = false;  // every search on the host-driven multi-kernel levels (GLMB_SEARCH_FORM=multi)
   int LW = 1;  // detection-set mask width (32-bit words) of the last gate
   uint32_t rec_hash_mask = 0xffffffffu;  // fingerprint bits of the (instance, detection set) records
   DevBuf rec_lead;                       // collision path: leader position of every record

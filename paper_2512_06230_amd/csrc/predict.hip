@@ -378,7 +378,7 @@ void stage_predict(Ctx& c, int k) {
               (const int32_t*)itoff, icount, itd, itg);
   // ---- exact selection
   trace(c, "predict.select", nitem);
-  SelectIn si{H, V, itoff, itd, itg, p.h_max, t0, &c.sel_multi[0], c.coop_ok};
+  SelectIn si{H, V, itoff, itd, itg, p.h_max, t0, &c.sel_multi[0], c.coop_ok, c.force_multi};
   Selected sel{};
   std::string serr;
   const int cap_nodes = p.cap_nodes > 0 ? p.cap_nodes : (1 << 22);

@@ -1253,7 +1253,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
   int used = 0, levels = 0, nc_fast = 0;
   uint32_t vary = 0xffffffffu;  // value-key bits that differ among the candidates
   bool fast = false;
-  if (!(in.prefer_multi && *in.prefer_multi)) {
+  if (!in.force_multi && !(in.prefer_multi && *in.prefer_multi)) {
     GLMB_LAUNCH(k_select_block, 1, kSB, 0, s, in.P, in.base, in.it_off, in.it_delta, in.it_group, in.K, in.t0,
                 std::min(cap, kBlockNodes), A.p, A.i, A.h, A.v, A.b, t, scal + 24,
                 need<int32_t>(b.cand, std::min(cap, kBlockNodes) + 1));
@@ -1270,7 +1270,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
   // On the whole GPU: one cooperative launch when the device supports it, else the
   // host-driven multi-kernel levels below.
   bool coop = false;
-  if (!fast && in.allow_coop) {
+  if (!fast && in.allow_coop && !in.force_multi) {
     int G = coop_grid(kCoopLds);
     if (G > 0) {
       CoopArgs ca{};
@@ -1312,7 +1312,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
         levels = hs[1];
         tr("coop", used, hs[4]);
         // a search that created few nodes fits one workgroup: try that first next time
-        if (in.prefer_multi && hs[2] == 0 && hs[4] < kBlockNodes / 4) *in.prefer_multi = false;
+        if (in.prefer_multi && !in.force_multi && hs[2] == 0 && hs[4] < kBlockNodes / 4) *in.prefer_multi = false;
         if (hs[2] == 1) {
           err = "selection: search node capacity exhausted (tie class at the cut larger than the node store?)";
           return GLMB_E_CAPACITY;
@@ -1436,7 +1436,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
       if (raise_and_compact(&c)) last_raise = used;
     }
   }
-  if (!fast && !coop && in.prefer_multi && created < kBlockNodes / 4) *in.prefer_multi = false;
+  if (!fast && !coop && in.prefer_multi && !in.force_multi && created < kBlockNodes / 4) *in.prefer_multi = false;
   tr("final", used, levels);
   tr("created", created, fast ? 1 : 0);
   // candidates: every node >= t, in enumeration order

@@ -261,6 +261,18 @@ def test_small_node_store(torch_cuda):
         check_update(st, z, dict(BASE, h_max=64, cap_nodes=cap))
 
 
+def test_small_node_store_multi_kernel(torch_cuda, monkeypatch):
+    """The same small stores on the host-driven multi-kernel levels (the whole-GPU form that
+    batched scenes use): threshold raising and node compaction reach the same hypotheses."""
+    monkeypatch.setenv("GLMB_SEARCH_FORM", "multi")
+    rng = np.random.default_rng(21)
+    st = sc.random_state(rng, n_lab=6, n_hyp=10, side=20.0, versions=2)
+    z = sc.measurements_near(rng, st, 4, 20.0, 1.0)
+    for cap in (90, 110, 0):
+        _, stats, _, _ = check_update(st, z, dict(BASE, h_max=64, cap_nodes=cap))
+        assert stats["search_form"] == 2, stats
+
+
 def test_hmax_one(torch_cuda):
     rng = np.random.default_rng(4)
     st = sc.random_state(rng, n_lab=5, n_hyp=6, side=20.0)
