@@ -242,6 +242,19 @@ glmb_status glmb_mlp_grad(glmb_ctx* ctx, const float* params_dev, const float* n
 glmb_status glmb_mlp_adam(glmb_ctx* ctx, float* params_dev, float* m_dev, float* v_dev, const float* grad_dev,
                           int32_t t, float lr, float beta1, float beta2, float eps);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * training or serving loops, harnesses that forbid hipMalloc): glmb_mlp_grad without any
+ * allocation.  Same arguments and the same results, bit for bit.  Its per-workgroup partial
+ * sums (one row of GLMB_MLP_NPARAM + 2 floats per 64 samples) live in a fixed device array of
+ * (GLMB_MLP_NOALLOC_MAX / 64) rows, 9.6 MB, that each GPU holds from the first glmb_create on
+ * it until the process ends.  n > GLMB_MLP_NOALLOC_MAX returns GLMB_E_CAPACITY before any
+ * device work.  Every call on one GPU shares that array, so calls that overlap on one GPU (from
+ * several streams, contexts or threads) race: the caller serialises them. */
+#define GLMB_MLP_NOALLOC_MAX 32768
+glmb_status glmb_mlp_grad_noalloc(glmb_ctx* ctx, const float* params_dev, const float* norm, const float* feat_dev,
+                                  const float* target_dev, const float* weight_dev, int32_t n, float* grad_dev,
+                                  float* loss_dev);
+
 /* ---- Batched scenes -------------------------------------------------------------------
  * An addition to the method (the paper filters one scene): many independent scenes of uneven
  * size advance one time step in one call.  Each scene is a context of its own (its state,

@@ -252,6 +252,7 @@ glmb_status glmb_create(const glmb_params* p, int device, void* stream, glmb_ctx
     if (bits >= 1 && bits < 32) x->c.rec_hash_mask = (1u << bits) - 1u;
   }
   glmb_status st = guarded(x, [&](Ctx& c) {
+    glmb::noalloc_setup(c.device);  // the device is current here
     c.ev_ok = true;
     for (auto& e : c.ev) GLMB_HIP(hipEventCreate(&e));
     // one hypothesis without tracks
@@ -640,6 +641,13 @@ glmb_status glmb_mlp_grad(glmb_ctx* x, const float* params, const float* norm, c
                           const float* w, int32_t n, float* grad, float* loss) {
   if (!x || !params || !norm || !grad || !loss || n < 1 || !feat || !y || !w) return GLMB_E_ARG;
   return guarded(x, [&](Ctx& c) { glmb::mlp_grad(c, params, norm, feat, y, w, n, grad, loss); });
+}
+
+glmb_status glmb_mlp_grad_noalloc(glmb_ctx* x, const float* params, const float* norm, const float* feat,
+                                  const float* y, const float* w, int32_t n, float* grad, float* loss) {
+  if (!x || !params || !norm || !grad || !loss || n < 1 || !feat || !y || !w) return GLMB_E_ARG;
+  if (n > GLMB_MLP_NOALLOC_MAX) return fail(x, GLMB_E_CAPACITY, "more samples than GLMB_MLP_NOALLOC_MAX");
+  return guarded(x, [&](Ctx& c) { glmb::mlp_grad_noalloc(c, params, norm, feat, y, w, n, grad, loss); });
 }
 
 glmb_status glmb_mlp_adam(glmb_ctx* x, float* params, float* m, float* v, const float* g, int32_t t, float lr,

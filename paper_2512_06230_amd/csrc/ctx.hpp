@@ -112,6 +112,11 @@ void mlp_grad(Ctx& c, const float* params, const float* norm, const float* feat,
               int n, float* grad, float* loss);
 void mlp_adam(Ctx& c, float* params, float* m, float* v, const float* g, int t, float lr, float b1, float b2,
               float eps);
+// allocation-free gradient: the partial sums live in a fixed per-device array, whose address
+// noalloc_setup (called by glmb_create with the context's device current) looks up once per device
+void noalloc_setup(int device);
+void mlp_grad_noalloc(Ctx& c, const float* params, const float* norm, const float* feat, const float* y,
+                      const float* w, int n, float* grad, float* loss);
 void gc_state(Ctx& c);
 
 // F and Q of the constant-velocity model (host constants passed to kernels)

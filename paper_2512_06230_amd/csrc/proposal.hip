@@ -11,6 +11,8 @@
 //   training   targets from the full posterior of the plain update; forward + backward over
 //              64 samples per workgroup with per-sample vectors in LDS and a fixed-order
 //              gradient reduction; Adam.
+#include <mutex>
+
 #include "ctx.hpp"
 
 namespace glmb {
@@ -612,15 +614,54 @@ void mlp_forward(Ctx& c, const float* params, const float* norm, const float* fe
   GLMB_LAUNCH(k_mlp_fwd, cdiv(n, 256), 256, 0, c.s, n, feat, params, norm_of(norm), logit);
 }
 
-void mlp_grad(Ctx& c, const float* params, const float* norm, const float* feat, const float* y, const float* w,
-              int n, float* grad, float* loss) {
+namespace {
+
+// Partial sums of glmb_mlp_grad_noalloc: one row of kPartW floats per 64-sample workgroup.
+// Host code never names this array: it uses the address noalloc_setup looked up per device.
+constexpr int kNoAllocBlocks = GLMB_MLP_NOALLOC_MAX / 64;
+static_assert(GLMB_MLP_NOALLOC_MAX % 64 == 0, "whole workgroups");
+__device__ __align__(256) float scratch[(size_t)kNoAllocBlocks * kPartW];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch[kMaxDevices] = {};  // device address of `scratch` on each device
+
+void mlp_grad_launch(Ctx& c, const float* params, const float* norm, const float* feat, const float* y,
+                     const float* w, int n, float* grad, float* loss, float* part) {
   const int nblk = std::max(1, cdiv(n, 64));
-  float* part = need<float>(c.mlp_part, (int64_t)nblk * kPartW);
   const size_t lds = (size_t)(kNParam + 3 + kNFeat * kLS + 4 * kNHid * kLS + 3 * 64) * sizeof(float);
   static_assert((kNParam + 3 + kNFeat * kLS + 4 * kNHid * kLS + 3 * 64) * 4 <= 160 * 1024, "LDS of k_mlp_fb");
   GLMB_HIP(hipFuncSetAttribute((const void*)k_mlp_fb, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   GLMB_LAUNCH(k_mlp_fb, nblk, 64, lds, c.s, n, feat, y, w, params, norm_of(norm), part);
   GLMB_LAUNCH(k_mlp_reduce, cdiv(kNParam + 1, 256), 256, 0, c.s, nblk, part, grad, loss);
+}
+
+}  // namespace
+
+void mlp_grad(Ctx& c, const float* params, const float* norm, const float* feat, const float* y, const float* w,
+              int n, float* grad, float* loss) {
+  const int nblk = std::max(1, cdiv(n, 64));
+  float* part = need<float>(c.mlp_part, (int64_t)nblk * kPartW);
+  mlp_grad_launch(c, params, norm, feat, y, w, n, grad, loss, part);
+}
+
+void noalloc_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) throw Error{GLMB_E_DEVICE, "device index beyond the supported 64"};
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    throw Error{GLMB_E_DEVICE, std::string("hipGetSymbolAddress of the gradient scratch array: ") + hipGetErrorString(e)};
+  g_scratch[device] = (float*)p;
+}
+
+void mlp_grad_noalloc(Ctx& c, const float* params, const float* norm, const float* feat, const float* y,
+                      const float* w, int n, float* grad, float* loss) {
+  float* part = (c.device >= 0 && c.device < kMaxDevices) ? g_scratch[c.device] : nullptr;
+  if (!part) throw Error{GLMB_E_STATE, "gradient scratch array not set up on this device"};
+  // every row the reduction reads (one per workgroup of this call) is written first by k_mlp_fb
+  mlp_grad_launch(c, params, norm, feat, y, w, n, grad, loss, part);
 }
 
 void mlp_adam(Ctx& c, float* params, float* m, float* v, const float* g, int t, float lr, float b1, float b2,

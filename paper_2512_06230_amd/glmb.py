@@ -20,10 +20,12 @@ EXPORTS = ["glmb_status_string", "glmb_last_error", "glmb_create", "glmb_destroy
            "glmb_state_sizes", "glmb_export_state", "glmb_predict", "glmb_update", "glmb_truncate",
            "glmb_estimate", "glmb_stats", "glmb_update_diag", "glmb_update_theta", "glmb_set_proposal",
            "glmb_pair_features", "glmb_proposal_lost", "glmb_mlp_forward", "glmb_mlp_grad", "glmb_mlp_adam",
+           "glmb_mlp_grad_noalloc",
            "glmb_batch_create", "glmb_batch_destroy", "glmb_batch_set_schedule", "glmb_batch_scene",
            "glmb_batch_step", "glmb_batch_stats_get", "glmb_batch_last_error"]
 
 MLP_NPARAM, MLP_NFEAT = 4673, 6
+MLP_NOALLOC_MAX = 32768
 PROPOSAL_APPLY, PROPOSAL_MEASURE = 1, 2
 
 
@@ -99,6 +101,7 @@ def load_library(path: str = LIB_PATH):
                                      ctypes.POINTER(ctypes.c_double)]
     L.glmb_mlp_forward.argtypes = [vp, vp, _F, vp, ctypes.c_int32, vp]
     L.glmb_mlp_grad.argtypes = [vp, vp, _F, vp, vp, vp, ctypes.c_int32, vp, vp]
+    L.glmb_mlp_grad_noalloc.argtypes = [vp, vp, _F, vp, vp, vp, ctypes.c_int32, vp, vp]
     L.glmb_mlp_adam.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float]
     L.glmb_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_int, ctypes.c_int32,
@@ -366,6 +369,23 @@ class Tracker:
                                           ctypes.c_void_p(g.data_ptr()), ctypes.c_void_p(loss.data_ptr())),
                     "glmb_mlp_grad")
         return g, loss
+
+    def mlp_grad_noalloc(self, params, norm, feat, y, w, grad_out, loss_out):
+        """glmb_mlp_grad_noalloc into the caller's CUDA float32 tensors grad_out [4673] and
+        loss_out [1]; every input must already be a contiguous CUDA float32 tensor, so that
+        nothing is allocated on the way (at most MLP_NOALLOC_MAX samples)."""
+        t = self.torch
+        n = int(feat.shape[0])
+        for a, shape in ((params, (MLP_NPARAM,)), (feat, (n, MLP_NFEAT)), (y, (n,)), (w, (n,)),
+                         (grad_out, (MLP_NPARAM,)), (loss_out, (1,))):
+            if not (a.is_cuda and a.dtype == t.float32 and a.is_contiguous() and tuple(a.shape) == shape):
+                raise ValueError("mlp_grad_noalloc takes contiguous CUDA float32 tensors of the stated shapes")
+        nm = self._norm(norm)
+        self._check(self._L.glmb_mlp_grad_noalloc(self._ctx, ctypes.c_void_p(params.data_ptr()), _fp(nm),
+                                                  ctypes.c_void_p(feat.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                                  ctypes.c_void_p(w.data_ptr()), n,
+                                                  ctypes.c_void_p(grad_out.data_ptr()),
+                                                  ctypes.c_void_p(loss_out.data_ptr())), "glmb_mlp_grad_noalloc")
 
     def mlp_adam(self, params, m, v, g, step: int, lr: float, beta1: float = 0.9, beta2: float = 0.999,
                  eps: float = 1e-8):
