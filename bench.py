@@ -19,7 +19,81 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GLMB updates/s and hyp·track·meas evals/s, N=500 H_max=1e4; learned vs plain"
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
-FP32_VECTOR_TFLOPS = 157.3  # MI355X FP32 vector (packed)
+FP32_VECTOR_TFLOPS = 157.3  # MI355X FP32 vector: 256 CUs x 128 lanes x 2 flops (FMA) x 2.4 GHz
+TRANS_PER_S = 9.8e12        # transcendental (exp / log) rate, assumed a quarter of the unpacked FP32 FMA rate
+INST_BYTES = 64             # one track instance record (mean, covariance, label slot, source)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def stage_roofline(stats, stage):
+    """Algorithmic lower bound on each update stage's time (mean over the timed updates), from
+    the work the method needs per unit: U1 14 FP32 flops per (instance, detection) pair; U2 one
+    read of every hypothesis row (|J| x 4 B) and two floats written per hypothesis (best child,
+    log mass) for hypotheses 1..H-1 (the association kernel's share); U4 the predicted rows read,
+    the child rows written and one record per new instance; births one exp per (hypothesis,
+    detection) cell.  The cut (U3) is a chain of dependent levels: time only."""
+    import numpy as np
+    H = np.mean([s["n_hyp_in"] for s in stats])
+    Ho = np.mean([s["n_hyp_out"] for s in stats])
+    M = np.mean([s["n_meas"] for s in stats])
+    U = np.mean([s["n_inst_in"] for s in stats])
+    Uo = np.mean([s["n_inst_out"] for s in stats])
+    J = np.mean([s["dense_triples"] / max(1, s["n_hyp_in"] * s["n_meas"]) for s in stats])
+    hbm = HBM_PEAK_GBS * 1e9
+    valu = FP32_VECTOR_TFLOPS * 1e12
+    out = {}
+    f_gate = 14.0 * U * M
+    out["gate"] = {"bound": "alu", "work": f_gate, "unit": "FP32 flop", "t_roof_ms": 1e3 * f_gate / valu}
+    b_assoc = (H - 1.0) * J * 4.0 + 8.0 * (H - 1.0)
+    out["assoc"] = {"bound": "hbm", "work": b_assoc, "unit": "B", "t_roof_ms": 1e3 * b_assoc / hbm}
+    out["select"] = {"bound": "latency", "work": None, "unit": None, "t_roof_ms": None}
+    b_mat = (H + Ho) * J * 4.0 + Uo * INST_BYTES
+    out["materialise"] = {"bound": "hbm", "work": b_mat, "unit": "B", "t_roof_ms": 1e3 * b_mat / hbm}
+    x_b = H * M
+    out["births"] = {"bound": "trans", "work": x_b, "unit": "exp", "t_roof_ms": 1e3 * x_b / TRANS_PER_S}
+    names = ["gate", "assoc", "select", "materialise", "births"]
+    for j, n in enumerate(names):
+        t = float(stage[j])
+        out[n]["measured_ms"] = t
+        tr = out[n]["t_roof_ms"]
+        out[n]["frac"] = (tr / t) if (tr is not None and t > 0) else None
+    t_roof = sum(out[n]["t_roof_ms"] or 0.0 for n in names)
+    out["update"] = {"t_roof_ms": t_roof, "measured_ms": float(stage[5]),
+                     "frac": t_roof / float(stage[5]) if stage[5] > 0 else None}
+    out["mean_tracks_per_hypothesis"] = float(J)
+    return out
+
+
+def accuracy(estimates, truths, cutoff=10.0):
+    """Cardinality error and Hungarian-matched position error of the per-scan estimates
+    (the metrics of the paper's Sec. 4.2): |n_hat - n| / n, and the mean distance of matched
+    (estimate, truth) pairs, pairs farther apart than `cutoff` counted as unmatched."""
+    import numpy as np
+    from scipy.optimize import linear_sum_assignment
+    card, errs, far = [], [], 0
+    for (labs, means), tx in zip(estimates, truths):
+        n = len(tx)
+        card.append(abs(len(means) - n) / max(n, 1))
+        if len(means) and n:
+            D = np.linalg.norm(np.asarray(means, np.float64)[:, None, :2] - np.asarray(tx)[None, :, :2], axis=2)
+            r, c = linear_sum_assignment(np.minimum(D, cutoff))
+            d = D[r, c]
+            errs.extend(d[d < cutoff].tolist())
+            far += int((d >= cutoff).sum()) + abs(len(means) - n)
+        else:
+            far += max(len(means), n)
+    return {"card_rel_err_mean": float(np.mean(card)), "matched_err_mean_m": float(np.mean(errs)) if errs else None,
+            "unmatched_per_scan": far / max(1, len(truths)), "cutoff_m": cutoff}
 
 
 
@@ -48,7 +122,9 @@ def main():
     ap.add_argument("--clutter", type=float, default=None)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=1)
+    ap.add_argument("--cpu-sample-hyp", type=int, default=2000,
+                    help="the oracle's timed sample: one full step from the GPU's state cut to its best this-many "
+                         "hypotheses (with H_max set to the same number); the rate is scaled by this share of H_max")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batch-scenes", type=int, default=256, help="scenes of the batched leg (0: skip it)")
     ap.add_argument("--no-autotune-cache", action="store_true")
@@ -56,6 +132,10 @@ def main():
                     help="first run one device-to-device copy of this many MiB (a known-size kernel that scales "
                          "hardware byte counters)")
     ap.add_argument("--proposal", default=None, help="trained proposal (.npz); default: the packaged one")
+    ap.add_argument("--preset", choices=["c3", "c1", "c2"], default="c3",
+                    help="c3: N objects in 100x100 m, clutter 0.2 N (default, with --n-obj / --h-max); "
+                         "c1: 5 objects, H_max 64, tau 1e-5, empty start; c2: 50 objects in 1000x1000 m with "
+                         "births, H_max 1024, tau 1e-5, warm start")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the multi-detection GLMB path runs on a single device "
@@ -75,11 +155,24 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    clutter = 0.2 * args.n_obj if args.clutter is None else args.clutter
-    spec = sc.spec_for("c3:%d" % args.n_obj, clutter_mean=clutter, seed=args.seed)
     n_scans = args.warmup + args.steps
+    tau = 0.0
+    if args.preset == "c3":
+        clutter = 0.2 * args.n_obj if args.clutter is None else args.clutter
+        spec = sc.spec_for("c3:%d" % args.n_obj, clutter_mean=clutter, seed=args.seed)
+        workload = "N=%d objects, H_max=%d, clutter %.0f/scan, 100x100 m, warm start, plain update" % (
+            args.n_obj, args.h_max, clutter)
+    else:
+        spec = sc.spec_for(args.preset, seed=args.seed)
+        args.n_obj, clutter, tau = spec.n_obj, spec.clutter_mean, 1e-5
+        args.h_max = 64 if args.preset == "c1" else 1024
+        args.no_learned, args.batch_scenes = True, 0
+        workload = ("%s: %d objects, H_max=%d, clutter %.0f/scan, %.0fx%.0f m, tau 1e-5, %s, plain update" % (
+            args.preset, spec.n_obj, args.h_max, clutter, spec.side, spec.side,
+            "empty start" if args.preset == "c1" else "warm start, object births"))
     scene = sc.make_scene(spec, n_steps=n_scans)
-    params = sc.filter_params(spec, args.h_max, 0.0)
+    params = sc.filter_params(spec, args.h_max, tau)
+    start = sc.empty_state() if args.preset == "c1" else sc.warm_start_state(scene)
     dev = torch.device("cuda:0")
     # every scan resident in HBM before timing
     zs = [torch.as_tensor(z, device=dev) for z in scene.meas]
@@ -88,7 +181,7 @@ def main():
     def run(proposal=None, measure=False):
         """Warm-up scans, then the timed scans; returns (seconds, per-scan stats)."""
         trk = Tracker(params)
-        trk.import_state(sc.warm_start_state(scene))
+        trk.import_state(start)
         if proposal is not None:
             trk.set_proposal(torch.as_tensor(proposal.params, device=dev), proposal.norm, proposal.threshold,
                              apply=True, measure=measure)
@@ -96,22 +189,24 @@ def main():
         def step(k):
             trk.predict(k)
             trk.update(k, zs[k])
-            trk.truncate(args.h_max, 0.0)
+            trk.truncate(args.h_max, tau)
             return trk.estimate()
 
         for k in range(args.warmup):
             step(k)
         torch.cuda.synchronize()
-        st = []
+        st, est = [], []
         t0 = time.perf_counter()
         for k in range(args.warmup, n_scans):
-            step(k)
+            est.append(step(k))
             st.append(trk.stats())
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        run.estimates = est
         return el, st, trk
 
     elapsed, stats, trk = run()
+    acc = accuracy(run.estimates, scene.truth_x[args.warmup:n_scans])
     ms_step = 1e3 * elapsed / args.steps
     dense = sum(s["dense_triples"] for s in stats)
     gated = sum(s["option_terms"] for s in stats)
@@ -130,21 +225,27 @@ def main():
         lost = np.array([s["lost_mass"] for s in st_m])
         # lost mass versus the plain update: along the plain trajectory, the plain update's
         # retained mass that the proposal's update does not retain (untimed)
+        # and along the learned trajectory (the predicted states the learned filter reaches)
         from paper_2512_06230_amd.proposal import retained_lost
-        ptrk = Tracker(params)
-        ptrk.import_state(sc.warm_start_state(scene))
-        probe = Tracker(params)
         pw = torch.as_tensor(prop.params, device=dev)
-        ret = []
-        for k in range(n_scans):
-            ptrk.predict(k)
-            if k >= args.warmup:
-                ret.append(retained_lost(probe, ptrk.export_state(), k, zs[k], pw, prop.norm, [prop.threshold])[0])
-            ptrk.update(k, zs[k])
-            ptrk.truncate(args.h_max, 0.0)
-        ptrk.close()
+        probe = Tracker(params)
+        ret_traj = {}
+        for leg in ("plain", "learned"):
+            ptrk = Tracker(params)
+            ptrk.import_state(start)
+            if leg == "learned":
+                ptrk.set_proposal(pw, prop.norm, prop.threshold, apply=True)
+            r = []
+            for k in range(n_scans):
+                ptrk.predict(k)
+                if k >= args.warmup:
+                    r.append(retained_lost(probe, ptrk.export_state(), k, zs[k], pw, prop.norm, [prop.threshold])[0])
+                ptrk.update(k, zs[k])
+                ptrk.truncate(args.h_max, 0.0)
+            ptrk.close()
+            ret_traj[leg] = np.clip(np.array(r), 0.0, 1.0)
         probe.close()
-        ret = np.array(ret)
+        ret = ret_traj["plain"]
         stage_l = np.mean(np.array([s["stage_ms"] for s in st_l]), axis=0)
         learned = {
             "value": args.steps / el_l, "unit": "GLMB updates/s", "ms_per_step": 1e3 * el_l / args.steps,
@@ -153,8 +254,13 @@ def main():
             "threshold": prop.threshold,
             "lost_mass_mean": float(ret.mean()), "lost_mass_max": float(ret.max()),
             "lost_mass_definition": "plain update's retained posterior mass absent from the learned update's "
-                                    "retained set, per scan",
-            "full_posterior_lost_mass_mean": float(lost.mean()), "full_posterior_lost_mass_max": float(lost.max()),
+                                    "retained set, per scan, from the plain filter's predicted states",
+            "lost_mass_learned_trajectory_mean": float(ret_traj["learned"].mean()),
+            "lost_mass_learned_trajectory_max": float(ret_traj["learned"].max()),
+            "full_posterior_lost_mass_mean": float(np.clip(lost, 0.0, 1.0).mean()),
+            "full_posterior_lost_mass_max": float(np.clip(lost, 0.0, 1.0).max()),
+            "n_births_mean": float(np.mean([s["n_births"] for s in st_l])),
+            "plain_n_births_mean": float(np.mean([s["n_births"] for s in stats])),
             "pairs_removed_frac": float(sum(s["pairs_removed"] for s in st_l) /
                                         max(1, sum(s["gated_pairs"] for s in st_l))),
             "option_terms_frac": float(sum(s["option_terms"] for s in st_l) / max(1, gated)),
@@ -206,12 +312,13 @@ def main():
 
     # roofline of the dominant kernel: the per-(hypothesis, detection) association kernel, which
     # covers hypotheses 1..H-1 (hypothesis 0's cells come from a one-workgroup kernel before it).
-    # Algorithmic HBM bytes per launch: each hypothesis row read once (L x 4 B) plus the three
-    # per-cell outputs written (best option 2 B, first deviation 4 B, relative log-sum-exp 4 B).
+    # Algorithmic HBM bytes per launch: each hypothesis row of |J| instance ids read once (4 B
+    # each) and two floats written per hypothesis (its best child's log weight and the log mass
+    # of all its children); the duration is the kernel's own, from HIP events around its launch.
     H = np.mean([s["n_hyp_in"] for s in stats])
     M = np.mean([s["n_meas"] for s in stats])
-    L = np.mean([s["n_labels"] for s in stats])
-    bytes_assoc = (H - 1.0) * (L * 4.0 + M * 10.0)
+    roof = stage_roofline(stats, stage)
+    bytes_assoc = roof["assoc"]["work"]
     t_assoc = float(stage[1]) * 1e-3
     achieved = bytes_assoc / t_assoc / 1e9 if t_assoc > 0 else 0.0
     # measured HBM bytes per launch (rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled by a copy kernel);
@@ -235,8 +342,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "N=%d objects, H_max=%d, clutter %.0f/scan, 100x100 m, warm start, plain update"
-                               % (args.n_obj, args.h_max, clutter),
+        "config": {"workload": workload,
                    "n_obj": args.n_obj, "h_max": args.h_max, "clutter_mean": clutter,
                    "mean_detections": float(M), "mean_hypotheses_in": float(H), "parallelism": "single GPU"},
         "evals_per_s": dense / elapsed,
@@ -246,7 +352,11 @@ def main():
                      "materialise": float(stage[3]), "births": float(stage[4]), "update": float(stage[5])},
         "roofline": {"kernel": "k_assoc", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "algorithmic_bytes": bytes_assoc},
+                     "algorithmic_bytes": bytes_assoc,
+                     "traffic_over_algorithmic": (traffic / bytes_assoc) if traffic else None},
+        "stage_roofline": roof,
+        "host_syncs_per_update": float(np.mean([s["host_syncs"] for s in stats])),
+        "accuracy": acc,
     }
     if learned is not None:
         out["learned"] = learned
@@ -256,23 +366,36 @@ def main():
     if not args.no_cpu_baseline:
         from oracle.oracle import Oracle
         st = trk.export_state()
-        o = Oracle(params)
+        nh = max(1, min(args.cpu_sample_hyp, len(st["hyp_logw"]), args.h_max))
+        # the best nh hypotheses (the state lists them in rank order), renormalised by import
+        st = dict(st, hyp_logw=st["hyp_logw"][:nh], hyp_off=st["hyp_off"][:nh + 1],
+                  hyp_idx=st["hyp_idx"][:st["hyp_off"][nh]])
+        o = Oracle(dict(params, h_max=nh))
         o.import_state({k: (np.asarray(v, np.float64) if np.asarray(v).dtype == np.float32 else v)
-                        for k, v in st.items()})
-        k0 = n_scans - 1
-        tc = time.perf_counter()
-        for j in range(args.cpu_sample_steps):
-            kk = min(k0 + j, n_scans - 1)
+                        for k, v in st.items() if k not in ("inst_src", "inst_nz", "inst_z", "hyp_parent")})
+        kk = n_scans - 1
+        # the oracle is single-threaded: pin this thread to one core for the timing
+        aff = os.sched_getaffinity(0)
+        core = min(aff)
+        os.sched_setaffinity(0, {core})
+        try:
+            tc = time.perf_counter()
             o.predict(kk)
             o.update(kk, scene.meas[kk])
-            o.truncate(args.h_max, 0.0)
+            o.truncate(nh, tau)
             o.estimate()
-        tcpu = time.perf_counter() - tc
-        out["cpu_baseline"] = {"value": args.cpu_sample_steps / tcpu, "unit": "GLMB updates/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": "%d full step(s) (predict+update+truncate+estimate) of the same workload "
-                                         "from the GPU's state after the timed steps, FP64, single thread"
-                                         % args.cpu_sample_steps}
+            tcpu = time.perf_counter() - tc
+        finally:
+            os.sched_setaffinity(0, aff)
+        share = nh / float(args.h_max)
+        out["cpu_baseline"] = {"value": share / tcpu, "unit": "GLMB updates/s", "cores": 1,
+                               "kind": "oracle", "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+                               "host_cpus_allowed": len(aff), "pinned_core": core, "sample_seconds": tcpu,
+                               "sample": "one full step (predict+update+truncate+estimate) of the same workload "
+                                         "from the GPU's state after the timed steps cut to its best %d "
+                                         "hypotheses (H_max %d), FP64, one thread pinned to one core; rate "
+                                         "scaled by %d/%d (work linear in the hypothesis count)"
+                                         % (nh, nh, nh, args.h_max)}
     print(json.dumps(out))
 
 

@@ -302,7 +302,8 @@ __global__ __launch_bounds__(1024) void k_lost_final(int H, int T, const float* 
     for (int h = threadIdx.x; h < H; h += blockDim.x)
       a += __expf(lz_full[h] - L) * -expm1f(dlt[(size_t)j * H + h]);
     a = wsum(a, red + 16);
-    if (threadIdx.x == 0) lost[j] = a;
+    // a mass fraction: FP32 rounding of the normalised weights can take the sum just outside [0, 1]
+    if (threadIdx.x == 0) lost[j] = fminf(fmaxf(a, 0.0f), 1.0f);
   }
 }
 
