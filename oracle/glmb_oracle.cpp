@@ -581,9 +581,38 @@ struct Oracle {
       d_best[h] = B[h] - LZ;
       d_logpi[h] = logZ[h] - LZ;
     }
+    // With pairs removed by a learned proposal, the clutter probability behind the births
+    // restores in every cell the removed pairs' likelihood summed over the instances of the
+    // most likely predicted hypothesis (hyp[0]), in the cell's mass and so in each
+    // hypothesis' mass, so that a detection whose track pairs were all removed is not taken
+    // for clutter.  Without removed pairs this is the plain marginal.
+    std::vector<double> removed(M, 0.0);
+    if (!skip.empty() && H > 0 && ORACLE_MUTANT != 13)  // planted 13: the removed mass not restored
+      for (int32_t u : hyp[0].inst)
+        for (const G& g : gated[u])
+          if (g.skip) removed[g.i] += std::exp(g.phi);
+    // hypothesis weights with the removed mass restored in every cell
+    std::vector<double> pir = pi;
+    if (std::any_of(removed.begin(), removed.end(), [](double r) { return r > 0.0; })) {
+      std::vector<double> lzr(H);
+      for (int32_t h = 0; h < H; ++h) {
+        lzr[h] = logZ[h];
+        for (int i = 0; i < M; ++i)
+          if (removed[i] > 0.0) {
+            const double l = lse_hi[(size_t)h * M + i];
+            lzr[h] += lse({l, std::log(removed[i])}) - l;
+          }
+      }
+      const double LZr = lse(lzr);
+      for (int32_t h = 0; h < H; ++h) pir[h] = std::exp(lzr[h] - LZr);
+    }
     for (int i = 0; i < M; ++i) {
       double pc = 0.0;
-      for (int32_t h = 0; h < H; ++h) pc += pi[h] * std::exp(lgk - lse_hi[(size_t)h * M + i]);
+      for (int32_t h = 0; h < H; ++h) {
+        double l = lse_hi[(size_t)h * M + i];
+        if (removed[i] > 0.0) l = lse({l, std::log(removed[i])});
+        pc += pir[h] * std::exp(lgk - l);
+      }
       d_ru[i] = 1.0 - pc;
     }
     {

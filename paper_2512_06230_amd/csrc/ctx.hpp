@@ -81,6 +81,8 @@ struct Ctx {
   float prop_norm[12] = {};
   DevBuf prop_w;          // float32 parameters
   DevBuf pcnt, poff, ppre, pu, pi, plogit, slot_r, slot_part, slot_age, pm_part, pe_part, lz_t, mlp_part;
+  DevBuf rmass;  // per detection: removed pairs' likelihood over the most likely hypothesis' instances
+  DevBuf lz_r;   // per hypothesis: log mass with the removed pairs restored, then their normaliser
   int32_t* age_pin = nullptr;  // pinned host buffer of the label ages uploaded per update
   int age_cap = 0;
   DevBuf est_buf;  // estimate: presence flags and means of the estimated hypothesis' tracks
@@ -103,6 +105,8 @@ void gate_lists(Ctx& c, int M);
 void assoc_norm(Ctx& c, int M);
 // proposal (proposal.hip)
 constexpr int kNFeat = 6, kNHid = 64, kNParam = 4673, kMaxThr = 16;
+// fixed-point scale of the removed likelihood sums (exp(phi) <= gamma / (2 pi sigma^2) per pair)
+constexpr double kRemovedScale = 281474976710656.0;  // 2^48
 void proposal_apply(Ctx& c, int k, int M);
 void proposal_lost(Ctx& c, int k, const float* z, int M, const float* thr_prob, int T, double* lost);
 int proposal_features(Ctx& c, int k, const float* z, int M, int cap, float* feat, int32_t* pair, float* target,

@@ -181,14 +181,23 @@ __global__ void k_pair_feat(int n, const int32_t* pu, const int32_t* pi, const D
   pair[2 * (size_t)p + 1] = i;
 }
 
-// network score of every pair; with `remove`, pairs scoring below thr leave the gate
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n) p[q] = 0ull;
+}
+
+// network score of every pair; with `remove`, pairs scoring below thr leave the gate, and the
+// likelihood exp(phi) of a removed pair whose instance belongs to the most likely predicted
+// hypothesis (row0) is added to its detection's removed mass (fixed point, so that the sum
+// does not depend on the order of the atomic additions)
 __global__ __launch_bounds__(256) void k_prop_apply(const int32_t* np, const int32_t* pu, const int32_t* pi,
                                                     const DInst* inst,
                                                     const float2* z, float sig2, const float* slot_r,
                                                     const int32_t* slot_age, const int32_t* pcnt,
                                                     const float* params, Norm nm, float thr, int remove, int M,
                                                     int W, float* phi, uint32_t* gbits, float* logit_out,
-                                                    int32_t* nremoved) {
+                                                    int32_t* nremoved, const int32_t* row0,
+                                                    unsigned long long* rmass) {
   __shared__ float sw[kNParam];
   const int n = *np;
   if ((int)(blockIdx.x * blockDim.x) >= n) return;  // the grid covers an upper bound
@@ -204,6 +213,8 @@ __global__ __launch_bounds__(256) void k_prop_apply(const int32_t* np, const int
     if (logit_out) logit_out[p] = s;
     if (remove && s < thr) {
       rm = true;
+      if (rmass && row0[x.slot] == u)
+        atomicAdd(&rmass[i], (unsigned long long)(expf(phi[(size_t)u * M + i]) * kRemovedScale));
       phi[(size_t)u * M + i] = -INFINITY;
       atomicAnd(&gbits[(size_t)u * W + (i >> 5)], ~(1u << (i & 31)));
     }
@@ -541,10 +552,16 @@ void score_pairs(Ctx& c, int n, int M, bool remove) {
   float* logit = remove ? nullptr : need<float>(c.plogit, cap);
   int32_t* nremoved = c.scal.as<int32_t>() + 18;
   const int grid = cdiv(cap, 256);
+  unsigned long long* rmass = nullptr;
+  if (remove) {
+    rmass = need<unsigned long long>(c.rmass, M + 1);
+    GLMB_LAUNCH(k_zero_u64, cdiv(M + 1, 256), 256, 0, c.s, rmass, M + 1);
+  }
   GLMB_LAUNCH(k_prop_apply, grid, 256, 0, c.s, c.poff.as<int32_t>() + c.ninst, c.pu.as<int32_t>(), c.pi.as<int32_t>(),
               (const DInst*)c.inst.p, c.z.as<float2>(), c.p.sigma_z * c.p.sigma_z, c.slot_r.as<float>(),
               c.slot_age.as<int32_t>(), c.pcnt.as<int32_t>(), c.prop_w.as<float>(), norm_of(c.prop_norm),
-              c.prop_thr, remove ? 1 : 0, M, W, c.phi.as<float>(), c.gbits.as<uint32_t>(), logit, nremoved);
+              c.prop_thr, remove ? 1 : 0, M, W, c.phi.as<float>(), c.gbits.as<uint32_t>(), logit, nremoved,
+              c.rows.as<int32_t>(), rmass);
 }
 }  // namespace
 

@@ -1179,8 +1179,50 @@ __global__ void k_def_flags(int U, const int32_t* first, int32_t* fl) {
 }
 
 // ------------------------------------------------------------------ births
+// With a learned proposal applied, rmass[i] (fixed point) is the likelihood of the pairs it
+// removed from detection i over the most likely hypothesis' instances; it is restored in every
+// cell's mass (and so in every hypothesis' mass), so that the clutter probabilities behind the
+// births do not count the removed pairs as clutter.
+// log(e^a + e^b); the log of 1 + x with x in (0, 1] loses at most 6e-8 absolute against log1p
+__device__ __forceinline__ float lse2(float a, float b) { return fmaxf(a, b) + __logf(1.0f + __expf(-fabsf(a - b))); }
+
+// per detection: the log of its removed mass shifted by the detection's cell offset c_i
+// (-inf without removed mass)
+__global__ void k_ru_lr(int M, const uint32_t* cmax, const unsigned long long* rmass, float* lr) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < M) lr[i] = rmass[i] == 0ull ? -INFINITY : logf((float)((double)rmass[i] / kRemovedScale)) - o2f(cmax[i]);
+}
+
+// one wave per hypothesis: lzr[h] = lzprime[h] + sum_i (log(e^{l_hi} + R_i) - l_hi), lanes over
+// the detections with removed mass, fixed butterfly
+__global__ __launch_bounds__(256) void k_ru_restore(int H, int M, const float* lzprime, const float* lserel,
+                                                    const float* lr, float* lzr) {
+  const int h = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kWave);
+  if (h >= H) return;
+  float acc = 0.0f;
+  for (int i = lane_id(); i < M; i += kWave) {
+    const float r = lr[i];
+    if (r == -INFINITY) continue;
+    const float ls = lserel[(size_t)h * M + i];
+    acc += lse2(ls, r) - ls;
+  }
+  for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_xor(acc, d, kWave);
+  if (lane_id() == 0) lzr[h] = lzprime[h] + acc;
+}
+// one workgroup: out = log sum_h exp(v[h])
+__global__ __launch_bounds__(1024) void k_lse_block(int H, const float* v, float* out) {
+  __shared__ float red[32];
+  float mx = -INFINITY;
+  for (int h = threadIdx.x; h < H; h += blockDim.x) mx = fmaxf(mx, v[h]);
+  mx = block_max_f(mx, red);
+  float sm = 0.0f;
+  for (int h = threadIdx.x; h < H; h += blockDim.x) sm += __expf(v[h] - mx);
+  sm = block_sum_f(sm, red + 16);
+  if (threadIdx.x == 0) *out = mx + __logf(sm);
+}
 __global__ __launch_bounds__(256) void k_ru_part(int H, int M, int hchunk, const float* lzprime, const float* lz,
-                                                 const float* lserel, const uint32_t* cmax, float lgk, float* part) {
+                                                 const float* lserel, const uint32_t* cmax, float lgk,
+                                                 const float* lrm, float* part) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int ch = blockIdx.y;
   if (i >= M) return;
@@ -1188,7 +1230,13 @@ __global__ __launch_bounds__(256) void k_ru_part(int H, int M, int hchunk, const
   const float L = *lz;
   float acc = 0.0f;
   const int h1 = min(H, (ch + 1) * hchunk);
-  for (int h = ch * hchunk; h < h1; ++h) acc += __expf(lzprime[h] - L + lgk - c - lserel[(size_t)h * M + i]);
+  if (!lrm || lrm[i] == -INFINITY) {
+    for (int h = ch * hchunk; h < h1; ++h) acc += __expf(lzprime[h] - L + lgk - c - lserel[(size_t)h * M + i]);
+  } else {
+    const float lr = lrm[i];
+    for (int h = ch * hchunk; h < h1; ++h)
+      acc += __expf(lzprime[h] - L + lgk - c - lse2(lserel[(size_t)h * M + i], lr));
+  }
   part[(size_t)ch * M + i] = acc;
 }
 // one wave per detection: the chunks' partial sums, lanes over the chunks, fixed butterfly
@@ -1751,8 +1799,20 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     const int hchunk = 16;
     const int nch = cdiv(H, hchunk);
     float* part = need<float>(c.ru_part, (int64_t)nch * M);
-    hipLaunchKernelGGL(k_ru_part, dim3(cdiv(M, T), nch), dim3(T), 0, s, H, M, hchunk, lzprime, lz, lserel, cmax, lgk,
-                       part);
+    const float* lzb = lzprime;
+    const float* Lb = lz;
+    float* lrm = nullptr;
+    if (c.prop_on) {  // hypothesis masses with the removed pairs restored, and their normaliser
+      float* lzr = need<float>(c.lz_r, H + 1 + M);
+      lrm = lzr + H + 1;
+      GLMB_LAUNCH(k_ru_lr, cdiv(M, T), T, 0, s, M, cmax, c.rmass.as<unsigned long long>(), lrm);
+      GLMB_LAUNCH(k_ru_restore, cdiv((int64_t)H * kWave, T), T, 0, s, H, M, lzprime, lserel, lrm, lzr);
+      GLMB_LAUNCH(k_lse_block, 1, 1024, 0, s, H, lzr, lzr + H);
+      lzb = lzr;
+      Lb = lzr + H;
+    }
+    hipLaunchKernelGGL(k_ru_part, dim3(cdiv(M, T), nch), dim3(T), 0, s, H, M, hchunk, lzb, Lb, lserel, cmax, lgk,
+                       lrm, part);
     GLMB_HIP(hipGetLastError());
     GLMB_LAUNCH(k_ru_final, cdiv((int64_t)M * kWave, T), T, 0, s, M, nch, part, ru);
   }

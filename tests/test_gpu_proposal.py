@@ -245,7 +245,15 @@ def test_learned_update_matches_oracle_with_removed_pairs(torch_cuda, seed):
         stats = g.stats()
         out_g = g.export_state()
         th_g = g.theta(len(out_g["hyp_logw"]), z.shape[0])
+        d_g = g.diag(len(st["hyp_logw"]), z.shape[0])
         g.close()
+        # the clutter probabilities behind the births (removed mass restored) and the births
+        if not near:
+            assert np.all(np.abs(d_g["ru"] - d_o["ru"]) <= 1e-4), (d_g["ru"], d_o["ru"])
+            if np.all(np.abs(d_o["ru"] - p["birth_ru_max"]) > 1e-3):
+                assert out_g["birth_lab"].tolist() == out_o["birth_lab"].tolist()
+                np.testing.assert_allclose(out_g["birth_m"], out_o["birth_m"], rtol=1e-4, atol=1e-4)
+                np.testing.assert_allclose(out_g["birth_r"], out_o["birth_r"], rtol=1e-4, atol=1e-6)
         if not near:
             assert stats["pairs_removed"] == int(drop.sum())
             assert abs(lost_g - d_o["lost"]) <= 1e-5 + 1e-3 * d_o["lost"], (lost_g, d_o["lost"])
@@ -325,3 +333,36 @@ def test_proposal_argument_errors(torch_cuda):
     with pytest.raises(GlmbError):
         g.proposal_lost(K_SCAN, z, [0.5] * 17)
     g.close()
+
+
+def test_learned_births_equal_plain_births_on_one_hypothesis(torch_cuda):
+    """From a state with a single hypothesis, restoring the removed pairs' mass makes the learned
+    update's clutter probabilities those of the plain update, so both seed the same births
+    (the packaged network at its threshold, on the 500-object scene it was trained for)."""
+    torch = torch_cuda
+    from paper_2512_06230_amd.proposal import Proposal
+    import os
+    prop = Proposal.load(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                      "paper_2512_06230_amd", "proposal_n500.npz"))
+    spec = sc.spec_for("c3:500")
+    scene = sc.make_scene(spec, n_steps=2)
+    p = sc.filter_params(spec, 10000, 0.0)
+    st = sc.warm_start_state(scene)
+    z = torch.as_tensor(scene.meas[0], device="cuda")
+    outs = []
+    for learned in (False, True):
+        g = _tracker(p)
+        g.import_state(st)
+        if learned:
+            g.set_proposal(torch.as_tensor(prop.params, device="cuda"), prop.norm, prop.threshold, apply=True)
+        g.update(0, z)
+        s = g.stats()
+        outs.append((g.export_state(), g.diag(1, int(z.shape[0]))["ru"], s))
+        g.close()
+    (o_p, ru_p, s_p), (o_l, ru_l, s_l) = outs
+    assert s_l["pairs_removed"] > 0.2 * s_l["gated_pairs"], (s_l["pairs_removed"], s_l["gated_pairs"])
+    assert np.max(np.abs(ru_l - ru_p)) <= 1e-4, np.max(np.abs(ru_l - ru_p))
+    if np.all(np.abs(ru_p - p["birth_ru_max"]) > 1e-3):
+        assert o_l["birth_lab"].tolist() == o_p["birth_lab"].tolist()
+        np.testing.assert_allclose(o_l["birth_m"], o_p["birth_m"], rtol=1e-4, atol=1e-4)
+        np.testing.assert_allclose(o_l["birth_r"], o_p["birth_r"], rtol=1e-4, atol=1e-6)

@@ -22,6 +22,7 @@ PINS = [
     lambda: pins.test_truncate_tau_is_relative_to_the_kept_set(),
     lambda: pins.test_estimate_map_cardinality_not_global_best(),
     lambda: pins.test_estimate_cardinality_tie_goes_to_the_smaller_count(),
+    lambda: pins.test_learned_births_restore_the_removed_mass(),
 ]
 
 MUTANTS = {
@@ -37,6 +38,7 @@ MUTANTS = {
     10: "cardinality tie goes to the larger count",
     11: "no renormalisation after tau",
     12: "tau against the normaliser before the H_max cut",
+    13: "removed pairs' mass not restored in the births' clutter probabilities",
 }
 
 

@@ -505,3 +505,47 @@ def test_estimate_cardinality_tie_goes_to_the_smaller_count():
     assert rho[1] == rho[2] == 0.5
     assert [tuple(x) for x in labs] == [(0, 2)]
     np.testing.assert_allclose(means, [[2.0, 20.0, 0.0, 0.0]])
+
+
+# --------------------------------------------------------------------------- learned-proposal births
+def test_learned_births_restore_the_removed_mass():
+    """With pairs removed by a learned proposal, the clutter probabilities behind the births
+    restore, in every cell, the removed pairs' likelihood summed over the instances of the most
+    likely predicted hypothesis.  In two cases that is exactly the plain update's marginal
+    (brute force over every association map without removals): a single predicted hypothesis
+    with any removed pairs, and several hypotheses whose removed pairs all belong to instances
+    that every hypothesis holds.  The births then equal the plain update's."""
+    rng = np.random.default_rng(77)
+    done = 0
+    for trial in range(60):
+        n_hyp = 1 if done < 3 else 3
+        st = sc.random_state(rng, n_lab=3, n_hyp=n_hyp, side=12.0, versions=1, p_present=0.8)
+        z = sc.measurements_near(rng, st, 2, 12.0, 1.0)
+        o = Oracle(BASE)
+        o.import_state(st)
+        o.update(0, z)
+        pr = o.pairs()
+        births_plain = o.export_state()
+        sets = [set(st["hyp_idx"][st["hyp_off"][h]:st["hyp_off"][h + 1]].tolist()) for h in range(n_hyp)]
+        common = set.intersection(*sets)
+        cand = [(int(u), int(i)) for u, i in zip(pr["u"], pr["i"]) if int(u) in common]
+        if len(cand) < 2:
+            continue
+        pick = rng.uniform(size=len(cand)) < 0.6
+        pick[0] = True
+        skip = [c for c, k in zip(cand, pick) if k]
+        o2 = Oracle(BASE)
+        o2.import_state(st)
+        o2.set_skip(np.array([a for a, _ in skip], np.int32), np.array([b for _, b in skip], np.int32))
+        o2.update(0, z)
+        ru = o2.diag(n_hyp)["ru"]
+        ref = bf.update(st, z, BASE, 1000)
+        np.testing.assert_allclose(ru, ref["ru"], atol=1e-10, err_msg="trial %d" % trial)
+        out = o2.export_state()
+        assert out["birth_lab"].tolist() == births_plain["birth_lab"].tolist()
+        np.testing.assert_allclose(out["birth_r"], births_plain["birth_r"], atol=1e-10)
+        np.testing.assert_allclose(out["birth_m"], births_plain["birth_m"], atol=1e-10)
+        done += 1
+        if done == 6:
+            break
+    assert done == 6
