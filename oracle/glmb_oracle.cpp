@@ -22,6 +22,14 @@
  *     {clutter} + its tracks; log W(h, theta) = log w_h - gamma |J_h| + sum_i phi_{h,i}(theta_i)
  *     (parent weight times the likelihood of the associations, Sec. 3 end);
  *   - the H_max most likely children are retained, then tau pruning (Sec. 3 end).
+ *
+ * Sampled children (the paper's own generator, Sec. 3 hypothesis generation): instead of
+ * the exact top-H_max, H_up association maps are drawn per predicted hypothesis, each
+ * measurement independently from the normalised row of the compatibility matrix over
+ * clutter and that hypothesis' tracks; only the distinct maps are kept, weighted by the
+ * parent weight times their association likelihood, then tau and H_max.  The uniform
+ * numbers come from the counter-based generator Philox4x32-10 (Salmon, Moraes, Dror and
+ * Shaw, SC'11) keyed by a seed and indexed by (measurement, draw, hypothesis rank).
  */
 #include <algorithm>
 #include <cmath>
@@ -44,6 +52,49 @@
 namespace {
 
 const double kNegInf = -std::numeric_limits<double>::infinity();
+
+// Philox4x32-10 as published by Salmon et al. (SC'11): a 4 x 32-bit counter is mixed by ten
+// rounds; each round multiplies words 0 and 2 by fixed odd constants, takes the high and low
+// halves of the 64-bit products and xors the high halves with the other two words and the
+// two key words; the key is advanced by the two Weyl constants before every round after
+// the first.
+static void philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  const uint64_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;
+  const uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
+  uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+  uint32_t k0 = key[0], k1 = key[1];
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += kW0;
+      k1 += kW1;
+    }
+    const uint64_t p0 = kM0 * (uint64_t)x0;
+    const uint64_t p1 = kM1 * (uint64_t)x2;
+    const uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+    const uint32_t y1 = (uint32_t)p1;
+    const uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+    const uint32_t y3 = (uint32_t)p0;
+    x0 = y0;
+    x1 = y1;
+    x2 = y2;
+    x3 = y3;
+  }
+  out[0] = x0;
+  out[1] = x1;
+  out[2] = x2;
+  out[3] = x3;
+}
+
+// Uniform number in [0, 1) with 24 bits (exactly representable in single precision) from
+// the first output word of Philox at counter (a, b, c, stream).
+static double philox_uniform(uint64_t seed, uint32_t a, uint32_t b, uint32_t c, uint32_t stream) {
+  const uint32_t ctr[4] = {a, b, c, stream};
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t out[4];
+  philox4x32_10(ctr, key, out);
+  return (double)(out[0] >> 8) * (1.0 / 16777216.0);
+}
+const uint32_t kStreamAssoc = 1;  // Philox stream of the association draws
 const double kLog2Pi = std::log(2.0 * M_PI);
 
 struct Params {
@@ -330,6 +381,12 @@ struct Oracle {
   std::vector<double> d_pair_phi, d_pair_mass, d_pair_exist;
   // pairs removed from the option sets by a proposal (instance input index, measurement)
   std::vector<std::pair<int32_t, int32_t>> skip;
+  // sampled children instead of the exact top-H_max (h_up draws per parent; 0 = exact)
+  int32_t sample_hup = 0;
+  uint64_t sample_seed = 0;
+  double sample_margin = 1e-6;        // a draw whose uniform lies this close to a boundary is fragile
+  std::vector<int32_t> d_fragile;     // parents (input rank) with at least one fragile draw
+  int64_t d_draws = 0, d_unique = 0;  // draws made and distinct maps among them
   double d_lost = 0.0;
   std::string err;
 
@@ -649,81 +706,157 @@ struct Oracle {
       for (int32_t h = 0; h < H; ++h) lost += std::exp(logZfull[h] - LZf) * (1.0 - std::exp(logZ[h] - logZfull[h]));
       d_lost = lost;
     }
-    // Lower bound on the K-th best child value: the K-th largest among the best children and
-    // the single-deviation children (all of them are children).  A deviation delta with
-    // B_h - delta below it belongs to no retained child, so each parent's deviation list is
-    // cut to the delta-prefix B_h - delta >= bound (item positions are unchanged by the cut).
-    double bound = kNegInf;
-    {
-      std::vector<double> cand;
+    // children to keep, in rank order: (parent, value, association map)
+    struct Kept {
+      int32_t parent;
+      double value;
+      std::vector<OptKey> th;
+    };
+    std::vector<Kept> kept;
+    if (sample_hup > 0) {
+      // The paper's generator (Sec. 3 hypothesis generation): per predicted hypothesis,
+      // sample_hup association maps, every measurement drawn independently from the
+      // normalised row of the compatibility matrix over clutter and the hypothesis' tracks
+      // (options in key order: clutter, then tracks by label); only distinct maps are kept,
+      // each weighted by its exact log W (parent weight times association likelihood).
+      struct Drawn {
+        int32_t parent, draw;
+        double value;
+        std::vector<OptKey> th;
+      };
+      std::vector<Drawn> drawn;
+      std::map<std::pair<int32_t, std::vector<OptKey>>, bool> seen;
+      d_fragile.clear();
+      d_draws = 0;
       for (int32_t h = 0; h < H; ++h) {
-        cand.push_back(B[h]);
-        for (int i = 0; i < M; ++i)
-          if (std::isfinite(dev1[(size_t)h * M + i])) cand.push_back(B[h] - dev1[(size_t)h * M + i]);
-      }
-      if ((int)cand.size() >= p.hmax) {
-        std::nth_element(cand.begin(), cand.begin() + (p.hmax - 1), cand.end(), std::greater<double>());
-        bound = cand[p.hmax - 1];
-      }
-    }
-    std::vector<ParentSpec> specs(H);
-    for (int32_t h = 0; h < H; ++h) {
-      ParentSpec& s = specs[h];
-      s.base = B[h];
-      bool any = false;
-      for (int i = 0; i < M; ++i)
-        if (B[h] - dev1[(size_t)h * M + i] >= bound) any = true;
-      if (!any) continue;
-      options(h, o, false);
-      for (int i = 0; i < M; ++i) {
-        if (o[i].size() < 2) continue;
-        GroupSpec g;
-        g.id = i;
-        for (size_t r = 1; r < o[i].size(); ++r) {
-          const double d = o[i][0].first - o[i][r].first;
-          if (B[h] - d >= bound) g.devs.push_back({d, o[i][r].second});
+        options(h, o, false);
+        for (auto& v : o)
+          std::sort(v.begin(), v.end(), [](const std::pair<double, OptKey>& x, const std::pair<double, OptKey>& y) {
+            return x.second < y.second;
+          });
+        const double base = hyp[h].logw - p.gamma * (double)hyp[h].inst.size();
+        bool fragile = false;
+        for (int32_t d = 0; d < sample_hup; ++d) {
+          std::vector<OptKey> th(M);
+          double v = base;
+          for (int i = 0; i < M; ++i) {
+            const double u = philox_uniform(sample_seed, (uint32_t)i, (uint32_t)d, (uint32_t)h, kStreamAssoc);
+            double tot = 0.0;
+            for (auto& x : o[i])
+              if (ORACLE_MUTANT != 14 || x.second.track) tot += std::exp(x.first);  // planted 14: no clutter term
+            // first option whose cumulative probability exceeds u
+            double cum = 0.0, below = 0.0;
+            size_t pick = o[i].size() - 1;
+            for (size_t r = 0; r < o[i].size(); ++r) {
+              below = cum;
+              cum += std::exp(o[i][r].first) / tot;
+              if (u < cum) {
+                pick = r;
+                break;
+              }
+            }
+            if ((pick > 0 && u - below < sample_margin) || (pick + 1 < o[i].size() && cum - u < sample_margin))
+              fragile = true;
+            th[i] = o[i][pick].second;
+            v += o[i][pick].first;
+          }
+          ++d_draws;
+          auto key = std::make_pair(h, th);
+          if (seen.count(key)) continue;
+          seen[key] = true;
+          drawn.push_back({h, d, v, th});
         }
-        if (!g.devs.empty()) s.groups.push_back(g);
+        if (fragile) d_fragile.push_back(h);
+      }
+      d_unique = (int64_t)drawn.size();
+      // rank order: value descending, then (parent rank, first draw) ascending; keep H_max
+      std::sort(drawn.begin(), drawn.end(), [](const Drawn& x, const Drawn& y) {
+        if (x.value != y.value) return x.value > y.value;
+        if (x.parent != y.parent) return x.parent < y.parent;
+        return x.draw < y.draw;
+      });
+      if ((int)drawn.size() > p.hmax) drawn.resize(p.hmax);
+      for (auto& x : drawn) kept.push_back({x.parent, x.value, x.th});
+    } else {
+    // Lower bound on the K-th best child value: the K-th largest among the best children and
+      // the single-deviation children (all of them are children).  A deviation delta with
+      // B_h - delta below it belongs to no retained child, so each parent's deviation list is
+      // cut to the delta-prefix B_h - delta >= bound (item positions are unchanged by the cut).
+      double bound = kNegInf;
+      {
+        std::vector<double> cand;
+        for (int32_t h = 0; h < H; ++h) {
+          cand.push_back(B[h]);
+          for (int i = 0; i < M; ++i)
+            if (std::isfinite(dev1[(size_t)h * M + i])) cand.push_back(B[h] - dev1[(size_t)h * M + i]);
+        }
+        if ((int)cand.size() >= p.hmax) {
+          std::nth_element(cand.begin(), cand.begin() + (p.hmax - 1), cand.end(), std::greater<double>());
+          bound = cand[p.hmax - 1];
+        }
+      }
+      std::vector<ParentSpec> specs(H);
+      for (int32_t h = 0; h < H; ++h) {
+        ParentSpec& s = specs[h];
+        s.base = B[h];
+        bool any = false;
+        for (int i = 0; i < M; ++i)
+          if (B[h] - dev1[(size_t)h * M + i] >= bound) any = true;
+        if (!any) continue;
+        options(h, o, false);
+        for (int i = 0; i < M; ++i) {
+          if (o[i].size() < 2) continue;
+          GroupSpec g;
+          g.id = i;
+          for (size_t r = 1; r < o[i].size(); ++r) {
+            const double d = o[i][0].first - o[i][r].first;
+            if (B[h] - d >= bound) g.devs.push_back({d, o[i][r].second});
+          }
+          if (!g.devs.empty()) s.groups.push_back(g);
+        }
+      }
+      // exact top-H_max children (Sec. 3 end); the association map of each is its parent's
+      // best option in every cell, with the picked deviations
+      std::vector<Child> ch = top_k(specs, p.hmax);
+      std::map<int32_t, std::vector<OptKey>> best_of;
+      for (const Child& c : ch) {
+        if (!best_of.count(c.parent)) {
+          options(c.parent, o, false);
+          std::vector<OptKey> b(M);
+          for (int i = 0; i < M; ++i) b[i] = o[i][0].second;
+          best_of[c.parent] = b;
+        }
+        std::vector<OptKey> th = best_of[c.parent];
+        const ParentSpec& s = specs[c.parent];
+        for (auto& pk : c.picks) {
+          const GroupSpec& g = s.groups[pk.first];
+          th[g.id] = g.devs[pk.second - 1].second;
+        }
+        kept.push_back({c.parent, c.value, th});
       }
     }
-    // exact top-H_max children (Sec. 3 end)
-    std::vector<Child> ch = top_k(specs, p.hmax);
     std::vector<double> vals;
-    for (auto& c : ch) vals.push_back(c.value);
+    for (auto& c : kept) vals.push_back(c.value);
     double zr = lse(vals);
     // tau pruning on weights normalised over the retained set; the best child is kept
-    size_t keep = ch.size();
+    size_t keep = kept.size();
     if (p.tau > 0.0) {
       keep = 1;
-      while (keep < ch.size() && std::exp(ch[keep].value - zr) >= p.tau) ++keep;
+      while (keep < kept.size() && std::exp(kept[keep].value - zr) >= p.tau) ++keep;
     }
-    ch.resize(keep);
+    kept.resize(keep);
     vals.resize(keep);
     zr = lse(vals);
     d_retained = std::exp(zr - LZ);
-    // best option of every cell of every retained parent
-    std::map<int32_t, std::vector<OptKey>> best_of;
-    for (const Child& c : ch) {
-      if (best_of.count(c.parent)) continue;
-      options(c.parent, o, false);
-      std::vector<OptKey> b(M);
-      for (int i = 0; i < M; ++i) b[i] = o[i][0].second;
-      best_of[c.parent] = b;
-    }
     // materialise: one new instance per distinct (predicted instance, detection set);
     // its density is the Kalman update with those detections (Sec. 3 end, batched update of
     // the unique (track, measurement) associations)
     std::map<std::pair<int32_t, std::vector<int32_t>>, int32_t> made;
     std::vector<Inst> ninst;
     std::vector<Hyp> nh;
-    for (const Child& c : ch) {
+    for (const Kept& c : kept) {
       const Hyp& ph = hyp[c.parent];
-      const ParentSpec& s = specs[c.parent];
-      std::vector<OptKey> th = best_of[c.parent];
-      for (auto& pk : c.picks) {
-        const GroupSpec& g = s.groups[pk.first];
-        th[g.id] = g.devs[pk.second - 1].second;
-      }
+      const std::vector<OptKey>& th = c.th;
       // detection set of every track of the parent (ph.inst is sorted by label)
       std::vector<std::vector<int32_t>> S(ph.inst.size());
       Hyp h;
@@ -1013,6 +1146,29 @@ void orc_set_skip(void* hd, int n, const int32_t* u, const int32_t* i) {
   Oracle* o = static_cast<Oracle*>(hd);
   o->skip.clear();
   for (int k = 0; k < n; ++k) o->skip.push_back({u[k], i[k]});
+}
+
+// sampled children in the following updates: h_up draws per parent (0 = exact top-H_max)
+void orc_set_sampling(void* hd, int h_up, uint64_t seed, double margin) {
+  Oracle* o = static_cast<Oracle*>(hd);
+  o->sample_hup = h_up;
+  o->sample_seed = seed;
+  o->sample_margin = margin;
+}
+
+// draws and distinct maps of the last sampled update; parents with a fragile draw (up to cap)
+int orc_sample_stats(void* hd, int64_t* counts, int32_t* fragile, int cap) {
+  Oracle* o = static_cast<Oracle*>(hd);
+  counts[0] = o->d_draws;
+  counts[1] = o->d_unique;
+  const int n = (int)o->d_fragile.size();
+  for (int k = 0; k < n && k < cap; ++k) fragile[k] = o->d_fragile[k];
+  return n;
+}
+
+void orc_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) { philox4x32_10(ctr, key, out); }
+double orc_philox_uniform(uint64_t seed, uint32_t a, uint32_t b, uint32_t c, uint32_t stream) {
+  return philox_uniform(seed, a, b, c, stream);
 }
 
 }  // extern "C"

@@ -56,6 +56,14 @@ def _load(path: str = None):
         L.orc_diag.argtypes = [vp, dp, dp, dp, dp]
         L.orc_pairs.argtypes = [vp, ip, ip, dp, dp, dp]
         L.orc_set_skip.argtypes = [vp, ctypes.c_int, ip, ip]
+        L.orc_set_sampling.argtypes = [vp, ctypes.c_int, ctypes.c_uint64, ctypes.c_double]
+        L.orc_sample_stats.argtypes = [vp, i64p, ip, ctypes.c_int]
+        L.orc_sample_stats.restype = ctypes.c_int
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        L.orc_philox.argtypes = [u32p, u32p, u32p]
+        L.orc_philox_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                         ctypes.c_uint32]
+        L.orc_philox_uniform.restype = ctypes.c_double
         _libs[path] = L
     return _libs[path]
 
@@ -167,6 +175,19 @@ class Oracle:
         i, pi = _i32(i)
         self._L.orc_set_skip(self._h, int(len(u)), pu, pi)
 
+    def set_sampling(self, h_up: int, seed: int, margin: float = 1e-6):
+        """Following updates draw h_up association maps per parent (the paper's generator)
+        instead of the exact top-H_max; h_up = 0 restores the exact children."""
+        self._L.orc_set_sampling(self._h, int(h_up), int(seed) & 0xFFFFFFFFFFFFFFFF, float(margin))
+
+    def sample_stats(self, cap: int = 1 << 16):
+        """(draws, distinct maps, parents with a draw within the margin of a boundary)."""
+        c = np.zeros(2, np.int64)
+        fr = np.zeros(cap, np.int32)
+        n = self._L.orc_sample_stats(self._h, c.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                     fr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), cap)
+        return int(c[0]), int(c[1]), fr[:min(n, cap)].tolist()
+
     def estimate(self, cap: int = 4096):
         n = np.zeros(1, np.int32)
         labs = np.zeros((cap, 2), np.int32)
@@ -187,3 +208,18 @@ def to_f32_state(s: dict) -> dict:
     for k in ("inst_m", "inst_P", "hyp_logw", "birth_m", "birth_P", "birth_r"):
         out[k] = np.asarray(s[k], dtype=np.float32).astype(np.float64)
     return out
+
+
+def philox4x32_10(ctr, key, lib: str = None):
+    """The oracle's Philox4x32-10 block: four 32-bit words from a 4-word counter and 2-word key."""
+    L = _load(lib)
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+    L.orc_philox(P(c), P(k), P(out))
+    return out
+
+
+def philox_uniform(seed: int, a: int, b: int, c: int, stream: int, lib: str = None) -> float:
+    return float(_load(lib).orc_philox_uniform(int(seed) & 0xFFFFFFFFFFFFFFFF, a, b, c, stream))

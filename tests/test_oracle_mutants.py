@@ -8,6 +8,7 @@ import pytest
 
 from oracle import oracle as orc
 from tests import test_oracle_pins as pins
+from tests import test_sampler_oracle as sampler
 
 PINS = [
     lambda: pins.test_predict_moments_match_van_loan(),
@@ -23,6 +24,8 @@ PINS = [
     lambda: pins.test_estimate_map_cardinality_not_global_best(),
     lambda: pins.test_estimate_cardinality_tie_goes_to_the_smaller_count(),
     lambda: pins.test_learned_births_restore_the_removed_mass(),
+    lambda: sampler.test_categorical_draw_follows_the_normalised_row(),
+    lambda: [sampler.test_sampled_children_are_children_with_their_exact_weights(s) for s in range(4)],
 ]
 
 MUTANTS = {
@@ -39,6 +42,7 @@ MUTANTS = {
     11: "no renormalisation after tau",
     12: "tau against the normaliser before the H_max cut",
     13: "removed pairs' mass not restored in the births' clutter probabilities",
+    14: "sampled rows normalised without the clutter entry",
 }
 
 
@@ -46,6 +50,7 @@ MUTANTS = {
 def test_planted_mistake_is_caught(mutant, tmp_path, monkeypatch):
     lib = orc.build(out=os.path.join(str(tmp_path), "liboracle_m%d.so" % mutant), mutant=mutant)
     monkeypatch.setattr(pins, "Oracle", functools.partial(orc.Oracle, lib=lib))
+    monkeypatch.setattr(sampler, "Oracle", functools.partial(orc.Oracle, lib=lib))
     failed = 0
     for pin in PINS:
         try:
