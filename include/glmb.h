@@ -113,7 +113,8 @@ typedef struct {
   int32_t rec_collisions;
   int32_t host_syncs;       /* host-device synchronisations made by the update            */
   int32_t search_form;      /* selection search of the update: 0 one workgroup, 1 one cooperative
-                               whole-GPU launch, 2 host-driven levels of whole-GPU kernels  */
+                               whole-GPU launch, 2 host-driven levels of whole-GPU kernels,
+                               3 sampled maps (glmb_set_sampling)                           */
 } glmb_step_stats;
 
 /* Library / status utilities */
@@ -145,6 +146,20 @@ glmb_status glmb_predict(glmb_ctx* ctx, int32_t k);
  * descending, canonical key ascending), applies tau, runs the Kalman update of every
  * distinct (track, detection set), and derives the birth components for scan k+1. */
 glmb_status glmb_update(glmb_ctx* ctx, int32_t k, const float* z_dev, int32_t M);
+
+/* The paper's own hypothesis generator (Sec. 3, hypothesis generation) in place of the exact
+ * h_max best maps, for the following glmb_update calls: every predicted hypothesis h draws
+ * h_up association maps, each detection independently from the normalised row of the
+ * compatibility matrix (Eq. 2) over clutter and h's gated tracks (options in order: clutter,
+ * then tracks by label; inverse distribution function of a uniform number); only distinct
+ * maps are kept, each with its exact weight (parent weight times association likelihood);
+ * then the h_max best (weight descending, then parent rank, then first draw) and tau.  The
+ * uniform numbers are Philox4x32-10 (Salmon et al., SC'11) under key `seed` at counter
+ * (detection, draw, hypothesis rank, 16 x k + 1), 24-bit.  h_up = 0 restores the exact
+ * update; 1 <= h_up <= 65536 and at most 2^30 draws (h_up x hypotheses) per update, else
+ * GLMB_E_ARG / GLMB_E_CAPACITY.  glmb_stats reports search_form 3 and the distinct maps in
+ * search_nodes. */
+glmb_status glmb_set_sampling(glmb_ctx* ctx, int32_t h_up, uint64_t seed);
 
 /* Keep the h_max first hypotheses in rank order, renormalise over them, drop the hypotheses
  * from the first weight below tau on (the first is always kept), renormalise again (Sec. 3

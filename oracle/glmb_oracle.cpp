@@ -29,7 +29,8 @@
  * clutter and that hypothesis' tracks; only the distinct maps are kept, weighted by the
  * parent weight times their association likelihood, then tau and H_max.  The uniform
  * numbers come from the counter-based generator Philox4x32-10 (Salmon, Moraes, Dror and
- * Shaw, SC'11) keyed by a seed and indexed by (measurement, draw, hypothesis rank).
+ * Shaw, SC'11) keyed by a seed and indexed by (measurement, draw, hypothesis rank, 16 x scan
+ * + 1).
  */
 #include <algorithm>
 #include <cmath>
@@ -740,7 +741,8 @@ struct Oracle {
           std::vector<OptKey> th(M);
           double v = base;
           for (int i = 0; i < M; ++i) {
-            const double u = philox_uniform(sample_seed, (uint32_t)i, (uint32_t)d, (uint32_t)h, kStreamAssoc);
+            const double u =
+                philox_uniform(sample_seed, (uint32_t)i, (uint32_t)d, (uint32_t)h, (uint32_t)k * 16u + kStreamAssoc);
             double tot = 0.0;
             for (auto& x : o[i])
               if (ORACLE_MUTANT != 14 || x.second.track) tot += std::exp(x.first);  // planted 14: no clutter term

@@ -643,6 +643,14 @@ glmb_status glmb_mlp_grad(glmb_ctx* x, const float* params, const float* norm, c
   return guarded(x, [&](Ctx& c) { glmb::mlp_grad(c, params, norm, feat, y, w, n, grad, loss); });
 }
 
+glmb_status glmb_set_sampling(glmb_ctx* x, int32_t h_up, uint64_t seed) {
+  if (!x) return GLMB_E_ARG;
+  if (h_up < 0 || h_up > 65536) return fail(x, GLMB_E_ARG, "h_up must lie in [0, 65536]");
+  x->c.sample_hup = h_up;
+  x->c.sample_seed = seed;
+  return GLMB_OK;
+}
+
 glmb_status glmb_mlp_grad_noalloc(glmb_ctx* x, const float* params, const float* norm, const float* feat,
                                   const float* y, const float* w, int32_t n, float* grad, float* loss) {
   if (!x || !params || !norm || !grad || !loss || n < 1 || !feat || !y || !w) return GLMB_E_ARG;

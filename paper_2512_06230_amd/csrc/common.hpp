@@ -146,7 +146,8 @@ struct Selected {
   int32_t* nd_h;          // parent hypothesis
   float* nd_value;
   int levels, nodes;
-  int form;               // 0: one workgroup, 1: cooperative whole-GPU launch, 2: multi-kernel levels
+  int form;               // 0: one workgroup, 1: cooperative whole-GPU launch, 2: multi-kernel levels,
+                          // 3: sampled maps (no search)
 };
 struct SelectBufs {
   DevBuf nd_parent, nd_item, nd_h, nd_value, nd_bloom, cnt, pre, pre64, flags, map, tmp, tk, tv, keys, vals, sel_node,

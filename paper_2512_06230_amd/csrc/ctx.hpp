@@ -73,6 +73,11 @@ struct Ctx {
   int LW = 1;  // detection-set mask width (32-bit words) of the last gate
   uint32_t rec_hash_mask = 0xffffffffu;  // fingerprint bits of the (instance, detection set) records
   DevBuf rec_lead;                       // collision path: leader position of every record
+  // ---- sampled children (the paper's generator) instead of the exact selection
+  int32_t sample_hup = 0;      // association maps drawn per hypothesis (0: exact top-H_max)
+  uint64_t sample_seed = 0;    // Philox key
+  int32_t sample_unique = 0;   // distinct maps among the last update's draws
+  DevBuf s_theta, s_value, s_keys, s_vals, s_flag, s_pre, s_rkeys, s_rvals, s_selv;
 
   // ---- learned pair proposal
   bool prop_loaded = false, prop_on = false, prop_measure = false;
@@ -119,6 +124,13 @@ void mlp_adam(Ctx& c, float* params, float* m, float* v, const float* g, int t, 
 // allocation-free gradient: the partial sums live in a fixed per-device array, whose address
 // noalloc_setup (called by glmb_create with the context's device current) looks up once per device
 void noalloc_setup(int device);
+// sampled children (sample.hip): returns the number of children taken (<= K), their values
+// buffer (filled by sample_children_devs) and the kept draws in rank order
+int sample_children(Ctx& c, int k, int M, int K, float** sel_value, const uint32_t** kept_draw);
+void sample_children_devs(Ctx& c, int M, int nk, const uint32_t* kept_draw, float* sel_value, int32_t* depth,
+                          int32_t* ch_h);
+void sample_children_list(Ctx& c, int M, int nk, const uint32_t* kept_draw, const int32_t* ch_h, const int32_t* doff,
+                          int32_t* dev_i, int32_t* dev_new, int32_t* dev_old);
 void mlp_grad_noalloc(Ctx& c, const float* params, const float* norm, const float* feat, const float* y,
                       const float* w, int n, float* grad, float* loss);
 void gc_state(Ctx& c);

@@ -1543,9 +1543,26 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   float* bprime = c.bprime.as<float>();
   float* lzprime = c.lzprime.as<float>();
 
+  const int K = p.h_max;
+  const bool sampled = c.sample_hup > 0;
+  Selected sel{};
+  const int32_t* ito = nullptr;
+  const int32_t* itg = nullptr;
+  int nsel = 0;
+  const uint32_t* kept_draw = nullptr;
+  float* sel_value = nullptr;
+  if (sampled) {
+    // ---- U3 by the paper's generator: h_up maps drawn per hypothesis, distinct ones kept
+    trace(c, "update.U3.sampled", H, c.sample_hup);
+    nsel = sample_children(c, k, M, K, &sel_value, &kept_draw);
+    if (nsel < 1) throw Error{GLMB_E_STATE, "sampled update kept no hypothesis"};
+    sel.n = nsel;
+    sel.nodes = c.sample_unique;
+    sel.value = sel_value;
+    sel.form = 3;
+  } else {
   // ---- U3: lower bound of the cut, deviation items, exact selection
   trace(c, "update.U3");
-  const int K = p.h_max;
   kth_bound_cells(bprime, dev1, H, M, K, t0, c.tmp, s);
   // counting bound, first pass (from the cells' first deviations): the items are generated
   // for the children above it only
@@ -1623,7 +1640,6 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   dp_bound_items(si, c.sb, s);  // second pass: raises *tcut
   if (c.trace) dp_bound_trace(c.sb, s);
   trace(c, "update.select", it.ncell, it.nitem);
-  Selected sel{};
   std::string serr;
   const int cap_nodes = p.cap_nodes > 0 ? p.cap_nodes : (1 << 22);
   glmb_status st = select_topk(si, cap_nodes, c.sb, sel, s, serr, c.trace);
@@ -1636,10 +1652,17 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     st = select_topk(si, cap_nodes, c.sb, sel, s, serr, c.trace);
   }
   if (st != GLMB_OK) throw Error{st, serr};
-  const int32_t* ito = it.ito;
-  const int32_t* itg = it.itg;
-  const int nsel = sel.n;
+  ito = it.ito;
+  itg = it.itg;
+  nsel = sel.n;
   if (nsel < 1) throw Error{GLMB_E_STATE, "selection kept no hypothesis (non-finite weights?)"};
+  }
+  if (sampled) {
+    // values of the taken maps in rank order, with their parents and deviation counts
+    int32_t* depth0 = need<int32_t>(c.ccount, nsel + 1);
+    int32_t* chh0 = need<int32_t>(c.child_par, nsel + 1);
+    sample_children_devs(c, M, nsel, kept_draw, sel_value, depth0, chh0);
+  }
   float* wout = need<float>(c.logw2, nsel);
   GLMB_LAUNCH(k_prune, 1, 1024, 0, s, nsel, sel.value, p.tau, lz, wout, nkeep, retained);
   const int nk = read1(s, nkeep);
@@ -1650,8 +1673,9 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   int32_t* depth = need<int32_t>(c.ccount, nk + 1);
   int32_t* chh = need<int32_t>(c.child_par, nk + 1);
   int32_t* doff = need<int32_t>(c.dev_off, nk + 1);
-  GLMB_LAUNCH(k_child_depth, cdiv(nk, T), T, 0, s, nk, sel.node, sel.nd_parent, sel.nd_item, sel.nd_h, depth, chh,
-              errf);
+  if (!sampled)
+    GLMB_LAUNCH(k_child_depth, cdiv(nk, T), T, 0, s, nk, sel.node, sel.nd_parent, sel.nd_item, sel.nd_h, depth, chh,
+                errf);
   scan_excl(depth, doff, nk, doff + nk, c.tmp, s);
   // retained parents
   int32_t* mark = need<int32_t>(c.row_mark, H + 1);
@@ -1667,8 +1691,11 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   int32_t* devi = need<int32_t>(c.dev_i, ndev);
   int32_t* devn = need<int32_t>(c.dev_slot, 2 * (int64_t)ndev);
   int32_t* devo = devn + ndev;
-  GLMB_LAUNCH(k_child_devs, cdiv(nk, T), T, 0, s, nk, M, sel.node, sel.nd_parent, sel.nd_item, chh, doff, itg, ito,
-              best16, devi, devn, devo);
+  if (sampled)
+    sample_children_list(c, M, nk, kept_draw, chh, doff, devi, devn, devo);
+  else
+    GLMB_LAUNCH(k_child_devs, cdiv(nk, T), T, 0, s, nk, M, sel.node, sel.nd_parent, sel.nd_item, chh, doff, itg, ito,
+                best16, devi, devn, devo);
   int32_t* plist = need<int32_t>(c.cells, np + 1);
   int32_t* hpm = need<int32_t>(c.hp_map, H + 1);
   GLMB_LAUNCH(k_plist, cdiv(H, T), T, 0, s, H, mark, ppre, plist, hpm);

@@ -20,7 +20,7 @@ EXPORTS = ["glmb_status_string", "glmb_last_error", "glmb_create", "glmb_destroy
            "glmb_state_sizes", "glmb_export_state", "glmb_predict", "glmb_update", "glmb_truncate",
            "glmb_estimate", "glmb_stats", "glmb_update_diag", "glmb_update_theta", "glmb_set_proposal",
            "glmb_pair_features", "glmb_proposal_lost", "glmb_mlp_forward", "glmb_mlp_grad", "glmb_mlp_adam",
-           "glmb_mlp_grad_noalloc",
+           "glmb_mlp_grad_noalloc", "glmb_set_sampling",
            "glmb_batch_create", "glmb_batch_destroy", "glmb_batch_set_schedule", "glmb_batch_scene",
            "glmb_batch_step", "glmb_batch_stats_get", "glmb_batch_last_error"]
 
@@ -102,6 +102,7 @@ def load_library(path: str = LIB_PATH):
     L.glmb_mlp_forward.argtypes = [vp, vp, _F, vp, ctypes.c_int32, vp]
     L.glmb_mlp_grad.argtypes = [vp, vp, _F, vp, vp, vp, ctypes.c_int32, vp, vp]
     L.glmb_mlp_grad_noalloc.argtypes = [vp, vp, _F, vp, vp, vp, ctypes.c_int32, vp, vp]
+    L.glmb_set_sampling.argtypes = [vp, ctypes.c_int32, ctypes.c_uint64]
     L.glmb_mlp_adam.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float]
     L.glmb_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_int, ctypes.c_int32,
@@ -295,6 +296,12 @@ class Tracker:
     def _norm(norm):
         n = np.ascontiguousarray(np.asarray(norm, np.float32).reshape(12))
         return n
+
+    def set_sampling(self, h_up: int, seed: int = 0):
+        """Following updates keep the distinct maps among h_up drawn per hypothesis (the paper's
+        generator) instead of the exact h_max best; h_up = 0 restores the exact update."""
+        self._check(self._L.glmb_set_sampling(self._ctx, int(h_up), int(seed) & 0xFFFFFFFFFFFFFFFF),
+                    "glmb_set_sampling")
 
     def set_proposal(self, params, norm, threshold: float = 0.5, apply: bool = True, measure: bool = False):
         """params: CUDA float32 [4673] (None unloads the proposal); norm: 12 floats.

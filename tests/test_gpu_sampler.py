@@ -1,0 +1,146 @@
+"""The paper's hypothesis generator on the GPU (glmb_set_sampling) against the oracle's
+sampled children on the same seeded inputs: the same Philox uniforms pick the same options,
+so both sides keep the same distinct association maps with the same weights, densities and
+births.  Draws whose uniform lies within 1e-6 of a boundary of the categorical distribution
+may be decided differently in FP32 and FP64; the oracle names their parents, whose children
+are exempt from the identity checks (and weights are compared renormalised over the common
+set when such a parent exists)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.oracle import Oracle, to_f32_state
+from paper_2512_06230_amd import scenarios as sc
+from tests import parity as pt
+
+pytestmark = pytest.mark.gpu
+
+BASE = dict(dt=1.0, q=1.0, sigma_z=1.0, p_survive=0.99, det_rate=1.47, clutter_density=2e-3,
+            gate_d2=-2.0 * math.log(1e-4), birth_r_max=0.5, birth_rate=0.5, birth_sigma_v=2.0,
+            birth_ru_max=0.5, birth_cluster_d=3.0, h_max=64, tau=0.0)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def check_sampled(state, z, p, h_up, seed, k=0):
+    """One sampled update on both sides from the same FP32 state; returns (matched, stats)."""
+    from paper_2512_06230_amd.glmb import Tracker
+    st = to_f32_state(state)
+    o = Oracle(p)
+    o.import_state(st)
+    o.set_sampling(h_up, seed)
+    o.update(k, z)
+    out_o = o.export_state()
+    d_o = o.diag(len(st["hyp_logw"]))
+    draws, uniq, fragile = o.sample_stats()
+    g = Tracker(p)
+    g.import_state(st)
+    g.set_sampling(h_up, seed)
+    g.update(k, z)
+    out_g = g.export_state()
+    M = np.asarray(z).reshape(-1, 2).shape[0]
+    th_g = g.theta(len(out_g["hyp_logw"]), M)
+    d_g = g.diag(len(st["hyp_logw"]), M)
+    stats = g.stats()
+    g.close()
+    assert stats["search_form"] == 3
+    near = pt.parents_with(st, pt.near_gate_instances(st, z, p["sigma_z"], p["gate_d2"]))
+    skip = set(fragile) | near
+    if not skip:
+        assert stats["search_nodes"] == uniq, (stats["search_nodes"], uniq)  # the same distinct maps
+    ids_o = pt.update_ids(out_o, out_o["theta"])
+    ids_g = pt.update_ids(out_g, th_g)
+    lw_o, lw_g = np.asarray(out_o["hyp_logw"], np.float64), np.asarray(out_g["hyp_logw"], np.float64)
+    if skip:
+        # weights renormalised over the identities both sides hold
+        common = set(ids_o) & set(ids_g)
+        io = np.array([x in common for x in ids_o])
+        ig = np.array([x in common for x in ids_g])
+        if io.any():
+            lw_o = lw_o - np.logaddexp.reduce(lw_o[io])
+            lw_g = lw_g - np.logaddexp.reduce(lw_g[ig])
+    matched = pt.compare_sets(ids_o, lw_o, ids_g, lw_g, skip)
+    pt.compare_densities(out_o, ids_o, out_g, ids_g, skip)
+    if not skip:
+        assert np.all(np.abs(d_g["ru"] - d_o["ru"]) <= 1e-4)
+    stats["fragile"] = fragile
+    stats["matched"] = matched
+    return matched, stats
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_sampled_update_random_states(torch_cuda, seed):
+    rng = np.random.default_rng(700 + seed)
+    st = sc.random_state(rng, n_lab=3 + seed % 4, n_hyp=2 + 3 * (seed % 3), side=15.0, versions=1 + seed % 2)
+    z = sc.measurements_near(rng, st, 2 + seed % 3, 15.0, 1.0)
+    for h_up, K in ((1, 64), (7, 5), (64, 1000)):
+        matched, s = check_sampled(st, z, dict(BASE, h_max=K), h_up, 1000 + seed)
+        assert matched > 0 or s["fragile"]
+
+
+def test_sampled_update_seed_and_scan_change_the_draws(torch_cuda):
+    from paper_2512_06230_amd.glmb import Tracker
+    rng = np.random.default_rng(3)
+    st = to_f32_state(sc.random_state(rng, n_lab=5, n_hyp=4, side=15.0, versions=2))
+    z = sc.measurements_near(rng, st, 3, 15.0, 1.0)
+    res = []
+    for seed, k in ((5, 0), (5, 0), (6, 0), (5, 1)):
+        g = Tracker(dict(BASE, h_max=1000))
+        g.import_state(st)
+        g.set_sampling(6, seed)
+        g.update(k, z)
+        out = g.export_state()
+        res.append(sorted(pt.update_ids(out, g.theta(len(out["hyp_logw"]), z.shape[0]))))
+        g.close()
+    assert res[0] == res[1]
+    assert res[0] != res[2] and res[0] != res[3]
+
+
+def test_sampled_update_along_a_scene(torch_cuda):
+    """The paper's setting (H_up = 100, tau = 1e-5) on the 5-object scene: the GPU filter runs
+    with sampled children; at every scan its predicted state is updated by both sides."""
+    from paper_2512_06230_amd.glmb import Tracker
+    spec = sc.spec_for("c1")
+    scene = sc.make_scene(spec, n_steps=8)
+    p = sc.filter_params(spec, 100, 1e-5)
+    g = Tracker(p)
+    g.import_state(sc.empty_state())
+    g.set_sampling(100, 77)
+    checked = 0
+    for k in range(8):
+        g.predict(k)
+        pre = g.export_state()
+        matched, s = check_sampled(pre, scene.meas[k], p, 100, 77, k)
+        checked += matched
+        g.update(k, scene.meas[k])
+        g.truncate(p["h_max"], p["tau"])
+    g.close()
+    assert checked > 50
+
+
+@pytest.mark.slow
+def test_sampled_update_hundred_objects(torch_cuda):
+    """A 100-object scene with 1000 predicted hypotheses and 16 maps each (16000 draws)."""
+    from paper_2512_06230_amd.glmb import Tracker
+    spec = sc.spec_for("c3:100")
+    scene = sc.make_scene(spec, n_steps=3)
+    p = sc.filter_params(spec, 1000, 0.0)
+    g = Tracker(p)
+    g.import_state(sc.warm_start_state(scene))
+    for k in range(2):
+        g.predict(k)
+        g.update(k, scene.meas[k])
+        g.truncate(1000, 0.0)
+    g.predict(2)
+    pre = g.export_state()
+    g.close()
+    matched, s = check_sampled(pre, scene.meas[2], p, 16, 4242, 2)
+    print("matched %d of %d kept, %d distinct maps, fragile parents %d" % (
+        matched, s["n_hyp_out"], s["search_nodes"], len(s["fragile"])), flush=True)
+    assert matched >= 0.9 * s["n_hyp_out"]
