@@ -317,6 +317,53 @@ static void kalman_predict(const double F[16], const double Q[16], double m[4], 
 
 // Update with n >= 1 detections z_1..z_n of the same object: equivalent to one update with
 // their mean and noise R/n (the product of n Gaussians in Hx is Gaussian in the mean).
+// Joint likelihood of a detection set S given a track with density N(x; m, P) (the "joint
+// likelihood of the sampled associations", Sec. 3 end): the marginal density of the stacked
+// detections, vec(z_S) ~ N(1 (x) H m, 1 1^T (x) H P H^T + I (x) R), by plain Gaussian
+// elimination on the 2|S| x 2|S| covariance.
+static double joint_loglik(double sigma, const std::vector<const double*>& zs, const double m[4], const double P[16]) {
+  const int n = (int)zs.size(), d = 2 * n;
+  std::vector<double> C((size_t)d * d), r(d);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b)
+      for (int p = 0; p < 2; ++p)
+        for (int q = 0; q < 2; ++q)
+          C[(size_t)(2 * a + p) * d + (2 * b + q)] =
+              (ORACLE_MUTANT == 15 && a != b ? 0.0 : P[p * 4 + q]) +  // planted 15: detections independent
+              (a == b && p == q ? sigma * sigma : 0.0);
+  for (int a = 0; a < n; ++a)
+    for (int p = 0; p < 2; ++p) r[2 * a + p] = zs[a][p] - m[p];
+  // Gaussian elimination with partial pivoting: log|C| and C^-1 r
+  double logdet = 0.0;
+  for (int c = 0; c < d; ++c) {
+    int piv = c;
+    for (int k = c + 1; k < d; ++k)
+      if (std::fabs(C[(size_t)k * d + c]) > std::fabs(C[(size_t)piv * d + c])) piv = k;
+    if (piv != c) {
+      for (int j = 0; j < d; ++j) std::swap(C[(size_t)c * d + j], C[(size_t)piv * d + j]);
+      std::swap(r[c], r[piv]);
+    }
+    const double dg = C[(size_t)c * d + c];
+    logdet += std::log(std::fabs(dg));
+    for (int k = c + 1; k < d; ++k) {
+      const double f = C[(size_t)k * d + c] / dg;
+      for (int j = c; j < d; ++j) C[(size_t)k * d + j] -= f * C[(size_t)c * d + j];
+      r[k] -= f * r[c];
+    }
+  }
+  // back substitution; the quadratic form is r0^T C^-1 r0 = sum of the eliminated system's terms
+  std::vector<double> x(d);
+  for (int c = d - 1; c >= 0; --c) {
+    double v = r[c];
+    for (int j = c + 1; j < d; ++j) v -= C[(size_t)c * d + j] * x[j];
+    x[c] = v / C[(size_t)c * d + c];
+  }
+  double quad = 0.0;
+  for (int a = 0; a < n; ++a)
+    for (int p = 0; p < 2; ++p) quad += (zs[a][p] - m[p]) * x[2 * a + p];
+  return -0.5 * d * std::log(2.0 * M_PI) - 0.5 * logdet - 0.5 * quad;
+}
+
 static void kalman_update_multi(double sigma, const std::vector<const double*>& zs, double m[4],
                                 double P[16]) {
   const double n = (double)zs.size();
@@ -385,6 +432,8 @@ struct Oracle {
   // sampled children instead of the exact top-H_max (h_up draws per parent; 0 = exact)
   int32_t sample_hup = 0;
   uint64_t sample_seed = 0;
+  // exact-joint reweighting of the kept hypotheses (joint likelihood of each detection set)
+  bool joint_rw = false;
   double sample_margin = 1e-6;        // a draw whose uniform lies this close to a boundary is fragile
   std::vector<int32_t> d_fragile;     // parents (input rank) with at least one fragile draw
   int64_t d_draws = 0, d_unique = 0;  // draws made and distinct maps among them
@@ -856,6 +905,7 @@ struct Oracle {
     std::map<std::pair<int32_t, std::vector<int32_t>>, int32_t> made;
     std::vector<Inst> ninst;
     std::vector<Hyp> nh;
+    std::vector<double> jcorr;
     for (const Kept& c : kept) {
       const Hyp& ph = hyp[c.parent];
       const std::vector<OptKey>& th = c.th;
@@ -873,8 +923,17 @@ struct Oracle {
         S[j].push_back(i);
         h.theta[i] = inst[ph.inst[j]].src;
       }
+      double corr = 0.0;  // joint reweighting: log J(u, S) - sum_{i in S} log l_ui over the tracks
       for (size_t j = 0; j < ph.inst.size(); ++j) {
         const int32_t u = ph.inst[j];
+        if (joint_rw && S[j].size() >= 2) {
+          std::vector<const double*> zs;
+          for (int32_t i : S[j]) zs.push_back(z + 2 * i);
+          corr += joint_loglik(p.sigma, zs, inst[u].m, inst[u].P);
+          for (int32_t i : S[j])
+            for (const G& g : gated[u])
+              if (g.i == i) corr -= g.phi - lgg;
+        }
         auto key = std::make_pair(u, S[j]);
         auto it = made.find(key);
         int32_t id;
@@ -895,6 +954,36 @@ struct Oracle {
         h.inst.push_back(id);
       }
       nh.push_back(h);
+      jcorr.push_back(corr);
+    }
+    if (joint_rw && !nh.empty()) {
+      // Exact-joint reweighting of the kept hypotheses: every track's product of per-detection
+      // likelihoods is replaced by the joint likelihood of its detection set; the hypotheses
+      // are re-ranked by the new weight (stable), tau is applied to the renormalised weights
+      // (the best is kept) and the kept ones renormalised.
+      std::vector<size_t> ord(nh.size());
+      std::vector<double> v(nh.size());
+      for (size_t q = 0; q < nh.size(); ++q) {
+        ord[q] = q;
+        v[q] = nh[q].logw + jcorr[q];
+      }
+      std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return v[a] > v[b]; });
+      std::vector<double> vs;
+      for (size_t q : ord) vs.push_back(v[q]);
+      double zj = lse(vs);
+      size_t keepj = vs.size();
+      if (p.tau > 0.0) {
+        keepj = 1;
+        while (keepj < vs.size() && std::exp(vs[keepj] - zj) >= p.tau) ++keepj;
+      }
+      vs.resize(keepj);
+      zj = lse(vs);
+      std::vector<Hyp> nh2;
+      for (size_t q = 0; q < keepj; ++q) {
+        nh2.push_back(nh[ord[q]]);
+        nh2.back().logw = vs[q] - zj;
+      }
+      nh.swap(nh2);
     }
     // births for the next scan from measurements that the posterior leaves unexplained
     make_births(k + 1, z, M);
@@ -1169,6 +1258,16 @@ int orc_sample_stats(void* hd, int64_t* counts, int32_t* fragile, int cap) {
 }
 
 void orc_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) { philox4x32_10(ctr, key, out); }
+
+// exact-joint reweighting of the kept hypotheses in the following updates (0 = factorised)
+void orc_set_joint(void* hd, int on) { static_cast<Oracle*>(hd)->joint_rw = on != 0; }
+
+// joint log-likelihood of n detections (z[2n]) given a track density N(m, P)
+double orc_joint_loglik(double sigma, int n, const double* z, const double* m, const double* P) {
+  std::vector<const double*> zs;
+  for (int a = 0; a < n; ++a) zs.push_back(z + 2 * a);
+  return joint_loglik(sigma, zs, m, P);
+}
 double orc_philox_uniform(uint64_t seed, uint32_t a, uint32_t b, uint32_t c, uint32_t stream) {
   return philox_uniform(seed, a, b, c, stream);
 }

@@ -64,6 +64,9 @@ def _load(path: str = None):
         L.orc_philox_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                          ctypes.c_uint32]
         L.orc_philox_uniform.restype = ctypes.c_double
+        L.orc_set_joint.argtypes = [vp, ctypes.c_int]
+        L.orc_joint_loglik.argtypes = [ctypes.c_double, ctypes.c_int, dp, dp, dp]
+        L.orc_joint_loglik.restype = ctypes.c_double
         _libs[path] = L
     return _libs[path]
 
@@ -180,6 +183,11 @@ class Oracle:
         instead of the exact top-H_max; h_up = 0 restores the exact children."""
         self._L.orc_set_sampling(self._h, int(h_up), int(seed) & 0xFFFFFFFFFFFFFFFF, float(margin))
 
+    def set_joint(self, on: bool):
+        """Following updates reweight the kept hypotheses with the joint likelihood of every
+        track's detection set (instead of the product of per-detection likelihoods)."""
+        self._L.orc_set_joint(self._h, 1 if on else 0)
+
     def sample_stats(self, cap: int = 1 << 16):
         """(draws, distinct maps, parents with a draw within the margin of a boundary)."""
         c = np.zeros(2, np.int64)
@@ -223,3 +231,12 @@ def philox4x32_10(ctr, key, lib: str = None):
 
 def philox_uniform(seed: int, a: int, b: int, c: int, stream: int, lib: str = None) -> float:
     return float(_load(lib).orc_philox_uniform(int(seed) & 0xFFFFFFFFFFFFFFFF, a, b, c, stream))
+
+
+def joint_loglik(sigma: float, z, m, P, lib: str = None) -> float:
+    """The oracle's joint log-likelihood of detections z [n, 2] given a track N(m, P)."""
+    L = _load(lib)
+    z, pz = _f64(np.asarray(z, np.float64).reshape(-1, 2))
+    m, pm = _f64(np.asarray(m, np.float64).reshape(4))
+    P, pP = _f64(np.asarray(P, np.float64).reshape(16))
+    return float(L.orc_joint_loglik(float(sigma), int(z.shape[0]), pz, pm, pP))

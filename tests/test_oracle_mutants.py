@@ -3,11 +3,13 @@ a wrong coefficient, a transposed operand, a missing search rule, a wrong tie-br
 a missing cap) built into a copy of the oracle on the CPU fails at least one pin."""
 import functools
 import os
+import types
 
 import pytest
 
 from oracle import oracle as orc
 from tests import test_oracle_pins as pins
+from tests import test_joint_oracle as joint
 from tests import test_sampler_oracle as sampler
 
 PINS = [
@@ -26,6 +28,8 @@ PINS = [
     lambda: pins.test_learned_births_restore_the_removed_mass(),
     lambda: sampler.test_categorical_draw_follows_the_normalised_row(),
     lambda: [sampler.test_sampled_children_are_children_with_their_exact_weights(s) for s in range(4)],
+    lambda: joint.test_joint_loglik_matches_sequential_kalman(2),
+    lambda: [joint.test_reweighted_update_matches_bruteforce(s) for s in range(2)],
 ]
 
 MUTANTS = {
@@ -43,6 +47,7 @@ MUTANTS = {
     12: "tau against the normaliser before the H_max cut",
     13: "removed pairs' mass not restored in the births' clutter probabilities",
     14: "sampled rows normalised without the clutter entry",
+    15: "joint likelihood without the shared track uncertainty between detections",
 }
 
 
@@ -51,6 +56,8 @@ def test_planted_mistake_is_caught(mutant, tmp_path, monkeypatch):
     lib = orc.build(out=os.path.join(str(tmp_path), "liboracle_m%d.so" % mutant), mutant=mutant)
     monkeypatch.setattr(pins, "Oracle", functools.partial(orc.Oracle, lib=lib))
     monkeypatch.setattr(sampler, "Oracle", functools.partial(orc.Oracle, lib=lib))
+    monkeypatch.setattr(joint, "Oracle", functools.partial(orc.Oracle, lib=lib))
+    monkeypatch.setattr(joint, "orc", types.SimpleNamespace(joint_loglik=functools.partial(orc.joint_loglik, lib=lib)))
     failed = 0
     for pin in PINS:
         try:
