@@ -161,6 +161,19 @@ glmb_status glmb_update(glmb_ctx* ctx, int32_t k, const float* z_dev, int32_t M)
  * search_nodes. */
 glmb_status glmb_set_sampling(glmb_ctx* ctx, int32_t h_up, uint64_t seed);
 
+/* Exact-joint reweighting of the kept hypotheses (Sec. 3 end: a new hypothesis' weight is its
+ * parent's times the joint likelihood of its associations), for the following glmb_update
+ * calls when on != 0: after the selection (which ranks by the factorised weights, i.e. the
+ * product of per-detection likelihoods), every track with a detection set S of two or more
+ * detections has that product replaced by the joint likelihood
+ *   J(S) = integral N(x; m, P) prod_{i in S} N(z_i; H x, R) dx
+ *        = (2 pi sigma^2)^-(|S|-1) |S|^-1 exp(-sum_i |z_i - zbar|^2 / (2 sigma^2)) N(zbar; H m, H P H^T + R/|S|);
+ * the hypotheses are re-ranked by the new weight (ties keep the selection's order), tau is
+ * applied to the renormalised weights (the best is kept) and the kept ones renormalised.
+ * glmb_update_theta lists the maps in the re-ranked order.  on = 0 restores the factorised
+ * weights. */
+glmb_status glmb_set_joint_reweighting(glmb_ctx* ctx, int32_t on);
+
 /* Keep the h_max first hypotheses in rank order, renormalise over them, drop the hypotheses
  * from the first weight below tau on (the first is always kept), renormalise again (Sec. 3
  * end). Idempotent. */

@@ -559,10 +559,18 @@ glmb_status glmb_update_theta(glmb_ctx* x, int32_t n_hyp, int32_t M, int32_t* th
     if (H * SW) GLMB_HIP(hipMemcpyAsync(prows.data(), c.rows2.p, prows.size() * 4, hipMemcpyDeviceToHost, s));
     if (UP) GLMB_HIP(hipMemcpyAsync(pinst.data(), c.inst2.p, (size_t)UP * sizeof(DInst), hipMemcpyDeviceToHost, s));
     GLMB_HIP(hipMemcpyAsync(par.data(), c.hparent.p, n * 4, hipMemcpyDeviceToHost, s));
-    GLMB_HIP(hipMemcpyAsync(doff.data(), c.dev_off.p, (n + 1) * 4, hipMemcpyDeviceToHost, s));
+    // children re-ranked by the exact-joint reweighting: child_perm names each one's position
+    // in the selection's order, which the deviation lists follow
+    std::vector<uint32_t> perm(n);
+    for (int h = 0; h < n; ++h) perm[h] = (uint32_t)h;
+    if (c.last_perm && n) GLMB_HIP(hipMemcpyAsync(perm.data(), c.child_perm.p, n * 4, hipMemcpyDeviceToHost, s));
+    int nsel = n;
+    for (int h = 0; h < n; ++h) nsel = std::max(nsel, (int)perm[h] + 1);
+    doff.resize(nsel + 1);
+    GLMB_HIP(hipMemcpyAsync(doff.data(), c.dev_off.p, (nsel + 1) * 4, hipMemcpyDeviceToHost, s));
     GLMB_HIP(stream_sync(s));
     for (int u = 0; u < UP; ++u) psrc[u] = pinst[u].src;
-    const int nd = doff[n];
+    const int nd = doff[nsel];
     std::vector<int32_t> di(nd), dn(nd);
     if (nd) {
       GLMB_HIP(hipMemcpyAsync(di.data(), c.dev_i.p, nd * 4, hipMemcpyDeviceToHost, s));
@@ -573,7 +581,8 @@ glmb_status glmb_update_theta(glmb_ctx* x, int32_t n_hyp, int32_t M, int32_t* th
       const int ph = par[h];
       std::vector<int32_t> sl(M);
       for (int i = 0; i < M; ++i) sl[i] = (int)best[(size_t)ph * M + i] - 1;
-      for (int q = doff[h]; q < doff[h + 1]; ++q) sl[di[q]] = dn[q];
+      const int o = (int)perm[h];
+      for (int q = doff[o]; q < doff[o + 1]; ++q) sl[di[q]] = dn[q];
       for (int i = 0; i < M; ++i)
         theta[(size_t)h * M + i] = sl[i] < 0 ? -1 : psrc[prows[(size_t)ph * SW + sl[i]]];
     }
@@ -648,6 +657,12 @@ glmb_status glmb_set_sampling(glmb_ctx* x, int32_t h_up, uint64_t seed) {
   if (h_up < 0 || h_up > 65536) return fail(x, GLMB_E_ARG, "h_up must lie in [0, 65536]");
   x->c.sample_hup = h_up;
   x->c.sample_seed = seed;
+  return GLMB_OK;
+}
+
+glmb_status glmb_set_joint_reweighting(glmb_ctx* x, int32_t on) {
+  if (!x) return GLMB_E_ARG;
+  x->c.joint_rw = on != 0;
   return GLMB_OK;
 }
 

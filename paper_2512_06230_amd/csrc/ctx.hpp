@@ -78,6 +78,10 @@ struct Ctx {
   uint64_t sample_seed = 0;    // Philox key
   int32_t sample_unique = 0;   // distinct maps among the last update's draws
   DevBuf s_theta, s_value, s_keys, s_vals, s_flag, s_pre, s_rkeys, s_rvals, s_selv;
+  // ---- exact-joint reweighting of the kept hypotheses (glmb_set_joint_reweighting)
+  bool joint_rw = false;
+  bool last_perm = false;  // the last update re-ranked its children: child_perm maps rank -> child
+  DevBuf j_corr, j_val, j_keys, child_perm, j_lw, j_tmp, rows3;
 
   // ---- learned pair proposal
   bool prop_loaded = false, prop_on = false, prop_measure = false;

@@ -1091,9 +1091,14 @@ __global__ void k_rec_ids(int n, const uint32_t* vals, const int32_t* flag, cons
 
 // Kalman update of every distinct (instance, detection set): the detections of one object are
 // equivalent to their mean observed with noise R / n
+// With jc non-null, also the exact-joint correction of every new instance with n >= 2
+// detections: log J(S) - sum_{i in S} log l_i, where the joint likelihood of the detection set
+// is J(S) = C_S N(zbar; H m, H P H^T + R/n) with
+// C_S = (2 pi sigma^2)^-(n-1) n^-1 exp(-sum_i |z_i - zbar|^2 / (2 sigma^2)) (the product of the
+// detections' densities around their mean, R = sigma^2 I), and log l_i = phi_i - log gamma.
 __global__ void k_kalman(int nnew, int LW, const int32_t* rep, const int32_t* ru, const uint32_t* rm,
                          const DInst* pin, const int32_t* loff, const int32_t* lmeas, const float2* z, float sig2,
-                         DInst* out, int32_t* onz, int32_t* oz) {
+                         DInst* out, int32_t* onz, int32_t* oz, const float* phi, int M, float lgg, float* jc) {
   const int id = blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= nnew) return;
   const int r = rep[id];
@@ -1139,8 +1144,98 @@ __global__ void k_kalman(int nnew, int LW, const int32_t* rep, const int32_t* ru
     int t = 0;
     for (int r0 = 0; r0 < 4; ++r0)
       for (int c0 = r0; c0 < 4; ++c0, ++t) y.P[t] = P[t] - (K0[r0] * a[c0] + K1[r0] * bq[c0]);
+    if (jc && nz >= 2) {
+      // second pass: the spread around the mean and the per-detection log likelihoods
+      float ss = 0.0f, sl = 0.0f;
+      const int u = ru[r];
+      for (int w = 0; w < LW; ++w) {
+        uint32_t b = m[w];
+        while (b) {
+          const int j = w * 32 + __ffs(b) - 1;
+          b &= b - 1;
+          const int i = lmeas[off + j];
+          const float dx = z[i].x - zb0, dy = z[i].y - zb1;
+          ss += dx * dx + dy * dy;
+          sl += phi[(size_t)u * M + i] - lgg;
+        }
+      }
+      const float l2pi = 1.8378770664093453f;  // log(2 pi)
+      const float lcs = -(float)(nz - 1) * (l2pi + logf(sig2)) - logf((float)nz) - 0.5f * ss / sig2;
+      const float quad = n0 * n0 * i00 + 2.0f * n0 * n1 * i01 + n1 * n1 * i11;
+      const float lzb = -l2pi - 0.5f * logf(det) - 0.5f * quad;
+      jc[id] = lcs + lzb - sl;
+    }
   }
+  if (jc && nz < 2) jc[id] = 0.0f;
   out[id] = y;
+}
+
+// exact-joint reweighting: one wave per kept child, its weight plus the corrections of the new
+// instances in its row (fixed order), keyed for the rank order (weight descending, then the
+// child's rank under the factorised weights)
+__global__ __launch_bounds__(256) void k_joint_child(int n, int stride, const int32_t* rows, const float* jc,
+                                                     const float* logw, float* val, uint64_t* keys, uint32_t* perm) {
+  const int c = (int)(((size_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  if (c >= n) return;
+  float a = 0.0f;
+  for (int s = lane_id(); s < stride; s += kWave) {
+    const int id = rows[(size_t)c * stride + s];
+    if (id >= 0) a += jc[id];
+  }
+  for (int d = kWave / 2; d > 0; d >>= 1) a += __shfl_xor(a, d, kWave);
+  if (lane_id() == 0) {
+    const float v = logw[c] + a;
+    val[c] = v;
+    keys[c] = ((uint64_t)(~f2o(v)) << 32) | (uint32_t)c;
+    perm[c] = (uint32_t)c;
+  }
+}
+
+// one workgroup: tau prefix of the re-ranked weights (the best is kept) and renormalisation
+__global__ __launch_bounds__(1024) void k_joint_tau(int n, const uint32_t* perm, const float* val, float tau,
+                                                    float* logw_out, int32_t* nkeep) {
+  __shared__ float red[32];
+  __shared__ int ired[32];
+  float mx = -INFINITY;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) mx = fmaxf(mx, val[perm[j]]);
+  mx = block_max_f(mx, red);
+  float sm = 0.0f;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) sm += __expf(val[perm[j]] - mx);
+  sm = block_sum_f(sm, red + 16);
+  const float L = mx + __logf(sm);
+  int keep = n;
+  if (tau > 0.0f) {
+    const float lt = __logf(tau);
+    int cnt = 0;  // sorted descending: the kept ones are a prefix
+    for (int j = threadIdx.x; j < n; j += blockDim.x) cnt += (val[perm[j]] - L >= lt) ? 1 : 0;
+    for (int d = kWave / 2; d > 0; d >>= 1) cnt += __shfl_xor(cnt, d, kWave);
+    __syncthreads();
+    if (lane_id() == 0) ired[threadIdx.x / kWave] = cnt;
+    __syncthreads();
+    keep = 0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) keep += ired[w];
+    keep = max(keep, 1);
+  }
+  float m2 = -INFINITY;
+  for (int j = threadIdx.x; j < keep; j += blockDim.x) m2 = fmaxf(m2, val[perm[j]]);
+  m2 = block_max_f(m2, red);
+  float s2 = 0.0f;
+  for (int j = threadIdx.x; j < keep; j += blockDim.x) s2 += __expf(val[perm[j]] - m2);
+  s2 = block_sum_f(s2, red + 16);
+  const float L2 = m2 + __logf(s2);
+  for (int j = threadIdx.x; j < keep; j += blockDim.x) logw_out[j] = val[perm[j]] - L2;
+  if (threadIdx.x == 0) *nkeep = keep;
+}
+
+__global__ void k_gather_rows(int n, int stride, const uint32_t* perm, const int32_t* in, int32_t* out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * stride) return;
+  const int j = (int)(t / stride), s = (int)(t % stride);
+  out[t] = in[(size_t)perm[j] * stride + s];
+}
+__global__ void k_gather_u(int n, const uint32_t* perm, const int32_t* in, int32_t* out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) out[j] = in[perm[j]];
 }
 
 // child rows: parent row with every instance replaced by its updated instance
@@ -1808,8 +1903,9 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   DInst* ninst = (DInst*)need<uint8_t>(c.inst2, (int64_t)(nnew + 1) * sizeof(DInst));
   int32_t* onz = need<int32_t>(c.inst_nz, nnew + 1);
   int32_t* oz = need<int32_t>(c.inst_z, 8 * (int64_t)(nnew + 1));
+  float* jc = c.joint_rw ? need<float>(c.j_corr, nnew + 1) : nullptr;
   GLMB_LAUNCH(k_kalman, cdiv(nnew, T), T, 0, s, nnew, LW, rep, rec_u, rec_m, (const DInst*)c.inst.p, loff, lmeas, z,
-              sig2, ninst, onz, oz);
+              sig2, ninst, onz, oz, phi, M, logf(p.det_rate), jc);
   int32_t* did = first + U + 1;
   GLMB_LAUNCH(k_did, cdiv(U, T), T, 0, s, U, first, dpre, rec_id, did);
   int32_t* nrows = need<int32_t>(c.rows2, (int64_t)nk * SW);
@@ -1817,6 +1913,32 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
               rec_b + nd + ne, rec_id + nd + ne, nrows);
   int32_t* nntrk = need<int32_t>(c.ntrk2, nk + 1);
   GLMB_LAUNCH(k_gather_i32, cdiv(nk, T), T, 0, s, nk, chh, c.ntrk.as<int32_t>(), nntrk);
+  c.last_perm = false;
+  int nkept = nk;  // children after the (optional) exact-joint reweighting
+  const int32_t* hpar = chh;
+  if (c.joint_rw && nk > 0) {
+    // ---- exact-joint reweighting of the kept children: joint likelihood of every track's
+    // detection set, re-ranked, tau on the renormalised weights, renormalised
+    trace(c, "update.joint", nk);
+    float* jv = need<float>(c.j_val, nk + 1);
+    uint64_t* jk = need<uint64_t>(c.j_keys, nk + 1);
+    uint32_t* perm = need<uint32_t>(c.child_perm, nk + 1);
+    GLMB_LAUNCH(k_joint_child, cdiv((int64_t)nk * kWave, T), T, 0, s, nk, SW, nrows, jc, wout, jv, jk, perm);
+    sort_pairs(jk, perm, nk, 0, 64, c.tk, c.tv, c.tmp, s);
+    float* jl = need<float>(c.j_lw, nk + 1);
+    GLMB_LAUNCH(k_joint_tau, 1, 1024, 0, s, nk, perm, jv, p.tau, jl, nkeep);
+    nkept = read1(s, nkeep);
+    int32_t* rows3 = need<int32_t>(c.rows3, (int64_t)nkept * SW + 1);
+    GLMB_LAUNCH(k_gather_rows, cdiv((int64_t)nkept * SW, T), T, 0, s, nkept, SW, perm, nrows, rows3);
+    int32_t* jt = need<int32_t>(c.j_tmp, 2 * (int64_t)nkept + 2);
+    GLMB_LAUNCH(k_gather_u, cdiv(nkept, T), T, 0, s, nkept, perm, nntrk, jt);
+    GLMB_LAUNCH(k_gather_u, cdiv(nkept, T), T, 0, s, nkept, perm, chh, jt + nkept + 1);
+    GLMB_HIP(hipMemcpyAsync(nntrk, jt, (size_t)nkept * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    GLMB_HIP(hipMemcpyAsync(wout, jl, (size_t)nkept * sizeof(float), hipMemcpyDeviceToDevice, s));
+    hpar = jt + nkept + 1;
+    std::swap(c.rows2, c.rows3);  // the re-ranked rows become the child rows
+    c.last_perm = true;
+  }
 
   // ---- births for the next scan
   trace(c, "update.births");
@@ -1873,15 +1995,15 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   std::swap(c.logw, c.logw2);
   std::swap(c.births, c.births2);
   {
-    int32_t* hp = need<int32_t>(c.hparent, nk + 1);
-    GLMB_HIP(hipMemcpyAsync(hp, chh, (size_t)nk * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    int32_t* hp = need<int32_t>(c.hparent, nkept + 1);
+    GLMB_HIP(hipMemcpyAsync(hp, hpar, (size_t)nkept * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   }
   c.ninst = nnew;
-  c.nhyp = nk;
+  c.nhyp = nkept;
   c.nbirth = hs[13];
   c.birth_lab.clear();
   for (int b = 0; b < c.nbirth; ++b) c.birth_lab.push_back({k + 1, b});
-  c.stats.n_hyp_out = nk;
+  c.stats.n_hyp_out = nkept;
   c.stats.n_inst_out = nnew;
   c.stats.gated_pairs = (int64_t)ng;
   c.stats.option_terms = (int64_t)no;

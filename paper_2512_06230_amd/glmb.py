@@ -20,7 +20,7 @@ EXPORTS = ["glmb_status_string", "glmb_last_error", "glmb_create", "glmb_destroy
            "glmb_state_sizes", "glmb_export_state", "glmb_predict", "glmb_update", "glmb_truncate",
            "glmb_estimate", "glmb_stats", "glmb_update_diag", "glmb_update_theta", "glmb_set_proposal",
            "glmb_pair_features", "glmb_proposal_lost", "glmb_mlp_forward", "glmb_mlp_grad", "glmb_mlp_adam",
-           "glmb_mlp_grad_noalloc", "glmb_set_sampling",
+           "glmb_mlp_grad_noalloc", "glmb_set_sampling", "glmb_set_joint_reweighting",
            "glmb_batch_create", "glmb_batch_destroy", "glmb_batch_set_schedule", "glmb_batch_scene",
            "glmb_batch_step", "glmb_batch_stats_get", "glmb_batch_last_error"]
 
@@ -103,6 +103,7 @@ def load_library(path: str = LIB_PATH):
     L.glmb_mlp_grad.argtypes = [vp, vp, _F, vp, vp, vp, ctypes.c_int32, vp, vp]
     L.glmb_mlp_grad_noalloc.argtypes = [vp, vp, _F, vp, vp, vp, ctypes.c_int32, vp, vp]
     L.glmb_set_sampling.argtypes = [vp, ctypes.c_int32, ctypes.c_uint64]
+    L.glmb_set_joint_reweighting.argtypes = [vp, ctypes.c_int32]
     L.glmb_mlp_adam.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float]
     L.glmb_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_int, ctypes.c_int32,
@@ -302,6 +303,11 @@ class Tracker:
         generator) instead of the exact h_max best; h_up = 0 restores the exact update."""
         self._check(self._L.glmb_set_sampling(self._ctx, int(h_up), int(seed) & 0xFFFFFFFFFFFFFFFF),
                     "glmb_set_sampling")
+
+    def set_joint_reweighting(self, on: bool = True):
+        """Following updates reweight the kept hypotheses with the joint likelihood of every
+        track's detection set (re-ranked, tau, renormalised); False restores the factorised weights."""
+        self._check(self._L.glmb_set_joint_reweighting(self._ctx, 1 if on else 0), "glmb_set_joint_reweighting")
 
     def set_proposal(self, params, norm, threshold: float = 0.5, apply: bool = True, measure: bool = False):
         """params: CUDA float32 [4673] (None unloads the proposal); norm: 12 floats.
