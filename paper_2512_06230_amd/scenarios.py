@@ -164,6 +164,74 @@ def make_scene(spec: SceneSpec, n_steps: Optional[int] = None) -> Scene:
                  prior_ids=prior_ids)
 
 
+# --------------------------------------------------------------------------- convoy (Sec. 4.1)
+def convoy_track(K: int = 548, dt: float = 0.1, loops: float = 2.0, center: float = 40.0) -> np.ndarray:
+    """A smooth closed ground-truth track standing in for the paper's GPS track (which is not
+    available): K positions 0.1 s apart inside an 80 x 80 m area, the closed curve
+    (30 cos t + 4 cos 3t, 24 sin t + 5 sin 2t) traversed `loops` times (two loops: about 6.5 m/s,
+    three: about 10 m/s), so that time offsets taken modulo K stay on a continuous path."""
+    t = 2.0 * math.pi * loops * np.arange(K) / K
+    x = center + 30.0 * np.cos(t) + 4.0 * np.cos(3.0 * t)
+    y = center + 24.0 * np.sin(t) + 5.0 * np.sin(2.0 * t)
+    return np.stack([x, y], axis=1)
+
+
+@dataclasses.dataclass
+class ConvoySpec:
+    n_obj: int = 5
+    delta: int = 2        # time offset between consecutive copies (steps)
+    det: int = 5          # detections per object per step (D)
+    sigma: float = 0.25   # detection noise std (m)
+    clutter: float = 0.0  # clutter detections per step (lambda = 0 in the paper)
+    K: int = 548          # steps of 0.1 s (54.8 s)
+    dt: float = 0.1
+    loops: float = 3.0    # times the base track goes round its closed curve (about 10 m/s)
+    seed: int = 0
+
+
+def make_convoy(spec: ConvoySpec, n_steps: Optional[int] = None) -> Scene:
+    """The paper's benchmark construction (Sec. 4.1): N copies of one track, copy n offset by
+    n * delta steps (position at step k is the base track's at (k + n delta) mod K), each
+    yielding D detections N(x, sigma^2 I) per step, listed object by object (the tracker is
+    invariant to their order).  Velocities in the truth are the track's finite differences."""
+    rng = np.random.default_rng(spec.seed)
+    base = convoy_track(spec.K, spec.dt, spec.loops)
+    vel = (np.roll(base, -1, axis=0) - base) / spec.dt
+    steps = spec.K if n_steps is None else n_steps
+    ids = np.arange(spec.n_obj, dtype=np.int32)
+    meas, tids, tx = [], [], []
+    for k in range(steps):
+        idx = (k + spec.delta * ids) % spec.K
+        x = np.concatenate([base[idx], vel[idx]], axis=1)
+        z = [x[j, 0:2] + spec.sigma * rng.standard_normal((spec.det, 2)) for j in range(spec.n_obj)]
+        if spec.clutter > 0:
+            nc = rng.poisson(spec.clutter)
+            if nc:
+                z.append(rng.uniform(0.0, 80.0, size=(nc, 2)))
+        meas.append(np.ascontiguousarray(np.concatenate(z, axis=0), dtype=np.float32))
+        tids.append(ids.copy())
+        tx.append(x)
+    prior = tx[0].copy()
+    prior[:, 0:2] -= spec.dt * prior[:, 2:4]
+    cs = SceneSpec(n_obj=spec.n_obj, side=80.0, n_steps=steps, dt=spec.dt, sigma=spec.sigma, pd=1.0,
+                   count_mode="poisson", count_mean=float(spec.det), clutter_mean=spec.clutter, seed=spec.seed)
+    return Scene(spec=cs, meas=meas, truth_ids=tids, truth_x=tx, prior_x=prior, prior_ids=ids.copy())
+
+
+def convoy_params(spec: ConvoySpec, h_max: int, tau: float = 1e-5) -> dict:
+    """Filter parameters for the convoy: gamma = D, constant-velocity model at dt = 0.1 with
+    q = 32 m^2/s^3 (the track turns at up to ~8 m/s^2 at 10 m/s), kappa = 1e-6 per m^2 (no
+    clutter, but a clutter option must exist), births from clusters within 3 sigma with a 3 m/s
+    velocity spread (chosen on the N = 10 and 20 convoys among q in {2, 8, 32} and spreads in
+    {3, 8, 15} m/s)."""
+    return dict(
+        dt=spec.dt, q=32.0, sigma_z=spec.sigma, p_survive=0.99, det_rate=float(spec.det),
+        clutter_density=max(spec.clutter / 6400.0, 1e-6), gate_d2=-2.0 * math.log(1e-4),
+        birth_r_max=0.5, birth_rate=0.5, birth_sigma_v=3.0, birth_ru_max=0.5, birth_cluster_d=3.0 * spec.sigma,
+        h_max=int(h_max), tau=float(tau),
+    )
+
+
 def filter_params(spec: SceneSpec, h_max: int, tau: float) -> dict:
     """Tracker parameters matched to a simulated scene: gamma = the simulator's mean
     detections per object, kappa = clutter mean / region area, chi-square(2) gate at 0.9999,

@@ -144,3 +144,36 @@ def test_sampled_update_hundred_objects(torch_cuda):
     print("matched %d of %d kept, %d distinct maps, fragile parents %d" % (
         matched, s["n_hyp_out"], s["search_nodes"], len(s["fragile"])), flush=True)
     assert matched >= 0.9 * s["n_hyp_out"]
+
+
+def test_sampled_update_on_the_convoy(torch_cuda):
+    """The paper's benchmark setting (Sec. 4.1): a 5-object convoy, D = 5, sigma = 0.25 m, no
+    clutter, H_up = 100, tau = 1e-5, H_max = 25.  The GPU filter runs 40 steps from an empty
+    state; every 4th predicted state is updated by both sides and compared."""
+    from paper_2512_06230_amd.glmb import Tracker
+    spec = sc.ConvoySpec(n_obj=5)
+    scene = sc.make_convoy(spec, n_steps=40)
+    p = sc.convoy_params(spec, 25, 1e-5)
+    g = Tracker(p)
+    g.import_state(sc.empty_state())
+    g.set_sampling(100, 11)
+    matched = 0
+    for k in range(40):
+        g.predict(k)
+        if k % 4 == 3:
+            m, _ = check_sampled(g.export_state(), scene.meas[k], p, 100, 11, k)
+            matched += m
+        g.update(k, scene.meas[k])
+        g.truncate(25, 1e-5)
+    g.close()
+    assert matched > 20
+
+
+@pytest.mark.slow
+def test_convoy_accuracy(torch_cuda):
+    """Behavioural check on the whole 548-step 5-object convoy (the metrics of Sec. 4.2): the
+    relative cardinality error and the Hungarian-matched position error stay small."""
+    from paper_2512_06230_amd import convoy
+    r = convoy.run(5, 25, 100, 1e-5, 0, 0, 548)
+    print(r, flush=True)
+    assert r["card_rel_err"] < 0.05 and r["matched_err_m"] < 0.25, r
