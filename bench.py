@@ -232,6 +232,7 @@ def main():
         pw = torch.as_tensor(prop.params, device=dev)
         probe = Tracker(params)
         ret_traj = {}
+        gain = None
         for leg in ("plain", "learned"):
             ptrk = Tracker(params)
             ptrk.import_state(start)
@@ -242,6 +243,11 @@ def main():
                 ptrk.predict(k)
                 if k >= args.warmup:
                     r.append(retained_lost(probe, ptrk.export_state(), k, zs[k], pw, prop.norm, [prop.threshold])[0])
+                if leg == "plain" and k == n_scans - 1:
+                    # what the network gains over the method without it: pairs kept by the plain
+                    # gate, by the tightest gate with the same lost-mass bound, and by the network
+                    from paper_2512_06230_amd.proposal import gate_gain
+                    gain = gate_gain(params, ptrk.export_state(), k, zs[k], prop)
                 ptrk.update(k, zs[k])
                 ptrk.truncate(args.h_max, 0.0)
             ptrk.close()
@@ -262,6 +268,7 @@ def main():
             "full_posterior_lost_mass_mean": float(np.clip(lost, 0.0, 1.0).mean()),
             "full_posterior_lost_mass_max": float(np.clip(lost, 0.0, 1.0).max()),
             "n_births_mean": float(np.mean([s["n_births"] for s in st_l])),
+            "gain_vs_gate": gain,
             "plain_n_births_mean": float(np.mean([s["n_births"] for s in stats])),
             "pairs_removed_frac": float(sum(s["pairs_removed"] for s in st_l) /
                                         max(1, sum(s["gated_pairs"] for s in st_l))),

@@ -176,3 +176,52 @@ def calibrate(params, norm, specs: List[sc.SceneSpec], h_max: int, n_steps: int,
             log("held-out seed %d: worst full-posterior lost mass %s" % (spec.seed, np.array2string(worst_full, precision=2)))
     ok = [t for t, L in zip(thresholds, worst_ret) if L <= max_lost]
     return (max(ok) if ok else None), worst_ret, worst_full
+
+
+GATE_GRID = [18.42, 16.0, 14.0, 12.0, 10.0, 9.0, 8.0, 7.0, 6.0, 5.0, 4.0, 3.0, 2.5, 2.0, 1.5, 1.0, 0.5]
+
+
+def gate_gain(params_filter: dict, pred_state: dict, k: int, z, prop: "Proposal", max_lost: float = 1e-3,
+              gates=GATE_GRID):
+    """What the learned proposal gains over the method without it, on one predicted state: the
+    gated pairs the update keeps (i) with the plain gate, (ii) with the tightest Mahalanobis gate
+    of the grid whose retained-set lost mass versus the plain update stays <= max_lost, and
+    (iii) with the proposal at its threshold (its lost mass measured the same way)."""
+    import torch
+    M = int(z.shape[0])
+
+    def update(p, proposal=None):
+        t = Tracker(p)
+        t.import_state(pred_state)
+        if proposal is not None:
+            t.set_proposal(torch.as_tensor(proposal.params, device="cuda"), proposal.norm, proposal.threshold,
+                           apply=True)
+        t.update(k, z)
+        out = t.export_state()
+        th = t.theta(len(out["hyp_logw"]), M)
+        st = t.stats()
+        t.close()
+        ids = {(int(a), r.tobytes()): float(w) for a, r, w in zip(out["hyp_parent"], th, np.exp(out["hyp_logw"]))}
+        return ids, st
+
+    ref, st0 = update(params_filter)
+
+    def lost(ids):
+        return float(sum(w for key, w in ref.items() if key not in ids))
+
+    res = dict(pairs_plain=int(st0["gated_pairs"]), gate_plain=float(params_filter["gate_d2"]))
+    best = None
+    for g in gates:
+        if g > params_filter["gate_d2"]:
+            continue
+        ids, st = update(dict(params_filter, gate_d2=g))
+        L = lost(ids)
+        if L <= max_lost:
+            best = (g, int(st["gated_pairs"]), L)
+        else:
+            break
+    res.update(gate_tight=best[0], pairs_tight_gate=best[1], lost_tight_gate=best[2])
+    ids, st = update(params_filter, prop)
+    res.update(pairs_mlp=int(st["gated_pairs"] - st["pairs_removed"]), lost_mlp=lost(ids),
+               gain_vs_tight_gate=best[1] / max(1, int(st["gated_pairs"] - st["pairs_removed"])))
+    return res

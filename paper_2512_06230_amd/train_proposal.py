@@ -2,8 +2,8 @@
 
     python -m paper_2512_06230_amd.train_proposal --out paper_2512_06230_amd/proposal_n500.npz
 
-Training scenes: N=200 and N=500 objects (clutter 0.2 N per scan), H_max=1e3, warm start,
-20 scans each, seeds 1000, 1001, ...  Threshold: the largest grid value whose lost posterior
+Training scenes: 200 scenes of N=200 objects (clutter 40 per scan), H_max=1e3, warm start,
+20 scans each, seeds 1000, 1001, ... (optionally also N=500 scenes, seeds 1500, ...).  Threshold: the largest grid value whose lost posterior
 mass versus the plain update stays <= 1e-3 on every scan of the held-out scenes (N=500,
 clutter 100, H_max=1e4, seeds 2000, ...), i.e. the benchmarked workload on scenes the
 benchmark does not use.
@@ -24,8 +24,8 @@ from .glmb import Tracker
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
-    ap.add_argument("--train-scenes", type=int, default=16)
-    ap.add_argument("--train-scenes-large", type=int, default=8)
+    ap.add_argument("--train-scenes", type=int, default=200)
+    ap.add_argument("--train-scenes-large", type=int, default=0)
     ap.add_argument("--train-steps", type=int, default=20)
     ap.add_argument("--train-n", type=int, default=200)
     ap.add_argument("--train-hmax", type=int, default=1000)
@@ -33,7 +33,7 @@ def main(argv=None):
     ap.add_argument("--heldout-steps", type=int, default=6)
     ap.add_argument("--heldout-n", type=int, default=500)
     ap.add_argument("--heldout-hmax", type=int, default=10000)
-    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--max-lost", type=float, default=1e-3)
