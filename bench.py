@@ -421,6 +421,7 @@ def main():
                                          "hypotheses (H_max %d), FP64, one thread pinned to one core; rate "
                                          "scaled by %d/%d (work linear in the hypothesis count)"
                                          % (nh, nh, nh, args.h_max)}
+    trk.close()
     print(json.dumps(out))
 
 
