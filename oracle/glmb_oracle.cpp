@@ -1092,6 +1092,47 @@ struct Oracle {
   }
 };
 
+
+// ---------------------------------------------------------------------------------
+// Particle form of the track densities (Sec. 3: P weighted particles per track, constant
+// turn rate and velocity kinematics, likelihood-weighted update with resampling).  State of a
+// particle: (x, y, v, psi, omega); arrays are component-major [5][n] and log weights [n].
+// ---------------------------------------------------------------------------------
+
+// standard normal pair by the Box-Muller transform of two Philox words of counter c
+static void philox_normals(uint64_t seed, uint32_t a, uint32_t b, uint32_t c, double* n1, double* n2) {
+  const uint32_t ctr[4] = {a, b, c, 0};
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t out[4];
+  philox4x32_10(ctr, key, out);
+  const double u1 = ((double)(out[0] >> 8) + 0.5) * (1.0 / 16777216.0);  // in (0, 1)
+  const double u2 = (double)(out[1] >> 8) * (1.0 / 16777216.0);
+  const double r = std::sqrt(-2.0 * std::log(u1));
+  *n1 = r * std::cos(2.0 * M_PI * u2);
+  *n2 = r * std::sin(2.0 * M_PI * u2);
+}
+
+// Constant turn rate and velocity prediction over dt with white accelerations nu_a (speed)
+// and nu_w (turn rate) held over the step:
+//   x += v/w (sin(psi + w dt) - sin psi) + dt^2/2 nu_a cos psi   (v cos psi dt when |w| < 1e-4)
+//   y += v/w (cos psi - cos(psi + w dt)) + dt^2/2 nu_a sin psi   (v sin psi dt when |w| < 1e-4)
+//   v += dt nu_a,  psi += w dt + dt^2/2 nu_w,  w += dt nu_w.
+static void ctrv_step(double dt, double nu_a, double nu_w, double* s) {
+  const double x = s[0], y = s[1], v = s[2], psi = s[3], w = s[4];
+  double dx, dy;
+  if (std::fabs(w) > 1e-4) {
+    dx = v / w * (std::sin(psi + w * dt) - std::sin(psi));
+    dy = (ORACLE_MUTANT == 16 ? -1.0 : 1.0) * v / w * (std::cos(psi) - std::cos(psi + w * dt));  // planted 16
+  } else {
+    dx = v * std::cos(psi) * dt;
+    dy = v * std::sin(psi) * dt;
+  }
+  s[0] = x + dx + 0.5 * dt * dt * nu_a * std::cos(psi);
+  s[1] = y + dy + 0.5 * dt * dt * nu_a * std::sin(psi);
+  s[2] = v + dt * nu_a;
+  s[3] = psi + w * dt + 0.5 * dt * dt * nu_w;
+  s[4] = w + dt * nu_w;
+}
 }  // namespace
 
 extern "C" {
@@ -1258,6 +1299,126 @@ int orc_sample_stats(void* hd, int64_t* counts, int32_t* fragile, int cap) {
 }
 
 void orc_philox(const uint32_t* ctr, const uint32_t* key, uint32_t* out) { philox4x32_10(ctr, key, out); }
+
+// Particle form.  Prediction of n = U * P particles in place (state [5][n]); the accelerations
+// of particle q at scan k are sigma_a n1, sigma_w n2 from Philox counter (q, 0, 16 k + 2).
+void orc_pf_predict(double* st, int64_t n, double dt, double sigma_a, double sigma_w, uint64_t seed, int k) {
+  for (int64_t q = 0; q < n; ++q) {
+    double n1, n2;
+    philox_normals(seed, (uint32_t)q, 0u, (uint32_t)k * 16u + 2u, &n1, &n2);
+    double s5[5];
+    for (int c = 0; c < 5; ++c) s5[c] = st[c * n + q];
+    ctrv_step(dt, sigma_a * n1, sigma_w * n2, s5);
+    for (int c = 0; c < 5; ++c) st[c * n + q] = s5[c];
+  }
+}
+
+// Association log-likelihoods of the particle tracks: for track u (particles u P .. u P + P - 1,
+// normalised log weights lw) and detection i, phi = log gamma + log sum_p w_p N(z_i; (x_p, y_p),
+// sigma^2 I) when the detection passes the gate d^2 <= G on the particles' weighted mean and
+// covariance plus sigma^2 I, else -inf.  phi is [U][M].
+void orc_pf_loglik(const double* st, const double* lw, int U, int P, const double* z, int M, double sigma,
+                   double gamma, double gate, double* phi) {
+  const int64_t n = (int64_t)U * P;
+  for (int u = 0; u < U; ++u) {
+    double mx = 0, my = 0, cxx = 0, cxy = 0, cyy = 0;
+    for (int p = 0; p < P; ++p) {
+      const int64_t q = (int64_t)u * P + p;
+      const double w = std::exp(lw[q]);
+      mx += w * st[q];
+      my += w * st[n + q];
+    }
+    for (int p = 0; p < P; ++p) {
+      const int64_t q = (int64_t)u * P + p;
+      const double w = std::exp(lw[q]);
+      const double dx = st[q] - mx, dy = st[n + q] - my;
+      cxx += w * dx * dx;
+      cxy += w * dx * dy;
+      cyy += w * dy * dy;
+    }
+    const double s00 = cxx + sigma * sigma, s01 = cxy, s11 = cyy + sigma * sigma;
+    const double det = s00 * s11 - s01 * s01;
+    for (int i = 0; i < M; ++i) {
+      const double nx = z[2 * i] - mx, ny = z[2 * i + 1] - my;
+      const double d2 = (s11 * nx * nx - 2.0 * s01 * nx * ny + s00 * ny * ny) / det;
+      if (!(d2 <= gate)) {
+        phi[(int64_t)u * M + i] = kNegInf;
+        continue;
+      }
+      std::vector<double> t(P);
+      for (int p = 0; p < P; ++p) {
+        const int64_t q = (int64_t)u * P + p;
+        const double ex = z[2 * i] - st[q], ey = z[2 * i + 1] - st[n + q];
+        t[p] = lw[q] - std::log(2.0 * M_PI * sigma * sigma) - (ex * ex + ey * ey) / (2.0 * sigma * sigma);
+      }
+      phi[(int64_t)u * M + i] = std::log(gamma) + lse(t);
+    }
+  }
+}
+
+// Particle update of R records (record r: track rec_u[r], detections rec_z[rec_off[r] ..
+// rec_off[r+1])): log w'_p = log w_p + sum_{i in S} log N(z_i; (x_p, y_p), sigma^2 I), normalised;
+// when the effective sample size 1 / sum w'^2 falls below ess_frac P, systematic resampling:
+// output particle j copies the first particle whose cumulative weight exceeds (j + u0) / P, u0
+// the Philox uniform at counter (r, 0, 16 k + 3), weights 1 / P.  Outputs [5][R P] and [R P];
+// resampled[r] = 1 when the record was resampled.  fragile[r] = 1 when some (j + u0) / P lies
+// within margin of a cumulative weight (where single and double precision may pick differently).
+void orc_pf_update(const double* st, const double* lw, int U, int P, int R, const int32_t* rec_u,
+                   const int32_t* rec_off, const int32_t* rec_z, const double* z, double sigma, double ess_frac,
+                   uint64_t seed, int k, double margin, double* ost, double* olw, int32_t* resampled,
+                   int32_t* fragile) {
+  const int64_t n = (int64_t)U * P, no = (int64_t)R * P;
+  for (int r = 0; r < R; ++r) {
+    const int u = rec_u[r];
+    std::vector<double> a(P);
+    for (int p = 0; p < P; ++p) {
+      const int64_t q = (int64_t)u * P + p;
+      double v = lw[q];
+      for (int e = rec_off[r]; e < rec_off[r + 1]; ++e) {
+        const int i = rec_z[e];
+        const double ex = z[2 * i] - st[q], ey = z[2 * i + 1] - st[n + q];
+        v += -std::log(2.0 * M_PI * sigma * sigma) - (ex * ex + ey * ey) / (2.0 * sigma * sigma);
+      }
+      a[p] = v;
+    }
+    const double L = lse(a);
+    double s2 = 0.0;
+    for (int p = 0; p < P; ++p) {
+      a[p] -= L;
+      s2 += std::exp(2.0 * a[p]);
+    }
+    const bool rs = 1.0 / s2 < ess_frac * P;
+    resampled[r] = rs ? 1 : 0;
+    fragile[r] = 0;
+    if (!rs) {
+      for (int p = 0; p < P; ++p) {
+        for (int c = 0; c < 5; ++c) ost[c * no + (int64_t)r * P + p] = st[c * n + (int64_t)u * P + p];
+        olw[(int64_t)r * P + p] = a[p];
+      }
+      continue;
+    }
+    const uint32_t ctr[4] = {(uint32_t)r, 0u, (uint32_t)k * 16u + 3u, 0u};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    philox4x32_10(ctr, key, out);
+    const double u0 = (double)(out[0] >> 8) * (1.0 / 16777216.0);
+    std::vector<double> cum(P);
+    double c = 0.0;
+    for (int p = 0; p < P; ++p) {
+      c += std::exp(a[p]);
+      cum[p] = c;
+    }
+    int p = 0;
+    for (int j = 0; j < P; ++j) {
+      const double pos = (j + u0) / P;
+      while (p < P - 1 && !(pos < cum[p])) ++p;
+      for (int b = std::max(0, p - 1); b <= p; ++b)
+        if (std::fabs(pos - cum[b]) < margin && b < P - 1) fragile[r] = 1;
+      for (int cc = 0; cc < 5; ++cc) ost[cc * no + (int64_t)r * P + j] = st[cc * n + (int64_t)u * P + p];
+      olw[(int64_t)r * P + j] = -std::log((double)P);
+    }
+  }
+}
 
 // exact-joint reweighting of the kept hypotheses in the following updates (0 = factorised)
 void orc_set_joint(void* hd, int on) { static_cast<Oracle*>(hd)->joint_rw = on != 0; }

@@ -64,6 +64,12 @@ def _load(path: str = None):
         L.orc_philox_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
                                          ctypes.c_uint32]
         L.orc_philox_uniform.restype = ctypes.c_double
+        L.orc_pf_predict.argtypes = [dp, ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_uint64, ctypes.c_int]
+        L.orc_pf_loglik.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, dp, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_double, dp]
+        L.orc_pf_update.argtypes = [dp, dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, ip, ip, dp, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_uint64, ctypes.c_int, ctypes.c_double, dp, dp, ip, ip]
         L.orc_set_joint.argtypes = [vp, ctypes.c_int]
         L.orc_joint_loglik.argtypes = [ctypes.c_double, ctypes.c_int, dp, dp, dp]
         L.orc_joint_loglik.restype = ctypes.c_double
@@ -240,3 +246,44 @@ def joint_loglik(sigma: float, z, m, P, lib: str = None) -> float:
     m, pm = _f64(np.asarray(m, np.float64).reshape(4))
     P, pP = _f64(np.asarray(P, np.float64).reshape(16))
     return float(L.orc_joint_loglik(float(sigma), int(z.shape[0]), pz, pm, pP))
+
+
+# ---- particle form (component-major states [5][n], log weights [n]) ----
+def pf_predict(st, dt: float, sigma_a: float, sigma_w: float, seed: int, k: int, lib: str = None):
+    """The oracle's constant-turn-rate-and-velocity prediction of every particle (a copy)."""
+    out = np.ascontiguousarray(np.array(st, np.float64).reshape(5, -1))
+    _load(lib).orc_pf_predict(out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.shape[1], float(dt),
+                              float(sigma_a), float(sigma_w), int(seed) & 0xFFFFFFFFFFFFFFFF, int(k))
+    return out
+
+
+def pf_loglik(st, lw, U: int, P: int, z, sigma: float, gamma: float, gate: float, lib: str = None):
+    """phi [U][M] of particle tracks (-inf outside the gate)."""
+    st, pst = _f64(np.asarray(st, np.float64).reshape(5, -1))
+    lw, plw = _f64(np.asarray(lw, np.float64).reshape(-1))
+    z, pz = _f64(np.asarray(z, np.float64).reshape(-1, 2))
+    phi = np.zeros((U, z.shape[0]))
+    _load(lib).orc_pf_loglik(pst, plw, U, P, pz, z.shape[0], float(sigma), float(gamma), float(gate),
+                             phi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return phi
+
+
+def pf_update(st, lw, U: int, P: int, rec_u, rec_off, rec_z, z, sigma: float, ess_frac: float, seed: int, k: int,
+              margin: float = 1e-6, lib: str = None):
+    """(states [5][R P], log weights [R P], resampled [R], fragile [R]) of the particle update."""
+    st, pst = _f64(np.asarray(st, np.float64).reshape(5, -1))
+    lw, plw = _f64(np.asarray(lw, np.float64).reshape(-1))
+    z, pz = _f64(np.asarray(z, np.float64).reshape(-1, 2))
+    ru, pru = _i32(rec_u)
+    ro, pro = _i32(rec_off)
+    rz, prz = _i32(rec_z if len(rec_z) else np.zeros(1, np.int32))
+    R = len(ru)
+    ost = np.zeros((5, R * P))
+    olw = np.zeros(R * P)
+    rs = np.zeros(R, np.int32)
+    fr = np.zeros(R, np.int32)
+    D = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    I = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    _load(lib).orc_pf_update(pst, plw, U, P, R, pru, pro, prz, pz, float(sigma), float(ess_frac),
+                             int(seed) & 0xFFFFFFFFFFFFFFFF, int(k), float(margin), D(ost), D(olw), I(rs), I(fr))
+    return ost, olw, rs, fr

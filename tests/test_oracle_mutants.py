@@ -10,6 +10,7 @@ import pytest
 from oracle import oracle as orc
 from tests import test_oracle_pins as pins
 from tests import test_joint_oracle as joint
+from tests import test_particles_oracle as particles
 from tests import test_sampler_oracle as sampler
 
 PINS = [
@@ -30,6 +31,8 @@ PINS = [
     lambda: [sampler.test_sampled_children_are_children_with_their_exact_weights(s) for s in range(4)],
     lambda: joint.test_joint_loglik_matches_sequential_kalman(2),
     lambda: [joint.test_reweighted_update_matches_bruteforce(s) for s in range(2)],
+    lambda: particles.test_ctrv_without_noise_is_a_line_or_a_circle(),
+    lambda: particles.test_update_weights_and_systematic_resampling(),
 ]
 
 MUTANTS = {
@@ -48,6 +51,7 @@ MUTANTS = {
     13: "removed pairs' mass not restored in the births' clutter probabilities",
     14: "sampled rows normalised without the clutter entry",
     15: "joint likelihood without the shared track uncertainty between detections",
+    16: "turning motion bends the wrong way in y",
 }
 
 
@@ -58,6 +62,8 @@ def test_planted_mistake_is_caught(mutant, tmp_path, monkeypatch):
     monkeypatch.setattr(sampler, "Oracle", functools.partial(orc.Oracle, lib=lib))
     monkeypatch.setattr(joint, "Oracle", functools.partial(orc.Oracle, lib=lib))
     monkeypatch.setattr(joint, "orc", types.SimpleNamespace(joint_loglik=functools.partial(orc.joint_loglik, lib=lib)))
+    monkeypatch.setattr(particles, "orc", types.SimpleNamespace(
+        **{f: functools.partial(getattr(orc, f), lib=lib) for f in ("pf_predict", "pf_loglik", "pf_update")}))
     failed = 0
     for pin in PINS:
         try:
