@@ -283,6 +283,43 @@ glmb_status glmb_mlp_grad_noalloc(glmb_ctx* ctx, const float* params_dev, const 
                                   const float* target_dev, const float* weight_dev, int32_t n, float* grad_dev,
                                   float* loss_dev);
 
+/* ---- Particle form of the track densities --------------------------------------------
+ * Sec. 3 represents every track by P weighted particles, propagated with constant turn rate and
+ * velocity (CTRV) kinematics and weighted by the measurement likelihood, with resampling to
+ * prevent degeneracy.  These three calls are stateless and stream-ordered on hip_stream (NULL:
+ * the default stream); every pointer is a device pointer owned by the caller.  Particle states
+ * are component-major float32 [5][n] (x, y, v, psi, omega; n = U P, track u holds particles
+ * u P .. u P + P - 1) with normalised natural-log weights float32 [n].  Uniform numbers are
+ * Philox4x32-10 (Salmon et al., SC'11) under key `seed`, 24-bit.  Errors: GLMB_E_ARG for a null
+ * pointer or a value out of range (nothing launched), GLMB_E_CAPACITY for P > 4096,
+ * GLMB_E_DEVICE when a launch fails.
+ *
+ * glmb_pf_predict: in place, every particle over dt with white accelerations
+ *   a_v = sigma_a n1, a_w = sigma_w n2 held over the step (n1, n2 standard normal by the
+ *   Box-Muller transform of the first two Philox words at counter (q, 0, 16 k + 2, 0), q the
+ *   particle index < 2^32):  x += v/w (sin(psi + w dt) - sin psi) + dt^2/2 a_v cos psi,
+ *   y += v/w (cos psi - cos(psi + w dt)) + dt^2/2 a_v sin psi (the straight-line limit as
+ *   w -> 0), v += dt a_v, psi += w dt + dt^2/2 a_w, w += dt a_w.
+ * glmb_pf_loglik: phi float32 [U][M], the Eq. 2 entry of every (track, detection) pair:
+ *   log gamma + log sum_p w_p N(z_i; (x_p, y_p), sigma^2 I) when the detection passes the gate
+ *   d^2 <= gate on the particles' weighted mean and covariance plus sigma^2 I, else -inf.
+ *   z: float32 [M][2].
+ * glmb_pf_update: R records (track rec_u[r], detections rec_z[rec_off[r] .. rec_off[r+1]) of
+ *   z [M][2]): log w'_p = log w_p + sum_{i in S} log N(z_i; (x_p, y_p), sigma^2 I), normalised;
+ *   when the effective sample size 1 / sum w'^2 < ess_frac P, systematic resampling (output
+ *   particle j copies the first particle whose cumulative weight exceeds (j + u0) / P, u0 the
+ *   Philox uniform at counter (r, 0, 16 k + 3, 0); weights 1 / P).  Outputs out_state [5][R P],
+ *   out_logw [R P], resampled[r] = 1 (resampled), 0 (reweighted) or -1 (the record names a
+ *   track or detection out of range: its outputs are left unwritten). */
+glmb_status glmb_pf_predict(void* hip_stream, float* state_dev, int64_t n, float dt, float sigma_a, float sigma_w,
+                            uint64_t seed, int32_t k);
+glmb_status glmb_pf_loglik(void* hip_stream, const float* state_dev, const float* logw_dev, int32_t U, int32_t P,
+                           const float* z_dev, int32_t M, float sigma, float gamma, float gate, float* phi_dev);
+glmb_status glmb_pf_update(void* hip_stream, const float* state_dev, const float* logw_dev, int32_t U, int32_t P,
+                           int32_t R, const int32_t* rec_u_dev, const int32_t* rec_off_dev, const int32_t* rec_z_dev,
+                           const float* z_dev, int32_t M, float sigma, float ess_frac, uint64_t seed, int32_t k,
+                           float* out_state_dev, float* out_logw_dev, int32_t* resampled_dev);
+
 /* ---- Batched scenes -------------------------------------------------------------------
  * An addition to the method (the paper filters one scene): many independent scenes of uneven
  * size advance one time step in one call.  Each scene is a context of its own (its state,

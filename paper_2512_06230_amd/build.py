@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libglmb.so")
 SOURCES = ["primitives.hip", "select.hip", "predict.hip", "update.hip", "sample.hip", "proposal.hip", "api.hip",
-           "batch.hip"]
+           "batch.hip", "particles.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of every kernel

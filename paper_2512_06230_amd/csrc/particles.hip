@@ -1,0 +1,299 @@
+// Particle form of the track densities (Sec. 3: every track is a set of P weighted particles
+// propagated with constant turn rate and velocity kinematics, weighted by the measurement
+// likelihood and resampled when degenerate), as three stateless stream-ordered calls:
+//
+//   predict   one thread per particle: Philox4x32-10 words -> two standard normals (Box-Muller)
+//             -> accelerations; the turn written in the form v dt sinc(omega dt / 2) of the
+//             chord, stable for every turn rate; 40 B of state read and written per particle;
+//   loglik    one workgroup per track: the particles' positions and log weights staged in LDS,
+//             their weighted mean and covariance (gate on d^2 <= G), then one wave per gated
+//             detection: log-sum-exp over the particles of log w + log N(z; (x, y), sigma^2 I);
+//   update    one workgroup per (track, detection set) record: new log weights in LDS, their
+//             normaliser and effective sample size; below ess_frac P, systematic resampling
+//             (cumulative weights scanned in LDS, one uniform per record, a binary search per
+//             output particle); 48 B read and written per particle.
+//
+// States are component-major [5][n] (x, y, v, psi, omega) so that every component load is
+// coalesced; log weights [n].
+#include "common.hpp"
+
+namespace glmb {
+
+namespace {
+
+constexpr int kPfMaxP = 4096;  // particles per track held in LDS by the update and the likelihoods
+constexpr float kTwoPi = 6.283185307179586f;
+
+struct Philox4 {
+  uint32_t w[4];
+};
+__device__ __forceinline__ Philox4 philox4(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3, uint32_t k0,
+                                           uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * x0, hi0 = __umulhi(0xD2511F53u, x0);
+    const uint32_t lo1 = 0xCD9E8D57u * x2, hi1 = __umulhi(0xCD9E8D57u, x2);
+    const uint32_t y0 = hi1 ^ x1 ^ k0, y2 = hi0 ^ x3 ^ k1;
+    x0 = y0;
+    x1 = lo1;
+    x2 = y2;
+    x3 = lo0;
+  }
+  return Philox4{{x0, x1, x2, x3}};
+}
+
+__device__ __forceinline__ float sinc_half(float a) {  // sin(a / 2) / (a / 2)
+  const float h = 0.5f * a;
+  return fabsf(h) < 1e-4f ? 1.0f - h * h * (1.0f / 6.0f) : sinf(h) / h;
+}
+
+__global__ __launch_bounds__(256) void k_pf_predict(float* st, int64_t n, float dt, float sa, float sw,
+                                                    uint32_t ctr2, uint32_t k0, uint32_t k1) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const Philox4 r = philox4((uint32_t)q, 0u, ctr2, 0u, k0, k1);
+  const float u1 = ((float)(r.w[0] >> 8) + 0.5f) * (1.0f / 16777216.0f);
+  const float u2 = (float)(r.w[1] >> 8) * (1.0f / 16777216.0f);
+  const float rad = sqrtf(-2.0f * logf(u1));
+  float s2, c2;
+  sincosf(kTwoPi * u2, &s2, &c2);
+  const float na = sa * rad * c2, nw = sw * rad * s2;
+  const float x = st[q], y = st[n + q], v = st[2 * n + q], psi = st[3 * n + q], w = st[4 * n + q];
+  const float a = w * dt;
+  float sh, ch, sp, cp;
+  sincosf(psi + 0.5f * a, &sh, &ch);
+  sincosf(psi, &sp, &cp);
+  const float chord = v * dt * sinc_half(a);
+  const float hdt2 = 0.5f * dt * dt;
+  st[q] = x + chord * ch + hdt2 * na * cp;
+  st[n + q] = y + chord * sh + hdt2 * na * sp;
+  st[2 * n + q] = v + dt * na;
+  st[3 * n + q] = psi + a + hdt2 * nw;
+  st[4 * n + q] = w + dt * nw;
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+  for (int d = kWave / 2; d > 0; d >>= 1) v = fmaxf(v, __shfl_xor(v, d, kWave));
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+// fixed-order block reductions (waves in order)
+__device__ float block_sum(float v, float* sh) {
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane_id() == 0) sh[threadIdx.x / kWave] = v;
+  __syncthreads();
+  float r = 0.0f;
+  for (int j = 0; j < (int)(blockDim.x / kWave); ++j) r += sh[j];
+  return r;
+}
+__device__ float block_max(float v, float* sh) {
+  v = wave_max(v);
+  __syncthreads();
+  if (lane_id() == 0) sh[threadIdx.x / kWave] = v;
+  __syncthreads();
+  float r = -INFINITY;
+  for (int j = 0; j < (int)(blockDim.x / kWave); ++j) r = fmaxf(r, sh[j]);
+  return r;
+}
+
+__global__ __launch_bounds__(256) void k_pf_loglik(const float* st, const float* lw, int P, int64_t n, const float2* z,
+                                                   int M, float sigma, float lgg, float gate, float* phi) {
+  __shared__ float px[kPfMaxP], py[kPfMaxP], pl[kPfMaxP];
+  __shared__ float red[16];
+  const int u = blockIdx.x;
+  const int64_t b = (int64_t)u * P;
+  float sw = 0.0f, mx = 0.0f, my = 0.0f;
+  for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    const float x = st[b + p], y = st[n + b + p], l = lw[b + p];
+    px[p] = x;
+    py[p] = y;
+    pl[p] = l;
+    const float w = __expf(l);
+    sw += w;
+    mx += w * x;
+    my += w * y;
+  }
+  sw = block_sum(sw, red);
+  mx = block_sum(mx, red) / sw;
+  my = block_sum(my, red) / sw;
+  float cxx = 0.0f, cxy = 0.0f, cyy = 0.0f;
+  for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    const float w = __expf(pl[p]);
+    const float dx = px[p] - mx, dy = py[p] - my;
+    cxx += w * dx * dx;
+    cxy += w * dx * dy;
+    cyy += w * dy * dy;
+  }
+  const float s2 = sigma * sigma;
+  const float s00 = block_sum(cxx, red) / sw + s2, s01 = block_sum(cxy, red) / sw, s11 = block_sum(cyy, red) / sw + s2;
+  const float det = s00 * s11 - s01 * s01;
+  const float lc = lgg - logf(kTwoPi * s2), inv2 = 0.5f / s2;
+  const int wv = threadIdx.x / kWave, nw = blockDim.x / kWave, lane = lane_id();
+  for (int i = wv; i < M; i += nw) {
+    const float2 zi = z[i];
+    const float nx = zi.x - mx, ny = zi.y - my;
+    const float d2 = (s11 * nx * nx - 2.0f * s01 * nx * ny + s00 * ny * ny) / det;
+    if (!(d2 <= gate)) {
+      if (lane == 0) phi[(size_t)u * M + i] = -INFINITY;
+      continue;
+    }
+    float m = -INFINITY;
+    for (int p = lane; p < P; p += kWave) {
+      const float ex = zi.x - px[p], ey = zi.y - py[p];
+      m = fmaxf(m, pl[p] - (ex * ex + ey * ey) * inv2);
+    }
+    m = wave_max(m);
+    float s = 0.0f;
+    for (int p = lane; p < P; p += kWave) {
+      const float ex = zi.x - px[p], ey = zi.y - py[p];
+      s += __expf(pl[p] - (ex * ex + ey * ey) * inv2 - m);
+    }
+    s = wave_sum(s);
+    if (lane == 0) phi[(size_t)u * M + i] = lc + m + logf(s);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_pf_update(const float* st, const float* lw, int U, int P, int64_t n,
+                                                   const int32_t* rec_u, const int32_t* rec_off, const int32_t* rec_z,
+                                                   const float2* z, int M, float sigma, float ess_frac, uint32_t ctr2,
+                                                   uint32_t k0, uint32_t k1, float* ost, float* olw, int64_t no,
+                                                   int32_t* resampled) {
+  __shared__ float a[kPfMaxP];
+  __shared__ float red[16];
+  __shared__ float tsum[256];
+  __shared__ int bad;
+  const int r = blockIdx.x;
+  const int u = rec_u[r];
+  const int e0 = rec_off[r], e1 = rec_off[r + 1];
+  // a record naming a track or a detection out of range is reported (-1) and left unwritten
+  if (threadIdx.x == 0) {
+    int ok = u >= 0 && u < U && e0 >= 0 && e1 >= e0;
+    for (int e = e0; ok && e < e1; ++e) ok = rec_z[e] >= 0 && rec_z[e] < M;
+    bad = !ok;
+    if (!ok) resampled[r] = -1;
+  }
+  __syncthreads();
+  if (bad) return;
+  const int64_t b = (int64_t)u * P, ob = (int64_t)r * P;
+  const float inv2 = 0.5f / (sigma * sigma), lc = -logf(kTwoPi * sigma * sigma);
+  float m = -INFINITY;
+  for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    const float x = st[b + p], y = st[n + b + p];
+    float v = lw[b + p];
+    for (int e = e0; e < e1; ++e) {
+      const float2 zi = z[rec_z[e]];
+      const float ex = zi.x - x, ey = zi.y - y;
+      v += lc - (ex * ex + ey * ey) * inv2;
+    }
+    a[p] = v;
+    m = fmaxf(m, v);
+  }
+  m = block_max(m, red);
+  float s = 0.0f;
+  for (int p = threadIdx.x; p < P; p += blockDim.x) s += __expf(a[p] - m);
+  s = block_sum(s, red);
+  const float L = m + logf(s);
+  float q2 = 0.0f;
+  for (int p = threadIdx.x; p < P; p += blockDim.x) {
+    const float l = a[p] - L;
+    a[p] = l;
+    q2 += __expf(2.0f * l);
+  }
+  q2 = block_sum(q2, red);
+  const bool rs = 1.0f / q2 < ess_frac * (float)P;
+  if (threadIdx.x == 0) resampled[r] = rs ? 1 : 0;
+  if (!rs) {
+    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) ost[c * no + ob + p] = st[c * n + b + p];
+      olw[ob + p] = a[p];
+    }
+    return;
+  }
+  // cumulative weights: each thread scans a contiguous chunk, chunk totals scanned in order
+  const int T = blockDim.x, chunk = (P + T - 1) / T;
+  const int p0 = min(P, (int)threadIdx.x * chunk), p1 = min(P, p0 + chunk);
+  float c = 0.0f;
+  for (int p = p0; p < p1; ++p) c += __expf(a[p]);
+  __syncthreads();
+  tsum[threadIdx.x] = c;
+  __syncthreads();
+  float off = 0.0f;
+  for (int t = 0; t < (int)threadIdx.x; ++t) off += tsum[t];
+  for (int p = p0; p < p1; ++p) {
+    off += __expf(a[p]);
+    a[p] = off;  // each thread rewrites only its own chunk, read only by it above
+  }
+  __syncthreads();
+  const Philox4 rr = philox4((uint32_t)r, 0u, ctr2, 0u, k0, k1);
+  const float u0 = (float)(rr.w[0] >> 8) * (1.0f / 16777216.0f);
+  const float invP = 1.0f / (float)P, lP = -logf((float)P);
+  for (int j = threadIdx.x; j < P; j += blockDim.x) {
+    const float pos = ((float)j + u0) * invP;
+    int lo = 0, hi = P - 1;  // first index with pos < cum, the last one if none
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (pos < a[mid]) hi = mid;
+      else lo = mid + 1;
+    }
+#pragma unroll
+    for (int cc = 0; cc < 5; ++cc) ost[cc * no + ob + j] = st[cc * n + b + lo];
+    olw[ob + j] = lP;
+  }
+}
+
+}  // namespace
+
+}  // namespace glmb
+
+using namespace glmb;
+
+extern "C" {
+
+glmb_status glmb_pf_predict(void* stream, float* state, int64_t n, float dt, float sigma_a, float sigma_w,
+                            uint64_t seed, int32_t k) {
+  if (n < 0 || (n > 0 && !state) || !(dt >= 0.0f) || !(sigma_a >= 0.0f) || !(sigma_w >= 0.0f) || k < 0)
+    return GLMB_E_ARG;
+  if (n == 0) return GLMB_OK;
+  hipLaunchKernelGGL(k_pf_predict, dim3(cdiv(n, 256)), dim3(256), 0, (hipStream_t)stream, state, n, dt, sigma_a,
+                     sigma_w, (uint32_t)k * 16u + 2u, (uint32_t)seed, (uint32_t)(seed >> 32));
+  return hipGetLastError() == hipSuccess ? GLMB_OK : GLMB_E_DEVICE;
+}
+
+glmb_status glmb_pf_loglik(void* stream, const float* state, const float* logw, int32_t U, int32_t P, const float* z,
+                           int32_t M, float sigma, float gamma, float gate, float* phi) {
+  if (U < 0 || P < 1 || M < 0 || (U > 0 && (!state || !logw)) || (M > 0 && !z) || (U * (int64_t)M > 0 && !phi) ||
+      !(sigma > 0.0f) || !(gamma > 0.0f) || !(gate >= 0.0f))
+    return GLMB_E_ARG;
+  if (P > kPfMaxP) return GLMB_E_CAPACITY;
+  if (U == 0 || M == 0) return GLMB_OK;
+  hipLaunchKernelGGL(k_pf_loglik, dim3(U), dim3(256), 0, (hipStream_t)stream, state, logw, P, (int64_t)U * P,
+                     (const float2*)z, M, sigma, logf(gamma), gate, phi);
+  return hipGetLastError() == hipSuccess ? GLMB_OK : GLMB_E_DEVICE;
+}
+
+glmb_status glmb_pf_update(void* stream, const float* state, const float* logw, int32_t U, int32_t P, int32_t R,
+                           const int32_t* rec_u, const int32_t* rec_off, const int32_t* rec_z, const float* z,
+                           int32_t M, float sigma, float ess_frac, uint64_t seed, int32_t k, float* out_state,
+                           float* out_logw, int32_t* resampled) {
+  if (U < 1 || P < 1 || R < 0 || M < 0 || !state || !logw ||
+      (R > 0 && (!rec_u || !rec_off || !out_state || !out_logw || !resampled)) || (M > 0 && (!z || !rec_z)) ||
+      !(sigma > 0.0f) || !(ess_frac >= 0.0f) || k < 0)
+    return GLMB_E_ARG;
+  if (P > kPfMaxP) return GLMB_E_CAPACITY;
+  if (R == 0) return GLMB_OK;
+  hipLaunchKernelGGL(k_pf_update, dim3(R), dim3(256), 0, (hipStream_t)stream, state, logw, U, P, (int64_t)U * P,
+                     rec_u, rec_off, rec_z, (const float2*)z, M, sigma, ess_frac, (uint32_t)k * 16u + 3u, (uint32_t)seed,
+                     (uint32_t)(seed >> 32), out_state, out_logw, (int64_t)R * P, resampled);
+  return hipGetLastError() == hipSuccess ? GLMB_OK : GLMB_E_DEVICE;
+}
+
+}  // extern "C"

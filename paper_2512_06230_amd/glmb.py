@@ -21,6 +21,7 @@ EXPORTS = ["glmb_status_string", "glmb_last_error", "glmb_create", "glmb_destroy
            "glmb_estimate", "glmb_stats", "glmb_update_diag", "glmb_update_theta", "glmb_set_proposal",
            "glmb_pair_features", "glmb_proposal_lost", "glmb_mlp_forward", "glmb_mlp_grad", "glmb_mlp_adam",
            "glmb_mlp_grad_noalloc", "glmb_set_sampling", "glmb_set_joint_reweighting",
+           "glmb_pf_predict", "glmb_pf_loglik", "glmb_pf_update",
            "glmb_batch_create", "glmb_batch_destroy", "glmb_batch_set_schedule", "glmb_batch_scene",
            "glmb_batch_step", "glmb_batch_stats_get", "glmb_batch_last_error"]
 
@@ -104,6 +105,10 @@ def load_library(path: str = LIB_PATH):
     L.glmb_mlp_grad_noalloc.argtypes = [vp, vp, _F, vp, vp, vp, ctypes.c_int32, vp, vp]
     L.glmb_set_sampling.argtypes = [vp, ctypes.c_int32, ctypes.c_uint64]
     L.glmb_set_joint_reweighting.argtypes = [vp, ctypes.c_int32]
+    f, i32, u64 = ctypes.c_float, ctypes.c_int32, ctypes.c_uint64
+    L.glmb_pf_predict.argtypes = [vp, vp, ctypes.c_int64, f, f, f, u64, i32]
+    L.glmb_pf_loglik.argtypes = [vp, vp, vp, i32, i32, vp, i32, f, f, f, vp]
+    L.glmb_pf_update.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, vp, vp, i32, f, f, u64, i32, vp, vp, vp]
     L.glmb_mlp_adam.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                 ctypes.c_float]
     L.glmb_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(Params), ctypes.c_int, ctypes.c_int32,
@@ -469,3 +474,67 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---- particle form (stateless calls on torch's current stream) ----------------------------
+def _stream_ptr(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _need(t, dtype, shape, what):
+    import torch
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+        raise ValueError("%s: contiguous CUDA %s tensor of shape %s expected" % (what, dtype, tuple(shape)))
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def pf_predict(state, dt: float, sigma_a: float, sigma_w: float, seed: int, k: int):
+    """CTRV prediction of every particle, in place (state: CUDA float32 [5, n])."""
+    import torch
+    L = load_library()
+    n = int(state.shape[1])
+    st = L.glmb_pf_predict(_stream_ptr(torch), _need(state, torch.float32, (5, n), "state"), n, float(dt),
+                           float(sigma_a), float(sigma_w), int(seed) & 0xFFFFFFFFFFFFFFFF, int(k))
+    if st != GLMB_OK:
+        raise GlmbError(st, "glmb_pf_predict: " + L.glmb_status_string(st).decode())
+
+
+def pf_loglik(state, logw, U: int, P: int, z, sigma: float, gamma: float, gate: float):
+    """phi [U, M] (CUDA float32) of particle tracks."""
+    import torch
+    L = load_library()
+    M = int(z.shape[0])
+    phi = torch.empty((U, M), dtype=torch.float32, device=state.device)
+    st = L.glmb_pf_loglik(_stream_ptr(torch), _need(state, torch.float32, (5, U * P), "state"),
+                          _need(logw, torch.float32, (U * P,), "logw"), int(U), int(P),
+                          _need(z, torch.float32, (M, 2), "z"), M, float(sigma), float(gamma), float(gate),
+                          ctypes.c_void_p(phi.data_ptr()))
+    if st != GLMB_OK:
+        raise GlmbError(st, "glmb_pf_loglik: " + L.glmb_status_string(st).decode())
+    return phi
+
+
+def pf_update(state, logw, U: int, P: int, rec_u, rec_off, rec_z, z, sigma: float, ess_frac: float, seed: int, k: int,
+              out=None):
+    """(out_state [5, R P], out_logw [R P], resampled [R]) CUDA tensors of the particle update;
+    `out` may hold preallocated (out_state, out_logw, resampled)."""
+    import torch
+    L = load_library()
+    R = int(rec_u.shape[0])
+    M = int(z.shape[0])
+    if out is None:
+        out = (torch.empty((5, R * P), dtype=torch.float32, device=state.device),
+               torch.empty((R * P,), dtype=torch.float32, device=state.device),
+               torch.empty((R,), dtype=torch.int32, device=state.device))
+    ost, olw, rs = out
+    rz = rec_z if rec_z.numel() else torch.zeros(1, dtype=torch.int32, device=state.device)
+    st = L.glmb_pf_update(_stream_ptr(torch), _need(state, torch.float32, (5, U * P), "state"),
+                          _need(logw, torch.float32, (U * P,), "logw"), int(U), int(P), R,
+                          _need(rec_u, torch.int32, (R,), "rec_u"), _need(rec_off, torch.int32, (R + 1,), "rec_off"),
+                          ctypes.c_void_p(rz.data_ptr()), _need(z, torch.float32, (M, 2), "z"), M, float(sigma),
+                          float(ess_frac), int(seed) & 0xFFFFFFFFFFFFFFFF, int(k),
+                          _need(ost, torch.float32, (5, R * P), "out_state"),
+                          _need(olw, torch.float32, (R * P,), "out_logw"), _need(rs, torch.int32, (R,), "resampled"))
+    if st != GLMB_OK:
+        raise GlmbError(st, "glmb_pf_update: " + L.glmb_status_string(st).decode())
+    return ost, olw, rs

@@ -1,0 +1,135 @@
+"""The particle form on the GPU (glmb_pf_predict / glmb_pf_loglik / glmb_pf_update) against
+the oracle's FP64 particle form on the same seeded inputs: predicted states (same Philox
+accelerations), association log-likelihoods and gate decisions, reweighted log weights, and
+the particles systematic resampling copies (records where a resampling position lies within
+1e-6 of a cumulative weight may pick differently in FP32 and FP64; the oracle names them)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+def _clouds(rng, U, P, spread=1.0):
+    centres = rng.uniform(5, 75, (U, 2))
+    st = np.zeros((5, U * P), np.float32)
+    for u in range(U):
+        sl = slice(u * P, (u + 1) * P)
+        st[0, sl] = centres[u, 0] + spread * rng.standard_normal(P)
+        st[1, sl] = centres[u, 1] + spread * rng.standard_normal(P)
+        st[2, sl] = rng.uniform(0, 12, P)
+        st[3, sl] = rng.uniform(-math.pi, math.pi, P)
+        st[4, sl] = rng.normal(0, 0.5, P) * (rng.uniform(size=P) < 0.8)  # some exactly straight
+    lw = rng.normal(0, 1, U * P)
+    for u in range(U):
+        sl = slice(u * P, (u + 1) * P)
+        lw[sl] -= np.logaddexp.reduce(lw[sl])
+    return st, lw.astype(np.float32), centres
+
+
+def _close(a, b, tol=TOL):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.abs(a - b) <= tol * np.maximum(np.abs(b), 1.0)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_predict_matches_oracle(torch_cuda, seed):
+    from paper_2512_06230_amd.glmb import pf_predict
+    torch = torch_cuda
+    rng = np.random.default_rng(50 + seed)
+    st, _, _ = _clouds(rng, 6, 700)
+    g = torch.as_tensor(st, device="cuda").contiguous()
+    for k in range(4):  # four steps, compared after each from the same FP32 input
+        ref = orc.pf_predict(g.cpu().numpy().astype(np.float64), 0.1, 2.0, 0.3, 1000 + seed, k)
+        pf_predict(g, 0.1, 2.0, 0.3, 1000 + seed, k)
+        got = g.cpu().numpy()
+        ok = _close(got, ref)
+        assert ok.all(), (k, np.argwhere(~ok)[:5], got[~ok][:5], ref[~ok][:5])
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_loglik_matches_oracle(torch_cuda, seed):
+    from paper_2512_06230_amd.glmb import pf_loglik
+    torch = torch_cuda
+    rng = np.random.default_rng(60 + seed)
+    U, P = 9, [64, 1000, 4096][seed]
+    st, lw, c = _clouds(rng, U, P, spread=[0.5, 1.0, 2.0][seed])
+    z = np.concatenate([c + rng.normal(0, 1.5, c.shape), rng.uniform(0, 80, (20, 2))]).astype(np.float32)
+    sigma, gamma, gate = 0.7, 3.0, 18.42
+    ref = orc.pf_loglik(st.astype(np.float64), lw.astype(np.float64), U, P, z.astype(np.float64), sigma, gamma, gate)
+    got = pf_loglik(torch.as_tensor(st, device="cuda"), torch.as_tensor(lw, device="cuda"), U, P,
+                    torch.as_tensor(z, device="cuda"), sigma, gamma, gate).cpu().numpy()
+    fin = np.isfinite(ref)
+    assert fin.sum() >= U  # every track gates its own detection at least
+    # the gate decision may differ only at the boundary (both sides' d^2 within 1e-4 G of it)
+    diff = fin != np.isfinite(got)
+    assert diff.sum() <= 1, diff.sum()
+    both = fin & np.isfinite(got)
+    assert _close(got[both], ref[both]).all(), (got[both][~_close(got[both], ref[both])][:5])
+
+
+@pytest.mark.parametrize("ess", [0.0, 0.5, 1.1])
+def test_update_matches_oracle(torch_cuda, ess):
+    from paper_2512_06230_amd.glmb import pf_update
+    torch = torch_cuda
+    rng = np.random.default_rng(70 + int(ess * 10))
+    U, P = 7, 1500
+    st, lw, c = _clouds(rng, U, P, spread=1.2)
+    st[2] = np.arange(U * P) % P  # tags the particles through the copies
+    z = np.concatenate([c + rng.normal(0, 1.0, c.shape), c + rng.normal(0, 1.0, c.shape)]).astype(np.float32)
+    rec_u, rec_off, rec_z = [], [0], []
+    for u in range(U):  # records: no detection, one, two (with the track's own detections)
+        for S in ([], [u], [u, U + u]):
+            rec_u.append(u)
+            rec_z += S
+            rec_off.append(len(rec_z))
+    rec_u, rec_off, rec_z = (np.array(a, np.int32) for a in (rec_u, rec_off, rec_z))
+    sigma = 0.8
+    ost_o, olw_o, rs_o, fr_o = orc.pf_update(st.astype(np.float64), lw.astype(np.float64), U, P, rec_u, rec_off,
+                                             rec_z, z.astype(np.float64), sigma, ess, 17, 2)
+    T = lambda a: torch.as_tensor(a, device="cuda")
+    ost, olw, rs = pf_update(T(st), T(lw), U, P, T(rec_u), T(rec_off), T(rec_z), T(z), sigma, ess, 17, 2)
+    ost, olw, rs = ost.cpu().numpy(), olw.cpu().numpy(), rs.cpu().numpy()
+    R = len(rec_u)
+    for r in range(R):
+        sl = slice(r * P, (r + 1) * P)
+        if fr_o[r]:
+            continue
+        assert rs[r] == rs_o[r], r
+        np.testing.assert_array_equal(ost[2, sl], ost_o[2, sl].astype(np.float32), err_msg="record %d copies" % r)
+        assert _close(ost[:, sl], ost_o[:, sl]).all(), r
+        assert _close(olw[sl], olw_o[sl]).all(), (r, olw[sl][:4], olw_o[sl][:4])
+    assert (rs == 1).sum() > 0 if ess > 1 else True
+
+
+def test_argument_errors_and_bad_records(torch_cuda):
+    from paper_2512_06230_amd.glmb import GLMB_E_ARG, GLMB_E_CAPACITY, GlmbError, pf_loglik, pf_update
+    torch = torch_cuda
+    st = torch.zeros((5, 2 * 5000), dtype=torch.float32, device="cuda")
+    lw = torch.full((2 * 5000,), -math.log(5000), dtype=torch.float32, device="cuda")
+    z = torch.zeros((3, 2), dtype=torch.float32, device="cuda")
+    with pytest.raises(GlmbError) as e:
+        pf_loglik(st, lw, 2, 5000, z, 1.0, 1.0, 18.0)
+    assert e.value.status == GLMB_E_CAPACITY
+    with pytest.raises(GlmbError) as e:
+        pf_loglik(st, lw, 2, 5000, z, -1.0, 1.0, 18.0)
+    assert e.value.status == GLMB_E_ARG
+    st = torch.zeros((5, 2 * 100), dtype=torch.float32, device="cuda")
+    lw = torch.full((200,), -math.log(100), dtype=torch.float32, device="cuda")
+    rec_u = torch.tensor([0, 5, 1], dtype=torch.int32, device="cuda")      # track 5 does not exist
+    rec_off = torch.tensor([0, 1, 2, 3], dtype=torch.int32, device="cuda")
+    rec_z = torch.tensor([0, 1, 7], dtype=torch.int32, device="cuda")      # detection 7 does not exist
+    _, _, rs = pf_update(st, lw, 2, 100, rec_u, rec_off, rec_z, z, 1.0, 0.5, 1, 0)
+    assert rs.cpu().tolist()[1:] == [-1, -1] and rs.cpu().tolist()[0] in (0, 1)
