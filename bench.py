@@ -97,6 +97,69 @@ def accuracy(estimates, truths, cutoff=10.0):
 
 
 
+def particle_leg(torch, scene, z, k, P, params, reps=20):
+    """The particle form on the benchmark scene's last scan: a cloud of P particles around every
+    object (n = N P), CTRV prediction, association log-likelihoods against every detection, and
+    the update of one record per object (its detections within 2 m).  Each call is timed with
+    events on torch's stream over `reps` launches; bytes are the states and log weights each
+    call must read and write (predict 40 B per particle; update 48 B per particle of a record),
+    exps one per (gated pair, particle)."""
+    import numpy as np
+    from paper_2512_06230_amd.glmb import pf_loglik, pf_predict, pf_update
+    rng = np.random.default_rng(7)
+    tx = scene.truth_x[k]
+    U = tx.shape[0]
+    st = np.zeros((5, U * P), np.float32)
+    st[0] = np.repeat(tx[:, 0], P) + rng.normal(0, 1.0, U * P)
+    st[1] = np.repeat(tx[:, 1], P) + rng.normal(0, 1.0, U * P)
+    st[2] = np.repeat(np.hypot(tx[:, 2], tx[:, 3]), P) + rng.normal(0, 0.5, U * P)
+    st[3] = np.repeat(np.arctan2(tx[:, 3], tx[:, 2]), P) + rng.normal(0, 0.2, U * P)
+    st[4] = rng.normal(0, 0.1, U * P)
+    lw = np.full(U * P, -np.log(P), np.float32)
+    zh = z.cpu().numpy()
+    d = np.linalg.norm(zh[None, :, :] - tx[:, None, :2], axis=2)
+    rec_u, rec_off, rec_z = [], [0], []
+    for u in range(U):
+        rec_u.append(u)
+        rec_z += np.nonzero(d[u] < 2.0)[0].tolist()
+        rec_off.append(len(rec_z))
+    T = lambda a: torch.as_tensor(np.asarray(a), device="cuda")
+    dst, dlw = T(st), T(lw)
+    ru, ro, rz = (T(np.asarray(a, np.int32)) for a in (rec_u, rec_off, rec_z))
+    sig, gam, gate = params["sigma_z"], params["det_rate"], params["gate_d2"]
+    out = (torch.empty((5, U * P), dtype=torch.float32, device="cuda"), torch.empty(U * P, dtype=torch.float32,
+           device="cuda"), torch.empty(U, dtype=torch.int32, device="cuda"))
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps * 1e-3
+
+    work = dst.clone()
+    t_pred = timed(lambda: pf_predict(work, 1.0, 1.0, 0.1, 3, k))
+    phi = pf_loglik(dst, dlw, U, P, z, sig, gam, gate)
+    gated = int(torch.isfinite(phi).sum())
+    t_lik = timed(lambda: pf_loglik(dst, dlw, U, P, z, sig, gam, gate))
+    t_upd = timed(lambda: pf_update(dst, dlw, U, P, ru, ro, rz, z, sig, 0.5, 3, k, out=out))
+    hbm = HBM_PEAK_GBS * 1e9
+    b_pred, b_upd = 40.0 * U * P, 48.0 * U * P
+    x_lik = float(gated) * P
+    return {"workload": "%d tracks x %d particles (CTRV), %d detections, %d gated pairs, %d update records"
+                        % (U, P, zh.shape[0], gated, U),
+            "predict": {"ms": t_pred * 1e3, "particles_per_s": U * P / t_pred, "bound": "hbm",
+                        "achieved_gbs": b_pred / t_pred / 1e9, "frac": b_pred / t_pred / hbm},
+            "loglik": {"ms": t_lik * 1e3, "bound": "trans", "exps_per_s": x_lik / t_lik,
+                       "frac": x_lik / t_lik / TRANS_PER_S},
+            "update": {"ms": t_upd * 1e3, "bound": "hbm", "achieved_gbs": b_upd / t_upd / 1e9,
+                       "frac": b_upd / t_upd / hbm}}
+
+
 def assoc_source_sha(rec):
     """sha256 of the source region holding the association kernels (the text between the
     two marker lines named in the traffic record), or None when the file or a marker is gone."""
@@ -127,6 +190,8 @@ def main():
                          "hypotheses (with H_max set to the same number); the rate is scaled by this share of H_max")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--batch-scenes", type=int, default=256, help="scenes of the batched leg (0: skip it)")
+    ap.add_argument("--particles", type=int, default=4096,
+                    help="particles per track of the particle-form leg (0: skip it)")
     ap.add_argument("--convoy-steps", type=int, default=548,
                     help="steps of the paper-setting leg (20-object convoy, H_max 100, H_up 100; 0: skip it)")
     ap.add_argument("--no-autotune-cache", action="store_true")
@@ -294,6 +359,10 @@ def main():
                       "paper": "update under the 0.1 s real-time budget almost always on an NVIDIA L40S "
                                "(Sec. 4.2, N=20, H_max=100; no number printed)"}
 
+    particle = None
+    if args.particles > 0 and args.preset == "c3":
+        particle = particle_leg(torch, scene, zs[n_scans - 1], n_scans - 1, args.particles, params)
+
     batched = None
     if args.batch_scenes > 0:
         from paper_2512_06230_amd.autotune import BatchTuner, workload_key
@@ -387,6 +456,8 @@ def main():
         out["batched"] = batched
     if convoy_leg is not None:
         out["convoy"] = convoy_leg
+    if particle is not None:
+        out["particle"] = particle
 
     if not args.no_cpu_baseline:
         from oracle.oracle import Oracle

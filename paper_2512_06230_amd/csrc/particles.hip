@@ -104,10 +104,14 @@ __device__ float block_max(float v, float* sh) {
   return r;
 }
 
+constexpr int kPfGated = 1024;  // gated detections of one track listed in LDS per pass
+
 __global__ __launch_bounds__(256) void k_pf_loglik(const float* st, const float* lw, int P, int64_t n, const float2* z,
                                                    int M, float sigma, float lgg, float gate, float* phi) {
   __shared__ float px[kPfMaxP], py[kPfMaxP], pl[kPfMaxP];
   __shared__ float red[16];
+  __shared__ int glist[kPfGated];
+  __shared__ int gcount;
   const int u = blockIdx.x;
   const int64_t b = (int64_t)u * P;
   float sw = 0.0f, mx = 0.0f, my = 0.0f;
@@ -137,38 +141,52 @@ __global__ __launch_bounds__(256) void k_pf_loglik(const float* st, const float*
   const float det = s00 * s11 - s01 * s01;
   const float lc = lgg - logf(kTwoPi * s2), inv2 = 0.5f / s2;
   const int wv = threadIdx.x / kWave, nw = blockDim.x / kWave, lane = lane_id();
-  for (int i = wv; i < M; i += nw) {
-    const float2 zi = z[i];
-    const float nx = zi.x - mx, ny = zi.y - my;
-    const float d2 = (s11 * nx * nx - 2.0f * s01 * nx * ny + s00 * ny * ny) / det;
-    if (!(d2 <= gate)) {
-      if (lane == 0) phi[(size_t)u * M + i] = -INFINITY;
-      continue;
+  // the gate over all detections in parallel (one thread per detection), the gated ones listed
+  // in LDS, then one wave per listed detection; the order of the list does not matter (each
+  // detection's value is computed by one wave in a fixed order)
+  for (int i0 = 0; i0 < M; i0 += kPfGated) {
+    if (threadIdx.x == 0) gcount = 0;
+    __syncthreads();
+    for (int i = i0 + threadIdx.x; i < min(M, i0 + kPfGated); i += blockDim.x) {
+      const float2 zi = z[i];
+      const float nx = zi.x - mx, ny = zi.y - my;
+      const float d2 = (s11 * nx * nx - 2.0f * s01 * nx * ny + s00 * ny * ny) / det;
+      if (d2 <= gate) glist[atomicAdd(&gcount, 1)] = i;
+      else phi[(size_t)u * M + i] = -INFINITY;
     }
-    float m = -INFINITY;
-    for (int p = lane; p < P; p += kWave) {
-      const float ex = zi.x - px[p], ey = zi.y - py[p];
-      m = fmaxf(m, pl[p] - (ex * ex + ey * ey) * inv2);
+    __syncthreads();
+    const int ng = gcount;
+    for (int g = wv; g < ng; g += nw) {
+      const int i = glist[g];
+      const float2 zi = z[i];
+      float m = -INFINITY;
+      for (int p = lane; p < P; p += kWave) {
+        const float ex = zi.x - px[p], ey = zi.y - py[p];
+        m = fmaxf(m, pl[p] - (ex * ex + ey * ey) * inv2);
+      }
+      m = wave_max(m);
+      float s = 0.0f;
+      for (int p = lane; p < P; p += kWave) {
+        const float ex = zi.x - px[p], ey = zi.y - py[p];
+        s += __expf(pl[p] - (ex * ex + ey * ey) * inv2 - m);
+      }
+      s = wave_sum(s);
+      if (lane == 0) phi[(size_t)u * M + i] = lc + m + logf(s);
     }
-    m = wave_max(m);
-    float s = 0.0f;
-    for (int p = lane; p < P; p += kWave) {
-      const float ex = zi.x - px[p], ey = zi.y - py[p];
-      s += __expf(pl[p] - (ex * ex + ey * ey) * inv2 - m);
-    }
-    s = wave_sum(s);
-    if (lane == 0) phi[(size_t)u * M + i] = lc + m + logf(s);
+    __syncthreads();  // the list is rebuilt for the next chunk of detections
   }
 }
 
-__global__ __launch_bounds__(256) void k_pf_update(const float* st, const float* lw, int U, int P, int64_t n,
+constexpr int kPfUpdT = 1024;  // most threads of the update's workgroup (four particles each at P = 4096)
+
+__global__ __launch_bounds__(kPfUpdT) void k_pf_update(const float* st, const float* lw, int U, int P, int64_t n,
                                                    const int32_t* rec_u, const int32_t* rec_off, const int32_t* rec_z,
                                                    const float2* z, int M, float sigma, float ess_frac, uint32_t ctr2,
                                                    uint32_t k0, uint32_t k1, float* ost, float* olw, int64_t no,
                                                    int32_t* resampled) {
   __shared__ float a[kPfMaxP];
   __shared__ float red[16];
-  __shared__ float tsum[256];
+  __shared__ float tsum[kPfUpdT];
   __shared__ int bad;
   const int r = blockIdx.x;
   const int u = rec_u[r];
@@ -290,7 +308,10 @@ glmb_status glmb_pf_update(void* stream, const float* state, const float* logw, 
     return GLMB_E_ARG;
   if (P > kPfMaxP) return GLMB_E_CAPACITY;
   if (R == 0) return GLMB_OK;
-  hipLaunchKernelGGL(k_pf_update, dim3(R), dim3(256), 0, (hipStream_t)stream, state, logw, U, P, (int64_t)U * P,
+  // 256 threads up to 2047 particles, 1024 above (measured: 0.020 vs 0.025 ms at P = 1024 and
+  // 0.079 vs 0.041 ms at P = 4096 for 500 records)
+  const int T = P >= 2048 ? kPfUpdT : 256;
+  hipLaunchKernelGGL(k_pf_update, dim3(R), dim3(T), 0, (hipStream_t)stream, state, logw, U, P, (int64_t)U * P,
                      rec_u, rec_off, rec_z, (const float2*)z, M, sigma, ess_frac, (uint32_t)k * 16u + 3u, (uint32_t)seed,
                      (uint32_t)(seed >> 32), out_state, out_logw, (int64_t)R * P, resampled);
   return hipGetLastError() == hipSuccess ? GLMB_OK : GLMB_E_DEVICE;

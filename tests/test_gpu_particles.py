@@ -80,12 +80,12 @@ def test_loglik_matches_oracle(torch_cuda, seed):
     assert _close(got[both], ref[both]).all(), (got[both][~_close(got[both], ref[both])][:5])
 
 
-@pytest.mark.parametrize("ess", [0.0, 0.5, 1.1])
-def test_update_matches_oracle(torch_cuda, ess):
+@pytest.mark.parametrize("ess,P", [(0.0, 1500), (0.5, 1500), (1.1, 1500), (0.5, 4096), (1.1, 4096)])
+def test_update_matches_oracle(torch_cuda, ess, P):
     from paper_2512_06230_amd.glmb import pf_update
     torch = torch_cuda
-    rng = np.random.default_rng(70 + int(ess * 10))
-    U, P = 7, 1500
+    rng = np.random.default_rng(70 + int(ess * 10) + P)
+    U = 7
     st, lw, c = _clouds(rng, U, P, spread=1.2)
     st[2] = np.arange(U * P) % P  # tags the particles through the copies
     z = np.concatenate([c + rng.normal(0, 1.0, c.shape), c + rng.normal(0, 1.0, c.shape)]).astype(np.float32)
