@@ -367,12 +367,15 @@ def main():
     if args.batch_scenes > 0:
         from paper_2512_06230_amd.autotune import BatchTuner, workload_key
         from paper_2512_06230_amd.glmb import Batch
-        nb_warm, nb_steps = 12, 5  # warm-up steps also serve the schedule tuner when its cache misses
-        specs = sc.batch_specs(args.batch_scenes, seed=args.seed, n_steps=nb_warm + nb_steps)
-        bscenes = [sc.make_scene(sp, n_steps=nb_warm + nb_steps) for sp, _ in specs]
+        # warm-up steps also serve the schedule tuner when its cache misses; then 50 timed steps of
+        # the tuned schedule and, from the same state onwards, 4 steps with one worker (the scenes
+        # one after another, one launch sequence per scene) for comparison
+        nb_warm, nb_steps, nb_seq = 12, 50, 4
+        specs = sc.batch_specs(args.batch_scenes, seed=args.seed, n_steps=nb_warm + nb_steps + nb_seq)
+        bscenes = [sc.make_scene(sp, n_steps=nb_warm + nb_steps + nb_seq) for sp, _ in specs]
         bparams = [sc.filter_params(sp, h, 1e-5) for sp, h in specs]
         bz, boff = [], []
-        for k in range(nb_warm + nb_steps):  # every scan of every scene resident in HBM
+        for k in range(nb_warm + nb_steps + nb_seq):  # every scan of every scene resident in HBM
             zk = [bs.meas[k] for bs in bscenes]
             boff.append(np.concatenate([[0], np.cumsum([z.shape[0] for z in zk])]).astype(np.int32))
             bz.append(torch.as_tensor(np.concatenate(zk, axis=0).reshape(-1, 2), device=dev).contiguous())
@@ -392,11 +395,21 @@ def main():
         torch.cuda.synchronize()
         el_b = time.perf_counter() - tb
         bst = batch.stats()
+        batch.set_schedule(1, True)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        for k in range(nb_warm + nb_steps, nb_warm + nb_steps + nb_seq):
+            batch.step(k, bz[k], boff[k])
+        torch.cuda.synchronize()
+        el_s = time.perf_counter() - ts
         batched = {"value": len(bscenes) * nb_steps / el_b, "unit": "scene-updates/s",
                    "ms_per_step": 1e3 * el_b / nb_steps, "scenes": len(bscenes), "steps": nb_steps,
                    "warmup": nb_warm, "workers": bst["workers"], "longest_first": bool(bst["longest_first"]),
                    "workload": "%d scenes: N ~ U{5..200} objects, H_max ~ logU[256, 8192], clutter 2/scan, "
                                "100x100 m, warm start" % len(bscenes),
+                   "one_scene_at_a_time": {"value": len(bscenes) * nb_seq / el_s, "ms_per_step": 1e3 * el_s / nb_seq,
+                                           "steps": nb_seq, "workers": 1},
+                   "speedup_vs_one_scene_at_a_time": (len(bscenes) * nb_steps / el_b) / (len(bscenes) * nb_seq / el_s),
                    "tuner_trials": [{"workers": c[0], "longest_first": c[1], "step_ms": ms} for c, ms in tuner.trials],
                    "mean_h_max": float(np.mean([h for _, h in specs])),
                    "mean_objects": float(np.mean([sp.n_obj for sp, _ in specs]))}

@@ -462,7 +462,6 @@ struct Oracle {
 
   // ---- prediction: survival of every track and LMB births (Sec. 3, prediction) -------
   int predict(int k) {
-    (void)k;
     double F[16], Q[16];
     cv_model(p, F, Q);
     const int32_t n_old = (int32_t)inst.size();
@@ -499,7 +498,87 @@ struct Oracle {
       dim(births[b].r, &bb[b], &bd[b], &y);
       b_yes[b] = y;
     }
+    // children: (parent, value, canonical key) with their instance sets
     std::vector<ParentSpec> specs(hyp.size());
+    std::vector<Child> ch;
+    std::vector<std::vector<int32_t>> sampled_set;  // sampled children: their instance sets
+    if (sample_hup > 0) {
+      // The Bernoulli stage of the paper's generator (Sec. 3, hypothesis generation), with
+      // survival decided in the prediction: per prior hypothesis h and draw d, every track
+      // survives when the Philox uniform at (label slot, d, h, 16 k + 4) lies below p_S and every
+      // pending birth b joins when the uniform at (labels + b, d, h, 16 k + 4) lies below r_b;
+      // distinct outcomes of a parent are kept with their exact predicted weight, ranked by
+      // (weight, parent rank, first draw), the H_max best kept; canonical key (parent, draw).
+      // Label slots are the positions of the labels in ascending order over the prior state.
+      std::vector<Label> labs;
+      for (const auto& x : inst) labs.push_back(x.lab);
+      std::sort(labs.begin(), labs.end());
+      labs.erase(std::unique(labs.begin(), labs.end()), labs.end());
+      const int32_t ns = (int32_t)std::count_if(labs.begin(), labs.end(), [&](const Label& l) {
+        for (int32_t b = 0; b < nb; ++b)
+          if (births[b].lab == l) return false;
+        return true;
+      });
+      struct Drawn {
+        int32_t parent, draw;
+        double value;
+        std::vector<int32_t> set;
+      };
+      std::vector<Drawn> drawn;
+      std::map<std::pair<int32_t, std::vector<int32_t>>, bool> seen;
+      d_fragile.clear();
+      d_draws = 0;
+      for (size_t h = 0; h < hyp.size(); ++h) {
+        bool fragile = false;
+        for (int32_t d = 0; d < sample_hup; ++d) {
+          std::vector<int32_t> set;
+          double v = hyp[h].logw;
+          for (int32_t u : hyp[h].inst) {
+            const int32_t slot = (int32_t)(std::lower_bound(labs.begin(), labs.end(), inst[u].lab) - labs.begin());
+            const double x = philox_uniform(sample_seed, (uint32_t)slot, (uint32_t)d, (uint32_t)h, (uint32_t)k * 16u + 4u);
+            if (std::fabs(x - p.ps) < sample_margin) fragile = true;
+            if (x < p.ps) {
+              set.push_back(u);
+              v += std::log(p.ps);
+            } else {
+              v += std::log1p(-p.ps);
+            }
+          }
+          for (int32_t b = 0; b < nb; ++b) {
+            const double x = philox_uniform(sample_seed, (uint32_t)(ns + b), (uint32_t)d, (uint32_t)h, (uint32_t)k * 16u + 4u);
+            if (std::fabs(x - births[b].r) < sample_margin) fragile = true;
+            if (x < births[b].r) {
+              set.push_back(n_old + b);
+              v += std::log(births[b].r);
+            } else {
+              v += std::log1p(-births[b].r);
+            }
+          }
+          std::sort(set.begin(), set.end());
+          ++d_draws;
+          auto key = std::make_pair((int32_t)h, set);
+          if (seen.count(key)) continue;
+          seen[key] = true;
+          drawn.push_back({(int32_t)h, d, v, set});
+        }
+        if (fragile) d_fragile.push_back((int32_t)h);
+      }
+      d_unique = (int64_t)drawn.size();
+      std::sort(drawn.begin(), drawn.end(), [](const Drawn& x, const Drawn& y) {
+        if (x.value != y.value) return x.value > y.value;
+        if (x.parent != y.parent) return x.parent < y.parent;
+        return x.draw < y.draw;
+      });
+      if ((int)drawn.size() > p.hmax) drawn.resize(p.hmax);
+      for (auto& x : drawn) {
+        Child c;
+        c.parent = x.parent;
+        c.value = x.value;
+        c.key = {x.draw};
+        ch.push_back(c);
+        sampled_set.push_back(x.set);
+      }
+    } else {
     for (size_t h = 0; h < hyp.size(); ++h) {
       const int32_t nt = (int32_t)hyp[h].inst.size();
       specs[h].base = hyp[h].logw + nt * tb;
@@ -536,7 +615,8 @@ struct Oracle {
         s.groups.push_back(g);
       }
     }
-    std::vector<Child> ch = top_k(specs, p.hmax);
+    ch = top_k(specs, p.hmax);
+    }
     // children's instance sets; identical sets from different parents are merged
     struct Merged {
       std::vector<int32_t> set;
@@ -545,17 +625,22 @@ struct Oracle {
     };
     std::map<std::vector<int32_t>, int32_t> where;
     std::vector<Merged> merged;
-    for (const Child& c : ch) {
-      const Hyp& ph = hyp[c.parent];
-      const int32_t nt = (int32_t)ph.inst.size();
-      std::vector<char> flip(nt + nb, 0);
-      for (auto& pk : c.picks) flip[specs[c.parent].groups[pk.first].id] = 1;
+    for (size_t ci = 0; ci < ch.size(); ++ci) {
+      const Child& c = ch[ci];
       std::vector<int32_t> set;
-      for (int32_t d = 0; d < nt; ++d)
-        if ((bool)t_yes != (bool)flip[d]) set.push_back(ph.inst[d]);
-      for (int32_t b = 0; b < nb; ++b)
-        if ((bool)b_yes[b] != (bool)flip[nt + b]) set.push_back(n_old + b);
-      std::sort(set.begin(), set.end());
+      if (sample_hup > 0) {
+        set = sampled_set[ci];
+      } else {
+        const Hyp& ph = hyp[c.parent];
+        const int32_t nt = (int32_t)ph.inst.size();
+        std::vector<char> flip(nt + nb, 0);
+        for (auto& pk : c.picks) flip[specs[c.parent].groups[pk.first].id] = 1;
+        for (int32_t d = 0; d < nt; ++d)
+          if ((bool)t_yes != (bool)flip[d]) set.push_back(ph.inst[d]);
+        for (int32_t b = 0; b < nb; ++b)
+          if ((bool)b_yes[b] != (bool)flip[nt + b]) set.push_back(n_old + b);
+        std::sort(set.begin(), set.end());
+      }
       auto it = where.find(set);
       if (it == where.end()) {
         where[set] = (int32_t)merged.size();

@@ -169,3 +169,59 @@ def test_seed_changes_and_repeats_the_draws():
         res.append([(int(a), tuple(int(x) for x in t)) for a, t in zip(out["hyp_parent"], out["theta"])])
     assert res[0] == res[1]
     assert res[0] != res[2]
+
+
+# --------------------------------------------------------------------------- sampled prediction
+def _pred_state(n_lab, n_hyp, rng, r_birth=()):
+    st = sc.random_state(rng, n_lab=n_lab, n_hyp=n_hyp, side=20.0, versions=1, p_present=1.0)
+    nb = len(r_birth)
+    st["birth_lab"] = np.array([[99, b] for b in range(nb)], np.int32).reshape(-1, 2)
+    st["birth_m"] = rng.uniform(0, 20, (nb, 4))
+    st["birth_P"] = np.tile(np.eye(4).reshape(1, 16), (nb, 1))
+    st["birth_r"] = np.asarray(r_birth, np.float64)
+    return st
+
+
+def test_sampled_prediction_frequencies():
+    """One hypothesis, one draw per seed: every track survives with frequency p_S and the
+    pending birth joins with frequency r_b (binomial tests)."""
+    rng = np.random.default_rng(12)
+    st = _pred_state(3, 1, rng, r_birth=[0.3])
+    p = dict(BASE, p_survive=0.7, h_max=10)
+    n = 3000
+    cnt = np.zeros(4)
+    for seed in range(n):
+        o = Oracle(p)
+        o.import_state(st)
+        o.set_sampling(1, seed)
+        o.predict(0)
+        out = o.export_state()
+        src = set(out["inst_src"][out["hyp_idx"][out["hyp_off"][0]:out["hyp_off"][1]]].tolist())
+        for j in range(3):
+            cnt[j] += j in src
+        cnt[3] += 3 in src  # the birth is input instance n_inst + 0
+    for j, pr in enumerate([0.7, 0.7, 0.7, 0.3]):
+        assert stats.binomtest(int(cnt[j]), n, pr).pvalue > 1e-4, (j, cnt[j] / n, pr)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_sampled_prediction_with_many_draws_is_the_exact_one(seed):
+    """With every survive/die x include/exclude outcome drawn (few dimensions, many draws), the
+    sampled prediction keeps them all and equals the brute-force prediction."""
+    rng = np.random.default_rng(40 + seed)
+    st = _pred_state(2 + seed % 2, 1 + seed % 3, rng, r_birth=[0.4])
+    p = dict(BASE, p_survive=0.6, h_max=1000)
+    o = Oracle(p)
+    o.import_state(st)
+    o.set_sampling(600, 5 + seed)
+    o.predict(0)
+    out = o.export_state()
+    ref, _ = bf.predict(st, p, 1000)
+    got = {}
+    for h in range(len(out["hyp_logw"])):
+        src = tuple(sorted(int(x) for x in out["inst_src"][out["hyp_idx"][out["hyp_off"][h]:out["hyp_off"][h + 1]]]))
+        got[src] = out["hyp_logw"][h]
+    want = {c["src"]: c["logw"] for c in ref}
+    assert set(got) == set(want)
+    for k in want:
+        assert abs(got[k] - want[k]) < 1e-9
