@@ -286,7 +286,7 @@ glmb_status glmb_destroy(glmb_ctx* x) {
                           &c.slot_part, &c.slot_age, &c.pm_part, &c.pe_part, &c.lz_t, &c.mlp_part, &c.est_buf, &c.ref_b1, &c.ref_opts, &c.ref_top, &c.ref_rest, &c.hopts, &c.rec_lead,
                           &c.s_theta, &c.s_value, &c.s_keys, &c.s_vals, &c.s_flag, &c.s_pre, &c.s_rkeys, &c.s_rvals,
                           &c.s_selv, &c.j_corr, &c.j_val, &c.j_keys, &c.child_perm, &c.j_lw, &c.j_tmp, &c.rows3,
-                          &c.rmass, &c.lz_r};
+                          &c.rmass, &c.lz_r, &c.s_prow, &c.s_hash, &c.s_nt, &c.s_krank, &c.s_br};
   for (auto* b : bufs) b->release();
   if (c.age_pin) (void)hipHostFree(c.age_pin);
   if (c.ev_ok)

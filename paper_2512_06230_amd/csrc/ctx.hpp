@@ -77,7 +77,8 @@ struct Ctx {
   int32_t sample_hup = 0;      // association maps drawn per hypothesis (0: exact top-H_max)
   uint64_t sample_seed = 0;    // Philox key
   int32_t sample_unique = 0;   // distinct maps among the last update's draws
-  DevBuf s_theta, s_value, s_keys, s_vals, s_flag, s_pre, s_rkeys, s_rvals, s_selv;
+  DevBuf s_theta, s_value, s_keys, s_vals, s_flag, s_pre, s_rkeys, s_rvals, s_selv, s_prow, s_hash, s_nt, s_krank,
+      s_br;
   // ---- exact-joint reweighting of the kept hypotheses (glmb_set_joint_reweighting)
   bool joint_rw = false;
   bool last_perm = false;  // the last update re-ranked its children: child_perm maps rank -> child
@@ -128,6 +129,18 @@ void mlp_adam(Ctx& c, float* params, float* m, float* v, const float* g, int t, 
 // allocation-free gradient: the partial sums live in a fixed per-device array, whose address
 // noalloc_setup (called by glmb_create with the context's device current) looks up once per device
 void noalloc_setup(int device);
+// sampled prediction (sample.hip): the kept outcomes in rank order, in the form the exact
+// prediction's selection leaves them for the merge of identical track sets
+struct PredictOut {
+  int32_t* crow;     // [n][NS + NB] child rows
+  uint64_t* hash;    // [n] row hashes
+  int32_t* ntc;      // [n] track counts
+  int32_t* parc;     // [n] parent hypotheses
+  float* value;      // [n] log weights, rank order
+  int32_t* keyrank;  // [n] canonical rank (below `nodes`)
+  int nodes;
+};
+int sample_predict(Ctx& c, int k, int NS, int NB, int U, float ps, const float* br, int K, PredictOut& out);
 // sampled children (sample.hip): returns the number of children taken (<= K), their values
 // buffer (filled by sample_children_devs) and the kept draws in rank order
 int sample_children(Ctx& c, int k, int M, int K, float** sel_value, const uint32_t** kept_draw);

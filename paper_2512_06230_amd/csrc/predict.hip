@@ -357,44 +357,71 @@ void stage_predict(Ctx& c, int k) {
   GLMB_HIP(hipMemcpyAsync(dby, by.data(), (NB + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
   GLMB_HIP(hipMemcpyAsync(dbs, bsv.data(), (nbs + 1) * sizeof(float), hipMemcpyHostToDevice, s));
   GLMB_HIP(hipMemcpyAsync(dbg, bgv.data(), (nbs + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  // ---- lower bound of the cut
-  float* V = need<float>(c.bprime, H);
-  float* pv = need<float>(c.pvals, (int64_t)H * (NB + 2));
-  int32_t* pm = need<int32_t>(c.pmult, (int64_t)H * (NB + 2));
-  GLMB_LAUNCH(k_pvals, cdiv(H, T), T, 0, s, H, NB, c.logw.as<float>(), c.ntrk.as<int32_t>(), tb, dt_, dbd, V, pv, pm);
-  kth_bound_mult(pv, pm, H * (NB + 2), p.h_max, t0, c.tmp, s);
-  // ---- items
-  int32_t* icount = need<int32_t>(c.ccount, H + 1);
-  GLMB_LAUNCH(k_pitems, H, 256, 0, s, H, nbs, nlt, SW, c.rows.as<int32_t>(), V, dt_, dbs, dbg, t0,
-              (const int32_t*)nullptr, icount, (float*)nullptr, (int32_t*)nullptr);
-  int32_t* itoff = need<int32_t>(c.it_off, H + 1);
-  scan_excl(icount, itoff, H, itoff + H, c.tmp, s);
-  int32_t nitem = 0;
-  GLMB_HIP(hipMemcpyAsync(&nitem, itoff + H, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(stream_sync(s));
-  float* itd = need<float>(c.it_delta, (int64_t)nitem + 1);
-  int32_t* itg = need<int32_t>(c.it_group, (int64_t)nitem + 1);
-  GLMB_LAUNCH(k_pitems, H, 256, 0, s, H, nbs, nlt, SW, c.rows.as<int32_t>(), V, dt_, dbs, dbg, t0,
-              (const int32_t*)itoff, icount, itd, itg);
-  // ---- exact selection
-  trace(c, "predict.select", nitem);
-  SelectIn si{H, V, itoff, itd, itg, p.h_max, t0, &c.sel_multi[0], c.coop_ok, c.force_multi};
-  Selected sel{};
-  std::string serr;
-  const int cap_nodes = p.cap_nodes > 0 ? p.cap_nodes : (1 << 22);
-  glmb_status st = select_topk(si, cap_nodes, c.sb, sel, s, serr, c.trace);
-  if (st != GLMB_OK) throw Error{st, serr};
-  const int n = sel.n;
-  if (n < 1) throw Error{GLMB_E_STATE, "prediction kept no hypothesis (non-finite weights?)"};
-  trace(c, "predict.merge", n);
   const int W2 = NS + NB;
-  // ---- child rows, duplicate merge
-  int32_t* crow = need<int32_t>(c.rows2, (int64_t)n * W2 + 1);
-  uint64_t* hash = need<uint64_t>(c.rec_keys, n + 1);
-  int32_t* ntc = need<int32_t>(c.ntrk2, n + 1);
-  int32_t* parc = need<int32_t>(c.child_par, n + 1);
-  GLMB_LAUNCH(k_prows, n, kWave, 0, s, n, NS, NB, SW, U, t_yes, dby, sel.node, sel.nd_parent, sel.nd_item, sel.nd_h, itg,
-              c.rows.as<int32_t>(), crow, hash, ntc, parc);
+  int n = 0, nodes = 0;
+  int32_t *crow = nullptr, *ntc = nullptr, *parc = nullptr;
+  uint64_t* hash = nullptr;
+  const float* selval = nullptr;
+  const int32_t* keyrank = nullptr;
+  if (c.sample_hup > 0) {
+    // ---- the paper's generator: survive/die and include/exclude drawn per hypothesis
+    trace(c, "predict.sampled", H, c.sample_hup);
+    std::vector<float> hr(NB + 1, 0.0f);
+    for (int b = 0; b < NB; ++b) hr[b] = hb[b].r;
+    float* br = need<float>(c.s_br, NB + 1);
+    GLMB_HIP(hipMemcpyAsync(br, hr.data(), (NB + 1) * sizeof(float), hipMemcpyHostToDevice, s));
+    PredictOut po{};
+    n = sample_predict(c, k, NS, NB, U, (float)p.p_survive, br, p.h_max, po);
+    if (n < 1) throw Error{GLMB_E_STATE, "sampled prediction kept no hypothesis"};
+    crow = po.crow;
+    hash = po.hash;
+    ntc = po.ntc;
+    parc = po.parc;
+    selval = po.value;
+    keyrank = po.keyrank;
+    nodes = po.nodes;
+  } else {
+    // ---- lower bound of the cut
+    float* V = need<float>(c.bprime, H);
+    float* pv = need<float>(c.pvals, (int64_t)H * (NB + 2));
+    int32_t* pm = need<int32_t>(c.pmult, (int64_t)H * (NB + 2));
+    GLMB_LAUNCH(k_pvals, cdiv(H, T), T, 0, s, H, NB, c.logw.as<float>(), c.ntrk.as<int32_t>(), tb, dt_, dbd, V, pv, pm);
+    kth_bound_mult(pv, pm, H * (NB + 2), p.h_max, t0, c.tmp, s);
+    // ---- items
+    int32_t* icount = need<int32_t>(c.ccount, H + 1);
+    GLMB_LAUNCH(k_pitems, H, 256, 0, s, H, nbs, nlt, SW, c.rows.as<int32_t>(), V, dt_, dbs, dbg, t0,
+                (const int32_t*)nullptr, icount, (float*)nullptr, (int32_t*)nullptr);
+    int32_t* itoff = need<int32_t>(c.it_off, H + 1);
+    scan_excl(icount, itoff, H, itoff + H, c.tmp, s);
+    int32_t nitem = 0;
+    GLMB_HIP(hipMemcpyAsync(&nitem, itoff + H, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GLMB_HIP(stream_sync(s));
+    float* itd = need<float>(c.it_delta, (int64_t)nitem + 1);
+    int32_t* itg = need<int32_t>(c.it_group, (int64_t)nitem + 1);
+    GLMB_LAUNCH(k_pitems, H, 256, 0, s, H, nbs, nlt, SW, c.rows.as<int32_t>(), V, dt_, dbs, dbg, t0,
+                (const int32_t*)itoff, icount, itd, itg);
+    // ---- exact selection
+    trace(c, "predict.select", nitem);
+    SelectIn si{H, V, itoff, itd, itg, p.h_max, t0, &c.sel_multi[0], c.coop_ok, c.force_multi};
+    Selected sel{};
+    std::string serr;
+    const int cap_nodes = p.cap_nodes > 0 ? p.cap_nodes : (1 << 22);
+    glmb_status st = select_topk(si, cap_nodes, c.sb, sel, s, serr, c.trace);
+    if (st != GLMB_OK) throw Error{st, serr};
+    n = sel.n;
+    if (n < 1) throw Error{GLMB_E_STATE, "prediction kept no hypothesis (non-finite weights?)"};
+    trace(c, "predict.merge", n);
+    // ---- child rows, duplicate merge
+    crow = need<int32_t>(c.rows2, (int64_t)n * W2 + 1);
+    hash = need<uint64_t>(c.rec_keys, n + 1);
+    ntc = need<int32_t>(c.ntrk2, n + 1);
+    parc = need<int32_t>(c.child_par, n + 1);
+    GLMB_LAUNCH(k_prows, n, kWave, 0, s, n, NS, NB, SW, U, t_yes, dby, sel.node, sel.nd_parent, sel.nd_item, sel.nd_h, itg,
+                c.rows.as<int32_t>(), crow, hash, ntc, parc);
+    selval = sel.value;
+    keyrank = sel.keyrank;
+    nodes = sel.nodes;
+  }
   uint64_t* hk = need<uint64_t>(c.keys, n + 1);
   uint32_t* hv = need<uint32_t>(c.vals32, n + 1);
   GLMB_LAUNCH(k_hash_keys, cdiv(n, T), T, 0, s, n, hash, hk, hv);
@@ -405,7 +432,7 @@ void stage_predict(Ctx& c, int k) {
   int32_t* mrep = mrank + n + 1;
   float* mval = need<float>(c.sel_logw, n + 1);
   GLMB_LAUNCH(k_leaders, cdiv(n, T), T, 0, s, n, W2, hk, hv, crow, leader);
-  GLMB_LAUNCH(k_merge, cdiv(n, T), T, 0, s, n, leader, sel.value, sel.keyrank, hk, hv, islead, mval, mrank, mrep);
+  GLMB_LAUNCH(k_merge, cdiv(n, T), T, 0, s, n, leader, selval, keyrank, hk, hv, islead, mval, mrank, mrep);
   int32_t* lpre = need<int32_t>(c.pre, n + 1);
   scan_excl(islead, lpre, n, tot, c.tmp, s);
   int32_t nh = 0;
@@ -414,7 +441,7 @@ void stage_predict(Ctx& c, int k) {
   uint64_t* lk = need<uint64_t>(c.rec_keys, nh + 1);
   uint32_t* lv = need<uint32_t>(c.rec_vals, nh + 1);
   int rb = 0;  // ranks are positions among the search's candidates, below its node count
-  while (((int64_t)1 << rb) < (int64_t)sel.nodes + 1) ++rb;
+  while (((int64_t)1 << rb) < (int64_t)nodes + 1) ++rb;
   rb = std::min(32, (rb + 7) / 8 * 8);
   GLMB_LAUNCH(k_lead_keys, cdiv(n, T), T, 0, s, n, rb, islead, lpre, mval, mrank, lk, lv);
   sort_pairs(lk, lv, nh, 0, 32 + rb, c.tk, c.tv, c.tmp, s);

@@ -175,7 +175,155 @@ __global__ void k_sample_devs(int n, int M, const uint32_t* rw, const int16_t* t
   }
 }
 
+// ---- the prediction's Bernoulli stage: one wave per draw w = h * h_up + d, lanes over the
+// columns of the child row (label slots, then pending births)
+__global__ __launch_bounds__(256) void k_psample_draws(int H, int NS, int NB, int stride, int U, int h_up,
+                                                       const int32_t* rows, const float* logw, float ps,
+                                                       const float* br, uint32_t ctr3, uint32_t seed_lo,
+                                                       uint32_t seed_hi, int32_t* drow, float* value, uint64_t* keys,
+                                                       uint32_t* vals, uint64_t* hfull, int32_t* ntv) {
+  const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (w >= (int64_t)H * h_up) return;
+  const int h = (int)(w / h_up), d = (int)(w % h_up);
+  const int W2 = NS + NB;
+  const int lane = lane_id();
+  float acc = 0.0f;
+  unsigned long long hs = 0;
+  int cnt = 0;
+  for (int s = lane; s < W2; s += kWave) {
+    int o = -1;
+    if (s < NS) {
+      const int u = rows[(size_t)h * stride + s];
+      if (u >= 0) {
+        const float x = uniform24(philox_first((uint32_t)s, (uint32_t)d, (uint32_t)h, ctr3, seed_lo, seed_hi));
+        if (x < ps) {
+          o = u;
+          acc += logf(ps);
+        } else {
+          acc += log1pf(-ps);
+        }
+      }
+    } else {
+      const float r = br[s - NS];
+      const float x = uniform24(philox_first((uint32_t)s, (uint32_t)d, (uint32_t)h, ctr3, seed_lo, seed_hi));
+      if (x < r) {
+        o = U + (s - NS);
+        acc += logf(r);
+      } else {
+        acc += log1pf(-r);
+      }
+    }
+    drow[(size_t)w * W2 + s] = o;
+    if (o >= 0) {
+      hs += mix64(((uint64_t)(uint32_t)s << 32) | (uint32_t)o);
+      ++cnt;
+    }
+  }
+  for (int t = kWave / 2; t > 0; t >>= 1) {
+    acc += __shfl_xor(acc, t, kWave);
+    hs += __shfl_xor(hs, t, kWave);
+    cnt += __shfl_xor(cnt, t, kWave);
+  }
+  if (lane == 0) {
+    value[w] = logw[h] + acc;
+    keys[w] = ((uint64_t)(uint32_t)h << 40) | (hs >> 24);
+    vals[w] = (uint32_t)w;
+    hfull[w] = hs;
+    ntv[w] = cnt;
+  }
+}
+
+// one thread per sorted draw: kept when no earlier draw of its (parent, fingerprint) run has
+// the same row
+__global__ void k_psample_distinct(int n, int W2, const uint64_t* keys, const uint32_t* vals, const int32_t* drow,
+                                   int32_t* flag) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const uint64_t k = keys[p];
+  const int32_t* a = drow + (size_t)vals[p] * W2;
+  int keep = 1;
+  for (int q = p - 1; q >= 0 && keys[q] == k; --q) {
+    const int32_t* b = drow + (size_t)vals[q] * W2;
+    int s = 0;
+    while (s < W2 && a[s] == b[s]) ++s;
+    if (s == W2) {
+      keep = 0;
+      break;
+    }
+  }
+  flag[p] = keep;
+}
+
+// the kept outcome c (draw rw[c], in rank order): hash, track count, parent, value and canonical
+// rank (the draw index: parent rank, then draw); then its row
+__global__ void k_psample_meta(int n, int h_up, const uint32_t* rw, const float* value, const uint64_t* hfull,
+                               const int32_t* ntv, uint64_t* hash, int32_t* ntc, int32_t* parc, float* sval,
+                               int32_t* krank) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  const uint32_t w = rw[c];
+  hash[c] = hfull[w];
+  ntc[c] = ntv[w];
+  parc[c] = (int)(w / (uint32_t)h_up);
+  sval[c] = value[w];
+  krank[c] = (int)w;
+}
+__global__ void k_psample_rows(int n, int W2, const uint32_t* rw, const int32_t* drow, int32_t* crow) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)n * W2) return;
+  const int c = (int)(t / W2), s = (int)(t % W2);
+  crow[t] = drow[(size_t)rw[c] * W2 + s];
+}
+
 }  // namespace
+
+int sample_predict(Ctx& c, int k, int NS, int NB, int U, float ps, const float* br, int K, PredictOut& out) {
+  hipStream_t s = c.s;
+  const int T = 256;
+  const int H = c.nhyp, SW = c.stride, hu = c.sample_hup, W2 = NS + NB;
+  const int64_t nd = (int64_t)H * hu;
+  if (nd > (int64_t)INT32_MAX / 2 || (uint64_t)H >= (1ull << 24))
+    throw Error{GLMB_E_CAPACITY, "sampled prediction: more than 2^30 draws or 2^24 hypotheses"};
+  if (nd * std::max(1, W2) > ((int64_t)1 << 31))
+    throw Error{GLMB_E_CAPACITY, "sampled prediction: draw rows above 8 GiB"};
+  const int n = (int)nd;
+  int32_t* drow = need<int32_t>(c.s_prow, std::max<int64_t>(1, nd * W2));
+  float* value = need<float>(c.s_value, n);
+  uint64_t* keys = need<uint64_t>(c.s_keys, n);
+  uint32_t* vals = need<uint32_t>(c.s_vals, n);
+  uint64_t* hfull = need<uint64_t>(c.s_hash, n);
+  int32_t* ntv = need<int32_t>(c.s_nt, n);
+  GLMB_LAUNCH(k_psample_draws, cdiv(nd * kWave, T), T, 0, s, H, NS, NB, SW, U, hu, c.rows.as<int32_t>(),
+              c.logw.as<float>(), ps, br, (uint32_t)k * 16u + 4u, (uint32_t)c.sample_seed,
+              (uint32_t)(c.sample_seed >> 32), drow, value, keys, vals, hfull, ntv);
+  int hb = 0;
+  while ((1 << hb) < H) ++hb;
+  sort_pairs(keys, vals, n, 0, 40 + ((hb + 7) / 8) * 8, c.tk, c.tv, c.tmp, s);
+  int32_t* flag = need<int32_t>(c.s_flag, n + 1);
+  int32_t* pre = need<int32_t>(c.s_pre, n + 1);
+  GLMB_LAUNCH(k_psample_distinct, cdiv(n, T), T, 0, s, n, W2, keys, vals, drow, flag);
+  scan_excl(flag, pre, n, pre + n, c.tmp, s);
+  int32_t nu = 0;
+  GLMB_HIP(hipMemcpyAsync(&nu, pre + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  GLMB_HIP(stream_sync(s));
+  c.sample_unique = nu;
+  uint64_t* rkeys = need<uint64_t>(c.s_rkeys, nu);
+  uint32_t* rvals = need<uint32_t>(c.s_rvals, nu);
+  GLMB_LAUNCH(k_sample_rank_keys, cdiv(n, T), T, 0, s, n, flag, pre, vals, value, rkeys, rvals);
+  sort_pairs(rkeys, rvals, nu, 0, 64, c.tk, c.tv, c.tmp, s);
+  const int nk = std::min(nu, K);
+  out.crow = need<int32_t>(c.rows2, (int64_t)nk * W2 + 1);
+  out.hash = need<uint64_t>(c.rec_keys, nk + 1);
+  out.ntc = need<int32_t>(c.ntrk2, nk + 1);
+  out.parc = need<int32_t>(c.child_par, nk + 1);
+  out.value = need<float>(c.s_selv, nk + 1);
+  out.keyrank = need<int32_t>(c.s_krank, nk + 1);
+  out.nodes = n;
+  GLMB_LAUNCH(k_psample_meta, cdiv(nk, T), T, 0, s, nk, hu, rvals, value, hfull, ntv, out.hash, out.ntc, out.parc,
+              out.value, out.keyrank);
+  if (W2 > 0) GLMB_LAUNCH(k_psample_rows, cdiv((int64_t)nk * W2, T), T, 0, s, nk, W2, rvals, drow, out.crow);
+  return nk;
+}
 
 int sample_children(Ctx& c, int k, int M, int K, float** sel_value, const uint32_t** kept_draw) {
   hipStream_t s = c.s;

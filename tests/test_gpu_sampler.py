@@ -177,3 +177,68 @@ def test_convoy_accuracy(torch_cuda):
     r = convoy.run(5, 25, 100, 1e-5, 0, 0, 548)
     print(r, flush=True)
     assert r["card_rel_err"] < 0.05 and r["matched_err_m"] < 0.25, r
+
+
+def check_sampled_predict(state, p, h_up, seed, k=0):
+    """The sampled prediction on both sides from the same FP32 state: the same merged track
+    sets with the same weights and predicted moments (skipped when the oracle reports a draw
+    within 1e-6 of its probability)."""
+    from paper_2512_06230_amd.glmb import Tracker
+    st = to_f32_state(state)
+    o = Oracle(p)
+    o.import_state(st)
+    o.set_sampling(h_up, seed)
+    o.predict(k)
+    out_o = o.export_state()
+    fragile = o.sample_stats()[2]
+    g = Tracker(p)
+    g.import_state(st)
+    g.set_sampling(h_up, seed)
+    g.predict(k)
+    out_g = g.export_state()
+    g.close()
+    if fragile:
+        return 0
+    ids_o = pt.predict_ids(out_o)
+    ids_g = pt.predict_ids(out_g)
+    matched = pt.compare_sets(ids_o, out_o["hyp_logw"], ids_g, out_g["hyp_logw"])
+    mo = {int(s): (m, P) for s, m, P in zip(out_o["inst_src"], out_o["inst_m"], out_o["inst_P"])}
+    for s, m, P in zip(out_g["inst_src"], out_g["inst_m"], out_g["inst_P"]):
+        mm, PP = mo[int(s)]
+        assert np.all(np.abs(m - mm) <= pt.tol(mm)) and np.all(np.abs(P - PP) <= pt.tol(PP))
+    return matched
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_sampled_prediction_random_states(torch_cuda, seed):
+    rng = np.random.default_rng(1300 + seed)
+    st = sc.random_state(rng, n_lab=3 + seed % 4, n_hyp=2 + 3 * (seed % 3), side=15.0, versions=1 + seed % 2)
+    nb = seed % 3
+    st["birth_lab"] = np.array([[99, b] for b in range(nb)], np.int32).reshape(-1, 2)
+    st["birth_m"] = rng.uniform(0, 15, (nb, 4))
+    st["birth_P"] = np.tile(np.eye(4).reshape(1, 16), (nb, 1))
+    st["birth_r"] = rng.uniform(0.05, 0.6, nb)
+    total = 0
+    for h_up, K, ps in ((1, 64, 0.9), (10, 8, 0.7), (200, 1000, 0.6)):
+        total += check_sampled_predict(st, dict(BASE, h_max=K, p_survive=ps), h_up, 50 + seed)
+    assert total > 0
+
+
+def test_sampled_filter_along_a_scene(torch_cuda):
+    """The whole filter with the paper's generator in both stages on the 5-object scene; at every
+    scan the GPU's prior state is predicted by both sides and compared."""
+    from paper_2512_06230_amd.glmb import Tracker
+    spec = sc.spec_for("c1")
+    scene = sc.make_scene(spec, n_steps=8)
+    p = sc.filter_params(spec, 100, 1e-5)
+    g = Tracker(p)
+    g.import_state(sc.empty_state())
+    g.set_sampling(100, 9)
+    total = 0
+    for k in range(8):
+        total += check_sampled_predict(g.export_state(), p, 100, 9, k)
+        g.predict(k)
+        g.update(k, scene.meas[k])
+        g.truncate(p["h_max"], p["tau"])
+    g.close()
+    assert total > 20
