@@ -176,11 +176,13 @@ struct CellOut {
   float b1, l;
   unsigned opts;
 };
-// The four first options of a cell in (value descending, candidate position) order, clutter
-// (slot -1) first among equals; unused entries hold -inf and slot -2.
-struct Top4 {
-  float v[4];
-  int32_t s[4];
+// The first kTop options of a cell in (value descending, candidate position) order, clutter
+// (slot -1) first among equals; unused entries hold -inf and slot -2.  Candidate position order
+// is label-slot order (the candidate lists are built slot by slot).
+constexpr int kTop = 8;
+struct TopT {
+  float v[kTop];
+  int32_t s[kTop];
 };
 __device__ __forceinline__ CellOut assoc_cell(int i, int M, const int32_t* row, float lgk, const int32_t* coff,
                                               const int32_t* cand, const float* phi, int16_t* best16, float* dev1,
@@ -248,22 +250,71 @@ __device__ __forceinline__ void assoc_finish(int h, float bsum, float lsum, unsi
 }
 
 // Hypothesis 0, one wave per cell: the lanes take the detection's candidates 64 at a time,
-// each keeping its first four options, log-sum-exp and option count, merged across the wave
+// each keeping its first kTop options, log-sum-exp and option count, merged across the wave
 // in a fixed butterfly.  Besides the cell's own results it stores the reference values the
-// other hypotheses start from (b1 - c_i, the option count, the first four options).
+// other hypotheses start from (b1 - c_i, the option count, the first kTop options and the mass
+// of the options after them).
 __device__ __forceinline__ bool top_before(float va, int sa, float vb, int sb) {
   return va > vb || (va == vb && sa < sb);
+}
+// Insert an option into a list ordered by top_before; it arrives after every listed option of
+// equal value (larger slot), so a strict comparison keeps the order.  Static indices only.
+__device__ __forceinline__ void top_insert(TopT& t, float f, int sl) {
+#pragma unroll
+  for (int j = kTop - 1; j > 0; --j) {
+    const bool up = f > t.v[j - 1];
+    const bool here = f > t.v[j];
+    t.s[j] = up ? t.s[j - 1] : (here ? sl : t.s[j]);
+    t.v[j] = up ? t.v[j - 1] : (here ? f : t.v[j]);
+  }
+  if (f > t.v[0]) {
+    t.v[0] = f;
+    t.s[0] = sl;
+  }
+}
+// The first kTop of the union of two ordered lists: the better of a[j] and b[kTop-1-j] (a
+// bitonic sequence holding exactly those entries), then a bitonic sort.  Both partners of a
+// butterfly get the same list.
+__device__ __forceinline__ TopT top_merge(const TopT& a, const TopT& b) {
+  TopT r;
+#pragma unroll
+  for (int j = 0; j < kTop; ++j) {
+    const bool ta = top_before(a.v[j], a.s[j], b.v[kTop - 1 - j], b.s[kTop - 1 - j]);
+    r.v[j] = ta ? a.v[j] : b.v[kTop - 1 - j];
+    r.s[j] = ta ? a.s[j] : b.s[kTop - 1 - j];
+  }
+#pragma unroll
+  for (int d = kTop / 2; d > 0; d >>= 1) {
+#pragma unroll
+    for (int j = 0; j < kTop; ++j) {
+      if (j & d) continue;
+      const bool sw = top_before(r.v[j + d], r.s[j + d], r.v[j], r.s[j]);
+      const float v0 = r.v[j], v1 = r.v[j + d];
+      const int s0 = r.s[j], s1 = r.s[j + d];
+      r.v[j] = sw ? v1 : v0;
+      r.s[j] = sw ? s1 : s0;
+      r.v[j + d] = sw ? v0 : v1;
+      r.s[j + d] = sw ? s0 : s1;
+    }
+  }
+  return r;
+}
+__device__ __forceinline__ bool top_has(const TopT& t, int sl) {
+  bool in = false;
+#pragma unroll
+  for (int j = 0; j < kTop; ++j) in |= t.s[j] == sl;
+  return in;
 }
 __global__ __launch_bounds__(256) void k_assoc_ref(int M, const int32_t* rows, float lgk, const int32_t* coff,
                                                    const int32_t* cand, const float* phi, const uint32_t* cmax,
                                                    int16_t* best16, float* dev1, float* lserel, float* ref_b1,
-                                                   int32_t* ref_opts, Top4* ref_top, float* ref_rest) {
+                                                   int32_t* ref_opts, TopT* ref_top, float* ref_rest) {
   const int i = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kWave);
   if (i >= M) return;
   const int lane = lane_id();
-  Top4 t;
+  TopT t;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < kTop; ++j) {
     t.v[j] = -INFINITY;
     t.s[j] = -2;
   }
@@ -282,16 +333,7 @@ __global__ __launch_bounds__(256) void k_assoc_ref(int M, const int32_t* rows, f
     const float f = phi[(size_t)u * M + i];
     if (!(f > -INFINITY)) continue;
     ++opts;
-    if (f > t.v[3]) {
-      int j = 3;
-      while (j > 0 && f > t.v[j - 1]) {
-        t.v[j] = t.v[j - 1];
-        t.s[j] = t.s[j - 1];
-        --j;
-      }
-      t.v[j] = f;
-      t.s[j] = sl;
-    }
+    top_insert(t, f, sl);
     if (f > mx) {
       sm = sm * __expf(mx - f) + 1.0f;
       mx = f;
@@ -299,46 +341,32 @@ __global__ __launch_bounds__(256) void k_assoc_ref(int M, const int32_t* rows, f
       sm += __expf(f - mx);
     }
   }
+  // not unrolled: the merge network inlined six times takes the compiler minutes
+#pragma unroll 1
   for (int d = kWave / 2; d > 0; d >>= 1) {
-    Top4 o;
+    TopT o;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < kTop; ++j) {
       o.v[j] = __shfl_xor(t.v[j], d, kWave);
       o.s[j] = __shfl_xor(t.s[j], d, kWave);
     }
     const float omx = __shfl_xor(mx, d, kWave), osm = __shfl_xor(sm, d, kWave);
     opts += __shfl_xor(opts, d, kWave);
-    // merge of two ordered lists (the same result on both partners)
-    Top4 r;
-    int a = 0, b = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (top_before(t.v[a], t.s[a], o.v[b], o.s[b])) {
-        r.v[j] = t.v[a];
-        r.s[j] = t.s[a];
-        ++a;
-      } else {
-        r.v[j] = o.v[b];
-        r.s[j] = o.s[b];
-        ++b;
-      }
-    }
-    t = r;
+    t = top_merge(t, o);
     const float m = fmaxf(mx, omx);
     sm = m > -INFINITY ? sm * __expf(mx - m) + osm * __expf(omx - m) : 0.0f;
     mx = m;
   }
-  // the same log-sum-exp without the best option, for hypotheses that lose it
-  const int k1 = t.s[0];
+  // the mass of the options after the listed ones (clutter among them when it is not listed)
   float rx = -INFINITY, rs = 0.0f;
-  if (lane == 0 && k1 != -1) {
+  if (lane == 0 && !top_has(t, -1)) {
     rx = lgk;
     rs = 1.0f;
   }
   for (int e = coff[i] + lane; e < coff[i + 1]; e += kWave) {
     const int sl = cand[e];
     const int u = rows[sl];
-    if (u < 0 || sl == k1) continue;
+    if (u < 0 || top_has(t, sl)) continue;
     const float f = phi[(size_t)u * M + i];
     if (!(f > -INFINITY)) continue;
     if (f > rx) {
@@ -357,7 +385,7 @@ __global__ __launch_bounds__(256) void k_assoc_ref(int M, const int32_t* rows, f
   if (lane == 0) {
     const float c = o2f(cmax[i]);
     const float l = mx + __logf(sm);
-    best16[i] = (int16_t)(k1 + 1);
+    best16[i] = (int16_t)(t.s[0] + 1);
     dev1[i] = t.v[1] > -INFINITY ? t.v[0] - t.v[1] : INFINITY;
     lserel[i] = l - c;
     ref_b1[i] = t.v[0] - c;
@@ -383,68 +411,228 @@ __global__ __launch_bounds__(256) void k_assoc_ref_sum(int M, const float* ref_b
   assoc_finish(0, bsum, lsum, opts, logw, ntrk, gamma, bprime, lzprime, hopts, red);
 }
 
-// Hypotheses 1..H-1, one workgroup each (row in LDS).  A cell's options depend only on the
-// instances of the labels gated with its detection, so a cell whose labels hold the same
-// instances as in hypothesis 0 is a copy of hypothesis 0's cell.  A cell that differs is
-// derived from hypothesis 0's: its options lose the changed labels' old instances and gain
-// their new ones, so with S = sum over options of exp(phi - c_i) (= exp(lserel)),
-//   S_h = S_0 - sum(removed) + sum(added),
-// taken from hypothesis 0's sum without its best option when that one is removed; the best
-// option and the second value follow from hypothesis 0's first four options that remain and
-// the added options.  The cell is recomputed from all its options instead when fewer than two
-// of the four remain (and hypothesis 0 had more), or when the removed options carry more than
-// half of the sum they are taken from (the difference would lose precision).
-__global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t* rows, const float* logw,
-                                               const int32_t* ntrk, float gamma, float lgk,
+// Hypotheses 1..H-1, one wave each (no workgroup barrier: the waves of a workgroup take
+// different hypotheses).  A cell's options depend only on the instances of the labels gated
+// with its detection, so a cell whose labels hold the same instances as in hypothesis 0 is a
+// copy of hypothesis 0's cell.  A cell that differs ("touched": gated with a label whose
+// instance changed) is derived from hypothesis 0's: it loses the changed labels' old options
+// and gains their new ones.  Its best option and second value follow from hypothesis 0's
+// first kTop options that remain and the added options; its option mass is the sum of three
+// positive parts, the remaining listed options, the unlisted mass less the unlisted options
+// removed, and the added options.  It is recomputed from all its options when fewer than two
+// listed options remain (and hypothesis 0 had unlisted ones), or when the removed unlisted
+// options carry more than half of the unlisted mass (the difference would lose precision).
+// The wave finds the changed labels with a ballot over the row, marks their gated detections
+// in an LDS bit set (all lanes on the flattened (label, detection) pairs), compacts the
+// touched cells into a list, derives them one per lane, then copies hypothesis 0's values into
+// the other cells.  More than kAssocNd changed labels: every cell recomputed.
+constexpr int kAssocNd = 64;
+// LDS words of one wave: changed labels (slot, old and new instance, list offset, length
+// prefix), touched bits, touched list (16-bit), gate words of the first nq changed labels
+__host__ __device__ inline int assoc_wave_words(int M, int nq) {
+  const int W = (M + 31) / 32;
+  return 5 * kAssocNd + 1 + W + (M + 1) / 2 + nq * W;
+}
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__global__ __launch_bounds__(256) void k_assoc(int H, int M, int stride, int nq, const int32_t* rows,
+                                               const float* logw, const int32_t* ntrk, float gamma, float lgk,
                                                const int32_t* coff, const int32_t* cand, const float* phi,
                                                const uint32_t* cmax, const int32_t* loff, const int32_t* llen,
                                                const int32_t* lmeas, const uint32_t* lbits, const float* ref_b1,
-                                               const int32_t* ref_opts, const Top4* ref_top,
+                                               const int32_t* ref_opts, const TopT* ref_top,
                                                const float* ref_rest, int16_t* best16, float* dev1, float* lserel,
                                                float* bprime, float* lzprime, int32_t* hopts) {
-  // LDS: row[stride] | changed slots, ascending[stride] | touched-detection bits[(M + 31) / 32]
-  extern __shared__ int32_t row[];
-  __shared__ float red[16];
-  __shared__ int32_t wcnt[8];
-  const int h = blockIdx.x + 1;
+  extern __shared__ int32_t lds[];
+  const int wv = (int)threadIdx.x / kWave, lane = lane_id();
+  const int h = 1 + (int)blockIdx.x * ((int)blockDim.x / kWave) + wv;
+  if (h >= H) return;  // whole waves only
   const int W = (M + 31) / 32;
-  int32_t* dl = row + stride;
-  uint32_t* touched = (uint32_t*)(dl + stride);
-  for (int s = threadIdx.x; s < stride; s += blockDim.x) row[s] = rows[(size_t)h * stride + s];
-  for (int w = threadIdx.x; w < W; w += blockDim.x) touched[w] = 0u;
-  __syncthreads();
-  // changed slots in ascending order (ballot prefix per wave, waves in order)
+  int32_t* ds = lds + (size_t)wv * assoc_wave_words(M, nq);  // changed label slots, ascending
+  int32_t* du0 = ds + kAssocNd;                               // their instances in hypothesis 0
+  int32_t* duh = du0 + kAssocNd;                              // ... and in hypothesis h
+  int32_t* dof = duh + kAssocNd;                              // offsets of their detection lists
+  int32_t* dpf = dof + kAssocNd;                              // prefix of the list lengths
+  uint32_t* touched = (uint32_t*)(dpf + kAssocNd + 1);
+  uint16_t* tl = (uint16_t*)(touched + W);
+  uint32_t* stage = touched + W + (M + 1) / 2;
+  const int32_t* rowh = rows + (size_t)h * stride;
   int nd = 0;
-  const int lane = lane_id(), wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
-  for (int s0 = 0; s0 < stride; s0 += blockDim.x) {
-    const int s = s0 + (int)threadIdx.x;
-    const bool f = s < stride && row[s] != rows[s];
+  for (int s0 = 0; s0 < stride; s0 += kWave) {
+    const int s = s0 + lane;
+    int uh = 0, u0 = 0;
+    if (s < stride) {
+      uh = rowh[s];
+      u0 = rows[s];
+    }
+    const bool f = uh != u0;
     const uint64_t bal = __ballot(f);
-    if (lane == 0) wcnt[wv] = __popcll(bal);
-    __syncthreads();
-    int before = 0, all = 0;
-    for (int j = 0; j < nw; ++j) {
-      before += j < wv ? wcnt[j] : 0;
-      all += wcnt[j];
+    const int pos = nd + __popcll(bal & lanemask_lt());
+    if (f && pos < kAssocNd) {
+      ds[pos] = s;
+      du0[pos] = u0;
+      duh[pos] = uh;
     }
-    if (f) dl[nd + before + __popcll(bal & lanemask_lt())] = s;
-    nd += all;
-    __syncthreads();
+    nd += __popcll(bal);
   }
-  for (int q = threadIdx.x; q < nd; q += blockDim.x) {
-    const int s = dl[q];
-    const int b = loff[s], e = b + llen[s];
-    for (int r = b; r < e; ++r) {
-      const int i = lmeas[r];
-      atomicOr(&touched[i >> 5], 1u << (i & 31));
-    }
-  }
-  __syncthreads();
   float bsum = 0.0f, lsum = 0.0f;
   unsigned opts = 0;
-  for (int i = threadIdx.x; i < M; i += blockDim.x) {
-    const size_t cell = (size_t)h * M + i;
-    if (!((touched[i >> 5] >> (i & 31)) & 1u)) {
+  if (nd > kAssocNd) {
+    for (int i = lane; i < M; i += kWave) {
+      const size_t cell = (size_t)h * M + i;
+      const float c = o2f(cmax[i]);
+      const CellOut o = assoc_cell(i, M, rowh, lgk, coff, cand, phi, best16, dev1, cell, c);
+      lserel[cell] = o.l - c;
+      bsum += o.b1 - c;
+      lsum += o.l - c;
+      opts += o.opts;
+    }
+  } else {
+    // lengths of the changed labels' detection lists, their prefix (wave scan) and total
+    int len = 0;
+    if (lane < nd) {
+      const int s = ds[lane];
+      dof[lane] = loff[s];
+      len = llen[s];
+    }
+    int x = len;
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int y = __shfl_up(x, d, kWave);
+      if (lane >= d) x += y;
+    }
+    if (lane < nd) dpf[lane + 1] = x;
+    if (lane == 0) dpf[0] = 0;
+    const int P = nd > 0 ? __shfl(x, nd - 1, kWave) : 0;
+    for (int w = lane; w < W; w += kWave) touched[w] = 0u;
+    const int nst = nd < nq ? nd : nq;
+    for (int e = lane; e < nst * W; e += kWave) {
+      const int q = e / W;
+      stage[e] = lbits[(size_t)ds[q] * W + (e - q * W)];
+    }
+    wave_lds_sync();
+    // touched detections: every (changed label, gated detection) pair, all lanes
+    for (int p = lane; p < P; p += kWave) {
+      int q = 0;
+      while (dpf[q + 1] <= p) ++q;
+      const int i = lmeas[dof[q] + (p - dpf[q])];
+      atomicOr(&touched[i >> 5], 1u << (i & 31));
+    }
+    wave_lds_sync();
+    // touched list, ascending
+    int nt = 0;
+    for (int w0 = 0; w0 < W; w0 += kWave) {
+      const int w = w0 + lane;
+      uint32_t word = w < W ? touched[w] : 0u;
+      const int cnt = __popc(word);
+      int y = cnt;
+      for (int d = 1; d < kWave; d <<= 1) {
+        const int z = __shfl_up(y, d, kWave);
+        if (lane >= d) y += z;
+      }
+      int pos = nt + y - cnt;
+      while (word) {
+        const int b = __ffs(word) - 1;
+        word &= word - 1u;
+        tl[pos++] = (uint16_t)(w * 32 + b);
+      }
+      nt += __shfl(y, kWave - 1, kWave);
+    }
+    wave_lds_sync();
+    // touched cells, one per lane
+    for (int t = lane; t < nt; t += kWave) {
+      const int i = tl[t];
+      const size_t cell = (size_t)h * M + i;
+      const float c = o2f(cmax[i]);
+      const TopT T = ref_top[i];
+      const float restT = ref_rest[i];
+      const uint32_t bit = 1u << (i & 31);
+      float rem = 0.0f, add = 0.0f;          // removed unlisted mass, added mass
+      float a1 = -INFINITY, a2 = -INFINITY;  // best two added options (best: smallest slot among equals)
+      int a1s = INT_MAX, dopt = 0;
+      unsigned gone = 0;  // listed entries whose option is removed
+      for (int q = 0; q < nd; ++q) {
+        const uint32_t g = q < nst ? stage[q * W + (i >> 5)] : lbits[(size_t)ds[q] * W + (i >> 5)];
+        if (!(g & bit)) continue;
+        const int s = ds[q], u0 = du0[q], uh = duh[q];
+        if (u0 >= 0) {
+          const float f0 = phi[(size_t)u0 * M + i];
+          if (f0 > -INFINITY) {
+            bool listed = false;
+#pragma unroll
+            for (int j = 0; j < kTop; ++j)
+              if (T.s[j] == s) {
+                gone |= 1u << j;
+                listed = true;
+              }
+            if (!listed) rem += __expf(f0 - c);
+            --dopt;
+          }
+        }
+        if (uh >= 0) {
+          const float fh = phi[(size_t)uh * M + i];
+          if (fh > -INFINITY) {
+            add += __expf(fh - c);
+            ++dopt;
+            if (fh > a1 || (fh == a1 && s < a1s)) {
+              a2 = a1;
+              a1 = fh;
+              a1s = s;
+            } else if (fh > a2) {
+              a2 = fh;
+            }
+          }
+        }
+      }
+      // hypothesis 0's listed options that remain, in order, and their mass
+      float r1 = -INFINITY, r2 = -INFINITY, top = 0.0f;
+      int r1s = -2, nrem = 0;
+#pragma unroll
+      for (int j = 0; j < kTop; ++j)
+        if (T.s[j] != -2 && !((gone >> j) & 1u)) {
+          if (nrem == 0) {
+            r1 = T.v[j];
+            r1s = T.s[j];
+          } else if (nrem == 1) {
+            r2 = T.v[j];
+          }
+          ++nrem;
+          top += __expf(T.v[j] - c);
+        }
+      const bool known = ref_opts[i] + 1 <= kTop || nrem >= 2;
+      if (!known || rem > 0.5f * restT) {
+        const CellOut o = assoc_cell(i, M, rowh, lgk, coff, cand, phi, best16, dev1, cell, c);
+        lserel[cell] = o.l - c;
+        bsum += o.b1 - c;
+        lsum += o.l - c;
+        opts += o.opts;
+      } else {
+        float nb1, nb2;
+        int nk1;
+        if (a1 > r1 || (a1 == r1 && a1s < r1s)) {
+          nb1 = a1;
+          nk1 = a1s;
+          nb2 = fmaxf(r1, a2);
+        } else {
+          nb1 = r1;
+          nk1 = r1s;
+          nb2 = fmaxf(r2, a1);
+        }
+        const float lc = __logf(top + fmaxf(restT - rem, 0.0f) + add);
+        best16[cell] = (int16_t)(nk1 + 1);
+        dev1[cell] = nb2 > -INFINITY ? nb1 - nb2 : INFINITY;
+        lserel[cell] = lc;
+        bsum += nb1 - c;
+        lsum += lc;
+        opts += (unsigned)(ref_opts[i] + dopt);
+      }
+    }
+    // the other cells: hypothesis 0's values
+    for (int i = lane; i < M; i += kWave) {
+      if ((touched[i >> 5] >> (i & 31)) & 1u) continue;
+      const size_t cell = (size_t)h * M + i;
       best16[cell] = best16[i];
       dev1[cell] = dev1[i];
       const float ls = lserel[i];
@@ -452,96 +640,21 @@ __global__ __launch_bounds__(256) void k_assoc(int M, int stride, const int32_t*
       bsum += ref_b1[i];
       lsum += ls;
       opts += (unsigned)ref_opts[i];
-      continue;
-    }
-    const float c = o2f(cmax[i]);
-    const float s_ref = __expf(lserel[i]);
-    const Top4 T = ref_top[i];
-    float rem = 0.0f, add = 0.0f;  // removed mass (hypothesis 0's best apart) and added mass
-    bool rbest = false;            // hypothesis 0's best option is removed
-    float a1 = -INFINITY, a2 = -INFINITY;  // best two added options (best: smallest slot among equals)
-    int a1s = INT_MAX, dopt = 0;
-    unsigned gone = 0;  // entries of T whose option is removed
-    const uint32_t bit = 1u << (i & 31);
-    for (int q = 0; q < nd; ++q) {
-      const int s = dl[q];
-      if (!(lbits[(size_t)s * W + (i >> 5)] & bit)) continue;
-      const int u0 = rows[s], uh = row[s];
-      if (u0 >= 0) {
-        const float f0 = phi[(size_t)u0 * M + i];
-        if (f0 > -INFINITY) {
-          if (s == T.s[0]) rbest = true;
-          else rem += __expf(f0 - c);
-          --dopt;
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (T.s[j] == s) gone |= 1u << j;
-        }
-      }
-      if (uh >= 0) {
-        const float fh = phi[(size_t)uh * M + i];
-        if (fh > -INFINITY) {
-          add += __expf(fh - c);
-          ++dopt;
-          if (fh > a1 || (fh == a1 && s < a1s)) {
-            a2 = a1;
-            a1 = fh;
-            a1s = s;
-          } else if (fh > a2) {
-            a2 = fh;
-          }
-        }
-      }
-    }
-    // hypothesis 0's first options that remain, in order
-    float r1 = -INFINITY, r2 = -INFINITY;
-    int r1s = -2, nrem = 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (T.s[j] != -2 && !((gone >> j) & 1u)) {
-        if (nrem == 0) {
-          r1 = T.v[j];
-          r1s = T.s[j];
-        } else if (nrem == 1) {
-          r2 = T.v[j];
-        }
-        ++nrem;
-      }
-    // Options of hypothesis 0 beyond its first four are worth at most T.v[3] and come after
-    // the first four's equals in candidate order, so the first remaining one is best among
-    // them and, with two remaining, the second value is known too.
-    const bool known = ref_opts[i] + 1 <= 4 || nrem >= 2;
-    // the remaining mass from a sum that excludes hypothesis 0's best when that is removed; a
-    // difference that would cancel most of it is recomputed instead
-    const float base = rbest ? ref_rest[i] : s_ref;
-    if (!known || rem > 0.5f * base) {
-      const CellOut o = assoc_cell(i, M, row, lgk, coff, cand, phi, best16, dev1, cell, c);
-      lserel[cell] = o.l - c;
-      bsum += o.b1 - c;
-      lsum += o.l - c;
-      opts += o.opts;
-    } else {
-      float nb1, nb2;
-      int nk1;
-      if (a1 > r1 || (a1 == r1 && a1s < r1s)) {
-        nb1 = a1;
-        nk1 = a1s;
-        nb2 = fmaxf(r1, a2);
-      } else {
-        nb1 = r1;
-        nk1 = r1s;
-        nb2 = fmaxf(r2, a1);
-      }
-      const float lc = __logf(base - rem + add);
-      best16[cell] = (int16_t)(nk1 + 1);
-      dev1[cell] = nb2 > -INFINITY ? nb1 - nb2 : INFINITY;
-      lserel[cell] = lc;
-      bsum += nb1 - c;
-      lsum += lc;
-      opts += (unsigned)(ref_opts[i] + dopt);
     }
   }
-  assoc_finish(h, bsum, lsum, opts, logw, ntrk, gamma, bprime, lzprime, hopts, red);
+  // per-hypothesis sums, fixed butterfly
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    bsum += __shfl_xor(bsum, d, kWave);
+    lsum += __shfl_xor(lsum, d, kWave);
+    opts += __shfl_xor(opts, d, kWave);
+  }
+  if (lane == 0) {
+    // the miss terms relative to hypothesis 0's track count keep the values small
+    const float base = logw[h] - gamma * (float)(ntrk[h] - ntrk[0]);
+    bprime[h] = base + bsum;
+    lzprime[h] = base + lsum;
+    hopts[h] = (int32_t)opts;
+  }
 }
 
 // ------------------------------------------------------------------ U3
@@ -1438,8 +1551,7 @@ template <class T> T read1(hipStream_t s, const T* p) {
   GLMB_HIP(stream_sync(s));
   return v;
 }
-void check_err(hipStream_t s, const uint32_t* errf) {
-  const uint32_t e = read1(s, errf);
+void check_err_bits(uint32_t e) {
   if (e & ERR_NAN) throw Error{GLMB_E_ARG, "detections contain NaN or infinity"};
   if (e & ERR_BIRTH) throw Error{GLMB_E_CAPACITY, "more than 4096 birth clusters in one scan"};
   if (e & ERR_DEPTH) throw Error{GLMB_E_CAPACITY, "a kept child deviates in more than 48 detections"};
@@ -1504,9 +1616,15 @@ void gate_lists(Ctx& c, int M) {
   scan_excl(llen, loff, NS, tot, c.tmp, s);
   int LW = 1, nl = 0;
   {
+    // one round trip: the list lengths, their total and the error flags (set by k_z_in and
+    // k_label_bits, both queued above)
     std::vector<int32_t> hl(NS + 1);
+    uint32_t e = 0;
     if (NS) GLMB_HIP(hipMemcpyAsync(hl.data(), llen, NS * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    nl = read1(s, tot);
+    GLMB_HIP(hipMemcpyAsync(&nl, tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    GLMB_HIP(hipMemcpyAsync(&e, errf, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    GLMB_HIP(stream_sync(s));
+    if (e & ERR_NAN) throw Error{GLMB_E_ARG, "detections contain NaN or infinity"};
     int mx = 0;
     for (int j = 0; j < NS; ++j) mx = std::max(mx, hl[j]);
     LW = std::max(1, (mx + 31) / 32);
@@ -1528,10 +1646,10 @@ void gate_lists(Ctx& c, int M) {
   GLMB_LAUNCH(k_cand, cdiv((int64_t)M * kWave, T), T, 0, s, lbits, NS, W, M, (const int32_t*)nullptr, ccnt,
               (int32_t*)nullptr);
   scan_excl(ccnt, coff, M, coff + M, c.tmp, s);
-  const int ncand = M > 0 ? read1(s, coff + M) : 0;
+  // the candidate lists hold the same gated (label, detection) pairs as the label lists
+  const int ncand = M > 0 ? nl : 0;
   int32_t* cand = need<int32_t>(c.cand, ncand);
   GLMB_LAUNCH(k_cand, cdiv((int64_t)M * kWave, T), T, 0, s, lbits, NS, W, M, (const int32_t*)coff, ccnt, cand);
-  check_err(s, errf);
   trace(c, "update.lists", ncand, NS);
 }
 
@@ -1553,7 +1671,7 @@ void assoc_norm(Ctx& c, int M) {
   float* lzprime = need<float>(c.lzprime, H);
   float* ref_b1 = need<float>(c.ref_b1, M + 1);
   int32_t* ref_opts = need<int32_t>(c.ref_opts, M + 1);
-  Top4* ref_top = need<Top4>(c.ref_top, M + 1);
+  TopT* ref_top = need<TopT>(c.ref_top, M + 1);
   float* ref_rest = need<float>(c.ref_rest, M + 1);
   int32_t* hopts = need<int32_t>(c.hopts, H + 1);
   GLMB_LAUNCH(k_assoc_ref, cdiv((int64_t)M * kWave, 256), 256, 0, s, M, c.rows.as<int32_t>(), lgk,
@@ -1562,14 +1680,21 @@ void assoc_norm(Ctx& c, int M) {
   GLMB_LAUNCH(k_assoc_ref_sum, 1, 256, 0, s, M, (const float*)ref_b1, (const float*)lserel,
               (const int32_t*)ref_opts, c.logw.as<float>(), c.ntrk.as<int32_t>(), p.det_rate, bprime, lzprime,
               hopts);
-  const size_t lds = (size_t)(2 * SW + (M + 31) / 32) * sizeof(int32_t);
+  // one wave per hypothesis; up to four waves per workgroup, as LDS allows
+  const int W = std::max(1, (M + 31) / 32);
+  const int nq = std::min(16, 512 / W);
+  const size_t wbytes = (size_t)assoc_wave_words(M, nq) * sizeof(int32_t);
+  const int wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (64 * 1024) / wbytes));
+  const size_t lds = wbytes * wpb;
+  if (lds > 160 * 1024) throw Error{GLMB_E_CAPACITY, "association pass needs more than 160 KB of LDS"};
   if (lds > 64 * 1024)
     GLMB_HIP(hipFuncSetAttribute((const void*)k_assoc, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   c.mark(1);  // the events bracket k_assoc alone
-  GLMB_LAUNCH(k_assoc, H - 1, 256, lds, s, M, SW, c.rows.as<int32_t>(), c.logw.as<float>(), c.ntrk.as<int32_t>(),
-              p.det_rate, lgk, c.coff.as<int32_t>(), c.cand.as<int32_t>(), c.phi.as<float>(), c.cmax.as<uint32_t>(),
-              c.loff.as<int32_t>(), c.llen.as<int32_t>(), c.lmeas.as<int32_t>(), c.lbits.as<uint32_t>(), ref_b1,
-              ref_opts, (const Top4*)ref_top, (const float*)ref_rest, best16, dev1, lserel, bprime, lzprime, hopts);
+  GLMB_LAUNCH(k_assoc, cdiv(H - 1, wpb), wpb * kWave, lds, s, H, M, SW, nq, c.rows.as<int32_t>(),
+              c.logw.as<float>(), c.ntrk.as<int32_t>(), p.det_rate, lgk, c.coff.as<int32_t>(), c.cand.as<int32_t>(),
+              c.phi.as<float>(), c.cmax.as<uint32_t>(), c.loff.as<int32_t>(), c.llen.as<int32_t>(),
+              c.lmeas.as<int32_t>(), c.lbits.as<uint32_t>(), ref_b1, ref_opts, (const TopT*)ref_top,
+              (const float*)ref_rest, best16, dev1, lserel, bprime, lzprime, hopts);
   c.mark(2);
   float* dbest = need<float>(c.diag_best, H);
   float* dlogpi = need<float>(c.diag_logpi, H);
@@ -1973,10 +2098,10 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   // ---- statistics and swap in the new state
   trace(c, "update.stats");
   c.mark(5);
-  check_err(s, errf);
-  int32_t hs[19];
+  int32_t hs[19];  // scalars, the error flags (scal[0]) among them: one round trip
   GLMB_HIP(hipMemcpyAsync(hs, scal, 19 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
   GLMB_HIP(stream_sync(s));
+  check_err_bits((uint32_t)hs[0]);
   uint64_t ng, no;
   std::memcpy(&ng, hs + 2, 8);
   std::memcpy(&no, hs + 4, 8);
@@ -2015,7 +2140,6 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   c.stats.retained_mass = std::exp((double)ret);
   c.stats.lost_mass = lost;
   c.stats.pairs_removed = hs[18];
-  GLMB_HIP(stream_sync(s));
   c.stats.host_syncs = (int32_t)(g_stream_syncs - syncs0);
   if (c.ev_ok) {
     const int a[6] = {0, 1, 2, 3, 4, 0}, b[6] = {1, 2, 3, 4, 5, 5};
