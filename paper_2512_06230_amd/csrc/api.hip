@@ -275,7 +275,7 @@ glmb_status glmb_destroy(glmb_ctx* x) {
                           &c.ntrk2, &c.rows2, &c.births, &c.births2, &c.diag_best, &c.diag_logpi, &c.diag_ru, &c.prev_rows,
                           &c.prev_src, &c.child_par, &c.dev_off, &c.dev_i, &c.dev_slot, &c.z, &c.cmax, &c.gbits,
                           &c.phi, &c.lbits, &c.lpre, &c.llen, &c.loff, &c.lmeas, &c.inst_beg, &c.ccnt, &c.coff,
-                          &c.cand, &c.best16, &c.dev1, &c.lserel, &c.bprime, &c.lzprime, &c.cells,
+                          &c.cand, &c.best16, &c.dev1, &c.lserel, &c.tbits, &c.tpre, &c.bprime, &c.lzprime, &c.cells,
                           &c.ccount, &c.coff2, &c.it_h, &c.it_delta, &c.it_group, &c.it_opt, &c.it_off, &c.keys,
                           &c.vals32, &c.scal, &c.sel_logw, &c.hp_map, &c.first, &c.dmask, &c.exc, &c.cmod, &c.recs,
                           &c.rec_keys, &c.rec_vals, &c.ids, &c.row_mark, &c.ru_part, &c.ru, &c.bt, &c.tmp, &c.tk,
@@ -283,7 +283,7 @@ glmb_status glmb_destroy(glmb_ctx* x) {
                           &c.sb.nd_value, &c.sb.cnt, &c.sb.pre, &c.sb.pre64, &c.sb.flags, &c.sb.map, &c.sb.tmp,
                           &c.sb.tk, &c.sb.tv, &c.sb.keys, &c.sb.vals, &c.sb.sel_node, &c.sb.sel_val, &c.sb.sel_rank, &c.sb.hist,
                           &c.sb.scal, &c.sb.dp, &c.sb.dpc, &c.sb.dpa, &c.sb.cand, &c.prop_w, &c.pcnt, &c.poff, &c.ppre, &c.pu, &c.pi, &c.plogit, &c.slot_r,
-                          &c.slot_part, &c.slot_age, &c.pm_part, &c.pe_part, &c.lz_t, &c.mlp_part, &c.est_buf, &c.ref_b1, &c.ref_opts, &c.ref_top, &c.ref_rest, &c.hopts, &c.rec_lead,
+                          &c.slot_part, &c.slot_age, &c.pm_part, &c.pe_part, &c.lz_t, &c.mlp_part, &c.est_buf, &c.ref_b1, &c.ref_opts, &c.ref_top, &c.ref_rest, &c.ref_tot, &c.hopts, &c.rec_lead,
                           &c.s_theta, &c.s_value, &c.s_keys, &c.s_vals, &c.s_flag, &c.s_pre, &c.s_rkeys, &c.s_rvals,
                           &c.s_selv, &c.j_corr, &c.j_val, &c.j_keys, &c.child_perm, &c.j_lw, &c.j_tmp, &c.rows3,
                           &c.rmass, &c.lz_r, &c.s_prow, &c.s_hash, &c.s_nt, &c.s_krank, &c.s_br};
@@ -558,7 +558,15 @@ glmb_status glmb_update_theta(glmb_ctx* x, int32_t n_hyp, int32_t M, int32_t* th
     const int UP = c.stats.n_inst_in;
     std::vector<int32_t> prows((size_t)H * SW), psrc(std::max(1, UP)), par(n), doff(n + 1);
     std::vector<DInst> pinst(std::max(1, UP));
-    if (H * M) GLMB_HIP(hipMemcpyAsync(best.data(), c.best16.p, best.size() * 2, hipMemcpyDeviceToHost, s));
+    // association cells: hypothesis 0 dense, the other hypotheses' touched cells (see CellView)
+    const int WM = (M + 31) / 32;
+    std::vector<uint32_t> tb((size_t)H * WM);
+    std::vector<uint16_t> tp((size_t)H * WM);
+    if (H * M) {
+      GLMB_HIP(hipMemcpyAsync(best.data(), c.best16.p, best.size() * 2, hipMemcpyDeviceToHost, s));
+      GLMB_HIP(hipMemcpyAsync(tb.data(), c.tbits.p, tb.size() * 4, hipMemcpyDeviceToHost, s));
+      GLMB_HIP(hipMemcpyAsync(tp.data(), c.tpre.p, tp.size() * 2, hipMemcpyDeviceToHost, s));
+    }
     if (H * SW) GLMB_HIP(hipMemcpyAsync(prows.data(), c.rows2.p, prows.size() * 4, hipMemcpyDeviceToHost, s));
     if (UP) GLMB_HIP(hipMemcpyAsync(pinst.data(), c.inst2.p, (size_t)UP * sizeof(DInst), hipMemcpyDeviceToHost, s));
     GLMB_HIP(hipMemcpyAsync(par.data(), c.hparent.p, n * 4, hipMemcpyDeviceToHost, s));
@@ -583,7 +591,15 @@ glmb_status glmb_update_theta(glmb_ctx* x, int32_t n_hyp, int32_t M, int32_t* th
     for (int h = 0; h < n; ++h) {
       const int ph = par[h];
       std::vector<int32_t> sl(M);
-      for (int i = 0; i < M; ++i) sl[i] = (int)best[(size_t)ph * M + i] - 1;
+      for (int i = 0; i < M; ++i) {
+        size_t at = (size_t)i;
+        if (ph > 0) {
+          const size_t wi = (size_t)ph * WM + (i >> 5);
+          const uint32_t bit = 1u << (i & 31);
+          if (tb[wi] & bit) at = (size_t)ph * M + tp[wi] + __builtin_popcount(tb[wi] & (bit - 1u));
+        }
+        sl[i] = (int)best[at] - 1;
+      }
       const int o = (int)perm[h];
       for (int q = doff[o]; q < doff[o + 1]; ++q) sl[di[q]] = dn[q];
       for (int i = 0; i < M; ++i)

@@ -104,6 +104,28 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
   return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
+// ------------------------------------------------------------------ association cells
+// The per-(hypothesis, detection) results of the association pass: best option (slot + 1),
+// first deviation and log option mass relative to c_i.  Hypothesis 0's cells are dense at
+// [0, M); hypothesis h >= 1 stores only its cells that differ from hypothesis 0's
+// ("touched"), in ascending detection order at [h * M, h * M + n_h), with one bit per
+// detection in tbits (H x W words) and the touched count before each word in tpre.
+struct CellView {
+  const int16_t* best16;
+  const float* dev1;
+  const float* lserel;
+  const uint32_t* tbits;
+  const uint16_t* tpre;
+  int M, W;
+  __device__ __forceinline__ size_t at(int h, int i) const {
+    if (h == 0) return (size_t)i;
+    const size_t wi = (size_t)h * W + (i >> 5);
+    const uint32_t word = tbits[wi], bit = 1u << (i & 31);
+    if (!(word & bit)) return (size_t)i;
+    return (size_t)h * M + tpre[wi] + __popc(word & (bit - 1u));
+  }
+};
+
 // ------------------------------------------------------------------ primitives (primitives.hip)
 // Exclusive scan of n int32 values (in may equal out); total written to *total (device).
 void scan_excl(const int32_t* in, int32_t* out, int n, int32_t* total, DevBuf& tmp, hipStream_t s);
@@ -116,8 +138,8 @@ void sort_pairs(uint64_t* keys, uint32_t* vals, int n, int bit0, int bit1, DevBu
 void kth_bound(const float* v, int n, int K, float* out, DevBuf& tmp, hipStream_t s);
 // Same, for values given as (value, multiplicity) pairs.
 void kth_bound_mult(const float* v, const int32_t* mult, int n, int K, float* out, DevBuf& tmp, hipStream_t s);
-// Same, over the H * (M + 1) values B[h] - dev1[h * M + i] (i < M) and B[h].
-void kth_bound_cells(const float* B, const float* dev1, int H, int M, int K, float* out, DevBuf& tmp,
+// Same, over the H * (M + 1) values B[h] - dev1 of cell (h, i) (i < M) and B[h].
+void kth_bound_cells(const float* B, const CellView& cv, int H, int M, int K, float* out, DevBuf& tmp,
                      hipStream_t s);
 
 // ------------------------------------------------------------------ selection engine (select.hip)
@@ -158,10 +180,10 @@ struct SelectBufs {
 glmb_status select_topk(const SelectIn& in, int cap_nodes, SelectBufs& b, Selected& out, hipStream_t s,
                         std::string& err, bool trace = false);
 // Counting lower bound on the K-th best child (select.hip): the first pass counts each parent's
-// first deviations dev1[h * M + i] and returns a device scalar holding the bound (t0 when no
+// first deviations (dev1 of its cells) and returns a device scalar holding the bound (t0 when no
 // count reaches K); dp_bound_items raises it with the items of the children above it;
 // dp_bound_refined reads whether it rose above t0 (synchronises).
-const float* dp_bound_rows(const float* base, int P, const float* dev1, int M, int K, const float* t0,
+const float* dp_bound_rows(const float* base, int P, const CellView& cv, int M, int K, const float* t0,
                            SelectBufs& b, hipStream_t s);
 void dp_bound_items(const SelectIn& in, SelectBufs& b, hipStream_t s);
 bool dp_bound_refined(SelectBufs& b, hipStream_t s);

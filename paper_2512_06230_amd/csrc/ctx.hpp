@@ -62,10 +62,10 @@ struct Ctx {
   glmb_step_stats stats{};
 
   // ---- update work buffers ----
-  DevBuf z, cmax, gbits, phi, lbits, lpre, llen, loff, lmeas, inst_beg, ccnt, coff, cand, best16, dev1, lserel,
+  DevBuf z, cmax, gbits, phi, lbits, lpre, llen, loff, lmeas, inst_beg, ccnt, coff, cand, best16, dev1, lserel, tbits, tpre,
       bprime, lzprime, cells, ccount, coff2, it_h, it_delta, it_group, it_opt, it_off, keys, vals32, scal,
       sel_logw, hp_map, first, dmask, exc, cmod, recs, rec_keys, rec_vals, ids, row_mark, ru_part, ru, bt,
-      tmp, tk, tv, flags, pre, pmult, pvals, rec_m, ref_b1, ref_opts, ref_top, ref_rest, hopts;
+      tmp, tk, tv, flags, pre, pmult, pvals, rec_m, ref_b1, ref_opts, ref_top, ref_rest, ref_tot, hopts;
   SelectBufs sb;
   bool sel_multi[2] = {false, false};  // per search site (prediction, update): start on the whole GPU
   bool coop_ok = true;  // cooperative launches allowed (they run one at a time on a device)
@@ -178,6 +178,12 @@ __device__ __forceinline__ void cv_predict(const CV& cv, float* m, float* P) {
   P[7] = P22 + cv.cq;
   P[8] = P23;
   P[9] = P33 + cv.cq;
+}
+
+// the association cells of the last association pass over M detections
+inline CellView cells_of(Ctx& c, int M) {
+  return CellView{c.best16.as<int16_t>(), c.dev1.as<float>(), c.lserel.as<float>(), c.tbits.as<uint32_t>(),
+                  c.tpre.as<uint16_t>(), M, (M + 31) / 32};
 }
 
 }  // namespace glmb

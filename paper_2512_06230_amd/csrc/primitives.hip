@@ -130,17 +130,22 @@ void scan_excl64(const int64_t* in, int64_t* out, int n, int64_t* total, DevBuf&
 }
 
 // ============================================================================ radix sort
+// Stable LSD radix sort by 8-bit digits.  Per pass: per-tile digit counts, then a scatter in
+// which every tile places its items at (items of smaller digits) + (items of its digit in
+// earlier tiles) + (rank within the tile).  With few tiles the scatter computes those offsets
+// from the counts itself; otherwise a scan of the counts runs between the two kernels.
 constexpr int kSortT = 256;
-constexpr int kSortR = 8;                 // rounds per tile
-constexpr int kSortTile = kSortT * kSortR;
+constexpr int kSortRBig = 8;    // rounds of kSortT items per tile for large inputs
+constexpr int kSortRSmall = 2;  // ... and for small ones (more tiles in flight)
+constexpr int kSortFuseTiles = 32;
 
-__global__ __launch_bounds__(kSortT) void k_sort_hist(const uint64_t* keys, int n, int shift, int nb,
+__global__ __launch_bounds__(kSortT) void k_sort_hist(const uint64_t* keys, int n, int shift, int nb, int rounds,
                                                       int32_t* hist) {
   __shared__ int32_t h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int base = blockIdx.x * kSortTile;
-  for (int r = 0; r < kSortR; ++r) {
+  const int base = blockIdx.x * kSortT * rounds;
+  for (int r = 0; r < rounds; ++r) {
     const int i = base + r * kSortT + threadIdx.x;
     if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255], 1);
   }
@@ -148,21 +153,38 @@ __global__ __launch_bounds__(kSortT) void k_sort_hist(const uint64_t* keys, int 
   hist[threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];
 }
 
+// hist: the scanned counts, or (fused) the raw counts [digit][tile]
 __global__ __launch_bounds__(kSortT) void k_sort_scatter(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
-                                                         uint32_t* vout, int n, int shift, int nb,
-                                                         const int32_t* hist_scan) {
+                                                         uint32_t* vout, int n, int shift, int nb, int rounds,
+                                                         const int32_t* hist, int fused) {
   __shared__ int32_t base_d[256];
   __shared__ int32_t running[256];
   __shared__ int32_t wcnt[kSortT / kWave][256];
   __shared__ int32_t woff[kSortT / kWave][256];
   __shared__ int32_t rtot[256];
+  __shared__ int32_t sh[32];
   const int t = threadIdx.x, w = t / kWave;
-  base_d[t] = hist_scan[t * nb + blockIdx.x];
+  if (fused) {
+    // this digit's counts in every tile, every load issued before the first add
+    int32_t v[kSortFuseTiles];
+#pragma unroll
+    for (int k = 0; k < kSortFuseTiles; ++k) v[k] = k < nb ? hist[t * nb + k] : 0;
+    int tot = 0, before = 0;
+#pragma unroll
+    for (int k = 0; k < kSortFuseTiles; ++k) {
+      tot += v[k];
+      before += k < (int)blockIdx.x ? v[k] : 0;
+    }
+    int all;
+    base_d[t] = block_excl_scan<int32_t>(tot, sh, &all) + before;
+  } else {
+    base_d[t] = hist[t * nb + blockIdx.x];
+  }
   running[t] = 0;
   for (int j = 0; j < kSortT / kWave; ++j) wcnt[j][t] = 0;
   __syncthreads();
-  const int tile = blockIdx.x * kSortTile;
-  for (int r = 0; r < kSortR; ++r) {
+  const int tile = blockIdx.x * kSortT * rounds;
+  for (int r = 0; r < rounds; ++r) {
     const int i = tile + r * kSortT + t;
     const bool valid = i < n;
     uint64_t k = valid ? kin[i] : 0;
@@ -199,10 +221,20 @@ __global__ __launch_bounds__(kSortT) void k_sort_scatter(const uint64_t* kin, co
   }
 }
 
+__global__ void k_copy_pairs(int n, const uint64_t* ks, const uint32_t* vs, uint64_t* kd, uint32_t* vd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    kd[i] = ks[i];
+    vd[i] = vs[i];
+  }
+}
+
 void sort_pairs(uint64_t* keys, uint32_t* vals, int n, int bit0, int bit1, DevBuf& tk, DevBuf& tv, DevBuf& tmp,
                 hipStream_t s) {
   if (n <= 1 || bit1 <= bit0) return;
-  const int nb = cdiv(n, kSortTile);
+  const int rounds = n <= kSortFuseTiles * kSortT * kSortRSmall ? kSortRSmall : kSortRBig;
+  const int nb = cdiv(n, kSortT * rounds);
+  const bool fused = nb <= kSortFuseTiles;
   uint64_t* k2 = need<uint64_t>(tk, n);
   uint32_t* v2 = need<uint32_t>(tv, n);
   // scan scratch: hist (256*nb) + tile sums
@@ -213,24 +245,23 @@ void sort_pairs(uint64_t* keys, uint32_t* vals, int n, int bit0, int bit1, DevBu
   uint32_t *va = vals, *vb = v2;
   int passes = 0;
   for (int sh = bit0; sh < bit1; sh += 8, ++passes) {
-    GLMB_LAUNCH(k_sort_hist, nb, kSortT, 0, s, ka, n, sh, nb, hist);
-    const int m = 256 * nb;
-    if (m <= kScanSmallT * kScanSmallI) {
-      GLMB_LAUNCH(k_scan_small<int32_t>, 1, kScanSmallT, 0, s, hist, hist, m, (int32_t*)nullptr);
-    } else {
-      const int nt = cdiv(m, kScanTile);
-      GLMB_LAUNCH(k_scan_tiles<int32_t>, nt, kScanT, 0, s, hist, hist, m, sums);
-      GLMB_LAUNCH(k_scan_sums<int32_t>, 1, kScanT, 0, s, sums, nt, (int32_t*)nullptr);
-      GLMB_LAUNCH(k_scan_add<int32_t>, nt, kScanT, 0, s, hist, m, sums);
+    GLMB_LAUNCH(k_sort_hist, nb, kSortT, 0, s, ka, n, sh, nb, rounds, hist);
+    if (!fused) {
+      const int m = 256 * nb;
+      if (m <= kScanSmallT * kScanSmallI) {
+        GLMB_LAUNCH(k_scan_small<int32_t>, 1, kScanSmallT, 0, s, hist, hist, m, (int32_t*)nullptr);
+      } else {
+        const int nt = cdiv(m, kScanTile);
+        GLMB_LAUNCH(k_scan_tiles<int32_t>, nt, kScanT, 0, s, hist, hist, m, sums);
+        GLMB_LAUNCH(k_scan_sums<int32_t>, 1, kScanT, 0, s, sums, nt, (int32_t*)nullptr);
+        GLMB_LAUNCH(k_scan_add<int32_t>, nt, kScanT, 0, s, hist, m, sums);
+      }
     }
-    GLMB_LAUNCH(k_sort_scatter, nb, kSortT, 0, s, ka, va, kb, vb, n, sh, nb, hist);
+    GLMB_LAUNCH(k_sort_scatter, nb, kSortT, 0, s, ka, va, kb, vb, n, sh, nb, rounds, hist, fused ? 1 : 0);
     std::swap(ka, kb);
     std::swap(va, vb);
   }
-  if (passes & 1) {
-    GLMB_HIP(hipMemcpyAsync(keys, ka, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
-    GLMB_HIP(hipMemcpyAsync(vals, va, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
-  }
+  if (passes & 1) GLMB_LAUNCH(k_copy_pairs, cdiv(n, 256), 256, 0, s, n, ka, va, keys, vals);
 }
 
 // ============================================================================ K-th bound
@@ -324,8 +355,8 @@ static void kth_bound_impl(const float* v, const int32_t* mult, int n, int K, fl
   GLMB_LAUNCH(k_bound_pick, 1, 1024, 0, s, hist, 1, prefix, need_k, out);
 }
 
-// the same bound over the values B[h] - dev1[h * M + i] of every cell and B[h] of every row
-__global__ __launch_bounds__(256) void k_bound_hist_cells(int H, int M, const float* B, const float* dev1, int pass,
+// the same bound over the values B[h] - dev1 of every cell (h, i) and B[h] of every row
+__global__ __launch_bounds__(256) void k_bound_hist_cells(int H, int M, const float* B, CellView cv, int pass,
                                                           const uint32_t* prefix, int32_t* hist) {
   __shared__ int32_t h[kBins];
   for (int j = threadIdx.x; j < kBins; j += blockDim.x) h[j] = 0;
@@ -337,13 +368,15 @@ __global__ __launch_bounds__(256) void k_bound_hist_cells(int H, int M, const fl
     return (o >> 20) == pre ? (int)((o >> 8) & (kBins - 1)) : -1;
   };
   // rows in turn, the threads along a row (no division per element); the values crowd into
-  // few bins, so a wave whose lanes all share one bin adds 64 with one atomic
+  // few bins, so a wave whose lanes all share one bin adds 64 with one atomic.  A row counts
+  // every cell with hypothesis 0's first deviation, then exchanges that count for its own on
+  // its touched cells, one (word, bit) of the touched set per thread (the counts are
+  // integers: the exchange is exact).
   for (int r = blockIdx.x; r < H; r += gridDim.x) {
     const float b = B[r];
-    const float* d = dev1 + (size_t)r * M;
     for (int i0 = 0; i0 < M; i0 += blockDim.x) {
       const int i = i0 + threadIdx.x;
-      const int bin = i < M ? bin_of(b - d[i]) : -1;
+      const int bin = i < M ? bin_of(b - cv.dev1[i]) : -1;
       const int b0 = __shfl(bin, 0, kWave);
       if (b0 >= 0 && __ballot(bin == b0) == ~0ull) {
         if (lane_id() == 0) atomicAdd(&h[b0], kWave);
@@ -351,6 +384,18 @@ __global__ __launch_bounds__(256) void k_bound_hist_cells(int H, int M, const fl
         atomicAdd(&h[bin], 1);
       }
     }
+    if (r > 0)
+      for (int x = threadIdx.x; x < 32 * cv.W; x += blockDim.x) {
+        const size_t wi = (size_t)r * cv.W + (x >> 5);
+        const uint32_t word = cv.tbits[wi], bit = 1u << (x & 31);
+        if (!(word & bit)) continue;
+        const size_t e = (size_t)r * M + cv.tpre[wi] + __popc(word & (bit - 1u));
+        const int bn = bin_of(b - cv.dev1[e]), bo = bin_of(b - cv.dev1[x]);
+        if (bn != bo) {
+          if (bn >= 0) atomicAdd(&h[bn], 1);
+          if (bo >= 0) atomicSub(&h[bo], 1);
+        }
+      }
     if (threadIdx.x == 0) {
       const int br = bin_of(b);
       if (br >= 0) atomicAdd(&h[br], 1);
@@ -361,7 +406,7 @@ __global__ __launch_bounds__(256) void k_bound_hist_cells(int H, int M, const fl
     if (h[j]) atomicAdd(&hist[j], h[j]);
 }
 
-void kth_bound_cells(const float* B, const float* dev1, int H, int M, int K, float* out, DevBuf& tmp,
+void kth_bound_cells(const float* B, const CellView& cv, int H, int M, int K, float* out, DevBuf& tmp,
                      hipStream_t s) {
   tmp.reserve((kBins + 8) * sizeof(int32_t));
   int32_t* hist = tmp.as<int32_t>();
@@ -370,9 +415,9 @@ void kth_bound_cells(const float* B, const float* dev1, int H, int M, int K, flo
   const int64_t n = (int64_t)H * (M + 1);
   GLMB_LAUNCH(k_bound_init, 1, 256, 0, s, hist, need_k, (int32_t)K);
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((n + 256 * 8 - 1) / (256 * 8), std::min(H, 1024)));
-  GLMB_LAUNCH(k_bound_hist_cells, grid, 256, 0, s, H, M, B, dev1, 0, prefix, hist);
+  GLMB_LAUNCH(k_bound_hist_cells, grid, 256, 0, s, H, M, B, cv, 0, prefix, hist);
   GLMB_LAUNCH(k_bound_pick, 1, 1024, 0, s, hist, 0, prefix, need_k, out);
-  GLMB_LAUNCH(k_bound_hist_cells, grid, 256, 0, s, H, M, B, dev1, 1, prefix, hist);
+  GLMB_LAUNCH(k_bound_hist_cells, grid, 256, 0, s, H, M, B, cv, 1, prefix, hist);
   GLMB_LAUNCH(k_bound_pick, 1, 1024, 0, s, hist, 1, prefix, need_k, out);
 }
 

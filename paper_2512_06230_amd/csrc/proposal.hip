@@ -322,7 +322,7 @@ __global__ __launch_bounds__(1024) void k_lost_final(int H, int T, const float* 
 // partial association masses over chunks of 256 hypotheses, one thread per (instance, chunk):
 // pm[ch][p] = sum over h in the chunk holding u of pi_h exp(phi_ui - LSE_hi), pe[ch][u] = sum of pi_h
 __global__ void k_pair_mass(int U, int H, int M, int SW, const DInst* inst, const int32_t* rows, const float* logpi,
-                            const float* lserel, const uint32_t* cmax, const float* phi, const int32_t* poff,
+                            CellView cv, const uint32_t* cmax, const float* phi, const int32_t* poff,
                             const int32_t* pi, int npairs, float* pm, float* pe) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   const int ch = blockIdx.y;
@@ -339,7 +339,7 @@ __global__ void k_pair_mass(int U, int H, int M, int SW, const DInst* inst, cons
     e += w;
     for (int p = p0; p < p1; ++p) {
       const int i = pi[p];
-      out[p] += w * __expf(phi[(size_t)u * M + i] - (lserel[(size_t)h * M + i] + o2f(cmax[i])));
+      out[p] += w * __expf(phi[(size_t)u * M + i] - (cv.lserel[cv.at(h, i)] + o2f(cmax[i])));
     }
   }
   pe[(size_t)ch * U + u] = e;
@@ -620,7 +620,7 @@ int proposal_features(Ctx& c, int k, const float* zin, int M, int cap, float* fe
   float* pm = need<float>(c.pm_part, (int64_t)nch * n);
   float* pe = need<float>(c.pe_part, (int64_t)nch * std::max(U, 1));
   hipLaunchKernelGGL(k_pair_mass, dim3(cdiv(U, T), nch), dim3(T), 0, s, U, H, M, SW, (const DInst*)c.inst.p,
-                     c.rows.as<int32_t>(), c.diag_logpi.as<float>(), c.lserel.as<float>(), c.cmax.as<uint32_t>(),
+                     c.rows.as<int32_t>(), c.diag_logpi.as<float>(), cells_of(c, M), c.cmax.as<uint32_t>(),
                      c.phi.as<float>(), c.poff.as<int32_t>(), c.pi.as<int32_t>(), n, pm, pe);
   GLMB_HIP(hipGetLastError());
   GLMB_LAUNCH(k_pair_target, cdiv(n, T), T, 0, s, n, U, nch, c.pu.as<int32_t>(), pm, pe, target, weight);

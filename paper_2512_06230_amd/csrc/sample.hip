@@ -143,30 +143,29 @@ __global__ void k_sample_rank_keys(int n, const int32_t* flag, const int32_t* pr
 
 // kept child c (draw rw[c]): its parent, value and number of deviations from the parent's best map
 __global__ void k_sample_depth(int n, int M, int h_up, const uint32_t* rw, const int16_t* theta, const float* value,
-                               const int16_t* best16, float* sel_value, int32_t* depth, int32_t* ch_h) {
+                               CellView cv, float* sel_value, int32_t* depth, int32_t* ch_h) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   const uint32_t w = rw[c];
   const int h = (int)(w / (uint32_t)h_up);
   const int16_t* t = theta + (size_t)w * M;
-  const int16_t* b = best16 + (size_t)h * M;
   int nd = 0;
-  for (int i = 0; i < M; ++i) nd += (t[i] != (int16_t)(b[i] - 1));
+  for (int i = 0; i < M; ++i) nd += (t[i] != (int16_t)(cv.best16[cv.at(h, i)] - 1));
   sel_value[c] = value[w];
   depth[c] = nd;
   ch_h[c] = h;
 }
 
-__global__ void k_sample_devs(int n, int M, const uint32_t* rw, const int16_t* theta, const int16_t* best16,
+__global__ void k_sample_devs(int n, int M, const uint32_t* rw, const int16_t* theta, CellView cv,
                               const int32_t* ch_h, const int32_t* doff, int32_t* dev_i, int32_t* dev_new,
                               int32_t* dev_old) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   const int16_t* t = theta + (size_t)rw[c] * M;
-  const int16_t* b = best16 + (size_t)ch_h[c] * M;
+  const int h = ch_h[c];
   int q = doff[c];
   for (int i = 0; i < M; ++i) {
-    const int bo = (int)b[i] - 1;
+    const int bo = (int)cv.best16[cv.at(h, i)] - 1;
     if ((int)t[i] == bo) continue;
     dev_i[q] = i;
     dev_new[q] = t[i];
@@ -366,13 +365,13 @@ int sample_children(Ctx& c, int k, int M, int K, float** sel_value, const uint32
 void sample_children_devs(Ctx& c, int M, int nk, const uint32_t* kept_draw, float* sel_value, int32_t* depth,
                           int32_t* ch_h) {
   GLMB_LAUNCH(k_sample_depth, cdiv(nk, 256), 256, 0, c.s, nk, M, c.sample_hup, kept_draw, c.s_theta.as<int16_t>(),
-              c.s_value.as<float>(), c.best16.as<int16_t>(), sel_value, depth, ch_h);
+              c.s_value.as<float>(), cells_of(c, M), sel_value, depth, ch_h);
 }
 
 void sample_children_list(Ctx& c, int M, int nk, const uint32_t* kept_draw, const int32_t* ch_h, const int32_t* doff,
                           int32_t* dev_i, int32_t* dev_new, int32_t* dev_old) {
   GLMB_LAUNCH(k_sample_devs, cdiv(nk, 256), 256, 0, c.s, nk, M, kept_draw, c.s_theta.as<int16_t>(),
-              c.best16.as<int16_t>(), ch_h, doff, dev_i, dev_new, dev_old);
+              cells_of(c, M), ch_h, doff, dev_i, dev_new, dev_old);
 }
 
 }  // namespace glmb

@@ -889,7 +889,7 @@ __global__ __launch_bounds__(kDpThreads) void k_dp_init(int P, const float* base
 // rounded cost with the 0/1 knapsack recursion (two items per step), added into C at the
 // parent's offset (its own rounded distance below vmax).
 constexpr int kDpRowMax = 4096;  // detections of a row looked at (a subset only loosens the bound)
-__global__ __launch_bounds__(kDpThreads) void k_dp_rows(const float* base, const float* dev1, int M, int K,
+__global__ __launch_bounds__(kDpThreads) void k_dp_rows(const float* base, CellView cv, int M, int K,
                                                         const DpState* st, const int32_t* act,
                                                         unsigned long long* C) {
   __shared__ float sv[kDpRowMax];
@@ -909,7 +909,7 @@ __global__ __launch_bounds__(kDpThreads) void k_dp_rows(const float* base, const
     if (!(dd < NB)) continue;
     const int dh = (int)dd;
     __syncthreads();  // the previous parent's arrays are no longer read
-    for (int q = threadIdx.x; q < P2; q += kDpThreads) sv[q] = q < Mr ? dev1[(size_t)h * M + q] : INFINITY;
+    for (int q = threadIdx.x; q < P2; q += kDpThreads) sv[q] = q < Mr ? cv.dev1[cv.at(h, q)] : INFINITY;
     for (int b = threadIdx.x; b < NB; b += kDpThreads) fa[b] = b == 0 ? 1 : 0;
     __syncthreads();
     for (int kk = 2; kk <= P2; kk <<= 1)
@@ -1169,7 +1169,7 @@ static int coop_grid(size_t lds) {
 }
 static void coop_disable() { g_coop_grid = 0; }
 
-const float* dp_bound_rows(const float* base, int P, const float* dev1, int M, int K, const float* t0,
+const float* dp_bound_rows(const float* base, int P, const CellView& cv, int M, int K, const float* t0,
                            SelectBufs& b, hipStream_t s) {
   DpState* st = need<DpState>(b.dp, 1);
   int32_t* act = need<int32_t>(b.dpa, std::max(P, 1));
@@ -1180,7 +1180,7 @@ const float* dp_bound_rows(const float* base, int P, const float* dev1, int M, i
   }
   GLMB_LAUNCH(k_dp_init, 1, kDpThreads, 0, s, P, base, t0, st, act);
   if (K > 0 && P > 0 && M > 0) {
-    GLMB_LAUNCH(k_dp_rows, std::min(P, kDpGrid), kDpThreads, 0, s, base, dev1, M, K, (const DpState*)st,
+    GLMB_LAUNCH(k_dp_rows, std::min(P, kDpGrid), kDpThreads, 0, s, base, cv, M, K, (const DpState*)st,
                 (const int32_t*)act, C);
     GLMB_LAUNCH(k_dp_pick, 1, kDpThreads, 0, s, 1, K, st, C);
   }

@@ -184,6 +184,11 @@ struct TopT {
   float v[kTop];
   int32_t s[kTop];
 };
+// a cell's listed options with their mass exp(v - c_i) (stored once by hypothesis 0's pass)
+struct TopE {
+  TopT t;
+  float e[kTop];
+};
 __device__ __forceinline__ CellOut assoc_cell(int i, int M, const int32_t* row, float lgk, const int32_t* coff,
                                               const int32_t* cand, const float* phi, int16_t* best16, float* dev1,
                                               size_t cell, float c) {
@@ -308,7 +313,7 @@ __device__ __forceinline__ bool top_has(const TopT& t, int sl) {
 __global__ __launch_bounds__(256) void k_assoc_ref(int M, const int32_t* rows, float lgk, const int32_t* coff,
                                                    const int32_t* cand, const float* phi, const uint32_t* cmax,
                                                    int16_t* best16, float* dev1, float* lserel, float* ref_b1,
-                                                   int32_t* ref_opts, TopT* ref_top, float* ref_rest) {
+                                                   int32_t* ref_opts, TopE* ref_top, float* ref_rest) {
   const int i = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kWave);
   if (i >= M) return;
   const int lane = lane_id();
@@ -390,43 +395,72 @@ __global__ __launch_bounds__(256) void k_assoc_ref(int M, const int32_t* rows, f
     lserel[i] = l - c;
     ref_b1[i] = t.v[0] - c;
     ref_opts[i] = (int32_t)opts;
-    ref_top[i] = t;
+    TopE te;
+    te.t = t;
+#pragma unroll
+    for (int j = 0; j < kTop; ++j) te.e[j] = t.v[j] > -INFINITY ? __expf(t.v[j] - c) : 0.0f;
+    ref_top[i] = te;
     ref_rest[i] = rx > -INFINITY ? rs * __expf(rx - c) : 0.0f;
   }
 }
 
-// hypothesis 0's sums over its cells, in a fixed order
+// hypothesis 0's sums over its cells, in a fixed order; the same sums in FP64 (rtot: b1, log
+// mass, options), from which the other hypotheses take their untouched cells' share
 __global__ __launch_bounds__(256) void k_assoc_ref_sum(int M, const float* ref_b1, const float* lserel,
                                                        const int32_t* ref_opts, const float* logw,
                                                        const int32_t* ntrk, float gamma, float* bprime,
-                                                       float* lzprime, int32_t* hopts) {
+                                                       float* lzprime, int32_t* hopts, double* rtot) {
   __shared__ float red[16];
+  __shared__ double dred[3][4];
   float bsum = 0.0f, lsum = 0.0f;
+  double db = 0.0, dl = 0.0, dn = 0.0;
   unsigned opts = 0;
   for (int i = threadIdx.x; i < M; i += blockDim.x) {
     bsum += ref_b1[i];
     lsum += lserel[i];
     opts += (unsigned)ref_opts[i];
+    db += (double)ref_b1[i];
+    dl += (double)lserel[i];
+    dn += (double)ref_opts[i];
   }
-  assoc_finish(0, bsum, lsum, opts, logw, ntrk, gamma, bprime, lzprime, hopts, red);
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    db += __shfl_xor(db, d, kWave);
+    dl += __shfl_xor(dl, d, kWave);
+    dn += __shfl_xor(dn, d, kWave);
+  }
+  if (lane_id() == 0) {
+    dred[0][threadIdx.x / kWave] = db;
+    dred[1][threadIdx.x / kWave] = dl;
+    dred[2][threadIdx.x / kWave] = dn;
+  }
+  assoc_finish(0, bsum, lsum, opts, logw, ntrk, gamma, bprime, lzprime, hopts, red);  // synchronises
+  if (threadIdx.x < 3) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) s += dred[threadIdx.x][w];
+    rtot[threadIdx.x] = s;
+  }
 }
 
 // Hypotheses 1..H-1, one wave each (no workgroup barrier: the waves of a workgroup take
 // different hypotheses).  A cell's options depend only on the instances of the labels gated
-// with its detection, so a cell whose labels hold the same instances as in hypothesis 0 is a
-// copy of hypothesis 0's cell.  A cell that differs ("touched": gated with a label whose
+// with its detection, so a cell whose labels hold the same instances as in hypothesis 0 equals
+// hypothesis 0's cell and is not stored again (the cell layout of CellView).  A cell that differs ("touched": gated with a label whose
 // instance changed) is derived from hypothesis 0's: it loses the changed labels' old options
 // and gains their new ones.  Its best option and second value follow from hypothesis 0's
 // first kTop options that remain and the added options; its option mass is the sum of three
 // positive parts, the remaining listed options, the unlisted mass less the unlisted options
 // removed, and the added options.  It is recomputed from all its options when fewer than two
 // listed options remain (and hypothesis 0 had unlisted ones), or when the removed unlisted
-// options carry more than half of the unlisted mass (the difference would lose precision).
+// options carry more than half of an unlisted mass that exceeds 64 times the cell's other
+// mass (the difference, exact to a few ulps of the unlisted mass, could then lose precision
+// against the cell's total).
 // The wave finds the changed labels with a ballot over the row, marks their gated detections
 // in an LDS bit set (all lanes on the flattened (label, detection) pairs), compacts the
-// touched cells into a list, derives them one per lane, then copies hypothesis 0's values into
-// the other cells.  More than kAssocNd changed labels: every cell recomputed.
+// touched cells into a list, derives them one per lane into the row's sparse entries, and adds
+// hypothesis 0's values of the other cells to the row's sums.  More than kAssocNd changed
+// labels: every cell recomputed and stored.
 constexpr int kAssocNd = 64;
+constexpr int kAssocRowChunks = 8;
 // LDS words of one wave: changed labels (slot, old and new instance, list offset, length
 // prefix), touched bits, touched list (16-bit), gate words of the first nq changed labels
 __host__ __device__ inline int assoc_wave_words(int M, int nq) {
@@ -443,8 +477,9 @@ __global__ __launch_bounds__(256) void k_assoc(int H, int M, int stride, int nq,
                                                const int32_t* coff, const int32_t* cand, const float* phi,
                                                const uint32_t* cmax, const int32_t* loff, const int32_t* llen,
                                                const int32_t* lmeas, const uint32_t* lbits, const float* ref_b1,
-                                               const int32_t* ref_opts, const TopT* ref_top,
+                                               const int32_t* ref_opts, const TopE* ref_top,
                                                const float* ref_rest, int16_t* best16, float* dev1, float* lserel,
+                                               uint32_t* tbits, uint16_t* tpre, const double* rtot,
                                                float* bprime, float* lzprime, int32_t* hopts) {
   extern __shared__ int32_t lds[];
   const int wv = (int)threadIdx.x / kWave, lane = lane_id();
@@ -461,13 +496,7 @@ __global__ __launch_bounds__(256) void k_assoc(int H, int M, int stride, int nq,
   uint32_t* stage = touched + W + (M + 1) / 2;
   const int32_t* rowh = rows + (size_t)h * stride;
   int nd = 0;
-  for (int s0 = 0; s0 < stride; s0 += kWave) {
-    const int s = s0 + lane;
-    int uh = 0, u0 = 0;
-    if (s < stride) {
-      uh = rowh[s];
-      u0 = rows[s];
-    }
+  auto changed = [&](int s, int uh, int u0) {
     const bool f = uh != u0;
     const uint64_t bal = __ballot(f);
     const int pos = nd + __popcll(bal & lanemask_lt());
@@ -477,10 +506,30 @@ __global__ __launch_bounds__(256) void k_assoc(int H, int M, int stride, int nq,
       duh[pos] = uh;
     }
     nd += __popcll(bal);
+  };
+  // the row in chunks of kAssocRowChunks x 64 slots, every load of a chunk issued before the
+  // first comparison (the row comes from HBM: one latency per chunk, not per 64 slots)
+  for (int s0 = 0; s0 < stride; s0 += kAssocRowChunks * kWave) {
+    int uh[kAssocRowChunks], u0[kAssocRowChunks];
+#pragma unroll
+    for (int j = 0; j < kAssocRowChunks; ++j) {
+      const int s = s0 + j * kWave + lane;
+      uh[j] = s < stride ? rowh[s] : 0;
+      u0[j] = s < stride ? rows[s] : 0;
+    }
+#pragma unroll
+    for (int j = 0; j < kAssocRowChunks; ++j) changed(s0 + j * kWave + lane, uh[j], u0[j]);
   }
-  float bsum = 0.0f, lsum = 0.0f;
+  float bsum = 0.0f, lsum = 0.0f;  // over the cells derived or recomputed here
   unsigned opts = 0;
+  double xb = 0.0, xl = 0.0, xo = 0.0;  // hypothesis 0's values of those cells
   if (nd > kAssocNd) {
+    // every cell stored (a dense row)
+    for (int w = lane; w < W; w += kWave) {
+      const int nb = min(32, M - 32 * w);
+      tbits[(size_t)h * W + w] = nb == 32 ? ~0u : ((1u << nb) - 1u);
+      tpre[(size_t)h * W + w] = (uint16_t)(32 * w);
+    }
     for (int i = lane; i < M; i += kWave) {
       const size_t cell = (size_t)h * M + i;
       const float c = o2f(cmax[i]);
@@ -489,6 +538,9 @@ __global__ __launch_bounds__(256) void k_assoc(int H, int M, int stride, int nq,
       bsum += o.b1 - c;
       lsum += o.l - c;
       opts += o.opts;
+      xb += (double)ref_b1[i];
+      xl += (double)lserel[i];
+      xo += (double)ref_opts[i];
     }
   } else {
     // lengths of the changed labels' detection lists, their prefix (wave scan) and total
@@ -514,10 +566,14 @@ __global__ __launch_bounds__(256) void k_assoc(int H, int M, int stride, int nq,
     }
     wave_lds_sync();
     // touched detections: every (changed label, gated detection) pair, all lanes
+    // (the pair's label by a fixed-length binary search over the length prefix, so that the
+    // detection loads of successive pairs do not wait on one another)
     for (int p = lane; p < P; p += kWave) {
-      int q = 0;
-      while (dpf[q + 1] <= p) ++q;
-      const int i = lmeas[dof[q] + (p - dpf[q])];
+      int lo = 0;  // largest q < nd with dpf[q] <= p
+#pragma unroll
+      for (int step = kAssocNd / 2; step > 0; step >>= 1)
+        if (lo + step < nd && dpf[lo + step] <= p) lo += step;
+      const int i = lmeas[dof[lo] + (p - dpf[lo])];
       atomicOr(&touched[i >> 5], 1u << (i & 31));
     }
     wave_lds_sync();
@@ -533,6 +589,10 @@ __global__ __launch_bounds__(256) void k_assoc(int H, int M, int stride, int nq,
         if (lane >= d) y += z;
       }
       int pos = nt + y - cnt;
+      if (w < W) {
+        tbits[(size_t)h * W + w] = word;
+        tpre[(size_t)h * W + w] = (uint16_t)pos;
+      }
       while (word) {
         const int b = __ffs(word) - 1;
         word &= word - 1u;
@@ -544,10 +604,14 @@ __global__ __launch_bounds__(256) void k_assoc(int H, int M, int stride, int nq,
     // touched cells, one per lane
     for (int t = lane; t < nt; t += kWave) {
       const int i = tl[t];
-      const size_t cell = (size_t)h * M + i;
+      const size_t cell = (size_t)h * M + t;  // the t-th touched cell of the row
       const float c = o2f(cmax[i]);
-      const TopT T = ref_top[i];
+      const TopE TE = ref_top[i];
+      const TopT& T = TE.t;
       const float restT = ref_rest[i];
+      xb += (double)ref_b1[i];
+      xl += (double)lserel[i];
+      xo += (double)ref_opts[i];
       const uint32_t bit = 1u << (i & 31);
       float rem = 0.0f, add = 0.0f;          // removed unlisted mass, added mass
       float a1 = -INFINITY, a2 = -INFINITY;  // best two added options (best: smallest slot among equals)
@@ -599,10 +663,12 @@ __global__ __launch_bounds__(256) void k_assoc(int H, int M, int stride, int nq,
             r2 = T.v[j];
           }
           ++nrem;
-          top += __expf(T.v[j] - c);
+          top += TE.e[j];
         }
       const bool known = ref_opts[i] + 1 <= kTop || nrem >= 2;
-      if (!known || rem > 0.5f * restT) {
+      // restT - rem loses at most a few ulps of restT: recomputed only when that could matter
+      // against the cell's mass (rem a large part of a restT that dwarfs the rest)
+      if (!known || (rem > 0.5f * restT && restT > 64.0f * (top + add))) {
         const CellOut o = assoc_cell(i, M, rowh, lgk, coff, cand, phi, best16, dev1, cell, c);
         lserel[cell] = o.l - c;
         bsum += o.b1 - c;
@@ -629,31 +695,23 @@ __global__ __launch_bounds__(256) void k_assoc(int H, int M, int stride, int nq,
         opts += (unsigned)(ref_opts[i] + dopt);
       }
     }
-    // the other cells: hypothesis 0's values
-    for (int i = lane; i < M; i += kWave) {
-      if ((touched[i >> 5] >> (i & 31)) & 1u) continue;
-      const size_t cell = (size_t)h * M + i;
-      best16[cell] = best16[i];
-      dev1[cell] = dev1[i];
-      const float ls = lserel[i];
-      lserel[cell] = ls;
-      bsum += ref_b1[i];
-      lsum += ls;
-      opts += (unsigned)ref_opts[i];
-    }
   }
-  // per-hypothesis sums, fixed butterfly
+  // per-hypothesis sums, fixed butterfly; the other cells are hypothesis 0's (not stored
+  // again): their share is hypothesis 0's total less its values of the cells above, in FP64
   for (int d = kWave / 2; d > 0; d >>= 1) {
     bsum += __shfl_xor(bsum, d, kWave);
     lsum += __shfl_xor(lsum, d, kWave);
     opts += __shfl_xor(opts, d, kWave);
+    xb += __shfl_xor(xb, d, kWave);
+    xl += __shfl_xor(xl, d, kWave);
+    xo += __shfl_xor(xo, d, kWave);
   }
   if (lane == 0) {
     // the miss terms relative to hypothesis 0's track count keep the values small
     const float base = logw[h] - gamma * (float)(ntrk[h] - ntrk[0]);
-    bprime[h] = base + bsum;
-    lzprime[h] = base + lsum;
-    hopts[h] = (int32_t)opts;
+    bprime[h] = base + (float)((double)bsum + (rtot[0] - xb));
+    lzprime[h] = base + (float)((double)lsum + (rtot[1] - xl));
+    hopts[h] = (int32_t)((double)opts + (rtot[2] - xo));
   }
 }
 
@@ -708,7 +766,7 @@ __global__ __launch_bounds__(1024) void k_norm(int H, int M, const float* bprime
 // One wave per parent: its cells (h, i) with B'_h - dev1 >= t0, in ascending i.  dev1 >= 0, so
 // a parent below the bound has none and its row is not read.  Counting pass (roff null):
 // rcount[h]; writing pass: cell indices h * M + i at roff[h].
-__global__ __launch_bounds__(256) void k_row_cells(int H, int M, const float* bprime, const float* dev1,
+__global__ __launch_bounds__(256) void k_row_cells(int H, int M, const float* bprime, CellView cv,
                                                    const float* t0, const int32_t* roff, int32_t* rcount,
                                                    int32_t* cells) {
   const int h = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kWave);
@@ -720,7 +778,7 @@ __global__ __launch_bounds__(256) void k_row_cells(int H, int M, const float* bp
     const int q0 = roff ? roff[h] : 0;
     for (int i0 = 0; i0 < M; i0 += kWave) {
       const int i = i0 + lane;
-      const bool f = i < M && B - dev1[(size_t)h * M + i] >= t;
+      const bool f = i < M && B - cv.dev1[cv.at(h, i)] >= t;
       const uint64_t bal = __ballot(f);
       if (roff && f) cells[q0 + cnt + __popcll(bal & lanemask_lt())] = h * M + i;
       cnt += __popcll(bal);
@@ -939,7 +997,7 @@ __global__ void k_child_depth(int n, const int32_t* sel_node, const int32_t* nd_
 
 __global__ void k_child_devs(int n, int M, const int32_t* sel_node, const int32_t* nd_parent, const int32_t* nd_item,
                              const int32_t* ch_h, const int32_t* doff, const int32_t* it_group, const int32_t* it_opt,
-                             const int16_t* best16, int32_t* dev_i, int32_t* dev_new, int32_t* dev_old) {
+                             CellView cv, int32_t* dev_i, int32_t* dev_new, int32_t* dev_old) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
   int q = doff[c];
@@ -949,7 +1007,7 @@ __global__ void k_child_devs(int n, int M, const int32_t* sel_node, const int32_
     const int i = it_group[it];
     dev_i[q] = i;
     dev_new[q] = it_opt[it];
-    dev_old[q] = (int)best16[(size_t)h * M + i] - 1;
+    dev_old[q] = (int)cv.best16[cv.at(h, i)] - 1;
   }
 }
 
@@ -984,12 +1042,12 @@ __device__ __forceinline__ int lpos(const int32_t* lmeas, int off, int len, int 
 
 // Detection-set masks of every slot of hypothesis h under its best association map.  A mask
 // has LW 32-bit words; bit j stands for the j-th detection gated with the slot's label.
-__device__ void build_masks(int h, int M, int nslot, int LW, const int16_t* best16, const int32_t* loff,
+__device__ void build_masks(int h, int M, int nslot, int LW, const CellView& cv, const int32_t* loff,
                             const int32_t* llen, const int32_t* lmeas, uint32_t* mask) {
   for (int k = threadIdx.x; k < nslot * LW; k += blockDim.x) mask[k] = 0u;
   __syncthreads();
   for (int i = threadIdx.x; i < M; i += blockDim.x) {
-    const int s = (int)best16[(size_t)h * M + i] - 1;
+    const int s = (int)cv.best16[cv.at(h, i)] - 1;
     if (s < 0) continue;
     const int j = lpos(lmeas, loff[s], llen[s], i);
     if (j < llen[s]) atomicOr(&mask[s * LW + (j >> 5)], 1u << (j & 31));
@@ -998,12 +1056,12 @@ __device__ void build_masks(int h, int M, int nslot, int LW, const int16_t* best
 }
 
 __global__ __launch_bounds__(256) void k_default_masks(const int32_t* plist, int M, int nslot, int LW, int stride,
-                                                       const int32_t* rows, const int16_t* best16,
+                                                       const int32_t* rows, CellView cv,
                                                        const int32_t* loff, const int32_t* llen,
                                                        const int32_t* lmeas, const int32_t* first, uint32_t* dmask) {
   extern __shared__ uint32_t mask[];
   const int h = plist[blockIdx.x];
-  build_masks(h, M, nslot, LW, best16, loff, llen, lmeas, mask);
+  build_masks(h, M, nslot, LW, cv, loff, llen, lmeas, mask);
   for (int s = threadIdx.x; s < nslot; s += blockDim.x) {
     const int u = rows[(size_t)h * stride + s];
     if (u >= 0 && first[u] == h)
@@ -1013,14 +1071,14 @@ __global__ __launch_bounds__(256) void k_default_masks(const int32_t* plist, int
 
 // (instance, slot) pairs of retained parents whose detection set differs from the default
 __global__ __launch_bounds__(256) void k_exceptions(const int32_t* plist, int M, int nslot, int LW, int stride,
-                                                    const int32_t* rows, const int16_t* best16, const int32_t* loff,
+                                                    const int32_t* rows, CellView cv, const int32_t* loff,
                                                     const int32_t* llen, const int32_t* lmeas, const uint32_t* dmask,
                                                     int32_t* nexc, int32_t* eu, int32_t* ea, int32_t* eb,
                                                     uint32_t* em, int cap) {
   extern __shared__ uint32_t mask[];
   const int hp = blockIdx.x;
   const int h = plist[hp];
-  build_masks(h, M, nslot, LW, best16, loff, llen, lmeas, mask);
+  build_masks(h, M, nslot, LW, cv, loff, llen, lmeas, mask);
   for (int s = threadIdx.x; s < nslot; s += blockDim.x) {
     const int u = rows[(size_t)h * stride + s];
     if (u < 0) continue;
@@ -1403,7 +1461,7 @@ __global__ void k_ru_lr(int M, const uint32_t* cmax, const unsigned long long* r
 
 // one wave per hypothesis: lzr[h] = lzprime[h] + sum_i (log(e^{l_hi} + R_i) - l_hi), lanes over
 // the detections with removed mass, fixed butterfly
-__global__ __launch_bounds__(256) void k_ru_restore(int H, int M, const float* lzprime, const float* lserel,
+__global__ __launch_bounds__(256) void k_ru_restore(int H, int M, const float* lzprime, CellView cv,
                                                     const float* lr, float* lzr) {
   const int h = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kWave);
   if (h >= H) return;
@@ -1411,7 +1469,7 @@ __global__ __launch_bounds__(256) void k_ru_restore(int H, int M, const float* l
   for (int i = lane_id(); i < M; i += kWave) {
     const float r = lr[i];
     if (r == -INFINITY) continue;
-    const float ls = lserel[(size_t)h * M + i];
+    const float ls = cv.lserel[cv.at(h, i)];
     acc += lse2(ls, r) - ls;
   }
   for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_xor(acc, d, kWave);
@@ -1428,24 +1486,45 @@ __global__ __launch_bounds__(1024) void k_lse_block(int H, const float* v, float
   sm = block_sum_f(sm, red + 16);
   if (threadIdx.x == 0) *out = mx + __logf(sm);
 }
-__global__ __launch_bounds__(256) void k_ru_part(int H, int M, int hchunk, const float* lzprime, const float* lz,
-                                                 const float* lserel, const uint32_t* cmax, float lgk,
+constexpr int kRuChunk = 16;  // hypotheses per partial sum of the births' clutter shares
+__global__ __launch_bounds__(256) void k_ru_part(int H, int M, const float* lzprime, const float* lz,
+                                                 CellView cv, const uint32_t* cmax, float lgk,
                                                  const float* lrm, float* part) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int ch = blockIdx.y;
   if (i >= M) return;
   const float c = o2f(cmax[i]);
   const float L = *lz;
-  float acc = 0.0f;
-  const int h1 = min(H, (ch + 1) * hchunk);
-  if (!lrm || lrm[i] == -INFINITY) {
-    for (int h = ch * hchunk; h < h1; ++h) acc += __expf(lzprime[h] - L + lgk - c - lserel[(size_t)h * M + i]);
-  } else {
-    const float lr = lrm[i];
-    for (int h = ch * hchunk; h < h1; ++h)
-      acc += __expf(lzprime[h] - L + lgk - c - lse2(lserel[(size_t)h * M + i], lr));
+  const bool rest = lrm && lrm[i] != -INFINITY;
+  const float lr = rest ? lrm[i] : 0.0f;
+  // the clutter share exp(log kappa - c_i - log mass) of a cell with log mass ls (relative to
+  // c_i, with the removed mass restored when the proposal removed pairs of this detection)
+  auto share = [&](float ls) { return __expf(lgk - c - (rest ? lse2(ls, lr) : ls)); };
+  // sum over the chunk of pi_h * share(ls_hi): the chunk's weight times hypothesis 0's share,
+  // plus pi_h * (share - hypothesis 0's) over the chunk's touched cells of detection i
+  const float g0 = share(cv.lserel[i]);
+  const uint32_t bit = 1u << (i & 31);
+  float wsum = 0.0f, acc = 0.0f;
+  // the chunk's touched words first (independent loads), then the touched cells
+  uint32_t word[kRuChunk];
+  float pi[kRuChunk];
+#pragma unroll
+  for (int j = 0; j < kRuChunk; ++j) {
+    const int h = ch * kRuChunk + j;
+    const bool in = h < H;
+    pi[j] = in ? __expf(lzprime[h] - L) : 0.0f;
+    word[j] = (in && h > 0) ? cv.tbits[(size_t)h * cv.W + (i >> 5)] : 0u;
   }
-  part[(size_t)ch * M + i] = acc;
+#pragma unroll
+  for (int j = 0; j < kRuChunk; ++j) {
+    wsum += pi[j];
+    if (word[j] & bit) {
+      const int h = ch * kRuChunk + j;
+      const size_t wi = (size_t)h * cv.W + (i >> 5);
+      acc += pi[j] * (share(cv.lserel[(size_t)h * M + cv.tpre[wi] + __popc(word[j] & (bit - 1u))]) - g0);
+    }
+  }
+  part[(size_t)ch * M + i] = wsum * g0 + acc;
 }
 // one wave per detection: the chunks' partial sums, lanes over the chunks, fixed butterfly
 __global__ __launch_bounds__(256) void k_ru_final(int M, int nch, const float* part, float* ru) {
@@ -1667,19 +1746,23 @@ void assoc_norm(Ctx& c, int M) {
   int16_t* best16 = need<int16_t>(c.best16, HM);
   float* dev1 = need<float>(c.dev1, HM);
   float* lserel = need<float>(c.lserel, HM);
+  const int WM = (M + 31) / 32;
+  uint32_t* tbits = need<uint32_t>(c.tbits, (int64_t)H * WM);
+  uint16_t* tpre = need<uint16_t>(c.tpre, (int64_t)H * WM);
   float* bprime = need<float>(c.bprime, H);
   float* lzprime = need<float>(c.lzprime, H);
   float* ref_b1 = need<float>(c.ref_b1, M + 1);
   int32_t* ref_opts = need<int32_t>(c.ref_opts, M + 1);
-  TopT* ref_top = need<TopT>(c.ref_top, M + 1);
+  TopE* ref_top = need<TopE>(c.ref_top, M + 1);
   float* ref_rest = need<float>(c.ref_rest, M + 1);
   int32_t* hopts = need<int32_t>(c.hopts, H + 1);
   GLMB_LAUNCH(k_assoc_ref, cdiv((int64_t)M * kWave, 256), 256, 0, s, M, c.rows.as<int32_t>(), lgk,
               c.coff.as<int32_t>(), c.cand.as<int32_t>(), c.phi.as<float>(), c.cmax.as<uint32_t>(), best16, dev1,
               lserel, ref_b1, ref_opts, ref_top, ref_rest);
+  double* rtot = need<double>(c.ref_tot, 4);
   GLMB_LAUNCH(k_assoc_ref_sum, 1, 256, 0, s, M, (const float*)ref_b1, (const float*)lserel,
               (const int32_t*)ref_opts, c.logw.as<float>(), c.ntrk.as<int32_t>(), p.det_rate, bprime, lzprime,
-              hopts);
+              hopts, rtot);
   // one wave per hypothesis; up to four waves per workgroup, as LDS allows
   const int W = std::max(1, (M + 31) / 32);
   const int nq = std::min(16, 512 / W);
@@ -1693,8 +1776,9 @@ void assoc_norm(Ctx& c, int M) {
   GLMB_LAUNCH(k_assoc, cdiv(H - 1, wpb), wpb * kWave, lds, s, H, M, SW, nq, c.rows.as<int32_t>(),
               c.logw.as<float>(), c.ntrk.as<int32_t>(), p.det_rate, lgk, c.coff.as<int32_t>(), c.cand.as<int32_t>(),
               c.phi.as<float>(), c.cmax.as<uint32_t>(), c.loff.as<int32_t>(), c.llen.as<int32_t>(),
-              c.lmeas.as<int32_t>(), c.lbits.as<uint32_t>(), ref_b1, ref_opts, (const TopT*)ref_top,
-              (const float*)ref_rest, best16, dev1, lserel, bprime, lzprime, hopts);
+              c.lmeas.as<int32_t>(), c.lbits.as<uint32_t>(), ref_b1, ref_opts, (const TopE*)ref_top,
+              (const float*)ref_rest, best16, dev1, lserel, tbits, tpre, (const double*)rtot, bprime, lzprime,
+              hopts);
   c.mark(2);
   float* dbest = need<float>(c.diag_best, H);
   float* dlogpi = need<float>(c.diag_logpi, H);
@@ -1757,9 +1841,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   // ---- U2: per (hypothesis, detection) normalisers
   trace(c, "update.U2");
   assoc_norm(c, M);
-  int16_t* best16 = c.best16.as<int16_t>();
-  float* dev1 = c.dev1.as<float>();
-  float* lserel = c.lserel.as<float>();
+  const CellView cv = cells_of(c, M);
   float* bprime = c.bprime.as<float>();
   float* lzprime = c.lzprime.as<float>();
 
@@ -1783,10 +1865,10 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   } else {
   // ---- U3: lower bound of the cut, deviation items, exact selection
   trace(c, "update.U3");
-  kth_bound_cells(bprime, dev1, H, M, K, t0, c.tmp, s);
+  kth_bound_cells(bprime, cv, H, M, K, t0, c.tmp, s);
   // counting bound, first pass (from the cells' first deviations): the items are generated
   // for the children above it only
-  const float* tcut = dp_bound_rows(bprime, H, dev1, M, K, t0, c.sb, s);
+  const float* tcut = dp_bound_rows(bprime, H, cv, M, K, t0, c.sb, s);
   struct Items {
     int ncell, nitem;
     int32_t *itoff, *itg, *ito;
@@ -1798,12 +1880,12 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     int32_t* rcount = need<int32_t>(c.flags, H + 1);
     int32_t* roff = need<int32_t>(c.pre, H + 1);
     const int row_blocks = cdiv((int64_t)H * kWave, 256);
-    GLMB_LAUNCH(k_row_cells, row_blocks, 256, 0, s, H, M, bprime, dev1, tb, (const int32_t*)nullptr, rcount,
+    GLMB_LAUNCH(k_row_cells, row_blocks, 256, 0, s, H, M, bprime, cv, tb, (const int32_t*)nullptr, rcount,
                 (int32_t*)nullptr);
     scan_excl(rcount, roff, H, tot, c.tmp, s);
     const int ncell = read1(s, tot);
     int32_t* cells = need<int32_t>(c.cells, ncell);
-    GLMB_LAUNCH(k_row_cells, row_blocks, 256, 0, s, H, M, bprime, dev1, tb, (const int32_t*)roff, rcount, cells);
+    GLMB_LAUNCH(k_row_cells, row_blocks, 256, 0, s, H, M, bprime, cv, tb, (const int32_t*)roff, rcount, cells);
     int32_t* icount = need<int32_t>(c.ccount, ncell + 1);
     int32_t* ioff = need<int32_t>(c.coff2, ncell + 1);
     const int item_blocks = cdiv((int64_t)ncell * kWave, 256);
@@ -1915,7 +1997,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     sample_children_list(c, M, nk, kept_draw, chh, doff, devi, devn, devo);
   else
     GLMB_LAUNCH(k_child_devs, cdiv(nk, T), T, 0, s, nk, M, sel.node, sel.nd_parent, sel.nd_item, chh, doff, itg, ito,
-                best16, devi, devn, devo);
+                cv, devi, devn, devo);
   int32_t* plist = need<int32_t>(c.cells, np + 1);
   int32_t* hpm = need<int32_t>(c.hp_map, H + 1);
   GLMB_LAUNCH(k_plist, cdiv(H, T), T, 0, s, H, mark, ppre, plist, hpm);
@@ -1924,7 +2006,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   GLMB_LAUNCH(k_first, cdiv((int64_t)np * SW, T), T, 0, s, np, plist, SW, c.rows.as<int32_t>(), first);
   uint32_t* dmask = need<uint32_t>(c.dmask, (int64_t)(U + 1) * LW);
   const size_t lds = (size_t)NS * LW * sizeof(uint32_t);
-  GLMB_LAUNCH(k_default_masks, np, 256, lds, s, plist, M, NS, LW, SW, c.rows.as<int32_t>(), best16, loff, llen, lmeas,
+  GLMB_LAUNCH(k_default_masks, np, 256, lds, s, plist, M, NS, LW, SW, c.rows.as<int32_t>(), cv, loff, llen, lmeas,
               first, dmask);
   int ecap = std::max(1024, 4 * nk);
   int32_t* nexc = scal + 14;
@@ -1934,7 +2016,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     return std::make_pair(b, m);
   };
   auto eb_ = exc_bufs(ecap);
-  GLMB_LAUNCH(k_exceptions, np, 256, lds, s, plist, M, NS, LW, SW, c.rows.as<int32_t>(), best16, loff, llen, lmeas,
+  GLMB_LAUNCH(k_exceptions, np, 256, lds, s, plist, M, NS, LW, SW, c.rows.as<int32_t>(), cv, loff, llen, lmeas,
               dmask, nexc, eb_.first, eb_.first + ecap, eb_.first + 2 * ecap, eb_.second, ecap);
   // child masks (count) and default records (flags) before the one round trip that reads the
   // exception, child-mask and default counts
@@ -1958,7 +2040,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     ecap = ne;
     eb_ = exc_bufs(ecap);
     GLMB_LAUNCH(k_fill_i32, 1, T, 0, s, nexc, 1, 0);
-    GLMB_LAUNCH(k_exceptions, np, 256, lds, s, plist, M, NS, LW, SW, c.rows.as<int32_t>(), best16, loff, llen,
+    GLMB_LAUNCH(k_exceptions, np, 256, lds, s, plist, M, NS, LW, SW, c.rows.as<int32_t>(), cv, loff, llen,
                 lmeas, dmask, nexc, eb_.first, eb_.first + ecap, eb_.first + 2 * ecap, eb_.second, ecap);
     ne = read1(s, nexc);
   }
@@ -2070,8 +2152,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   c.mark(4);
   float* ru = need<float>(c.diag_ru, M + 1);
   if (M > 0) {
-    const int hchunk = 16;
-    const int nch = cdiv(H, hchunk);
+    const int nch = cdiv(H, kRuChunk);
     float* part = need<float>(c.ru_part, (int64_t)nch * M);
     const float* lzb = lzprime;
     const float* Lb = lz;
@@ -2080,12 +2161,12 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
       float* lzr = need<float>(c.lz_r, H + 1 + M);
       lrm = lzr + H + 1;
       GLMB_LAUNCH(k_ru_lr, cdiv(M, T), T, 0, s, M, cmax, c.rmass.as<unsigned long long>(), lrm);
-      GLMB_LAUNCH(k_ru_restore, cdiv((int64_t)H * kWave, T), T, 0, s, H, M, lzprime, lserel, lrm, lzr);
+      GLMB_LAUNCH(k_ru_restore, cdiv((int64_t)H * kWave, T), T, 0, s, H, M, lzprime, cv, lrm, lzr);
       GLMB_LAUNCH(k_lse_block, 1, 1024, 0, s, H, lzr, lzr + H);
       lzb = lzr;
       Lb = lzr + H;
     }
-    hipLaunchKernelGGL(k_ru_part, dim3(cdiv(M, T), nch), dim3(T), 0, s, H, M, hchunk, lzb, Lb, lserel, cmax, lgk,
+    hipLaunchKernelGGL(k_ru_part, dim3(cdiv(M, T), nch), dim3(T), 0, s, H, M, lzb, Lb, cv, cmax, lgk,
                        lrm, part);
     GLMB_HIP(hipGetLastError());
     GLMB_LAUNCH(k_ru_final, cdiv((int64_t)M * kWave, T), T, 0, s, M, nch, part, ru);
