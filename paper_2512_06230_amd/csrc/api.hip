@@ -65,6 +65,10 @@ void stage_truncate(Ctx& c, int hmax, float tau) {
   const int n = std::min(c.nhyp, hmax);
   int32_t* scal = need<int32_t>(c.scal, 64);
   GLMB_LAUNCH(k_truncate, 1, 1024, 0, c.s, n, tau, c.logw.as<float>(), scal + 15);
+  if (tau <= 0.0f) {  // no weight threshold: the first n are kept, no round trip
+    c.nhyp = n;
+    return;
+  }
   int32_t keep = 0;
   GLMB_HIP(hipMemcpyAsync(&keep, scal + 15, sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
   GLMB_HIP(stream_sync(c.s));

@@ -473,13 +473,10 @@ void stage_predict(Ctx& c, int k) {
   GLMB_LAUNCH(k_final_meta, cdiv(nh, T), T, 0, s, nh, lv, ntc, parc, mrep, fnt, fpar);
   DInst* ninst = (DInst*)need<uint8_t>(c.inst2, (int64_t)(Unew + 1) * sizeof(DInst));
   GLMB_LAUNCH(k_compact_inst, cdiv(U2, T), T, 0, s, U2, uused, upre, spre, c.inst.as<DInst>(), ninst);
-  // rows / counts into the primary buffers
-  int32_t* rows = need<int32_t>(c.rows, (int64_t)nh * NS2 + 1);
-  GLMB_HIP(hipMemcpyAsync(rows, frows, (size_t)nh * NS2 * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-  int32_t* nt = need<int32_t>(c.ntrk, nh + 1);
-  GLMB_HIP(hipMemcpyAsync(nt, fnt, (size_t)nh * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-  float* lw = need<float>(c.logw, nh + 1);
-  GLMB_HIP(hipMemcpyAsync(lw, nlw, (size_t)nh * sizeof(float), hipMemcpyDeviceToDevice, s));
+  // the final rows, counts and weights become the primary buffers (the old ones, scratch)
+  std::swap(c.rows, c.prev_rows);
+  std::swap(c.ntrk, c.hp_map);
+  std::swap(c.logw, c.logw2);
   std::swap(c.inst, c.inst2);
   // host label table
   std::vector<std::pair<int32_t, int32_t>> lab;
@@ -492,7 +489,6 @@ void stage_predict(Ctx& c, int k) {
   c.nhyp = nh;
   c.nbirth = 0;
   c.birth_lab.clear();
-  GLMB_HIP(stream_sync(s));
 }
 
 }  // namespace glmb
