@@ -434,6 +434,18 @@ def main():
         rec = json.load(open(tf))
         if assoc_source_sha(rec) == rec["source_sha256"] and args.n_obj == 500 and args.h_max == 10000:
             traffic = rec["bytes_per_launch"]
+    # measured HBM bytes of the materialisation stage per update (same counters and scaling),
+    # null once update.hip differs from the source the counters were taken with
+    uf = os.path.join(ROOT, "profiles", "u4_n500_h1e4_traffic.json")
+    if os.path.exists(uf) and args.n_obj == 500 and args.h_max == 10000 and args.preset == "c3":
+        import hashlib
+        urec = json.load(open(uf))
+        src = os.path.join(ROOT, urec["source"])
+        same = os.path.exists(src) and hashlib.sha256(open(src).read().encode()).hexdigest() == urec["source_sha256"]
+        mat = roof["materialise"]
+        mat["traffic"] = urec["bytes_per_update"] if same else None
+        mat["traffic_frac"] = (urec["bytes_per_update"] / (mat["measured_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9)
+                               if same and mat["measured_ms"] > 0 else None)
     out = {
         "metric": METRIC,
         "value": args.steps / elapsed,

@@ -42,38 +42,48 @@ __global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
 }
 
 // one wave per (instance, chunk of 64 detections)
+// One wave per (group of kGateIpw instances, 64 detections): per instance the gate test and
+// score of its 64 pairs, one ballot into the gate bitmap; the running maximum of the scores
+// goes to the per-detection reference c_i with one atomic per lane for the whole group.
+constexpr int kGateIpw = 8;
 __global__ __launch_bounds__(256) void k_gate(const DInst* inst, int U, const float2* z, int M, int W, float sig2,
                                               float gate, float lgc, uint32_t* gbits, float* phi, uint32_t* cmax,
                                               unsigned long long* ngated) {
   const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   const int nch = (M + kWave - 1) / kWave;
-  const int u = gw / nch, ch = gw % nch;
+  const int ug = gw / nch, ch = gw % nch;
   const int lane = lane_id();
   const int i = ch * kWave + lane;
-  const bool live = u < U;  // waves past the last instance only join the workgroup barrier
-  bool g = false;
-  float f = -INFINITY;
-  if (live && i < M) {
-    const DInst& x = inst[u];
-    const float s00 = x.P[0] + sig2, s01 = x.P[1], s11 = x.P[4] + sig2;
-    const float det = s00 * s11 - s01 * s01;
-    const float2 zi = z[i];
-    const float n0 = zi.x - x.m[0], n1 = zi.y - x.m[1];
-    const float qd = s11 * n0 * n0 - 2.0f * s01 * n0 * n1 + s00 * n1 * n1;
-    const float d2 = qd / det;
-    g = d2 <= gate;
-    if (g) f = lgc - 0.5f * __logf(det) - 0.5f * d2;
-    phi[(size_t)u * M + i] = f;
-    if (g) atomicMax(&cmax[i], f2o(f));
+  const float2 zi = i < M ? z[i] : make_float2(0.0f, 0.0f);
+  float fmx = -INFINITY;
+  int ng = 0;
+  for (int k = 0; k < kGateIpw; ++k) {
+    const int u = ug * kGateIpw + k;
+    if (u >= U) break;  // the same for the whole wave
+    bool g = false;
+    if (i < M) {
+      const DInst& x = inst[u];
+      const float s00 = x.P[0] + sig2, s01 = x.P[1], s11 = x.P[4] + sig2;
+      const float det = s00 * s11 - s01 * s01;
+      const float n0 = zi.x - x.m[0], n1 = zi.y - x.m[1];
+      const float qd = s11 * n0 * n0 - 2.0f * s01 * n0 * n1 + s00 * n1 * n1;
+      const float d2 = qd / det;
+      g = d2 <= gate;
+      const float f = g ? lgc - 0.5f * __logf(det) - 0.5f * d2 : -INFINITY;
+      phi[(size_t)u * M + i] = f;
+      fmx = fmaxf(fmx, f);
+    }
+    const uint64_t bal = __ballot(g);
+    if (lane == 0) {
+      gbits[(size_t)u * W + 2 * ch] = (uint32_t)bal;
+      if (2 * ch + 1 < W) gbits[(size_t)u * W + 2 * ch + 1] = (uint32_t)(bal >> 32);
+    }
+    ng += __popcll(bal);
   }
-  const uint64_t bal = __ballot(g);
-  if (live && lane == 0) {
-    gbits[(size_t)u * W + 2 * ch] = (uint32_t)bal;
-    if (2 * ch + 1 < W) gbits[(size_t)u * W + 2 * ch + 1] = (uint32_t)(bal >> 32);
-  }
+  if (fmx > -INFINITY) atomicMax(&cmax[i], f2o(fmx));
   // one counter update per workgroup
   __shared__ int32_t wg[4];
-  if (lane == 0) wg[threadIdx.x / kWave] = __popcll(bal);
+  if (lane == 0) wg[threadIdx.x / kWave] = ng;
   __syncthreads();
   if (threadIdx.x == 0) {
     const int n = wg[0] + wg[1] + wg[2] + wg[3];
@@ -1665,7 +1675,7 @@ void gate_scores(Ctx& c, const float* zin, int M) {
   uint32_t* gbits = need<uint32_t>(c.gbits, (int64_t)U * W);
   float* phi = need<float>(c.phi, (int64_t)U * M);
   if (U > 0 && M > 0) {
-    const int64_t waves = (int64_t)U * cdiv(M, kWave);
+    const int64_t waves = (int64_t)cdiv(U, kGateIpw) * cdiv(M, kWave);
     GLMB_LAUNCH(k_gate, cdiv(waves * kWave, T), T, 0, s, (const DInst*)c.inst.p, U, z, M, W, sig2, p.gate_d2, lgc,
                 gbits, phi, cmax, ngated);
   } else if (U > 0) {
