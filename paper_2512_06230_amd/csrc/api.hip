@@ -69,10 +69,7 @@ void stage_truncate(Ctx& c, int hmax, float tau) {
     c.nhyp = n;
     return;
   }
-  int32_t keep = 0;
-  GLMB_HIP(hipMemcpyAsync(&keep, scal + 15, sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
-  GLMB_HIP(stream_sync(c.s));
-  c.nhyp = keep;
+  c.nhyp = (int32_t)read_back(c.sb.hs, c.s, {{scal + 15, 1}})[0];
 }
 
 // ------------------------------------------------------------------ estimate
@@ -292,6 +289,7 @@ glmb_status glmb_destroy(glmb_ctx* x) {
                           &c.s_selv, &c.j_corr, &c.j_val, &c.j_keys, &c.child_perm, &c.j_lw, &c.j_tmp, &c.rows3,
                           &c.rmass, &c.lz_r, &c.s_prow, &c.s_hash, &c.s_nt, &c.s_krank, &c.s_br};
   for (auto* b : bufs) b->release();
+  c.sb.hs.release();
   if (c.age_pin) (void)hipHostFree(c.age_pin);
   if (c.ev_ok)
     for (auto& e : c.ev) (void)hipEventDestroy(e);
@@ -507,12 +505,12 @@ glmb_status glmb_estimate(glmb_ctx* x, int32_t cap, int32_t* n_out, int32_t* lab
     int32_t r[2];
     std::vector<int32_t> hp(NS);
     std::vector<float> hm(4 * (size_t)NS);
-    GLMB_HIP(hipMemcpyAsync(r, scal + 20, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
-    if (NS) {
-      GLMB_HIP(hipMemcpyAsync(hp.data(), present, NS * sizeof(int32_t), hipMemcpyDeviceToHost, c.s));
-      GLMB_HIP(hipMemcpyAsync(hm.data(), means, NS * sizeof(float4), hipMemcpyDeviceToHost, c.s));
+    {
+      const uint32_t* h = glmb::read_back(c.sb.hs, c.s, {{scal + 20, 2}, {present, NS}, {means, 4 * (int64_t)NS}});
+      std::memcpy(r, h, sizeof(r));
+      std::memcpy(hp.data(), h + 2, (size_t)NS * sizeof(int32_t));
+      std::memcpy(hm.data(), h + 2 + NS, (size_t)NS * sizeof(float4));
     }
-    GLMB_HIP(stream_sync(c.s));
     const int n = r[0];
     *n_out = n;
     if (n > cap) {

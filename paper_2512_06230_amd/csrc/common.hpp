@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <string>
 #include <vector>
 
@@ -76,6 +77,45 @@ struct DevBuf {
     bytes = 0;
   }
 };
+
+// Pinned host memory, mapped into the device's address space and coherent, into which one
+// kernel copies the small results (sizes, counts, flags) that a host round trip reads.
+struct HostStage {
+  uint32_t* h = nullptr;  // host address
+  uint32_t* d = nullptr;  // the same memory as the device addresses it
+  size_t words = 0;
+  void reserve(size_t n) {
+    if (n <= words) return;
+    size_t nw = words ? words : 1024;
+    while (nw < n) nw *= 2;
+    release();  // every read waits for its kernel: nothing still writes the old block
+    void* q = nullptr;
+    if (hipHostMalloc(&q, nw * sizeof(uint32_t), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+      throw Error{GLMB_E_NOMEM, "hipHostMalloc of " + std::to_string(nw * 4) + " bytes failed"};
+    void* dq = nullptr;
+    if (hipHostGetDevicePointer(&dq, q, 0) != hipSuccess) {
+      (void)hipHostFree(q);
+      throw Error{GLMB_E_DEVICE, "hipHostGetDevicePointer failed on pinned host memory"};
+    }
+    h = (uint32_t*)q;
+    d = (uint32_t*)dq;
+    words = nw;
+  }
+  void release() {
+    if (h) (void)hipHostFree(h);
+    h = d = nullptr;
+    words = 0;
+  }
+};
+// A piece of device memory read back: `words` 32-bit words from `src` (4-byte aligned).
+struct ReadPiece {
+  const void* src;
+  int64_t words;
+};
+// One host round trip: the pieces are copied, in order and packed, into st by one kernel on s,
+// then the host waits for s.  Returns the host address of the first piece's first word.  At most
+// eight pieces.
+const uint32_t* read_back(HostStage& st, hipStream_t s, std::initializer_list<ReadPiece> pieces);
 
 template <class T> inline T* need(DevBuf& b, int64_t n) {
   b.reserve((size_t)std::max<int64_t>(n, 1) * sizeof(T));
@@ -174,6 +214,7 @@ struct Selected {
 struct SelectBufs {
   DevBuf nd_parent, nd_item, nd_h, nd_value, nd_bloom, cnt, pre, pre64, flags, map, tmp, tk, tv, keys, vals, sel_node,
       sel_val, sel_rank, scal, hist, dp, dpc, dpa, cand;
+  HostStage hs;             // host round trips of the selection and of the stages that own it
   bool hist_ready = false;  // hist holds zeros (the cooperative search leaves it so)
   bool dpc_ready = false;   // dpc holds zeros (the counting bound leaves it so)
 };

@@ -322,10 +322,11 @@ void stage_predict(Ctx& c, int k) {
   const int t_yes = ly >= ln ? 1 : 0;
   const float tb = (float)std::max(ly, ln);
   const float dt_ = (float)std::fabs(ly - ln);
+  static_assert(sizeof(DBirth) % 4 == 0, "whole words");
   std::vector<DBirth> hb(NB);
   if (NB) {
-    GLMB_HIP(hipMemcpyAsync(hb.data(), c.births.p, (size_t)NB * sizeof(DBirth), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(stream_sync(s));
+    const uint32_t* h = read_back(c.sb.hs, s, {{c.births.p, (int64_t)NB * (int64_t)(sizeof(DBirth) / 4)}});
+    std::memcpy(hb.data(), h, (size_t)NB * sizeof(DBirth));
   }
   std::vector<float> bd(NB + 1, 0.0f);
   std::vector<int32_t> by(NB + 1, 0);
@@ -353,10 +354,15 @@ void stage_predict(Ctx& c, int k) {
   int32_t* dby = (int32_t*)(dbd + NB + 1);
   float* dbs = (float*)(dby + NB + 1);
   int32_t* dbg = (int32_t*)(dbs + NB + 1);
-  GLMB_HIP(hipMemcpyAsync(dbd, bd.data(), (NB + 1) * sizeof(float), hipMemcpyHostToDevice, s));
-  GLMB_HIP(hipMemcpyAsync(dby, by.data(), (NB + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
-  GLMB_HIP(hipMemcpyAsync(dbs, bsv.data(), (nbs + 1) * sizeof(float), hipMemcpyHostToDevice, s));
-  GLMB_HIP(hipMemcpyAsync(dbg, bgv.data(), (nbs + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+  {
+    // the four birth tables packed into one upload
+    std::vector<uint32_t> up(4 * (size_t)NB + 4, 0u);
+    std::memcpy(up.data(), bd.data(), (NB + 1) * sizeof(float));
+    std::memcpy(up.data() + NB + 1, by.data(), (NB + 1) * sizeof(int32_t));
+    std::memcpy(up.data() + 2 * (NB + 1), bsv.data(), (nbs + 1) * sizeof(float));
+    std::memcpy(up.data() + 3 * (NB + 1), bgv.data(), (nbs + 1) * sizeof(int32_t));
+    GLMB_HIP(hipMemcpyAsync(dbd, up.data(), up.size() * sizeof(uint32_t), hipMemcpyHostToDevice, s));
+  }
   const int W2 = NS + NB;
   int n = 0, nodes = 0;
   int32_t *crow = nullptr, *ntc = nullptr, *parc = nullptr;
@@ -393,9 +399,7 @@ void stage_predict(Ctx& c, int k) {
                 (const int32_t*)nullptr, icount, (float*)nullptr, (int32_t*)nullptr);
     int32_t* itoff = need<int32_t>(c.it_off, H + 1);
     scan_excl(icount, itoff, H, itoff + H, c.tmp, s);
-    int32_t nitem = 0;
-    GLMB_HIP(hipMemcpyAsync(&nitem, itoff + H, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(stream_sync(s));
+    const int32_t nitem = (int32_t)read_back(c.sb.hs, s, {{itoff + H, 1}})[0];
     float* itd = need<float>(c.it_delta, (int64_t)nitem + 1);
     int32_t* itg = need<int32_t>(c.it_group, (int64_t)nitem + 1);
     GLMB_LAUNCH(k_pitems, H, 256, 0, s, H, nbs, nlt, SW, c.rows.as<int32_t>(), V, dt_, dbs, dbg, t0,
@@ -435,9 +439,7 @@ void stage_predict(Ctx& c, int k) {
   GLMB_LAUNCH(k_merge, cdiv(n, T), T, 0, s, n, leader, selval, keyrank, hk, hv, islead, mval, mrank, mrep);
   int32_t* lpre = need<int32_t>(c.pre, n + 1);
   scan_excl(islead, lpre, n, tot, c.tmp, s);
-  int32_t nh = 0;
-  GLMB_HIP(hipMemcpyAsync(&nh, tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(stream_sync(s));
+  const int32_t nh = (int32_t)read_back(c.sb.hs, s, {{tot, 1}})[0];
   uint64_t* lk = need<uint64_t>(c.rec_keys, nh + 1);
   uint32_t* lv = need<uint32_t>(c.rec_vals, nh + 1);
   int rb = 0;  // ranks are positions among the search's candidates, below its node count
@@ -460,10 +462,11 @@ void stage_predict(Ctx& c, int k) {
   scan_excl(uused, upre, U2, upre + U2, c.tmp, s);
   std::vector<int32_t> hsu(W2 + 1);
   int32_t cnts[2];
-  GLMB_HIP(hipMemcpyAsync(hsu.data(), sused, (size_t)(W2 + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipMemcpyAsync(&cnts[0], spre + W2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipMemcpyAsync(&cnts[1], upre + U2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(stream_sync(s));
+  {
+    const uint32_t* h = read_back(c.sb.hs, s, {{sused, W2}, {spre + W2, 1}, {upre + U2, 1}});
+    std::memcpy(hsu.data(), h, (size_t)W2 * sizeof(int32_t));
+    std::memcpy(cnts, h + W2, sizeof(cnts));
+  }
   const int NS2 = cnts[0], Unew = cnts[1];
   int32_t* frows = need<int32_t>(c.prev_rows, (int64_t)nh * NS2 + 1);
   int32_t* fnt = need<int32_t>(c.hp_map, nh + 1);

@@ -4,6 +4,43 @@
 
 namespace glmb {
 
+// ============================================================================ read back
+constexpr int kReadMax = 8;
+struct ReadList {
+  const uint32_t* src[kReadMax];
+  int32_t n[kReadMax];
+  int32_t off[kReadMax];
+  int32_t cnt;
+};
+
+__global__ __launch_bounds__(256) void k_read_back(ReadList l, uint32_t* dst) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int p = 0; p < l.cnt; ++p) {
+    const uint32_t* src = l.src[p];
+    uint32_t* out = dst + l.off[p];
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < l.n[p]; j += stride) out[j] = src[j];
+  }
+}
+
+const uint32_t* read_back(HostStage& st, hipStream_t s, std::initializer_list<ReadPiece> pieces) {
+  if (pieces.size() > (size_t)kReadMax) throw Error{GLMB_E_STATE, "read_back: more than eight pieces"};
+  ReadList l{};
+  int64_t tot = 0, mx = 0;
+  for (const ReadPiece& p : pieces) {
+    const int64_t w = std::max<int64_t>(p.words, 0);
+    l.src[l.cnt] = (const uint32_t*)p.src;
+    l.n[l.cnt] = (int32_t)w;
+    l.off[l.cnt] = (int32_t)tot;
+    tot += w;
+    mx = std::max(mx, w);
+    ++l.cnt;
+  }
+  st.reserve((size_t)std::max<int64_t>(tot, 1));
+  if (tot > 0) GLMB_LAUNCH(k_read_back, std::min(64, cdiv(mx, 256)), 256, 0, s, l, st.d);
+  GLMB_HIP(stream_sync(s));
+  return st.h;
+}
+
 // ============================================================================ scan
 constexpr int kScanT = 256;
 constexpr int kScanI = 8;

@@ -486,12 +486,6 @@ __global__ void k_adam(int n, float* th, float* m, float* v, const float* g, flo
 
 // ------------------------------------------------------------------ host side
 namespace {
-template <class T> T read_one(hipStream_t s, const T* p) {
-  T v;
-  GLMB_HIP(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(stream_sync(s));
-  return v;
-}
 
 Norm norm_of(const float* nm) {
   Norm n;
@@ -536,7 +530,7 @@ int prepare_pairs(Ctx& c, int k, int M, bool host_count = true) {
   int32_t* ppre = need<int32_t>(c.ppre, (int64_t)U * W);
   GLMB_LAUNCH(k_pair_count, cdiv((int64_t)U * kWave, T), T, 0, s, U, W, c.gbits.as<uint32_t>(), cnt, ppre);
   scan_excl(cnt, off, U, off + U, c.tmp, s);
-  const int n = !host_count ? -1 : U > 0 ? read_one(s, off + U) : 0;
+  const int n = !host_count ? -1 : U > 0 ? (int)read_back(c.sb.hs, s, {{off + U, 1}})[0] : 0;
   const int64_t cap = host_count ? n : (int64_t)U * M;
   int32_t* pu = need<int32_t>(c.pu, cap);
   int32_t* pi = need<int32_t>(c.pi, cap);
@@ -595,8 +589,7 @@ void proposal_lost(Ctx& c, int k, const float* zin, int M, const float* thr_prob
               c.ppre.as<int32_t>(), c.poff.as<int32_t>(), c.plogit.as<float>(), T, thr, H, lzf, dlt);
   GLMB_LAUNCH(k_lost_final, 1, 1024, 0, s, H, T, lzf, dlt, out);
   float h[kMaxThr];
-  GLMB_HIP(hipMemcpyAsync(h, out, T * sizeof(float), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(stream_sync(s));
+  std::memcpy(h, read_back(c.sb.hs, s, {{out, T}}), (size_t)T * sizeof(float));
   for (int j = 0; j < T; ++j) lost[j] = h[j];
   c.last_M = -1;  // the update diagnostics buffers no longer describe an update
 }

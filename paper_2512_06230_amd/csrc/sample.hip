@@ -303,8 +303,7 @@ int sample_predict(Ctx& c, int k, int NS, int NB, int U, float ps, const float* 
   GLMB_LAUNCH(k_psample_distinct, cdiv(n, T), T, 0, s, n, W2, keys, vals, drow, flag);
   scan_excl(flag, pre, n, pre + n, c.tmp, s);
   int32_t nu = 0;
-  GLMB_HIP(hipMemcpyAsync(&nu, pre + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(stream_sync(s));
+  nu = (int32_t)read_back(c.sb.hs, s, {{pre + n, 1}})[0];
   c.sample_unique = nu;
   uint64_t* rkeys = need<uint64_t>(c.s_rkeys, nu);
   uint32_t* rvals = need<uint32_t>(c.s_rvals, nu);
@@ -350,8 +349,7 @@ int sample_children(Ctx& c, int k, int M, int K, float** sel_value, const uint32
   GLMB_LAUNCH(k_sample_distinct, cdiv(n, T), T, 0, s, n, M, keys, vals, theta, flag);
   scan_excl(flag, pre, n, pre + n, c.tmp, s);
   int32_t nu = 0;
-  GLMB_HIP(hipMemcpyAsync(&nu, pre + n, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(stream_sync(s));
+  nu = (int32_t)read_back(c.sb.hs, s, {{pre + n, 1}})[0];
   c.sample_unique = nu;
   uint64_t* rkeys = need<uint64_t>(c.s_rkeys, nu);
   uint32_t* rvals = need<uint32_t>(c.s_rvals, nu);

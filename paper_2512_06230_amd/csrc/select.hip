@@ -1197,10 +1197,7 @@ void dp_bound_items(const SelectIn& in, SelectBufs& b, hipStream_t s) {
 }
 
 bool dp_bound_refined(SelectBufs& b, hipStream_t s) {
-  int32_t refined = 0;
-  GLMB_HIP(hipMemcpyAsync(&refined, &b.dp.as<DpState>()->refined, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(stream_sync(s));
-  return refined != 0;
+  return read_back(b.hs, s, {{&b.dp.as<DpState>()->refined, 1}})[0] != 0;
 }
 
 void dp_bound_trace(SelectBufs& b, hipStream_t s) {
@@ -1243,10 +1240,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
   float* t2 = (float*)(scal + 9);
   GLMB_HIP(hipMemcpyAsync(t, in.t0, sizeof(float), hipMemcpyDeviceToDevice, s));
   int32_t hs[8];
-  auto read = [&](int n) {
-    GLMB_HIP(hipMemcpyAsync(hs, scal, n * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(stream_sync(s));
-  };
+  auto read = [&](int n) { std::memcpy(hs, read_back(b.hs, s, {{scal, n}}), n * sizeof(int32_t)); };
   // Small searches run in one workgroup (no host round trip per level).  A search that
   // outgrows kBlockNodes continues on the whole GPU (multi-kernel levels below); the call
   // site remembers that and starts there next time, until a search is small again.
@@ -1257,8 +1251,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
     GLMB_LAUNCH(k_select_block, 1, kSB, 0, s, in.P, in.base, in.it_off, in.it_delta, in.it_group, in.K, in.t0,
                 std::min(cap, kBlockNodes), A.p, A.i, A.h, A.v, A.b, t, scal + 24,
                 need<int32_t>(b.cand, std::min(cap, kBlockNodes) + 1));
-    GLMB_HIP(hipMemcpyAsync(hs, scal + 24, 5 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(stream_sync(s));
+    std::memcpy(hs, read_back(b.hs, s, {{scal + 24, 5}}), 5 * sizeof(int32_t));
     used = hs[0];
     levels = hs[1];
     fast = hs[2] == 0;
@@ -1306,8 +1299,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
       const hipError_t e = hipLaunchCooperativeKernel((const void*)k_select_coop, dim3(G), dim3(kCB), args,
                                                       kCoopLds, s);
       if (e == hipSuccess) {
-        GLMB_HIP(hipMemcpyAsync(hs, scal + 16, 5 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        GLMB_HIP(stream_sync(s));
+        std::memcpy(hs, read_back(b.hs, s, {{scal + 16, 5}}), 5 * sizeof(int32_t));
         used = hs[0];
         levels = hs[1];
         tr("coop", used, hs[4]);
@@ -1349,8 +1341,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
     kth_bound(A.v, used, in.K, t2, b.tmp, s);
     // t = max(t, t2)
     float th[2];
-    GLMB_HIP(hipMemcpyAsync(th, (float*)(scal + 8), 2 * sizeof(float), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(stream_sync(s));
+    std::memcpy(th, read_back(b.hs, s, {{scal + 8, 2}}), sizeof(th));
     if (!(th[1] > th[0])) return false;
     GLMB_HIP(hipMemcpyAsync(t, t2, sizeof(float), hipMemcpyDeviceToDevice, s));
     int32_t* fl = need<int32_t>(b.flags, used + 1);
@@ -1360,8 +1351,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
     GLMB_LAUNCH(k_compact_nodes, cdiv(used, T), T, 0, s, used, t, pre, A.p, A.i, A.h, A.v, A.b, B.p, B.i, B.h, B.v,
                 B.b);
     GLMB_LAUNCH(k_remap_pos, 1, 64, 0, s, pre, scal, used, level_first, *cursor, level_end, scal + 4);
-    GLMB_HIP(hipMemcpyAsync(hs, scal, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(stream_sync(s));
+    read(8);
     used = hs[0];
     level_first = hs[4];
     *cursor = hs[5];
@@ -1388,8 +1378,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
       GLMB_LAUNCH(k_count, cdiv(nlev, T), T, 0, s, cursor, nlev, A.i, A.h, A.v, in.it_off, in.it_delta, t, cnt);
       scan_excl64(cnt, pre, nlev, tot64, b.tmp, s);
       int64_t total = 0;
-      GLMB_HIP(hipMemcpyAsync(&total, tot64, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-      GLMB_HIP(stream_sync(s));
+      std::memcpy(&total, read_back(b.hs, s, {{tot64, 2}}), sizeof(total));
       if (total == 0) break;
       // Expand at most about as many nodes as the store holds (at least 2K) before the
       // threshold is raised again: a raised threshold prunes the rest of the level.
@@ -1399,8 +1388,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
       int64_t te = total;
       auto cut = [&](int64_t r) {
         GLMB_LAUNCH(k_cut, 1, 64, 0, s, pre, cnt, nlev, r, scal + 1);
-        GLMB_HIP(hipMemcpyAsync(hs, scal, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        GLMB_HIP(stream_sync(s));
+        read(3);
         m = hs[1];
         te = hs[2];
       };

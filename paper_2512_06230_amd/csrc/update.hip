@@ -1634,10 +1634,11 @@ __global__ __launch_bounds__(64) void k_births(int M, const float2* z, const flo
 
 // ------------------------------------------------------------------ orchestration
 namespace {
-template <class T> T read1(hipStream_t s, const T* p) {
+template <class T> T read1(Ctx& c, const T* p) {
+  static_assert(sizeof(T) == 4, "one 32-bit word");
+  const uint32_t* h = read_back(c.sb.hs, c.s, {{p, 1}});
   T v;
-  GLMB_HIP(hipMemcpyAsync(&v, p, sizeof(T), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(stream_sync(s));
+  std::memcpy(&v, h, sizeof(T));
   return v;
 }
 void check_err_bits(uint32_t e) {
@@ -1707,12 +1708,10 @@ void gate_lists(Ctx& c, int M) {
   {
     // one round trip: the list lengths, their total and the error flags (set by k_z_in and
     // k_label_bits, both queued above)
-    std::vector<int32_t> hl(NS + 1);
-    uint32_t e = 0;
-    if (NS) GLMB_HIP(hipMemcpyAsync(hl.data(), llen, NS * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(hipMemcpyAsync(&nl, tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(hipMemcpyAsync(&e, errf, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(stream_sync(s));
+    const uint32_t* hb = read_back(c.sb.hs, s, {{llen, NS}, {tot, 1}, {errf, 1}});
+    const int32_t* hl = (const int32_t*)hb;
+    nl = hl[NS];
+    const uint32_t e = hb[NS + 1];
     if (e & ERR_NAN) throw Error{GLMB_E_ARG, "detections contain NaN or infinity"};
     int mx = 0;
     for (int j = 0; j < NS; ++j) mx = std::max(mx, hl[j]);
@@ -1893,7 +1892,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     GLMB_LAUNCH(k_row_cells, row_blocks, 256, 0, s, H, M, bprime, cv, tb, (const int32_t*)nullptr, rcount,
                 (int32_t*)nullptr);
     scan_excl(rcount, roff, H, tot, c.tmp, s);
-    const int ncell = read1(s, tot);
+    const int ncell = read1(c, tot);
     int32_t* cells = need<int32_t>(c.cells, ncell);
     GLMB_LAUNCH(k_row_cells, row_blocks, 256, 0, s, H, M, bprime, cv, tb, (const int32_t*)roff, rcount, cells);
     int32_t* icount = need<int32_t>(c.ccount, ncell + 1);
@@ -1910,9 +1909,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     GLMB_LAUNCH(k_fill_i32, 1, T, 0, s, maxlen, 2, 0);
     GLMB_LAUNCH(k_item_ranges, cdiv(H + 1, T), T, 0, s, H, ncell, M, cells, ioff, itoff, maxlen, nlist, ilist);
     int32_t hv[2];
-    GLMB_HIP(hipMemcpyAsync(hv, ioff + ncell, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(hipMemcpyAsync(hv + 1, maxlen, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(stream_sync(s));
+    std::memcpy(hv, read_back(c.sb.hs, s, {{ioff + ncell, 1}, {maxlen, 1}}), sizeof(hv));
     const int nitem = hv[0];
     float* itd0 = need<float>(c.it_delta, 2 * (int64_t)nitem);
     int32_t* itg0 = need<int32_t>(c.it_group, 2 * (int64_t)nitem);
@@ -1977,7 +1974,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   }
   float* wout = need<float>(c.logw2, nsel);
   GLMB_LAUNCH(k_prune, 1, 1024, 0, s, nsel, sel.value, p.tau, lz, wout, nkeep, retained);
-  const int nk = read1(s, nkeep);
+  const int nk = read1(c, nkeep);
 
   // ---- U4: children, distinct (instance, detection set), Kalman, rows
   trace(c, "update.U4", nsel, nk);
@@ -1995,10 +1992,8 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   GLMB_LAUNCH(k_mark, cdiv(nk, T), T, 0, s, nk, chh, mark);
   int32_t* ppre = need<int32_t>(c.pre, H + 1);
   scan_excl(mark, ppre, H, tot, c.tmp, s);
-  int32_t cnt2[2];  // deviations of the kept children, retained parents: one round trip
-  GLMB_HIP(hipMemcpyAsync(&cnt2[0], doff + nk, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipMemcpyAsync(&cnt2[1], tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(stream_sync(s));
+  // deviations of the kept children, retained parents: one round trip
+  const int32_t* cnt2 = (const int32_t*)read_back(c.sb.hs, s, {{doff + nk, 1}, {tot, 1}});
   const int ndev = cnt2[0], np = cnt2[1];
   int32_t* devi = need<int32_t>(c.dev_i, ndev);
   int32_t* devn = need<int32_t>(c.dev_slot, 2 * (int64_t)ndev);
@@ -2039,11 +2034,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   int32_t* dpre = need<int32_t>(c.pmult, U + 1);
   GLMB_LAUNCH(k_def_flags, cdiv(U, T), T, 0, s, U, first, dfl);
   scan_excl(dfl, dpre, U, tot, c.tmp, s);
-  int32_t cnt3[3];
-  GLMB_HIP(hipMemcpyAsync(&cnt3[0], nexc, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipMemcpyAsync(&cnt3[1], moff + nk, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(hipMemcpyAsync(&cnt3[2], tot, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(stream_sync(s));
+  const int32_t* cnt3 = (const int32_t*)read_back(c.sb.hs, s, {{nexc, 1}, {moff + nk, 1}, {tot, 1}});
   int ne = cnt3[0];
   const int nm = cnt3[1], nd = cnt3[2];
   if (ne > ecap) {  // grow and redo
@@ -2052,7 +2043,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     GLMB_LAUNCH(k_fill_i32, 1, T, 0, s, nexc, 1, 0);
     GLMB_LAUNCH(k_exceptions, np, 256, lds, s, plist, M, NS, LW, SW, c.rows.as<int32_t>(), cv, loff, llen,
                 lmeas, dmask, nexc, eb_.first, eb_.first + ecap, eb_.first + 2 * ecap, eb_.second, ecap);
-    ne = read1(s, nexc);
+    ne = read1(c, nexc);
   }
   // exceptions sorted by (retained parent, slot)
   int32_t *eu0 = eb_.first, *ea0 = eu0 + ecap, *eb0 = ea0 + ecap, *eu = eb0 + ecap, *ea = eu + ecap, *eb = ea + ecap;
@@ -2098,15 +2089,14 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   int nnew = 0;
   {
     int32_t hv2[13];
-    GLMB_HIP(hipMemcpyAsync(hv2, tot, 13 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    GLMB_HIP(stream_sync(s));
+    std::memcpy(hv2, read_back(c.sb.hs, s, {{tot, 13}}), sizeof(hv2));
     nnew = hv2[0];
     if (hv2[12] > 0) {  // fingerprint collisions: ids by full comparison within each run
       trace(c, "update.fingerprint_collisions", hv2[12]);
       rlead = need<int32_t>(c.rec_lead, R + 1);
       GLMB_LAUNCH(k_rec_resolve, cdiv(R, T), T, 0, s, R, LW, rk, rv, rec_u, rec_m, rfl, rlead);
       scan_excl(rfl, rpre, R, tot, c.tmp, s);
-      nnew = read1(s, tot);
+      nnew = read1(c, tot);
     }
     c.stats.rec_collisions = hv2[12];
   }
@@ -2144,7 +2134,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     sort_pairs(jk, perm, nk, 0, 64, c.tk, c.tv, c.tmp, s);
     float* jl = need<float>(c.j_lw, nk + 1);
     GLMB_LAUNCH(k_joint_tau, 1, 1024, 0, s, nk, perm, jv, p.tau, jl, nkeep);
-    nkept = read1(s, nkeep);
+    nkept = read1(c, nkeep);
     int32_t* rows3 = need<int32_t>(c.rows3, (int64_t)nkept * SW + 1);
     GLMB_LAUNCH(k_gather_rows, cdiv((int64_t)nkept * SW, T), T, 0, s, nkept, SW, perm, nrows, rows3);
     int32_t* jt = need<int32_t>(c.j_tmp, 2 * (int64_t)nkept + 2);
@@ -2190,8 +2180,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   trace(c, "update.stats");
   c.mark(5);
   int32_t hs[19];  // scalars, the error flags (scal[0]) among them: one round trip
-  GLMB_HIP(hipMemcpyAsync(hs, scal, 19 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  GLMB_HIP(stream_sync(s));
+  std::memcpy(hs, read_back(c.sb.hs, s, {{scal, 19}}), sizeof(hs));
   check_err_bits((uint32_t)hs[0]);
   uint64_t ng, no;
   std::memcpy(&ng, hs + 2, 8);
