@@ -284,7 +284,7 @@ glmb_status glmb_destroy(glmb_ctx* x) {
                           &c.sb.nd_value, &c.sb.cnt, &c.sb.pre, &c.sb.pre64, &c.sb.flags, &c.sb.map, &c.sb.tmp,
                           &c.sb.tk, &c.sb.tv, &c.sb.keys, &c.sb.vals, &c.sb.sel_node, &c.sb.sel_val, &c.sb.sel_rank, &c.sb.hist,
                           &c.sb.scal, &c.sb.dp, &c.sb.dpc, &c.sb.dpa, &c.sb.cand, &c.prop_w, &c.pcnt, &c.poff, &c.ppre, &c.pu, &c.pi, &c.plogit, &c.slot_r,
-                          &c.slot_part, &c.slot_age, &c.pm_part, &c.pe_part, &c.lz_t, &c.mlp_part, &c.est_buf, &c.ref_b1, &c.ref_opts, &c.ref_top, &c.ref_rest, &c.ref_tot, &c.hopts, &c.rec_lead,
+                          &c.slot_part, &c.slot_age, &c.pm_part, &c.pe_part, &c.lz_t, &c.mlp_part, &c.est_buf, &c.ref_b1, &c.ref_opts, &c.ref_top, &c.ref_rest, &c.ref_tot, &c.hopts, &c.ref_sel, &c.rec_lead,
                           &c.s_theta, &c.s_value, &c.s_keys, &c.s_vals, &c.s_flag, &c.s_pre, &c.s_rkeys, &c.s_rvals,
                           &c.s_selv, &c.j_corr, &c.j_val, &c.j_keys, &c.child_perm, &c.j_lw, &c.j_tmp, &c.rows3,
                           &c.rmass, &c.lz_r, &c.s_prow, &c.s_hash, &c.s_nt, &c.s_krank, &c.s_br};

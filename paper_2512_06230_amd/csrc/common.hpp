@@ -181,6 +181,10 @@ void kth_bound_mult(const float* v, const int32_t* mult, int n, int K, float* ou
 // Same, over the H * (M + 1) values B[h] - dev1 of cell (h, i) (i < M) and B[h].
 void kth_bound_cells(const float* B, const CellView& cv, int H, int M, int K, float* out, DevBuf& tmp,
                      hipStream_t s);
+// Same, over the roots and, per row, the cells of the m detections with the smallest first
+// deviations in row 0 (m chosen from H and K; all cells when that subset would be most of them).
+void kth_bound_cells_sub(const float* B, const CellView& cv, int H, int M, int K, float* out, DevBuf& tmp,
+                         DevBuf& selbuf, hipStream_t s);
 
 // ------------------------------------------------------------------ selection engine (select.hip)
 // Parents with base values; per-parent item lists sorted by (delta, group, option).

@@ -65,7 +65,7 @@ struct Ctx {
   DevBuf z, cmax, gbits, phi, lbits, lpre, llen, loff, lmeas, inst_beg, ccnt, coff, cand, best16, dev1, lserel, tbits, tpre,
       bprime, lzprime, cells, ccount, coff2, it_h, it_delta, it_group, it_opt, it_off, keys, vals32, scal,
       sel_logw, hp_map, first, dmask, exc, cmod, recs, rec_keys, rec_vals, ids, row_mark, ru_part, ru, bt,
-      tmp, tk, tv, flags, pre, pmult, pvals, rec_m, ref_b1, ref_opts, ref_top, ref_rest, ref_tot, hopts;
+      tmp, tk, tv, flags, pre, pmult, pvals, rec_m, ref_b1, ref_opts, ref_top, ref_rest, ref_tot, hopts, ref_sel;
   SelectBufs sb;
   bool sel_multi[2] = {false, false};  // per search site (prediction, update): start on the whole GPU
   bool coop_ok = true;  // cooperative launches allowed (they run one at a time on a device)
@@ -110,7 +110,9 @@ void stage_predict(Ctx& c, int k);
 void stage_update(Ctx& c, int k, const float* z, int M);
 void stage_truncate(Ctx& c, int hmax, float tau);
 // pieces of the update shared with the proposal
-void gate_scores(Ctx& c, const float* z, int M);
+// with pairs: also the gated pairs of the learned update (c.pu / c.pi, count at scal[19]) and
+// every instance's gated count (c.pcnt)
+void gate_scores(Ctx& c, const float* z, int M, bool pairs = false);
 void gate_lists(Ctx& c, int M);
 void assoc_norm(Ctx& c, int M);
 // proposal (proposal.hip)

@@ -458,6 +458,154 @@ void kth_bound_cells(const float* B, const CellView& cv, int H, int M, int K, fl
   GLMB_LAUNCH(k_bound_pick, 1, 1024, 0, s, hist, 1, prefix, need_k, out);
 }
 
+// The same bound over a subset of the children: every root B[h] and, in every row, the cells of
+// the m detections whose first deviation is smallest in row 0 (sel).  The K-th largest of a
+// subset of the children's values is at most the K-th largest of all, so the result is still
+// a lower bound; it reads H (m + 1) cells instead of H (M + 1).
+__global__ __launch_bounds__(256) void k_bound_hist_sub(int H, int m, const int32_t* sel, const int32_t* msel,
+                                                        const float* B, CellView cv, int pass, const uint32_t* prefix,
+                                                        int32_t* hist) {
+  __shared__ int32_t h[kBins];
+  for (int j = threadIdx.x; j < kBins; j += blockDim.x) h[j] = 0;
+  __syncthreads();
+  const uint32_t pre = pass ? *prefix : 0u;
+  const int mt = min(*msel, m), lane = lane_id();
+  auto bin_of = [&](float v) -> int {
+    const uint32_t o = f2o(v);
+    if (pass == 0) return (int)(o >> 20);
+    return (o >> 20) == pre ? (int)((o >> 8) & (kBins - 1)) : -1;
+  };
+  // each wave takes kRB rows at a time (the loads of all of them issued before any is used):
+  // the lanes over the selected detections, lane 0 also the roots; a wave whose lanes all
+  // share one bin adds its count with one atomic
+  constexpr int kRB = 4;
+  const int nw = gridDim.x * (blockDim.x / kWave);
+  const int gw = blockIdx.x * (blockDim.x / kWave) + (int)threadIdx.x / kWave;
+  for (int q0 = 0; q0 < mt; q0 += kWave) {
+    const int q = q0 + lane;
+    const bool on = q < mt;
+    const int iq = on ? sel[q] : 0;
+    const uint64_t all = __ballot(on);
+    for (int r0 = gw; r0 < H; r0 += kRB * nw) {
+      float bv[kRB], dv[kRB];
+#pragma unroll
+      for (int j = 0; j < kRB; ++j) {
+        const int r = r0 + j * nw;
+        bv[j] = r < H ? B[r] : -INFINITY;
+        dv[j] = (r < H && on) ? cv.dev1[cv.at(r, iq)] : INFINITY;
+      }
+#pragma unroll
+      for (int j = 0; j < kRB; ++j) {
+        const int r = r0 + j * nw;
+        if (r >= H) break;  // uniform: r depends on the wave only
+        const int bin = on ? bin_of(bv[j] - dv[j]) : -1;
+        const int b0 = __shfl(bin, 0, kWave);
+        if (b0 >= 0 && __ballot(bin == b0) == all) {
+          if (lane == 0) atomicAdd(&h[b0], __popcll(all));
+        } else if (bin >= 0) {
+          atomicAdd(&h[bin], 1);
+        }
+        if (q0 == 0 && lane == 0) {
+          const int br = bin_of(bv[j]);
+          if (br >= 0) atomicAdd(&h[br], 1);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < kBins; j += blockDim.x)
+    if (h[j]) atomicAdd(&hist[j], h[j]);
+}
+
+// One workgroup: about m detections with the smallest first deviations of row 0 (any subset of
+// the cells gives a valid bound; the smallest ones make it tight).  A 256-bin histogram of the
+// top byte of the orderable values finds the bin b in which the m-th smallest lies; every
+// detection of a lower bin is taken, then those of bin b in index order, up to m in all
+// (m <= M, so exactly m are taken; the count is written to *msel all the same).
+__global__ __launch_bounds__(1024) void k_ref_order(int M, const float* dev1, int m, int32_t* sel, int32_t* msel) {
+  __shared__ int32_t hist[256];
+  __shared__ int32_t wc[16];
+  __shared__ int32_t cut, taken;
+  const int t = threadIdx.x, lane = lane_id(), w = t / kWave, nw = blockDim.x / kWave;
+  if (t < 256) hist[t] = 0;
+  __syncthreads();
+  for (int i = t; i < M; i += blockDim.x) atomicAdd(&hist[f2o(dev1[i]) >> 24], 1);
+  __syncthreads();
+  // the bin where the running count from the smallest values reaches m: a scan over the 256
+  // bins by the first four waves (bin 255 when the count stays below m)
+  if (t == 0) {
+    cut = 255;
+    taken = 0;
+  }
+  int c = 0, x = 0;
+  if (t < 256) {
+    c = hist[t];
+    x = c;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const int y = __shfl_up(x, d, kWave);
+      if (lane >= d) x += y;
+    }
+    if (lane == kWave - 1) wc[w] = x;
+  }
+  __syncthreads();
+  if (t < 256) {
+    int before = x - c;
+    for (int q = 0; q < w; ++q) before += wc[q];
+    if (before < m && before + c >= m) cut = t;
+  }
+  __syncthreads();
+  const int b = cut;
+  // two sweeps in index order: the lower bins, then bin b while fewer than m are taken
+  for (int sweep = 0; sweep < 2; ++sweep) {
+    for (int i0 = 0; i0 < M; i0 += blockDim.x) {
+      const int i = i0 + t;
+      const int bi = i < M ? (int)(f2o(dev1[i]) >> 24) : 256;
+      const bool on = sweep == 0 ? bi < b : bi == b;
+      const uint64_t bal = __ballot(on);
+      if (lane == 0) wc[w] = __popcll(bal);
+      __syncthreads();
+      int before = 0, tot = 0;
+      for (int x = 0; x < nw; ++x) {
+        if (x < w) before += wc[x];
+        tot += wc[x];
+      }
+      const int at = taken + before + __popcll(bal & lanemask_lt());
+      if (on && at < m) sel[at] = i;
+      __syncthreads();
+      if (t == 0) taken = min(m, taken + tot);
+      __syncthreads();
+      if (taken >= m) break;
+    }
+  }
+  if (t == 0) *msel = taken;
+}
+
+void kth_bound_cells_sub(const float* B, const CellView& cv, int H, int M, int K, float* out, DevBuf& tmp,
+                         DevBuf& selbuf, hipStream_t s) {
+  // enough values that the subset's K-th largest stays close to the full one's
+  int m = 64;
+  if ((int64_t)H * (m + 1) < 4 * (int64_t)K) m = (int)std::min<int64_t>(M, cdiv(4 * (int64_t)K, H));
+  if (m * 2 > M || H < 2) {
+    kth_bound_cells(B, cv, H, M, K, out, tmp, s);
+    return;
+  }
+  int32_t* sel = need<int32_t>(selbuf, m + 1);
+  GLMB_LAUNCH(k_ref_order, 1, 1024, 0, s, M, cv.dev1, m, sel, sel + m);
+  tmp.reserve((kBins + 8) * sizeof(int32_t));
+  int32_t* hist = tmp.as<int32_t>();
+  uint32_t* prefix = (uint32_t*)(hist + kBins);
+  int32_t* need_k = hist + kBins + 1;
+  GLMB_LAUNCH(k_bound_init, 1, 256, 0, s, hist, need_k, (int32_t)K);
+  const int grid = std::max(1, std::min(cdiv(H, 4 * 4), 256));
+  GLMB_LAUNCH(k_bound_hist_sub, grid, 256, 0, s, H, m, (const int32_t*)sel, (const int32_t*)(sel + m), B, cv, 0, prefix,
+              hist);
+  GLMB_LAUNCH(k_bound_pick, 1, 1024, 0, s, hist, 0, prefix, need_k, out);
+  GLMB_LAUNCH(k_bound_hist_sub, grid, 256, 0, s, H, m, (const int32_t*)sel, (const int32_t*)(sel + m), B, cv, 1, prefix,
+              hist);
+  GLMB_LAUNCH(k_bound_pick, 1, 1024, 0, s, hist, 1, prefix, need_k, out);
+}
+
 void kth_bound(const float* v, int n, int K, float* out, DevBuf& tmp, hipStream_t s) {
   kth_bound_impl(v, nullptr, n, K, out, tmp, s);
 }

@@ -69,13 +69,121 @@ __device__ __forceinline__ float layer2_unit(const float* sw, const float* h1, i
   return a;
 }
 
-__device__ __forceinline__ float mlp_logit(const float* sw, const float* x, const Norm& nm) {
-  float xs[kNFeat], h1[kNHid];
-  standardise(x, nm, xs);
-  layer1(sw, xs, h1);
-  float s = sw[oB3];
-  for (int j = 0; j < kNHid; ++j) s = fmaf(sw[oW3 + j], bf16r(fmaxf(layer2_unit(sw, h1, j), 0.0f)), s);
-  return s;
+// Inference form of the network: weights and activations as packed bfloat16 pairs; the first
+// layer's sums of two products taken by one v_dot2 instruction into an FP32 accumulator
+// (products of two bfloat16 values are exact in FP32).  LDS words: W1 [64][3] | W2 [64][32] | w3 [32] packed,
+// then b1 [64] | b2 [64] | b3 as floats.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+constexpr int qW1 = 0, qW2 = qW1 + kNHid * (kNFeat / 2), qW3 = qW2 + kNHid * (kNHid / 2), qB1 = qW3 + kNHid / 2,
+              qB2 = qB1 + kNHid, qB3 = qB2 + kNHid, kNQ = qB3 + 1;
+static_assert(kNFeat % 2 == 0, "inputs in pairs");
+
+// two floats rounded to the nearest bfloat16 values (ties to even) and packed, lo in the low
+// half (one v_cvt_pk_bf16_f32)
+__device__ __forceinline__ uint32_t pack2(float lo, float hi) {
+  const bf16x2_t v = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(uint32_t, v);
+}
+__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float c) {
+  return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a), __builtin_bit_cast(bf16x2_t, b), c, false);
+}
+
+__device__ __forceinline__ void load_params_q(const float* __restrict__ w, uint32_t* q) {
+  for (int j = threadIdx.x; j < kNHid * (kNFeat / 2); j += blockDim.x)
+    q[qW1 + j] = pack2(w[oW1 + 2 * j], w[oW1 + 2 * j + 1]);
+  for (int j = threadIdx.x; j < kNHid * (kNHid / 2); j += blockDim.x)
+    q[qW2 + j] = pack2(w[oW2 + 2 * j], w[oW2 + 2 * j + 1]);
+  for (int j = threadIdx.x; j < kNHid / 2; j += blockDim.x) q[qW3 + j] = pack2(w[oW3 + 2 * j], w[oW3 + 2 * j + 1]);
+  for (int j = threadIdx.x; j < kNHid; j += blockDim.x) {
+    q[qB1 + j] = __float_as_uint(bf16r(w[oB1 + j]));
+    q[qB2 + j] = __float_as_uint(bf16r(w[oB2 + j]));
+  }
+  if (threadIdx.x == 0) q[qB3] = __float_as_uint(bf16r(w[oB3]));
+  __syncthreads();
+}
+
+// standardised inputs and the first hidden layer of one sample, packed
+__device__ __forceinline__ void layer1_q(const uint32_t* q, const float* x, const Norm& nm, uint32_t* h1) {
+  uint32_t xq[kNFeat / 2];
+#pragma unroll
+  for (int k = 0; k < kNFeat / 2; ++k)
+    xq[k] = pack2((x[2 * k] - nm.mu[2 * k]) / nm.sd[2 * k], (x[2 * k + 1] - nm.mu[2 * k + 1]) / nm.sd[2 * k + 1]);
+#pragma unroll
+  for (int j = 0; j < kNHid; j += 2) {
+    float a0 = __uint_as_float(q[qB1 + j]), a1 = __uint_as_float(q[qB1 + j + 1]);
+#pragma unroll
+    for (int k = 0; k < kNFeat / 2; ++k) {
+      a0 = dot2(q[qW1 + j * (kNFeat / 2) + k], xq[k], a0);
+      a1 = dot2(q[qW1 + (j + 1) * (kNFeat / 2) + k], xq[k], a1);
+    }
+    h1[j / 2] = pack2(fmaxf(a0, 0.0f), fmaxf(a1, 0.0f));
+  }
+}
+
+// The same network for the 64 samples of a wave (lane l: sample l; every lane of the wave must
+// call it): layer 1 per lane with v_dot2, the 64 x 64 layer on the matrix cores as
+// H2^T = W2 H1^T (units as rows, samples as columns) with v_mfma_f32_32x32x16_bf16: two tiles of
+// 32 units by two tiles of 32 samples, four steps of 16 inputs.  Operand layouts (lane l, half
+// g = l / 32): A holds row l % 32, inputs 8g..8g+7 of the step; B holds column l % 32, the same
+// inputs; the accumulator's value v holds row 8 (v / 4) + 4 g + v % 4, column l % 32.  Column c of
+// sample tile t is sample 32 t + c, whose hidden values lane 32 t + c holds: a lane keeps the
+// half of the step's inputs its own B needs and swaps the other half with lane l ^ 32.  The
+// output layer sums each lane's 32 units and its partner's.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float mlp_logit_mfma(const uint32_t* q, const float* x, const Norm& nm) {
+  uint32_t h1[kNHid / 2];
+  layer1_q(q, x, nm, h1);
+  const int l = lane_id(), g = l >> 5, col = l & 31;
+  f32x16_t acc[2][2];  // [unit tile][sample tile]
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const float b = __uint_as_float(q[qB2 + mt * 32 + 8 * (v >> 2) + 4 * g + (v & 3)]);
+      acc[mt][0][v] = b;
+      acc[mt][1][v] = b;
+    }
+#pragma unroll
+  for (int ks = 0; ks < 4; ++ks) {
+    // this lane's inputs [16 ks, 16 ks + 8) and [16 ks + 8, 16 ks + 16), four words each
+    u32x4_t lo, hi, snd, rcv;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      lo[e] = h1[8 * ks + e];
+      hi[e] = h1[8 * ks + 4 + e];
+    }
+    snd = g ? lo : hi;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) rcv[e] = (uint32_t)__shfl_xor((int)snd[e], 32, kWave);
+    const u32x4_t b0 = g ? rcv : lo;  // samples 0..31: sample col, inputs of half g
+    const u32x4_t b1 = g ? hi : rcv;  // samples 32..63
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      const u32x4_t a = *(const u32x4_t*)(q + qW2 + (mt * 32 + col) * (kNHid / 2) + 8 * ks + 4 * g);
+      acc[mt][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a),
+                                                          __builtin_bit_cast(bf16x8_t, b0), acc[mt][0], 0, 0, 0);
+      acc[mt][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8_t, a),
+                                                          __builtin_bit_cast(bf16x8_t, b1), acc[mt][1], 0, 0, 0);
+    }
+  }
+  // output layer: values v and v + 1 of a lane are units u and u + 1 (u even), one packed
+  // weight word and one v_dot2 per pair of units
+  float part[2] = {0.0f, 0.0f};
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int v = 0; v < 16; v += 2) {
+      const int unit = mt * 32 + 8 * (v >> 2) + 4 * g + (v & 3);
+      const uint32_t wq = q[qW3 + unit / 2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+        part[t] = dot2(wq, pack2(fmaxf(acc[mt][t][v], 0.0f), fmaxf(acc[mt][t][v + 1], 0.0f)), part[t]);
+    }
+  const float mine = part[g];
+  return __uint_as_float(q[qB3]) + (mine + __shfl_xor(part[g ^ 1], 32, kWave));
 }
 
 // features of pair (instance x, detection zi); d2 uses the gate's expression
@@ -145,15 +253,24 @@ __global__ void k_pair_list(int U, int W, const uint32_t* gbits, const int32_t* 
 }
 
 // existence probability of every label slot: partial sums over chunks of kSlotChunk hypotheses
-constexpr int kSlotChunk = 32;
+constexpr int kSlotChunk = 16;
 __global__ void k_slot_part(int H, int NS, int SW, const int32_t* rows, const float* logw, float* part) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   const int ch = blockIdx.y;
   if (s >= NS) return;
+  // the chunk's row entries and weights first (independent loads), then the sum in order
+  int32_t id[kSlotChunk];
+  float lw[kSlotChunk];
+#pragma unroll
+  for (int j = 0; j < kSlotChunk; ++j) {
+    const int h = ch * kSlotChunk + j;
+    id[j] = h < H ? rows[(size_t)h * SW + s] : -1;
+    lw[j] = h < H ? logw[h] : -INFINITY;
+  }
   float acc = 0.0f;
-  const int h1 = min(H, (ch + 1) * kSlotChunk);
-  for (int h = ch * kSlotChunk; h < h1; ++h)
-    if (rows[(size_t)h * SW + s] >= 0) acc += __expf(logw[h]);
+#pragma unroll
+  for (int j = 0; j < kSlotChunk; ++j)
+    if (id[j] >= 0) acc += __expf(lw[j]);
   part[(size_t)ch * NS + s] = acc;
 }
 // one wave per slot: the partial sums, lanes over the chunks, then a fixed butterfly
@@ -181,15 +298,11 @@ __global__ void k_pair_feat(int n, const int32_t* pu, const int32_t* pi, const D
   pair[2 * (size_t)p + 1] = i;
 }
 
-__global__ void k_zero_u64(unsigned long long* p, int n) {
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q < n) p[q] = 0ull;
-}
 
 // network score of every pair; with `remove`, pairs scoring below thr leave the gate, and the
 // likelihood exp(phi) of a removed pair whose instance belongs to the most likely predicted
 // hypothesis (row0) is added to its detection's removed mass (fixed point, so that the sum
-// does not depend on the order of the atomic additions)
+// does not depend on the order of the atomic additions; zeroed with the detections)
 __global__ __launch_bounds__(256) void k_prop_apply(const int32_t* np, const int32_t* pu, const int32_t* pi,
                                                     const DInst* inst,
                                                     const float2* z, float sig2, const float* slot_r,
@@ -198,29 +311,51 @@ __global__ __launch_bounds__(256) void k_prop_apply(const int32_t* np, const int
                                                     int W, float* phi, uint32_t* gbits, float* logit_out,
                                                     int32_t* nremoved, const int32_t* row0,
                                                     unsigned long long* rmass) {
-  __shared__ float sw[kNParam];
+  __shared__ __align__(16) uint32_t sq[kNQ];
   const int n = *np;
   if ((int)(blockIdx.x * blockDim.x) >= n) return;  // the grid covers an upper bound
-  load_params(params, sw);
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  bool rm = false;
-  if (p < n) {
-    const int u = pu[p], i = pi[p];
-    const DInst x = inst[u];
-    float f[kNFeat];
-    pair_feature(x, z[i], sig2, slot_r[x.slot], (float)slot_age[x.slot], (float)pcnt[u], f);
-    const float s = mlp_logit(sw, f, nm);
-    if (logit_out) logit_out[p] = s;
-    if (remove && s < thr) {
-      rm = true;
-      if (rmass && row0[x.slot] == u)
-        atomicAdd(&rmass[i], (unsigned long long)(expf(phi[(size_t)u * M + i]) * kRemovedScale));
-      phi[(size_t)u * M + i] = -INFINITY;
-      atomicAnd(&gbits[(size_t)u * W + (i >> 5)], ~(1u << (i & 31)));
+  load_params_q(params, sq);
+  const int lane = lane_id();
+  // workgroups take chunks of blockDim pairs in turn (the parameters are loaded once)
+  for (int p0 = blockIdx.x * blockDim.x; p0 < n; p0 += gridDim.x * blockDim.x) {
+    const int p = p0 + threadIdx.x;
+    const bool valid = p < n;
+    // every lane takes part in the network (a lane without a pair scores zero features)
+    int u = 0, i = 0, slot = 0;
+    float f[kNFeat] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+    if (valid) {
+      u = pu[p];
+      i = pi[p];
+      const DInst x = inst[u];
+      slot = x.slot;
+      pair_feature(x, z[i], sig2, slot_r[x.slot], (float)slot_age[x.slot], (float)pcnt[u], f);
     }
+    const float s = mlp_logit_mfma(sq, f, nm);
+    bool rm = false;
+    if (valid) {
+      if (logit_out) logit_out[p] = s;
+      if (remove && s < thr) {
+        rm = true;
+        if (rmass && row0[slot] == u)
+          atomicAdd(&rmass[i], (unsigned long long)(expf(phi[(size_t)u * M + i]) * kRemovedScale));
+        phi[(size_t)u * M + i] = -INFINITY;
+      }
+    }
+    // the removed pairs' gate bits: the pairs are listed by (instance, detection), so the lanes
+    // of one gate word are adjacent; each run's first lane clears the run's bits with one atomic
+    const int key = valid ? u * W + (i >> 5) : INT32_MAX;
+    uint32_t bits = rm ? (1u << (i & 31)) : 0u;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+      const uint32_t ob = __shfl_down(bits, d, kWave);
+      const int ok = __shfl_down(key, d, kWave);
+      if (lane + d < kWave && ok == key) bits |= ob;
+    }
+    const int pk = __shfl_up(key, 1, kWave);
+    if (valid && bits && (lane == 0 || pk != key)) atomicAnd(&gbits[key], ~bits);
+    const uint64_t b = __ballot(rm);
+    if (lane == 0 && b) atomicAdd(nremoved, (int32_t)__popcll(b));
   }
-  const uint64_t b = __ballot(rm);
-  if (lane_id() == 0 && b) atomicAdd(nremoved, (int32_t)__popcll(b));
 }
 
 // ------------------------------------------------------------------ lost mass
@@ -362,14 +497,14 @@ __global__ void k_pair_target(int n, int U, int nch, const int32_t* pu, const fl
 // ------------------------------------------------------------------ network kernels
 __global__ __launch_bounds__(256) void k_mlp_fwd(int n, const float* feat, const float* params, Norm nm,
                                                  float* logit) {
-  __shared__ float sw[kNParam];
-  load_params(params, sw);
+  __shared__ __align__(16) uint32_t sq[kNQ];
+  load_params_q(params, sq);
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
   float f[kNFeat];
 #pragma unroll
-  for (int k = 0; k < kNFeat; ++k) f[k] = feat[(size_t)p * kNFeat + k];
-  logit[p] = mlp_logit(sw, f, nm);
+  for (int k = 0; k < kNFeat; ++k) f[k] = p < n ? feat[(size_t)p * kNFeat + k] : 0.0f;
+  const float s = mlp_logit_mfma(sq, f, nm);  // every lane of the wave
+  if (p < n) logit[p] = s;
 }
 
 // One wave per 64 samples: forward, loss, backward to per-sample vectors in LDS, then the
@@ -496,14 +631,11 @@ Norm norm_of(const float* nm) {
   return n;
 }
 
-// label existence, label ages, and the compacted pair list of the current gate; returns the
-// pair count when host_count, else -1 (the count stays on the device at c.poff[U], the lists
-// are sized for every instance x detection pair)
-int prepare_pairs(Ctx& c, int k, int M, bool host_count = true) {
+// label existence and age of every slot (the network's inputs besides the pair's own)
+void prepare_slots(Ctx& c, int k) {
   hipStream_t s = c.s;
   const int T = 256;
-  const int H = c.nhyp, U = c.ninst, NS = c.nslot, SW = c.stride;
-  const int W = std::max(1, (M + 31) / 32);
+  const int H = c.nhyp, NS = c.nslot, SW = c.stride;
   const int nch = cdiv(H, kSlotChunk);
   float* part = need<float>(c.slot_part, (int64_t)nch * std::max(NS, 1));
   float* r = need<float>(c.slot_r, NS + 1);
@@ -525,33 +657,40 @@ int prepare_pairs(Ctx& c, int k, int M, bool host_count = true) {
   for (int j = 0; j < NS; ++j) c.age_pin[j] = k - c.slot_lab[j].first;
   int32_t* age = need<int32_t>(c.slot_age, NS + 1);
   if (NS) GLMB_HIP(hipMemcpyAsync(age, c.age_pin, NS * sizeof(int32_t), hipMemcpyHostToDevice, s));
+}
+
+// label existence and ages, and the gated pairs listed by (instance, detection); returns their
+// count (one round trip)
+int prepare_pairs(Ctx& c, int k, int M) {
+  hipStream_t s = c.s;
+  const int T = 256;
+  const int U = c.ninst;
+  const int W = std::max(1, (M + 31) / 32);
+  prepare_slots(c, k);
   int32_t* cnt = need<int32_t>(c.pcnt, U + 1);
   int32_t* off = need<int32_t>(c.poff, U + 1);
   int32_t* ppre = need<int32_t>(c.ppre, (int64_t)U * W);
   GLMB_LAUNCH(k_pair_count, cdiv((int64_t)U * kWave, T), T, 0, s, U, W, c.gbits.as<uint32_t>(), cnt, ppre);
   scan_excl(cnt, off, U, off + U, c.tmp, s);
-  const int n = !host_count ? -1 : U > 0 ? (int)read_back(c.sb.hs, s, {{off + U, 1}})[0] : 0;
-  const int64_t cap = host_count ? n : (int64_t)U * M;
-  int32_t* pu = need<int32_t>(c.pu, cap);
-  int32_t* pi = need<int32_t>(c.pi, cap);
+  const int n = U > 0 ? (int)read_back(c.sb.hs, s, {{off + U, 1}})[0] : 0;
+  int32_t* pu = need<int32_t>(c.pu, n);
+  int32_t* pi = need<int32_t>(c.pi, n);
   GLMB_LAUNCH(k_pair_list, cdiv((int64_t)U * W, T), T, 0, s, U, W, c.gbits.as<uint32_t>(), off, ppre, pu, pi);
   return n;
 }
 
 // network scores of the listed pairs (into c.plogit unless removing), optionally removing the
-// low ones; n < 0: the count is on the device (c.poff[U]) and the grid covers at most cap pairs
+// low ones; n < 0: the gate's pair list, whose count is on the device (scal[19]), and the grid
+// covers at most U x M pairs
 void score_pairs(Ctx& c, int n, int M, bool remove) {
   const int W = std::max(1, (M + 31) / 32);
   const int64_t cap = n >= 0 ? n : (int64_t)c.ninst * M;
   float* logit = remove ? nullptr : need<float>(c.plogit, cap);
   int32_t* nremoved = c.scal.as<int32_t>() + 18;
-  const int grid = cdiv(cap, 256);
-  unsigned long long* rmass = nullptr;
-  if (remove) {
-    rmass = need<unsigned long long>(c.rmass, M + 1);
-    GLMB_LAUNCH(k_zero_u64, cdiv(M + 1, 256), 256, 0, c.s, rmass, M + 1);
-  }
-  GLMB_LAUNCH(k_prop_apply, grid, 256, 0, c.s, c.poff.as<int32_t>() + c.ninst, c.pu.as<int32_t>(), c.pi.as<int32_t>(),
+  const int grid = std::min(cdiv(cap, 256), 4096);
+  unsigned long long* rmass = remove ? c.rmass.as<unsigned long long>() : nullptr;
+  const int32_t* np = n >= 0 ? c.poff.as<int32_t>() + c.ninst : c.scal.as<int32_t>() + 19;
+  GLMB_LAUNCH(k_prop_apply, grid, 256, 0, c.s, np, c.pu.as<int32_t>(), c.pi.as<int32_t>(),
               (const DInst*)c.inst.p, c.z.as<float2>(), c.p.sigma_z * c.p.sigma_z, c.slot_r.as<float>(),
               c.slot_age.as<int32_t>(), c.pcnt.as<int32_t>(), c.prop_w.as<float>(), norm_of(c.prop_norm),
               c.prop_thr, remove ? 1 : 0, M, W, c.phi.as<float>(), c.gbits.as<uint32_t>(), logit, nremoved,
@@ -561,8 +700,9 @@ void score_pairs(Ctx& c, int n, int M, bool remove) {
 
 void proposal_apply(Ctx& c, int k, int M) {
   trace(c, "update.proposal");
-  const int n = prepare_pairs(c, k, M, false);
-  score_pairs(c, n, M, true);
+  // the gate listed the pairs (count at scal[19]) and the per-instance counts
+  prepare_slots(c, k);
+  score_pairs(c, -1, M, true);
 }
 
 void proposal_lost(Ctx& c, int k, const float* zin, int M, const float* thr_prob, int T, double* lost) {

@@ -24,8 +24,13 @@ namespace glmb {
 enum : uint32_t { ERR_BIRTH = 1, ERR_DEPTH = 4, ERR_NAN = 8 };
 
 // ------------------------------------------------------------------ U0 / U1
-__global__ void k_z_in(const float* zin, int M, float2* z, uint32_t* errf) {
+// detections in; with pcnt (the learned update), also the n per-instance gated counts and the
+// M + 1 removed masses zeroed
+__global__ void k_z_in(const float* zin, int M, float2* z, uint32_t* errf, int32_t* pcnt, int n,
+                       unsigned long long* rmass) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pcnt && i < n) pcnt[i] = 0;
+  if (rmass && i <= M) rmass[i] = 0ull;
   if (i >= M) return;
   const float x = zin[2 * i], y = zin[2 * i + 1];
   if (!(x == x) || !(y == y) || isinf(x) || isinf(y)) atomicOr(errf, ERR_NAN);
@@ -46,9 +51,13 @@ __global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
 // score of its 64 pairs, one ballot into the gate bitmap; the running maximum of the scores
 // goes to the per-detection reference c_i with one atomic per lane for the whole group.
 constexpr int kGateIpw = 8;
+// With pn (the learned update): every instance's gated count is added to pcnt, and the gated
+// pairs are appended to (pu, pi), one reservation per wave, each wave's pairs by (instance,
+// detection); the order of the waves' runs is arbitrary.
 __global__ __launch_bounds__(256) void k_gate(const DInst* inst, int U, const float2* z, int M, int W, float sig2,
                                               float gate, float lgc, uint32_t* gbits, float* phi, uint32_t* cmax,
-                                              unsigned long long* ngated) {
+                                              unsigned long long* ngated, int32_t* pcnt, int32_t* pn, int32_t* pu,
+                                              int32_t* pi) {
   const int gw = (int)((blockIdx.x * blockDim.x + threadIdx.x) / kWave);
   const int nch = (M + kWave - 1) / kWave;
   const int ug = gw / nch, ch = gw % nch;
@@ -57,6 +66,7 @@ __global__ __launch_bounds__(256) void k_gate(const DInst* inst, int U, const fl
   const float2 zi = i < M ? z[i] : make_float2(0.0f, 0.0f);
   float fmx = -INFINITY;
   int ng = 0;
+  uint32_t gk = 0;  // this lane's gate decisions, one bit per instance of the group
   for (int k = 0; k < kGateIpw; ++k) {
     const int u = ug * kGateIpw + k;
     if (u >= U) break;  // the same for the whole wave
@@ -77,8 +87,27 @@ __global__ __launch_bounds__(256) void k_gate(const DInst* inst, int U, const fl
     if (lane == 0) {
       gbits[(size_t)u * W + 2 * ch] = (uint32_t)bal;
       if (2 * ch + 1 < W) gbits[(size_t)u * W + 2 * ch + 1] = (uint32_t)(bal >> 32);
+      if (pn && bal) atomicAdd(&pcnt[u], (int32_t)__popcll(bal));
     }
+    if (g) gk |= 1u << k;
     ng += __popcll(bal);
+  }
+  if (pn && ng) {
+    int base = 0;
+    if (lane == 0) base = atomicAdd(pn, ng);
+    base = __shfl(base, 0, kWave);
+    for (int k = 0; k < kGateIpw; ++k) {
+      const int u = ug * kGateIpw + k;
+      if (u >= U) break;
+      const bool g = (gk >> k) & 1u;
+      const uint64_t bal = __ballot(g);
+      if (g) {
+        const int at = base + __popcll(bal & lanemask_lt());
+        pu[at] = u;
+        pi[at] = i;
+      }
+      base += __popcll(bal);
+    }
   }
   if (fmx > -INFINITY) atomicMax(&cmax[i], f2o(fmx));
   // one counter update per workgroup
@@ -1469,21 +1498,50 @@ __global__ void k_ru_lr(int M, const uint32_t* cmax, const unsigned long long* r
   if (i < M) lr[i] = rmass[i] == 0ull ? -INFINITY : logf((float)((double)rmass[i] / kRemovedScale)) - o2f(cmax[i]);
 }
 
-// one wave per hypothesis: lzr[h] = lzprime[h] + sum_i (log(e^{l_hi} + R_i) - l_hi), lanes over
-// the detections with removed mass, fixed butterfly
+// lzr[h] = lzprime[h] + sum_i (log(e^{l_hi} + R_i) - l_hi) over the detections with removed
+// mass.  Hypothesis 0's terms T0_i (k_ru_t0) and their FP64 total stand for every untouched
+// cell; one wave per hypothesis then exchanges T0_i for its own term on its touched cells
+// (lanes over the touched-set words, bits in ascending order), fixed butterfly.
+__global__ __launch_bounds__(256) void k_ru_t0(int M, const float* lserel0, const float* lr, float* t0,
+                                               double* tot) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < M; i += blockDim.x) {
+    const float r = lr[i];
+    const float ls = lserel0[i];
+    const float v = r == -INFINITY ? 0.0f : lse2(ls, r) - ls;
+    t0[i] = v;
+    acc += (double)v;
+  }
+  for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_xor(acc, d, kWave);
+  if (lane_id() == 0) red[threadIdx.x / kWave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) *tot = red[0] + red[1] + red[2] + red[3];
+}
 __global__ __launch_bounds__(256) void k_ru_restore(int H, int M, const float* lzprime, CellView cv,
-                                                    const float* lr, float* lzr) {
+                                                    const float* lr, const float* t0, const double* tot,
+                                                    float* lzr) {
   const int h = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kWave);
   if (h >= H) return;
   float acc = 0.0f;
-  for (int i = lane_id(); i < M; i += kWave) {
-    const float r = lr[i];
-    if (r == -INFINITY) continue;
-    const float ls = cv.lserel[cv.at(h, i)];
-    acc += lse2(ls, r) - ls;
-  }
+  if (h > 0)
+    for (int x = lane_id(); x < cv.W; x += kWave) {
+      const size_t wi = (size_t)h * cv.W + x;
+      uint32_t word = cv.tbits[wi];
+      size_t pos = (size_t)h * M + cv.tpre[wi];
+      while (word) {
+        const int i = 32 * x + __ffs(word) - 1;
+        word &= word - 1u;
+        const float r = lr[i];
+        if (r != -INFINITY) {
+          const float ls = cv.lserel[pos];
+          acc += (lse2(ls, r) - ls) - t0[i];
+        }
+        ++pos;
+      }
+    }
   for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_xor(acc, d, kWave);
-  if (lane_id() == 0) lzr[h] = lzprime[h] + acc;
+  if (lane_id() == 0) lzr[h] = lzprime[h] + (float)(*tot + (double)acc);
 }
 // one workgroup: out = log sum_h exp(v[h])
 __global__ __launch_bounds__(1024) void k_lse_block(int H, const float* v, float* out) {
@@ -1650,7 +1708,7 @@ void check_err_bits(uint32_t e) {
 
 // U0 + U1 scores: detections, gate bits and Eq. 2 entries of every (instance, detection) pair.
 // Scalars: see stage_update.
-void gate_scores(Ctx& c, const float* zin, int M) {
+void gate_scores(Ctx& c, const float* zin, int M, bool pairs) {
   hipStream_t s = c.s;
   const int T = 256;
   const int U = c.ninst;
@@ -1664,7 +1722,9 @@ void gate_scores(Ctx& c, const float* zin, int M) {
   unsigned long long* ngated = (unsigned long long*)(scal + 2);
   GLMB_HIP(hipMemsetAsync(scal, 0, 64 * sizeof(int32_t), s));
   float2* z = need<float2>(c.z, M);
-  GLMB_LAUNCH(k_z_in, cdiv(M, T), T, 0, s, zin, M, z, errf);
+  int32_t* pcnt = pairs ? need<int32_t>(c.pcnt, U + 1) : nullptr;
+  unsigned long long* rmass = pairs ? need<unsigned long long>(c.rmass, M + 1) : nullptr;
+  GLMB_LAUNCH(k_z_in, cdiv(std::max(M + 1, pairs ? U + 1 : 0), T), T, 0, s, zin, M, z, errf, pcnt, U + 1, rmass);
   uint32_t* cmax = need<uint32_t>(c.cmax, M);
   {
     float fl = lgk;
@@ -1675,10 +1735,16 @@ void gate_scores(Ctx& c, const float* zin, int M) {
   }
   uint32_t* gbits = need<uint32_t>(c.gbits, (int64_t)U * W);
   float* phi = need<float>(c.phi, (int64_t)U * M);
+  int32_t *pn = nullptr, *pu = nullptr, *pi = nullptr;
+  if (pairs) {  // the learned update's pair list, in arbitrary order of the gate's waves
+    pn = scal + 19;  // zeroed with the scalars above
+    pu = need<int32_t>(c.pu, (int64_t)U * M);
+    pi = need<int32_t>(c.pi, (int64_t)U * M);
+  }
   if (U > 0 && M > 0) {
     const int64_t waves = (int64_t)cdiv(U, kGateIpw) * cdiv(M, kWave);
     GLMB_LAUNCH(k_gate, cdiv(waves * kWave, T), T, 0, s, (const DInst*)c.inst.p, U, z, M, W, sig2, p.gate_d2, lgc,
-                gbits, phi, cmax, ngated);
+                gbits, phi, cmax, ngated, pcnt, pn, pu, pi);
   } else if (U > 0) {
     GLMB_LAUNCH(k_fill_u32, cdiv((int64_t)U * W, T), T, 0, s, gbits, U * W, 0u);  // no detections: nothing gated
   }
@@ -1820,7 +1886,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   // ---- U0 + U1: detections, gate, scores
   trace(c, "update.begin", H, M);
   c.mark(0);
-  gate_scores(c, zin, M);
+  gate_scores(c, zin, M, c.prop_on && M > 0);
   int32_t* scal = c.scal.as<int32_t>();
   uint32_t* errf = (uint32_t*)scal;
   unsigned long long* ngated = (unsigned long long*)(scal + 2);
@@ -1874,7 +1940,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   } else {
   // ---- U3: lower bound of the cut, deviation items, exact selection
   trace(c, "update.U3");
-  kth_bound_cells(bprime, cv, H, M, K, t0, c.tmp, s);
+  kth_bound_cells_sub(bprime, cv, H, M, K, t0, c.tmp, c.ref_sel, s);
   // counting bound, first pass (from the cells' first deviations): the items are generated
   // for the children above it only
   const float* tcut = dp_bound_rows(bprime, H, cv, M, K, t0, c.sb, s);
@@ -2158,10 +2224,16 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     const float* Lb = lz;
     float* lrm = nullptr;
     if (c.prop_on) {  // hypothesis masses with the removed pairs restored, and their normaliser
-      float* lzr = need<float>(c.lz_r, H + 1 + M);
+      // [H + 1 masses and normaliser | M removed masses | M terms of hypothesis 0 | FP64 total]
+      const int64_t o_tot = ((int64_t)H + 1 + 2 * (int64_t)M + 1) & ~(int64_t)1;
+      float* lzr = need<float>(c.lz_r, o_tot + 2);
       lrm = lzr + H + 1;
+      float* t0r = lrm + M;
+      double* tot0 = (double*)(lzr + o_tot);
       GLMB_LAUNCH(k_ru_lr, cdiv(M, T), T, 0, s, M, cmax, c.rmass.as<unsigned long long>(), lrm);
-      GLMB_LAUNCH(k_ru_restore, cdiv((int64_t)H * kWave, T), T, 0, s, H, M, lzprime, cv, lrm, lzr);
+      GLMB_LAUNCH(k_ru_t0, 1, 256, 0, s, M, cv.lserel, (const float*)lrm, t0r, tot0);
+      GLMB_LAUNCH(k_ru_restore, cdiv((int64_t)H * kWave, T), T, 0, s, H, M, lzprime, cv, (const float*)lrm,
+                  (const float*)t0r, (const double*)tot0, lzr);
       GLMB_LAUNCH(k_lse_block, 1, 1024, 0, s, H, lzr, lzr + H);
       lzb = lzr;
       Lb = lzr + H;
