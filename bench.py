@@ -161,8 +161,8 @@ def particle_leg(torch, scene, z, k, P, params, reps=20):
 
 
 def assoc_source_sha(rec):
-    """sha256 of the source region holding the association kernels (the text between the
-    two marker lines named in the traffic record), or None when the file or a marker is gone."""
+    """sha256 of the source region holding the measured kernels (the text between the two
+    marker lines named in the traffic record), or None when the file or a marker is gone."""
     import hashlib
     src = os.path.join(ROOT, rec["source"])
     if not os.path.exists(src):
@@ -435,13 +435,11 @@ def main():
         if assoc_source_sha(rec) == rec["source_sha256"] and args.n_obj == 500 and args.h_max == 10000:
             traffic = rec["bytes_per_launch"]
     # measured HBM bytes of the materialisation stage per update (same counters and scaling),
-    # null once update.hip differs from the source the counters were taken with
+    # null once the materialisation kernels' source differs from the one the counters were taken with
     uf = os.path.join(ROOT, "profiles", "u4_n500_h1e4_traffic.json")
     if os.path.exists(uf) and args.n_obj == 500 and args.h_max == 10000 and args.preset == "c3":
-        import hashlib
         urec = json.load(open(uf))
-        src = os.path.join(ROOT, urec["source"])
-        same = os.path.exists(src) and hashlib.sha256(open(src).read().encode()).hexdigest() == urec["source_sha256"]
+        same = assoc_source_sha(urec) == urec["source_sha256"]
         mat = roof["materialise"]
         mat["traffic"] = urec["bytes_per_update"] if same else None
         mat["traffic_frac"] = (urec["bytes_per_update"] / (mat["measured_ms"] * 1e-3) / (HBM_PEAK_GBS * 1e9)

@@ -248,6 +248,7 @@ glmb_status glmb_create(const glmb_params* p, int device, void* stream, glmb_ctx
   // diagnostic: GLMB_SEARCH_FORM=multi runs every selection on the host-driven multi-kernel
   // levels (the form a batched scene falls back to when its search outgrows one workgroup)
   if (const char* sf = std::getenv("GLMB_SEARCH_FORM")) x->c.force_multi = std::strcmp(sf, "multi") == 0;
+  if (const char* ss = std::getenv("GLMB_SIDE_STREAM")) x->c.fork_ok = std::strcmp(ss, "0") != 0;
   if (const char* hb = std::getenv("GLMB_REC_HASH_BITS")) {
     const int bits = std::atoi(hb);
     if (bits >= 1 && bits < 32) x->c.rec_hash_mask = (1u << bits) - 1u;
@@ -272,6 +273,11 @@ glmb_status glmb_destroy(glmb_ctx* x) {
   (void)hipSetDevice(x->c.device);
   (void)hipStreamSynchronize(x->c.s);
   glmb::Ctx& c = x->c;
+  if (c.s2) {
+    (void)hipStreamSynchronize(c.s2);
+    for (auto& e : c.fork) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(c.s2);
+  }
   glmb::DevBuf* bufs[] = {&c.inst, &c.inst2, &c.inst_nz, &c.inst_z, &c.logw, &c.ntrk, &c.rows, &c.hparent, &c.logw2,
                           &c.ntrk2, &c.rows2, &c.births, &c.births2, &c.diag_best, &c.diag_logpi, &c.diag_ru, &c.prev_rows,
                           &c.prev_src, &c.child_par, &c.dev_off, &c.dev_i, &c.dev_slot, &c.z, &c.cmax, &c.gbits,

@@ -65,6 +65,8 @@ glmb_status glmb_batch_create(int32_t n, const glmb_params* params, int device, 
     // cooperative launches run one at a time on a device: concurrent scenes use the
     // multi-kernel form of the whole-GPU search, which overlaps across streams
     b->ctx[i]->c.coop_ok = false;
+    // scenes overlap across the worker streams already: no side stream per scene
+    b->ctx[i]->c.fork_ok = false;
   }
   *out = b;
   return GLMB_OK;

@@ -40,6 +40,17 @@ struct Ctx {
   bool trace = false;  // GLMB_TRACE=1: print every host-side stage to stderr (flushed)
   hipEvent_t ev[8] = {};  // stage timing events on the context's stream
   bool ev_ok = false;
+  // Side stream for work that overlaps the main chain: the births' clutter probabilities run
+  // beside the selection and materialisation, the learned proposal's label inputs beside the
+  // gate.  Created on first use (default priority); fork[j] are its fork / join events.
+  bool fork_ok = true;
+  hipStream_t s2 = nullptr;
+  hipEvent_t fork[4] = {};
+  void side_ready() {
+    if (s2) return;
+    GLMB_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+    for (auto& e : fork) GLMB_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
   void mark(int i) {
     if (ev_ok) (void)hipEventRecord(ev[i], s);
   }
@@ -119,7 +130,10 @@ void assoc_norm(Ctx& c, int M);
 constexpr int kNFeat = 6, kNHid = 64, kNParam = 4673, kMaxThr = 16;
 // fixed-point scale of the removed likelihood sums (exp(phi) <= gamma / (2 pi sigma^2) per pair)
 constexpr double kRemovedScale = 281474976710656.0;  // 2^48
-void proposal_apply(Ctx& c, int k, int M);
+// the label inputs (existence, age) of the learned update on stream st
+void prepare_slots(Ctx& c, int k, hipStream_t st);
+// slots_ready: prepare_slots was queued on the side stream, joined by event fork[2]
+void proposal_apply(Ctx& c, int k, int M, bool slots_ready = false);
 void proposal_lost(Ctx& c, int k, const float* z, int M, const float* thr_prob, int T, double* lost);
 int proposal_features(Ctx& c, int k, const float* z, int M, int cap, float* feat, int32_t* pair, float* target,
                       float* weight);

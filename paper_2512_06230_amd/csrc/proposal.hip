@@ -632,8 +632,9 @@ Norm norm_of(const float* nm) {
 }
 
 // label existence and age of every slot (the network's inputs besides the pair's own)
-void prepare_slots(Ctx& c, int k) {
-  hipStream_t s = c.s;
+}  // namespace
+
+void prepare_slots(Ctx& c, int k, hipStream_t s) {
   const int T = 256;
   const int H = c.nhyp, NS = c.nslot, SW = c.stride;
   const int nch = cdiv(H, kSlotChunk);
@@ -659,6 +660,8 @@ void prepare_slots(Ctx& c, int k) {
   if (NS) GLMB_HIP(hipMemcpyAsync(age, c.age_pin, NS * sizeof(int32_t), hipMemcpyHostToDevice, s));
 }
 
+namespace {
+
 // label existence and ages, and the gated pairs listed by (instance, detection); returns their
 // count (one round trip)
 int prepare_pairs(Ctx& c, int k, int M) {
@@ -666,7 +669,7 @@ int prepare_pairs(Ctx& c, int k, int M) {
   const int T = 256;
   const int U = c.ninst;
   const int W = std::max(1, (M + 31) / 32);
-  prepare_slots(c, k);
+  prepare_slots(c, k, s);
   int32_t* cnt = need<int32_t>(c.pcnt, U + 1);
   int32_t* off = need<int32_t>(c.poff, U + 1);
   int32_t* ppre = need<int32_t>(c.ppre, (int64_t)U * W);
@@ -698,10 +701,11 @@ void score_pairs(Ctx& c, int n, int M, bool remove) {
 }
 }  // namespace
 
-void proposal_apply(Ctx& c, int k, int M) {
+void proposal_apply(Ctx& c, int k, int M, bool slots_ready) {
   trace(c, "update.proposal");
   // the gate listed the pairs (count at scal[19]) and the per-instance counts
-  prepare_slots(c, k);
+  if (slots_ready) GLMB_HIP(hipStreamWaitEvent(c.s, c.fork[2], 0));
+  else prepare_slots(c, k, c.s);
   score_pairs(c, -1, M, true);
 }
 

@@ -1491,23 +1491,17 @@ __global__ void k_def_flags(int U, const int32_t* first, int32_t* fl) {
 // log(e^a + e^b); the log of 1 + x with x in (0, 1] loses at most 6e-8 absolute against log1p
 __device__ __forceinline__ float lse2(float a, float b) { return fmaxf(a, b) + __logf(1.0f + __expf(-fabsf(a - b))); }
 
-// per detection: the log of its removed mass shifted by the detection's cell offset c_i
-// (-inf without removed mass)
-__global__ void k_ru_lr(int M, const uint32_t* cmax, const unsigned long long* rmass, float* lr) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < M) lr[i] = rmass[i] == 0ull ? -INFINITY : logf((float)((double)rmass[i] / kRemovedScale)) - o2f(cmax[i]);
-}
-
 // lzr[h] = lzprime[h] + sum_i (log(e^{l_hi} + R_i) - l_hi) over the detections with removed
-// mass.  Hypothesis 0's terms T0_i (k_ru_t0) and their FP64 total stand for every untouched
-// cell; one wave per hypothesis then exchanges T0_i for its own term on its touched cells
-// (lanes over the touched-set words, bits in ascending order), fixed butterfly.
-__global__ __launch_bounds__(256) void k_ru_t0(int M, const float* lserel0, const float* lr, float* t0,
-                                               double* tot) {
+// mass R_i.  One workgroup first: per detection lr_i = log R_i - c_i (-inf without removed
+// mass; R_i from the fixed-point sums) and hypothesis 0's terms T0_i, with their FP64 total,
+// which stand for every untouched cell.
+__global__ __launch_bounds__(256) void k_ru_t0(int M, const uint32_t* cmax, const unsigned long long* rmass,
+                                               const float* lserel0, float* lr, float* t0, double* tot) {
   __shared__ double red[4];
   double acc = 0.0;
   for (int i = threadIdx.x; i < M; i += blockDim.x) {
-    const float r = lr[i];
+    const float r = rmass[i] == 0ull ? -INFINITY : logf((float)((double)rmass[i] / kRemovedScale)) - o2f(cmax[i]);
+    lr[i] = r;
     const float ls = lserel0[i];
     const float v = r == -INFINITY ? 0.0f : lse2(ls, r) - ls;
     t0[i] = v;
@@ -1518,30 +1512,55 @@ __global__ __launch_bounds__(256) void k_ru_t0(int M, const float* lserel0, cons
   __syncthreads();
   if (threadIdx.x == 0) *tot = red[0] + red[1] + red[2] + red[3];
 }
-__global__ __launch_bounds__(256) void k_ru_restore(int H, int M, const float* lzprime, CellView cv,
-                                                    const float* lr, const float* t0, const double* tot,
-                                                    float* lzr) {
-  const int h = (int)((blockIdx.x * (size_t)blockDim.x + threadIdx.x) / kWave);
-  if (h >= H) return;
-  float acc = 0.0f;
-  if (h > 0)
-    for (int x = lane_id(); x < cv.W; x += kWave) {
-      const size_t wi = (size_t)h * cv.W + x;
-      uint32_t word = cv.tbits[wi];
-      size_t pos = (size_t)h * M + cv.tpre[wi];
-      while (word) {
-        const int i = 32 * x + __ffs(word) - 1;
-        word &= word - 1u;
-        const float r = lr[i];
-        if (r != -INFINITY) {
-          const float ls = cv.lserel[pos];
-          acc += (lse2(ls, r) - ls) - t0[i];
+// Then one wave per hypothesis exchanges T0_i for its own term on its touched cells: the
+// touched cells lie at h M + j in ascending detection order, so the wave lists their detection
+// indices in LDS (a chunk of 64 touched-set words at a time) and its lanes take the cells in
+// turn, fixed butterfly.  (A last-workgroup normaliser here measured slower than its own
+// launch: the agent-scope fences it needs write back every XCD's L2.)
+constexpr int kRestoreT = 256;
+__global__ __launch_bounds__(kRestoreT) void k_ru_restore(int H, int M, const float* lzprime, CellView cv,
+                                                          const float* lr, const float* t0, const double* tot,
+                                                          float* lzr) {
+  __shared__ uint16_t list[kRestoreT / kWave][kWave * 32];
+  const int w = threadIdx.x / kWave, lane = lane_id();
+  const int h = blockIdx.x * (kRestoreT / kWave) + w;
+  if (h < H) {
+    float acc = 0.0f;
+    if (h > 0) {
+      int nbase = 0;  // touched cells before the chunk
+      for (int x0 = 0; x0 < cv.W; x0 += kWave) {
+        const int x = x0 + lane;
+        const uint32_t word = x < cv.W ? cv.tbits[(size_t)h * cv.W + x] : 0u;
+        const int c = __popc(word);
+        int incl = c;  // inclusive scan of the counts over the lanes
+        for (int d = 1; d < kWave; d <<= 1) {
+          const int y = __shfl_up(incl, d, kWave);
+          if (lane >= d) incl += y;
         }
-        ++pos;
+        const int tot_c = __shfl(incl, kWave - 1, kWave);
+        uint32_t b = word;
+        for (int q = incl - c; b; ++q) {
+          list[w][q] = (uint16_t)(32 * x + __ffs(b) - 1);
+          b &= b - 1u;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int j = lane; j < tot_c; j += kWave) {
+          const int i = list[w][j];
+          const float r = lr[i];
+          if (r != -INFINITY) {
+            const float ls = cv.lserel[(size_t)h * M + nbase + j];
+            acc += (lse2(ls, r) - ls) - t0[i];
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        nbase += tot_c;
       }
     }
-  for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_xor(acc, d, kWave);
-  if (lane_id() == 0) lzr[h] = lzprime[h] + (float)(*tot + (double)acc);
+    for (int d = kWave / 2; d > 0; d >>= 1) acc += __shfl_xor(acc, d, kWave);
+    if (lane == 0) lzr[h] = lzprime[h] + (float)(*tot + (double)acc);
+  }
 }
 // one workgroup: out = log sum_h exp(v[h])
 __global__ __launch_bounds__(1024) void k_lse_block(int H, const float* v, float* out) {
@@ -1886,6 +1905,16 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   // ---- U0 + U1: detections, gate, scores
   trace(c, "update.begin", H, M);
   c.mark(0);
+  // the learned proposal's label inputs beside the gate (joined before the pairs are scored)
+  bool slots_ready = false;
+  if (c.prop_on && M > 0 && c.fork_ok) {
+    c.side_ready();
+    GLMB_HIP(hipEventRecord(c.fork[0], s));
+    GLMB_HIP(hipStreamWaitEvent(c.s2, c.fork[0], 0));
+    prepare_slots(c, k, c.s2);
+    GLMB_HIP(hipEventRecord(c.fork[2], c.s2));
+    slots_ready = true;
+  }
   gate_scores(c, zin, M, c.prop_on && M > 0);
   int32_t* scal = c.scal.as<int32_t>();
   uint32_t* errf = (uint32_t*)scal;
@@ -1904,7 +1933,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   float2* z = c.z.as<float2>();
   uint32_t* cmax = c.cmax.as<uint32_t>();
   float* phi = c.phi.as<float>();
-  if (c.prop_on && M > 0) proposal_apply(c, k, M);
+  if (c.prop_on && M > 0) proposal_apply(c, k, M, slots_ready);
   gate_lists(c, M);
   const int LW = c.LW;
   int32_t* loff = c.loff.as<int32_t>();
@@ -1919,6 +1948,44 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   const CellView cv = cells_of(c, M);
   float* bprime = c.bprime.as<float>();
   float* lzprime = c.lzprime.as<float>();
+
+  // ---- the births' clutter probabilities r_U(z_i) need only U2's results: on the side
+  // stream, beside the selection and the materialisation (joined before the births)
+  float* ru = need<float>(c.diag_ru, M + 1);
+  auto launch_ru = [&](hipStream_t st) {
+    const int nch = cdiv(H, kRuChunk);
+    float* part = need<float>(c.ru_part, (int64_t)nch * M);
+    const float* lzb = lzprime;
+    const float* Lb = lz;
+    float* lrm = nullptr;
+    if (c.prop_on) {  // hypothesis masses with the removed pairs restored, and their normaliser
+      // [H + 1 masses and normaliser | M removed masses | M terms of hypothesis 0 | FP64 total]
+      const int64_t o_tot = ((int64_t)H + 1 + 2 * (int64_t)M + 1) & ~(int64_t)1;
+      float* lzr = need<float>(c.lz_r, o_tot + 2);
+      lrm = lzr + H + 1;
+      float* t0r = lrm + M;
+      double* tot0 = (double*)(lzr + o_tot);
+      GLMB_LAUNCH(k_ru_t0, 1, 256, 0, st, M, cmax, (const unsigned long long*)c.rmass.as<unsigned long long>(),
+                  cv.lserel, lrm, t0r, tot0);
+      GLMB_LAUNCH(k_ru_restore, cdiv(H, kRestoreT / kWave), kRestoreT, 0, st, H, M, lzprime, cv, (const float*)lrm,
+                  (const float*)t0r, (const double*)tot0, lzr);
+      GLMB_LAUNCH(k_lse_block, 1, 1024, 0, st, H, lzr, lzr + H);
+      lzb = lzr;
+      Lb = lzr + H;
+    }
+    hipLaunchKernelGGL(k_ru_part, dim3(cdiv(M, T), nch), dim3(T), 0, st, H, M, lzb, Lb, cv, cmax, lgk, lrm, part);
+    GLMB_HIP(hipGetLastError());
+    GLMB_LAUNCH(k_ru_final, cdiv((int64_t)M * kWave, T), T, 0, st, M, nch, part, ru);
+  };
+  bool ru_forked = false;
+  if (M > 0 && c.fork_ok) {
+    c.side_ready();
+    GLMB_HIP(hipEventRecord(c.fork[1], s));
+    GLMB_HIP(hipStreamWaitEvent(c.s2, c.fork[1], 0));
+    launch_ru(c.s2);
+    GLMB_HIP(hipEventRecord(c.fork[3], c.s2));
+    ru_forked = true;
+  }
 
   const int K = p.h_max;
   const bool sampled = c.sample_hup > 0;
@@ -2216,32 +2283,9 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   // ---- births for the next scan
   trace(c, "update.births");
   c.mark(4);
-  float* ru = need<float>(c.diag_ru, M + 1);
   if (M > 0) {
-    const int nch = cdiv(H, kRuChunk);
-    float* part = need<float>(c.ru_part, (int64_t)nch * M);
-    const float* lzb = lzprime;
-    const float* Lb = lz;
-    float* lrm = nullptr;
-    if (c.prop_on) {  // hypothesis masses with the removed pairs restored, and their normaliser
-      // [H + 1 masses and normaliser | M removed masses | M terms of hypothesis 0 | FP64 total]
-      const int64_t o_tot = ((int64_t)H + 1 + 2 * (int64_t)M + 1) & ~(int64_t)1;
-      float* lzr = need<float>(c.lz_r, o_tot + 2);
-      lrm = lzr + H + 1;
-      float* t0r = lrm + M;
-      double* tot0 = (double*)(lzr + o_tot);
-      GLMB_LAUNCH(k_ru_lr, cdiv(M, T), T, 0, s, M, cmax, c.rmass.as<unsigned long long>(), lrm);
-      GLMB_LAUNCH(k_ru_t0, 1, 256, 0, s, M, cv.lserel, (const float*)lrm, t0r, tot0);
-      GLMB_LAUNCH(k_ru_restore, cdiv((int64_t)H * kWave, T), T, 0, s, H, M, lzprime, cv, (const float*)lrm,
-                  (const float*)t0r, (const double*)tot0, lzr);
-      GLMB_LAUNCH(k_lse_block, 1, 1024, 0, s, H, lzr, lzr + H);
-      lzb = lzr;
-      Lb = lzr + H;
-    }
-    hipLaunchKernelGGL(k_ru_part, dim3(cdiv(M, T), nch), dim3(T), 0, s, H, M, lzb, Lb, cv, cmax, lgk,
-                       lrm, part);
-    GLMB_HIP(hipGetLastError());
-    GLMB_LAUNCH(k_ru_final, cdiv((int64_t)M * kWave, T), T, 0, s, M, nch, part, ru);
+    if (ru_forked) GLMB_HIP(hipStreamWaitEvent(s, c.fork[3], 0));
+    else launch_ru(s);
   }
   int32_t* member = need<int32_t>(c.ru, (int64_t)M + 1);
   DBirth* nb = (DBirth*)need<uint8_t>(c.births2, (int64_t)(M + 1) * sizeof(DBirth));
