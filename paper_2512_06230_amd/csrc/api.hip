@@ -251,7 +251,7 @@ glmb_status glmb_create(const glmb_params* p, int device, void* stream, glmb_ctx
   if (const char* ss = std::getenv("GLMB_SIDE_STREAM")) x->c.fork_ok = std::strcmp(ss, "0") != 0;
   if (const char* hb = std::getenv("GLMB_REC_HASH_BITS")) {
     const int bits = std::atoi(hb);
-    if (bits >= 1 && bits < 32) x->c.rec_hash_mask = (1u << bits) - 1u;
+    if (bits >= 1 && bits < 16) x->c.rec_hash_mask = (1u << bits) - 1u;
   }
   glmb_status st = guarded(x, [&](Ctx& c) {
     glmb::noalloc_setup(c.device);  // the device is current here

@@ -82,7 +82,9 @@ struct Ctx {
   bool coop_ok = true;  // cooperative launches allowed (they run one at a time on a device)
   bool force_multi = false;  // every search on the host-driven multi-kernel levels (GLMB_SEARCH_FORM=multi)
   int LW = 1;  // detection-set mask width (32-bit words) of the last gate
-  uint32_t rec_hash_mask = 0xffffffffu;  // fingerprint bits of the (instance, detection set) records
+  // fingerprint bits of the (instance, detection set) records (16 at most: records of one instance
+  // with equal fingerprints are told apart by full comparison)
+  uint32_t rec_hash_mask = 0xffffu;
   DevBuf rec_lead;                       // collision path: leader position of every record
   // ---- sampled children (the paper's generator) instead of the exact selection
   int32_t sample_hup = 0;      // association maps drawn per hypothesis (0: exact top-H_max)

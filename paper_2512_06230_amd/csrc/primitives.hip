@@ -174,7 +174,7 @@ void scan_excl64(const int64_t* in, int64_t* out, int n, int64_t* total, DevBuf&
 constexpr int kSortT = 256;
 constexpr int kSortRBig = 8;    // rounds of kSortT items per tile for large inputs
 constexpr int kSortRSmall = 2;  // ... and for small ones (more tiles in flight)
-constexpr int kSortFuseTiles = 32;
+constexpr int kSortFuseTiles = 64;
 
 __global__ __launch_bounds__(kSortT) void k_sort_hist(const uint64_t* keys, int n, int shift, int nb, int rounds,
                                                       int32_t* hist) {

@@ -1252,7 +1252,8 @@ __global__ void k_rec_keys(int n, int LW, uint32_t hmask, const int32_t* ru, con
                            uint32_t* vals) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
-  keys[k] = ((uint64_t)(uint32_t)ru[k] << 32) | (mask_hash(rm + (size_t)k * LW, LW) & hmask);
+  const uint32_t hh = mask_hash(rm + (size_t)k * LW, LW);
+  keys[k] = ((uint64_t)(uint32_t)ru[k] << 16) | ((hh ^ (hh >> 16)) & hmask & 0xFFFFu);
   vals[k] = (uint32_t)k;
 }
 __device__ __forceinline__ bool rec_equal(int LW, const int32_t* ru, const uint32_t* rm, uint32_t a, uint32_t b) {
@@ -2211,7 +2212,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   GLMB_LAUNCH(k_rec_keys, cdiv(R, T), T, 0, s, R, LW, c.rec_hash_mask, rec_u, rec_m, rk, rv);
   int ub = 0;
   while ((1 << ub) < U) ++ub;
-  sort_pairs(rk, rv, R, 0, 32 + ((ub + 7) / 8) * 8, c.tk, c.tv, c.tmp, s);
+  sort_pairs(rk, rv, R, 0, 16 + ((ub + 7) / 8) * 8, c.tk, c.tv, c.tmp, s);
   int32_t* rfl = need<int32_t>(c.flags, R + 1);
   int32_t* rpre = need<int32_t>(c.pre, R + 1);
   int32_t* ncoll = scal + 24;  // tot (scal + 12) and this count come back in one round trip
