@@ -12,11 +12,6 @@
 
 namespace glmb {
 
-__global__ void k_pfill(int32_t* p, int n, int32_t v) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = v;
-}
-
 __global__ void k_kpredict(DInst* inst, int U, CV cv) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u >= U) return;
@@ -163,7 +158,7 @@ __global__ __launch_bounds__(64) void k_prows(int n, int NS, int NB, int stride,
 __global__ void k_hash_keys(int n, const uint64_t* hash, uint64_t* keys, uint32_t* vals) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
-  keys[c] = hash[c] >> 40;
+  keys[c] = hash[c] >> 48;
   vals[c] = (uint32_t)c;
 }
 
@@ -429,7 +424,7 @@ void stage_predict(Ctx& c, int k) {
   uint64_t* hk = need<uint64_t>(c.keys, n + 1);
   uint32_t* hv = need<uint32_t>(c.vals32, n + 1);
   GLMB_LAUNCH(k_hash_keys, cdiv(n, T), T, 0, s, n, hash, hk, hv);
-  sort_pairs(hk, hv, n, 0, 24, c.tk, c.tv, c.tmp, s);
+  sort_pairs(hk, hv, n, 0, 16, c.tk, c.tv, c.tmp, s);  // 16 hash bits: rows of a run are compared in full
   int32_t* leader = need<int32_t>(c.first, 4 * (int64_t)n + 4);
   int32_t* islead = leader + n + 1;
   int32_t* mrank = islead + n + 1;
@@ -446,7 +441,8 @@ void stage_predict(Ctx& c, int k) {
   while (((int64_t)1 << rb) < (int64_t)nodes + 1) ++rb;
   rb = std::min(32, (rb + 7) / 8 * 8);
   GLMB_LAUNCH(k_lead_keys, cdiv(n, T), T, 0, s, n, rb, islead, lpre, mval, mrank, lk, lv);
-  sort_pairs(lk, lv, nh, 0, 32 + rb, c.tk, c.tv, c.tmp, s);
+  // without merged children the leaders are every child, in rank order already
+  if (nh < n) sort_pairs(lk, lv, nh, 0, 32 + rb, c.tk, c.tv, c.tmp, s);
   // ---- normalise, garbage-collect labels and instances, final rows
   trace(c, "predict.gc", nh);
   float* nlw = need<float>(c.logw2, nh + 1);
@@ -471,7 +467,7 @@ void stage_predict(Ctx& c, int k) {
   int32_t* frows = need<int32_t>(c.prev_rows, (int64_t)nh * NS2 + 1);
   int32_t* fnt = need<int32_t>(c.hp_map, nh + 1);
   int32_t* fpar = need<int32_t>(c.hparent, nh + 1);
-  GLMB_LAUNCH(k_pfill, cdiv((int64_t)nh * NS2, T), T, 0, s, frows, nh * NS2, -1);
+  // every (hypothesis, kept slot) entry is written: a kept slot is used, absent tracks as -1
   GLMB_LAUNCH(k_final_rows, cdiv((int64_t)nh * W2, T), T, 0, s, nh, W2, NS2, lv, crow, spre, sused, upre, frows);
   GLMB_LAUNCH(k_final_meta, cdiv(nh, T), T, 0, s, nh, lv, ntc, parc, mrep, fnt, fpar);
   DInst* ninst = (DInst*)need<uint8_t>(c.inst2, (int64_t)(Unew + 1) * sizeof(DInst));
