@@ -84,6 +84,7 @@ struct HostStage {
   uint32_t* h = nullptr;  // host address
   uint32_t* d = nullptr;  // the same memory as the device addresses it
   size_t words = 0;
+  uint32_t seq = 0;       // sequence number of the last round trip (word 0, the data follow; never 0)
   void reserve(size_t n) {
     if (n <= words) return;
     size_t nw = words ? words : 1024;
@@ -100,6 +101,7 @@ struct HostStage {
     h = (uint32_t*)q;
     d = (uint32_t*)dq;
     words = nw;
+    std::memset(h, 0, nw * sizeof(uint32_t));  // no stale word can equal a later sequence number
   }
   void release() {
     if (h) (void)hipHostFree(h);
@@ -112,9 +114,9 @@ struct ReadPiece {
   const void* src;
   int64_t words;
 };
-// One host round trip: the pieces are copied, in order and packed, into st by one kernel on s,
-// then the host waits for s.  Returns the host address of the first piece's first word.  At most
-// eight pieces.
+// One host round trip: the pieces are copied, in order and packed, into st (from word 1) by one
+// kernel on s, which then writes a new sequence number to word 0; the host waits for that number
+// (or for s).  Returns the host address of the first piece's first word.  At most eight pieces.
 const uint32_t* read_back(HostStage& st, hipStream_t s, std::initializer_list<ReadPiece> pieces);
 
 template <class T> inline T* need(DevBuf& b, int64_t n) {

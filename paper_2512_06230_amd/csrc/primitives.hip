@@ -2,10 +2,13 @@
 // and a two-pass histogram bound on the K-th largest float.
 #include "common.hpp"
 
+#include <chrono>
+
 namespace glmb {
 
 // ============================================================================ read back
 constexpr int kReadMax = 8;
+constexpr int kReadSpinUs = 2000;  // host spin before a stream wait takes over
 struct ReadList {
   const uint32_t* src[kReadMax];
   int32_t n[kReadMax];
@@ -13,32 +16,52 @@ struct ReadList {
   int32_t cnt;
 };
 
-__global__ __launch_bounds__(256) void k_read_back(ReadList l, uint32_t* dst) {
-  const int stride = gridDim.x * blockDim.x;
+// One workgroup copies the pieces to dst[1..], then every thread's stores are made visible to
+// the host (system-scope fence) before thread 0 writes the sequence number to dst[0], a word that
+// never holds data: the host may wait for that word instead of for the stream.
+constexpr int kReadT = 1024;
+__global__ __launch_bounds__(kReadT) void k_read_back(ReadList l, uint32_t* dst, uint32_t seq) {
   for (int p = 0; p < l.cnt; ++p) {
     const uint32_t* src = l.src[p];
-    uint32_t* out = dst + l.off[p];
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < l.n[p]; j += stride) out[j] = src[j];
+    uint32_t* out = dst + 1 + l.off[p];
+    for (int j = threadIdx.x; j < l.n[p]; j += kReadT) out[j] = src[j];
   }
+  __threadfence_system();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(dst, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 const uint32_t* read_back(HostStage& st, hipStream_t s, std::initializer_list<ReadPiece> pieces) {
   if (pieces.size() > (size_t)kReadMax) throw Error{GLMB_E_STATE, "read_back: more than eight pieces"};
   ReadList l{};
-  int64_t tot = 0, mx = 0;
+  int64_t tot = 0;
   for (const ReadPiece& p : pieces) {
     const int64_t w = std::max<int64_t>(p.words, 0);
     l.src[l.cnt] = (const uint32_t*)p.src;
     l.n[l.cnt] = (int32_t)w;
     l.off[l.cnt] = (int32_t)tot;
     tot += w;
-    mx = std::max(mx, w);
     ++l.cnt;
   }
-  st.reserve((size_t)std::max<int64_t>(tot, 1));
-  if (tot > 0) GLMB_LAUNCH(k_read_back, std::min(64, cdiv(mx, 256)), 256, 0, s, l, st.d);
-  GLMB_HIP(stream_sync(s));
-  return st.h;
+  st.reserve((size_t)tot + 1);
+  if (++st.seq == 0) st.seq = 1;
+  const uint32_t seq = st.seq;
+  GLMB_LAUNCH(k_read_back, 1, kReadT, 0, s, l, st.d, seq);
+  // wait for the sequence word (a spin on pinned memory answers sooner than a stream wait);
+  // after a while, or if the word does not come, wait for the stream, which also reports
+  // any device error
+  ++g_stream_syncs;
+  const auto t0 = std::chrono::steady_clock::now();
+  bool seen = false;
+  while (!(seen = __atomic_load_n(st.h, __ATOMIC_ACQUIRE) == seq)) {
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(kReadSpinUs)) break;
+  }
+  if (!seen) {
+    GLMB_HIP(hipStreamSynchronize(s));
+    if (__atomic_load_n(st.h, __ATOMIC_ACQUIRE) != seq)
+      throw Error{GLMB_E_DEVICE, "read_back: the gather kernel finished without its sequence word"};
+  }
+  return st.h + 1;
 }
 
 // ============================================================================ scan
