@@ -196,6 +196,8 @@ void upload_state(Ctx& c, const std::vector<std::pair<int32_t, int32_t>>& labs, 
   c.nhyp = H;
   c.nbirth = (int)births.size();
   c.birth_lab = blab;
+  c.birth_host = births;
+  c.birth_host_ok = true;
   auto up = [&](glmb::DevBuf& b, const void* src, size_t bytes) {
     b.reserve(std::max<size_t>(bytes, 64));
     if (bytes) GLMB_HIP(hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, s));

@@ -64,6 +64,8 @@ struct Ctx {
   DevBuf logw, ntrk, rows, hparent;
   DevBuf logw2, ntrk2, rows2;  // double buffers
   DevBuf births, births2;      // DBirth (the update writes the next scan's into births2)
+  std::vector<DBirth> birth_host;  // host copy of the pending births, when birth_host_ok
+  bool birth_host_ok = false;
 
   // ---- last update (for diagnostics / exports) ----
   int last_H = 0, last_M = 0, last_stride = 0;

@@ -319,7 +319,9 @@ void stage_predict(Ctx& c, int k) {
   const float dt_ = (float)std::fabs(ly - ln);
   static_assert(sizeof(DBirth) % 4 == 0, "whole words");
   std::vector<DBirth> hb(NB);
-  if (NB) {
+  if (c.birth_host_ok && (int)c.birth_host.size() == NB) {
+    hb = c.birth_host;  // read back with the last update's statistics, or imported
+  } else if (NB) {
     const uint32_t* h = read_back(c.sb.hs, s, {{c.births.p, (int64_t)NB * (int64_t)(sizeof(DBirth) / 4)}});
     std::memcpy(hb.data(), h, (size_t)NB * sizeof(DBirth));
   }
@@ -394,13 +396,15 @@ void stage_predict(Ctx& c, int k) {
                 (const int32_t*)nullptr, icount, (float*)nullptr, (int32_t*)nullptr);
     int32_t* itoff = need<int32_t>(c.it_off, H + 1);
     scan_excl(icount, itoff, H, itoff + H, c.tmp, s);
-    const int32_t nitem = (int32_t)read_back(c.sb.hs, s, {{itoff + H, 1}})[0];
-    float* itd = need<float>(c.it_delta, (int64_t)nitem + 1);
-    int32_t* itg = need<int32_t>(c.it_group, (int64_t)nitem + 1);
+    // a parent has at most one item per present track and per birth: the item lists are
+    // sized for that, so their total needs no round trip
+    const int64_t icap = (int64_t)H * (SW + nbs) + 1;
+    float* itd = need<float>(c.it_delta, icap);
+    int32_t* itg = need<int32_t>(c.it_group, icap);
     GLMB_LAUNCH(k_pitems, H, 256, 0, s, H, nbs, nlt, SW, c.rows.as<int32_t>(), V, dt_, dbs, dbg, t0,
                 (const int32_t*)itoff, icount, itd, itg);
     // ---- exact selection
-    trace(c, "predict.select", nitem);
+    trace(c, "predict.select", H);
     SelectIn si{H, V, itoff, itd, itg, p.h_max, t0, &c.sel_multi[0], c.coop_ok, c.force_multi};
     Selected sel{};
     std::string serr;
@@ -487,6 +491,8 @@ void stage_predict(Ctx& c, int k) {
   c.ninst = Unew;
   c.nhyp = nh;
   c.nbirth = 0;
+  c.birth_host.clear();
+  c.birth_host_ok = true;
   c.birth_lab.clear();
 }
 

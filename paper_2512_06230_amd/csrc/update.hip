@@ -2296,8 +2296,16 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   // ---- statistics and swap in the new state
   trace(c, "update.stats");
   c.mark(5);
-  int32_t hs[19];  // scalars, the error flags (scal[0]) among them: one round trip
-  std::memcpy(hs, read_back(c.sb.hs, s, {{scal, 19}}), sizeof(hs));
+  // scalars (the error flags, scal[0], among them) and the first births: one round trip; the
+  // prediction then needs no read of the births when there are at most kBirthHost of them
+  constexpr int kBirthHost = 64;
+  const int nbh = std::min(M + 1, kBirthHost);
+  int32_t hs[19];
+  const uint32_t* hb = read_back(c.sb.hs, s, {{scal, 19}, {nb, (int64_t)nbh * (int64_t)(sizeof(DBirth) / 4)}});
+  std::memcpy(hs, hb, sizeof(hs));
+  c.birth_host_ok = hs[13] >= 0 && hs[13] <= nbh;
+  c.birth_host.resize(c.birth_host_ok ? hs[13] : 0);
+  if (c.birth_host_ok && hs[13] > 0) std::memcpy(c.birth_host.data(), hb + 19, (size_t)hs[13] * sizeof(DBirth));
   check_err_bits((uint32_t)hs[0]);
   uint64_t ng, no;
   std::memcpy(&ng, hs + 2, 8);
