@@ -582,38 +582,18 @@ __global__ __launch_bounds__(256) void k_assoc(int H, int M, int stride, int nq,
       xo += (double)ref_opts[i];
     }
   } else {
-    // lengths of the changed labels' detection lists, their prefix (wave scan) and total
-    int len = 0;
-    if (lane < nd) {
-      const int s = ds[lane];
-      dof[lane] = loff[s];
-      len = llen[s];
-    }
-    int x = len;
-    for (int d = 1; d < kWave; d <<= 1) {
-      const int y = __shfl_up(x, d, kWave);
-      if (lane >= d) x += y;
-    }
-    if (lane < nd) dpf[lane + 1] = x;
-    if (lane == 0) dpf[0] = 0;
-    const int P = nd > 0 ? __shfl(x, nd - 1, kWave) : 0;
-    for (int w = lane; w < W; w += kWave) touched[w] = 0u;
     const int nst = nd < nq ? nd : nq;
     for (int e = lane; e < nst * W; e += kWave) {
       const int q = e / W;
       stage[e] = lbits[(size_t)ds[q] * W + (e - q * W)];
     }
     wave_lds_sync();
-    // touched detections: every (changed label, gated detection) pair, all lanes
-    // (the pair's label by a fixed-length binary search over the length prefix, so that the
-    // detection loads of successive pairs do not wait on one another)
-    for (int p = lane; p < P; p += kWave) {
-      int lo = 0;  // largest q < nd with dpf[q] <= p
-#pragma unroll
-      for (int step = kAssocNd / 2; step > 0; step >>= 1)
-        if (lo + step < nd && dpf[lo + step] <= p) lo += step;
-      const int i = lmeas[dof[lo] + (p - dpf[lo])];
-      atomicOr(&touched[i >> 5], 1u << (i & 31));
+    // touched detections: the union of the changed labels' gate words (a label's detection
+    // list holds exactly the bits of its gate words), lanes over the words
+    for (int w = lane; w < W; w += kWave) {
+      uint32_t acc = 0u;
+      for (int q = 0; q < nd; ++q) acc |= q < nst ? stage[q * W + w] : lbits[(size_t)ds[q] * W + w];
+      touched[w] = acc;
     }
     wave_lds_sync();
     // touched list, ascending
