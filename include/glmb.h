@@ -104,14 +104,15 @@ typedef struct {
   /* stage durations of the last update from HIP events on the context's stream (ms):
    * [0] gate + score (through the per-label lists and hypothesis 0's cells), [1] the
    * per-(hypothesis, detection) association kernel of hypotheses 1..H-1 alone, [2] cut bound + deviation items + selection, [3] materialise + Kalman,
-   * [4] births, [5] whole update */
+   * [4] births (with the side stream, the clutter probabilities run beside [2] and [3], and
+   * [4] is the wait for them and the clustering), [5] whole update */
   float stage_ms[6];
-  /* (instance, detection set) records whose 32-bit fingerprint equalled that of a different
+  /* (instance, detection set) records whose 16-bit fingerprint equalled that of a different
    * set of the same instance; such runs are resolved by full comparison (results unchanged).
-   * The environment variable GLMB_REC_HASH_BITS (1..32, read by glmb_create) narrows the
+   * The environment variable GLMB_REC_HASH_BITS (1..15, read by glmb_create) narrows the
    * fingerprint so that this path can be exercised. */
   int32_t rec_collisions;
-  int32_t host_syncs;       /* host-device synchronisations made by the update            */
+  int32_t host_syncs;       /* host round trips (waits for the device) made by the update  */
   int32_t search_form;      /* selection search of the update: 0 one workgroup, 1 one cooperative
                                whole-GPU launch, 2 host-driven levels of whole-GPU kernels,
                                3 sampled maps (glmb_set_sampling)                           */
@@ -122,7 +123,13 @@ const char* glmb_status_string(glmb_status s);
 const char* glmb_last_error(const glmb_ctx* ctx);
 
 /* Create a filter on HIP device `device` using `hip_stream` (a hipStream_t, or NULL for the
- * null stream) for every launch.  The context holds one hypothesis with no tracks. */
+ * null stream) for every launch.  The context holds one hypothesis with no tracks.  The update
+ * also uses a second stream of its own (created on first use, default priority) for work that
+ * overlaps the main chain (the births' clutter probabilities, the learned proposal's label
+ * inputs), joined by events before its results are read; the environment variable
+ * GLMB_SIDE_STREAM=0 (read here) keeps every stage on `hip_stream`.  Host round trips wait
+ * for a word the device writes to pinned host memory, spinning briefly before a stream
+ * wait. */
 glmb_status glmb_create(const glmb_params* params, int device, void* hip_stream, glmb_ctx** out);
 glmb_status glmb_destroy(glmb_ctx* ctx);
 
