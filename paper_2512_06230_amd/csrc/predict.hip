@@ -452,9 +452,11 @@ void stage_predict(Ctx& c, int k) {
   float* nlw = need<float>(c.logw2, nh + 1);
   GLMB_LAUNCH(k_pnorm, 1, 1024, 0, s, nh, lv, mval, nlw);
   const int U2 = U + NB;
-  int32_t* sused = need<int32_t>(c.flags, (int64_t)W2 + U2 + 2);
+  // zeroed as whole 16-byte words (one fill kernel)
+  const size_t nused = ((size_t)W2 + U2 + 2 + 3) & ~(size_t)3;
+  int32_t* sused = need<int32_t>(c.flags, (int64_t)nused);
   int32_t* uused = sused + W2 + 1;
-  GLMB_HIP(hipMemsetAsync(sused, 0, ((size_t)W2 + U2 + 2) * sizeof(int32_t), s));
+  GLMB_HIP(hipMemsetAsync(sused, 0, nused * sizeof(int32_t), s));
   GLMB_LAUNCH(k_used, cdiv((int64_t)nh * W2, T), T, 0, s, nh, W2, lv, crow, sused, uused);
   int32_t* spre = need<int32_t>(c.lpre, (int64_t)W2 + U2 + 4);
   int32_t* upre = spre + W2 + 2;

@@ -1238,7 +1238,8 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
                                                // [24..28] one-workgroup search
   float* t = (float*)(scal + 8);               // current threshold
   float* t2 = (float*)(scal + 9);
-  GLMB_HIP(hipMemcpyAsync(t, in.t0, sizeof(float), hipMemcpyDeviceToDevice, s));
+  // t is written by every search form (the one-workgroup and cooperative kernels at their end,
+  // the host-driven levels from t0 before their roots)
   int32_t hs[8];
   auto read = [&](int n) { std::memcpy(hs, read_back(b.hs, s, {{scal, n}}), n * sizeof(int32_t)); };
   // Small searches run in one workgroup (no host round trip per level).  A search that

@@ -2304,7 +2304,9 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   std::swap(c.ntrk, c.ntrk2);
   std::swap(c.logw, c.logw2);
   std::swap(c.births, c.births2);
-  {
+  if (hpar == c.child_par.as<int32_t>()) {
+    std::swap(c.hparent, c.child_par);  // the children's parents become the state's (no copy)
+  } else {
     int32_t* hp = need<int32_t>(c.hparent, nkept + 1);
     GLMB_HIP(hipMemcpyAsync(hp, hpar, (size_t)nkept * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   }
