@@ -128,7 +128,7 @@ void stage_truncate(Ctx& c, int hmax, float tau);
 // with pairs: also the gated pairs of the learned update (c.pu / c.pi, count at scal[19]) and
 // every instance's gated count (c.pcnt)
 void gate_scores(Ctx& c, const float* z, int M, bool pairs = false);
-void gate_lists(Ctx& c, int M);
+void gate_lists(Ctx& c, int M, bool defer = false);
 void assoc_norm(Ctx& c, int M);
 // proposal (proposal.hip)
 constexpr int kNFeat = 6, kNHid = 64, kNParam = 4673, kMaxThr = 16;

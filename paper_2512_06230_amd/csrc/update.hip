@@ -135,7 +135,7 @@ __global__ void k_inst_beg(const DInst* inst, int U, int nslot, int32_t* beg) {
 
 // per label: union of its instances' gate bits, prefix popcounts, list length
 __global__ __launch_bounds__(256) void k_label_bits(const uint32_t* gbits, const int32_t* beg, int W, uint32_t* lbits,
-                                                    int32_t* lpre, int32_t* llen, uint32_t* errf) {
+                                                    int32_t* lpre, int32_t* llen, uint32_t* errf, int32_t* maxlen) {
   __shared__ int32_t pc[1024];
   const int s = blockIdx.x;
   for (int w = threadIdx.x; w < W; w += blockDim.x) {
@@ -152,6 +152,7 @@ __global__ __launch_bounds__(256) void k_label_bits(const uint32_t* gbits, const
       run += pc[w];
     }
     llen[s] = run;
+    if (run) atomicMax(maxlen, run);
   }
 }
 
@@ -1706,6 +1707,23 @@ void check_err_bits(uint32_t e) {
 }
 }  // namespace
 
+// Lists sized for every (label, detection) pair when that stays below kListsCap entries.
+constexpr int64_t kListsCap = int64_t(1) << 26;
+// mask width in words for a longest list of mx detections, with the LDS the mask kernels need
+static int mask_width(int NS, int mx) {
+  const int LW = std::max(1, (mx + 31) / 32);
+  const size_t lds_need = (size_t)NS * LW * sizeof(uint32_t);
+  if (lds_need > 160 * 1024)
+    throw Error{GLMB_E_CAPACITY, "labels x detection-set mask width exceed the 160 KB LDS of a workgroup"};
+  if (lds_need > 64 * 1024) {
+    GLMB_HIP(hipFuncSetAttribute((const void*)k_default_masks, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds_need));
+    GLMB_HIP(hipFuncSetAttribute((const void*)k_exceptions, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds_need));
+  }
+  return LW;
+}
+
 // U0 + U1 scores: detections, gate bits and Eq. 2 entries of every (instance, detection) pair.
 // Scalars: see stage_update.
 void gate_scores(Ctx& c, const float* zin, int M, bool pairs) {
@@ -1751,8 +1769,11 @@ void gate_scores(Ctx& c, const float* zin, int M, bool pairs) {
 }
 
 // U1 lists from the gate bits: per-label gated detection lists and per-detection candidate
-// label slots.  Sets c.LW (detection-set mask width in words).
-void gate_lists(Ctx& c, int M) {
+// label slots.  Sets c.LW (detection-set mask width in words), or with `defer` leaves it to
+// lw_from_lists (the longest list is at scal[27]) and sizes the lists for every (label,
+// detection) pair instead of reading their total back; the error flags are then read with
+// the update's statistics.
+void gate_lists(Ctx& c, int M, bool defer) {
   hipStream_t s = c.s;
   const int T = 256;
   const int U = c.ninst, NS = c.nslot;
@@ -1767,11 +1788,16 @@ void gate_lists(Ctx& c, int M) {
   int32_t* lpre = need<int32_t>(c.lpre, (int64_t)NS * W);
   int32_t* llen = need<int32_t>(c.llen, NS + 1);
   int32_t* loff = need<int32_t>(c.loff, NS + 1);
-  if (M > 0) GLMB_LAUNCH(k_label_bits, NS, 256, 0, s, gbits, beg, W, lbits, lpre, llen, errf);
+  int32_t* maxlen = scal + 27;  // zeroed with the scalars at the start of the update
+  if (M > 0) GLMB_LAUNCH(k_label_bits, NS, 256, 0, s, gbits, beg, W, lbits, lpre, llen, errf, maxlen);
   else GLMB_LAUNCH(k_fill_i32, cdiv(NS + 1, T), T, 0, s, llen, NS + 1, 0);
   scan_excl(llen, loff, NS, tot, c.tmp, s);
   int LW = 1, nl = 0;
-  {
+  defer = defer && (int64_t)NS * M <= kListsCap;
+  if (defer) {
+    nl = NS * M;
+    LW = 0;  // lw_from_lists
+  } else {
     // one round trip: the list lengths, their total and the error flags (set by k_z_in and
     // k_label_bits, both queued above)
     const uint32_t* hb = read_back(c.sb.hs, s, {{llen, NS}, {tot, 1}, {errf, 1}});
@@ -1781,16 +1807,7 @@ void gate_lists(Ctx& c, int M) {
     if (e & ERR_NAN) throw Error{GLMB_E_ARG, "detections contain NaN or infinity"};
     int mx = 0;
     for (int j = 0; j < NS; ++j) mx = std::max(mx, hl[j]);
-    LW = std::max(1, (mx + 31) / 32);
-    const size_t lds_need = (size_t)NS * LW * sizeof(uint32_t);
-    if (lds_need > 160 * 1024)
-      throw Error{GLMB_E_CAPACITY, "labels x detection-set mask width exceed the 160 KB LDS of a workgroup"};
-    if (lds_need > 64 * 1024) {
-      GLMB_HIP(hipFuncSetAttribute((const void*)k_default_masks, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds_need));
-      GLMB_HIP(hipFuncSetAttribute((const void*)k_exceptions, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)lds_need));
-    }
+    LW = mask_width(NS, mx);
   }
   c.LW = LW;
   int32_t* lmeas = need<int32_t>(c.lmeas, nl);
@@ -1915,8 +1932,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   uint32_t* cmax = c.cmax.as<uint32_t>();
   float* phi = c.phi.as<float>();
   if (c.prop_on && M > 0) proposal_apply(c, k, M, slots_ready);
-  gate_lists(c, M);
-  const int LW = c.LW;
+  gate_lists(c, M, true);
   int32_t* loff = c.loff.as<int32_t>();
   int32_t* llen = c.llen.as<int32_t>();
   int32_t* lmeas = c.lmeas.as<int32_t>();
@@ -2106,9 +2122,12 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   GLMB_LAUNCH(k_mark, cdiv(nk, T), T, 0, s, nk, chh, mark);
   int32_t* ppre = need<int32_t>(c.pre, H + 1);
   scan_excl(mark, ppre, H, tot, c.tmp, s);
-  // deviations of the kept children, retained parents: one round trip
-  const int32_t* cnt2 = (const int32_t*)read_back(c.sb.hs, s, {{doff + nk, 1}, {tot, 1}});
+  // deviations of the kept children, retained parents (and the longest label list, when the
+  // gate left the mask width open): one round trip
+  const int32_t* cnt2 = (const int32_t*)read_back(c.sb.hs, s, {{doff + nk, 1}, {tot, 1}, {scal + 27, 1}});
   const int ndev = cnt2[0], np = cnt2[1];
+  if (c.LW == 0) c.LW = mask_width(NS, cnt2[2]);
+  const int LW = c.LW;
   int32_t* devi = need<int32_t>(c.dev_i, ndev);
   int32_t* devn = need<int32_t>(c.dev_slot, 2 * (int64_t)ndev);
   int32_t* devo = devn + ndev;
