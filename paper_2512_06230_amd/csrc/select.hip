@@ -909,35 +909,64 @@ __global__ __launch_bounds__(kDpThreads) void k_dp_rows(const float* base, CellV
     if (!(dd < NB)) continue;
     const int dh = (int)dd;
     __syncthreads();  // the previous parent's arrays are no longer read
-    for (int q = threadIdx.x; q < P2; q += kDpThreads) sv[q] = q < Mr ? cv.dev1[cv.at(h, q)] : INFINITY;
-    for (int b = threadIdx.x; b < NB; b += kDpThreads) fa[b] = b == 0 ? 1 : 0;
+    if (threadIdx.x == 0) ne_s = 0;
     __syncthreads();
-    for (int kk = 2; kk <= P2; kk <<= 1)
-      for (int j = kk >> 1; j > 0; j >>= 1) {
-        for (int q = threadIdx.x; q < P2; q += kDpThreads) {
-          const int r = q ^ j;
-          if (r > q) {
-            const float x = sv[q], y = sv[r];
-            if ((x > y) == ((q & kk) == 0)) {
-              sv[q] = y;
-              sv[r] = x;
+    // the row's first deviations, and how many lie within the range
+    int mine = 0;
+    for (int q = threadIdx.x; q < Mr; q += kDpThreads) {
+      const float v = cv.dev1[cv.at(h, q)];
+      sv[q] = v;
+      mine += (double)v <= E - gap ? 1 : 0;
+    }
+    for (int b = threadIdx.x; b < NB; b += kDpThreads) fa[b] = b == 0 ? 1 : 0;
+    if (mine) atomicAdd(&ne_s, mine);
+    __syncthreads();
+    const int nin = ne_s;
+    __syncthreads();  // every thread has read the count before it is reused below
+    if (nin <= kDpItems1) {
+      // all of them are items: the counts of a 0/1 knapsack (saturated at K) do not depend on
+      // the order of its items, so no sort is needed
+      if (threadIdx.x == 0) ne_s = 0;
+      __syncthreads();
+      for (int q = threadIdx.x; q < Mr; q += kDpThreads) {
+        const float v = sv[q];
+        if ((double)v <= E - gap) {
+          const double c = ceil((double)v / w);
+          cst[atomicAdd(&ne_s, 1)] = c < NB ? (int)c : NB;
+        }
+      }
+      __syncthreads();
+    } else {
+      // more than kDpItems1: the smallest kDpItems1 of them, by a bitonic sort of the row
+      for (int q = Mr + threadIdx.x; q < P2; q += kDpThreads) sv[q] = INFINITY;
+      __syncthreads();
+      for (int kk = 2; kk <= P2; kk <<= 1)
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+          for (int q = threadIdx.x; q < P2; q += kDpThreads) {
+            const int r = q ^ j;
+            if (r > q) {
+              const float x = sv[q], y = sv[r];
+              if ((x > y) == ((q & kk) == 0)) {
+                sv[q] = y;
+                sv[r] = x;
+              }
             }
           }
+          __syncthreads();
         }
-        __syncthreads();
+      // the first deviations within the range (a prefix of the sorted ones), at most kDpItems1
+      if (threadIdx.x < kWave) {
+        const int q = threadIdx.x;
+        const bool in = q < min(Mr, kDpItems1) && (double)sv[q] <= E - gap;
+        const uint64_t bal = __ballot(in);
+        if (in) {
+          const double c = ceil((double)sv[q] / w);
+          cst[q] = c < NB ? (int)c : NB;
+        }
+        if (q == 0) ne_s = __popcll(bal);
       }
-    // the first deviations within the range (a prefix of the sorted ones), at most kDpItems1
-    if (threadIdx.x < kWave) {
-      const int q = threadIdx.x;
-      const bool in = q < min(Mr, kDpItems1) && (double)sv[q] <= E - gap;
-      const uint64_t bal = __ballot(in);
-      if (in) {
-        const double c = ceil((double)sv[q] / w);
-        cst[q] = c < NB ? (int)c : NB;
-      }
-      if (q == 0) ne_s = __popcll(bal);
+      __syncthreads();
     }
-    __syncthreads();
     const int ne = ne_s;
     int32_t* f = fa;
     int32_t* g = fb;
