@@ -471,6 +471,11 @@ def main():
                      "traffic_over_algorithmic": (traffic / bytes_assoc) if traffic else None},
         "stage_roofline": roof,
         "host_syncs_per_update": float(np.mean([s["host_syncs"] for s in stats])),
+        # the update's exact selection: nodes written, levels, form (0 one workgroup, 1 cooperative
+        # whole-GPU launch, 2 host-driven multi-kernel levels)
+        "search": {"nodes_mean": float(np.mean([s["search_nodes"] for s in stats])),
+                   "levels_mean": float(np.mean([s["search_levels"] for s in stats])),
+                   "forms": sorted(set(int(s["search_form"]) for s in stats))},
         "accuracy": acc,
     }
     if learned is not None:

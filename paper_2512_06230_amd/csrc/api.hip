@@ -248,8 +248,12 @@ glmb_status glmb_create(const glmb_params* p, int device, void* stream, glmb_ctx
   const char* tr = std::getenv("GLMB_TRACE");
   x->c.trace = tr && tr[0] && tr[0] != '0';
   // diagnostic: GLMB_SEARCH_FORM=multi runs every selection on the host-driven multi-kernel
-  // levels (the form a batched scene falls back to when its search outgrows one workgroup)
-  if (const char* sf = std::getenv("GLMB_SEARCH_FORM")) x->c.force_multi = std::strcmp(sf, "multi") == 0;
+  // levels (the form a batched scene falls back to when its search outgrows one workgroup);
+  // GLMB_SEARCH_FORM=coop starts every selection on the whole GPU (one cooperative launch)
+  if (const char* sf = std::getenv("GLMB_SEARCH_FORM")) {
+    x->c.force_multi = std::strcmp(sf, "multi") == 0;
+    x->c.force_coop = std::strcmp(sf, "coop") == 0;
+  }
   if (const char* ss = std::getenv("GLMB_SIDE_STREAM")) x->c.fork_ok = std::strcmp(ss, "0") != 0;
   if (const char* hb = std::getenv("GLMB_REC_HASH_BITS")) {
     const int bits = std::atoi(hb);

@@ -83,6 +83,7 @@ struct Ctx {
   bool sel_multi[2] = {false, false};  // per search site (prediction, update): start on the whole GPU
   bool coop_ok = true;  // cooperative launches allowed (they run one at a time on a device)
   bool force_multi = false;  // every search on the host-driven multi-kernel levels (GLMB_SEARCH_FORM=multi)
+  bool force_coop = false;   // every search starts on the whole GPU (GLMB_SEARCH_FORM=coop)
   int LW = 1;  // detection-set mask width (32-bit words) of the last gate
   // fingerprint bits of the (instance, detection set) records (16 at most: records of one instance
   // with equal fingerprints are told apart by full comparison)

@@ -405,6 +405,7 @@ void stage_predict(Ctx& c, int k) {
                 (const int32_t*)itoff, icount, itd, itg);
     // ---- exact selection
     trace(c, "predict.select", H);
+    if (c.force_coop) c.sel_multi[0] = true;
     SelectIn si{H, V, itoff, itd, itg, p.h_max, t0, &c.sel_multi[0], c.coop_ok, c.force_multi};
     Selected sel{};
     std::string serr;

@@ -264,6 +264,7 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
   __shared__ float cv[kSB];       // value, parent and group bits of the chunk's nodes
   __shared__ int32_t chh[kSB];
   __shared__ uint64_t cbb[kSB];
+  __shared__ int32_t cnn[kSB];    // node index of the chunk's nodes
   __shared__ float ldel[kSearchLdsItems];  // the item deltas, when they fit
   const int nitem = it_off[P];
   const float* idel = it_delta;
@@ -276,52 +277,62 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
   float t = *t0;
   int status = 0;  // 0 done, 1 node store full, 2 too deep
   int used = 0;
-  // roots, in parent rank order, with the number of their extensions above t
-  int64_t rext = 0;
+  // roots, in parent rank order; the roots with an extension above t (the items with
+  // v - delta >= t are a prefix of the parent's list) are listed in cand, in the same order, so
+  // that the first level looks at those only.  One scan counts both: roots in the low half of
+  // the 64-bit value, listed roots in the high half.
+  int nx = 0;
   for (int c0 = 0; c0 < P; c0 += kSB) {
     const int h = c0 + threadIdx.x;
-    const int f = (h < P && base[h] >= t) ? 1 : 0;
+    const float v = h < P ? base[h] : -INFINITY;
+    const int f = h < P && v >= t ? 1 : 0;  // t may be -inf
+    int x = 0;
+    if (f) {
+      const int b0 = it_off[h], b1 = it_off[h + 1];
+      x = b0 < b1 && v - idel[b0] >= t ? 1 : 0;
+    }
     int64_t tot;
-    const int64_t off = sb_excl_scan(f, sh, &tot);
-    if (used + tot > cap) {
+    const int64_t off = sb_excl_scan((int64_t)f | ((int64_t)x << 32), sh, &tot);
+    const int tf = (int)(tot & 0xffffffff), tx = (int)(tot >> 32);
+    if (used + tf > cap) {
       status = 1;
       break;
     }
     if (f) {
-      const int n = used + (int)off;
-      const float v = base[h];
+      const int n = used + (int)(off & 0xffffffff);
       nd_p[n] = -1;
       nd_i[n] = -1;
       nd_h[n] = h;
       nd_v[n] = v;
       nd_b[n] = 0ull;
-      // extensions of the root: the items with v - delta >= t, a prefix of the parent's list
-      const int b0 = it_off[h], b1 = it_off[h + 1];
-      if (b0 < b1 && v - idel[b0] >= t) rext += 1;
+      if (x) cand[nx + (int)(off >> 32)] = n;
     }
-    used += (int)tot;
+    used += tf;
+    nx += tx;
   }
-  __syncthreads();
-  int64_t rext_all;
-  (void)sb_excl_scan(rext, sh, &rext_all);
+  __syncthreads();  // the roots and the list are read by other threads below
   // no root has a child above t: the candidates are the roots, in order
-  const bool roots_only = status == 0 && rext_all == 0;
-  int first = 0, end = roots_only ? 0 : used, levels = roots_only ? 1 : 0, last_raise = used;
+  const bool roots_only = status == 0 && nx == 0;
+  // a level expands the nodes [first, end), through the list lst when it is set (the first level)
+  const int32_t* lst = cand;
+  int first = 0, end = roots_only ? 0 : nx, levels = roots_only ? 1 : 0, last_raise = used;
   while (status == 0 && first < end) {
     if (++levels > kMaxDepth + 1) {
       status = 2;
       break;
     }
+    const int level_start = used;  // the nodes this level writes start here
     int c0 = first;
     while (c0 < end) {
       const int nchunk = min(kSB, end - c0);
-      const int n = c0 + (int)threadIdx.x;
       int lo = 0, hi = 0;
       if ((int)threadIdx.x < nchunk) {
+        const int n = lst ? lst[c0 + threadIdx.x] : c0 + (int)threadIdx.x;
         ext_range(n, nd_i, nd_h, nd_v, it_off, idel, t, &lo, &hi);
         cv[threadIdx.x] = nd_v[n];
         chh[threadIdx.x] = nd_h[n];
         cbb[threadIdx.x] = nd_b[n];
+        cnn[threadIdx.x] = n;
       }
       const int64_t cnt = hi - lo;
       int64_t tot;
@@ -373,7 +384,7 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
           if (cpre[m] <= e) a = m;
           else b = m - 1;
         }
-        const int nn = c0 + a;
+        const int nn = cnn[a];
         const int q = clo[a] + (int)(e - cpre[a]);
         float v = cv[a] - idel[q];
         const int g = it_group[q];
@@ -403,8 +414,9 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
       }
     }
     if (status != 0) break;
-    first = end;
+    first = level_start;
     end = used;
+    lst = nullptr;
     // at a level's end once the store has grown by a quarter since the last raise (each raise
     // reads every node twice)
     if (first < end && used >= K && used >= last_raise + last_raise / 4) {

@@ -2075,6 +2075,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     return r;
   };
   Items it = make_items(tcut);
+  if (c.force_coop) c.sel_multi[1] = true;
   SelectIn si{H, bprime, it.itoff, it.itd, it.itg, K, tcut, &c.sel_multi[1], c.coop_ok, c.force_multi};
   dp_bound_items(si, c.sb, s);  // second pass: raises *tcut
   if (c.trace) dp_bound_trace(c.sb, s);
@@ -2087,6 +2088,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     // caller's bound, with the items above it
     trace(c, "update.refine_retry", sel.n, K);
     it = make_items(t0);
+    if (c.force_coop) c.sel_multi[1] = true;
     si = SelectIn{H, bprime, it.itoff, it.itd, it.itg, K, t0, &c.sel_multi[1], c.coop_ok, c.force_multi};
     st = select_topk(si, cap_nodes, c.sb, sel, s, serr, c.trace);
   }
