@@ -182,6 +182,28 @@ __global__ void k_take(int n, const uint64_t* keys, const uint32_t* vals, const 
 constexpr int kSB = 1024;
 constexpr int kBlockNodes = 1 << 18;  // node budget of the one-workgroup search
 constexpr int kSearchLdsItems = 24576;  // item deltas kept in LDS (the 160 KB of a CDNA4 workgroup)
+constexpr int kSmallItems = 1024;       // items whose group tables are kept in LDS too (one per thread)
+
+// end of the largest prefix of items [lo, b) with v - delta >= t (monotone in delta): probes at
+// lo + 2^k - 1 first, since near the threshold the prefix is short, then bisection of the gap
+__device__ __forceinline__ int ext_end(int lo, int b, float v, const float* it_delta, float t) {
+  int a = lo;
+  for (int step = 1; a < b; step <<= 1) {
+    const int m = min(a + step - 1, b - 1);
+    if (v - it_delta[m] >= t) {
+      a = m + 1;
+    } else {
+      b = m;
+      break;
+    }
+  }
+  while (a < b) {
+    const int m = (a + b) >> 1;
+    if (v - it_delta[m] >= t) a = m + 1;
+    else b = m;
+  }
+  return a;
+}
 
 __device__ __forceinline__ int64_t sb_excl_scan(int64_t v, int64_t* sh, int64_t* total) {
   const int lane = lane_id(), w = threadIdx.x / kWave;
@@ -216,10 +238,34 @@ __device__ float sb_bound(const float* v, int n, int K, int32_t* hist, int64_t* 
   for (int pass = 0; pass < 2; ++pass) {
     for (int j = threadIdx.x; j < 4096; j += kSB) hist[j] = 0;
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += kSB) {
-      const uint32_t o = f2o(v[i]);
-      if (pass == 0) atomicAdd(&hist[o >> 20], 1);
-      else if ((o >> 20) == prefix) atomicAdd(&hist[(o >> 8) & 4095], 1);
+    for (int i0 = 0; i0 < n; i0 += kSB) {
+      const int i = i0 + (int)threadIdx.x;
+      bool act = false;
+      uint32_t bin = 0;
+      if (i < n) {
+        const uint32_t o = f2o(v[i]);
+        if (pass == 0) {
+          act = true;
+          bin = o >> 20;
+        } else if ((o >> 20) == prefix) {
+          act = true;
+          bin = (o >> 8) & 4095;
+        }
+      }
+      // The values of a search cluster in few bins, and same-address LDS atomics serialise: the
+      // lanes that share the bin of the first pending lane add once, for a few rounds; the lanes
+      // left then add one each.
+      uint64_t pend = __ballot(act);
+      for (int r = 0; r < 4 && pend != 0ull; ++r) {
+        const int lead = __ffsll((unsigned long long)pend) - 1;
+        const uint32_t b = (uint32_t)__shfl((int)bin, lead, kWave);
+        const bool mine = act && bin == b;
+        const uint64_t same = __ballot(mine);
+        if (lane_id() == lead) atomicAdd(&hist[b], (int)__popcll(same));
+        if (mine) act = false;
+        pend &= ~same;
+      }
+      if (act) atomicAdd(&hist[bin], 1);
     }
     __syncthreads();
     const int t = threadIdx.x;  // owns bins 4t .. 4t+3
@@ -265,14 +311,53 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
   __shared__ int32_t chh[kSB];
   __shared__ uint64_t cbb[kSB];
   __shared__ int32_t cnn[kSB];    // node index of the chunk's nodes
-  __shared__ float ldel[kSearchLdsItems];  // the item deltas, when they fit
+  __shared__ __align__(16) float ldel[kSearchLdsItems];  // the item deltas, when they fit
+  __shared__ int32_t s_ng;
   const int nitem = it_off[P];
   const float* idel = it_delta;
   if (nitem <= kSearchLdsItems) {
     for (int q = threadIdx.x; q < nitem; q += kSB) ldel[q] = it_delta[q];
-    __syncthreads();
     idel = ldel;
   }
+  // Up to kSmallItems items also keep, behind their deltas in the same LDS array: their group
+  // (lg), the bit of their group (ibit) and the end of their parent's item list (iend, set for
+  // the items of the roots the first level expands).  The bit is exact when the items carry at
+  // most 64 distinct groups (gm = 2: a set bit proves the group picked, so no walk up a node's
+  // picks is needed), else the hashed bit of group_bit (gm = 1).  Distinct groups get their
+  // numbers through a hash table in hist (keys in its first half, numbers in its second).
+  static_assert(5 * kSmallItems <= kSearchLdsItems, "item tables exceed the delta array");
+  int32_t* lg = (int32_t*)(ldel + kSmallItems);
+  uint64_t* ibit = (uint64_t*)(ldel + 2 * kSmallItems);
+  int32_t* iend = (int32_t*)(ldel + 4 * kSmallItems);
+  int gm = 0;
+  if (nitem <= kSmallItems) {
+    constexpr int32_t kEmpty = (int32_t)0x80000000;  // groups are indices (>= 0)
+    for (int j = threadIdx.x; j < 2048; j += kSB) hist[j] = kEmpty;
+    if (threadIdx.x == 0) s_ng = 0;
+    __syncthreads();
+    const int q = threadIdx.x;
+    int slot = 0, g = 0;
+    if (q < nitem) {
+      g = it_group[q];
+      lg[q] = g;
+      // at most kSmallItems (1024) keys in 2048 slots: an empty or matching slot is always found
+      int sl = (int)(((uint32_t)g * 0x9E3779B1u) >> 21);
+      for (;;) {
+        const int prev = atomicCAS(&hist[sl], kEmpty, g);
+        if (prev == kEmpty) {
+          hist[2048 + sl] = atomicAdd(&s_ng, 1);
+          break;
+        }
+        if (prev == g) break;
+        sl = (sl + 1) & 2047;
+      }
+      slot = sl;
+    }
+    __syncthreads();
+    gm = s_ng <= 64 ? 2 : 1;
+    if (q < nitem) ibit[q] = gm == 2 ? 1ull << hist[2048 + slot] : group_bit(g);
+  }
+  __syncthreads();
   const float nan = __uint_as_float(0xffc00000u);
   float t = *t0;
   int status = 0;  // 0 done, 1 node store full, 2 too deep
@@ -281,36 +366,95 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
   // v - delta >= t are a prefix of the parent's list) are listed in cand, in the same order, so
   // that the first level looks at those only.  One scan counts both: roots in the low half of
   // the 64-bit value, listed roots in the high half.
+  // Each thread takes one contiguous range of parents: it counts them, one scan places them,
+  // and a second sweep writes them.
+  // Ordered compaction of the roots without a scan per 1024 parents: wave w takes the parents
+  // [w*span, (w+1)*span), reads them kWave at a time (kRootBatch loads in flight), counts its roots
+  // and listed roots with ballots; the waves' counts give each wave its first positions, and a
+  // second sweep writes the roots there, in order (consecutive lanes write consecutive nodes).
+  constexpr int kRootBatch = 8;
+  constexpr int kWaves = kSB / kWave;
   int nx = 0;
-  for (int c0 = 0; c0 < P; c0 += kSB) {
-    const int h = c0 + threadIdx.x;
-    const float v = h < P ? base[h] : -INFINITY;
-    const int f = h < P && v >= t ? 1 : 0;  // t may be -inf
-    int x = 0;
-    if (f) {
-      const int b0 = it_off[h], b1 = it_off[h + 1];
-      x = b0 < b1 && v - idel[b0] >= t ? 1 : 0;
+  {
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const uint64_t lt = (1ull << lane) - 1ull;  // lanes below this one
+    const int span = ((P + kWaves - 1) / kWaves + kWave - 1) / kWave * kWave;
+    const int a = min(P, w * span), b = min(P, a + span);
+    float bv[kRootBatch];
+    int bo0[kRootBatch], bo1[kRootBatch];
+    // parent i = i0 + u*kWave + lane of the batch at i0: root (bit 0), listed (bit 1)
+    auto load = [&](int i0) {
+#pragma unroll
+      for (int u = 0; u < kRootBatch; ++u) {
+        const int i = i0 + u * kWave + lane;
+        const bool in = i < b;
+        bv[u] = in ? base[i] : 0.f;
+        bo0[u] = in ? it_off[i] : 0;
+        bo1[u] = in ? it_off[i + 1] : 0;  // it_off has P + 1 entries
+      }
+    };
+    auto flags = [&](int i0, int u) {
+      const int i = i0 + u * kWave + lane;
+      if (!(i < b && bv[u] >= t)) return 0;
+      return 1 | (bo0[u] < bo1[u] && bv[u] - idel[bo0[u]] >= t ? 2 : 0);
+    };
+    int cf = 0, cx = 0;
+    for (int i0 = a; i0 < b; i0 += kRootBatch * kWave) {
+      load(i0);
+#pragma unroll
+      for (int u = 0; u < kRootBatch; ++u) {
+        const int fl = flags(i0, u);
+        cf += __popcll(__ballot(fl & 1));
+        cx += __popcll(__ballot((fl >> 1) & 1));
+      }
     }
-    int64_t tot;
-    const int64_t off = sb_excl_scan((int64_t)f | ((int64_t)x << 32), sh, &tot);
-    const int tf = (int)(tot & 0xffffffff), tx = (int)(tot >> 32);
-    if (used + tf > cap) {
+    int32_t* ws = clo;  // per-wave counts (clo is free until the levels)
+    if (lane == 0) {
+      ws[w] = cf;
+      ws[kWaves + w] = cx;
+    }
+    __syncthreads();
+    int of = 0, ox = 0, tf = 0, tx = 0;
+    for (int j = 0; j < kWaves; ++j) {
+      const int u = ws[j], v = ws[kWaves + j];
+      if (j < w) {
+        of += u;
+        ox += v;
+      }
+      tf += u;
+      tx += v;
+    }
+    if (tf > cap) {
       status = 1;
-      break;
+    } else {
+      for (int i0 = a; i0 < b; i0 += kRootBatch * kWave) {
+        load(i0);
+#pragma unroll
+        for (int u = 0; u < kRootBatch; ++u) {
+          const int fl = flags(i0, u);
+          const uint64_t bf = __ballot(fl & 1), bx = __ballot((fl >> 1) & 1);
+          if (fl & 1) {
+            const int n = of + (int)__popcll(bf & lt);
+            nd_p[n] = -1;
+            nd_i[n] = -1;
+            nd_h[n] = i0 + u * kWave + lane;
+            nd_v[n] = bv[u];
+            nd_b[n] = 0ull;
+            if (fl & 2) {
+              cand[ox + (int)__popcll(bx & lt)] = n;
+              if (gm)
+                for (int q = bo0[u]; q < bo1[u]; ++q) iend[q] = bo1[u];
+            }
+          }
+          of += (int)__popcll(bf);
+          ox += (int)__popcll(bx);
+        }
+      }
+      used = tf;
+      nx = tx;
     }
-    if (f) {
-      const int n = used + (int)(off & 0xffffffff);
-      nd_p[n] = -1;
-      nd_i[n] = -1;
-      nd_h[n] = h;
-      nd_v[n] = v;
-      nd_b[n] = 0ull;
-      if (x) cand[nx + (int)(off >> 32)] = n;
-    }
-    used += tf;
-    nx += tx;
   }
-  __syncthreads();  // the roots and the list are read by other threads below
+  __syncthreads();  // the roots, the list and iend are read by other threads below
   // no root has a child above t: the candidates are the roots, in order
   const bool roots_only = status == 0 && nx == 0;
   // a level expands the nodes [first, end), through the list lst when it is set (the first level)
@@ -328,9 +472,19 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
       int lo = 0, hi = 0;
       if ((int)threadIdx.x < nchunk) {
         const int n = lst ? lst[c0 + threadIdx.x] : c0 + (int)threadIdx.x;
-        ext_range(n, nd_i, nd_h, nd_v, it_off, idel, t, &lo, &hi);
-        cv[threadIdx.x] = nd_v[n];
-        chh[threadIdx.x] = nd_h[n];
+        const int ni = nd_i[n], h = nd_h[n];
+        const float v = nd_v[n];
+        // the items after the node's last pick, to the end of its parent's list
+        if (ni < 0) {
+          lo = it_off[h];
+          hi = it_off[h + 1];
+        } else {
+          lo = ni + 1;
+          hi = gm ? iend[ni] : it_off[h + 1];
+        }
+        hi = v >= t ? ext_end(lo, hi, v, idel, t) : lo;
+        cv[threadIdx.x] = v;
+        chh[threadIdx.x] = h;
         cbb[threadIdx.x] = nd_b[n];
         cnn[threadIdx.x] = n;
       }
@@ -387,14 +541,21 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
         const int nn = cnn[a];
         const int q = clo[a] + (int)(e - cpre[a]);
         float v = cv[a] - idel[q];
-        const int g = it_group[q];
-        const uint64_t pb = cbb[a], gb = group_bit(g);
-        if (pb & gb)
-          for (int x = nn; nd_i[x] >= 0; x = nd_p[x])
-            if (it_group[nd_i[x]] == g) {
-              v = nan;  // two picks in one group: not a child
-              break;
+        const int g = gm ? lg[q] : it_group[q];
+        const uint64_t pb = cbb[a], gb = gm ? ibit[q] : group_bit(g);
+        if (pb & gb) {
+          if (gm == 2) {
+            v = nan;  // exact bits: the group is picked already, so not a child
+          } else {
+            for (int x = nn; nd_i[x] >= 0; x = nd_p[x]) {
+              const int ix = nd_i[x];
+              if ((gm ? lg[ix] : it_group[ix]) == g) {
+                v = nan;  // two picks in one group: not a child
+                break;
+              }
             }
+          }
+        }
         const int o = used + (int)e;
         nd_b[o] = pb | gb;
         nd_p[o] = nn;
@@ -441,20 +602,51 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
       mhi = max(mhi, o);
     }
     nc = used;
-  } else if (status == 0)
-    for (int c0 = 0; c0 < used; c0 += kSB) {
-      const int n = c0 + (int)threadIdx.x;
-      const int f = n < used && nd_v[n] >= t ? 1 : 0;
-      int64_t tot;
-      const int64_t off = sb_excl_scan(f, sh, &tot);
-      if (f) {
-        cand[nc + off] = n;
-        const uint32_t o = f2o(nd_v[n]);
-        mlo = min(mlo, o);
-        mhi = max(mhi, o);
+  } else if (status == 0) {
+    // the same ordered compaction as the roots': per-wave ranges, ballots, coalesced writes
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const uint64_t lt = (1ull << lane) - 1ull;
+    const int span = ((used + kWaves - 1) / kWaves + kWave - 1) / kWave * kWave;
+    const int a = min(used, w * span), b = min(used, a + span);
+    float bv[kRootBatch];
+    auto load = [&](int i0) {
+#pragma unroll
+      for (int u = 0; u < kRootBatch; ++u) {
+        const int i = i0 + u * kWave + lane;
+        bv[u] = i < b ? nd_v[i] : nan;
       }
-      nc += (int)tot;
+    };
+    int cf = 0;
+    for (int i0 = a; i0 < b; i0 += kRootBatch * kWave) {
+      load(i0);
+#pragma unroll
+      for (int u = 0; u < kRootBatch; ++u) cf += __popcll(__ballot(bv[u] >= t));
     }
+    __syncthreads();  // clo is no longer read by the levels
+    if (lane == 0) clo[w] = cf;
+    __syncthreads();
+    int of = 0;
+    for (int j = 0; j < kWaves; ++j) {
+      const int u = clo[j];
+      if (j < w) of += u;
+      nc += u;
+    }
+    for (int i0 = a; i0 < b; i0 += kRootBatch * kWave) {
+      load(i0);
+#pragma unroll
+      for (int u = 0; u < kRootBatch; ++u) {
+        const bool f = bv[u] >= t;
+        const uint64_t bf = __ballot(f);
+        if (f) {
+          cand[of + (int)__popcll(bf & lt)] = i0 + u * kWave + lane;
+          const uint32_t k = f2o(bv[u]);
+          mlo = min(mlo, k);
+          mhi = max(mhi, k);
+        }
+        of += (int)__popcll(bf);
+      }
+    }
+  }
   for (int d = kWave / 2; d > 0; d >>= 1) {
     mlo = min(mlo, (uint32_t)__shfl_xor((int)mlo, d, kWave));
     mhi = max(mhi, (uint32_t)__shfl_xor((int)mhi, d, kWave));
