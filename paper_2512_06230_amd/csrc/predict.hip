@@ -153,8 +153,9 @@ __global__ __launch_bounds__(64) void k_prows(int n, int NS, int NB, int stride,
   }
 }
 
-// 24 bits of the row hash: children with equal rows share them, and rows of one run are
-// compared in full, so a shorter key only lengthens a few runs (about n^2 / 2^25 collisions)
+// 16 bits of the row hash: children with equal rows share them, and rows of one run are
+// compared by full hash and then in full, so a shorter key only lengthens a few runs (about
+// n^2 / 2^17 pairs)
 __global__ void k_hash_keys(int n, const uint64_t* hash, uint64_t* keys, uint32_t* vals) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= n) return;
@@ -162,26 +163,38 @@ __global__ void k_hash_keys(int n, const uint64_t* hash, uint64_t* keys, uint32_
   vals[c] = (uint32_t)c;
 }
 
+// eight words per step, all loaded before they are compared
 __device__ bool rows_equal(const int32_t* a, const int32_t* b, int W2) {
-  for (int s = 0; s < W2; ++s)
+  int s = 0;
+  for (; s + 8 <= W2; s += 8) {
+    int d = 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) d |= a[s + u] ^ b[s + u];
+    if (d) return false;
+  }
+  for (; s < W2; ++s)
     if (a[s] != b[s]) return false;
   return true;
 }
 
-// leader of every child: first child of its hash run with an identical row
-__global__ void k_leaders(int n, int W2, const uint64_t* keys, const uint32_t* vals, const int32_t* crow,
-                          int32_t* leader) {
+// leader of every child: first child of its hash run with an identical row.  Equal rows have
+// equal 64-bit row hashes, so rows are compared in full only where those agree.
+__global__ void k_leaders(int n, int W2, const uint64_t* keys, const uint32_t* vals, const uint64_t* hash,
+                          const int32_t* crow, int32_t* leader) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= n) return;
   int r0 = p;
   while (r0 > 0 && keys[r0 - 1] == keys[p]) --r0;
   const uint32_t me = vals[p];
+  const uint64_t hm = hash[me];
   int lead = (int)me;
-  for (int q = r0; q < p; ++q)
-    if (rows_equal(crow + (size_t)vals[q] * W2, crow + (size_t)me * W2, W2)) {
-      lead = (int)vals[q];
+  for (int q = r0; q < p; ++q) {
+    const uint32_t o = vals[q];
+    if (hash[o] == hm && rows_equal(crow + (size_t)o * W2, crow + (size_t)me * W2, W2)) {
+      lead = (int)o;
       break;
     }
+  }
   leader[me] = lead;
 }
 
@@ -435,7 +448,7 @@ void stage_predict(Ctx& c, int k) {
   int32_t* mrank = islead + n + 1;
   int32_t* mrep = mrank + n + 1;
   float* mval = need<float>(c.sel_logw, n + 1);
-  GLMB_LAUNCH(k_leaders, cdiv(n, T), T, 0, s, n, W2, hk, hv, crow, leader);
+  GLMB_LAUNCH(k_leaders, cdiv(n, T), T, 0, s, n, W2, hk, hv, (const uint64_t*)hash, crow, leader);
   GLMB_LAUNCH(k_merge, cdiv(n, T), T, 0, s, n, leader, selval, keyrank, hk, hv, islead, mval, mrank, mrep);
   int32_t* lpre = need<int32_t>(c.pre, n + 1);
   scan_excl(islead, lpre, n, tot, c.tmp, s);
