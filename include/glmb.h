@@ -115,7 +115,13 @@ typedef struct {
   int32_t host_syncs;       /* host round trips (waits for the device) made by the update  */
   int32_t search_form;      /* selection search of the update: 0 one workgroup, 1 one cooperative
                                whole-GPU launch, 2 host-driven levels of whole-GPU kernels,
-                               3 sampled maps (glmb_set_sampling)                           */
+                               3 sampled maps (glmb_set_sampling).  Diagnostic environment
+                               variables read by glmb_create: GLMB_SEARCH_FORM=multi|coop starts
+                               every search on form 2 or 1; GLMB_SEARCH_GROUP_BITS=0|1|2 limits
+                               how form 0 rejects a second pick in one group (0 item tables in
+                               global memory, 1 in LDS with hashed group bits, 2 exact bits when
+                               the items carry at most 64 groups: the default).  Results do not
+                               depend on either.                                            */
 } glmb_step_stats;
 
 /* Library / status utilities */

@@ -254,6 +254,12 @@ glmb_status glmb_create(const glmb_params* p, int device, void* stream, glmb_ctx
     x->c.force_multi = std::strcmp(sf, "multi") == 0;
     x->c.force_coop = std::strcmp(sf, "coop") == 0;
   }
+  // diagnostic: GLMB_SEARCH_GROUP_BITS=0|1|2 limits the one-workgroup search's item tables in LDS
+  // (0: none, 1: hashed group bits only, 2: exact bits allowed, the default)
+  if (const char* gb = std::getenv("GLMB_SEARCH_GROUP_BITS")) {
+    const int v = std::atoi(gb);
+    if (v >= 0 && v <= 2) x->c.group_bits = v;
+  }
   if (const char* ss = std::getenv("GLMB_SIDE_STREAM")) x->c.fork_ok = std::strcmp(ss, "0") != 0;
   if (const char* hb = std::getenv("GLMB_REC_HASH_BITS")) {
     const int bits = std::atoi(hb);

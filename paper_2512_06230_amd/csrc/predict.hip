@@ -420,6 +420,7 @@ void stage_predict(Ctx& c, int k) {
     trace(c, "predict.select", H);
     if (c.force_coop) c.sel_multi[0] = true;
     SelectIn si{H, V, itoff, itd, itg, p.h_max, t0, &c.sel_multi[0], c.coop_ok, c.force_multi};
+    si.group_bits = c.group_bits;
     Selected sel{};
     std::string serr;
     const int cap_nodes = p.cap_nodes > 0 ? p.cap_nodes : (1 << 22);

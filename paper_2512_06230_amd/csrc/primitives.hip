@@ -26,7 +26,9 @@ __global__ __launch_bounds__(kReadT) void k_read_back(ReadList l, uint32_t* dst,
     uint32_t* out = dst + 1 + l.off[p];
     for (int j = threadIdx.x; j < l.n[p]; j += kReadT) out[j] = src[j];
   }
-  __threadfence_system();
+  // a release at system scope (the host reads the words once it sees the sequence number); no
+  // acquire, so the device's L2 is written back but not invalidated for the kernels after this
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
   __syncthreads();
   if (threadIdx.x == 0) __hip_atomic_store(dst, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }

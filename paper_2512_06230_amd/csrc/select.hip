@@ -300,7 +300,7 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
                                                       const float* it_delta, const int32_t* it_group, int K,
                                                       const float* t0, int cap, int32_t* nd_p, int32_t* nd_i,
                                                       int32_t* nd_h, float* nd_v, uint64_t* nd_b, float* t_out,
-                                                      int32_t* out, int32_t* cand) {
+                                                      int32_t* out, int32_t* cand, int gmax) {
   __shared__ int64_t sh[40];
   __shared__ int32_t hist[4096];
   __shared__ int64_t sel[4];
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
   uint64_t* ibit = (uint64_t*)(ldel + 2 * kSmallItems);
   int32_t* iend = (int32_t*)(ldel + 4 * kSmallItems);
   int gm = 0;
-  if (nitem <= kSmallItems) {
+  if (nitem <= kSmallItems && gmax > 0) {
     constexpr int32_t kEmpty = (int32_t)0x80000000;  // groups are indices (>= 0)
     for (int j = threadIdx.x; j < 2048; j += kSB) hist[j] = kEmpty;
     if (threadIdx.x == 0) s_ng = 0;
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kSB) void k_select_block(int P, const float* base, 
       slot = sl;
     }
     __syncthreads();
-    gm = s_ng <= 64 ? 2 : 1;
+    gm = s_ng <= 64 && gmax == 2 ? 2 : 1;
     if (q < nitem) ibit[q] = gm == 2 ? 1ull << hist[2048 + slot] : group_bit(g);
   }
   __syncthreads();
@@ -1484,7 +1484,7 @@ glmb_status select_topk(const SelectIn& in, int cap, SelectBufs& b, Selected& ou
   if (!in.force_multi && !(in.prefer_multi && *in.prefer_multi)) {
     GLMB_LAUNCH(k_select_block, 1, kSB, 0, s, in.P, in.base, in.it_off, in.it_delta, in.it_group, in.K, in.t0,
                 std::min(cap, kBlockNodes), A.p, A.i, A.h, A.v, A.b, t, scal + 24,
-                need<int32_t>(b.cand, std::min(cap, kBlockNodes) + 1));
+                need<int32_t>(b.cand, std::min(cap, kBlockNodes) + 1), in.group_bits);
     std::memcpy(hs, read_back(b.hs, s, {{scal + 24, 5}}), 5 * sizeof(int32_t));
     used = hs[0];
     levels = hs[1];

@@ -2077,6 +2077,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   Items it = make_items(tcut);
   if (c.force_coop) c.sel_multi[1] = true;
   SelectIn si{H, bprime, it.itoff, it.itd, it.itg, K, tcut, &c.sel_multi[1], c.coop_ok, c.force_multi};
+  si.group_bits = c.group_bits;
   dp_bound_items(si, c.sb, s);  // second pass: raises *tcut
   if (c.trace) dp_bound_trace(c.sb, s);
   trace(c, "update.select", it.ncell, it.nitem);
@@ -2090,6 +2091,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
     it = make_items(t0);
     if (c.force_coop) c.sel_multi[1] = true;
     si = SelectIn{H, bprime, it.itoff, it.itd, it.itg, K, t0, &c.sel_multi[1], c.coop_ok, c.force_multi};
+    si.group_bits = c.group_bits;
     st = select_topk(si, cap_nodes, c.sb, sel, s, serr, c.trace);
   }
   if (st != GLMB_OK) throw Error{st, serr};

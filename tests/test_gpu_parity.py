@@ -273,6 +273,22 @@ def test_small_node_store_multi_kernel(torch_cuda, monkeypatch):
         assert stats["search_form"] == 2, stats
 
 
+@pytest.mark.parametrize("mode", ["0", "1", "2"])
+def test_search_group_bits(torch_cuda, monkeypatch, mode):
+    """The one-workgroup search's three ways of rejecting a second pick in one group: item tables
+    in global memory with hashed bits and a walk up the picks (0), tables in LDS with hashed bits
+    (1), and exact bits when the items carry at most 64 groups (2).  Updates and predictions of
+    random states under each against the oracle."""
+    monkeypatch.setenv("GLMB_SEARCH_GROUP_BITS", mode)
+    for seed in range(4):
+        rng = np.random.default_rng(900 + seed)
+        st = sc.random_state(rng, n_lab=3 + seed, n_hyp=4 + 3 * seed, side=20.0, versions=2)
+        z = sc.measurements_near(rng, st, 3 + seed, 20.0, 1.0)
+        for K in (5, 64, 1000):
+            check_update(st, z, dict(BASE, h_max=K))
+        check_predict(st, dict(BASE, h_max=200))
+
+
 def test_hmax_one(torch_cuda):
     rng = np.random.default_rng(4)
     st = sc.random_state(rng, n_lab=5, n_hyp=6, side=20.0)
