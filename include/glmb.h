@@ -120,8 +120,11 @@ typedef struct {
                                every search on form 2 or 1; GLMB_SEARCH_GROUP_BITS=0|1|2 limits
                                how form 0 rejects a second pick in one group (0 item tables in
                                global memory, 1 in LDS with hashed group bits, 2 exact bits when
-                               the items carry at most 64 groups: the default).  Results do not
-                               depend on either.                                            */
+                               the items carry at most 64 groups: the default);
+                               GLMB_DP_BOUND_INFLATE=x (0 < x < 1) raises the update's counting
+                               bound that part of the way to the best value, so that the search
+                               again from the caller's bound runs.  Results do not depend on
+                               any of them.                                                 */
 } glmb_step_stats;
 
 /* Library / status utilities */

@@ -260,6 +260,13 @@ glmb_status glmb_create(const glmb_params* p, int device, void* stream, glmb_ctx
     const int v = std::atoi(gb);
     if (v >= 0 && v <= 2) x->c.group_bits = v;
   }
+  // diagnostic: GLMB_DP_BOUND_INFLATE=x (0 < x < 1) raises the update's counting bound part of
+  // the way to the best value, so that its search keeps fewer than K children and the search
+  // again from the caller's bound runs (results unchanged)
+  if (const char* di = std::getenv("GLMB_DP_BOUND_INFLATE")) {
+    const float v = std::strtof(di, nullptr);
+    if (v > 0.f && v < 1.f) x->c.dp_inflate = v;
+  }
   if (const char* ss = std::getenv("GLMB_SIDE_STREAM")) x->c.fork_ok = std::strcmp(ss, "0") != 0;
   if (const char* hb = std::getenv("GLMB_REC_HASH_BITS")) {
     const int bits = std::atoi(hb);

@@ -201,6 +201,7 @@ struct SelectIn {
   bool* prefer_multi;     // per call site: the previous search outgrew one workgroup (may be null)
   bool allow_coop = true; // the whole-GPU search may be one cooperative launch
   bool force_multi = false;  // always the host-driven multi-kernel levels (diagnostic setting)
+  float dp_inflate = 0.f;    // diagnostic: the counting bound raised this part of the way to the best value
   int group_bits = 2;        // one-workgroup search, items' group tables in LDS: 0 never, 1 with hashed
                              // group bits only, 2 exact bits where the items carry <= 64 groups
 };

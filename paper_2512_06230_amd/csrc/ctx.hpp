@@ -85,6 +85,7 @@ struct Ctx {
   bool force_multi = false;  // every search on the host-driven multi-kernel levels (GLMB_SEARCH_FORM=multi)
   bool force_coop = false;   // every search starts on the whole GPU (GLMB_SEARCH_FORM=coop)
   int group_bits = 2;         // SelectIn::group_bits of every search (GLMB_SEARCH_GROUP_BITS)
+  float dp_inflate = 0.f;     // SelectIn::dp_inflate of the update's search (GLMB_DP_BOUND_INFLATE)
   int LW = 1;  // detection-set mask width (32-bit words) of the last gate
   // fingerprint bits of the (instance, detection set) records (16 at most: records of one instance
   // with equal fingerprints are told apart by full comparison)

@@ -1319,7 +1319,8 @@ __global__ __launch_bounds__(kDpCountThreads) void k_dp_count(const float* base,
 
 // first bin whose cumulative count reaches K; the bound it gives, and the next pass's range.
 // Leaves C zeroed.
-__global__ __launch_bounds__(kDpThreads) void k_dp_pick(int pass, int K, DpState* st, unsigned long long* C) {
+__global__ __launch_bounds__(kDpThreads) void k_dp_pick(int pass, int K, DpState* st, unsigned long long* C,
+                                                        float inflate) {
   __shared__ unsigned long long part[kDpThreads];
   __shared__ int32_t first;
   const int NB = pass == 1 ? kDpBins1 : kDpBins2, per = NB / kDpThreads;
@@ -1369,6 +1370,10 @@ __global__ __launch_bounds__(kDpThreads) void k_dp_pick(int pass, int K, DpState
     st->E = (j + 2) * w;  // the fine pass covers the coarse bin found and the next
     st->ok = j > 0 ? 1 : 0;
   }
+  // diagnostic (0 < inflate < 1): a refined bound moved that part of the way up to the best
+  // value, no longer a bound, so that the search keeps fewer than K children and the caller's
+  // search again from its own bound is exercised
+  if (inflate > 0.f && st->refined) st->tref = st->tref + inflate * (st->vmax - st->tref);
 }
 
 namespace {
@@ -1415,7 +1420,7 @@ const float* dp_bound_rows(const float* base, int P, const CellView& cv, int M, 
   if (K > 0 && P > 0 && M > 0) {
     GLMB_LAUNCH(k_dp_rows, std::min(P, kDpGrid), kDpThreads, 0, s, base, cv, M, K, (const DpState*)st,
                 (const int32_t*)act, C);
-    GLMB_LAUNCH(k_dp_pick, 1, kDpThreads, 0, s, 1, K, st, C);
+    GLMB_LAUNCH(k_dp_pick, 1, kDpThreads, 0, s, 1, K, st, C, 0.f);
   }
   return &st->tref;
 }
@@ -1426,7 +1431,7 @@ void dp_bound_items(const SelectIn& in, SelectBufs& b, hipStream_t s) {
   unsigned long long* C = b.dpc.as<unsigned long long>();
   GLMB_LAUNCH(k_dp_count, std::min(in.P, kDpGrid), kDpCountThreads, 0, s, in.base, in.it_off, in.it_delta,
               in.it_group, in.K, (const DpState*)st, (const int32_t*)b.dpa.as<int32_t>(), C);
-  GLMB_LAUNCH(k_dp_pick, 1, kDpThreads, 0, s, 2, in.K, st, C);
+  GLMB_LAUNCH(k_dp_pick, 1, kDpThreads, 0, s, 2, in.K, st, C, in.dp_inflate);
 }
 
 bool dp_bound_refined(SelectBufs& b, hipStream_t s) {

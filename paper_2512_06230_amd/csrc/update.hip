@@ -2078,6 +2078,7 @@ void stage_update(Ctx& c, int k, const float* zin, int M) {
   if (c.force_coop) c.sel_multi[1] = true;
   SelectIn si{H, bprime, it.itoff, it.itd, it.itg, K, tcut, &c.sel_multi[1], c.coop_ok, c.force_multi};
   si.group_bits = c.group_bits;
+  si.dp_inflate = c.dp_inflate;
   dp_bound_items(si, c.sb, s);  // second pass: raises *tcut
   if (c.trace) dp_bound_trace(c.sb, s);
   trace(c, "update.select", it.ncell, it.nitem);

@@ -289,6 +289,23 @@ def test_search_group_bits(torch_cuda, monkeypatch, mode):
         check_predict(st, dict(BASE, h_max=200))
 
 
+def test_refine_retry(torch_cuda, monkeypatch, capfd):
+    """The update's counting bound raised on purpose above the K-th best child
+    (GLMB_DP_BOUND_INFLATE): its search keeps fewer than K children, the update searches again
+    from the caller's bound, and the result is still the oracle's."""
+    monkeypatch.setenv("GLMB_DP_BOUND_INFLATE", "0.9")
+    monkeypatch.setenv("GLMB_TRACE", "1")
+    retries = 0
+    for seed in range(4):
+        rng = np.random.default_rng(700 + seed)
+        st = sc.random_state(rng, n_lab=4 + seed, n_hyp=6 + 2 * seed, side=20.0, versions=2)
+        z = sc.measurements_near(rng, st, 4 + seed, 20.0, 1.0)
+        for K in (5, 20):
+            check_update(st, z, dict(BASE, h_max=K))
+            retries += capfd.readouterr().err.count("update.refine_retry")
+    assert retries > 0
+
+
 def test_hmax_one(torch_cuda):
     rng = np.random.default_rng(4)
     st = sc.random_state(rng, n_lab=5, n_hyp=6, side=20.0)
