@@ -241,14 +241,16 @@ __global__ void k_lead_keys(int n, int rb, const int32_t* is_lead, const int32_t
   vals[d] = (uint32_t)c;
 }
 
-__global__ void k_used(int nh, int W2, const uint32_t* order, const int32_t* crow, int32_t* sused, int32_t* uused) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)nh * W2) return;
-  const int h = (int)(t / W2), s = (int)(t % W2);
-  const int u = crow[(size_t)order[h] * W2 + s];
-  if (u >= 0) {
-    sused[s] = 1;
-    uused[u] = 1;
+// one workgroup per final hypothesis: the slots and instances its row uses.  Many rows share
+// them, so a flag is written only where it still reads clear (all writers store the same 1).
+__global__ void k_used(int W2, const uint32_t* order, const int32_t* crow, int32_t* sused, int32_t* uused) {
+  const int32_t* r = crow + (size_t)order[blockIdx.x] * W2;
+  for (int s = threadIdx.x; s < W2; s += blockDim.x) {
+    const int u = r[s];
+    if (u >= 0) {
+      if (!sused[s]) sused[s] = 1;
+      if (!uused[u]) uused[u] = 1;
+    }
   }
 }
 
@@ -282,15 +284,17 @@ __global__ void k_final_meta(int nh, const uint32_t* order, const int32_t* nt_c,
   hpar[h] = par_c[mrep[c]];
 }
 
-__global__ void k_final_rows(int nh, int W2, int NS2, const uint32_t* order, const int32_t* crow, const int32_t* spre,
+// one workgroup per final hypothesis h: its row over the kept slots
+__global__ void k_final_rows(int W2, int NS2, const uint32_t* order, const int32_t* crow, const int32_t* spre,
                              const int32_t* sused, const int32_t* upre, int32_t* rows) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= (int64_t)nh * W2) return;
-  const int h = (int)(t / W2), s = (int)(t % W2);
-  const int c = (int)order[h];
-  if (!sused[s]) return;
-  const int u = crow[(size_t)c * W2 + s];
-  rows[(size_t)h * NS2 + spre[s]] = u >= 0 ? upre[u] : -1;
+  const int h = blockIdx.x;
+  const int32_t* r = crow + (size_t)order[h] * W2;
+  int32_t* o = rows + (size_t)h * NS2;
+  for (int s = threadIdx.x; s < W2; s += blockDim.x) {
+    if (!sused[s]) continue;
+    const int u = r[s];
+    o[spre[s]] = u >= 0 ? upre[u] : -1;
+  }
 }
 
 __global__ void k_compact_inst(int U2, const int32_t* uused, const int32_t* upre, const int32_t* spre, const DInst* in,
@@ -472,7 +476,7 @@ void stage_predict(Ctx& c, int k) {
   int32_t* sused = need<int32_t>(c.flags, (int64_t)nused);
   int32_t* uused = sused + W2 + 1;
   GLMB_HIP(hipMemsetAsync(sused, 0, nused * sizeof(int32_t), s));
-  GLMB_LAUNCH(k_used, cdiv((int64_t)nh * W2, T), T, 0, s, nh, W2, lv, crow, sused, uused);
+  GLMB_LAUNCH(k_used, nh, T, 0, s, W2, lv, crow, sused, uused);
   int32_t* spre = need<int32_t>(c.lpre, (int64_t)W2 + U2 + 4);
   int32_t* upre = spre + W2 + 2;
   scan_excl(sused, spre, W2, spre + W2, c.tmp, s);
@@ -489,7 +493,7 @@ void stage_predict(Ctx& c, int k) {
   int32_t* fnt = need<int32_t>(c.hp_map, nh + 1);
   int32_t* fpar = need<int32_t>(c.hparent, nh + 1);
   // every (hypothesis, kept slot) entry is written: a kept slot is used, absent tracks as -1
-  GLMB_LAUNCH(k_final_rows, cdiv((int64_t)nh * W2, T), T, 0, s, nh, W2, NS2, lv, crow, spre, sused, upre, frows);
+  GLMB_LAUNCH(k_final_rows, nh, T, 0, s, W2, NS2, lv, crow, spre, sused, upre, frows);
   GLMB_LAUNCH(k_final_meta, cdiv(nh, T), T, 0, s, nh, lv, ntc, parc, mrep, fnt, fpar);
   DInst* ninst = (DInst*)need<uint8_t>(c.inst2, (int64_t)(Unew + 1) * sizeof(DInst));
   GLMB_LAUNCH(k_compact_inst, cdiv(U2, T), T, 0, s, U2, uused, upre, spre, c.inst.as<DInst>(), ninst);
