@@ -24,26 +24,35 @@ __device__ __forceinline__ float tsum(float v, float* sh) {
 // one block: normalise the first n weights, keep the prefix before the first weight below tau
 // (the first is always kept), renormalise.  The rows are in rank order (weight descending),
 // so the prefix is the set of weights >= tau; the maximum is reduced rather than assumed.
+// Up to kTruncLds weights are read from HBM once and kept in LDS for the later passes.
+constexpr int kTruncLds = 16384;
 __global__ __launch_bounds__(1024) void k_truncate(int n, float tau, float* logw, int32_t* nkeep) {
   __shared__ float red[32];
   __shared__ int32_t ired[16];
+  __shared__ float lw[kTruncLds];
+  const bool cached = n <= kTruncLds;
   float mx = -INFINITY;
-  for (int h = threadIdx.x; h < n; h += blockDim.x) mx = fmaxf(mx, logw[h]);
+  for (int h = threadIdx.x; h < n; h += blockDim.x) {
+    const float v = logw[h];
+    if (cached) lw[h] = v;
+    mx = fmaxf(mx, v);
+  }
   for (int d = kWave / 2; d > 0; d >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d, kWave));
   if (lane_id() == 0) red[threadIdx.x / kWave] = mx;
   __syncthreads();
   mx = red[0];
   for (int j = 1; j < (int)(blockDim.x / kWave); ++j) mx = fmaxf(mx, red[j]);
   __syncthreads();
+  const float* w = cached ? lw : logw;  // LDS entries written before the barrier above
   float s = 0.0f;
-  for (int h = threadIdx.x; h < n; h += blockDim.x) s += __expf(logw[h] - mx);
+  for (int h = threadIdx.x; h < n; h += blockDim.x) s += __expf(w[h] - mx);
   s = tsum(s, red);
   const float L = mx + __logf(s);
   // first index h >= 1 whose normalised weight is below tau
   int first = n;
   if (tau > 0.0f)
     for (int h = 1 + threadIdx.x; h < n; h += blockDim.x)
-      if (__expf(logw[h] - L) < tau) {
+      if (__expf(w[h] - L) < tau) {
         first = h;
         break;
       }
@@ -53,11 +62,11 @@ __global__ __launch_bounds__(1024) void k_truncate(int n, float tau, float* logw
   int keep = ired[0];
   for (int j = 1; j < (int)(blockDim.x / kWave); ++j) keep = min(keep, ired[j]);
   float s2 = 0.0f;
-  for (int h = threadIdx.x; h < keep; h += blockDim.x) s2 += __expf(logw[h] - mx);
+  for (int h = threadIdx.x; h < keep; h += blockDim.x) s2 += __expf(w[h] - mx);
   s2 = tsum(s2, red + 16);
   const float L2 = mx + __logf(s2);
   __syncthreads();
-  for (int h = threadIdx.x; h < keep; h += blockDim.x) logw[h] -= L2;
+  for (int h = threadIdx.x; h < keep; h += blockDim.x) logw[h] = w[h] - L2;
   if (threadIdx.x == 0) *nkeep = keep;
 }
 

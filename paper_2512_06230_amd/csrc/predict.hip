@@ -122,32 +122,50 @@ __global__ __launch_bounds__(64) void k_prows(int n, int NS, int NB, int stride,
   const int node = sel_node[c];
   const int h = nd_h[node];
   int32_t* o = out + (size_t)c * W2;
-  for (int s = threadIdx.x; s < W2; s += blockDim.x) {
-    if (s < NS) o[s] = t_yes ? rows[(size_t)h * stride + s] : -1;
-    else o[s] = byes[s - NS] ? U + (s - NS) : -1;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int x = node; nd_item[x] >= 0; x = nd_parent[x]) {
-      const int g = it_g[nd_item[x]];
-      if (g < NS) o[g] = t_yes ? -1 : rows[(size_t)h * stride + g];
-      else o[g] = byes[g - NS] ? -1 : U + (g - NS);
-    }
-    par[c] = h;
-  }
-  __syncthreads();
+  // slot s of the parent's row (kept tracks, or births taken), and its value with the child's
+  // deviation at s (the track dropped or the birth not taken, and the reverse)
+  auto dflt = [&](int s) {
+    if (s < NS) return t_yes ? rows[(size_t)h * stride + s] : -1;
+    return byes[s - NS] ? U + (s - NS) : -1;
+  };
+  auto flip = [&](int s) {
+    if (s < NS) return t_yes ? -1 : rows[(size_t)h * stride + s];
+    return byes[s - NS] ? -1 : U + (s - NS);
+  };
+  // hash and track count of the default row, taken while it is written; the deviations' slots
+  // are corrected below (the hash is a sum over the occupied slots, so a slot's term can be
+  // taken out exactly)
   unsigned long long hl = 0;
   int cl = 0;
-  for (int s = threadIdx.x; s < W2; s += blockDim.x)
-    if (o[s] >= 0) {
-      hl += mix64(((uint64_t)(uint32_t)s << 32) | (uint32_t)o[s]);
+  for (int s = threadIdx.x; s < W2; s += blockDim.x) {
+    const int v = dflt(s);
+    o[s] = v;
+    if (v >= 0) {
+      hl += mix64(((uint64_t)(uint32_t)s << 32) | (uint32_t)v);
       ++cl;
     }
+  }
   for (int d = kWave / 2; d > 0; d >>= 1) {
     hl += __shfl_xor(hl, d, kWave);
     cl += __shfl_xor(cl, d, kWave);
   }
+  __syncthreads();  // the default row is written before the deviations overwrite their slots
   if (threadIdx.x == 0) {
+    // one deviation per slot (a child picks at most one item per group)
+    for (int x = node; nd_item[x] >= 0; x = nd_parent[x]) {
+      const int g = it_g[nd_item[x]];
+      const int ov = dflt(g), nv = flip(g);
+      o[g] = nv;
+      if (ov >= 0) {
+        hl -= mix64(((uint64_t)(uint32_t)g << 32) | (uint32_t)ov);
+        --cl;
+      }
+      if (nv >= 0) {
+        hl += mix64(((uint64_t)(uint32_t)g << 32) | (uint32_t)nv);
+        ++cl;
+      }
+    }
+    par[c] = h;
     hash[c] = hl;
     nt[c] = cl;
   }
