@@ -82,14 +82,25 @@ void stage_truncate(Ctx& c, int hmax, float tau) {
 }
 
 // ------------------------------------------------------------------ estimate
+// Up to kEstLds hypotheses' weights and track counts are read from HBM once and kept in LDS
+// for the passes over the cardinalities.
+constexpr int kEstLds = 12288;
 __global__ __launch_bounds__(1024) void k_estimate(int H, const float* logw, const int32_t* ntrk, int32_t* out) {
   __shared__ float red[32];
   __shared__ int32_t ired[32];
+  __shared__ float lw[kEstLds];
+  __shared__ int32_t ln[kEstLds];
+  const bool cached = H <= kEstLds;
   // range of track counts
   int lo = INT_MAX, hi = -1;
   for (int h = threadIdx.x; h < H; h += blockDim.x) {
-    lo = min(lo, ntrk[h]);
-    hi = max(hi, ntrk[h]);
+    const int n = ntrk[h];
+    if (cached) {
+      ln[h] = n;
+      lw[h] = logw[h];
+    }
+    lo = min(lo, n);
+    hi = max(hi, n);
   }
   for (int d = kWave / 2; d > 0; d >>= 1) {
     lo = min(lo, __shfl_xor(lo, d, kWave));
@@ -107,13 +118,15 @@ __global__ __launch_bounds__(1024) void k_estimate(int H, const float* logw, con
     hi = max(hi, ired[16 + j]);
   }
   __syncthreads();
+  const float* wv = cached ? lw : logw;  // LDS entries written before the barriers above
+  const int32_t* nv = cached ? ln : ntrk;
   // cardinality distribution, one fixed-order reduction per count; MAP with ties to the smaller
   float best = -1.0f;
   int nbest = lo;
   for (int n = lo; n <= hi; ++n) {
     float s = 0.0f;
     for (int h = threadIdx.x; h < H; h += blockDim.x)
-      if (ntrk[h] == n) s += __expf(logw[h]);
+      if (nv[h] == n) s += __expf(wv[h]);
     s = tsum(s, red);
     if (s > best) {
       best = s;
@@ -123,7 +136,7 @@ __global__ __launch_bounds__(1024) void k_estimate(int H, const float* logw, con
   // most likely hypothesis of that size (rows are in rank order)
   int first = INT_MAX;
   for (int h = threadIdx.x; h < H; h += blockDim.x)
-    if (ntrk[h] == nbest) {
+    if (nv[h] == nbest) {
       first = h;
       break;
     }

@@ -272,7 +272,7 @@ __global__ void k_used(int W2, const uint32_t* order, const int32_t* crow, int32
   }
 }
 
-// one block: normalised log weights of the merged hypotheses in final order
+// sum over the workgroup (every thread gets it)
 __device__ __forceinline__ float bsum(float v, float* sh) {
   for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
   __syncthreads();
@@ -282,14 +282,24 @@ __device__ __forceinline__ float bsum(float v, float* sh) {
   for (int j = 0; j < (int)(blockDim.x / kWave); ++j) r += sh[j];
   return r;
 }
+
+// one block: normalised log weights of the merged hypotheses in final order (up to kPnormLds
+// values gathered once and kept in LDS for the second pass)
+constexpr int kPnormLds = 16384;
 __global__ __launch_bounds__(1024) void k_pnorm(int nh, const uint32_t* order, const float* mval, float* logw) {
   __shared__ float red[16];
+  __shared__ float lv[kPnormLds];
+  const bool cached = nh <= kPnormLds;
   const float mx = mval[order[0]];
   float s = 0.0f;
-  for (int h = threadIdx.x; h < nh; h += blockDim.x) s += __expf(mval[order[h]] - mx);
-  s = bsum(s, red);
+  for (int h = threadIdx.x; h < nh; h += blockDim.x) {
+    const float v = mval[order[h]];
+    if (cached) lv[h] = v;
+    s += __expf(v - mx);
+  }
+  s = bsum(s, red);  // its barriers also make lv visible
   const float L = mx + __logf(s);
-  for (int h = threadIdx.x; h < nh; h += blockDim.x) logw[h] = mval[order[h]] - L;
+  for (int h = threadIdx.x; h < nh; h += blockDim.x) logw[h] = (cached ? lv[h] : mval[order[h]]) - L;
 }
 
 // track count and parent of every final hypothesis (also when rows have no slots)
